@@ -1,0 +1,230 @@
+"""ORACLE -- test infrastructure, not part of the product.
+
+ctypes binding of the plain FP64 CPU oracle in ba_oracle.c.  Only the test
+suite, the smoke check and the CPU-baseline leg of the benchmark may import
+this module.  It shares no code with the GPU library.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "ba_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "libba_oracle.so")
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (plain -O2, no fast-math, no FMA contraction)."""
+    if force or not os.path.exists(_LIB_PATH):
+        tmp = _LIB_PATH + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared",
+                               "-ffp-contract=off", "-Wall", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+class Options(C.Structure):
+    _fields_ = [("d", C.c_int32), ("huber_delta", C.c_double), ("cg_rtol", C.c_double),
+                ("cg_maxiter", C.c_int32), ("lambda0", C.c_double), ("lambda_min", C.c_double),
+                ("lambda_max", C.c_double), ("diag_min", C.c_double), ("diag_max", C.c_double)]
+
+
+class StepInfo(C.Structure):
+    _fields_ = [("cost_before", C.c_double), ("cost_after", C.c_double),
+                ("lambda_used", C.c_double), ("lambda_next", C.c_double),
+                ("cg_rel_resid", C.c_double), ("pred", C.c_double), ("grad_inf", C.c_double),
+                ("accepted", C.c_int32), ("cg_iters", C.c_int32), ("cg_breakdown", C.c_int32),
+                ("status", C.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        path = _LIB_PATH if os.path.exists(_LIB_PATH) else build(force=False)
+        L = C.CDLL(path)
+        P = C.c_void_p
+        L.orc_create.restype = P
+        L.orc_create.argtypes = [C.POINTER(Options), C.c_int32, C.c_int32, C.c_int64, P, P, P, P, P]
+        L.orc_destroy.argtypes = [P]
+        L.orc_set_params.argtypes = [P, P, P]
+        L.orc_get_params.argtypes = [P, P, P]
+        L.orc_set_lambda.argtypes = [P, C.c_double]
+        L.orc_get_lambda.argtypes = [P]
+        L.orc_get_lambda.restype = C.c_double
+        L.orc_nnzb.argtypes = [P]
+        L.orc_nnzb.restype = C.c_int64
+        L.orc_cost.argtypes = [P, P, P]
+        L.orc_cost.restype = C.c_double
+        L.orc_compute_step.argtypes = [P, C.c_double, C.c_int32, C.POINTER(StepInfo)]
+        L.orc_lm_step.argtypes = [P, C.c_double, C.c_int32, C.POINTER(StepInfo)]
+        L.orc_get_linearization.argtypes = [P, P, P, P, P, P]
+        L.orc_get_normal.argtypes = [P, P, P, P, P]
+        L.orc_get_schur.argtypes = [P, P, P, P, P]
+        L.orc_get_step.argtypes = [P, P, P, P]
+        L.orc_project.argtypes = [P, P, C.c_int32, P, P, P]
+        L.orc_project.restype = C.c_double
+        L.orc_retract_camera.argtypes = [P, P, C.c_int32, P]
+        _lib = L
+    return _lib
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p) if a is not None else None
+
+
+def project(cam, X, d: int = 9):
+    """(pixel[2], Jc[2,d], Jp[2,3], Y_z) of one observation."""
+    cam = np.ascontiguousarray(cam, np.float64)
+    X = np.ascontiguousarray(X, np.float64)
+    pix = np.zeros(2)
+    Jc = np.zeros((2, d))
+    Jp = np.zeros((2, 3))
+    yz = lib().orc_project(_p(cam), _p(X), d, _p(pix), _p(Jc), _p(Jp))
+    return pix, Jc, Jp, yz
+
+
+def retract_camera(cam, delta, d: int = 9):
+    cam = np.ascontiguousarray(cam, np.float64)
+    delta = np.ascontiguousarray(delta, np.float64)
+    out = np.zeros(10)
+    lib().orc_retract_camera(_p(cam), _p(delta), d, _p(out))
+    return out
+
+
+@dataclass
+class OracleOptions:
+    d: int = 9
+    huber_delta: float = 0.0
+    cg_rtol: float = 1e-4
+    cg_maxiter: int = 250
+    lambda0: float = 1e-4
+    lambda_min: float = 1e-12
+    lambda_max: float = 1e12
+    diag_min: float = 1e-6
+    diag_max: float = 1e32
+
+    def c(self) -> Options:
+        return Options(self.d, self.huber_delta, self.cg_rtol, self.cg_maxiter, self.lambda0,
+                       self.lambda_min, self.lambda_max, self.diag_min, self.diag_max)
+
+
+class Oracle:
+    """One BA problem held by the C oracle."""
+
+    def __init__(self, n_cams, n_pts, cam_idx, pt_idx, obs, obs_w=None, fixed=None,
+                 options: OracleOptions | None = None):
+        self.opt = options or OracleOptions()
+        self.d = self.opt.d
+        self.nc, self.np = int(n_cams), int(n_pts)
+        self._cidx = np.ascontiguousarray(cam_idx, np.int32)
+        self._pidx = np.ascontiguousarray(pt_idx, np.int32)
+        self.no = int(self._cidx.size)
+        self._obs = np.ascontiguousarray(obs, np.float64).reshape(self.no, 2)
+        self._w = None if obs_w is None else np.ascontiguousarray(obs_w, np.float64)
+        fx = np.zeros(self.nc, np.uint8)
+        if fixed is not None and len(fixed):
+            fx[np.asarray(fixed)] = 1
+        self._fixed = fx
+        self._copt = self.opt.c()
+        self._h = lib().orc_create(C.byref(self._copt), self.nc, self.np, self.no,
+                                   _p(self._cidx), _p(self._pidx), _p(self._obs),
+                                   _p(self._w), _p(self._fixed))
+
+    @classmethod
+    def from_scene(cls, scene, **kw):
+        opt = kw.pop("options", None) or OracleOptions(huber_delta=scene.huber_delta)
+        o = cls(scene.n_cams, scene.n_pts, scene.cam_idx, scene.pt_idx, scene.obs,
+                scene.obs_w, scene.fixed_cams, options=opt, **kw)
+        o.set_params(scene.cams0, scene.pts0)
+        return o
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            lib().orc_destroy(h)
+            self._h = None
+
+    def set_params(self, cams, pts):
+        cams = np.ascontiguousarray(cams, np.float64)
+        pts = np.ascontiguousarray(pts, np.float64)
+        lib().orc_set_params(self._h, _p(cams), _p(pts))
+
+    def get_params(self):
+        cams = np.zeros((self.nc, 10))
+        pts = np.zeros((self.np, 3))
+        lib().orc_get_params(self._h, _p(cams), _p(pts))
+        return cams, pts
+
+    @property
+    def lam(self) -> float:
+        return lib().orc_get_lambda(self._h)
+
+    @lam.setter
+    def lam(self, v: float):
+        lib().orc_set_lambda(self._h, float(v))
+
+    def cost(self, cams=None, pts=None) -> float:
+        if cams is None:
+            cams, pts = self.get_params()
+        cams = np.ascontiguousarray(cams, np.float64)
+        pts = np.ascontiguousarray(pts, np.float64)
+        return lib().orc_cost(self._h, _p(cams), _p(pts))
+
+    def compute_step(self, rtol: float = -1.0, maxiter: int = -1) -> dict:
+        info = StepInfo()
+        lib().orc_compute_step(self._h, rtol, maxiter, C.byref(info))
+        return info.as_dict()
+
+    def lm_step(self, rtol: float = -1.0, maxiter: int = -1) -> dict:
+        info = StepInfo()
+        lib().orc_lm_step(self._h, rtol, maxiter, C.byref(info))
+        return info.as_dict()
+
+    def linearization(self):
+        r = np.zeros((self.no, 2))
+        w = np.zeros(self.no)
+        Jc = np.zeros((self.no, 2, self.d))
+        Jp = np.zeros((self.no, 2, 3))
+        F = C.c_double()
+        lib().orc_get_linearization(self._h, _p(r), _p(w), _p(Jc), _p(Jp), C.byref(F))
+        return r, w, Jc, Jp, F.value
+
+    def normal(self):
+        d = self.d
+        U = np.zeros((self.nc, d, d))
+        V = np.zeros((self.np, 3, 3))
+        gc = np.zeros((self.nc, d))
+        gp = np.zeros((self.np, 3))
+        lib().orc_get_normal(self._h, _p(U), _p(V), _p(gc), _p(gp))
+        return U, V, gc, gp
+
+    def nnzb(self) -> int:
+        return int(lib().orc_nnzb(self._h))
+
+    def schur(self):
+        d = self.d
+        nnzb = self.nnzb()
+        ptr = np.zeros(self.nc + 1, np.int64)
+        col = np.zeros(nnzb, np.int32)
+        S = np.zeros((nnzb, d, d))
+        bS = np.zeros((self.nc, d))
+        lib().orc_get_schur(self._h, _p(ptr), _p(col), _p(S), _p(bS))
+        return ptr, col, S, bS
+
+    def step(self):
+        dc = np.zeros((self.nc, self.d))
+        dp = np.zeros((self.np, 3))
+        Vinv = np.zeros((self.np, 3, 3))
+        lib().orc_get_step(self._h, _p(dc), _p(dp), _p(Vinv))
+        return dc, dp, Vinv
