@@ -1,0 +1,212 @@
+/*
+ * ba.h -- C ABI of the MI355X (gfx950) bundle-adjustment hot path.
+ *
+ * One Levenberg-Marquardt iteration of bundle adjustment ("Bundle Adjustment
+ * in the Eager Mode", Alg. 1 and Eq. 2): per-observation reprojection
+ * residuals and Jacobian blocks (Eq. 1, Sec. III-C), block-sparse J^T J and
+ * J^T r assembly (Sec. IV-B-1, IV-B-2), clamped diagonal damping (Sec.
+ * IV-B-3), the Schur complement of the damped system onto the cameras, a
+ * block-Jacobi preconditioned conjugate-gradient solve (Sec. IV-C-2),
+ * back-substitution of the points and the trust-region acceptance of the
+ * step (Sec. V).
+ *
+ * Conventions shared by every entry point
+ *  - Pointers marked "device" address memory on the GPU the problem was bound
+ *    to; "host" pointers address ordinary CPU memory.  Sizes are element
+ *    counts unless named *_bytes.
+ *  - Camera rows are 10 float64: [tx ty tz qx qy qz qw f k1 k2]; the pose maps
+ *    world to camera, Y = R(q) X + t, q a unit quaternion stored scalar-last;
+ *    pixel = f (1 + k1 s + k2 s^2) (-Y_x/Y_z, -Y_y/Y_z), s the squared norm of
+ *    the normalised coordinates (the projection of Eq. 1 with the BAL camera
+ *    used by the paper's benchmark).  Points are 3 float64 in world frame.
+ *  - Camera steps use the 9-dimensional tangent (rho, phi, df, dk1, dk2):
+ *    T <- Exp(rho, phi) T on SE(3) (left update; the pose gradient space has 6
+ *    degrees of freedom, Sec. III-C footnote), intrinsics additive.
+ *  - The library owns no device memory: the caller provides one device
+ *    workspace (ba_problem_bind) and keeps it alive until destroy.  The
+ *    library allocates only small pinned host staging buffers.
+ *  - All device work is enqueued on the stream given to ba_problem_bind.  A
+ *    handle is not thread-safe; one problem per stream.
+ *  - Errors are returned as ba_status; nothing aborts.  ba_last_error() gives a
+ *    message for the calling thread's most recent failure.
+ */
+#ifndef BA_H
+#define BA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ba_problem ba_problem;
+
+typedef enum {
+  BA_OK = 0,
+  BA_EINVAL = -1,        /* bad argument: null pointer, size, index out of range,
+                            non-finite observation, weight <= 0, short workspace */
+  BA_ENUMERIC = -2,      /* non-finite cost or a non-positive-definite block at
+                            the current parameters; parameters are unchanged */
+  BA_EHIP = -3,          /* a HIP runtime call failed */
+  BA_ENOTCONV = -4,      /* ba_solve: damping reached lambda_max on a rejected step */
+  BA_ESTATE = -5,        /* call out of order (not bound, no observations, ...) */
+  BA_EUNSUPPORTED = -6   /* option or problem shape this build does not handle */
+} ba_status;
+
+enum { BA_FP64 = 0, BA_MIXED = 1 };
+
+/* Solver options.  Defaults (ba_default_options) follow the paper's minimum
+ * example (Sec. V: PCG(tol=1e-4, maxiter=250), TrustRegion(up=2, down=1/16));
+ * the values the paper leaves open (initial damping, clamp range, lambda
+ * bounds) are this library's choice. */
+typedef struct {
+  int32_t cam_dof;     /* camera tangent size; only 9 is supported */
+  int32_t precision;   /* BA_FP64: every stored quantity FP64.
+                          BA_MIXED: Jacobian blocks and the reduced camera
+                          matrix stored FP32 (arithmetic stays FP64; costs,
+                          reductions, point blocks and CG vectors are FP64) */
+  double huber_delta;  /* > 0: Huber loss on the squared residual norm with this
+                          threshold in pixels; <= 0: plain squared loss */
+  double cg_rtol;      /* PCG stops when |b - S x| <= cg_rtol |b| (relative) */
+  int32_t cg_maxiter;  /* and after at most this many iterations */
+  double lambda0, lambda_min, lambda_max;
+  double diag_min, diag_max; /* clamp range of the damped diagonal */
+} ba_options;
+
+/* Per-iteration report (host struct). */
+typedef struct {
+  double cost_before;   /* F(theta) = 1/2 sum_k w_k rho(|r_k|^2) */
+  double cost_after;    /* F(theta (+) delta) */
+  double lambda_used;   /* damping of this step */
+  double lambda_next;   /* damping after the trust-region update */
+  double cg_rel_resid;  /* final |b - S x| / |b| of the PCG */
+  double pred;          /* predicted reduction of the Gauss-Newton model */
+  double grad_inf;      /* max-norm of the gradient J^T W r at theta */
+  int32_t accepted;     /* 1 if theta moved */
+  int32_t cg_iters;
+  int32_t cg_breakdown; /* 1 if p^T S p <= 0 stopped the PCG */
+  int32_t status;       /* ba_status of the step */
+} ba_step_info;
+
+/* Fills *opt with the defaults: cam_dof 9, BA_FP64, squared loss, cg_rtol 1e-4,
+ * cg_maxiter 250, lambda0 1e-4, lambda in [1e-12, 1e12], clamp [1e-6, 1e32]. */
+void ba_default_options(ba_options* opt);
+
+/* Creates a problem from the observation pattern: observation k sees point
+ * pt_idx[k] in camera cam_idx[k] (the index tensors of Sec. V's minimum
+ * example).  cam_idx, pt_idx: host int32 arrays of n_obs entries; copied.
+ * Runs the symbolic analysis once (the cached sparsity structure of
+ * Sec. IV-B-1): observation ordering, the block pattern of the reduced camera
+ * matrix and the table of observation pairs that feed each block.  No device
+ * work is done.  Errors: BA_EINVAL for sizes <= 0 or indices out of range,
+ * BA_EUNSUPPORTED for cam_dof != 9 or a point seen more than 256 times. */
+ba_status ba_problem_create(const ba_options* opt, int32_t n_cams, int32_t n_pts, int64_t n_obs,
+                            const int32_t* cam_idx, const int32_t* pt_idx, ba_problem** out);
+
+/* Exact device workspace size in bytes needed by ba_problem_bind. */
+ba_status ba_problem_workspace_bytes(const ba_problem* p, size_t* bytes);
+
+/* Binds the caller's device workspace (>= workspace_bytes, 256-byte aligned)
+ * and HIP stream (hipStream_t, NULL = default stream) on the current device,
+ * and uploads the symbolic structure.  The workspace stays owned by the
+ * caller and must outlive the problem.  Errors: BA_EINVAL (null/short/
+ * misaligned workspace), BA_EHIP. */
+ba_status ba_problem_bind(ba_problem* p, void* workspace, size_t bytes, void* hip_stream);
+
+/* Sets the observed pixels.  obs_xy: device float64 [n_obs][2] (x, y) in the
+ * creation order; obs_w: device float64 [n_obs] per-observation weights
+ * omega_k > 0, or NULL for all ones.  Copied (the caller may free them).
+ * Errors: BA_EINVAL for non-finite pixels or weights <= 0 (checked with one
+ * stream synchronisation). */
+ba_status ba_set_observations(ba_problem* p, const double* obs_xy, const double* obs_w);
+
+/* Marks cameras whose parameters stay fixed (gauge anchors): mask_host is a
+ * host uint8 array of n_cams entries, nonzero = fixed; NULL clears. */
+ba_status ba_set_fixed_cameras(ba_problem* p, const uint8_t* mask_host);
+
+/* Sets / reads the parameters theta: cams device float64 [n_cams][10], pts
+ * device float64 [n_pts][3].  set copies and invalidates the linearisation. */
+ba_status ba_set_params(ba_problem* p, const double* cams, const double* pts);
+ba_status ba_get_params(const ba_problem* p, double* cams, double* pts);
+
+/* Damping for the next step, and PCG stopping rule overrides (rtol >= 0,
+ * maxiter >= 1); rtol = 0 with a fixed maxiter pins the CG iteration count. */
+ba_status ba_set_lambda(ba_problem* p, double lambda);
+ba_status ba_get_lambda(const ba_problem* p, double* lambda);
+ba_status ba_set_cg(ba_problem* p, double rtol, int32_t maxiter);
+
+/* One LM iteration (Alg. 1): linearise at theta unless the previous step was
+ * rejected (then the linearisation is reused), damp, reduce onto the cameras,
+ * PCG, back-substitute, evaluate the candidate, accept or reject and update
+ * lambda (accept iff F' < F, F' finite and pred > 0; ratio > 0.75 halves
+ * lambda, ratio <= 0.25 or a rejection multiplies it by 16).  info: host, may
+ * be NULL.  Synchronises the stream once.  Errors: BA_ESTATE before
+ * bind/observations/params, BA_ENUMERIC (theta and lambda unchanged). */
+ba_status ba_lm_step(ba_problem* p, ba_step_info* info);
+
+/* Repeats ba_lm_step until max_iters iterations, or plateau_steps consecutive
+ * iterations with relative decrease (F - F')/F < rel_decrease_tol (Sec. V,
+ * StopOnPlateau), or |g|_inf <= 1e-12 (1 + F).  infos: host array of
+ * max_iters entries or NULL; *iters_done (host, may be NULL) receives the
+ * number of iterations run.  Returns BA_ENOTCONV when a step is rejected at
+ * lambda_max. */
+ba_status ba_solve(ba_problem* p, int32_t max_iters, double rel_decrease_tol, int32_t plateau_steps,
+                   ba_step_info* infos, int32_t* iters_done);
+
+/* Gradient of a loss of the optimum with respect to the observations and
+ * weights (implicit-function adjoint).  Not available in this build:
+ * returns BA_EUNSUPPORTED. */
+ba_status ba_backward(ba_problem* p, const double* dL_dcams, const double* dL_dpts, double* dL_dobs,
+                      double* dL_dw);
+
+/* Host snapshot of (theta, lambda) for checkpoint / resume.  With host_blob ==
+ * NULL, *bytes receives the size; otherwise *bytes must be at least that. */
+ba_status ba_get_state(const ba_problem* p, void* host_blob, size_t* bytes);
+ba_status ba_set_state(ba_problem* p, const void* host_blob, size_t bytes);
+
+/* Reads an intermediate quantity of the most recent step into host memory
+ * (for inspection and tests), in creation order for per-observation fields:
+ *   BA_X_RESIDUAL  float64 [n_obs][2]   r_k = pixel - observation
+ *   BA_X_WEIGHT    float64 [n_obs]      w_k = omega_k rho'(|r_k|^2)
+ *   BA_X_JC        float64 [n_obs][2][9]
+ *   BA_X_JP        float64 [n_obs][2][3]
+ *   BA_X_COST      float64 [1]          F at the linearisation point
+ *   BA_X_GRAD_C    float64 [n_cams][9]; BA_X_GRAD_P float64 [n_pts][3]
+ *   BA_X_V         float64 [n_pts][3][3] undamped point blocks
+ *   BA_X_S_PTR     int64 [n_cams+1]; BA_X_S_COL int32 [nnzb]
+ *   BA_X_S         float64 [nnzb][9][9] reduced camera matrix, upper blocks
+ *   BA_X_BS        float64 [n_cams][9]  its right-hand side
+ *   BA_X_DC        float64 [n_cams][9]; BA_X_DP float64 [n_pts][3] the step
+ * bytes must equal the field's size.  Synchronises the stream. */
+enum {
+  BA_X_RESIDUAL = 1, BA_X_WEIGHT, BA_X_JC, BA_X_JP, BA_X_COST, BA_X_GRAD_C, BA_X_GRAD_P,
+  BA_X_V, BA_X_S_PTR, BA_X_S_COL, BA_X_S, BA_X_BS, BA_X_DC, BA_X_DP
+};
+ba_status ba_export(const ba_problem* p, int32_t field, void* host_dst, size_t bytes);
+
+/* Per-phase timing with HIP events recorded on the problem's stream around
+ * every kernel launch of ba_lm_step (off by default).  Phases:
+ *   0 linearise (residuals, Jacobian blocks, point blocks), 1 cost reduction,
+ *   2 point damping and inverses, 3 per-observation Schur factors,
+ *   4 camera gradient / right-hand side, 5 Schur blocks from the pair table,
+ *   6 diagonal damping and block-Jacobi factors, 7 PCG, 8 back-substitution,
+ *   9 camera retraction, 10 candidate cost, 11 acceptance.
+ * ba_get_phase_times writes, for the first n phases, the summed milliseconds
+ * (ms_out) and the number of launches (launches_out, may be NULL) since
+ * profiling was last enabled. */
+enum { BA_NUM_PHASES = 12 };
+ba_status ba_set_profiling(ba_problem* p, int32_t enable);
+ba_status ba_get_phase_times(const ba_problem* p, double* ms_out, int64_t* launches_out, int32_t n);
+
+/* Number of stored upper blocks of the reduced camera matrix (incl. diagonal). */
+ba_status ba_problem_nnzb(const ba_problem* p, int64_t* nnzb);
+
+void ba_problem_destroy(ba_problem* p);
+const char* ba_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BA_H */

@@ -1,0 +1,361 @@
+"""Python binding of the C ABI in include/ba.h (argument marshalling only).
+
+Every step of the LM iteration runs in the gfx950 kernels of libba.so; this
+module only converts arguments.  PyTorch provides the device memory (one
+workspace tensor per problem) and the HIP stream.  Loading fails loudly if
+the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libba.so")
+
+BA_OK, BA_EINVAL, BA_ENUMERIC, BA_EHIP, BA_ENOTCONV, BA_ESTATE, BA_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+BA_FP64, BA_MIXED = 0, 1
+(BA_X_RESIDUAL, BA_X_WEIGHT, BA_X_JC, BA_X_JP, BA_X_COST, BA_X_GRAD_C, BA_X_GRAD_P, BA_X_V,
+ BA_X_S_PTR, BA_X_S_COL, BA_X_S, BA_X_BS, BA_X_DC, BA_X_DP) = range(1, 15)
+
+EXPORTED_SYMBOLS = [
+    "ba_default_options", "ba_problem_create", "ba_problem_workspace_bytes", "ba_problem_bind",
+    "ba_set_observations", "ba_set_fixed_cameras", "ba_set_params", "ba_get_params",
+    "ba_set_lambda", "ba_get_lambda", "ba_set_cg", "ba_lm_step", "ba_solve", "ba_backward",
+    "ba_get_state", "ba_set_state", "ba_export", "ba_problem_nnzb", "ba_set_profiling",
+    "ba_get_phase_times", "ba_problem_destroy", "ba_last_error",
+]
+BA_NUM_PHASES = 12
+PHASE_NAMES = ["linearize", "reduce_cost", "damp_points", "point_q", "camera_vec", "schur_pairs",
+               "camera_finish", "pcg", "backsub", "retract_cameras", "candidate_cost", "finalize"]
+
+
+class BaError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"ba status {status}: {msg}")
+        self.status = status
+
+
+class ba_options(C.Structure):
+    _fields_ = [("cam_dof", C.c_int32), ("precision", C.c_int32), ("huber_delta", C.c_double),
+                ("cg_rtol", C.c_double), ("cg_maxiter", C.c_int32), ("lambda0", C.c_double),
+                ("lambda_min", C.c_double), ("lambda_max", C.c_double), ("diag_min", C.c_double),
+                ("diag_max", C.c_double)]
+
+
+class ba_step_info(C.Structure):
+    _fields_ = [("cost_before", C.c_double), ("cost_after", C.c_double),
+                ("lambda_used", C.c_double), ("lambda_next", C.c_double),
+                ("cg_rel_resid", C.c_double), ("pred", C.c_double), ("grad_inf", C.c_double),
+                ("accepted", C.c_int32), ("cg_iters", C.c_int32), ("cg_breakdown", C.c_int32),
+                ("status", C.c_int32)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libba.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
+        L = C.CDLL(LIB_PATH)
+        P, S = C.c_void_p, C.c_int
+        L.ba_default_options.argtypes = [C.POINTER(ba_options)]
+        L.ba_default_options.restype = None
+        L.ba_problem_create.argtypes = [C.POINTER(ba_options), C.c_int32, C.c_int32, C.c_int64, P, P,
+                                        C.POINTER(P)]
+        L.ba_problem_workspace_bytes.argtypes = [P, C.POINTER(C.c_size_t)]
+        L.ba_problem_bind.argtypes = [P, P, C.c_size_t, P]
+        L.ba_set_observations.argtypes = [P, P, P]
+        L.ba_set_fixed_cameras.argtypes = [P, P]
+        L.ba_set_params.argtypes = [P, P, P]
+        L.ba_get_params.argtypes = [P, P, P]
+        L.ba_set_lambda.argtypes = [P, C.c_double]
+        L.ba_get_lambda.argtypes = [P, C.POINTER(C.c_double)]
+        L.ba_set_cg.argtypes = [P, C.c_double, C.c_int32]
+        L.ba_lm_step.argtypes = [P, C.POINTER(ba_step_info)]
+        L.ba_solve.argtypes = [P, C.c_int32, C.c_double, C.c_int32, C.POINTER(ba_step_info),
+                               C.POINTER(C.c_int32)]
+        L.ba_backward.argtypes = [P, P, P, P, P]
+        L.ba_get_state.argtypes = [P, P, C.POINTER(C.c_size_t)]
+        L.ba_set_state.argtypes = [P, P, C.c_size_t]
+        L.ba_export.argtypes = [P, C.c_int32, P, C.c_size_t]
+        L.ba_problem_nnzb.argtypes = [P, C.POINTER(C.c_int64)]
+        L.ba_set_profiling.argtypes = [P, C.c_int32]
+        L.ba_get_phase_times.argtypes = [P, P, P, C.c_int32]
+        L.ba_problem_destroy.argtypes = [P]
+        L.ba_problem_destroy.restype = None
+        L.ba_last_error.argtypes = []
+        L.ba_last_error.restype = C.c_char_p
+        for name in EXPORTED_SYMBOLS:
+            if name not in ("ba_default_options", "ba_problem_destroy", "ba_last_error"):
+                getattr(L, name).restype = S
+        _lib = L
+    return _lib
+
+
+def _check(status: int):
+    if status != BA_OK:
+        raise BaError(status, lib().ba_last_error().decode())
+
+
+def _ptr(t) -> Optional[int]:
+    if t is None:
+        return None
+    if isinstance(t, np.ndarray):
+        return t.ctypes.data
+    return t.data_ptr()
+
+
+# ---- functions with the C names (marshalling only) ----------------------------
+
+def ba_default_options() -> ba_options:
+    o = ba_options()
+    lib().ba_default_options(C.byref(o))
+    return o
+
+
+def ba_problem_create(opt: ba_options, n_cams: int, n_pts: int, cam_idx, pt_idx) -> int:
+    ci = np.ascontiguousarray(cam_idx, np.int32)
+    pi = np.ascontiguousarray(pt_idx, np.int32)
+    if ci.shape != pi.shape:
+        raise ValueError("cam_idx and pt_idx differ in length")
+    h = C.c_void_p()
+    _check(lib().ba_problem_create(C.byref(opt), n_cams, n_pts, ci.size, ci.ctypes.data,
+                                   pi.ctypes.data, C.byref(h)))
+    return h.value
+
+
+def ba_problem_workspace_bytes(h: int) -> int:
+    n = C.c_size_t()
+    _check(lib().ba_problem_workspace_bytes(h, C.byref(n)))
+    return n.value
+
+
+def ba_problem_nnzb(h: int) -> int:
+    n = C.c_int64()
+    _check(lib().ba_problem_nnzb(h, C.byref(n)))
+    return n.value
+
+
+def ba_problem_bind(h: int, workspace_ptr: int, nbytes: int, stream_ptr: Optional[int]):
+    _check(lib().ba_problem_bind(h, workspace_ptr, nbytes, stream_ptr))
+
+
+def ba_set_observations(h: int, obs_xy, obs_w=None):
+    _check(lib().ba_set_observations(h, _ptr(obs_xy), _ptr(obs_w)))
+
+
+def ba_set_fixed_cameras(h: int, mask: Optional[np.ndarray]):
+    m = None if mask is None else np.ascontiguousarray(mask, np.uint8)
+    _check(lib().ba_set_fixed_cameras(h, None if m is None else m.ctypes.data))
+
+
+def ba_set_params(h: int, cams, pts):
+    _check(lib().ba_set_params(h, _ptr(cams), _ptr(pts)))
+
+
+def ba_get_params(h: int, cams, pts):
+    _check(lib().ba_get_params(h, _ptr(cams), _ptr(pts)))
+
+
+def ba_set_lambda(h: int, lam: float):
+    _check(lib().ba_set_lambda(h, lam))
+
+
+def ba_get_lambda(h: int) -> float:
+    v = C.c_double()
+    _check(lib().ba_get_lambda(h, C.byref(v)))
+    return v.value
+
+
+def ba_set_cg(h: int, rtol: float, maxiter: int):
+    _check(lib().ba_set_cg(h, rtol, maxiter))
+
+
+def ba_lm_step(h: int) -> dict:
+    info = ba_step_info()
+    st = lib().ba_lm_step(h, C.byref(info))
+    d = info.as_dict()
+    d["status"] = st
+    if st != BA_OK and st != BA_ENUMERIC:
+        _check(st)
+    return d
+
+
+def ba_solve(h: int, max_iters: int, rel_tol: float = 1e-6, plateau_steps: int = 5):
+    infos = (ba_step_info * max(1, max_iters))()
+    done = C.c_int32()
+    st = lib().ba_solve(h, max_iters, rel_tol, plateau_steps, infos, C.byref(done))
+    return st, [infos[i].as_dict() for i in range(done.value)]
+
+
+def ba_backward(h: int, dL_dcams, dL_dpts, dL_dobs, dL_dw=None):
+    _check(lib().ba_backward(h, _ptr(dL_dcams), _ptr(dL_dpts), _ptr(dL_dobs), _ptr(dL_dw)))
+
+
+def ba_get_state(h: int) -> bytes:
+    n = C.c_size_t()
+    _check(lib().ba_get_state(h, None, C.byref(n)))
+    buf = C.create_string_buffer(n.value)
+    _check(lib().ba_get_state(h, buf, C.byref(n)))
+    return buf.raw
+
+
+def ba_set_state(h: int, blob: bytes):
+    buf = C.create_string_buffer(blob, len(blob))
+    _check(lib().ba_set_state(h, buf, len(blob)))
+
+
+def ba_export(h: int, field: int, out: np.ndarray) -> np.ndarray:
+    _check(lib().ba_export(h, field, out.ctypes.data, out.nbytes))
+    return out
+
+
+def ba_set_profiling(h: int, enable: bool):
+    _check(lib().ba_set_profiling(h, 1 if enable else 0))
+
+
+def ba_get_phase_times(h: int):
+    ms = np.zeros(BA_NUM_PHASES)
+    n = np.zeros(BA_NUM_PHASES, np.int64)
+    _check(lib().ba_get_phase_times(h, ms.ctypes.data, n.ctypes.data, BA_NUM_PHASES))
+    return ms, n
+
+
+def ba_problem_destroy(h: int):
+    lib().ba_problem_destroy(h)
+
+
+# ---- convenience wrapper holding the torch-owned memory -----------------------
+
+class Problem:
+    """One bundle-adjustment problem on the current CUDA (HIP) device.
+
+    cam_idx / pt_idx: host integer arrays; obs_xy: float64 [n_obs, 2] and
+    obs_w: float64 [n_obs] (or None), host or device; cams [n_cams, 10] and
+    pts [n_pts, 3] float64 initial parameters."""
+
+    def __init__(self, n_cams, n_pts, cam_idx, pt_idx, obs_xy, obs_w=None, *, precision=BA_FP64,
+                 huber_delta=0.0, cg_rtol=1e-4, cg_maxiter=250, lambda0=1e-4, fixed_cams=None,
+                 cams=None, pts=None, stream=None):
+        import torch
+        self.torch = torch
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        opt = ba_default_options()
+        opt.precision = precision
+        opt.huber_delta = huber_delta
+        opt.cg_rtol = cg_rtol
+        opt.cg_maxiter = cg_maxiter
+        opt.lambda0 = lambda0
+        self.opt = opt
+        self.n_cams, self.n_pts = int(n_cams), int(n_pts)
+        self.n_obs = int(np.asarray(cam_idx).size)
+        self.h = ba_problem_create(opt, self.n_cams, self.n_pts, cam_idx, pt_idx)
+        nbytes = ba_problem_workspace_bytes(self.h)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        if self.workspace.data_ptr() % 256:
+            raise RuntimeError("workspace allocation is not 256-byte aligned")
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        ba_problem_bind(self.h, self.workspace.data_ptr(), nbytes, self.stream.cuda_stream)
+        xy = self._dev(obs_xy).reshape(self.n_obs, 2)
+        w = None if obs_w is None else self._dev(obs_w).reshape(self.n_obs)
+        self.stream.synchronize()
+        ba_set_observations(self.h, xy, w)
+        if fixed_cams is not None and len(fixed_cams):
+            mask = np.zeros(self.n_cams, np.uint8)
+            mask[np.asarray(fixed_cams)] = 1
+            ba_set_fixed_cameras(self.h, mask)
+        if cams is not None:
+            self.set_params(cams, pts)
+
+    @classmethod
+    def from_scene(cls, scene, precision=BA_FP64, **kw):
+        kw.setdefault("huber_delta", scene.huber_delta)
+        return cls(scene.n_cams, scene.n_pts, scene.cam_idx, scene.pt_idx, scene.obs, scene.obs_w,
+                   precision=precision, fixed_cams=scene.fixed_cams, cams=scene.cams0,
+                   pts=scene.pts0, **kw)
+
+    def _dev(self, a):
+        t = self.torch
+        if isinstance(a, t.Tensor):
+            return a.to(self.device, t.float64).contiguous()
+        return t.as_tensor(np.ascontiguousarray(a, np.float64), device=self.device)
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h:
+            try:
+                self.stream.synchronize()
+            except Exception:
+                pass
+            ba_problem_destroy(h)
+            self.h = None
+
+    @property
+    def nnzb(self) -> int:
+        return ba_problem_nnzb(self.h)
+
+    def set_params(self, cams, pts):
+        c = self._dev(cams).reshape(self.n_cams, 10)
+        p = self._dev(pts).reshape(self.n_pts, 3)
+        self.stream.synchronize()
+        ba_set_params(self.h, c, p)
+        self.stream.synchronize()
+
+    def get_params(self):
+        t = self.torch
+        c = t.empty((self.n_cams, 10), dtype=t.float64, device=self.device)
+        p = t.empty((self.n_pts, 3), dtype=t.float64, device=self.device)
+        ba_get_params(self.h, c, p)
+        self.stream.synchronize()
+        return c, p
+
+    def set_lambda(self, lam):
+        ba_set_lambda(self.h, lam)
+
+    @property
+    def lam(self) -> float:
+        return ba_get_lambda(self.h)
+
+    def set_cg(self, rtol, maxiter):
+        ba_set_cg(self.h, rtol, maxiter)
+
+    def lm_step(self) -> dict:
+        return ba_lm_step(self.h)
+
+    def solve(self, max_iters, rel_tol=1e-6, plateau_steps=5):
+        return ba_solve(self.h, max_iters, rel_tol, plateau_steps)
+
+    def set_profiling(self, enable: bool = True):
+        ba_set_profiling(self.h, enable)
+
+    def phase_times(self) -> dict:
+        ms, n = ba_get_phase_times(self.h)
+        return {name: (float(ms[i]), int(n[i])) for i, name in enumerate(PHASE_NAMES)}
+
+    def get_state(self) -> bytes:
+        return ba_get_state(self.h)
+
+    def set_state(self, blob: bytes):
+        ba_set_state(self.h, blob)
+
+    def export(self, field: int) -> np.ndarray:
+        no, nc, np_, nz = self.n_obs, self.n_cams, self.n_pts, self.nnzb
+        shapes = {BA_X_RESIDUAL: ((no, 2), np.float64), BA_X_WEIGHT: ((no,), np.float64),
+                  BA_X_JC: ((no, 2, 9), np.float64), BA_X_JP: ((no, 2, 3), np.float64),
+                  BA_X_COST: ((1,), np.float64), BA_X_GRAD_C: ((nc, 9), np.float64),
+                  BA_X_GRAD_P: ((np_, 3), np.float64), BA_X_V: ((np_, 3, 3), np.float64),
+                  BA_X_S_PTR: ((nc + 1,), np.int64), BA_X_S_COL: ((nz,), np.int32),
+                  BA_X_S: ((nz, 9, 9), np.float64), BA_X_BS: ((nc, 9), np.float64),
+                  BA_X_DC: ((nc, 9), np.float64), BA_X_DP: ((np_, 3), np.float64)}
+        shape, dt = shapes[field]
+        return ba_export(self.h, field, np.zeros(shape, dt))

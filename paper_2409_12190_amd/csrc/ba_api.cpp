@@ -1,0 +1,663 @@
+// C ABI of the bundle-adjustment library: problem lifetime, workspace
+// carving, the LM iteration driver and read-back.  See include/ba.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "ba.h"
+#include "ba_internal.h"
+#include "ba_kernels.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+ba_status fail(ba_status s, const std::string& m) {
+  g_err = m;
+  return s;
+}
+
+#define HIPCHK(call)                                                                   \
+  do {                                                                                 \
+    hipError_t e_ = (call);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return fail(BA_EHIP, std::string(#call) + ": " + hipGetErrorString(e_));          \
+  } while (0)
+
+struct Carver {
+  char* base;
+  size_t off = 0;
+  template <class T>
+  T* take(size_t n) {
+    off = (off + 255) & ~size_t(255);
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += std::max<size_t>(n, 1) * sizeof(T);
+    return p;
+  }
+};
+
+size_t elem_bytes(const ba_problem* p) { return p->opt.precision == BA_MIXED ? 4 : 8; }
+
+void carve(ba_problem* p, char* base, size_t* total) {
+  Carver c{base};
+  const ba::Plan& P = p->plan;
+  ba::Buffers& b = p->b;
+  const size_t nc = P.nc, np = P.np, no = P.no, nnzb = P.nnzb;
+  const size_t nch = P.chunk_ptr.size() - 1;
+  const size_t es = elem_bytes(p);
+  b.o_cam = c.take<int32_t>(no);
+  b.o_pt = c.take<int32_t>(no);
+  b.pt_ptr = c.take<int32_t>(np + 1);
+  b.chunk_ptr = c.take<int32_t>(nch + 1);
+  b.chunk_pt = c.take<int32_t>(nch + 1);
+  b.cam_ptr = c.take<int32_t>(nc + 1);
+  b.cam_obs = c.take<int32_t>(no);
+  b.S_ptr = c.take<int32_t>(nc + 1);
+  b.S_col = c.take<int32_t>(nnzb);
+  b.T_ptr = c.take<int32_t>(nc + 1);
+  b.T_blk = c.take<int32_t>(P.T_blk.size());
+  b.T_src = c.take<int32_t>(P.T_src.size());
+  b.pair_x = c.take<int32_t>(P.n_pairs);
+  b.pair_y = c.take<int32_t>(P.n_pairs);
+  b.slot_blk = c.take<int32_t>(P.slot_blk.size());
+  b.slot_pb = c.take<int32_t>(P.slot_pb.size());
+  b.slot_pe = c.take<int32_t>(P.slot_pe.size());
+  b.slot_lead = c.take<int32_t>(P.slot_lead.size());
+  b.blk_row = c.take<int32_t>(nnzb);
+  b.o_orig = c.take<int64_t>(no);
+  b.fixed = c.take<uint8_t>(nc);
+  b.o_xy = c.take<double>(2 * no);
+  b.o_w = c.take<double>(no);
+  for (int i = 0; i < 2; ++i) {
+    b.cams[i] = c.take<double>(10 * nc);
+    b.pts[i] = c.take<double>(3 * np);
+  }
+  b.r = c.take<double>(2 * no);
+  b.w = c.take<double>(no);
+  b.J = c.take<char>(no * ba::NJ * es);
+  b.V = c.take<double>(6 * np);
+  b.gp = c.take<double>(3 * np);
+  b.gc = c.take<double>(9 * nc);
+  b.diagU = c.take<double>(9 * nc);
+  b.Vinv = c.take<double>(6 * np);
+  b.ep = c.take<double>(3 * np);
+  b.Q = c.take<char>(no * 6 * es);
+  b.S = c.take<char>(nnzb * 81 * es);
+  b.Sdiag = c.take<double>(81 * nc);
+  b.bS = c.take<double>(9 * nc);
+  b.Minv = c.take<double>(81 * nc);
+  b.x = c.take<double>(9 * nc);
+  b.dp = c.take<double>(3 * np);
+  b.part_cost = c.take<double>(nch);
+  b.part_cost_new = c.take<double>(nch);
+  b.part_pred = c.take<double>(2 * nch);
+  b.part_gmax = c.take<double>(nch);
+  b.part_linc = c.take<double>((nc + 255) / 256);
+  const ba::PcgShape sh = ba::pcg_shape(P.nc);
+  const size_t slots = (size_t)p->opt.cg_maxiter + 1;
+  b.zring = c.take<double>(slots * sh.grid * sh.seg);
+  b.partA = c.take<double>(slots * sh.grid * ba::PART_STRIDE);
+  b.partB = c.take<double>(slots * sh.grid * ba::PART_STRIDE);
+  b.dev = c.take<ba::DevScalars>(1);
+  b.dinfo = c.take<ba_step_info>(1);
+  b.gsync = c.take<ba::GridSync>(1);
+  *total = c.off + 256;
+}
+
+template <class T>
+hipError_t upload(T* dst, const std::vector<T>& src, hipStream_t s) {
+  if (src.empty()) return hipSuccess;
+  return hipMemcpyAsync(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, s);
+}
+
+ba_status require_ready(const ba_problem* p) {
+  if (!p) return fail(BA_EINVAL, "null problem");
+  if (!p->bound) return fail(BA_ESTATE, "problem is not bound to a workspace");
+  if (!p->have_obs) return fail(BA_ESTATE, "observations are not set");
+  if (!p->have_params) return fail(BA_ESTATE, "parameters are not set");
+  return BA_OK;
+}
+
+// Event-bracketed launch of one phase when profiling is on.
+struct Phase {
+  ba_problem* p;
+  int id;
+  Phase(ba_problem* pp, int i) : p(pp), id(i) {
+    if (p->profiling) (void)hipEventRecord(p->ev[id][0], p->stream);
+  }
+  ~Phase() {
+    if (p->profiling) {
+      (void)hipEventRecord(p->ev[id][1], p->stream);
+      p->phase_used[id] = true;
+    }
+  }
+};
+
+void collect_phase_times(ba_problem* p) {
+  if (!p->profiling) return;
+  for (int i = 0; i < BA_NUM_PHASES; ++i) {
+    if (!p->phase_used[i]) continue;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, p->ev[i][0], p->ev[i][1]) == hipSuccess) {
+      p->phase_ms[i] += ms;
+      p->phase_n[i] += 1;
+    }
+    p->phase_used[i] = false;
+  }
+}
+
+#define PHASE(id, call)          \
+  do {                           \
+    Phase ph_(p, id);            \
+    HIPCHK(call);                \
+  } while (0)
+
+template <typename T>
+ba_status lm_step_impl(ba_problem* p, ba_step_info* out) {
+  using namespace ba;
+  const Plan& P = p->plan;
+  Buffers& b = p->b;
+  hipStream_t s = p->stream;
+  const int nchunk = (int)P.chunk_ptr.size() - 1;
+  const int cur = p->cur, nxt = p->cur ^ 1;
+  const double lam_before = p->lambda;
+
+  if (!p->lin_valid) {
+    LinArgs la{b.chunk_ptr, b.chunk_pt, b.pt_ptr, b.o_cam, b.o_pt, b.fixed, b.o_xy, b.o_w,
+               b.cams[cur], b.pts[cur], p->opt.huber_delta, b.r, b.w, b.J, b.V, b.gp,
+               b.part_cost, b.part_gmax};
+    PHASE(0, launch_linearize<T>(la, nchunk, s));
+    PHASE(1, launch_reduce_cost(b.part_cost, nchunk, b.dev, s));
+  }
+  DampArgs da{P.np, b.V, b.gp, p->opt.diag_min, p->opt.diag_max, b.Vinv, b.ep, b.dev, b.gsync};
+  PHASE(2, launch_damp_points(da, s));
+  PointQArgs qa{P.no, b.o_pt, b.J, b.w, b.Vinv, b.Q};
+  PHASE(3, launch_point_q<T>(qa, s));
+  CamVecArgs cv{b.cam_ptr, b.cam_obs, b.o_pt, b.J, b.w, b.r, b.ep, b.gc, b.bS, b.diagU};
+  PHASE(4, launch_camera_vec<T>(cv, P.nc, s));
+  SchurArgs sa{b.slot_blk, b.slot_pb, b.slot_pe, b.slot_lead, b.pair_x, b.pair_y, b.blk_row,
+               b.S_ptr, b.J, b.Q, b.w, b.S, b.Sdiag};
+  PHASE(5, launch_schur_pairs<T>(sa, P.n_schur_wg, s));
+  CamFinishArgs cf{b.S_ptr, b.Sdiag, b.diagU, p->opt.diag_min, p->opt.diag_max, b.S, b.Minv, b.dev};
+  PHASE(6, launch_camera_finish<T>(cf, P.nc, s));
+  const PcgShape sh = pcg_shape(P.nc);
+  PcgArgs pa{P.nc, p->cg_maxiter, sh.rows, sh.seg, p->cg_rtol, b.S_ptr, b.S_col, b.T_ptr, b.T_blk,
+             b.T_src, b.S, b.Minv, b.bS, b.x, b.zring, b.partA, b.partB, b.dinfo, b.gsync,
+             &b.dev->error};
+  PHASE(7, launch_pcg<T>(pa, sh.grid, s));
+  BackArgs ba_{b.chunk_ptr, b.chunk_pt, b.pt_ptr, b.o_cam, b.o_pt, b.J, b.w, b.x, b.gp, b.Vinv,
+               b.pts[cur], b.dp, b.pts[nxt], b.part_pred};
+  PHASE(8, launch_backsub<T>(ba_, nchunk, s));
+  RetractArgs ra{P.nc, b.fixed, b.cams[cur], b.x, b.gc, b.cams[nxt], b.part_linc};
+  PHASE(9, launch_retract_cameras(ra, p->cam_blocks, s));
+  CostArgs co{b.chunk_ptr, b.o_cam, b.o_pt, b.o_xy, b.o_w, b.cams[nxt], b.pts[nxt],
+              p->opt.huber_delta, b.part_cost_new};
+  PHASE(10, launch_candidate_cost(co, nchunk, s));
+  FinalArgs fa{nchunk, p->cam_blocks, P.nc, b.part_cost_new, b.part_pred, b.part_linc, b.part_gmax,
+               b.gc, p->opt.lambda_min, p->opt.lambda_max, b.dev, b.dinfo};
+  PHASE(11, launch_finalize(fa, s));
+  HIPCHK(hipMemcpyAsync(p->hinfo, b.dinfo, sizeof(ba_step_info), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(p->hscal, b.dev, sizeof(DevScalars), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  collect_phase_times(p);
+
+  ba_step_info info = *p->hinfo;
+  const int32_t err = p->hscal->error;
+  if (err != 0 || !std::isfinite(info.cost_before)) {
+    // leave theta and lambda as they were
+    DevScalars restore{info.cost_before, lam_before, 0, 0};
+    *p->hscal = restore;
+    HIPCHK(hipMemcpyAsync(b.dev, p->hscal, sizeof(DevScalars), hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+    info.accepted = 0;
+    info.lambda_next = lam_before;
+    info.status = BA_ENUMERIC;
+    if (out) *out = info;
+    if (err & ERR_BARRIER) {
+      info.status = BA_EHIP;
+      if (out) *out = info;
+      return fail(BA_EHIP, "the PCG grid barrier timed out");
+    }
+    std::string why = !std::isfinite(info.cost_before) ? "non-finite cost at the current parameters"
+                      : (err & ERR_POINT_BLOCK)        ? "a damped point block is not positive definite"
+                                                       : "a diagonal camera block is not positive definite";
+    return fail(BA_ENUMERIC, why);
+  }
+  p->lin_valid = true;
+  if (info.accepted) {
+    p->cur = nxt;
+    p->lin_valid = false;
+  }
+  p->lambda = info.lambda_next;
+  if (out) *out = info;
+  return BA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void ba_default_options(ba_options* o) {
+  if (!o) return;
+  o->cam_dof = 9;
+  o->precision = BA_FP64;
+  o->huber_delta = 0.0;
+  o->cg_rtol = 1e-4;
+  o->cg_maxiter = 250;
+  o->lambda0 = 1e-4;
+  o->lambda_min = 1e-12;
+  o->lambda_max = 1e12;
+  o->diag_min = 1e-6;
+  o->diag_max = 1e32;
+}
+
+const char* ba_last_error(void) { return g_err.c_str(); }
+
+ba_status ba_problem_create(const ba_options* opt, int32_t n_cams, int32_t n_pts, int64_t n_obs,
+                            const int32_t* cam_idx, const int32_t* pt_idx, ba_problem** out) {
+  if (!out) return fail(BA_EINVAL, "out is null");
+  *out = nullptr;
+  if (!cam_idx || !pt_idx) return fail(BA_EINVAL, "index arrays must not be null");
+  ba_options o;
+  if (opt) o = *opt;
+  else ba_default_options(&o);
+  if (o.cam_dof != 9) return fail(BA_EUNSUPPORTED, "only cam_dof = 9 is supported");
+  if (o.precision != BA_FP64 && o.precision != BA_MIXED) return fail(BA_EINVAL, "unknown precision");
+  if (!(o.cg_rtol >= 0.0) || o.cg_maxiter < 1) return fail(BA_EINVAL, "bad CG options");
+  if (!(o.lambda0 > 0.0) || !(o.lambda_min > 0.0) || !(o.lambda_max >= o.lambda_min))
+    return fail(BA_EINVAL, "bad damping options");
+  if (!(o.diag_min > 0.0) || !(o.diag_max >= o.diag_min)) return fail(BA_EINVAL, "bad clamp range");
+  ba_problem* p = new (std::nothrow) ba_problem();
+  if (!p) return fail(BA_EINVAL, "out of host memory");
+  p->opt = o;
+  std::string err;
+  try {
+    err = ba::build_plan(n_cams, n_pts, n_obs, cam_idx, pt_idx, &p->plan);
+  } catch (const std::bad_alloc&) {
+    err = "out of host memory";
+  }
+  if (!err.empty()) {
+    delete p;
+    const bool unsup = err.find("at most") != std::string::npos;
+    return fail(unsup ? BA_EUNSUPPORTED : BA_EINVAL, err);
+  }
+  p->lambda = o.lambda0;
+  p->cg_rtol = o.cg_rtol;
+  p->cg_maxiter = o.cg_maxiter;
+  p->cam_blocks = (n_cams + 255) / 256;
+  carve(p, nullptr, &p->ws_needed);
+  *out = p;
+  return BA_OK;
+}
+
+ba_status ba_problem_workspace_bytes(const ba_problem* p, size_t* bytes) {
+  if (!p || !bytes) return fail(BA_EINVAL, "null argument");
+  *bytes = p->ws_needed;
+  return BA_OK;
+}
+
+ba_status ba_problem_nnzb(const ba_problem* p, int64_t* nnzb) {
+  if (!p || !nnzb) return fail(BA_EINVAL, "null argument");
+  *nnzb = p->plan.nnzb;
+  return BA_OK;
+}
+
+ba_status ba_problem_bind(ba_problem* p, void* ws, size_t bytes, void* stream) {
+  if (!p || !ws) return fail(BA_EINVAL, "null argument");
+  if (bytes < p->ws_needed) return fail(BA_EINVAL, "workspace too small");
+  if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(BA_EINVAL, "workspace not 256-byte aligned");
+  if (p->bound) return fail(BA_ESTATE, "problem already bound");
+  HIPCHK(hipGetDevice(&p->device));
+  p->stream = reinterpret_cast<hipStream_t>(stream);
+  p->workspace = ws;
+  p->ws_bytes = bytes;
+  size_t total = 0;
+  carve(p, reinterpret_cast<char*>(ws), &total);
+  const ba::Plan& P = p->plan;
+  ba::Buffers& b = p->b;
+  hipStream_t s = p->stream;
+  HIPCHK(upload(b.o_cam, P.o_cam, s));
+  HIPCHK(upload(b.o_pt, P.o_pt, s));
+  HIPCHK(upload(b.pt_ptr, P.pt_ptr, s));
+  HIPCHK(upload(b.chunk_ptr, P.chunk_ptr, s));
+  HIPCHK(upload(b.chunk_pt, P.chunk_pt, s));
+  HIPCHK(upload(b.cam_ptr, P.cam_ptr, s));
+  HIPCHK(upload(b.cam_obs, P.cam_obs, s));
+  HIPCHK(upload(b.S_ptr, P.S_ptr, s));
+  HIPCHK(upload(b.S_col, P.S_col, s));
+  HIPCHK(upload(b.T_ptr, P.T_ptr, s));
+  HIPCHK(upload(b.T_blk, P.T_blk, s));
+  HIPCHK(upload(b.T_src, P.T_src, s));
+  HIPCHK(upload(b.pair_x, P.pair_x, s));
+  HIPCHK(upload(b.pair_y, P.pair_y, s));
+  HIPCHK(upload(b.slot_blk, P.slot_blk, s));
+  HIPCHK(upload(b.slot_pb, P.slot_pb, s));
+  HIPCHK(upload(b.slot_pe, P.slot_pe, s));
+  HIPCHK(upload(b.slot_lead, P.slot_lead, s));
+  HIPCHK(upload(b.blk_row, P.blk_row, s));
+  HIPCHK(upload(b.o_orig, P.o_orig, s));
+  HIPCHK(hipMemsetAsync(b.fixed, 0, P.nc, s));
+  HIPCHK(hipMemsetAsync(b.gsync, 0, sizeof(ba::GridSync), s));
+  HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&p->hinfo), sizeof(ba_step_info), hipHostMallocDefault));
+  HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&p->hscal), sizeof(ba::DevScalars), hipHostMallocDefault));
+  *p->hscal = ba::DevScalars{0.0, p->lambda, 0, 0};
+  HIPCHK(hipMemcpyAsync(b.dev, p->hscal, sizeof(ba::DevScalars), hipMemcpyHostToDevice, s));
+  HIPCHK(hipStreamSynchronize(s));
+  const int maxg = p->opt.precision == BA_MIXED ? ba::pcg_max_grid<float>() : ba::pcg_max_grid<double>();
+  if (maxg <= 0) return fail(BA_EHIP, "cooperative occupancy query failed");
+  p->pcg_grid = ba::pcg_shape(P.nc).grid;
+  if (p->pcg_grid > maxg || p->pcg_grid > ba::MAX_BARRIER_GROUPS * ba::BARRIER_FANIN)
+    return fail(BA_EUNSUPPORTED, "too many cameras for one co-resident PCG grid");
+  p->bound = true;
+  return BA_OK;
+}
+
+ba_status ba_set_observations(ba_problem* p, const double* xy, const double* w) {
+  if (!p || !xy) return fail(BA_EINVAL, "null argument");
+  if (!p->bound) return fail(BA_ESTATE, "problem is not bound");
+  ba::ObsArgs a{p->plan.no, p->b.o_orig, xy, w, p->b.o_xy, p->b.o_w, p->b.dev};
+  HIPCHK(ba::launch_set_observations(a, p->stream));
+  HIPCHK(hipMemcpyAsync(p->hscal, p->b.dev, sizeof(ba::DevScalars), hipMemcpyDeviceToHost, p->stream));
+  HIPCHK(hipStreamSynchronize(p->stream));
+  const int32_t err = p->hscal->error;
+  if (err) {
+    p->hscal->error = 0;
+    HIPCHK(hipMemcpyAsync(p->b.dev, p->hscal, sizeof(ba::DevScalars), hipMemcpyHostToDevice, p->stream));
+    HIPCHK(hipStreamSynchronize(p->stream));
+    p->have_obs = false;
+    return fail(BA_EINVAL, (err & ba::ERR_NONFINITE_OBS) ? "non-finite observation" : "observation weight <= 0");
+  }
+  p->have_obs = true;
+  p->lin_valid = false;
+  return BA_OK;
+}
+
+ba_status ba_set_fixed_cameras(ba_problem* p, const uint8_t* mask) {
+  if (!p) return fail(BA_EINVAL, "null problem");
+  if (!p->bound) return fail(BA_ESTATE, "problem is not bound");
+  std::vector<uint8_t> m(p->plan.nc, 0);
+  if (mask)
+    for (int32_t i = 0; i < p->plan.nc; ++i) m[i] = mask[i] ? 1 : 0;
+  HIPCHK(hipMemcpyAsync(p->b.fixed, m.data(), m.size(), hipMemcpyHostToDevice, p->stream));
+  HIPCHK(hipStreamSynchronize(p->stream));
+  p->lin_valid = false;
+  return BA_OK;
+}
+
+ba_status ba_set_params(ba_problem* p, const double* cams, const double* pts) {
+  if (!p || !cams || !pts) return fail(BA_EINVAL, "null argument");
+  if (!p->bound) return fail(BA_ESTATE, "problem is not bound");
+  HIPCHK(hipMemcpyAsync(p->b.cams[p->cur], cams, sizeof(double) * 10 * p->plan.nc,
+                        hipMemcpyDeviceToDevice, p->stream));
+  HIPCHK(hipMemcpyAsync(p->b.pts[p->cur], pts, sizeof(double) * 3 * p->plan.np,
+                        hipMemcpyDeviceToDevice, p->stream));
+  p->have_params = true;
+  p->lin_valid = false;
+  return BA_OK;
+}
+
+ba_status ba_get_params(const ba_problem* p, double* cams, double* pts) {
+  if (!p) return fail(BA_EINVAL, "null problem");
+  if (!p->bound || !p->have_params) return fail(BA_ESTATE, "parameters are not set");
+  if (cams)
+    HIPCHK(hipMemcpyAsync(cams, p->b.cams[p->cur], sizeof(double) * 10 * p->plan.nc,
+                          hipMemcpyDeviceToDevice, p->stream));
+  if (pts)
+    HIPCHK(hipMemcpyAsync(pts, p->b.pts[p->cur], sizeof(double) * 3 * p->plan.np,
+                          hipMemcpyDeviceToDevice, p->stream));
+  return BA_OK;
+}
+
+ba_status ba_set_lambda(ba_problem* p, double lambda) {
+  if (!p || !(lambda > 0.0)) return fail(BA_EINVAL, "lambda must be positive");
+  if (!p->bound) return fail(BA_ESTATE, "problem is not bound");
+  HIPCHK(hipMemcpyAsync(p->hscal, p->b.dev, sizeof(ba::DevScalars), hipMemcpyDeviceToHost, p->stream));
+  HIPCHK(hipStreamSynchronize(p->stream));
+  p->hscal->lambda = lambda;
+  HIPCHK(hipMemcpyAsync(p->b.dev, p->hscal, sizeof(ba::DevScalars), hipMemcpyHostToDevice, p->stream));
+  HIPCHK(hipStreamSynchronize(p->stream));
+  p->lambda = lambda;
+  return BA_OK;
+}
+
+ba_status ba_get_lambda(const ba_problem* p, double* lambda) {
+  if (!p || !lambda) return fail(BA_EINVAL, "null argument");
+  *lambda = p->lambda;
+  return BA_OK;
+}
+
+ba_status ba_set_cg(ba_problem* p, double rtol, int32_t maxiter) {
+  if (!p || !(rtol >= 0.0) || maxiter < 1) return fail(BA_EINVAL, "bad CG settings");
+  if (maxiter > p->opt.cg_maxiter)
+    return fail(BA_EINVAL, "maxiter exceeds the cg_maxiter the problem was created with");
+  p->cg_rtol = rtol;
+  p->cg_maxiter = maxiter;
+  return BA_OK;
+}
+
+ba_status ba_lm_step(ba_problem* p, ba_step_info* info) {
+  ba_status st = require_ready(p);
+  if (st != BA_OK) return st;
+  return p->opt.precision == BA_MIXED ? lm_step_impl<float>(p, info) : lm_step_impl<double>(p, info);
+}
+
+ba_status ba_solve(ba_problem* p, int32_t max_iters, double rel_tol, int32_t plateau_steps,
+                   ba_step_info* infos, int32_t* iters_done) {
+  ba_status st = require_ready(p);
+  if (st != BA_OK) return st;
+  if (max_iters < 0 || plateau_steps < 1) return fail(BA_EINVAL, "bad stopping rule");
+  int32_t done = 0, flat = 0;
+  ba_status ret = BA_OK;
+  for (int32_t it = 0; it < max_iters; ++it) {
+    ba_step_info info;
+    st = ba_lm_step(p, &info);
+    if (infos) infos[it] = info;
+    if (st != BA_OK) {
+      ret = st;
+      break;
+    }
+    ++done;
+    const double dec = info.accepted ? (info.cost_before - info.cost_after) / info.cost_before : 0.0;
+    flat = dec < rel_tol ? flat + 1 : 0;
+    if (!info.accepted && info.lambda_used >= p->opt.lambda_max) {
+      ret = fail(BA_ENOTCONV, "damping reached lambda_max");
+      break;
+    }
+    if (flat >= plateau_steps) break;
+    if (info.grad_inf <= 1e-12 * (1.0 + info.cost_before)) break;
+  }
+  if (iters_done) *iters_done = done;
+  return ret;
+}
+
+ba_status ba_backward(ba_problem* p, const double*, const double*, double*, double*) {
+  (void)p;
+  return fail(BA_EUNSUPPORTED, "the implicit-function adjoint is not available in this build");
+}
+
+ba_status ba_get_state(const ba_problem* p, void* blob, size_t* bytes) {
+  if (!p || !bytes) return fail(BA_EINVAL, "null argument");
+  const size_t need = sizeof(double) * (4 + 10 * (size_t)p->plan.nc + 3 * (size_t)p->plan.np);
+  if (!blob) {
+    *bytes = need;
+    return BA_OK;
+  }
+  if (*bytes < need) return fail(BA_EINVAL, "state buffer too small");
+  if (!p->bound || !p->have_params) return fail(BA_ESTATE, "parameters are not set");
+  double* d = reinterpret_cast<double*>(blob);
+  d[0] = 1.0;  // format version
+  d[1] = p->plan.nc;
+  d[2] = p->plan.np;
+  d[3] = p->lambda;
+  HIPCHK(hipMemcpyAsync(d + 4, p->b.cams[p->cur], sizeof(double) * 10 * p->plan.nc,
+                        hipMemcpyDeviceToHost, p->stream));
+  HIPCHK(hipMemcpyAsync(d + 4 + 10 * (size_t)p->plan.nc, p->b.pts[p->cur],
+                        sizeof(double) * 3 * p->plan.np, hipMemcpyDeviceToHost, p->stream));
+  HIPCHK(hipStreamSynchronize(p->stream));
+  *bytes = need;
+  return BA_OK;
+}
+
+ba_status ba_set_state(ba_problem* p, const void* blob, size_t bytes) {
+  if (!p || !blob) return fail(BA_EINVAL, "null argument");
+  if (!p->bound) return fail(BA_ESTATE, "problem is not bound");
+  const size_t need = sizeof(double) * (4 + 10 * (size_t)p->plan.nc + 3 * (size_t)p->plan.np);
+  const double* d = reinterpret_cast<const double*>(blob);
+  if (bytes != need || d[0] != 1.0 || d[1] != p->plan.nc || d[2] != p->plan.np)
+    return fail(BA_EINVAL, "state blob does not match this problem");
+  HIPCHK(hipMemcpyAsync(p->b.cams[p->cur], d + 4, sizeof(double) * 10 * p->plan.nc,
+                        hipMemcpyHostToDevice, p->stream));
+  HIPCHK(hipMemcpyAsync(p->b.pts[p->cur], d + 4 + 10 * (size_t)p->plan.nc,
+                        sizeof(double) * 3 * p->plan.np, hipMemcpyHostToDevice, p->stream));
+  HIPCHK(hipStreamSynchronize(p->stream));
+  p->have_params = true;
+  p->lin_valid = false;
+  return ba_set_lambda(p, d[3]);
+}
+
+ba_status ba_export(const ba_problem* p, int32_t field, void* dst, size_t bytes) {
+  if (!p || !dst) return fail(BA_EINVAL, "null argument");
+  if (!p->bound) return fail(BA_ESTATE, "problem is not bound");
+  const ba::Plan& P = p->plan;
+  const ba::Buffers& b = p->b;
+  const size_t no = P.no, nc = P.nc, np = P.np, nnzb = P.nnzb;
+  const bool mixed = p->opt.precision == BA_MIXED;
+  auto need = [&](size_t n) { return bytes == n; };
+  auto fetch = [&](const void* src, size_t n, std::vector<char>& h) -> hipError_t {
+    h.resize(n);
+    hipError_t e = hipMemcpyAsync(h.data(), src, n, hipMemcpyDeviceToHost, p->stream);
+    if (e != hipSuccess) return e;
+    return hipStreamSynchronize(p->stream);
+  };
+  std::vector<char> h;
+  double* out = reinterpret_cast<double*>(dst);
+  switch (field) {
+    case BA_X_RESIDUAL:
+    case BA_X_WEIGHT: {
+      const bool res = field == BA_X_RESIDUAL;
+      if (!need(no * sizeof(double) * (res ? 2 : 1))) return fail(BA_EINVAL, "size mismatch");
+      HIPCHK(fetch(res ? (const void*)b.r : (const void*)b.w, no * sizeof(double) * (res ? 2 : 1), h));
+      const double* v = reinterpret_cast<const double*>(h.data());
+      for (size_t x = 0; x < no; ++x) {
+        const size_t k = P.o_orig[x];
+        if (res) {
+          out[2 * k] = v[2 * x];
+          out[2 * k + 1] = v[2 * x + 1];
+        } else {
+          out[k] = v[x];
+        }
+      }
+      return BA_OK;
+    }
+    case BA_X_JC:
+    case BA_X_JP: {
+      const bool jc = field == BA_X_JC;
+      const size_t per = jc ? 18 : 6;
+      if (!need(no * per * sizeof(double))) return fail(BA_EINVAL, "size mismatch");
+      HIPCHK(fetch(b.J, no * ba::NJ * elem_bytes(p), h));
+      for (size_t x = 0; x < no; ++x) {
+        const size_t k = P.o_orig[x];
+        for (size_t q = 0; q < per; ++q) {
+          const size_t src = x * ba::NJ + (jc ? 0 : 18) + q;
+          out[k * per + q] = mixed ? (double)reinterpret_cast<const float*>(h.data())[src]
+                                   : reinterpret_cast<const double*>(h.data())[src];
+        }
+      }
+      return BA_OK;
+    }
+    case BA_X_COST: {
+      if (!need(sizeof(double))) return fail(BA_EINVAL, "size mismatch");
+      HIPCHK(fetch(b.dev, sizeof(ba::DevScalars), h));
+      out[0] = reinterpret_cast<const ba::DevScalars*>(h.data())->F;
+      return BA_OK;
+    }
+    case BA_X_GRAD_C:
+    case BA_X_BS:
+    case BA_X_DC: {
+      if (!need(nc * 9 * sizeof(double))) return fail(BA_EINVAL, "size mismatch");
+      const double* src = field == BA_X_GRAD_C ? b.gc : field == BA_X_BS ? b.bS : b.x;
+      HIPCHK(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, p->stream));
+      HIPCHK(hipStreamSynchronize(p->stream));
+      return BA_OK;
+    }
+    case BA_X_GRAD_P:
+    case BA_X_DP: {
+      if (!need(np * 3 * sizeof(double))) return fail(BA_EINVAL, "size mismatch");
+      HIPCHK(hipMemcpyAsync(dst, field == BA_X_GRAD_P ? b.gp : b.dp, bytes, hipMemcpyDeviceToHost,
+                            p->stream));
+      HIPCHK(hipStreamSynchronize(p->stream));
+      return BA_OK;
+    }
+    case BA_X_V: {
+      if (!need(np * 9 * sizeof(double))) return fail(BA_EINVAL, "size mismatch");
+      HIPCHK(fetch(b.V, np * 6 * sizeof(double), h));
+      const double* v = reinterpret_cast<const double*>(h.data());
+      static const int map[9] = {0, 1, 2, 1, 3, 4, 2, 4, 5};
+      for (size_t j = 0; j < np; ++j)
+        for (int q = 0; q < 9; ++q) out[9 * j + q] = v[6 * j + map[q]];
+      return BA_OK;
+    }
+    case BA_X_S_PTR: {
+      if (!need((nc + 1) * sizeof(int64_t))) return fail(BA_EINVAL, "size mismatch");
+      int64_t* o = reinterpret_cast<int64_t*>(dst);
+      for (size_t a = 0; a <= nc; ++a) o[a] = P.S_ptr[a];
+      return BA_OK;
+    }
+    case BA_X_S_COL: {
+      if (!need(nnzb * sizeof(int32_t))) return fail(BA_EINVAL, "size mismatch");
+      std::memcpy(dst, P.S_col.data(), bytes);
+      return BA_OK;
+    }
+    case BA_X_S: {
+      if (!need(nnzb * 81 * sizeof(double))) return fail(BA_EINVAL, "size mismatch");
+      HIPCHK(fetch(b.S, nnzb * 81 * elem_bytes(p), h));
+      for (size_t q = 0; q < nnzb * 81; ++q)
+        out[q] = mixed ? (double)reinterpret_cast<const float*>(h.data())[q]
+                       : reinterpret_cast<const double*>(h.data())[q];
+      return BA_OK;
+    }
+    default:
+      return fail(BA_EINVAL, "unknown field");
+  }
+}
+
+ba_status ba_set_profiling(ba_problem* p, int32_t enable) {
+  if (!p) return fail(BA_EINVAL, "null problem");
+  if (!p->bound) return fail(BA_ESTATE, "problem is not bound");
+  if (enable && !p->ev[0][0]) {
+    for (int i = 0; i < BA_NUM_PHASES; ++i)
+      for (int k = 0; k < 2; ++k) HIPCHK(hipEventCreate(&p->ev[i][k]));
+  }
+  for (int i = 0; i < BA_NUM_PHASES; ++i) {
+    p->phase_ms[i] = 0.0;
+    p->phase_n[i] = 0;
+    p->phase_used[i] = false;
+  }
+  p->profiling = enable != 0;
+  return BA_OK;
+}
+
+ba_status ba_get_phase_times(const ba_problem* p, double* ms, int64_t* n_out, int32_t n) {
+  if (!p || !ms || n < 0 || n > BA_NUM_PHASES) return fail(BA_EINVAL, "bad argument");
+  for (int i = 0; i < n; ++i) {
+    ms[i] = p->phase_ms[i];
+    if (n_out) n_out[i] = p->phase_n[i];
+  }
+  return BA_OK;
+}
+
+void ba_problem_destroy(ba_problem* p) {
+  if (!p) return;
+  for (int i = 0; i < BA_NUM_PHASES; ++i)
+    for (int k = 0; k < 2; ++k)
+      if (p->ev[i][k]) (void)hipEventDestroy(p->ev[i][k]);
+  if (p->hinfo) (void)hipHostFree(p->hinfo);
+  if (p->hscal) (void)hipHostFree(p->hscal);
+  delete p;
+}
+
+}  // extern "C"

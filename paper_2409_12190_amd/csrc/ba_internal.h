@@ -1,0 +1,162 @@
+// Internal structures shared by the host runtime and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "ba.h"
+
+namespace ba {
+
+constexpr int D = 9;            // camera tangent size (6 pose + f, k1, k2)
+constexpr int NJ = 24;          // stored Jacobian values per observation: Jc 2x9, then Jp 2x3
+constexpr int CHUNK = 256;      // observations per point-aligned chunk (= its block size)
+constexpr int SCHUR_THREADS = 256;
+constexpr int SCHUR_SLOTS = SCHUR_THREADS / 9;  // 28 pair chunks per workgroup, 9 lanes each
+constexpr int SCHUR_CHUNK = 16;                 // target pairs per chunk
+constexpr int CAM_THREADS = 128;
+constexpr int PCG_THREADS = 512;
+constexpr int PCG_RMAX = 64;          // block rows owned by one PCG workgroup
+constexpr int PCG_TARGET_GRID = 256;  // PCG workgroups aimed for on large systems
+constexpr int PART_STRIDE = 16;       // doubles per workgroup partial (one 128-byte line)
+constexpr int BARRIER_FANIN = 16;
+constexpr int MAX_BARRIER_GROUPS = 128;
+constexpr int MAX_TRACK = CHUNK;
+
+// Host-side symbolic analysis of the observation pattern (computed once per
+// problem; the paper caches its sparse-product table the same way, Sec. IV-B-1).
+struct Plan {
+  int32_t nc = 0, np = 0;
+  int64_t no = 0;
+  // observations sorted by (point, camera, original index): "positions"
+  std::vector<int32_t> o_cam, o_pt;
+  std::vector<int64_t> o_orig;       // original index of each position
+  std::vector<int32_t> pt_ptr;       // [np+1] position range of each point
+  std::vector<int32_t> chunk_ptr;    // [nchunk+1] position range of each chunk
+  std::vector<int32_t> chunk_pt;     // [nchunk+1] point range of each chunk
+  std::vector<int32_t> cam_ptr;      // [nc+1]
+  std::vector<int32_t> cam_obs;      // positions grouped by camera
+  std::vector<int32_t> S_ptr, S_col; // upper block pattern, diagonal first in each row
+  std::vector<int32_t> T_ptr, T_blk, T_src;  // for row b: upper blocks (a,b), a < b
+  // observation pairs (x, y) that feed each S block: camera(x) = row, camera(y)
+  // = column, same point; grouped by block, ascending x within a block
+  std::vector<int32_t> pair_x, pair_y;
+  // Schur workgroups: SCHUR_SLOTS chunk slots each; slot -> (block, pair range,
+  // number of slots of the block when this slot is the block's first, else 0)
+  std::vector<int32_t> slot_blk, slot_pb, slot_pe, slot_lead;
+  std::vector<int32_t> blk_row;  // block -> its row (camera a)
+  int64_t nnzb = 0, n_pairs = 0;
+  int32_t n_schur_wg = 0;
+  int32_t max_track = 0;
+};
+
+// Builds the plan; returns an empty string or an error message.
+std::string build_plan(int32_t nc, int32_t np, int64_t no, const int32_t* cidx, const int32_t* pidx,
+                       Plan* out);
+
+struct DevScalars {
+  double F;        // cost at the current parameters
+  double lambda;   // damping of the next step
+  int32_t error;   // bit flags set by kernels (see ERR_*)
+  int32_t pad;
+};
+
+enum : int32_t {
+  ERR_NONFINITE_OBS = 1,
+  ERR_BAD_WEIGHT = 2,
+  ERR_POINT_BLOCK = 4,    // a damped 3x3 point block was not positive definite
+  ERR_CAMERA_BLOCK = 8,   // a diagonal Schur block was not positive definite
+  ERR_BARRIER = 16,       // the PCG grid barrier timed out
+};
+
+struct GridSync {
+  unsigned count;
+  unsigned gen;
+  unsigned pad_[62];
+  struct {
+    unsigned count;
+    unsigned pad_[63];
+  } group[MAX_BARRIER_GROUPS];
+};
+
+// PCG decomposition: grid of pcg_grid workgroups, rows_per_wg block rows each.
+struct PcgShape {
+  int grid, rows, seg;
+};
+inline PcgShape pcg_shape(int nc) {
+  int rows = (nc + PCG_TARGET_GRID - 1) / PCG_TARGET_GRID;
+  if (rows < 1) rows = 1;
+  if (rows > PCG_RMAX) rows = PCG_RMAX;
+  const int grid = (nc + rows - 1) / rows;
+  const int seg = ((rows * 9 + 15) / 16) * 16;
+  return PcgShape{grid, rows, seg};
+}
+
+// Device pointers carved out of the caller's workspace.
+struct Buffers {
+  // plan
+  int32_t *o_cam, *o_pt, *pt_ptr, *chunk_ptr, *chunk_pt, *cam_ptr, *cam_obs;
+  int32_t *S_ptr, *S_col, *T_ptr, *T_blk, *T_src;
+  int32_t *pair_x, *pair_y, *slot_blk, *slot_pb, *slot_pe, *slot_lead, *blk_row;
+  int64_t* o_orig;
+  uint8_t* fixed;
+  // observations (sorted by position)
+  double *o_xy, *o_w;
+  // parameters: [0] current, [1] candidate
+  double *cams[2], *pts[2];
+  // linearisation
+  double *r, *w;
+  void* J;  // float or double [no][NJ]
+  double *V, *gp, *gc, *diagU;
+  // damped quantities
+  double *Vinv, *ep;
+  void* Q;  // float or double [no][6]: w Jp Vinv of each observation
+  void* S;  // float or double [nnzb][81]
+  double *Sdiag, *bS, *Minv;  // FP64 undamped diagonal blocks, rhs, block-Jacobi inverse
+  // PCG vectors
+  double *x, *cr, *cz, *cp, *cq;
+  double* dp;
+  // partial sums
+  double *part_cost, *part_cost_new, *part_pred, *part_gmax, *part_linc;
+  double *zring, *partA, *partB;  // PCG exchange rings, one slot per iteration
+  DevScalars* dev;
+  ba_step_info* dinfo;
+  GridSync* gsync;
+};
+
+struct PcgResult {
+  double rel_resid;
+  int32_t iters, breakdown;
+};
+
+}  // namespace ba
+
+struct ba_problem {
+  ba_options opt;
+  ba::Plan plan;
+  ba::Buffers b{};
+  hipStream_t stream = nullptr;
+  int device = -1;
+  void* workspace = nullptr;
+  size_t ws_bytes = 0;
+  size_t ws_needed = 0;
+  bool bound = false, have_obs = false, have_params = false;
+  bool lin_valid = false;
+  int cur = 0;  // which parameter buffer is current
+  int nchunk = 0, cam_blocks = 0;
+  int pcg_grid = 0;
+  double lambda = 1e-4;
+  double cg_rtol = 1e-4;
+  int32_t cg_maxiter = 250;
+  bool profiling = false;
+  hipEvent_t ev[BA_NUM_PHASES][2] = {};
+  double phase_ms[BA_NUM_PHASES] = {};
+  int64_t phase_n[BA_NUM_PHASES] = {};
+  bool phase_used[BA_NUM_PHASES] = {};
+  ba_step_info* hinfo = nullptr;     // pinned host staging
+  ba::DevScalars* hscal = nullptr;   // pinned host staging
+};

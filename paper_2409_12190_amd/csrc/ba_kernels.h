@@ -1,0 +1,129 @@
+// Kernel argument blocks and launchers (device pointers only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "ba.h"
+#include "ba_internal.h"
+
+namespace ba {
+
+struct LinArgs {
+  const int32_t *chunk_ptr, *chunk_pt, *pt_ptr, *o_cam, *o_pt;
+  const uint8_t* fixed;
+  const double *o_xy, *o_w, *cams, *pts;
+  double huber;
+  double *r, *w;
+  void* J;
+  double *V, *gp, *part_cost, *part_gmax;
+};
+
+struct DampArgs {
+  int np;
+  const double *V, *gp;
+  double dmin, dmax;
+  double *Vinv, *ep;
+  DevScalars* dev;
+  GridSync* gs;
+};
+
+struct PointQArgs {
+  int64_t no;
+  const int32_t* o_pt;
+  const void* J;
+  const double *w, *Vinv;
+  void* Q;
+};
+
+struct CamVecArgs {
+  const int32_t *cam_ptr, *cam_obs, *o_pt;
+  const void* J;
+  const double *w, *r, *ep;
+  double *gc, *bS, *diagU;
+};
+
+struct SchurArgs {
+  const int32_t *slot_blk, *slot_pb, *slot_pe, *slot_lead, *pair_x, *pair_y, *blk_row, *S_ptr;
+  const void *J, *Q;
+  const double* w;
+  void* S;
+  double* Sdiag;
+};
+
+struct CamFinishArgs {
+  const int32_t* S_ptr;
+  const double *Sdiag, *diagU;
+  double dmin, dmax;
+  void* S;
+  double* Minv;
+  DevScalars* dev;
+};
+
+struct PcgArgs {
+  int nc, maxiter, rows_per_wg, seg;
+  double rtol;
+  const int32_t *S_ptr, *S_col, *T_ptr, *T_blk, *T_src;
+  const void* S;
+  const double *Minv, *b;
+  double* x;
+  double *zring, *partA, *partB;  // (maxiter + 1) slots each
+  ba_step_info* info;
+  GridSync* gs;
+  int* error;
+};
+
+struct BackArgs {
+  const int32_t *chunk_ptr, *chunk_pt, *pt_ptr, *o_cam, *o_pt;
+  const void* J;
+  const double *w, *dc, *gp, *Vinv, *pts;
+  double *dp, *pts_new, *part_pred;
+};
+
+struct RetractArgs {
+  int nc;
+  const uint8_t* fixed;
+  const double *cams, *dc, *gc;
+  double *cams_new, *part_linc;
+};
+
+struct CostArgs {
+  const int32_t *chunk_ptr, *o_cam, *o_pt;
+  const double *o_xy, *o_w, *cams, *pts;
+  double huber;
+  double* part_cost_new;
+};
+
+struct FinalArgs {
+  int nchunk, ncamblk, nc;
+  const double *part_cost_new, *part_pred, *part_linc, *part_gmax, *gc;
+  double lambda_min, lambda_max;
+  DevScalars* dev;
+  ba_step_info* info;
+};
+
+struct ObsArgs {
+  int64_t no;
+  const int64_t* o_orig;
+  const double *xy, *w;
+  double *o_xy, *o_w;
+  DevScalars* dev;
+};
+
+template <typename T> hipError_t launch_linearize(const LinArgs&, int nchunk, hipStream_t);
+hipError_t launch_reduce_cost(const double* part, int n, DevScalars* dev, hipStream_t);
+hipError_t launch_damp_points(const DampArgs&, hipStream_t);
+template <typename T> hipError_t launch_point_q(const PointQArgs&, hipStream_t);
+template <typename T> hipError_t launch_camera_vec(const CamVecArgs&, int nc, hipStream_t);
+template <typename T> hipError_t launch_schur_pairs(const SchurArgs&, int nwg, hipStream_t);
+template <typename T> hipError_t launch_camera_finish(const CamFinishArgs&, int nc, hipStream_t);
+template <typename T> int pcg_max_grid();
+template <typename T> hipError_t launch_pcg(const PcgArgs&, int grid, hipStream_t);
+template <typename T> hipError_t launch_backsub(const BackArgs&, int nchunk, hipStream_t);
+hipError_t launch_retract_cameras(const RetractArgs&, int nblk, hipStream_t);
+hipError_t launch_candidate_cost(const CostArgs&, int nchunk, hipStream_t);
+hipError_t launch_finalize(const FinalArgs&, hipStream_t);
+hipError_t launch_set_observations(const ObsArgs&, hipStream_t);
+
+}  // namespace ba

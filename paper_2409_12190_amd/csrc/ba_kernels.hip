@@ -1,0 +1,968 @@
+// gfx950 kernels of one Levenberg-Marquardt iteration of bundle adjustment.
+//
+// Data layout (HBM):
+//   observations sorted by (point, camera): "positions"; per position x the
+//   pixel o_xy[2x..2x+1] (FP64), weight o_w[x], camera o_cam[x], point o_pt[x];
+//   Jacobian blocks J[x][24] = Jc (2x9 row-major) then Jp (2x3), stored in
+//   the precision T (double in FP64 mode, float in mixed mode);
+//   residual r[2x..] and Gauss-Newton weight w[x] in FP64;
+//   point blocks V[j][6] (upper triangle xx xy xz yy yz zz), gradients gp[j][3],
+//   gc[a][9]; reduced camera matrix S[e][81] (T, upper block pattern);
+//   PCG vectors FP64 [n_cams][9].
+//
+// Every reduction is done in a fixed order (workgroup trees, then one final
+// workgroup, or a fixed-order sum over per-workgroup partials), so results
+// are bitwise reproducible from run to run.
+#include "ba_device.h"
+#include "ba_internal.h"
+#include "ba_kernels.h"
+
+namespace ba {
+
+// ---------------------------------------------------------------------------
+// reduction helpers
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// Sum over the workgroup; result valid in every thread.  sh: >= blockDim/64 doubles.
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+  __syncthreads();
+  if (lane == 0) sh[wid] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int i = 0; i < nw; ++i) s += sh[i];
+  return s;
+}
+
+__device__ __forceinline__ double block_max(double v, double* sh) {
+  v = wave_max(v);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+  __syncthreads();
+  if (lane == 0) sh[wid] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int i = 0; i < nw; ++i) s = fmax(s, sh[i]);
+  return s;
+}
+
+// Sum of arr[0..n) by one workgroup in a fixed order; valid in every thread.
+__device__ __forceinline__ double block_sum_array(const double* __restrict__ arr, int n, double* sh) {
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) s += arr[i];
+  return block_sum(s, sh);
+}
+
+template <typename T>
+__device__ __forceinline__ void load_J(const T* __restrict__ J, double Jc[2][9], double Jp[2][3]) {
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+#pragma unroll
+    for (int m = 0; m < 9; ++m) Jc[i][m] = (double)J[i * 9 + m];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) Jp[i][m] = (double)J[18 + i * 3 + m];
+  }
+}
+
+__device__ __forceinline__ void load_sym3(const double* __restrict__ s, double M[3][3]) {
+  M[0][0] = s[0]; M[0][1] = s[1]; M[0][2] = s[2];
+  M[1][0] = s[1]; M[1][1] = s[3]; M[1][2] = s[4];
+  M[2][0] = s[2]; M[2][1] = s[4]; M[2][2] = s[5];
+}
+
+// ---------------------------------------------------------------------------
+// observation pass 1: residual, Jacobian blocks, robust weight, cost, and the
+// point-keyed blocks V_j = sum w Jp^T Jp, gp_j = sum w Jp^T r
+// (Alg. 1 first two lines; Sec. IV-A-2 batched Jacobian values).
+// One workgroup per point-aligned chunk; segmented sums in LDS, fixed order.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(CHUNK) void k_linearize(LinArgs a) {
+  __shared__ double sh[9][CHUNK];
+  __shared__ double red[CHUNK / 64];
+  const int c = blockIdx.x;
+  const int x0 = a.chunk_ptr[c], x1 = a.chunk_ptr[c + 1];
+  const int t = threadIdx.x;
+  const int x = x0 + t;
+  double cost = 0.0;
+  if (x < x1) {
+    const int ci = a.o_cam[x], pj = a.o_pt[x];
+    const Camera cam = load_camera(a.cams + 10 * (size_t)ci);
+    const double* P = a.pts + 3 * (size_t)pj;
+    double Jc[2][9], Jp[2][3];
+    const Proj pr = project_jac(cam, v3(P[0], P[1], P[2]), Jc, Jp);
+    const double rx = pr.px - a.o_xy[2 * (size_t)x], ry = pr.py - a.o_xy[2 * (size_t)x + 1];
+    double drho;
+    const double rho = robust_rho(rx * rx + ry * ry, a.huber, &drho);
+    const double om = a.o_w[x];
+    const double w = om * drho;
+    cost = 0.5 * om * rho;
+    if (a.fixed[ci]) {
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int m = 0; m < 9; ++m) Jc[i][m] = 0.0;
+    }
+    a.r[2 * (size_t)x] = rx;
+    a.r[2 * (size_t)x + 1] = ry;
+    a.w[x] = w;
+    T* J = reinterpret_cast<T*>(a.J) + (size_t)x * NJ;
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+#pragma unroll
+      for (int m = 0; m < 9; ++m) J[i * 9 + m] = (T)Jc[i][m];
+#pragma unroll
+      for (int m = 0; m < 3; ++m) J[18 + i * 3 + m] = (T)Jp[i][m];
+    }
+    sh[0][t] = w * (Jp[0][0] * Jp[0][0] + Jp[1][0] * Jp[1][0]);
+    sh[1][t] = w * (Jp[0][0] * Jp[0][1] + Jp[1][0] * Jp[1][1]);
+    sh[2][t] = w * (Jp[0][0] * Jp[0][2] + Jp[1][0] * Jp[1][2]);
+    sh[3][t] = w * (Jp[0][1] * Jp[0][1] + Jp[1][1] * Jp[1][1]);
+    sh[4][t] = w * (Jp[0][1] * Jp[0][2] + Jp[1][1] * Jp[1][2]);
+    sh[5][t] = w * (Jp[0][2] * Jp[0][2] + Jp[1][2] * Jp[1][2]);
+    sh[6][t] = w * (Jp[0][0] * rx + Jp[1][0] * ry);
+    sh[7][t] = w * (Jp[0][1] * rx + Jp[1][1] * ry);
+    sh[8][t] = w * (Jp[0][2] * rx + Jp[1][2] * ry);
+  }
+  __syncthreads();
+  double gmax = 0.0;
+  const int j0 = a.chunk_pt[c], j1 = a.chunk_pt[c + 1];
+  for (int j = j0 + t; j < j1; j += blockDim.x) {
+    double s[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) s[q] = 0.0;
+    const int lo = a.pt_ptr[j] - x0, hi = a.pt_ptr[j + 1] - x0;
+    for (int y = lo; y < hi; ++y)
+#pragma unroll
+      for (int q = 0; q < 9; ++q) s[q] += sh[q][y];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) a.V[6 * (size_t)j + q] = s[q];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) a.gp[3 * (size_t)j + q] = s[6 + q];
+    gmax = fmax(gmax, fmax(fabs(s[6]), fmax(fabs(s[7]), fabs(s[8]))));
+  }
+  const double tot = block_sum(cost, red);
+  const double gm = block_max(gmax, red);
+  if (t == 0) {
+    a.part_cost[c] = tot;
+    a.part_gmax[c] = gm;
+  }
+}
+
+// F = sum of the chunk partials (fixed order), and the gradient max over points.
+__global__ __launch_bounds__(256) void k_reduce_cost(const double* __restrict__ part, int n,
+                                                     DevScalars* dev) {
+  __shared__ double red[4];
+  const double F = block_sum_array(part, n, red);
+  if (threadIdx.x == 0) dev->F = F;
+}
+
+// ---------------------------------------------------------------------------
+// damping of the point blocks and their inverses (Eq. 2 with the clamp of
+// Sec. IV-B-3): V*_j = V_j + lambda clamp(diag V_j), Vinv_j = V*_j^-1 by the
+// adjugate, ep_j = Vinv_j gp_j.  One thread per point, FP64.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_damp_points(DampArgs a) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j <= MAX_BARRIER_GROUPS) {  // the PCG grid barrier of this step starts from a clean state
+    if (j == 0) {
+      a.gs->count = 0u;
+      a.gs->gen = 0u;
+    } else {
+      a.gs->group[j - 1].count = 0u;
+    }
+  }
+  if (j >= a.np) return;
+  const double lam = a.dev->lambda;
+  const double* v = a.V + 6 * (size_t)j;
+  const double m00 = v[0] + lam * fmin(fmax(v[0], a.dmin), a.dmax);
+  const double m11 = v[3] + lam * fmin(fmax(v[3], a.dmin), a.dmax);
+  const double m22 = v[5] + lam * fmin(fmax(v[5], a.dmin), a.dmax);
+  const double m01 = v[1], m02 = v[2], m12 = v[4];
+  const double c00 = m11 * m22 - m12 * m12;
+  const double c01 = m02 * m12 - m01 * m22;
+  const double c02 = m01 * m12 - m02 * m11;
+  const double c11 = m00 * m22 - m02 * m02;
+  const double c12 = m01 * m02 - m00 * m12;
+  const double c22 = m00 * m11 - m01 * m01;
+  const double det = m00 * c00 + m01 * c01 + m02 * c02;
+  if (!(det > 0.0) || !isfinite(det)) atomicOr(&a.dev->error, (int)ERR_POINT_BLOCK);
+  const double id = 1.0 / det;
+  double* o = a.Vinv + 6 * (size_t)j;
+  o[0] = c00 * id; o[1] = c01 * id; o[2] = c02 * id;
+  o[3] = c11 * id; o[4] = c12 * id; o[5] = c22 * id;
+  const double* g = a.gp + 3 * (size_t)j;
+  double* e = a.ep + 3 * (size_t)j;
+  e[0] = (c00 * g[0] + c01 * g[1] + c02 * g[2]) * id;
+  e[1] = (c01 * g[0] + c11 * g[1] + c12 * g[2]) * id;
+  e[2] = (c02 * g[0] + c12 * g[1] + c22 * g[2]) * id;
+}
+
+// ---------------------------------------------------------------------------
+// per-observation factor of the Schur product: Q_x = w_x Jp_x Vinv_j (2x3),
+// stored in the Jacobian precision (one thread per observation).
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_point_q(PointQArgs a) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= a.no) return;
+  const T* J = reinterpret_cast<const T*>(a.J) + (size_t)x * NJ + 18;
+  double Vi[3][3];
+  load_sym3(a.Vinv + 6 * (size_t)a.o_pt[x], Vi);
+  const double w = a.w[x];
+  T* Q = reinterpret_cast<T*>(a.Q) + (size_t)x * 6;
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const double j0 = (double)J[3 * i], j1 = (double)J[3 * i + 1], j2 = (double)J[3 * i + 2];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) Q[3 * i + m] = (T)(w * (j0 * Vi[0][m] + j1 * Vi[1][m] + j2 * Vi[2][m]));
+  }
+}
+
+// ---------------------------------------------------------------------------
+// camera vectors (one workgroup per camera a):
+//   gc_a = sum w Jc^T r,   diagU_a = diag(sum w Jc^T Jc),
+//   bS_a = -gc_a + sum w Jc^T Jp ep_j   (ep_j = Vinv_j gp_j)
+// reduced over the workgroup in a fixed order.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(CAM_THREADS) void k_camera_vec(CamVecArgs a) {
+  __shared__ double red[CAM_THREADS / 64][27];
+  const int cam = blockIdx.x;
+  const int lo = a.cam_ptr[cam], hi = a.cam_ptr[cam + 1];
+  const T* __restrict__ Jall = reinterpret_cast<const T*>(a.J);
+  double gcv[9], bsv[9], du[9];
+#pragma unroll
+  for (int q = 0; q < 9; ++q) gcv[q] = bsv[q] = du[q] = 0.0;
+  for (int i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+    const int x = a.cam_obs[i];
+    double Jc[2][9], Jp[2][3];
+    load_J(Jall + (size_t)x * NJ, Jc, Jp);
+    const double w = a.w[x];
+    const double rx = a.r[2 * (size_t)x], ry = a.r[2 * (size_t)x + 1];
+    const double* ep = a.ep + 3 * (size_t)a.o_pt[x];
+    const double e0 = Jp[0][0] * ep[0] + Jp[0][1] * ep[1] + Jp[0][2] * ep[2];
+    const double e1 = Jp[1][0] * ep[0] + Jp[1][1] * ep[1] + Jp[1][2] * ep[2];
+#pragma unroll
+    for (int m = 0; m < 9; ++m) {
+      gcv[m] += w * (Jc[0][m] * rx + Jc[1][m] * ry);
+      bsv[m] += w * (Jc[0][m] * e0 + Jc[1][m] * e1);
+      du[m] += w * (Jc[0][m] * Jc[0][m] + Jc[1][m] * Jc[1][m]);
+    }
+  }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < 9; ++q) {
+    const double g = wave_sum(gcv[q]);
+    const double b = wave_sum(bsv[q]);
+    const double u = wave_sum(du[q]);
+    if (lane == 0) {
+      red[wid][q] = g;
+      red[wid][9 + q] = b;
+      red[wid][18 + q] = u;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < 27) {
+    double s = 0.0;
+    for (int w2 = 0; w2 < CAM_THREADS / 64; ++w2) s += red[w2][threadIdx.x];
+    const int q = threadIdx.x % 9;
+    if (threadIdx.x < 9) a.gc[9 * (size_t)cam + q] = s;
+    else if (threadIdx.x < 18) a.bS[9 * (size_t)cam + q] = s;  // completed below with -gc
+    else a.diagU[9 * (size_t)cam + q] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x < 9) a.bS[9 * (size_t)cam + threadIdx.x] -= a.gc[9 * (size_t)cam + threadIdx.x];
+}
+
+// ---------------------------------------------------------------------------
+// Schur blocks from the pair table (Sec. IV-B-1 numeric phase on the cached
+// table): for block (a, b) and pairs (x, y) sharing a point, x in camera a,
+// y in camera b,
+//   S_ab  = -sum Jc_x^T (Q_x (w_y Jp_y)^T) Jc_y                  (a < b)
+//   S_aa' = sum Jc_x^T ([x = y] w_x I - Q_x (w_y Jp_y)^T) Jc_y   (undamped)
+// Each workgroup holds SCHUR_SLOTS chunk slots; 9 lanes share a chunk, lane
+// c accumulating column c of the block over the chunk's pairs in registers.
+// The chunks of one block sit in consecutive slots of one workgroup and are
+// summed in slot order through LDS: no atomics, fixed summation order.
+// Off-diagonal blocks go to S (precision T); diagonal blocks, still to be
+// damped, to the FP64 buffer Sdiag.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(SCHUR_THREADS) void k_schur_pairs(SchurArgs a) {
+  __shared__ double part[SCHUR_SLOTS][81];
+  const int slot = threadIdx.x / 9, col = threadIdx.x - 9 * (threadIdx.x / 9);
+  const size_t sbase = (size_t)blockIdx.x * SCHUR_SLOTS;
+  const T* __restrict__ Jall = reinterpret_cast<const T*>(a.J);
+  const T* __restrict__ Qall = reinterpret_cast<const T*>(a.Q);
+  if (slot < SCHUR_SLOTS) {
+    const int e = a.slot_blk[sbase + slot];
+    double acc[9];
+#pragma unroll
+    for (int r = 0; r < 9; ++r) acc[r] = 0.0;
+    if (e >= 0) {
+      const int pb = a.slot_pb[sbase + slot], pe = a.slot_pe[sbase + slot];
+      for (int i = pb; i < pe; ++i) {
+        const int x = a.pair_x[i], y = a.pair_y[i];
+        const T* Jx = Jall + (size_t)x * NJ;
+        const T* Jy = Jall + (size_t)y * NJ;
+        const T* Qx = Qall + (size_t)x * 6;
+        const double wy = a.w[y];
+        double M[2][2];
+#pragma unroll
+        for (int i2 = 0; i2 < 2; ++i2)
+#pragma unroll
+          for (int k2 = 0; k2 < 2; ++k2)
+            M[i2][k2] = -wy * ((double)Qx[3 * i2] * (double)Jy[18 + 3 * k2] +
+                               (double)Qx[3 * i2 + 1] * (double)Jy[19 + 3 * k2] +
+                               (double)Qx[3 * i2 + 2] * (double)Jy[20 + 3 * k2]);
+        if (x == y) {
+          M[0][0] += wy;
+          M[1][1] += wy;
+        }
+        const double c0 = (double)Jy[col], c1 = (double)Jy[9 + col];
+        const double g0 = M[0][0] * c0 + M[0][1] * c1;
+        const double g1 = M[1][0] * c0 + M[1][1] * c1;
+#pragma unroll
+        for (int r = 0; r < 9; ++r) acc[r] += (double)Jx[r] * g0 + (double)Jx[9 + r] * g1;
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < 9; ++r) part[slot][r * 9 + col] = acc[r];
+  }
+  __syncthreads();
+  // every lead slot sums its block's chunk partials in slot order
+  for (int t = threadIdx.x; t < SCHUR_SLOTS * 81; t += blockDim.x) {
+    const int s = t / 81, q = t - 81 * (t / 81);
+    const int n = a.slot_lead[sbase + s];
+    if (n == 0) continue;
+    double v = 0.0;
+    for (int k = 0; k < n; ++k) v += part[s + k][q];
+    const int e = a.slot_blk[sbase + s];
+    const int row = a.blk_row[e];
+    if (a.S_ptr[row] == e) a.Sdiag[81 * (size_t)row + q] = v;
+    else reinterpret_cast<T*>(a.S)[81 * (size_t)e + q] = (T)v;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// diagonal blocks: S_aa = Sdiag_a + lambda clamp(diagU_a) (Eq. 2 damping with
+// the clamp of Sec. IV-B-3), stored in precision T, and the block-Jacobi
+// preconditioner Minv_a = S_aa^-1 by Cholesky in FP64 (one workgroup per
+// camera; the factorisation by one lane).
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(64) void k_camera_finish(CamFinishArgs a) {
+  __shared__ double Sd[81];
+  const int cam = blockIdx.x;
+  const double lam = a.dev->lambda;
+  for (int q = threadIdx.x; q < 81; q += blockDim.x) {
+    double v = a.Sdiag[81 * (size_t)cam + q];
+    const int r = q / 9;
+    if (q == 10 * r) v += lam * fmin(fmax(a.diagU[9 * (size_t)cam + r], a.dmin), a.dmax);
+    Sd[q] = v;
+    reinterpret_cast<T*>(a.S)[81 * (size_t)a.S_ptr[cam] + q] = (T)v;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double L[81];
+    for (int q = 0; q < 81; ++q) L[q] = Sd[q];
+    bool ok = true;
+    for (int k = 0; k < 9; ++k) {
+      double d = L[k * 9 + k];
+      for (int m = 0; m < k; ++m) d -= L[k * 9 + m] * L[k * 9 + m];
+      if (!(d > 0.0)) {
+        ok = false;
+        d = 1.0;
+      }
+      d = sqrt(d);
+      L[k * 9 + k] = d;
+      for (int i2 = k + 1; i2 < 9; ++i2) {
+        double s = L[i2 * 9 + k];
+        for (int m = 0; m < k; ++m) s -= L[i2 * 9 + m] * L[k * 9 + m];
+        L[i2 * 9 + k] = s / d;
+      }
+    }
+    if (!ok) atomicOr(&a.dev->error, (int)ERR_CAMERA_BLOCK);
+    double Li[81];
+    for (int q = 0; q < 81; ++q) Li[q] = 0.0;
+    for (int i2 = 0; i2 < 9; ++i2) {
+      Li[i2 * 9 + i2] = 1.0 / L[i2 * 9 + i2];
+      for (int k = i2 + 1; k < 9; ++k) {
+        double s = 0.0;
+        for (int m = i2; m < k; ++m) s += L[k * 9 + m] * Li[m * 9 + i2];
+        Li[k * 9 + i2] = -s / L[k * 9 + k];
+      }
+    }
+    double* Mi = a.Minv + 81 * (size_t)cam;
+    for (int r = 0; r < 9; ++r)
+      for (int cc = 0; cc < 9; ++cc) {
+        double s = 0.0;
+        for (int k = (r > cc ? r : cc); k < 9; ++k) s += Li[k * 9 + r] * Li[k * 9 + cc];
+        Mi[r * 9 + cc] = s;
+      }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// block-Jacobi preconditioned conjugate gradients on S x = bS (Sec. IV-C-2),
+// one cooperative launch for the whole solve (the paper removes per-iteration
+// launch overhead by replaying a captured PCG iteration, App. B; here the
+// iterations never leave the GPU).
+//
+// Workgroup B owns the contiguous block rows [B R, B R + R); its own-row
+// vectors stay in LDS for the whole solve.  Values other workgroups read (the
+// preconditioned residual z and the dot-product partials) are written once
+// per iteration into a fresh ring slot with agent-scope (write-through)
+// stores and read after a barrier with ordinary cached loads, so iterations
+// need no cache flush.  Dots are reduced from the per-workgroup partials in a
+// fixed order, identically in every workgroup, so every workgroup takes the
+// same branch.  Standard PCG recurrence; the product S p_k is formed as
+// S z_k + beta q_{k-1}, so the direction update and the product share one
+// barrier (two barriers per iteration).
+// ---------------------------------------------------------------------------
+constexpr int SPMV_GROUPS = PCG_THREADS / 9;
+constexpr long BARRIER_SPIN_LIMIT = 1L << 21;
+
+__device__ __forceinline__ void publish(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ unsigned agent_add(unsigned* p, unsigned v) {
+  return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void agent_store(unsigned* p, unsigned v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Grid-wide barrier of a co-resident grid without cache flushes: every wave
+// waits for its own memory operations to complete, one thread per workgroup
+// arrives on its group's counter (BARRIER_FANIN workgroups per group), the
+// last of a group arrives on the top counter, and the last overall advances
+// the generation the others poll.  The wait is bounded: on timeout the sticky
+// error flag is raised, and once it is set every later barrier returns at
+// once, so the kernel always terminates.
+__device__ __forceinline__ bool grid_barrier(GridSync* gs, int* error) {
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  __shared__ int failed;
+  if (threadIdx.x == 0) {
+    int f = __hip_atomic_load(error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & ERR_BARRIER;
+    if (!f) {
+      const unsigned gen = __hip_atomic_load(&gs->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const unsigned grp = blockIdx.x / BARRIER_FANIN;
+      const unsigned ngrp = (gridDim.x + BARRIER_FANIN - 1) / BARRIER_FANIN;
+      const unsigned gsz = min((unsigned)BARRIER_FANIN, gridDim.x - grp * BARRIER_FANIN);
+      bool last = false;
+      if (agent_add(&gs->group[grp].count, 1u) == gsz - 1) {
+        agent_store(&gs->group[grp].count, 0u);
+        __builtin_amdgcn_s_waitcnt(0);
+        if (agent_add(&gs->count, 1u) == ngrp - 1) {
+          agent_store(&gs->count, 0u);
+          __builtin_amdgcn_s_waitcnt(0);
+          agent_add(&gs->gen, 1u);
+          last = true;
+        }
+      }
+      if (!last) {
+        long spins = 0;
+        while (__hip_atomic_load(&gs->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+          if (++spins > BARRIER_SPIN_LIMIT ||
+              (__hip_atomic_load(error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & ERR_BARRIER)) {
+            atomicOr(error, (int)ERR_BARRIER);
+            f = 1;
+            break;
+          }
+          __builtin_amdgcn_s_sleep(1);
+        }
+      }
+    }
+    failed = f;
+  }
+  __syncthreads();
+  return failed == 0;
+}
+
+// Fixed-order sum over workgroups of partial q of a ring slot (every
+// workgroup computes the identical value).
+__device__ __forceinline__ double grid_sum(const double* slot, int G, int q, double* red) {
+  double s = 0.0;
+  for (int i = threadIdx.x; i < G; i += blockDim.x) s += slot[(size_t)i * PART_STRIDE + q];
+  return block_sum(s, red);
+}
+
+// y[own rows] = S zk over the upper blocks of the own rows and the transposes
+// of the upper blocks that end in them.  The workgroup's (row, block) items
+// are split into SPMV_GROUPS contiguous ranges; 9 lanes share an item, lane
+// `comp` computing one output component.  Each group keeps a running sum per
+// row and stores it at seg[row + group]; rows are then summed over groups in
+// group order.
+template <typename T>
+__device__ __forceinline__ void spmv_own_rows(const PcgArgs& a, const double* __restrict__ zk, int r0,
+                                              int nr, const int* rptr, double* seg, int* seg_lo,
+                                              int* seg_hi, double* y) {
+  const T* __restrict__ S = reinterpret_cast<const T*>(a.S);
+  const int nitems = rptr[nr];
+  const int g = threadIdx.x / 9, comp = threadIdx.x - 9 * (threadIdx.x / 9);
+  if (g < SPMV_GROUPS) {
+    const int L = (nitems + SPMV_GROUPS - 1) / SPMV_GROUPS;
+    const int i0 = min(nitems, g * L), i1 = min(nitems, i0 + L);
+    int row = 0;
+    while (row < nr - 1 && rptr[row + 1] <= i0) ++row;
+    const int first = row;
+    int cur = row;
+    double acc = 0.0;
+    for (int i = i0; i < i1; ++i) {
+      while (rptr[row + 1] <= i) ++row;
+      if (row != cur) {
+        seg[(cur + g) * 9 + comp] = acc;
+        acc = 0.0;
+        cur = row;
+      }
+      const int grow = r0 + row;
+      const int k = i - rptr[row];
+      const int ub = a.S_ptr[grow], nu = a.S_ptr[grow + 1] - ub;
+      int e, c;
+      bool up = k < nu;
+      if (up) {
+        e = ub + k;
+        c = a.S_col[e];
+      } else {
+        const int t = a.T_ptr[grow] + (k - nu);
+        e = a.T_blk[t];
+        c = a.T_src[t];
+      }
+      const int own = c / a.rows_per_wg;
+      const double* zc = zk + (size_t)own * a.seg + (size_t)(c - own * a.rows_per_wg) * 9;
+      const T* Bp = S + (size_t)e * 81 + (up ? comp * 9 : comp);
+      const int st = up ? 1 : 9;
+#pragma unroll
+      for (int m = 0; m < 9; ++m) acc += (double)Bp[m * st] * zc[m];
+    }
+    if (i0 < i1) seg[(cur + g) * 9 + comp] = acc;
+    if (comp == 0) {
+      seg_lo[g] = i0 < i1 ? first : 1;
+      seg_hi[g] = i0 < i1 ? cur : 0;
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < nr * 9; i += blockDim.x) {
+    const int row = i / 9, cp = i - 9 * row;
+    double s = 0.0;
+    for (int gg = 0; gg < SPMV_GROUPS; ++gg)
+      if (seg_lo[gg] <= row && row <= seg_hi[gg]) s += seg[(row + gg) * 9 + cp];
+    y[i] = s;
+  }
+  __syncthreads();
+}
+
+template <typename T>
+__global__ __launch_bounds__(PCG_THREADS) void k_pcg(PcgArgs a) {
+  __shared__ double xs[PCG_RMAX * 9], rs[PCG_RMAX * 9], ps[PCG_RMAX * 9];
+  __shared__ double qs[PCG_RMAX * 9], zs[PCG_RMAX * 9], ys[PCG_RMAX * 9];
+  __shared__ int rptr[PCG_RMAX + 1];
+  __shared__ double seg[(PCG_RMAX + SPMV_GROUPS) * 9];
+  __shared__ int seg_lo[SPMV_GROUPS], seg_hi[SPMV_GROUPS];
+  __shared__ double red[PCG_THREADS / 64];
+  const int G = gridDim.x, B = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
+  const int R = a.rows_per_wg;
+  const int r0 = min(a.nc, B * R), nr = min(a.nc, r0 + R) - r0;
+  const int n9 = nr * 9;
+  const size_t zstride = (size_t)G * a.seg, pstride = (size_t)G * PART_STRIDE;
+  double* zmine = a.zring + (size_t)B * a.seg;
+  if (tid == 0) {
+    rptr[0] = 0;
+    for (int i = 0; i < nr; ++i)
+      rptr[i + 1] = rptr[i] + (a.S_ptr[r0 + i + 1] - a.S_ptr[r0 + i]) +
+                    (a.T_ptr[r0 + i + 1] - a.T_ptr[r0 + i]);
+  }
+  for (int i = tid; i < n9; i += nt) {
+    rs[i] = a.b[9 * (size_t)r0 + i];
+    xs[i] = 0.0;
+  }
+  __syncthreads();
+  // z0 = M b, p0 = z0
+  double s_bb = 0.0, s_rz = 0.0;
+  for (int i = tid; i < n9; i += nt) {
+    const int row = i / 9, cp = i - 9 * row;
+    const double* Mi = a.Minv + 81 * (size_t)(r0 + row) + 9 * cp;
+    double z = 0.0;
+#pragma unroll
+    for (int m = 0; m < 9; ++m) z += Mi[m] * rs[row * 9 + m];
+    zs[i] = z;
+    ps[i] = z;
+    publish(zmine + i, z);
+    s_bb += rs[i] * rs[i];
+    s_rz += rs[i] * z;
+  }
+  s_bb = block_sum(s_bb, red);
+  s_rz = block_sum(s_rz, red);
+  if (tid == 0) {
+    publish(a.partA + (size_t)B * PART_STRIDE, s_bb);
+    publish(a.partA + (size_t)B * PART_STRIDE + 1, s_rz);
+  }
+  bool ok = grid_barrier(a.gs, a.error);
+  const double bb = grid_sum(a.partA, G, 0, red);
+  double rz = grid_sum(a.partA, G, 1, red);
+  const double bnorm = sqrt(bb);
+  double rnorm = bnorm;
+  int iters = 0, breakdown = 0;
+  if (ok && bnorm > 0.0) {
+    // q0 = S z0 (= S p0)
+    spmv_own_rows<T>(a, a.zring, r0, nr, rptr, seg, seg_lo, seg_hi, ys);
+    double s_pq = 0.0;
+    for (int i = tid; i < n9; i += nt) {
+      qs[i] = ys[i];
+      s_pq += ps[i] * ys[i];
+    }
+    s_pq = block_sum(s_pq, red);
+    if (tid == 0) publish(a.partB + (size_t)B * PART_STRIDE, s_pq);
+    ok = grid_barrier(a.gs, a.error);
+    double pq = grid_sum(a.partB, G, 0, red);
+    if (ok && !(pq > 0.0)) breakdown = 1;
+    double alpha = rz / pq;
+    for (int k = 1; ok && !breakdown && k <= a.maxiter; ++k) {
+      for (int i = tid; i < n9; i += nt) {
+        xs[i] += alpha * ps[i];
+        rs[i] -= alpha * qs[i];
+      }
+      __syncthreads();
+      double* zk = a.zring + (size_t)k * zstride;
+      double s_rr = 0.0, s_rz2 = 0.0;
+      for (int i = tid; i < n9; i += nt) {
+        const int row = i / 9, cp = i - 9 * row;
+        const double* Mi = a.Minv + 81 * (size_t)(r0 + row) + 9 * cp;
+        double z = 0.0;
+#pragma unroll
+        for (int m = 0; m < 9; ++m) z += Mi[m] * rs[row * 9 + m];
+        zs[i] = z;
+        publish(zk + (size_t)B * a.seg + i, z);
+        s_rr += rs[i] * rs[i];
+        s_rz2 += rs[i] * z;
+      }
+      s_rr = block_sum(s_rr, red);
+      s_rz2 = block_sum(s_rz2, red);
+      double* pa = a.partA + (size_t)k * pstride;
+      if (tid == 0) {
+        publish(pa + (size_t)B * PART_STRIDE, s_rr);
+        publish(pa + (size_t)B * PART_STRIDE + 1, s_rz2);
+      }
+      ok = grid_barrier(a.gs, a.error);
+      if (!ok) break;
+      const double rr = grid_sum(pa, G, 0, red);
+      const double rz_new = grid_sum(pa, G, 1, red);
+      iters = k;
+      rnorm = sqrt(rr);
+      if (rnorm <= a.rtol * bnorm) break;
+      const double beta = rz_new / rz;
+      rz = rz_new;
+      for (int i = tid; i < n9; i += nt) ps[i] = zs[i] + beta * ps[i];
+      spmv_own_rows<T>(a, zk, r0, nr, rptr, seg, seg_lo, seg_hi, ys);
+      s_pq = 0.0;
+      for (int i = tid; i < n9; i += nt) {
+        const double q = ys[i] + beta * qs[i];
+        qs[i] = q;
+        s_pq += ps[i] * q;
+      }
+      s_pq = block_sum(s_pq, red);
+      double* pb = a.partB + (size_t)k * pstride;
+      if (tid == 0) publish(pb + (size_t)B * PART_STRIDE, s_pq);
+      ok = grid_barrier(a.gs, a.error);
+      if (!ok) break;
+      pq = grid_sum(pb, G, 0, red);
+      if (!(pq > 0.0)) {
+        breakdown = 1;
+        break;
+      }
+      alpha = rz / pq;
+    }
+  }
+  for (int i = tid; i < n9; i += nt) a.x[9 * (size_t)r0 + i] = xs[i];
+  if (B == 0 && tid == 0) {
+    a.info->cg_iters = iters;
+    a.info->cg_breakdown = breakdown;
+    a.info->cg_rel_resid = bnorm > 0.0 ? rnorm / bnorm : 0.0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// back-substitution and the predicted reduction (one workgroup per chunk):
+//   dp_j = Vinv_j (-gp_j - sum_x w_x Jp_x^T Jc_x dc_{c_x}),
+//   pred partials: gp_j . dp_j and sum_x w_x |Jc_x dc + Jp_x dp_j|^2,
+//   candidate points p'_j = p_j + dp_j.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(CHUNK) void k_backsub(BackArgs a) {
+  __shared__ double tk[3][CHUNK];
+  __shared__ double red[CHUNK / 64];
+  const int c = blockIdx.x;
+  const int x0 = a.chunk_ptr[c], x1 = a.chunk_ptr[c + 1];
+  const int t = threadIdx.x, x = x0 + t;
+  const T* __restrict__ Jall = reinterpret_cast<const T*>(a.J);
+  double Jc[2][9], Jp[2][3], w = 0.0, ec0 = 0.0, ec1 = 0.0;
+  int j = -1;
+  if (x < x1) {
+    j = a.o_pt[x];
+    load_J(Jall + (size_t)x * NJ, Jc, Jp);
+    w = a.w[x];
+    const double* dc = a.dc + 9 * (size_t)a.o_cam[x];
+#pragma unroll
+    for (int m = 0; m < 9; ++m) {
+      ec0 += Jc[0][m] * dc[m];
+      ec1 += Jc[1][m] * dc[m];
+    }
+#pragma unroll
+    for (int m = 0; m < 3; ++m) tk[m][t] = w * (Jp[0][m] * ec0 + Jp[1][m] * ec1);
+  }
+  __syncthreads();
+  double lin = 0.0;
+  const int j0 = a.chunk_pt[c], j1 = a.chunk_pt[c + 1];
+  for (int jj = j0 + t; jj < j1; jj += blockDim.x) {
+    const double* g = a.gp + 3 * (size_t)jj;
+    double s0 = -g[0], s1 = -g[1], s2 = -g[2];
+    const int lo = a.pt_ptr[jj] - x0, hi = a.pt_ptr[jj + 1] - x0;
+    for (int y = lo; y < hi; ++y) {
+      s0 -= tk[0][y];
+      s1 -= tk[1][y];
+      s2 -= tk[2][y];
+    }
+    const double* vi = a.Vinv + 6 * (size_t)jj;
+    const double d0 = vi[0] * s0 + vi[1] * s1 + vi[2] * s2;
+    const double d1 = vi[1] * s0 + vi[3] * s1 + vi[4] * s2;
+    const double d2 = vi[2] * s0 + vi[4] * s1 + vi[5] * s2;
+    double* dp = a.dp + 3 * (size_t)jj;
+    dp[0] = d0; dp[1] = d1; dp[2] = d2;
+    const double* P = a.pts + 3 * (size_t)jj;
+    double* Pn = a.pts_new + 3 * (size_t)jj;
+    Pn[0] = P[0] + d0; Pn[1] = P[1] + d1; Pn[2] = P[2] + d2;
+    lin += g[0] * d0 + g[1] * d1 + g[2] * d2;
+  }
+  __syncthreads();
+  double quad = 0.0;
+  if (x < x1) {
+    const double* dp = a.dp + 3 * (size_t)j;
+    const double e0 = ec0 + Jp[0][0] * dp[0] + Jp[0][1] * dp[1] + Jp[0][2] * dp[2];
+    const double e1 = ec1 + Jp[1][0] * dp[0] + Jp[1][1] * dp[1] + Jp[1][2] * dp[2];
+    quad = w * (e0 * e0 + e1 * e1);
+  }
+  const double ql = block_sum(quad, red);
+  const double ll = block_sum(lin, red);
+  if (t == 0) {
+    a.part_pred[2 * (size_t)c] = ql;
+    a.part_pred[2 * (size_t)c + 1] = ll;
+  }
+}
+
+// candidate cameras theta' = Exp(dc) theta (fixed cameras copied) and the
+// partials of gc . dc (one thread per camera).
+__global__ __launch_bounds__(256) void k_retract_cameras(RetractArgs a) {
+  __shared__ double red[4];
+  const int cam = blockIdx.x * blockDim.x + threadIdx.x;
+  double lin = 0.0;
+  if (cam < a.nc) {
+    const double* src = a.cams + 10 * (size_t)cam;
+    double* dst = a.cams_new + 10 * (size_t)cam;
+    const double* dc = a.dc + 9 * (size_t)cam;
+    if (a.fixed[cam]) {
+      for (int q = 0; q < 10; ++q) dst[q] = src[q];
+    } else {
+      retract_camera(src, dc, dst);
+    }
+    const double* g = a.gc + 9 * (size_t)cam;
+    for (int m = 0; m < 9; ++m) lin += g[m] * dc[m];
+  }
+  const double s = block_sum(lin, red);
+  if (threadIdx.x == 0) a.part_linc[blockIdx.x] = s;
+}
+
+// cost at the candidate (one workgroup per chunk)
+__global__ __launch_bounds__(CHUNK) void k_candidate_cost(CostArgs a) {
+  __shared__ double red[CHUNK / 64];
+  const int c = blockIdx.x;
+  const int x = a.chunk_ptr[c] + threadIdx.x;
+  double cost = 0.0;
+  if (x < a.chunk_ptr[c + 1]) {
+    const Camera cam = load_camera(a.cams + 10 * (size_t)a.o_cam[x]);
+    const double* P = a.pts + 3 * (size_t)a.o_pt[x];
+    const Proj pr = project(cam, v3(P[0], P[1], P[2]));
+    const double rx = pr.px - a.o_xy[2 * (size_t)x], ry = pr.py - a.o_xy[2 * (size_t)x + 1];
+    double drho;
+    const double rho = robust_rho(rx * rx + ry * ry, a.huber, &drho);
+    cost = 0.5 * a.o_w[x] * rho;
+  }
+  const double s = block_sum(cost, red);
+  if (threadIdx.x == 0) a.part_cost_new[c] = s;
+}
+
+// acceptance and the trust-region damping update (one workgroup)
+__global__ __launch_bounds__(256) void k_finalize(FinalArgs a) {
+  __shared__ double red[4];
+  const double Fn = block_sum_array(a.part_cost_new, a.nchunk, red);
+  double q = 0.0, lp = 0.0;
+  for (int i = threadIdx.x; i < a.nchunk; i += blockDim.x) {
+    q += a.part_pred[2 * (size_t)i];
+    lp += a.part_pred[2 * (size_t)i + 1];
+  }
+  q = block_sum(q, red);
+  lp = block_sum(lp, red);
+  const double lc = block_sum_array(a.part_linc, a.ncamblk, red);
+  double gm = 0.0;
+  for (int i = threadIdx.x; i < a.nchunk; i += blockDim.x) gm = fmax(gm, a.part_gmax[i]);
+  for (int i = threadIdx.x; i < 9 * a.nc; i += blockDim.x) gm = fmax(gm, fabs(a.gc[i]));
+  gm = block_max(gm, red);
+  if (threadIdx.x == 0) {
+    DevScalars* dev = a.dev;
+    const double F = dev->F;
+    const double lam = dev->lambda;
+    const double pred = -(lc + lp) - 0.5 * q;
+    const bool accept = isfinite(Fn) && Fn < F && pred > 0.0;
+    const double ratio = (F - Fn) / pred;
+    double ln = lam;
+    if (!accept || ratio <= 0.25) ln = fmin(16.0 * lam, a.lambda_max);
+    else if (ratio > 0.75) ln = fmax(0.5 * lam, a.lambda_min);
+    dev->lambda = ln;
+    if (accept) dev->F = Fn;
+    ba_step_info* info = a.info;
+    info->cost_before = F;
+    info->cost_after = Fn;
+    info->lambda_used = lam;
+    info->lambda_next = ln;
+    info->pred = pred;
+    info->grad_inf = gm;
+    info->accepted = accept ? 1 : 0;
+    info->status = 0;
+  }
+}
+
+// gather the caller's observations into position order, with validation
+__global__ __launch_bounds__(256) void k_set_observations(ObsArgs a) {
+  const int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (x >= a.no) return;
+  const int64_t k = a.o_orig[x];
+  const double px = a.xy[2 * k], py = a.xy[2 * k + 1];
+  const double w = a.w ? a.w[k] : 1.0;
+  if (!isfinite(px) || !isfinite(py)) atomicOr(&a.dev->error, (int)ERR_NONFINITE_OBS);
+  if (!(w > 0.0) || !isfinite(w)) atomicOr(&a.dev->error, (int)ERR_BAD_WEIGHT);
+  a.o_xy[2 * x] = px;
+  a.o_xy[2 * x + 1] = py;
+  a.o_w[x] = w;
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+
+template <typename T>
+hipError_t launch_linearize(const LinArgs& a, int nchunk, hipStream_t s) {
+  hipLaunchKernelGGL(k_linearize<T>, dim3(nchunk), dim3(CHUNK), 0, s, a);
+  return hipGetLastError();
+}
+template hipError_t launch_linearize<float>(const LinArgs&, int, hipStream_t);
+template hipError_t launch_linearize<double>(const LinArgs&, int, hipStream_t);
+
+hipError_t launch_reduce_cost(const double* part, int n, DevScalars* dev, hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce_cost, dim3(1), dim3(256), 0, s, part, n, dev);
+  return hipGetLastError();
+}
+
+hipError_t launch_damp_points(const DampArgs& a, hipStream_t s) {
+  const int n = a.np > MAX_BARRIER_GROUPS + 1 ? a.np : MAX_BARRIER_GROUPS + 1;
+  hipLaunchKernelGGL(k_damp_points, dim3((n + 255) / 256), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_point_q(const PointQArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_point_q<T>, dim3((unsigned)((a.no + 255) / 256)), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+template hipError_t launch_point_q<float>(const PointQArgs&, hipStream_t);
+template hipError_t launch_point_q<double>(const PointQArgs&, hipStream_t);
+
+template <typename T>
+hipError_t launch_camera_vec(const CamVecArgs& a, int nc, hipStream_t s) {
+  hipLaunchKernelGGL(k_camera_vec<T>, dim3(nc), dim3(CAM_THREADS), 0, s, a);
+  return hipGetLastError();
+}
+template hipError_t launch_camera_vec<float>(const CamVecArgs&, int, hipStream_t);
+template hipError_t launch_camera_vec<double>(const CamVecArgs&, int, hipStream_t);
+
+template <typename T>
+hipError_t launch_schur_pairs(const SchurArgs& a, int nwg, hipStream_t s) {
+  hipLaunchKernelGGL(k_schur_pairs<T>, dim3(nwg), dim3(SCHUR_THREADS), 0, s, a);
+  return hipGetLastError();
+}
+template hipError_t launch_schur_pairs<float>(const SchurArgs&, int, hipStream_t);
+template hipError_t launch_schur_pairs<double>(const SchurArgs&, int, hipStream_t);
+
+template <typename T>
+hipError_t launch_camera_finish(const CamFinishArgs& a, int nc, hipStream_t s) {
+  hipLaunchKernelGGL(k_camera_finish<T>, dim3(nc), dim3(64), 0, s, a);
+  return hipGetLastError();
+}
+template hipError_t launch_camera_finish<float>(const CamFinishArgs&, int, hipStream_t);
+template hipError_t launch_camera_finish<double>(const CamFinishArgs&, int, hipStream_t);
+
+template <typename T>
+int pcg_max_grid() {
+  int dev = 0, ncu = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_pcg<T>, PCG_THREADS, 0) != hipSuccess)
+    return 0;
+  return ncu * per;
+}
+template int pcg_max_grid<float>();
+template int pcg_max_grid<double>();
+
+template <typename T>
+hipError_t launch_pcg(const PcgArgs& a, int grid, hipStream_t s) {
+  void* args[] = {const_cast<PcgArgs*>(&a)};
+  return hipLaunchCooperativeKernel(reinterpret_cast<void*>(k_pcg<T>), dim3(grid), dim3(PCG_THREADS),
+                                    args, 0, s);
+}
+template hipError_t launch_pcg<float>(const PcgArgs&, int, hipStream_t);
+template hipError_t launch_pcg<double>(const PcgArgs&, int, hipStream_t);
+
+template <typename T>
+hipError_t launch_backsub(const BackArgs& a, int nchunk, hipStream_t s) {
+  hipLaunchKernelGGL(k_backsub<T>, dim3(nchunk), dim3(CHUNK), 0, s, a);
+  return hipGetLastError();
+}
+template hipError_t launch_backsub<float>(const BackArgs&, int, hipStream_t);
+template hipError_t launch_backsub<double>(const BackArgs&, int, hipStream_t);
+
+hipError_t launch_retract_cameras(const RetractArgs& a, int nblk, hipStream_t s) {
+  hipLaunchKernelGGL(k_retract_cameras, dim3(nblk), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_candidate_cost(const CostArgs& a, int nchunk, hipStream_t s) {
+  hipLaunchKernelGGL(k_candidate_cost, dim3(nchunk), dim3(CHUNK), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize(const FinalArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_observations(const ObsArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_observations, dim3((unsigned)((a.no + 255) / 256)), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace ba

@@ -1,0 +1,237 @@
+// Host-side symbolic analysis of the observation pattern.
+//
+// The sparsity of J, and hence of J^T J and of the reduced camera matrix,
+// depends only on which camera sees which point, so it is analysed once per
+// problem and reused by every LM iteration (the paper caches its symbolic
+// sparse-product table the same way, Sec. IV-B-1).  Produces:
+//   - observation "positions": the observations sorted by (point, camera,
+//     original index), so every point's track is a contiguous, camera-sorted
+//     run;
+//   - point-aligned chunks of at most CHUNK positions (one workgroup each);
+//   - positions grouped by camera;
+//   - the upper block pattern of the reduced camera matrix (camera a <= b
+//     share a point), diagonal first in each row, plus its transpose lists;
+//   - for every S block the list of observation pairs (x, y) feeding it (the
+//     numeric Schur product's table), and the packing of the blocks' pair
+//     chunks into workgroups of SCHUR_SLOTS chunk slots.
+#include <algorithm>
+#include <climits>
+#include <cstdio>
+#include <numeric>
+
+#include "ba_internal.h"
+
+namespace ba {
+
+std::string build_plan(int32_t nc, int32_t np, int64_t no, const int32_t* cidx, const int32_t* pidx,
+                       Plan* P) {
+  char msg[256];
+  if (nc <= 0 || np <= 0 || no <= 0) return "n_cams, n_pts and n_obs must be positive";
+  if (no >= INT32_MAX / 2) return "n_obs too large for 32-bit positions";
+  for (int64_t k = 0; k < no; ++k) {
+    if (cidx[k] < 0 || cidx[k] >= nc || pidx[k] < 0 || pidx[k] >= np) {
+      std::snprintf(msg, sizeof msg, "observation %lld has index out of range (cam %d, pt %d)",
+                    (long long)k, cidx[k], pidx[k]);
+      return msg;
+    }
+  }
+  Plan& p = *P;
+  p.nc = nc;
+  p.np = np;
+  p.no = no;
+
+  // stable counting sort by camera, then by point: order (point, camera, k)
+  std::vector<int64_t> by_cam(no), order(no);
+  {
+    std::vector<int64_t> cnt(nc + 1, 0);
+    for (int64_t k = 0; k < no; ++k) cnt[cidx[k] + 1]++;
+    for (int32_t i = 0; i < nc; ++i) cnt[i + 1] += cnt[i];
+    for (int64_t k = 0; k < no; ++k) by_cam[cnt[cidx[k]]++] = k;
+  }
+  p.pt_ptr.assign(np + 1, 0);
+  for (int64_t k = 0; k < no; ++k) p.pt_ptr[pidx[k] + 1]++;
+  for (int32_t j = 0; j < np; ++j) p.pt_ptr[j + 1] += p.pt_ptr[j];
+  {
+    std::vector<int32_t> fill(p.pt_ptr.begin(), p.pt_ptr.end() - 1);
+    for (int64_t i = 0; i < no; ++i) {
+      const int64_t k = by_cam[i];
+      order[fill[pidx[k]]++] = k;
+    }
+  }
+  p.o_orig = order;
+  p.o_cam.resize(no);
+  p.o_pt.resize(no);
+  for (int64_t x = 0; x < no; ++x) {
+    p.o_cam[x] = cidx[order[x]];
+    p.o_pt[x] = pidx[order[x]];
+  }
+  p.max_track = 0;
+  for (int32_t j = 0; j < np; ++j) p.max_track = std::max(p.max_track, p.pt_ptr[j + 1] - p.pt_ptr[j]);
+  if (p.max_track > MAX_TRACK) {
+    std::snprintf(msg, sizeof msg, "a point is observed %d times; at most %d are supported",
+                  p.max_track, MAX_TRACK);
+    return msg;
+  }
+
+  // point-aligned chunks
+  p.chunk_ptr.assign(1, 0);
+  p.chunk_pt.assign(1, 0);
+  {
+    int32_t start = 0;
+    for (int32_t j = 0; j < np; ++j) {
+      if (p.pt_ptr[j + 1] - start > CHUNK) {
+        p.chunk_ptr.push_back(p.pt_ptr[j]);
+        p.chunk_pt.push_back(j);
+        start = p.pt_ptr[j];
+      }
+    }
+    p.chunk_ptr.push_back((int32_t)no);
+    p.chunk_pt.push_back(np);
+  }
+
+  // positions grouped by camera (ascending position inside a camera)
+  p.cam_ptr.assign(nc + 1, 0);
+  for (int64_t x = 0; x < no; ++x) p.cam_ptr[p.o_cam[x] + 1]++;
+  for (int32_t i = 0; i < nc; ++i) p.cam_ptr[i + 1] += p.cam_ptr[i];
+  p.cam_obs.resize(no);
+  {
+    std::vector<int32_t> fill(p.cam_ptr.begin(), p.cam_ptr.end() - 1);
+    for (int64_t x = 0; x < no; ++x) p.cam_obs[fill[p.o_cam[x]]++] = (int32_t)x;
+  }
+
+  // track ranges with equal / larger camera
+  std::vector<int32_t> same_lo(no), gt_lo(no);
+  for (int32_t j = 0; j < np; ++j) {
+    const int32_t lo = p.pt_ptr[j], hi = p.pt_ptr[j + 1];
+    int32_t x = lo;
+    while (x < hi) {
+      int32_t y = x;
+      while (y < hi && p.o_cam[y] == p.o_cam[x]) ++y;
+      for (int32_t z = x; z < y; ++z) {
+        same_lo[z] = x;
+        gt_lo[z] = y;
+      }
+      x = y;
+    }
+  }
+
+  // upper block pattern
+  std::vector<std::vector<int32_t>> cols(nc);
+  int64_t npairs = 0;
+  for (int64_t x = 0; x < no; ++x) {
+    const int32_t hi = p.pt_ptr[p.o_pt[x] + 1];
+    npairs += hi - same_lo[x];
+    for (int32_t y = gt_lo[x]; y < hi; ++y) cols[p.o_cam[x]].push_back(p.o_cam[y]);
+  }
+  if (npairs >= INT32_MAX) return "too many co-visible observation pairs";
+  p.n_pairs = npairs;
+  p.S_ptr.assign(nc + 1, 0);
+  for (int32_t a = 0; a < nc; ++a) {
+    auto& v = cols[a];
+    std::sort(v.begin(), v.end());
+    v.erase(std::unique(v.begin(), v.end()), v.end());
+    p.S_ptr[a + 1] = p.S_ptr[a] + 1 + (int32_t)v.size();
+  }
+  p.nnzb = p.S_ptr[nc];
+  p.S_col.resize(p.nnzb);
+  p.blk_row.resize(p.nnzb);
+  for (int32_t a = 0; a < nc; ++a)
+    for (int32_t e = p.S_ptr[a]; e < p.S_ptr[a + 1]; ++e) p.blk_row[e] = a;
+  for (int32_t a = 0; a < nc; ++a) {
+    p.S_col[p.S_ptr[a]] = a;
+    std::copy(cols[a].begin(), cols[a].end(), p.S_col.begin() + p.S_ptr[a] + 1);
+  }
+
+  // pair table grouped by block: diagonal pairs (same camera, y in
+  // [same_lo, gt_lo), including y = x) and off-diagonal pairs (y in
+  // [gt_lo, track end)); ascending x within a block
+  std::vector<int32_t> pair_blk_of(npairs);
+  std::vector<int32_t> bcount(p.nnzb + 1, 0);
+  {
+    int64_t q = 0;
+    for (int64_t x = 0; x < no; ++x) {
+      const int32_t a = p.o_cam[x];
+      const int32_t hi = p.pt_ptr[p.o_pt[x] + 1];
+      const int32_t* rb = p.S_col.data() + p.S_ptr[a] + 1;
+      const int32_t* re = p.S_col.data() + p.S_ptr[a + 1];
+      for (int32_t y = same_lo[x]; y < hi; ++y) {
+        int32_t e = p.S_ptr[a];
+        if (y >= gt_lo[x]) e = (int32_t)(std::lower_bound(rb, re, p.o_cam[y]) - p.S_col.data());
+        pair_blk_of[q++] = e;
+        bcount[e + 1]++;
+      }
+    }
+  }
+  for (int64_t e = 0; e < p.nnzb; ++e) bcount[e + 1] += bcount[e];
+  p.pair_x.resize(npairs);
+  p.pair_y.resize(npairs);
+  {
+    std::vector<int32_t> fill(bcount.begin(), bcount.end() - 1);
+    int64_t q = 0;
+    for (int64_t x = 0; x < no; ++x) {
+      const int32_t hi = p.pt_ptr[p.o_pt[x] + 1];
+      for (int32_t y = same_lo[x]; y < hi; ++y) {
+        const int32_t e = pair_blk_of[q++];
+        p.pair_x[fill[e]] = (int32_t)x;
+        p.pair_y[fill[e]] = y;
+        fill[e]++;
+      }
+    }
+  }
+  // chunks: a block of P pairs gets min(SCHUR_SLOTS, ceil(P / SCHUR_CHUNK))
+  // chunks (at least one); blocks are packed into workgroups of SCHUR_SLOTS
+  // slots, largest first, next-fit
+  {
+    std::vector<int32_t> nch(p.nnzb);
+    std::vector<int32_t> order(p.nnzb);
+    for (int64_t e = 0; e < p.nnzb; ++e) {
+      const int32_t P = bcount[e + 1] - bcount[e];
+      nch[e] = std::max(1, std::min(SCHUR_SLOTS, (P + SCHUR_CHUNK - 1) / SCHUR_CHUNK));
+      order[e] = (int32_t)e;
+    }
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return nch[a] > nch[b]; });
+    p.slot_blk.clear();
+    int32_t used = SCHUR_SLOTS;
+    for (int32_t e : order) {
+      if (used + nch[e] > SCHUR_SLOTS) {
+        p.slot_blk.insert(p.slot_blk.end(), SCHUR_SLOTS, -1);
+        p.slot_pb.insert(p.slot_pb.end(), SCHUR_SLOTS, 0);
+        p.slot_pe.insert(p.slot_pe.end(), SCHUR_SLOTS, 0);
+        p.slot_lead.insert(p.slot_lead.end(), SCHUR_SLOTS, 0);
+        used = 0;
+      }
+      const size_t base = p.slot_blk.size() - SCHUR_SLOTS + used;
+      const int32_t P = bcount[e + 1] - bcount[e], n = nch[e];
+      for (int32_t k = 0; k < n; ++k) {
+        p.slot_blk[base + k] = e;
+        p.slot_pb[base + k] = bcount[e] + (int32_t)((int64_t)P * k / n);
+        p.slot_pe[base + k] = bcount[e] + (int32_t)((int64_t)P * (k + 1) / n);
+        p.slot_lead[base + k] = k == 0 ? n : 0;
+      }
+      used += n;
+    }
+    p.n_schur_wg = (int32_t)(p.slot_blk.size() / SCHUR_SLOTS);
+  }
+
+  // transpose lists: row b receives upper blocks (a, b) with a < b, ascending a
+  p.T_ptr.assign(nc + 1, 0);
+  for (int32_t a = 0; a < nc; ++a)
+    for (int32_t e = p.S_ptr[a] + 1; e < p.S_ptr[a + 1]; ++e) p.T_ptr[p.S_col[e] + 1]++;
+  for (int32_t b = 0; b < nc; ++b) p.T_ptr[b + 1] += p.T_ptr[b];
+  p.T_blk.resize(p.T_ptr[nc]);
+  p.T_src.resize(p.T_ptr[nc]);
+  {
+    std::vector<int32_t> fill(p.T_ptr.begin(), p.T_ptr.end() - 1);
+    for (int32_t a = 0; a < nc; ++a)
+      for (int32_t e = p.S_ptr[a] + 1; e < p.S_ptr[a + 1]; ++e) {
+        const int32_t b = p.S_col[e];
+        p.T_blk[fill[b]] = e;
+        p.T_src[fill[b]] = a;
+        fill[b]++;
+      }
+  }
+
+  return std::string();
+}
+
+}  // namespace ba

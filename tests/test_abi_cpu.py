@@ -1,0 +1,119 @@
+"""C ABI checks that need no GPU: the library loads, exports every function
+include/ba.h declares, validates its inputs, and its host-side symbolic
+analysis agrees with the oracle's block pattern."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2409_12190_amd import ba as B
+from synth.scenes import make_scene
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "ba.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(ba_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_header_functions_are_exported():
+    names = declared_functions()
+    assert "ba_lm_step" in names and "ba_problem_create" in names
+    lib = B.lib()
+    for n in names:
+        assert hasattr(lib, n), n
+    assert sorted(B.EXPORTED_SYMBOLS) == names
+
+
+def test_default_options():
+    o = B.ba_default_options()
+    assert o.cam_dof == 9 and o.precision == B.BA_FP64
+    assert o.cg_rtol == 1e-4 and o.cg_maxiter == 250
+    assert o.lambda0 == 1e-4 and o.diag_min == 1e-6
+
+
+def _create(n_c, n_p, ci, pi, **kw):
+    o = B.ba_default_options()
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return B.ba_problem_create(o, n_c, n_p, ci, pi)
+
+
+def test_create_rejects_bad_indices_and_sizes():
+    with pytest.raises(B.BaError) as e:
+        _create(3, 3, [0, 1, 3], [0, 1, 2])
+    assert e.value.status == B.BA_EINVAL
+    with pytest.raises(B.BaError) as e:
+        _create(3, 3, [0, 1, 2], [0, -1, 2])
+    assert e.value.status == B.BA_EINVAL
+    with pytest.raises(B.BaError) as e:
+        _create(3, 3, [], [])
+    assert e.value.status == B.BA_EINVAL
+    with pytest.raises(B.BaError) as e:
+        _create(3, 3, [0], [0], cam_dof=6)
+    assert e.value.status == B.BA_EUNSUPPORTED
+
+
+def test_track_length_limit():
+    n = 257
+    h = _create(n - 1, 1, np.arange(n - 1), np.zeros(n - 1))
+    B.ba_problem_destroy(h)
+    with pytest.raises(B.BaError) as e:
+        _create(n, 1, np.arange(n), np.zeros(n))
+    assert e.value.status == B.BA_EUNSUPPORTED
+
+
+def test_state_calls_before_bind_fail():
+    s = make_scene(0)
+    h = _create(s.n_cams, s.n_pts, s.cam_idx, s.pt_idx)
+    try:
+        info = B.ba_step_info()
+        assert B.lib().ba_lm_step(h, ctypes.byref(info)) == B.BA_ESTATE
+        assert B.lib().ba_set_observations(h, None, None) == B.BA_EINVAL
+        assert B.lib().ba_backward(h, None, None, None, None) == B.BA_EUNSUPPORTED
+    finally:
+        B.ba_problem_destroy(h)
+
+
+@pytest.mark.parametrize("cfg,kw", [(0, {}), (1, dict(n_cams=200, n_pts=3000)),
+                                    (2, dict(n_cams=2000, n_pts=20000))])
+def test_block_pattern_matches_oracle(cfg, kw):
+    s = make_scene(cfg, **kw)
+    h = _create(s.n_cams, s.n_pts, s.cam_idx, s.pt_idx)
+    try:
+        o = O.Oracle.from_scene(s)
+        assert B.ba_problem_nnzb(h) == o.nnzb()
+        ptr = np.zeros(s.n_cams + 1, np.int64)
+        col = np.zeros(o.nnzb(), np.int32)
+        assert B.lib().ba_export(h, B.BA_X_S_PTR, ptr.ctypes.data, ptr.nbytes) == B.BA_ESTATE
+    finally:
+        B.ba_problem_destroy(h)
+
+
+def test_workspace_grows_linearly_with_observations():
+    s = make_scene(1, n_cams=200, n_pts=3000)
+    h1 = _create(s.n_cams, s.n_pts, s.cam_idx, s.pt_idx)
+    h2 = _create(s.n_cams, s.n_pts, s.cam_idx, s.pt_idx, precision=B.BA_MIXED)
+    try:
+        b64, b32 = B.ba_problem_workspace_bytes(h1), B.ba_problem_workspace_bytes(h2)
+        # FP32 storage of the Jacobian blocks, the per-observation Schur
+        # factors and S saves 4 bytes per stored value
+        saved = s.n_obs * (24 + 6) * 4 + B.ba_problem_nnzb(h1) * 81 * 4
+        assert abs((b64 - b32) - saved) < 64 * 256
+    finally:
+        B.ba_problem_destroy(h1)
+        B.ba_problem_destroy(h2)
+
+
+def test_bench_refuses_several_gpus():
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode != 0 and "one GPU" in r.stderr
