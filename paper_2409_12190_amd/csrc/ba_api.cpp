@@ -68,6 +68,12 @@ void carve(ba_problem* p, char* base, size_t* total) {
   b.slot_pe = c.take<int32_t>(P.slot_pe.size());
   b.slot_lead = c.take<int32_t>(P.slot_lead.size());
   b.blk_row = c.take<int32_t>(nnzb);
+  b.pcg_row = c.take<int32_t>(P.pcg_row.size());
+  b.item_ptr = c.take<int32_t>(P.item_ptr.size());
+  b.item_e = c.take<int32_t>(P.item_e.size());
+  b.item_code = c.take<int32_t>(P.item_code.size());
+  b.ucol_ptr = c.take<int32_t>(P.ucol_ptr.size());
+  b.ucol = c.take<int32_t>(P.ucol.size());
   b.o_orig = c.take<int64_t>(no);
   b.fixed = c.take<uint8_t>(nc);
   b.o_xy = c.take<double>(2 * no);
@@ -97,11 +103,10 @@ void carve(ba_problem* p, char* base, size_t* total) {
   b.part_pred = c.take<double>(2 * nch);
   b.part_gmax = c.take<double>(nch);
   b.part_linc = c.take<double>((nc + 255) / 256);
-  const ba::PcgShape sh = ba::pcg_shape(P.nc);
   const size_t slots = (size_t)p->opt.cg_maxiter + 1;
-  b.zring = c.take<double>(slots * sh.grid * sh.seg);
-  b.partA = c.take<double>(slots * sh.grid * ba::PART_STRIDE);
-  b.partB = c.take<double>(slots * sh.grid * ba::PART_STRIDE);
+  b.zring = c.take<double>(slots * nc * ba::ZSTRIDE);
+  b.partA = c.take<double>(slots * P.pcg_grid * ba::PART_STRIDE);
+  b.partB = c.take<double>(slots * P.pcg_grid * ba::PART_STRIDE);
   b.dev = c.take<ba::DevScalars>(1);
   b.dinfo = c.take<ba_step_info>(1);
   b.gsync = c.take<ba::GridSync>(1);
@@ -182,13 +187,12 @@ ba_status lm_step_impl(ba_problem* p, ba_step_info* out) {
   SchurArgs sa{b.slot_blk, b.slot_pb, b.slot_pe, b.slot_lead, b.pair_x, b.pair_y, b.blk_row,
                b.S_ptr, b.J, b.Q, b.w, b.S, b.Sdiag};
   PHASE(5, launch_schur_pairs<T>(sa, P.n_schur_wg, s));
-  CamFinishArgs cf{b.S_ptr, b.Sdiag, b.diagU, p->opt.diag_min, p->opt.diag_max, b.S, b.Minv, b.dev};
+  CamFinishArgs cf{b.Sdiag, b.diagU, p->opt.diag_min, p->opt.diag_max, b.Minv, b.dev};
   PHASE(6, launch_camera_finish<T>(cf, P.nc, s));
-  const PcgShape sh = pcg_shape(P.nc);
-  PcgArgs pa{P.nc, p->cg_maxiter, sh.rows, sh.seg, p->cg_rtol, b.S_ptr, b.S_col, b.T_ptr, b.T_blk,
-             b.T_src, b.S, b.Minv, b.bS, b.x, b.zring, b.partA, b.partB, b.dinfo, b.gsync,
-             &b.dev->error};
-  PHASE(7, launch_pcg<T>(pa, sh.grid, s));
+  PcgArgs pa{P.nc, p->cg_maxiter, p->cg_rtol, b.S_ptr, b.T_ptr, b.pcg_row, b.item_ptr, b.item_e,
+             b.item_code, b.ucol_ptr, b.ucol, b.S, b.Sdiag, b.Minv, b.bS, b.x, b.zring, b.partA,
+             b.partB, b.dinfo, b.gsync, &b.dev->error};
+  PHASE(7, launch_pcg<T>(pa, P.pcg_grid, P.pcg_resident, s));
   BackArgs ba_{b.chunk_ptr, b.chunk_pt, b.pt_ptr, b.o_cam, b.o_pt, b.J, b.w, b.x, b.gp, b.Vinv,
                b.pts[cur], b.dp, b.pts[nxt], b.part_pred};
   PHASE(8, launch_backsub<T>(ba_, nchunk, s));
@@ -339,6 +343,12 @@ ba_status ba_problem_bind(ba_problem* p, void* ws, size_t bytes, void* stream) {
   HIPCHK(upload(b.slot_pe, P.slot_pe, s));
   HIPCHK(upload(b.slot_lead, P.slot_lead, s));
   HIPCHK(upload(b.blk_row, P.blk_row, s));
+  HIPCHK(upload(b.pcg_row, P.pcg_row, s));
+  HIPCHK(upload(b.item_ptr, P.item_ptr, s));
+  HIPCHK(upload(b.item_e, P.item_e, s));
+  HIPCHK(upload(b.item_code, P.item_code, s));
+  HIPCHK(upload(b.ucol_ptr, P.ucol_ptr, s));
+  HIPCHK(upload(b.ucol, P.ucol, s));
   HIPCHK(upload(b.o_orig, P.o_orig, s));
   HIPCHK(hipMemsetAsync(b.fixed, 0, P.nc, s));
   HIPCHK(hipMemsetAsync(b.gsync, 0, sizeof(ba::GridSync), s));
@@ -347,9 +357,10 @@ ba_status ba_problem_bind(ba_problem* p, void* ws, size_t bytes, void* stream) {
   *p->hscal = ba::DevScalars{0.0, p->lambda, 0, 0};
   HIPCHK(hipMemcpyAsync(b.dev, p->hscal, sizeof(ba::DevScalars), hipMemcpyHostToDevice, s));
   HIPCHK(hipStreamSynchronize(s));
-  const int maxg = p->opt.precision == BA_MIXED ? ba::pcg_max_grid<float>() : ba::pcg_max_grid<double>();
+  const int maxg = p->opt.precision == BA_MIXED ? ba::pcg_max_grid<float>(P.pcg_resident)
+                                                : ba::pcg_max_grid<double>(P.pcg_resident);
   if (maxg <= 0) return fail(BA_EHIP, "cooperative occupancy query failed");
-  p->pcg_grid = ba::pcg_shape(P.nc).grid;
+  p->pcg_grid = P.pcg_grid;
   if (p->pcg_grid > maxg || p->pcg_grid > ba::MAX_BARRIER_GROUPS * ba::BARRIER_FANIN)
     return fail(BA_EUNSUPPORTED, "too many cameras for one co-resident PCG grid");
   p->bound = true;
@@ -618,6 +629,11 @@ ba_status ba_export(const ba_problem* p, int32_t field, void* dst, size_t bytes)
       for (size_t q = 0; q < nnzb * 81; ++q)
         out[q] = mixed ? (double)reinterpret_cast<const float*>(h.data())[q]
                        : reinterpret_cast<const double*>(h.data())[q];
+      std::vector<char> hd;
+      HIPCHK(fetch(b.Sdiag, nc * 81 * sizeof(double), hd));  // diagonal blocks are kept in FP64
+      const double* d = reinterpret_cast<const double*>(hd.data());
+      for (size_t a = 0; a < nc; ++a)
+        std::memcpy(out + (size_t)P.S_ptr[a] * 81, d + a * 81, 81 * sizeof(double));
       return BA_OK;
     }
     default:

@@ -19,10 +19,16 @@ constexpr int SCHUR_THREADS = 256;
 constexpr int SCHUR_SLOTS = SCHUR_THREADS / 9;  // 28 pair chunks per workgroup, 9 lanes each
 constexpr int SCHUR_CHUNK = 16;                 // target pairs per chunk
 constexpr int CAM_THREADS = 128;
-constexpr int PCG_THREADS = 512;
+constexpr int PCG_THREADS = 1024;
 constexpr int PCG_RMAX = 64;          // block rows owned by one PCG workgroup
-constexpr int PCG_TARGET_GRID = 256;  // PCG workgroups aimed for on large systems
+constexpr int PCG_MAX_GRID = 256;     // PCG workgroups (one per compute unit)
+constexpr int PCG_GROUPS = PCG_THREADS / 9;  // 9-lane groups of a PCG workgroup
+constexpr int PCG_IPG = 3;            // register-resident items per lane group
+constexpr int ZSTRIDE = 16;           // doubles per block column in a PCG exchange slot
 constexpr int PART_STRIDE = 16;       // doubles per workgroup partial (one 128-byte line)
+constexpr int PCG_ZCOLS = 768;        // distinct block columns one PCG workgroup may touch
+constexpr int ITEM_TRANS = 1 << 16;   // PCG item flags: transposed upper block,
+constexpr int ITEM_DIAG = 1 << 17;    //   diagonal block (FP64, indexed by camera)
 constexpr int BARRIER_FANIN = 16;
 constexpr int MAX_BARRIER_GROUPS = 128;
 constexpr int MAX_TRACK = CHUNK;
@@ -49,6 +55,13 @@ struct Plan {
   // number of slots of the block when this slot is the block's first, else 0)
   std::vector<int32_t> slot_blk, slot_pb, slot_pe, slot_lead;
   std::vector<int32_t> blk_row;  // block -> its row (camera a)
+  // PCG workgroup decomposition: workgroup g owns rows [pcg_row[g],
+  // pcg_row[g+1]); its (row, block) items in row order with block index and
+  // code (local column | flags), and the distinct block columns it reads.
+  // pcg_resident: every lane group has at most PCG_IPG items.
+  std::vector<int32_t> pcg_row, item_ptr, item_e, item_code, ucol_ptr, ucol;
+  int32_t max_ucol = 0, pcg_grid = 0;
+  bool pcg_resident = false;
   int64_t nnzb = 0, n_pairs = 0;
   int32_t n_schur_wg = 0;
   int32_t max_track = 0;
@@ -83,25 +96,13 @@ struct GridSync {
   } group[MAX_BARRIER_GROUPS];
 };
 
-// PCG decomposition: grid of pcg_grid workgroups, rows_per_wg block rows each.
-struct PcgShape {
-  int grid, rows, seg;
-};
-inline PcgShape pcg_shape(int nc) {
-  int rows = (nc + PCG_TARGET_GRID - 1) / PCG_TARGET_GRID;
-  if (rows < 1) rows = 1;
-  if (rows > PCG_RMAX) rows = PCG_RMAX;
-  const int grid = (nc + rows - 1) / rows;
-  const int seg = ((rows * 9 + 15) / 16) * 16;
-  return PcgShape{grid, rows, seg};
-}
-
 // Device pointers carved out of the caller's workspace.
 struct Buffers {
   // plan
   int32_t *o_cam, *o_pt, *pt_ptr, *chunk_ptr, *chunk_pt, *cam_ptr, *cam_obs;
   int32_t *S_ptr, *S_col, *T_ptr, *T_blk, *T_src;
   int32_t *pair_x, *pair_y, *slot_blk, *slot_pb, *slot_pe, *slot_lead, *blk_row;
+  int32_t *pcg_row, *item_ptr, *item_e, *item_code, *ucol_ptr, *ucol;
   int64_t* o_orig;
   uint8_t* fixed;
   // observations (sorted by position)
@@ -115,22 +116,16 @@ struct Buffers {
   // damped quantities
   double *Vinv, *ep;
   void* Q;  // float or double [no][6]: w Jp Vinv of each observation
-  void* S;  // float or double [nnzb][81]
-  double *Sdiag, *bS, *Minv;  // FP64 undamped diagonal blocks, rhs, block-Jacobi inverse
-  // PCG vectors
-  double *x, *cr, *cz, *cp, *cq;
-  double* dp;
+  void* S;  // float or double [nnzb][81]; diagonal blocks live in Sdiag
+  double *Sdiag, *bS, *Minv;  // FP64 diagonal blocks (damped in place), rhs, block-Jacobi inverse
+  // step
+  double *x, *dp;
   // partial sums
   double *part_cost, *part_cost_new, *part_pred, *part_gmax, *part_linc;
   double *zring, *partA, *partB;  // PCG exchange rings, one slot per iteration
   DevScalars* dev;
   ba_step_info* dinfo;
   GridSync* gsync;
-};
-
-struct PcgResult {
-  double rel_resid;
-  int32_t iters, breakdown;
 };
 
 }  // namespace ba

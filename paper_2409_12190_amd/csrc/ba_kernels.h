@@ -53,20 +53,19 @@ struct SchurArgs {
 };
 
 struct CamFinishArgs {
-  const int32_t* S_ptr;
-  const double *Sdiag, *diagU;
+  double* Sdiag;  // undamped on entry, damped on exit
+  const double* diagU;
   double dmin, dmax;
-  void* S;
   double* Minv;
   DevScalars* dev;
 };
 
 struct PcgArgs {
-  int nc, maxiter, rows_per_wg, seg;
+  int nc, maxiter;
   double rtol;
-  const int32_t *S_ptr, *S_col, *T_ptr, *T_blk, *T_src;
+  const int32_t *S_ptr, *T_ptr, *wg_row, *item_ptr, *item_e, *item_code, *ucol_ptr, *ucol;
   const void* S;
-  const double *Minv, *b;
+  const double *Sdiag, *Minv, *b;
   double* x;
   double *zring, *partA, *partB;  // (maxiter + 1) slots each
   ba_step_info* info;
@@ -118,8 +117,8 @@ template <typename T> hipError_t launch_point_q(const PointQArgs&, hipStream_t);
 template <typename T> hipError_t launch_camera_vec(const CamVecArgs&, int nc, hipStream_t);
 template <typename T> hipError_t launch_schur_pairs(const SchurArgs&, int nwg, hipStream_t);
 template <typename T> hipError_t launch_camera_finish(const CamFinishArgs&, int nc, hipStream_t);
-template <typename T> int pcg_max_grid();
-template <typename T> hipError_t launch_pcg(const PcgArgs&, int grid, hipStream_t);
+template <typename T> int pcg_max_grid(bool resident);
+template <typename T> hipError_t launch_pcg(const PcgArgs&, int grid, bool resident, hipStream_t);
 template <typename T> hipError_t launch_backsub(const BackArgs&, int nchunk, hipStream_t);
 hipError_t launch_retract_cameras(const RetractArgs&, int nblk, hipStream_t);
 hipError_t launch_candidate_cost(const CostArgs&, int nchunk, hipStream_t);

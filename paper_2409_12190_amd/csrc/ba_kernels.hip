@@ -359,7 +359,7 @@ __global__ __launch_bounds__(SCHUR_THREADS) void k_schur_pairs(SchurArgs a) {
 
 // ---------------------------------------------------------------------------
 // diagonal blocks: S_aa = Sdiag_a + lambda clamp(diagU_a) (Eq. 2 damping with
-// the clamp of Sec. IV-B-3), stored in precision T, and the block-Jacobi
+// the clamp of Sec. IV-B-3), kept in FP64 (damped in place), and the block-Jacobi
 // preconditioner Minv_a = S_aa^-1 by Cholesky in FP64 (one workgroup per
 // camera; the factorisation by one lane).
 // ---------------------------------------------------------------------------
@@ -373,7 +373,7 @@ __global__ __launch_bounds__(64) void k_camera_finish(CamFinishArgs a) {
     const int r = q / 9;
     if (q == 10 * r) v += lam * fmin(fmax(a.diagU[9 * (size_t)cam + r], a.dmin), a.dmax);
     Sd[q] = v;
-    reinterpret_cast<T*>(a.S)[81 * (size_t)a.S_ptr[cam] + q] = (T)v;
+    a.Sdiag[81 * (size_t)cam + q] = v;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -422,16 +422,23 @@ __global__ __launch_bounds__(64) void k_camera_finish(CamFinishArgs a) {
 // launch overhead by replaying a captured PCG iteration, App. B; here the
 // iterations never leave the GPU).
 //
-// Workgroup B owns the contiguous block rows [B R, B R + R); its own-row
-// vectors stay in LDS for the whole solve.  Values other workgroups read (the
-// preconditioned residual z and the dot-product partials) are written once
-// per iteration into a fresh ring slot with agent-scope (write-through)
-// stores and read after a barrier with ordinary cached loads, so iterations
-// need no cache flush.  Dots are reduced from the per-workgroup partials in a
-// fixed order, identically in every workgroup, so every workgroup takes the
-// same branch.  Standard PCG recurrence; the product S p_k is formed as
-// S z_k + beta q_{k-1}, so the direction update and the product share one
-// barrier (two barriers per iteration).
+// Workgroup B owns the contiguous block rows [wg_row[B], wg_row[B+1]), chosen
+// on the host so that workgroups hold similar numbers of (row, block) items.
+// Its own-row vectors and block-Jacobi factors stay in LDS for the whole
+// solve.  The items are split into SPMV_GROUPS contiguous ranges; 9 lanes
+// share an item, lane `comp` holding row `comp` of the block (column `comp`
+// for a transposed upper block).  When every range has at most PCG_IPG items
+// (RES = true) the lanes keep their block values in registers for the whole
+// solve; otherwise they are streamed in batches of PCG_IPG each iteration.
+//
+// Values other workgroups read (the preconditioned residual z, by column,
+// and the dot-product partials) are written once per iteration into a fresh
+// ring slot with agent-scope (write-through) stores and read after a barrier
+// with ordinary cached loads, so iterations need no cache flush.  Dots are
+// reduced from the per-workgroup partials in a fixed order, identically in
+// every workgroup, so every workgroup takes the same branch.  Standard PCG
+// recurrence; the product S p_k is formed as S z_k + beta q_{k-1}, so the
+// direction update and the product share one barrier (two per iteration).
 // ---------------------------------------------------------------------------
 constexpr int SPMV_GROUPS = PCG_THREADS / 9;
 constexpr long BARRIER_SPIN_LIMIT = 1L << 21;
@@ -461,7 +468,7 @@ __device__ __forceinline__ bool grid_barrier(GridSync* gs, int* error) {
   __shared__ int failed;
   if (threadIdx.x == 0) {
     int f = __hip_atomic_load(error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & ERR_BARRIER;
-    if (!f) {
+    if (!f && gridDim.x > 1) {
       const unsigned gen = __hip_atomic_load(&gs->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       const unsigned grp = blockIdx.x / BARRIER_FANIN;
       const unsigned ngrp = (gridDim.x + BARRIER_FANIN - 1) / BARRIER_FANIN;
@@ -496,66 +503,81 @@ __device__ __forceinline__ bool grid_barrier(GridSync* gs, int* error) {
   return failed == 0;
 }
 
-// Fixed-order sum over workgroups of partial q of a ring slot (every
-// workgroup computes the identical value).
-__device__ __forceinline__ double grid_sum(const double* slot, int G, int q, double* red) {
-  double s = 0.0;
-  for (int i = threadIdx.x; i < G; i += blockDim.x) s += slot[(size_t)i * PART_STRIDE + q];
-  return block_sum(s, red);
+// Block values of a lane group's items (row `comp` of each block, or column
+// `comp` of a transposed upper block), with the item's LDS column slot and
+// local row.
+struct PcgItems {
+  double v[PCG_IPG][9];
+  int lc[PCG_IPG], rl[PCG_IPG];
+};
+
+template <typename T>
+__device__ __forceinline__ void pcg_load_items(const PcgArgs& a, int ib, int k0, int k1, const int* rptr,
+                                               int comp, PcgItems& it) {
+  const T* __restrict__ S = reinterpret_cast<const T*>(a.S);
+  int row = 0;
+  while (rptr[row + 1] <= k0) ++row;
+#pragma unroll
+  for (int kk = 0; kk < PCG_IPG; ++kk) {
+    const int i = k0 + kk;
+    if (i < k1) {
+      while (rptr[row + 1] <= i) ++row;
+      const int code = a.item_code[ib + i];
+      const int e = a.item_e[ib + i];
+      it.lc[kk] = code & 0xFFFF;
+      it.rl[kk] = row;
+      if (code & ITEM_DIAG) {
+        const double* Bp = a.Sdiag + (size_t)e * 81 + comp * 9;
+#pragma unroll
+        for (int m = 0; m < 9; ++m) it.v[kk][m] = Bp[m];
+      } else if (code & ITEM_TRANS) {
+        const T* Bp = S + (size_t)e * 81 + comp;
+#pragma unroll
+        for (int m = 0; m < 9; ++m) it.v[kk][m] = (double)Bp[9 * m];
+      } else {
+        const T* Bp = S + (size_t)e * 81 + comp * 9;
+#pragma unroll
+        for (int m = 0; m < 9; ++m) it.v[kk][m] = (double)Bp[m];
+      }
+    } else {
+      it.lc[kk] = 0;
+      it.rl[kk] = -1;
+    }
+  }
 }
 
-// y[own rows] = S zk over the upper blocks of the own rows and the transposes
-// of the upper blocks that end in them.  The workgroup's (row, block) items
-// are split into SPMV_GROUPS contiguous ranges; 9 lanes share an item, lane
-// `comp` computing one output component.  Each group keeps a running sum per
-// row and stores it at seg[row + group]; rows are then summed over groups in
-// group order.
-template <typename T>
-__device__ __forceinline__ void spmv_own_rows(const PcgArgs& a, const double* __restrict__ zk, int r0,
-                                              int nr, const int* rptr, double* seg, int* seg_lo,
-                                              int* seg_hi, double* y) {
-  const T* __restrict__ S = reinterpret_cast<const T*>(a.S);
-  const int nitems = rptr[nr];
+// y[own rows] = S z, with z's needed block columns already in LDS (zl).
+// Each group keeps a running sum per row and stores it at seg[row + group];
+// rows are then summed over groups in group order.
+template <typename T, bool RES>
+__device__ __forceinline__ void pcg_spmv(const PcgArgs& a, int ib, int i0, int i1, int nr,
+                                         const int* rptr, PcgItems& it, const double* zl, double* seg,
+                                         int* seg_lo, int* seg_hi, double* y) {
   const int g = threadIdx.x / 9, comp = threadIdx.x - 9 * (threadIdx.x / 9);
   if (g < SPMV_GROUPS) {
-    const int L = (nitems + SPMV_GROUPS - 1) / SPMV_GROUPS;
-    const int i0 = min(nitems, g * L), i1 = min(nitems, i0 + L);
-    int row = 0;
-    while (row < nr - 1 && rptr[row + 1] <= i0) ++row;
-    const int first = row;
-    int cur = row;
     double acc = 0.0;
-    for (int i = i0; i < i1; ++i) {
-      while (rptr[row + 1] <= i) ++row;
-      if (row != cur) {
-        seg[(cur + g) * 9 + comp] = acc;
-        acc = 0.0;
-        cur = row;
-      }
-      const int grow = r0 + row;
-      const int k = i - rptr[row];
-      const int ub = a.S_ptr[grow], nu = a.S_ptr[grow + 1] - ub;
-      int e, c;
-      bool up = k < nu;
-      if (up) {
-        e = ub + k;
-        c = a.S_col[e];
-      } else {
-        const int t = a.T_ptr[grow] + (k - nu);
-        e = a.T_blk[t];
-        c = a.T_src[t];
-      }
-      const int own = c / a.rows_per_wg;
-      const double* zc = zk + (size_t)own * a.seg + (size_t)(c - own * a.rows_per_wg) * 9;
-      const T* Bp = S + (size_t)e * 81 + (up ? comp * 9 : comp);
-      const int st = up ? 1 : 9;
+    int cur = -1, first = -1;
+    for (int k0 = i0; k0 < i1; k0 += PCG_IPG) {
+      if (!RES) pcg_load_items<T>(a, ib, k0, i1, rptr, comp, it);
 #pragma unroll
-      for (int m = 0; m < 9; ++m) acc += (double)Bp[m * st] * zc[m];
+      for (int kk = 0; kk < PCG_IPG; ++kk) {
+        const int rl = it.rl[kk];
+        if (rl < 0) continue;
+        if (rl != cur) {
+          if (cur >= 0) seg[(cur + g) * 9 + comp] = acc;
+          if (first < 0) first = rl;
+          acc = 0.0;
+          cur = rl;
+        }
+        const double* zc = zl + it.lc[kk] * 9;
+#pragma unroll
+        for (int m = 0; m < 9; ++m) acc += it.v[kk][m] * zc[m];
+      }
     }
-    if (i0 < i1) seg[(cur + g) * 9 + comp] = acc;
+    if (cur >= 0) seg[(cur + g) * 9 + comp] = acc;
     if (comp == 0) {
-      seg_lo[g] = i0 < i1 ? first : 1;
-      seg_hi[g] = i0 < i1 ? cur : 0;
+      seg_lo[g] = cur >= 0 ? first : 1;
+      seg_hi[g] = cur >= 0 ? cur : 0;
     }
   }
   __syncthreads();
@@ -569,20 +591,35 @@ __device__ __forceinline__ void spmv_own_rows(const PcgArgs& a, const double* __
   __syncthreads();
 }
 
-template <typename T>
+// fetch the block columns this workgroup reads from ring slot zk into LDS
+__device__ __forceinline__ void pcg_fetch_z(const PcgArgs& a, const double* zk, int ub, int nuc,
+                                            double* zl) {
+  for (int u = threadIdx.x; u < nuc * 9; u += blockDim.x) {
+    const int j = u / 9;
+    zl[u] = zk[(size_t)a.ucol[ub + j] * ZSTRIDE + (u - 9 * j)];
+  }
+}
+
+template <typename T, bool RES>
 __global__ __launch_bounds__(PCG_THREADS) void k_pcg(PcgArgs a) {
   __shared__ double xs[PCG_RMAX * 9], rs[PCG_RMAX * 9], ps[PCG_RMAX * 9];
   __shared__ double qs[PCG_RMAX * 9], zs[PCG_RMAX * 9], ys[PCG_RMAX * 9];
-  __shared__ int rptr[PCG_RMAX + 1];
+  __shared__ double Ml[PCG_RMAX * 81];
+  __shared__ double zl[PCG_ZCOLS * 9];
   __shared__ double seg[(PCG_RMAX + SPMV_GROUPS) * 9];
   __shared__ int seg_lo[SPMV_GROUPS], seg_hi[SPMV_GROUPS];
+  __shared__ int rptr[PCG_RMAX + 1];
   __shared__ double red[PCG_THREADS / 64];
   const int G = gridDim.x, B = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
-  const int R = a.rows_per_wg;
-  const int r0 = min(a.nc, B * R), nr = min(a.nc, r0 + R) - r0;
+  const int r0 = a.wg_row[B], nr = a.wg_row[B + 1] - r0;
   const int n9 = nr * 9;
-  const size_t zstride = (size_t)G * a.seg, pstride = (size_t)G * PART_STRIDE;
-  double* zmine = a.zring + (size_t)B * a.seg;
+  const int ib = a.item_ptr[B], nitems = a.item_ptr[B + 1] - ib;
+  const int ub = a.ucol_ptr[B], nuc = a.ucol_ptr[B + 1] - ub;
+  const size_t zstride = (size_t)a.nc * ZSTRIDE, pstride = (size_t)G * PART_STRIDE;
+  const int g = tid / 9, comp = tid - 9 * (tid / 9);
+  const int L = (nitems + SPMV_GROUPS - 1) / SPMV_GROUPS;
+  const int i0 = g < SPMV_GROUPS ? min(nitems, g * L) : nitems;
+  const int i1 = g < SPMV_GROUPS ? min(nitems, i0 + L) : nitems;
   if (tid == 0) {
     rptr[0] = 0;
     for (int i = 0; i < nr; ++i)
@@ -593,18 +630,25 @@ __global__ __launch_bounds__(PCG_THREADS) void k_pcg(PcgArgs a) {
     rs[i] = a.b[9 * (size_t)r0 + i];
     xs[i] = 0.0;
   }
+  for (int i = tid; i < nr * 81; i += nt) Ml[i] = a.Minv[81 * (size_t)r0 + i];
   __syncthreads();
+  PcgItems it;
+  if (RES && i0 < i1) pcg_load_items<T>(a, ib, i0, i1, rptr, comp, it);
+  else {
+#pragma unroll
+    for (int kk = 0; kk < PCG_IPG; ++kk) it.rl[kk] = -1, it.lc[kk] = 0;
+  }
+
   // z0 = M b, p0 = z0
   double s_bb = 0.0, s_rz = 0.0;
   for (int i = tid; i < n9; i += nt) {
     const int row = i / 9, cp = i - 9 * row;
-    const double* Mi = a.Minv + 81 * (size_t)(r0 + row) + 9 * cp;
     double z = 0.0;
 #pragma unroll
-    for (int m = 0; m < 9; ++m) z += Mi[m] * rs[row * 9 + m];
+    for (int m = 0; m < 9; ++m) z += Ml[row * 81 + cp * 9 + m] * rs[row * 9 + m];
     zs[i] = z;
     ps[i] = z;
-    publish(zmine + i, z);
+    publish(a.zring + (size_t)(r0 + row) * ZSTRIDE + cp, z);
     s_bb += rs[i] * rs[i];
     s_rz += rs[i] * z;
   }
@@ -615,14 +659,20 @@ __global__ __launch_bounds__(PCG_THREADS) void k_pcg(PcgArgs a) {
     publish(a.partA + (size_t)B * PART_STRIDE + 1, s_rz);
   }
   bool ok = grid_barrier(a.gs, a.error);
-  const double bb = grid_sum(a.partA, G, 0, red);
-  double rz = grid_sum(a.partA, G, 1, red);
+  pcg_fetch_z(a, a.zring, ub, nuc, zl);
+  double t0 = 0.0, t1 = 0.0;
+  for (int i = tid; i < G; i += nt) {
+    t0 += a.partA[(size_t)i * PART_STRIDE];
+    t1 += a.partA[(size_t)i * PART_STRIDE + 1];
+  }
+  const double bb = block_sum(t0, red);
+  double rz = block_sum(t1, red);
   const double bnorm = sqrt(bb);
   double rnorm = bnorm;
   int iters = 0, breakdown = 0;
   if (ok && bnorm > 0.0) {
     // q0 = S z0 (= S p0)
-    spmv_own_rows<T>(a, a.zring, r0, nr, rptr, seg, seg_lo, seg_hi, ys);
+    pcg_spmv<T, RES>(a, ib, i0, i1, nr, rptr, it, zl, seg, seg_lo, seg_hi, ys);
     double s_pq = 0.0;
     for (int i = tid; i < n9; i += nt) {
       qs[i] = ys[i];
@@ -631,7 +681,9 @@ __global__ __launch_bounds__(PCG_THREADS) void k_pcg(PcgArgs a) {
     s_pq = block_sum(s_pq, red);
     if (tid == 0) publish(a.partB + (size_t)B * PART_STRIDE, s_pq);
     ok = grid_barrier(a.gs, a.error);
-    double pq = grid_sum(a.partB, G, 0, red);
+    t0 = 0.0;
+    for (int i = tid; i < G; i += nt) t0 += a.partB[(size_t)i * PART_STRIDE];
+    double pq = block_sum(t0, red);
     if (ok && !(pq > 0.0)) breakdown = 1;
     double alpha = rz / pq;
     for (int k = 1; ok && !breakdown && k <= a.maxiter; ++k) {
@@ -644,12 +696,11 @@ __global__ __launch_bounds__(PCG_THREADS) void k_pcg(PcgArgs a) {
       double s_rr = 0.0, s_rz2 = 0.0;
       for (int i = tid; i < n9; i += nt) {
         const int row = i / 9, cp = i - 9 * row;
-        const double* Mi = a.Minv + 81 * (size_t)(r0 + row) + 9 * cp;
         double z = 0.0;
 #pragma unroll
-        for (int m = 0; m < 9; ++m) z += Mi[m] * rs[row * 9 + m];
+        for (int m = 0; m < 9; ++m) z += Ml[row * 81 + cp * 9 + m] * rs[row * 9 + m];
         zs[i] = z;
-        publish(zk + (size_t)B * a.seg + i, z);
+        publish(zk + (size_t)(r0 + row) * ZSTRIDE + cp, z);
         s_rr += rs[i] * rs[i];
         s_rz2 += rs[i] * z;
       }
@@ -662,15 +713,23 @@ __global__ __launch_bounds__(PCG_THREADS) void k_pcg(PcgArgs a) {
       }
       ok = grid_barrier(a.gs, a.error);
       if (!ok) break;
-      const double rr = grid_sum(pa, G, 0, red);
-      const double rz_new = grid_sum(pa, G, 1, red);
+      // the partials and the z columns arrive in the same memory round trip
+      pcg_fetch_z(a, zk, ub, nuc, zl);
+      t0 = 0.0;
+      t1 = 0.0;
+      for (int i = tid; i < G; i += nt) {
+        t0 += pa[(size_t)i * PART_STRIDE];
+        t1 += pa[(size_t)i * PART_STRIDE + 1];
+      }
+      const double rr = block_sum(t0, red);
+      const double rz_new = block_sum(t1, red);
       iters = k;
       rnorm = sqrt(rr);
       if (rnorm <= a.rtol * bnorm) break;
       const double beta = rz_new / rz;
       rz = rz_new;
       for (int i = tid; i < n9; i += nt) ps[i] = zs[i] + beta * ps[i];
-      spmv_own_rows<T>(a, zk, r0, nr, rptr, seg, seg_lo, seg_hi, ys);
+      pcg_spmv<T, RES>(a, ib, i0, i1, nr, rptr, it, zl, seg, seg_lo, seg_hi, ys);
       s_pq = 0.0;
       for (int i = tid; i < n9; i += nt) {
         const double q = ys[i] + beta * qs[i];
@@ -682,7 +741,9 @@ __global__ __launch_bounds__(PCG_THREADS) void k_pcg(PcgArgs a) {
       if (tid == 0) publish(pb + (size_t)B * PART_STRIDE, s_pq);
       ok = grid_barrier(a.gs, a.error);
       if (!ok) break;
-      pq = grid_sum(pb, G, 0, red);
+      t0 = 0.0;
+      for (int i = tid; i < G; i += nt) t0 += pb[(size_t)i * PART_STRIDE];
+      pq = block_sum(t0, red);
       if (!(pq > 0.0)) {
         breakdown = 1;
         break;
@@ -917,25 +978,27 @@ template hipError_t launch_camera_finish<float>(const CamFinishArgs&, int, hipSt
 template hipError_t launch_camera_finish<double>(const CamFinishArgs&, int, hipStream_t);
 
 template <typename T>
-int pcg_max_grid() {
+int pcg_max_grid(bool resident) {
   int dev = 0, ncu = 0, per = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
   if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_pcg<T>, PCG_THREADS, 0) != hipSuccess)
-    return 0;
+  const void* f = resident ? reinterpret_cast<const void*>(k_pcg<T, true>)
+                           : reinterpret_cast<const void*>(k_pcg<T, false>);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, f, PCG_THREADS, 0) != hipSuccess) return 0;
   return ncu * per;
 }
-template int pcg_max_grid<float>();
-template int pcg_max_grid<double>();
+template int pcg_max_grid<float>(bool);
+template int pcg_max_grid<double>(bool);
 
 template <typename T>
-hipError_t launch_pcg(const PcgArgs& a, int grid, hipStream_t s) {
+hipError_t launch_pcg(const PcgArgs& a, int grid, bool resident, hipStream_t s) {
   void* args[] = {const_cast<PcgArgs*>(&a)};
-  return hipLaunchCooperativeKernel(reinterpret_cast<void*>(k_pcg<T>), dim3(grid), dim3(PCG_THREADS),
-                                    args, 0, s);
+  const void* f = resident ? reinterpret_cast<const void*>(k_pcg<T, true>)
+                           : reinterpret_cast<const void*>(k_pcg<T, false>);
+  return hipLaunchCooperativeKernel(f, dim3(grid), dim3(PCG_THREADS), args, 0, s);
 }
-template hipError_t launch_pcg<float>(const PcgArgs&, int, hipStream_t);
-template hipError_t launch_pcg<double>(const PcgArgs&, int, hipStream_t);
+template hipError_t launch_pcg<float>(const PcgArgs&, int, bool, hipStream_t);
+template hipError_t launch_pcg<double>(const PcgArgs&, int, bool, hipStream_t);
 
 template <typename T>
 hipError_t launch_backsub(const BackArgs& a, int nchunk, hipStream_t s) {

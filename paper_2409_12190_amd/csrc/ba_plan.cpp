@@ -231,6 +231,87 @@ std::string build_plan(int32_t nc, int32_t np, int64_t no, const int32_t* cidx, 
       }
   }
 
+  // PCG workgroups: contiguous row ranges.  First try ranges of at most
+  // PCG_IPG * PCG_GROUPS items (block values register-resident); if that
+  // needs more than PCG_MAX_GRID workgroups, split the items evenly over
+  // PCG_MAX_GRID workgroups and stream the block values.
+  {
+    std::vector<int64_t> row_items(nc);
+    int64_t total = 0;
+    for (int32_t a = 0; a < nc; ++a) {
+      row_items[a] = (p.S_ptr[a + 1] - p.S_ptr[a]) + (p.T_ptr[a + 1] - p.T_ptr[a]);
+      total += row_items[a];
+    }
+    auto partition = [&](int64_t cap, int64_t target, std::vector<int32_t>& rows) {
+      rows.assign(1, 0);
+      int64_t items = 0;
+      int32_t nrow = 0;
+      for (int32_t a = 0; a < nc; ++a) {
+        if (cap > 0 && row_items[a] > cap) return false;
+        const bool close = nrow > 0 && (nrow == PCG_RMAX || (cap > 0 && items + row_items[a] > cap) ||
+                                        (target > 0 && items >= target));
+        if (close) {
+          rows.push_back(a);
+          items = 0;
+          nrow = 0;
+        }
+        items += row_items[a];
+        ++nrow;
+      }
+      rows.push_back(nc);
+      return true;
+    };
+    p.pcg_resident = partition((int64_t)PCG_IPG * PCG_GROUPS, 0, p.pcg_row) &&
+                     (int32_t)p.pcg_row.size() - 1 <= PCG_MAX_GRID;
+    if (!p.pcg_resident) partition(0, (total + PCG_MAX_GRID - 1) / PCG_MAX_GRID, p.pcg_row);
+    p.pcg_grid = (int32_t)p.pcg_row.size() - 1;
+    if (p.pcg_grid > PCG_MAX_GRID) {
+      std::snprintf(msg, sizeof msg, "the reduced camera system needs %d PCG workgroups; at most %d",
+                    p.pcg_grid, PCG_MAX_GRID);
+      return msg;
+    }
+    p.item_ptr.assign(p.pcg_grid + 1, 0);
+    p.ucol_ptr.assign(p.pcg_grid + 1, 0);
+    p.item_e.clear();
+    p.item_code.clear();
+    p.ucol.clear();
+    p.max_ucol = 0;
+    std::vector<int32_t> uc;
+    for (int32_t g = 0; g < p.pcg_grid; ++g) {
+      const int32_t r0 = p.pcg_row[g], r1 = p.pcg_row[g + 1];
+      uc.clear();
+      for (int32_t a = r0; a < r1; ++a) {
+        for (int32_t e = p.S_ptr[a]; e < p.S_ptr[a + 1]; ++e) uc.push_back(p.S_col[e]);
+        for (int32_t t = p.T_ptr[a]; t < p.T_ptr[a + 1]; ++t) uc.push_back(p.T_src[t]);
+      }
+      std::sort(uc.begin(), uc.end());
+      uc.erase(std::unique(uc.begin(), uc.end()), uc.end());
+      p.max_ucol = std::max(p.max_ucol, (int32_t)uc.size());
+      auto local = [&](int32_t c) {
+        return (int32_t)(std::lower_bound(uc.begin(), uc.end(), c) - uc.begin());
+      };
+      for (int32_t a = r0; a < r1; ++a) {
+        for (int32_t e = p.S_ptr[a]; e < p.S_ptr[a + 1]; ++e) {
+          const bool diag = e == p.S_ptr[a];
+          p.item_e.push_back(diag ? a : e);
+          p.item_code.push_back(local(p.S_col[e]) | (diag ? ITEM_DIAG : 0));
+        }
+        for (int32_t t = p.T_ptr[a]; t < p.T_ptr[a + 1]; ++t) {
+          p.item_e.push_back(p.T_blk[t]);
+          p.item_code.push_back(local(p.T_src[t]) | ITEM_TRANS);
+        }
+      }
+      p.item_ptr[g + 1] = (int32_t)p.item_e.size();
+      p.ucol.insert(p.ucol.end(), uc.begin(), uc.end());
+      p.ucol_ptr[g + 1] = (int32_t)p.ucol.size();
+    }
+    if (p.max_ucol > PCG_ZCOLS) {
+      std::snprintf(msg, sizeof msg,
+                    "a PCG workgroup would read %d block columns; at most %d are supported",
+                    p.max_ucol, PCG_ZCOLS);
+      return msg;
+    }
+  }
   return std::string();
 }
 
