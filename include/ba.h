@@ -72,7 +72,14 @@ typedef struct {
   int32_t cg_maxiter;  /* and after at most this many iterations */
   double lambda0, lambda_min, lambda_max;
   double diag_min, diag_max; /* clamp range of the damped diagonal */
+  int32_t cg_variant;  /* BA_CG_PIPELINED: one grid synchronisation per CG
+                          iteration (same iterates in exact arithmetic; relative
+                          residuals below ~1e-10 may not be attainable);
+                          BA_CG_STANDARD: the textbook recurrence, two per
+                          iteration */
 } ba_options;
+
+enum { BA_CG_PIPELINED = 0, BA_CG_STANDARD = 1 };
 
 /* Per-iteration report (host struct). */
 typedef struct {
@@ -90,7 +97,8 @@ typedef struct {
 } ba_step_info;
 
 /* Fills *opt with the defaults: cam_dof 9, BA_FP64, squared loss, cg_rtol 1e-4,
- * cg_maxiter 250, lambda0 1e-4, lambda in [1e-12, 1e12], clamp [1e-6, 1e32]. */
+ * cg_maxiter 250, lambda0 1e-4, lambda in [1e-12, 1e12], clamp [1e-6, 1e32],
+ * BA_CG_PIPELINED. */
 void ba_default_options(ba_options* opt);
 
 /* Creates a problem from the observation pattern: observation k sees point

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_PKG, "libba.so")
 
 BA_OK, BA_EINVAL, BA_ENUMERIC, BA_EHIP, BA_ENOTCONV, BA_ESTATE, BA_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 BA_FP64, BA_MIXED = 0, 1
+BA_CG_PIPELINED, BA_CG_STANDARD = 0, 1
 (BA_X_RESIDUAL, BA_X_WEIGHT, BA_X_JC, BA_X_JP, BA_X_COST, BA_X_GRAD_C, BA_X_GRAD_P, BA_X_V,
  BA_X_S_PTR, BA_X_S_COL, BA_X_S, BA_X_BS, BA_X_DC, BA_X_DP) = range(1, 15)
 
@@ -43,7 +44,7 @@ class ba_options(C.Structure):
     _fields_ = [("cam_dof", C.c_int32), ("precision", C.c_int32), ("huber_delta", C.c_double),
                 ("cg_rtol", C.c_double), ("cg_maxiter", C.c_int32), ("lambda0", C.c_double),
                 ("lambda_min", C.c_double), ("lambda_max", C.c_double), ("diag_min", C.c_double),
-                ("diag_max", C.c_double)]
+                ("diag_max", C.c_double), ("cg_variant", C.c_int32)]
 
 
 class ba_step_info(C.Structure):
@@ -246,7 +247,7 @@ class Problem:
 
     def __init__(self, n_cams, n_pts, cam_idx, pt_idx, obs_xy, obs_w=None, *, precision=BA_FP64,
                  huber_delta=0.0, cg_rtol=1e-4, cg_maxiter=250, lambda0=1e-4, fixed_cams=None,
-                 cams=None, pts=None, stream=None):
+                 cams=None, pts=None, stream=None, cg_variant=BA_CG_PIPELINED):
         import torch
         self.torch = torch
         self.device = torch.device("cuda", torch.cuda.current_device())
@@ -256,6 +257,7 @@ class Problem:
         opt.cg_rtol = cg_rtol
         opt.cg_maxiter = cg_maxiter
         opt.lambda0 = lambda0
+        opt.cg_variant = cg_variant
         self.opt = opt
         self.n_cams, self.n_pts = int(n_cams), int(n_pts)
         self.n_obs = int(np.asarray(cam_idx).size)

@@ -103,7 +103,7 @@ void carve(ba_problem* p, char* base, size_t* total) {
   b.part_pred = c.take<double>(2 * nch);
   b.part_gmax = c.take<double>(nch);
   b.part_linc = c.take<double>((nc + 255) / 256);
-  const size_t slots = (size_t)p->opt.cg_maxiter + 1;
+  const size_t slots = (size_t)p->opt.cg_maxiter + 2;
   b.zring = c.take<double>(slots * nc * ba::ZSTRIDE);
   b.partA = c.take<double>(slots * P.pcg_grid * ba::PART_STRIDE);
   b.partB = c.take<double>(slots * P.pcg_grid * ba::PART_STRIDE);
@@ -192,7 +192,7 @@ ba_status lm_step_impl(ba_problem* p, ba_step_info* out) {
   PcgArgs pa{P.nc, p->cg_maxiter, p->cg_rtol, b.S_ptr, b.T_ptr, b.pcg_row, b.item_ptr, b.item_e,
              b.item_code, b.ucol_ptr, b.ucol, b.S, b.Sdiag, b.Minv, b.bS, b.x, b.zring, b.partA,
              b.partB, b.dinfo, b.gsync, &b.dev->error};
-  PHASE(7, launch_pcg<T>(pa, P.pcg_grid, P.pcg_resident, s));
+  PHASE(7, launch_pcg<T>(pa, P.pcg_grid, P.pcg_resident, p->opt.cg_variant == BA_CG_PIPELINED, s));
   BackArgs ba_{b.chunk_ptr, b.chunk_pt, b.pt_ptr, b.o_cam, b.o_pt, b.J, b.w, b.x, b.gp, b.Vinv,
                b.pts[cur], b.dp, b.pts[nxt], b.part_pred};
   PHASE(8, launch_backsub<T>(ba_, nchunk, s));
@@ -257,6 +257,7 @@ void ba_default_options(ba_options* o) {
   o->lambda_max = 1e12;
   o->diag_min = 1e-6;
   o->diag_max = 1e32;
+  o->cg_variant = BA_CG_PIPELINED;
 }
 
 const char* ba_last_error(void) { return g_err.c_str(); }
@@ -272,6 +273,8 @@ ba_status ba_problem_create(const ba_options* opt, int32_t n_cams, int32_t n_pts
   if (o.cam_dof != 9) return fail(BA_EUNSUPPORTED, "only cam_dof = 9 is supported");
   if (o.precision != BA_FP64 && o.precision != BA_MIXED) return fail(BA_EINVAL, "unknown precision");
   if (!(o.cg_rtol >= 0.0) || o.cg_maxiter < 1) return fail(BA_EINVAL, "bad CG options");
+  if (o.cg_variant != BA_CG_PIPELINED && o.cg_variant != BA_CG_STANDARD)
+    return fail(BA_EINVAL, "unknown CG variant");
   if (!(o.lambda0 > 0.0) || !(o.lambda_min > 0.0) || !(o.lambda_max >= o.lambda_min))
     return fail(BA_EINVAL, "bad damping options");
   if (!(o.diag_min > 0.0) || !(o.diag_max >= o.diag_min)) return fail(BA_EINVAL, "bad clamp range");
@@ -357,8 +360,9 @@ ba_status ba_problem_bind(ba_problem* p, void* ws, size_t bytes, void* stream) {
   *p->hscal = ba::DevScalars{0.0, p->lambda, 0, 0};
   HIPCHK(hipMemcpyAsync(b.dev, p->hscal, sizeof(ba::DevScalars), hipMemcpyHostToDevice, s));
   HIPCHK(hipStreamSynchronize(s));
-  const int maxg = p->opt.precision == BA_MIXED ? ba::pcg_max_grid<float>(P.pcg_resident)
-                                                : ba::pcg_max_grid<double>(P.pcg_resident);
+  const bool pipe = p->opt.cg_variant == BA_CG_PIPELINED;
+  const int maxg = p->opt.precision == BA_MIXED ? ba::pcg_max_grid<float>(P.pcg_resident, pipe)
+                                                : ba::pcg_max_grid<double>(P.pcg_resident, pipe);
   if (maxg <= 0) return fail(BA_EHIP, "cooperative occupancy query failed");
   p->pcg_grid = P.pcg_grid;
   if (p->pcg_grid > maxg || p->pcg_grid > ba::MAX_BARRIER_GROUPS * ba::BARRIER_FANIN)

@@ -20,7 +20,7 @@ constexpr int SCHUR_SLOTS = SCHUR_THREADS / 9;  // 28 pair chunks per workgroup,
 constexpr int SCHUR_CHUNK = 16;                 // target pairs per chunk
 constexpr int CAM_THREADS = 128;
 constexpr int PCG_THREADS = 1024;
-constexpr int PCG_RMAX = 64;          // block rows owned by one PCG workgroup
+constexpr int PCG_RMAX = 48;          // block rows owned by one PCG workgroup
 constexpr int PCG_MAX_GRID = 256;     // PCG workgroups (one per compute unit)
 constexpr int PCG_GROUPS = PCG_THREADS / 9;  // 9-lane groups of a PCG workgroup
 constexpr int PCG_IPG = 3;            // register-resident items per lane group

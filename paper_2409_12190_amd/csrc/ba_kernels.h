@@ -117,8 +117,9 @@ template <typename T> hipError_t launch_point_q(const PointQArgs&, hipStream_t);
 template <typename T> hipError_t launch_camera_vec(const CamVecArgs&, int nc, hipStream_t);
 template <typename T> hipError_t launch_schur_pairs(const SchurArgs&, int nwg, hipStream_t);
 template <typename T> hipError_t launch_camera_finish(const CamFinishArgs&, int nc, hipStream_t);
-template <typename T> int pcg_max_grid(bool resident);
-template <typename T> hipError_t launch_pcg(const PcgArgs&, int grid, bool resident, hipStream_t);
+template <typename T> int pcg_max_grid(bool resident, bool pipelined);
+template <typename T>
+hipError_t launch_pcg(const PcgArgs&, int grid, bool resident, bool pipelined, hipStream_t);
 template <typename T> hipError_t launch_backsub(const BackArgs&, int nchunk, hipStream_t);
 hipError_t launch_retract_cameras(const RetractArgs&, int nblk, hipStream_t);
 hipError_t launch_candidate_cost(const CostArgs&, int nchunk, hipStream_t);

@@ -548,15 +548,17 @@ __device__ __forceinline__ void pcg_load_items(const PcgArgs& a, int ib, int k0,
 
 // y[own rows] = S z, with z's needed block columns already in LDS (zl).
 // Each group keeps a running sum per row and stores it at seg[row + group];
-// rows are then summed over groups in group order.
+// row `row` was touched exactly by groups rptr[row]/L .. (rptr[row+1]-1)/L,
+// whose partials are then summed by 8 lanes per output (strided, then a
+// 3-step butterfly): fixed order.
 template <typename T, bool RES>
-__device__ __forceinline__ void pcg_spmv(const PcgArgs& a, int ib, int i0, int i1, int nr,
+__device__ __forceinline__ void pcg_spmv(const PcgArgs& a, int ib, int i0, int i1, int nr, int L,
                                          const int* rptr, PcgItems& it, const double* zl, double* seg,
-                                         int* seg_lo, int* seg_hi, double* y) {
+                                         double* y) {
   const int g = threadIdx.x / 9, comp = threadIdx.x - 9 * (threadIdx.x / 9);
   if (g < SPMV_GROUPS) {
     double acc = 0.0;
-    int cur = -1, first = -1;
+    int cur = -1;
     for (int k0 = i0; k0 < i1; k0 += PCG_IPG) {
       if (!RES) pcg_load_items<T>(a, ib, k0, i1, rptr, comp, it);
 #pragma unroll
@@ -565,7 +567,6 @@ __device__ __forceinline__ void pcg_spmv(const PcgArgs& a, int ib, int i0, int i
         if (rl < 0) continue;
         if (rl != cur) {
           if (cur >= 0) seg[(cur + g) * 9 + comp] = acc;
-          if (first < 0) first = rl;
           acc = 0.0;
           cur = rl;
         }
@@ -575,18 +576,21 @@ __device__ __forceinline__ void pcg_spmv(const PcgArgs& a, int ib, int i0, int i
       }
     }
     if (cur >= 0) seg[(cur + g) * 9 + comp] = acc;
-    if (comp == 0) {
-      seg_lo[g] = cur >= 0 ? first : 1;
-      seg_hi[g] = cur >= 0 ? cur : 0;
-    }
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < nr * 9; i += blockDim.x) {
-    const int row = i / 9, cp = i - 9 * row;
+  const int nout = nr * 9;
+  for (int base = 0; base < nout * 8; base += blockDim.x) {
+    const int t = base + threadIdx.x, o = t >> 3, sub = t & 7;
     double s = 0.0;
-    for (int gg = 0; gg < SPMV_GROUPS; ++gg)
-      if (seg_lo[gg] <= row && row <= seg_hi[gg]) s += seg[(row + gg) * 9 + cp];
-    y[i] = s;
+    if (o < nout) {
+      const int row = o / 9, cp = o - 9 * row;
+      const int g0 = rptr[row] / L, g1 = (rptr[row + 1] - 1) / L;
+      for (int gg = g0 + sub; gg <= g1; gg += 8) s += seg[(row + gg) * 9 + cp];
+    }
+    s += __shfl_xor(s, 1, 64);
+    s += __shfl_xor(s, 2, 64);
+    s += __shfl_xor(s, 4, 64);
+    if (o < nout && sub == 0) y[o] = s;
   }
   __syncthreads();
 }
@@ -601,13 +605,12 @@ __device__ __forceinline__ void pcg_fetch_z(const PcgArgs& a, const double* zk, 
 }
 
 template <typename T, bool RES>
-__global__ __launch_bounds__(PCG_THREADS) void k_pcg(PcgArgs a) {
+__global__ __launch_bounds__(PCG_THREADS) void k_pcg_standard(PcgArgs a) {
   __shared__ double xs[PCG_RMAX * 9], rs[PCG_RMAX * 9], ps[PCG_RMAX * 9];
   __shared__ double qs[PCG_RMAX * 9], zs[PCG_RMAX * 9], ys[PCG_RMAX * 9];
   __shared__ double Ml[PCG_RMAX * 81];
   __shared__ double zl[PCG_ZCOLS * 9];
   __shared__ double seg[(PCG_RMAX + SPMV_GROUPS) * 9];
-  __shared__ int seg_lo[SPMV_GROUPS], seg_hi[SPMV_GROUPS];
   __shared__ int rptr[PCG_RMAX + 1];
   __shared__ double red[PCG_THREADS / 64];
   const int G = gridDim.x, B = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
@@ -617,7 +620,7 @@ __global__ __launch_bounds__(PCG_THREADS) void k_pcg(PcgArgs a) {
   const int ub = a.ucol_ptr[B], nuc = a.ucol_ptr[B + 1] - ub;
   const size_t zstride = (size_t)a.nc * ZSTRIDE, pstride = (size_t)G * PART_STRIDE;
   const int g = tid / 9, comp = tid - 9 * (tid / 9);
-  const int L = (nitems + SPMV_GROUPS - 1) / SPMV_GROUPS;
+  const int L = max(1, (nitems + SPMV_GROUPS - 1) / SPMV_GROUPS);
   const int i0 = g < SPMV_GROUPS ? min(nitems, g * L) : nitems;
   const int i1 = g < SPMV_GROUPS ? min(nitems, i0 + L) : nitems;
   if (tid == 0) {
@@ -672,7 +675,7 @@ __global__ __launch_bounds__(PCG_THREADS) void k_pcg(PcgArgs a) {
   int iters = 0, breakdown = 0;
   if (ok && bnorm > 0.0) {
     // q0 = S z0 (= S p0)
-    pcg_spmv<T, RES>(a, ib, i0, i1, nr, rptr, it, zl, seg, seg_lo, seg_hi, ys);
+    pcg_spmv<T, RES>(a, ib, i0, i1, nr, L, rptr, it, zl, seg, ys);
     double s_pq = 0.0;
     for (int i = tid; i < n9; i += nt) {
       qs[i] = ys[i];
@@ -729,7 +732,7 @@ __global__ __launch_bounds__(PCG_THREADS) void k_pcg(PcgArgs a) {
       const double beta = rz_new / rz;
       rz = rz_new;
       for (int i = tid; i < n9; i += nt) ps[i] = zs[i] + beta * ps[i];
-      pcg_spmv<T, RES>(a, ib, i0, i1, nr, rptr, it, zl, seg, seg_lo, seg_hi, ys);
+      pcg_spmv<T, RES>(a, ib, i0, i1, nr, L, rptr, it, zl, seg, ys);
       s_pq = 0.0;
       for (int i = tid; i < n9; i += nt) {
         const double q = ys[i] + beta * qs[i];
@@ -750,6 +753,154 @@ __global__ __launch_bounds__(PCG_THREADS) void k_pcg(PcgArgs a) {
       }
       alpha = rz / pq;
     }
+  }
+  for (int i = tid; i < n9; i += nt) a.x[9 * (size_t)r0 + i] = xs[i];
+  if (B == 0 && tid == 0) {
+    a.info->cg_iters = iters;
+    a.info->cg_breakdown = breakdown;
+    a.info->cg_rel_resid = bnorm > 0.0 ? rnorm / bnorm : 0.0;
+  }
+}
+
+// Pipelined PCG (Ghysels and Vanroose, "Hiding global synchronization
+// latency in the preconditioned Conjugate Gradient algorithm", 2014): the
+// same Krylov iterates as the standard recurrence in exact arithmetic, with
+// the three dot products of an iteration reduced together and the product
+// n = S m computed after the same barrier, so each iteration needs one grid
+// barrier and one memory round trip.  Its attainable accuracy is lower than
+// the standard recurrence's (relative residuals below ~1e-10 may not be
+// reached), which is why the standard kernel stays selectable.
+template <typename T, bool RES>
+__global__ __launch_bounds__(PCG_THREADS) void k_pcg_pipelined(PcgArgs a) {
+  __shared__ double xs[PCG_RMAX * 9], rs[PCG_RMAX * 9], us[PCG_RMAX * 9], ws[PCG_RMAX * 9];
+  __shared__ double ms_[PCG_RMAX * 9], ns[PCG_RMAX * 9], zs[PCG_RMAX * 9], qs[PCG_RMAX * 9];
+  __shared__ double ss[PCG_RMAX * 9], ps[PCG_RMAX * 9];
+  __shared__ double Ml[PCG_RMAX * 81];
+  __shared__ double zl[PCG_ZCOLS * 9];
+  __shared__ double seg[(PCG_RMAX + SPMV_GROUPS) * 9];
+  __shared__ int rptr[PCG_RMAX + 1];
+  __shared__ double red[PCG_THREADS / 64];
+  const int G = gridDim.x, B = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
+  const int r0 = a.wg_row[B], nr = a.wg_row[B + 1] - r0;
+  const int n9 = nr * 9;
+  const int ib = a.item_ptr[B], nitems = a.item_ptr[B + 1] - ib;
+  const int ub = a.ucol_ptr[B], nuc = a.ucol_ptr[B + 1] - ub;
+  const size_t zstride = (size_t)a.nc * ZSTRIDE, pstride = (size_t)G * PART_STRIDE;
+  const int g = tid / 9, comp = tid - 9 * (tid / 9);
+  const int L = max(1, (nitems + SPMV_GROUPS - 1) / SPMV_GROUPS);
+  const int i0 = g < SPMV_GROUPS ? min(nitems, g * L) : nitems;
+  const int i1 = g < SPMV_GROUPS ? min(nitems, i0 + L) : nitems;
+  if (tid == 0) {
+    rptr[0] = 0;
+    for (int i = 0; i < nr; ++i)
+      rptr[i + 1] = rptr[i] + (a.S_ptr[r0 + i + 1] - a.S_ptr[r0 + i]) +
+                    (a.T_ptr[r0 + i + 1] - a.T_ptr[r0 + i]);
+  }
+  for (int i = tid; i < n9; i += nt) {
+    rs[i] = a.b[9 * (size_t)r0 + i];
+    xs[i] = 0.0;
+  }
+  for (int i = tid; i < nr * 81; i += nt) Ml[i] = a.Minv[81 * (size_t)r0 + i];
+  __syncthreads();
+  PcgItems it;
+  if (RES && i0 < i1) pcg_load_items<T>(a, ib, i0, i1, rptr, comp, it);
+  else {
+#pragma unroll
+    for (int kk = 0; kk < PCG_IPG; ++kk) it.rl[kk] = -1, it.lc[kk] = 0;
+  }
+  // u0 = M b, published in slot 0; w0 = S u0
+  double s_bb = 0.0;
+  for (int i = tid; i < n9; i += nt) {
+    const int row = i / 9, cp = i - 9 * row;
+    double u = 0.0;
+#pragma unroll
+    for (int m = 0; m < 9; ++m) u += Ml[row * 81 + cp * 9 + m] * rs[row * 9 + m];
+    us[i] = u;
+    publish(a.zring + (size_t)(r0 + row) * ZSTRIDE + cp, u);
+    s_bb += rs[i] * rs[i];
+  }
+  s_bb = block_sum(s_bb, red);
+  if (tid == 0) publish(a.partB + (size_t)B * PART_STRIDE, s_bb);
+  bool ok = grid_barrier(a.gs, a.error);
+  pcg_fetch_z(a, a.zring, ub, nuc, zl);
+  double t0 = 0.0;
+  for (int i = tid; i < G; i += nt) t0 += a.partB[(size_t)i * PART_STRIDE];
+  const double bnorm = sqrt(block_sum(t0, red));
+  pcg_spmv<T, RES>(a, ib, i0, i1, nr, L, rptr, it, zl, seg, ws);
+  double rnorm = bnorm, gamma_old = 1.0, alpha_old = 1.0;
+  int iters = 0, breakdown = 0;
+  for (int i = 0; ok && bnorm > 0.0 && i <= a.maxiter; ++i) {
+    // local: partial dots of r, u, w; m = M w published in slot i + 1
+    double* zk = a.zring + (size_t)(i + 1) * zstride;
+    double s_g = 0.0, s_d = 0.0, s_r = 0.0;
+    for (int k = tid; k < n9; k += nt) {
+      const int row = k / 9, cp = k - 9 * row;
+      double m = 0.0;
+#pragma unroll
+      for (int q = 0; q < 9; ++q) m += Ml[row * 81 + cp * 9 + q] * ws[row * 9 + q];
+      ms_[k] = m;
+      publish(zk + (size_t)(r0 + row) * ZSTRIDE + cp, m);
+      s_g += rs[k] * us[k];
+      s_d += ws[k] * us[k];
+      s_r += rs[k] * rs[k];
+    }
+    s_g = wave_sum(s_g);
+    s_d = wave_sum(s_d);
+    s_r = wave_sum(s_r);
+    __shared__ double red3[PCG_THREADS / 64][3];
+    if ((tid & 63) == 0) {
+      red3[tid >> 6][0] = s_g;
+      red3[tid >> 6][1] = s_d;
+      red3[tid >> 6][2] = s_r;
+    }
+    __syncthreads();
+    double* pa = a.partA + (size_t)i * pstride;
+    if (tid < 3) {
+      double v = 0.0;
+      for (int w2 = 0; w2 < PCG_THREADS / 64; ++w2) v += red3[w2][tid];
+      publish(pa + (size_t)B * PART_STRIDE + tid, v);
+    }
+    ok = grid_barrier(a.gs, a.error);
+    if (!ok) break;
+    // the partials and the m columns arrive in the same memory round trip
+    pcg_fetch_z(a, zk, ub, nuc, zl);
+    double tg = 0.0, td = 0.0, tr = 0.0;
+    for (int w2 = tid; w2 < G; w2 += nt) {
+      tg += pa[(size_t)w2 * PART_STRIDE];
+      td += pa[(size_t)w2 * PART_STRIDE + 1];
+      tr += pa[(size_t)w2 * PART_STRIDE + 2];
+    }
+    const double gamma = block_sum(tg, red);
+    const double delta = block_sum(td, red);
+    const double rr = block_sum(tr, red);
+    iters = i;
+    rnorm = sqrt(rr);
+    if (rnorm <= a.rtol * bnorm || i == a.maxiter) break;
+    const double beta = i > 0 ? gamma / gamma_old : 0.0;
+    const double den = i > 0 ? delta - beta * gamma / alpha_old : delta;
+    if (!(den > 0.0)) {
+      breakdown = 1;
+      break;
+    }
+    const double alpha = gamma / den;
+    pcg_spmv<T, RES>(a, ib, i0, i1, nr, L, rptr, it, zl, seg, ns);
+    for (int k = tid; k < n9; k += nt) {
+      const double z = ns[k] + beta * zs[k];
+      const double q = ms_[k] + beta * qs[k];
+      const double sv = ws[k] + beta * ss[k];
+      const double pv = us[k] + beta * ps[k];
+      zs[k] = z;
+      qs[k] = q;
+      ss[k] = sv;
+      ps[k] = pv;
+      xs[k] += alpha * pv;
+      rs[k] -= alpha * sv;
+      us[k] -= alpha * q;
+      ws[k] -= alpha * z;
+    }
+    __syncthreads();
+    gamma_old = gamma;
+    alpha_old = alpha;
   }
   for (int i = tid; i < n9; i += nt) a.x[9 * (size_t)r0 + i] = xs[i];
   if (B == 0 && tid == 0) {
@@ -978,27 +1129,35 @@ template hipError_t launch_camera_finish<float>(const CamFinishArgs&, int, hipSt
 template hipError_t launch_camera_finish<double>(const CamFinishArgs&, int, hipStream_t);
 
 template <typename T>
-int pcg_max_grid(bool resident) {
+static const void* pcg_kernel(bool resident, bool pipelined) {
+  if (pipelined)
+    return resident ? reinterpret_cast<const void*>(k_pcg_pipelined<T, true>)
+                    : reinterpret_cast<const void*>(k_pcg_pipelined<T, false>);
+  return resident ? reinterpret_cast<const void*>(k_pcg_standard<T, true>)
+                  : reinterpret_cast<const void*>(k_pcg_standard<T, false>);
+}
+
+template <typename T>
+int pcg_max_grid(bool resident, bool pipelined) {
   int dev = 0, ncu = 0, per = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
   if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-  const void* f = resident ? reinterpret_cast<const void*>(k_pcg<T, true>)
-                           : reinterpret_cast<const void*>(k_pcg<T, false>);
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, f, PCG_THREADS, 0) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, pcg_kernel<T>(resident, pipelined),
+                                                   PCG_THREADS, 0) != hipSuccess)
+    return 0;
   return ncu * per;
 }
-template int pcg_max_grid<float>(bool);
-template int pcg_max_grid<double>(bool);
+template int pcg_max_grid<float>(bool, bool);
+template int pcg_max_grid<double>(bool, bool);
 
 template <typename T>
-hipError_t launch_pcg(const PcgArgs& a, int grid, bool resident, hipStream_t s) {
+hipError_t launch_pcg(const PcgArgs& a, int grid, bool resident, bool pipelined, hipStream_t s) {
   void* args[] = {const_cast<PcgArgs*>(&a)};
-  const void* f = resident ? reinterpret_cast<const void*>(k_pcg<T, true>)
-                           : reinterpret_cast<const void*>(k_pcg<T, false>);
-  return hipLaunchCooperativeKernel(f, dim3(grid), dim3(PCG_THREADS), args, 0, s);
+  return hipLaunchCooperativeKernel(pcg_kernel<T>(resident, pipelined), dim3(grid), dim3(PCG_THREADS),
+                                    args, 0, s);
 }
-template hipError_t launch_pcg<float>(const PcgArgs&, int, bool, hipStream_t);
-template hipError_t launch_pcg<double>(const PcgArgs&, int, bool, hipStream_t);
+template hipError_t launch_pcg<float>(const PcgArgs&, int, bool, bool, hipStream_t);
+template hipError_t launch_pcg<double>(const PcgArgs&, int, bool, bool, hipStream_t);
 
 template <typename T>
 hipError_t launch_backsub(const BackArgs& a, int nchunk, hipStream_t s) {
