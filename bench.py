@@ -33,26 +33,98 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def kernel_bytes(name, scene, nnzb, es, cg_iters):
-    """Algorithmic HBM bytes of one launch of a phase (each input read once,
-    each output written once; see the design notes for the derivation)."""
+def kernel_bytes(name, scene, nnzb, n_pairs, es, cg_iters):
+    """Algorithmic HBM bytes of one launch of a phase: every input the
+    kernel needs read once and every output written once (gathered
+    per-point or per-camera data counted once per point or camera).
+    es = bytes per stored Jacobian / Q / S value (8 FP64, 4 mixed)."""
     no, nc, np_ = scene.n_obs, scene.n_cams, scene.n_pts
     nnz_off = nnzb - nc
-    if name == "linearize":
+    if name == "linearize":   # obs xy, w, indices in; r, w, J out; V, gp per point
         return no * (16 + 8 + 4 + 4 + 16 + 8 + 24 * es) + nc * 80 + np_ * (24 + 72)
-    if name == "camera_diag":
-        return no * (4 + 4 + 24 * es + 8 + 16) + np_ * (48 + 24) + nc * (81 * es + 3 * 72 + 648)
-    if name == "schur_offdiag":
-        return no * (4 + 24 * es + 8) + np_ * 48 + nnz_off * 81 * es
-    if name == "pcg":
-        s_bytes = (nnz_off * 81 + nc * 45) * es
-        per_iter = s_bytes + nc * 45 * 8 + 8 * nc * 9 * 8
-        return cg_iters * per_iter + nc * 9 * 8 * 5
-    if name == "backsub":
+    if name == "damp_points":  # V, gp in; Vinv, ep out
+        return np_ * (48 + 24 + 48 + 24)
+    if name == "point_q":      # point index, Jp, w in; Q out; Vinv per point
+        return no * (4 + 6 * es + 8 + 6 * es) + np_ * 48
+    if name == "camera_vec":   # indices, J, w, r in; ep per point; gc, bS, diagU out
+        return no * (4 + 4 + 24 * es + 8 + 16) + np_ * 24 + nc * 216
+    if name == "schur_pairs":  # pair table; J, Q, w per observation; S blocks out
+        return n_pairs * 8 + no * (24 * es + 6 * es + 8) + nnz_off * 81 * es + nc * 648
+    if name == "camera_finish":  # diagonal blocks and diagU in; damped blocks, inverses out
+        return nc * (648 + 72 + 648 + 648)
+    if name == "pcg":          # per CG iteration: S (upper blocks, symmetric diagonal),
+        per_iter = ((nnz_off * 81 + nc * 45) * es   # block-Jacobi factors and the
+                    + nc * 45 * es + 8 * nc * 9 * 8)  # FP64 vectors (x, r, z, p, q touches)
+        return cg_iters * per_iter + nc * 9 * 8 * 2
+    if name == "backsub":      # indices, J, w per observation; dc per camera;
         return no * (4 + 4 + 24 * es + 8) + nc * 72 + np_ * (24 + 48 + 24 + 24 + 24)
+    if name == "retract_cameras":
+        return nc * (80 + 72 + 80 + 72 + 1)
     if name == "candidate_cost":
-        return no * (16 + 8 + 4 + 4) + nc * 80 + np_ * 24
+        return no * (4 + 4 + 16 + 8) + nc * 80 + np_ * 24
     return None
+
+
+def iteration_bytes(scene, nnzb, es, cg_iters):
+    """Compulsory bytes of one LM iteration (observation stream at the
+    current and the candidate parameters, FP64 parameters read twice and
+    written once, S written once and read every CG iteration with its
+    block-Jacobi factors, FP64 CG vectors); storing J, Q and the per-point
+    blocks between kernels is implementation overhead and not counted."""
+    no, nc, np_ = scene.n_obs, scene.n_cams, scene.n_pts
+    d = 9
+    s_x = 8
+    b_obs = 2 * no * (8 + 2 * s_x + (s_x if scene.obs_w is not None else 0))
+    b_par = 3 * (nc * 80 + np_ * 24)
+    b_s = (1 + cg_iters) * ((nnzb - nc) * d * d + nc * d * (d + 1) // 2) * es
+    b_pc = cg_iters * nc * d * (d + 1) // 2 * es
+    b_vec = cg_iters * 8 * nc * d * 8
+    return b_obs + b_par + b_s + b_pc + b_vec
+
+
+def source_digest():
+    """Digest of the kernel sources: HBM traffic counters recorded for other
+    sources no longer describe the kernels."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("ba_kernels.hip", "ba_kernels.h", "ba_internal.h", "ba_device.h"):
+        with open(os.path.join(ROOT, "paper_2409_12190_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def recorded_traffic(workload, kernel):
+    """Per-launch HBM bytes of a kernel from the counter summary under
+    profiles/ (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy's reading),
+    or None when the summary is absent or was taken on other sources."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("source_digest") != source_digest():
+        return None
+    try:
+        return float(vals["bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def copy_probe():
+    """A plain device copy of known size (512 MiB read, 512 MiB written),
+    the calibration of the HBM byte counters."""
+    import torch
+    n = 512 << 20
+    src = torch.ones(n // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_read": n, "copy_probe_bytes_written": n, "launches": 5}))
 
 
 def run_steps(prob, steps, cams0, pts0, lam0):
@@ -105,13 +177,18 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0,
                     help="seconds of oracle work for the CPU baseline (0 disables it)")
     ap.add_argument("--skip-fp64", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="run only a plain 512 MiB device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         log("bench.py measures one GPU only: this build has no multi-GPU path "
             f"(asked for --gpus {args.gpus}).")
         sys.exit(2)
 
-    import numpy as np
+    if args.copy_probe:
+        copy_probe()
+        return
+
     import torch
 
     from paper_2409_12190_amd import ba as B
@@ -153,7 +230,7 @@ def main():
         "metric": METRIC, "value": value, "unit": "obs*LM-iters/s", "n_gpus": 1, "steps": K,
         "warmup": args.warmup, "ms_per_step": mixed["k_time"] / K * 1e3, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64",
-        "data": "synthetic",
+        "data": "synthetic (seeded generator, structure of the workload; no dataset)",
         "config": {"workload": CONFIG_NAMES[cfg], "n_cams": scene.n_cams, "n_pts": scene.n_pts,
                    "n_obs": scene.n_obs, "precision": "mixed (fp32 J/S storage, fp64 arithmetic)",
                    "loss": f"huber {scene.huber_delta}" if scene.huber_delta > 0 else "l2",
@@ -167,12 +244,28 @@ def main():
     out["phases_ms_per_step"] = {k: round(v[0] / K, 4) for k, v in ph.items()}
     dom = max(ph, key=lambda k: ph[k][0])
     ms, n = ph[dom]
-    per_launch = kernel_bytes(dom, scene, nnzb, es, cg_total / max(n, 1))
+    import numpy as np
+    t = np.bincount(scene.pt_idx, minlength=scene.n_pts).astype(np.int64)
+    n_pairs = int((t * (t + 1) // 2).sum())   # (x, y) pairs with camera(x) <= camera(y)
+    per_launch = kernel_bytes(dom, scene, nnzb, n_pairs, es, cg_total / max(n, 1))
     if per_launch is not None:
         achieved = per_launch / (ms / n * 1e-3) / 1e9
         out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                           "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": dom,
-                           "avg_launch_ms": ms / n, "launches": n}
+                           "frac": achieved / HBM_PEAK_GBS,
+                           "traffic": recorded_traffic(args.workload, dom),
+                           "kernel": dom, "avg_launch_ms": ms / n, "launches": n,
+                           "algorithmic_bytes_per_launch": per_launch}
+    out["phase_roofline"] = {}
+    for k, (pms, pn) in ph.items():
+        kb = kernel_bytes(k, scene, nnzb, n_pairs, es, cg_total / max(pn, 1))
+        if kb is not None:
+            gbs = kb / (pms / pn * 1e-3) / 1e9
+            out["phase_roofline"][k] = {"GB/s": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
+                                        "avg_launch_us": round(pms / pn * 1e3, 2)}
+    it_bytes = iteration_bytes(scene, nnzb, es, cg_total / K)
+    it_s = mixed["k_time"] / K
+    out["iteration_roofline"] = {"compulsory_bytes": it_bytes, "ms": it_s * 1e3,
+                                 "frac": it_bytes / it_s / 1e9 / HBM_PEAK_GBS}
     out["cg_iters_per_step"] = cg_total / K
     out["nnzb"] = nnzb
     out["final_cost_after_K"] = mixed["infos"][K - 1]["cost_after"]

@@ -781,3 +781,271 @@ void orc_get_step(const orc_ctx *c, double *dc, double *dp, double *Vinv)
     if (dp) memcpy(dp, c->dp, sizeof(double) * 3 * c->np);
     if (Vinv) memcpy(Vinv, c->Vinv, sizeof(double) * 9 * c->np);
 }
+
+/* ------------------------------------------------------------------------ */
+/* implicit-function adjoint at a stationary point                           */
+/*                                                                            */
+/* The paper uses the solver inside learning pipelines, where a loss on the   */
+/* optimum theta* is differentiated with respect to the observations          */
+/* (Sec. VI-D and App. A: bilevel use).  At theta* the tangent gradient      */
+/* G(theta, x, omega) = sum_k omega_k J_k^T r_k vanishes; the implicit        */
+/* function theorem gives d theta* / d x_k = H^-1 omega_k J_k^T and          */
+/* d theta* / d omega_k = -H^-1 J_k^T r_k, with H the exact Hessian of        */
+/* delta -> F(Retract(theta*, delta)) at delta = 0:                           */
+/*   H = sum_k omega_k (J_k^T J_k + sum_m r_km Hess(pi_km)).                  */
+/* With v = H^-1 dL/dtheta:                                                   */
+/*   dL/dx_k = omega_k J_k v,   dL/domega_k = -r_k . (J_k v).                 */
+/* Squared loss only.  Fixed cameras are constrained: their tangent is zero.  */
+/* The linear system is solved exactly: points eliminated block by block,     */
+/* the reduced camera system by a dense Cholesky factorisation.               */
+/* ------------------------------------------------------------------------ */
+
+/* hyper-dual numbers a + b e1 + c e2 + d e1 e2 with e1^2 = e2^2 = 0: for
+ * f(x + e1 u + e2 w) the e1 part is f'(x) u and the e1 e2 part u^T f''(x) w. */
+typedef struct { double a, b, c, d; } hd;
+
+static hd hd_k(double a) { hd r = {a, 0.0, 0.0, 0.0}; return r; }
+static hd hd_add(hd x, hd y) { hd r = {x.a + y.a, x.b + y.b, x.c + y.c, x.d + y.d}; return r; }
+static hd hd_sub(hd x, hd y) { hd r = {x.a - y.a, x.b - y.b, x.c - y.c, x.d - y.d}; return r; }
+static hd hd_scale(double s, hd x) { hd r = {s * x.a, s * x.b, s * x.c, s * x.d}; return r; }
+static hd hd_mul(hd x, hd y)
+{
+    hd r = {x.a * y.a, x.a * y.b + x.b * y.a, x.a * y.c + x.c * y.a,
+            x.a * y.d + x.b * y.c + x.c * y.b + x.d * y.a};
+    return r;
+}
+static hd hd_div(hd x, hd y)
+{
+    /* 1/y = 1/a - b/a^2 e1 - c/a^2 e2 + (2bc/a^3 - d/a^2) e1 e2 */
+    const double i = 1.0 / y.a;
+    const hd inv = {i, -y.b * i * i, -y.c * i * i, (2.0 * y.b * y.c * i - y.d) * i * i};
+    return hd_mul(x, inv);
+}
+static void hd_cross(const hd a[3], const hd b[3], hd out[3])
+{
+    out[0] = hd_sub(hd_mul(a[1], b[2]), hd_mul(a[2], b[1]));
+    out[1] = hd_sub(hd_mul(a[2], b[0]), hd_mul(a[0], b[2]));
+    out[2] = hd_sub(hd_mul(a[0], b[1]), hd_mul(a[1], b[0]));
+}
+
+/* Pixel of the point X + dX seen by the camera retracted along the tangent
+ * dt = [rho, phi, (df, dk1, dk2), dX] (hyper-dual, zero value part).  The
+ * SE(3) exponential acting on a point is I + xi^ + xi^2/2 here: every product
+ * of three tangent components vanishes in this algebra, so the series is
+ * exact.  xi^ [Y; 1] = phi x Y + rho. */
+static void project_hd(const double *cam, const double *X, int d, const hd *dt, hd pix[2])
+{
+    double R[9];
+    quat_to_rot(cam + 3, R);
+    const hd *rho = dt, *phi = dt + 3, *dX = dt + d;
+    hd Yp[3];
+    for (int i = 0; i < 3; ++i) {
+        hd s = hd_k(cam[i]);
+        for (int j = 0; j < 3; ++j) s = hd_add(s, hd_scale(R[3 * i + j], hd_add(hd_k(X[j]), dX[j])));
+        Yp[i] = s;
+    }
+    hd a[3], b[3], Y[3];
+    hd_cross(phi, Yp, a);
+    for (int i = 0; i < 3; ++i) a[i] = hd_add(a[i], rho[i]);
+    hd_cross(phi, a, b);
+    for (int i = 0; i < 3; ++i) Y[i] = hd_add(hd_add(Yp[i], a[i]), hd_scale(0.5, b[i]));
+    hd f = hd_k(cam[7]), k1 = hd_k(cam[8]), k2 = hd_k(cam[9]);
+    if (d == 9) {
+        f = hd_add(f, dt[6]);
+        k1 = hd_add(k1, dt[7]);
+        k2 = hd_add(k2, dt[8]);
+    }
+    const hd u = hd_scale(-1.0, hd_div(Y[0], Y[2]));
+    const hd v = hd_scale(-1.0, hd_div(Y[1], Y[2]));
+    const hd s = hd_add(hd_mul(u, u), hd_mul(v, v));
+    const hd D = hd_add(hd_k(1.0), hd_add(hd_mul(k1, s), hd_mul(k2, hd_mul(s, s))));
+    const hd fD = hd_mul(f, D);
+    pix[0] = hd_mul(fD, u);
+    pix[1] = hd_mul(fD, v);
+}
+
+/* For observation k: residual r (2), J (2 x n, tangent order [camera d,
+ * point 3], n = d + 3) and C = sum_m r_m Hess(pi_m) (n x n), all from the
+ * hyper-dual evaluation of the projection. */
+void orc_obs_second_order(const orc_ctx *c, int64_t k, double *r, double *J, double *C)
+{
+    const int d = c->o.d, n = d + 3;
+    const double *cam = c->cams + 10 * (int64_t)c->cidx[k];
+    const double *X = c->pts + 3 * (int64_t)c->pidx[k];
+    double H0[144], H1[144];
+    hd pix[2];
+    for (int i = 0; i < n; ++i) {
+        for (int j = i; j < n; ++j) {
+            hd dt[12];
+            for (int q = 0; q < 12; ++q) dt[q] = hd_k(0.0);
+            dt[i].b = 1.0;
+            dt[j].c = 1.0;
+            project_hd(cam, X, d, dt, pix);
+            if (j == i) {
+                J[i] = pix[0].b;
+                J[n + i] = pix[1].b;
+            }
+            H0[i * n + j] = H0[j * n + i] = pix[0].d;
+            H1[i * n + j] = H1[j * n + i] = pix[1].d;
+        }
+    }
+    r[0] = pix[0].a - c->obs[2 * k];
+    r[1] = pix[1].a - c->obs[2 * k + 1];
+    for (int q = 0; q < n * n; ++q) C[q] = r[0] * H0[q] + r[1] * H1[q];
+}
+
+/* Dense Cholesky solve of an SPD system of any size: returns 0 on success. */
+static int dense_spd_solve(int n, const double *A, const double *b, double *x)
+{
+    double *L = xcalloc((size_t)n * n, sizeof(double));
+    double *y = xcalloc((size_t)n, sizeof(double));
+    int st = cholesky(n, A, L);
+    if (st == 0) {
+        for (int i = 0; i < n; ++i) {
+            double s = b[i];
+            for (int q = 0; q < i; ++q) s -= L[(size_t)i * n + q] * y[q];
+            y[i] = s / L[(size_t)i * n + i];
+        }
+        for (int i = n - 1; i >= 0; --i) {
+            double s = y[i];
+            for (int q = i + 1; q < n; ++q) s -= L[(size_t)q * n + i] * x[q];
+            x[i] = s / L[(size_t)i * n + i];
+        }
+    }
+    free(L);
+    free(y);
+    return st;
+}
+
+/* Adjoint at the current parameters (assumed stationary).  gLc: dL/dtheta
+ * for the cameras (nc x d, tangent), gLp: for the points (np x 3).  Outputs
+ * dLdx (no x 2), dLdw (no, may be NULL), and the adjoint vector v (vc: nc x d,
+ * vp: np x 3, either may be NULL).  Returns 0, -1 for a Huber loss
+ * (unsupported), -2 when H is not positive definite on the free variables. */
+int orc_backward(orc_ctx *c, const double *gLc, const double *gLp, double *dLdx, double *dLdw,
+                 double *vc_out, double *vp_out)
+{
+    if (c->o.huber_delta > 0.0) return -1;
+    const int d = c->o.d, n = d + 3;
+    const int64_t no = c->no;
+    const int nc = c->nc, np = c->np;
+    double *J = xcalloc((size_t)no * 2 * n, sizeof(double));
+    double *r = xcalloc((size_t)no * 2, sizeof(double));
+    double *U = xcalloc((size_t)nc * d * d, sizeof(double));
+    double *V = xcalloc((size_t)np * 9, sizeof(double));
+    double *W = xcalloc((size_t)no * d * 3, sizeof(double));
+    double *Vi = xcalloc((size_t)np * 9, sizeof(double));
+    double C[144], A[144];
+    for (int64_t k = 0; k < no; ++k) {
+        double *Jk = J + (size_t)k * 2 * n;
+        orc_obs_second_order(c, k, r + 2 * k, Jk, C);
+        if (c->fixed[c->cidx[k]]) { /* constrained camera: no camera tangent */
+            for (int m = 0; m < 2; ++m)
+                for (int i = 0; i < d; ++i) Jk[m * n + i] = 0.0;
+            for (int i = 0; i < n; ++i)
+                for (int j = 0; j < n; ++j)
+                    if (i < d || j < d) C[i * n + j] = 0.0;
+        }
+        const double wk = c->ow[k];
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j)
+                A[i * n + j] = wk * (Jk[i] * Jk[j] + Jk[n + i] * Jk[n + j] + C[i * n + j]);
+        double *Ua = U + (size_t)c->cidx[k] * d * d;
+        double *Vj = V + (size_t)c->pidx[k] * 9;
+        for (int i = 0; i < d; ++i)
+            for (int j = 0; j < d; ++j) Ua[i * d + j] += A[i * n + j];
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) Vj[i * 3 + j] += A[(d + i) * n + d + j];
+        for (int i = 0; i < d; ++i)
+            for (int j = 0; j < 3; ++j) W[(size_t)k * d * 3 + i * 3 + j] = A[i * n + d + j];
+    }
+    int st = 0;
+    for (int j = 0; j < np && st == 0; ++j) {
+        if (c->pt_ptr[j + 1] == c->pt_ptr[j]) continue; /* unobserved: v_p = dL/dp / 0 undefined */
+        const double det = inverse3(V + 9 * (size_t)j, Vi + 9 * (size_t)j);
+        if (!(det > 0.0)) st = -2;
+    }
+    const int ns = d * nc;
+    double *S = xcalloc((size_t)ns * ns, sizeof(double));
+    double *b = xcalloc((size_t)ns, sizeof(double));
+    double *vc = xcalloc((size_t)ns, sizeof(double));
+    double *vp = xcalloc((size_t)np * 3, sizeof(double));
+    if (st == 0) {
+        for (int a = 0; a < nc; ++a)
+            for (int i = 0; i < d; ++i) {
+                b[a * d + i] = gLc[a * d + i];
+                for (int j = 0; j < d; ++j)
+                    S[(size_t)(a * d + i) * ns + a * d + j] = U[(size_t)a * d * d + i * d + j];
+            }
+        for (int j = 0; j < np; ++j) {
+            const double *Vij = Vi + 9 * (size_t)j;
+            for (int64_t xi = c->pt_ptr[j]; xi < c->pt_ptr[j + 1]; ++xi) {
+                const int64_t x = c->pt_obs[xi];
+                const double *Wx = W + (size_t)x * d * 3;
+                double Y[27]; /* Y = W_x V_j^-1 (d x 3) */
+                for (int i = 0; i < d; ++i)
+                    for (int q = 0; q < 3; ++q)
+                        Y[i * 3 + q] = Wx[i * 3] * Vij[q] + Wx[i * 3 + 1] * Vij[3 + q] +
+                                       Wx[i * 3 + 2] * Vij[6 + q];
+                const int ax = c->cidx[x];
+                for (int i = 0; i < d; ++i)
+                    b[ax * d + i] -= Y[i * 3] * gLp[3 * j] + Y[i * 3 + 1] * gLp[3 * j + 1] +
+                                     Y[i * 3 + 2] * gLp[3 * j + 2];
+                for (int64_t yi = c->pt_ptr[j]; yi < c->pt_ptr[j + 1]; ++yi) {
+                    const int64_t y = c->pt_obs[yi];
+                    const double *Wy = W + (size_t)y * d * 3;
+                    const int ay = c->cidx[y];
+                    for (int i = 0; i < d; ++i)
+                        for (int q = 0; q < d; ++q)
+                            S[(size_t)(ax * d + i) * ns + ay * d + q] -=
+                                Y[i * 3] * Wy[q * 3] + Y[i * 3 + 1] * Wy[q * 3 + 1] +
+                                Y[i * 3 + 2] * Wy[q * 3 + 2];
+                }
+            }
+        }
+        for (int a = 0; a < nc; ++a) {
+            if (!c->fixed[a]) continue;
+            for (int i = 0; i < d; ++i) {
+                const int row = a * d + i;
+                for (int q = 0; q < ns; ++q) S[(size_t)row * ns + q] = S[(size_t)q * ns + row] = 0.0;
+                S[(size_t)row * ns + row] = 1.0;
+                b[row] = 0.0;
+            }
+        }
+        if (dense_spd_solve(ns, S, b, vc) != 0) st = -2;
+    }
+    if (st == 0) {
+        for (int j = 0; j < np; ++j) {
+            double s[3] = {gLp[3 * j], gLp[3 * j + 1], gLp[3 * j + 2]};
+            for (int64_t xi = c->pt_ptr[j]; xi < c->pt_ptr[j + 1]; ++xi) {
+                const int64_t x = c->pt_obs[xi];
+                const double *Wx = W + (size_t)x * d * 3;
+                const double *va = vc + (size_t)c->cidx[x] * d;
+                for (int q = 0; q < 3; ++q)
+                    for (int i = 0; i < d; ++i) s[q] -= Wx[i * 3 + q] * va[i];
+            }
+            const double *Vij = Vi + 9 * (size_t)j;
+            for (int q = 0; q < 3; ++q)
+                vp[3 * j + q] = Vij[3 * q] * s[0] + Vij[3 * q + 1] * s[1] + Vij[3 * q + 2] * s[2];
+        }
+        for (int64_t k = 0; k < no; ++k) {
+            const double *Jk = J + (size_t)k * 2 * n;
+            const double *va = vc + (size_t)c->cidx[k] * d, *vq = vp + 3 * (size_t)c->pidx[k];
+            double e[2];
+            for (int m = 0; m < 2; ++m) {
+                double s = 0.0;
+                for (int i = 0; i < d; ++i) s += Jk[m * n + i] * va[i];
+                for (int i = 0; i < 3; ++i) s += Jk[m * n + d + i] * vq[i];
+                e[m] = s;
+            }
+            dLdx[2 * k] = c->ow[k] * e[0];
+            dLdx[2 * k + 1] = c->ow[k] * e[1];
+            if (dLdw) dLdw[k] = -(r[2 * k] * e[0] + r[2 * k + 1] * e[1]);
+        }
+        if (vc_out) memcpy(vc_out, vc, sizeof(double) * ns);
+        if (vp_out) memcpy(vp_out, vp, sizeof(double) * 3 * np);
+    }
+    void *p[] = {J, r, U, V, W, Vi, S, b, vc, vp};
+    for (size_t i = 0; i < sizeof(p) / sizeof(p[0]); ++i) free(p[i]);
+    return st;
+}

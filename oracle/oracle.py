@@ -75,6 +75,9 @@ def lib():
         L.orc_project.argtypes = [P, P, C.c_int32, P, P, P]
         L.orc_project.restype = C.c_double
         L.orc_retract_camera.argtypes = [P, P, C.c_int32, P]
+        L.orc_obs_second_order.argtypes = [P, C.c_int64, P, P, P]
+        L.orc_backward.argtypes = [P, P, P, P, P, P, P]
+        L.orc_backward.restype = C.c_int
         _lib = L
     return _lib
 
@@ -228,3 +231,28 @@ class Oracle:
         Vinv = np.zeros((self.np, 3, 3))
         lib().orc_get_step(self._h, _p(dc), _p(dp), _p(Vinv))
         return dc, dp, Vinv
+
+    def obs_second_order(self, k: int):
+        """(r[2], J[2, d+3], C[d+3, d+3]) of observation k at the current
+        parameters: residual, Jacobian in the tangent order [camera, point]
+        and sum_m r_m Hess(pi_m)."""
+        n = self.d + 3
+        r = np.zeros(2)
+        J = np.zeros((2, n))
+        Cm = np.zeros((n, n))
+        lib().orc_obs_second_order(self._h, int(k), _p(r), _p(J), _p(Cm))
+        return r, J, Cm
+
+    def backward(self, gL_cams, gL_pts):
+        """Implicit-function adjoint at the current (stationary) parameters:
+        returns (dL/dobs [no, 2], dL/dw [no], v_cams [nc, d], v_pts [np, 3])."""
+        gc = np.ascontiguousarray(gL_cams, np.float64).reshape(self.nc, self.d)
+        gp = np.ascontiguousarray(gL_pts, np.float64).reshape(self.np, 3)
+        dx = np.zeros((self.no, 2))
+        dw = np.zeros(self.no)
+        vc = np.zeros((self.nc, self.d))
+        vp = np.zeros((self.np, 3))
+        st = lib().orc_backward(self._h, _p(gc), _p(gp), _p(dx), _p(dw), _p(vc), _p(vp))
+        if st != 0:
+            raise RuntimeError(f"oracle backward failed ({st})")
+        return dx, dw, vc, vp
