@@ -77,6 +77,9 @@ typedef struct {
                           residuals below ~1e-10 may not be attainable);
                           BA_CG_STANDARD: the textbook recurrence, two per
                           iteration */
+  int32_t enable_backward; /* nonzero: the workspace also holds the FP64 buffers
+                              of ba_backward (about 1 KB per observation) */
+  double adjoint_rtol;     /* relative residual of ba_backward's PCG solve */
 } ba_options;
 
 enum { BA_CG_PIPELINED = 0, BA_CG_STANDARD = 1 };
@@ -98,7 +101,7 @@ typedef struct {
 
 /* Fills *opt with the defaults: cam_dof 9, BA_FP64, squared loss, cg_rtol 1e-4,
  * cg_maxiter 250, lambda0 1e-4, lambda in [1e-12, 1e12], clamp [1e-6, 1e32],
- * BA_CG_PIPELINED. */
+ * BA_CG_PIPELINED, backward disabled, adjoint_rtol 1e-10. */
 void ba_default_options(ba_options* opt);
 
 /* Creates a problem from the observation pattern: observation k sees point
@@ -162,11 +165,33 @@ ba_status ba_lm_step(ba_problem* p, ba_step_info* info);
 ba_status ba_solve(ba_problem* p, int32_t max_iters, double rel_decrease_tol, int32_t plateau_steps,
                    ba_step_info* infos, int32_t* iters_done);
 
-/* Gradient of a loss of the optimum with respect to the observations and
- * weights (implicit-function adjoint).  Not available in this build:
- * returns BA_EUNSUPPORTED. */
+/* Gradient of a loss L(theta*) of the optimum with respect to the observed
+ * pixels and the per-observation weights: the implicit-function adjoint of
+ * the stationarity condition sum_k w_k J_k^T r_k = 0 (the solver inside a
+ * bilevel learning pipeline, Sec. VI-D and App. A).  With H the exact Hessian
+ * of delta -> F(theta* (+) delta) at 0 (Gauss-Newton term plus the projection
+ * curvature weighted by the residuals) and v = H^-1 dL/dtheta (tangent):
+ *   dL/dx_k = w_k J_k v,   dL/dw_k = -r_k . (J_k v).
+ * H v = dL/dtheta is solved exactly like the LM system (points eliminated,
+ * the same pair table, block-Jacobi PCG with the standard recurrence to
+ * adjoint_rtol within cg_maxiter iterations), in FP64 whatever the precision.
+ *   dL_dcams: device float64 [n_cams][10], dL/d(stored camera row); its
+ *             component along the quaternion's own direction is ignored (the
+ *             gradient is taken along the retraction); fixed cameras ignored;
+ *   dL_dpts:  device float64 [n_pts][3];
+ *   dL_dobs:  device float64 [n_obs][2] output, creation order;
+ *   dL_dw:    device float64 [n_obs] output, or NULL;
+ *   info:     host, may be NULL: cg_iters, cg_rel_resid, status.
+ * theta must be a stationary point (run ba_solve first); squared loss only
+ * (huber_delta <= 0).  Overwrites the intermediate quantities of the last
+ * ba_lm_step (ba_export then shows the adjoint's), and the next ba_lm_step
+ * re-linearises.  Synchronises the stream.  Errors: BA_ESTATE (not bound /
+ * enable_backward not set at creation), BA_EUNSUPPORTED (Huber loss),
+ * BA_EINVAL (null pointer), BA_ENUMERIC (H not positive definite on a point
+ * or camera block: not at a minimum), BA_ENOTCONV (the PCG did not reach
+ * adjoint_rtol; outputs written), BA_EHIP. */
 ba_status ba_backward(ba_problem* p, const double* dL_dcams, const double* dL_dpts, double* dL_dobs,
-                      double* dL_dw);
+                      double* dL_dw, ba_step_info* info);
 
 /* Host snapshot of (theta, lambda) for checkpoint / resume.  With host_blob ==
  * NULL, *bytes receives the size; otherwise *bytes must be at least that. */
@@ -186,10 +211,12 @@ ba_status ba_set_state(ba_problem* p, const void* host_blob, size_t bytes);
  *   BA_X_S         float64 [nnzb][9][9] reduced camera matrix, upper blocks
  *   BA_X_BS        float64 [n_cams][9]  its right-hand side
  *   BA_X_DC        float64 [n_cams][9]; BA_X_DP float64 [n_pts][3] the step
+ *   BA_X_ADJ_VC    float64 [n_cams][9]; BA_X_ADJ_VP float64 [n_pts][3] the
+ *                  adjoint vector v of the last ba_backward
  * bytes must equal the field's size.  Synchronises the stream. */
 enum {
   BA_X_RESIDUAL = 1, BA_X_WEIGHT, BA_X_JC, BA_X_JP, BA_X_COST, BA_X_GRAD_C, BA_X_GRAD_P,
-  BA_X_V, BA_X_S_PTR, BA_X_S_COL, BA_X_S, BA_X_BS, BA_X_DC, BA_X_DP
+  BA_X_V, BA_X_S_PTR, BA_X_S_COL, BA_X_S, BA_X_BS, BA_X_DC, BA_X_DP, BA_X_ADJ_VC, BA_X_ADJ_VP
 };
 ba_status ba_export(const ba_problem* p, int32_t field, void* host_dst, size_t bytes);
 

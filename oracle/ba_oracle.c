@@ -873,7 +873,7 @@ void orc_obs_second_order(const orc_ctx *c, int64_t k, double *r, double *J, dou
     const double *cam = c->cams + 10 * (int64_t)c->cidx[k];
     const double *X = c->pts + 3 * (int64_t)c->pidx[k];
     double H0[144], H1[144];
-    hd pix[2];
+    hd pix[2] = {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}};
     for (int i = 0; i < n; ++i) {
         for (int j = i; j < n; ++j) {
             hd dt[12];

@@ -2,4 +2,4 @@
 iteration (residuals and Jacobian blocks, J^T J / J^T r assembly, Schur
 complement onto the cameras, block-Jacobi PCG) as HIP kernels behind the C
 ABI of include/ba.h, with a thin Python binding."""
-from .ba import (BA_FP64, BA_MIXED, BaError, Problem, lib)  # noqa: F401
+from .ba import (BA_FP64, BA_MIXED, BaError, Problem, bundle_adjust, lib)  # noqa: F401

@@ -20,7 +20,7 @@ BA_OK, BA_EINVAL, BA_ENUMERIC, BA_EHIP, BA_ENOTCONV, BA_ESTATE, BA_EUNSUPPORTED 
 BA_FP64, BA_MIXED = 0, 1
 BA_CG_PIPELINED, BA_CG_STANDARD = 0, 1
 (BA_X_RESIDUAL, BA_X_WEIGHT, BA_X_JC, BA_X_JP, BA_X_COST, BA_X_GRAD_C, BA_X_GRAD_P, BA_X_V,
- BA_X_S_PTR, BA_X_S_COL, BA_X_S, BA_X_BS, BA_X_DC, BA_X_DP) = range(1, 15)
+ BA_X_S_PTR, BA_X_S_COL, BA_X_S, BA_X_BS, BA_X_DC, BA_X_DP, BA_X_ADJ_VC, BA_X_ADJ_VP) = range(1, 17)
 
 EXPORTED_SYMBOLS = [
     "ba_default_options", "ba_problem_create", "ba_problem_workspace_bytes", "ba_problem_bind",
@@ -44,7 +44,8 @@ class ba_options(C.Structure):
     _fields_ = [("cam_dof", C.c_int32), ("precision", C.c_int32), ("huber_delta", C.c_double),
                 ("cg_rtol", C.c_double), ("cg_maxiter", C.c_int32), ("lambda0", C.c_double),
                 ("lambda_min", C.c_double), ("lambda_max", C.c_double), ("diag_min", C.c_double),
-                ("diag_max", C.c_double), ("cg_variant", C.c_int32)]
+                ("diag_max", C.c_double), ("cg_variant", C.c_int32), ("enable_backward", C.c_int32),
+                ("adjoint_rtol", C.c_double)]
 
 
 class ba_step_info(C.Structure):
@@ -85,7 +86,7 @@ def lib():
         L.ba_lm_step.argtypes = [P, C.POINTER(ba_step_info)]
         L.ba_solve.argtypes = [P, C.c_int32, C.c_double, C.c_int32, C.POINTER(ba_step_info),
                                C.POINTER(C.c_int32)]
-        L.ba_backward.argtypes = [P, P, P, P, P]
+        L.ba_backward.argtypes = [P, P, P, P, P, C.POINTER(ba_step_info)]
         L.ba_get_state.argtypes = [P, P, C.POINTER(C.c_size_t)]
         L.ba_set_state.argtypes = [P, P, C.c_size_t]
         L.ba_export.argtypes = [P, C.c_int32, P, C.c_size_t]
@@ -199,8 +200,12 @@ def ba_solve(h: int, max_iters: int, rel_tol: float = 1e-6, plateau_steps: int =
     return st, [infos[i].as_dict() for i in range(done.value)]
 
 
-def ba_backward(h: int, dL_dcams, dL_dpts, dL_dobs, dL_dw=None):
-    _check(lib().ba_backward(h, _ptr(dL_dcams), _ptr(dL_dpts), _ptr(dL_dobs), _ptr(dL_dw)))
+def ba_backward(h: int, dL_dcams, dL_dpts, dL_dobs, dL_dw=None) -> dict:
+    info = ba_step_info()
+    st = lib().ba_backward(h, _ptr(dL_dcams), _ptr(dL_dpts), _ptr(dL_dobs), _ptr(dL_dw),
+                           C.byref(info))
+    _check(st)
+    return info.as_dict()
 
 
 def ba_get_state(h: int) -> bytes:
@@ -247,7 +252,8 @@ class Problem:
 
     def __init__(self, n_cams, n_pts, cam_idx, pt_idx, obs_xy, obs_w=None, *, precision=BA_FP64,
                  huber_delta=0.0, cg_rtol=1e-4, cg_maxiter=250, lambda0=1e-4, fixed_cams=None,
-                 cams=None, pts=None, stream=None, cg_variant=BA_CG_PIPELINED):
+                 cams=None, pts=None, stream=None, cg_variant=BA_CG_PIPELINED,
+                 enable_backward=False, adjoint_rtol=1e-10):
         import torch
         self.torch = torch
         self.device = torch.device("cuda", torch.cuda.current_device())
@@ -258,6 +264,8 @@ class Problem:
         opt.cg_maxiter = cg_maxiter
         opt.lambda0 = lambda0
         opt.cg_variant = cg_variant
+        opt.enable_backward = 1 if enable_backward else 0
+        opt.adjoint_rtol = adjoint_rtol
         self.opt = opt
         self.n_cams, self.n_pts = int(n_cams), int(n_pts)
         self.n_obs = int(np.asarray(cam_idx).size)
@@ -268,10 +276,7 @@ class Problem:
             raise RuntimeError("workspace allocation is not 256-byte aligned")
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         ba_problem_bind(self.h, self.workspace.data_ptr(), nbytes, self.stream.cuda_stream)
-        xy = self._dev(obs_xy).reshape(self.n_obs, 2)
-        w = None if obs_w is None else self._dev(obs_w).reshape(self.n_obs)
-        self.stream.synchronize()
-        ba_set_observations(self.h, xy, w)
+        self.set_observations(obs_xy, obs_w)
         if fixed_cams is not None and len(fixed_cams):
             mask = np.zeros(self.n_cams, np.uint8)
             mask[np.asarray(fixed_cams)] = 1
@@ -301,6 +306,12 @@ class Problem:
                 pass
             ba_problem_destroy(h)
             self.h = None
+
+    def set_observations(self, obs_xy, obs_w=None):
+        xy = self._dev(obs_xy).reshape(self.n_obs, 2)
+        w = None if obs_w is None else self._dev(obs_w).reshape(self.n_obs)
+        self.stream.synchronize()
+        ba_set_observations(self.h, xy, w)
 
     @property
     def nnzb(self) -> int:
@@ -337,6 +348,20 @@ class Problem:
     def solve(self, max_iters, rel_tol=1e-6, plateau_steps=5):
         return ba_solve(self.h, max_iters, rel_tol, plateau_steps)
 
+    def backward(self, dL_dcams, dL_dpts, want_dw: bool = True):
+        """Implicit-function adjoint at the current (stationary) parameters:
+        dL_dcams [n_cams, 10] (gradient w.r.t. the stored camera rows),
+        dL_dpts [n_pts, 3]; returns (dL/dobs [n_obs, 2], dL/dw [n_obs] or
+        None, info dict)."""
+        t = self.torch
+        gc = self._dev(dL_dcams).reshape(self.n_cams, 10)
+        gp = self._dev(dL_dpts).reshape(self.n_pts, 3)
+        dx = t.empty((self.n_obs, 2), dtype=t.float64, device=self.device)
+        dw = t.empty(self.n_obs, dtype=t.float64, device=self.device) if want_dw else None
+        self.stream.synchronize()
+        info = ba_backward(self.h, gc, gp, dx, dw)
+        return dx, dw, info
+
     def set_profiling(self, enable: bool = True):
         ba_set_profiling(self.h, enable)
 
@@ -358,6 +383,55 @@ class Problem:
                   BA_X_GRAD_P: ((np_, 3), np.float64), BA_X_V: ((np_, 3, 3), np.float64),
                   BA_X_S_PTR: ((nc + 1,), np.int64), BA_X_S_COL: ((nz,), np.int32),
                   BA_X_S: ((nz, 9, 9), np.float64), BA_X_BS: ((nc, 9), np.float64),
-                  BA_X_DC: ((nc, 9), np.float64), BA_X_DP: ((np_, 3), np.float64)}
+                  BA_X_DC: ((nc, 9), np.float64), BA_X_DP: ((np_, 3), np.float64),
+                  BA_X_ADJ_VC: ((nc, 9), np.float64), BA_X_ADJ_VP: ((np_, 3), np.float64)}
         shape, dt = shapes[field]
         return ba_export(self.h, field, np.zeros(shape, dt))
+
+
+# ---- differentiable layer ------------------------------------------------------
+
+def _layer_function():
+    import torch
+
+    class _BundleAdjust(torch.autograd.Function):
+        """theta* = argmin F(theta; x, w) from the problem's current parameters;
+        backward through the implicit-function adjoint (ba_backward)."""
+
+        @staticmethod
+        def forward(ctx, obs_xy, obs_w, problem, max_iters, rel_tol, plateau_steps):
+            problem.set_observations(obs_xy.detach(), None if obs_w is None else obs_w.detach())
+            st, _ = problem.solve(max_iters, rel_tol, plateau_steps)
+            if st not in (BA_OK, BA_ENOTCONV):
+                _check(st)
+            ctx.problem = problem
+            ctx.want_dw = obs_w is not None
+            cams, pts = problem.get_params()
+            return cams, pts
+
+        @staticmethod
+        def backward(ctx, g_cams, g_pts):
+            p = ctx.problem
+            if g_cams is None:
+                g_cams = torch.zeros((p.n_cams, 10), dtype=torch.float64, device=p.device)
+            if g_pts is None:
+                g_pts = torch.zeros((p.n_pts, 3), dtype=torch.float64, device=p.device)
+            dx, dw, _ = p.backward(g_cams, g_pts, want_dw=ctx.want_dw)
+            return dx, dw, None, None, None, None
+
+    return _BundleAdjust
+
+
+_LAYER = None
+
+
+def bundle_adjust(problem: Problem, obs_xy, obs_w=None, max_iters: int = 100, rel_tol: float = 1e-10,
+                  plateau_steps: int = 5):
+    """Differentiable bundle adjustment: solves from the problem's current
+    parameters and returns (cams [n_cams, 10], pts [n_pts, 3]); gradients flow
+    to obs_xy and obs_w through the implicit-function adjoint.  The problem
+    must be created with enable_backward=True and the squared loss."""
+    global _LAYER
+    if _LAYER is None:
+        _LAYER = _layer_function()
+    return _LAYER.apply(obs_xy, obs_w, problem, max_iters, rel_tol, plateau_steps)

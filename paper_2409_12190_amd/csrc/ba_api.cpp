@@ -9,6 +9,7 @@
 #include <string>
 
 #include "ba.h"
+#include "ba_adjoint.h"
 #include "ba_internal.h"
 #include "ba_kernels.h"
 
@@ -110,6 +111,18 @@ void carve(ba_problem* p, char* base, size_t* total) {
   b.dev = c.take<ba::DevScalars>(1);
   b.dinfo = c.take<ba_step_info>(1);
   b.gsync = c.take<ba::GridSync>(1);
+  if (p->opt.enable_backward) {
+    b.adjA = c.take<double>(78 * no);
+    b.adjJ = c.take<double>(24 * no);
+    b.adjY = c.take<double>(27 * no);
+    b.adjU = c.take<double>(81 * nc);
+    b.adjS = es == 8 ? reinterpret_cast<double*>(b.S) : c.take<double>(81 * nnzb);
+    b.adj_gt = c.take<double>(9 * nc);
+    b.adj_vc = c.take<double>(9 * nc);
+    b.adj_vp = c.take<double>(3 * np);
+    b.adj_dev = c.take<ba::DevScalars>(1);
+    b.adj_info = c.take<ba_step_info>(1);
+  }
   *total = c.off + 256;
 }
 
@@ -258,6 +271,8 @@ void ba_default_options(ba_options* o) {
   o->diag_min = 1e-6;
   o->diag_max = 1e32;
   o->cg_variant = BA_CG_PIPELINED;
+  o->enable_backward = 0;
+  o->adjoint_rtol = 1e-10;
 }
 
 const char* ba_last_error(void) { return g_err.c_str(); }
@@ -367,6 +382,8 @@ ba_status ba_problem_bind(ba_problem* p, void* ws, size_t bytes, void* stream) {
   p->pcg_grid = P.pcg_grid;
   if (p->pcg_grid > maxg || p->pcg_grid > ba::MAX_BARRIER_GROUPS * ba::BARRIER_FANIN)
     return fail(BA_EUNSUPPORTED, "too many cameras for one co-resident PCG grid");
+  p->adj_grid_ok = p->opt.enable_backward &&
+                   p->pcg_grid <= ba::pcg_max_grid<double>(P.pcg_resident, false);
   p->bound = true;
   return BA_OK;
 }
@@ -489,9 +506,65 @@ ba_status ba_solve(ba_problem* p, int32_t max_iters, double rel_tol, int32_t pla
   return ret;
 }
 
-ba_status ba_backward(ba_problem* p, const double*, const double*, double*, double*) {
-  (void)p;
-  return fail(BA_EUNSUPPORTED, "the implicit-function adjoint is not available in this build");
+ba_status ba_backward(ba_problem* p, const double* dL_dcams, const double* dL_dpts, double* dL_dobs,
+                      double* dL_dw, ba_step_info* info) {
+  using namespace ba;
+  if (!p) return fail(BA_EINVAL, "null problem");
+  if (p->opt.huber_delta > 0.0)
+    return fail(BA_EUNSUPPORTED, "the adjoint is implemented for the squared loss only");
+  ba_status st = require_ready(p);
+  if (st != BA_OK) return st;
+  if (!p->opt.enable_backward) return fail(BA_ESTATE, "create the problem with enable_backward set");
+  if (!dL_dcams || !dL_dpts || !dL_dobs) return fail(BA_EINVAL, "null argument");
+  if (!p->adj_grid_ok)
+    return fail(BA_EUNSUPPORTED, "the FP64 PCG does not fit the co-resident grid of this problem");
+  const Plan& P = p->plan;
+  Buffers& b = p->b;
+  hipStream_t s = p->stream;
+  const int nchunk = (int)P.chunk_ptr.size() - 1;
+  const int cur = p->cur;
+  p->lin_valid = false;  // the linearisation buffers are reused below
+  HIPCHK(hipMemsetAsync(b.adj_dev, 0, sizeof(DevScalars), s));
+  HIPCHK(hipMemsetAsync(b.adj_info, 0, sizeof(ba_step_info), s));
+  HIPCHK(hipMemsetAsync(b.diagU, 0, 9 * sizeof(double) * P.nc, s));  // no damping term
+  AdjTangentArgs ta{P.nc, b.fixed, b.cams[cur], dL_dcams, b.adj_gt};
+  HIPCHK(launch_adj_tangent(ta, s));
+  AdjObsArgs oa{P.no, b.o_cam, b.o_pt, b.fixed, b.o_xy, b.o_w, b.cams[cur], b.pts[cur],
+                b.adjA, b.adjJ, b.r};
+  HIPCHK(launch_adj_obs(oa, s));
+  AdjPointArgs pa{b.chunk_ptr, b.chunk_pt, b.pt_ptr, b.o_pt, b.adjA, b.Vinv, b.adjY, b.gsync,
+                  &b.adj_dev->error};
+  HIPCHK(launch_adj_points(pa, nchunk, s));
+  AdjCameraArgs ca{b.cam_ptr, b.cam_obs, b.o_pt, b.fixed, b.adjA, b.adjY, dL_dpts, b.adj_gt,
+                   b.adjU, b.bS};
+  HIPCHK(launch_adj_camera(ca, P.nc, s));
+  AdjSchurArgs sa{b.slot_blk, b.slot_pb, b.slot_pe, b.slot_lead, b.pair_x, b.pair_y, b.blk_row,
+                  b.S_ptr, b.adjA, b.adjY, b.adjU, b.adjS, b.Sdiag};
+  HIPCHK(launch_adj_schur(sa, P.n_schur_wg, s));
+  // block-Jacobi factors of the undamped blocks (lambda = 0 in adj_dev)
+  CamFinishArgs cf{b.Sdiag, b.diagU, p->opt.diag_min, p->opt.diag_max, b.Minv, b.adj_dev};
+  HIPCHK(launch_camera_finish<double>(cf, P.nc, s));
+  PcgArgs ga{P.nc, p->opt.cg_maxiter, p->opt.adjoint_rtol, b.S_ptr, b.T_ptr, b.pcg_row, b.item_ptr,
+             b.item_e, b.item_code, b.ucol_ptr, b.ucol, b.adjS, b.Sdiag, b.Minv, b.bS, b.adj_vc,
+             b.zring, b.partA, b.partB, b.adj_info, b.gsync, &b.adj_dev->error};
+  HIPCHK(launch_pcg<double>(ga, P.pcg_grid, P.pcg_resident, false, s));
+  AdjBackArgs bb{b.chunk_ptr, b.chunk_pt, b.pt_ptr, b.o_cam, b.o_pt, b.o_orig, b.adjA, b.adjJ,
+                 b.r, b.o_w, b.Vinv, b.adj_vc, dL_dpts, b.adj_vp, dL_dobs, dL_dw};
+  HIPCHK(launch_adj_backsub(bb, nchunk, s));
+  HIPCHK(hipMemcpyAsync(p->hinfo, b.adj_info, sizeof(ba_step_info), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(p->hscal, b.adj_dev, sizeof(DevScalars), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  ba_step_info out = *p->hinfo;
+  const int32_t err = p->hscal->error;
+  st = BA_OK;
+  if (err & ERR_BARRIER) st = fail(BA_EHIP, "the PCG grid barrier timed out");
+  else if (err & ERR_POINT_BLOCK) st = fail(BA_ENUMERIC, "an exact point block is not positive definite");
+  else if (err & ERR_CAMERA_BLOCK) st = fail(BA_ENUMERIC, "an exact camera block is not positive definite");
+  else if (!(out.cg_rel_resid <= p->opt.adjoint_rtol))
+    st = fail(BA_ENOTCONV, "the adjoint PCG did not reach adjoint_rtol");
+  out.status = st;
+  if (info) *info = out;
+  return st;
 }
 
 ba_status ba_get_state(const ba_problem* p, void* blob, size_t* bytes) {
@@ -604,6 +677,15 @@ ba_status ba_export(const ba_problem* p, int32_t field, void* dst, size_t bytes)
       if (!need(np * 3 * sizeof(double))) return fail(BA_EINVAL, "size mismatch");
       HIPCHK(hipMemcpyAsync(dst, field == BA_X_GRAD_P ? b.gp : b.dp, bytes, hipMemcpyDeviceToHost,
                             p->stream));
+      HIPCHK(hipStreamSynchronize(p->stream));
+      return BA_OK;
+    }
+    case BA_X_ADJ_VC:
+    case BA_X_ADJ_VP: {
+      if (!p->opt.enable_backward) return fail(BA_ESTATE, "backward buffers are not enabled");
+      const bool vc = field == BA_X_ADJ_VC;
+      if (!need((vc ? nc * 9 : np * 3) * sizeof(double))) return fail(BA_EINVAL, "size mismatch");
+      HIPCHK(hipMemcpyAsync(dst, vc ? b.adj_vc : b.adj_vp, bytes, hipMemcpyDeviceToHost, p->stream));
       HIPCHK(hipStreamSynchronize(p->stream));
       return BA_OK;
     }

@@ -118,6 +118,124 @@ __device__ __forceinline__ Proj project_jac(const Camera& c, V3 X, double Jc[2][
   return pr;
 }
 
+// Index of (i, j), i <= j, in the packed upper triangle of a 12 x 12 matrix.
+__device__ __forceinline__ int sym12(int i, int j) { return i * 12 - (i * (i - 1)) / 2 + (j - i); }
+
+// Curvature of one observation's pixel contracted with its residual r:
+//   C = sum_m r_m Hess(pixel_m)
+// over the 12-dimensional tangent z = [rho(3), phi(3), f, k1, k2, dX(3)] at
+// z = 0, written packed upper (78 values).  To second order the camera-frame
+// point is
+//   Y = Y0 + R dX + rho + phi x Y0 + phi x (R dX) + 1/2 phi x (phi x Y0)
+//       + 1/2 phi x rho
+// (the SE(3) exponential acting on the moved point), and the pixel is
+// q(Y, f, k1, k2) = f D(s) u with u = -(Y_x, Y_y)/Y_z.  With g = r . dq/dY,
+// H_Y = r . d2q/dY2, H_Yk = r . d2q/dY dk and H_kk = r . d2q/dk2:
+//   C = JY^T H_Y JY + sum_i g_i Hess(Y_i) + JY^T H_Yk + H_Yk^T JY + H_kk,
+// JY = dY/dz = [I | -[Y0]x | 0 | R], and the second derivatives of Y are
+//   phi-phi: 1/2 (g Y0^T + Y0 g^T) - (g . Y0) I,
+//   phi-rho: -1/2 [g]x,   phi-dX: -[g]x R.
+__device__ inline void curvature12(const Camera& c, V3 X, double r0, double r1, double* __restrict__ C) {
+  const V3 Y = quat_rotate(c.qv, c.qw, X) + c.t;
+  const double iz = 1.0 / Y.z;
+  const double u[2] = {-Y.x * iz, -Y.y * iz};
+  const double rr[2] = {r0, r1};
+  const double s = u[0] * u[0] + u[1] * u[1];
+  const double D = 1.0 + s * (c.k1 + c.k2 * s);
+  const double D1 = c.k1 + 2.0 * c.k2 * s;  // dD/ds
+  const double D2 = 2.0 * c.k2;              // d2D/ds2
+  const double ru = r0 * u[0] + r1 * u[1];
+  // derivatives of r . q with respect to u (2) and u-u (2 x 2)
+  double gu[2], Hu[2][2];
+  for (int n = 0; n < 2; ++n) {
+    gu[n] = c.f * (D * rr[n] + 2.0 * D1 * ru * u[n]);
+    for (int o = 0; o < 2; ++o)
+      Hu[n][o] = c.f * (2.0 * D1 * (u[o] * rr[n] + u[n] * rr[o] + (n == o ? ru : 0.0)) +
+                        4.0 * D2 * ru * u[n] * u[o]);
+  }
+  // du_n/dY = -iz (e_n + u_n e_z)
+  double B[2][3] = {{-iz, 0.0, -iz * u[0]}, {0.0, -iz, -iz * u[1]}};
+  double gY[3], HY[3][3];
+  for (int j = 0; j < 3; ++j) gY[j] = gu[0] * B[0][j] + gu[1] * B[1][j];
+  for (int j = 0; j < 3; ++j)
+    for (int k = 0; k < 3; ++k) {
+      double h = 0.0;
+      for (int n = 0; n < 2; ++n)
+        for (int o = 0; o < 2; ++o) h += Hu[n][o] * B[n][j] * B[o][k];
+      HY[j][k] = h;
+    }
+  // + sum_n gu_n d2u_n/dY2,  d2u_n/dY_j dY_k = iz^2 (d_jn d_kz + d_jz d_kn + 2 u_n d_jz d_kz)
+  const double iz2 = iz * iz;
+  HY[0][2] += gu[0] * iz2;
+  HY[2][0] += gu[0] * iz2;
+  HY[1][2] += gu[1] * iz2;
+  HY[2][1] += gu[1] * iz2;
+  HY[2][2] += 2.0 * iz2 * (gu[0] * u[0] + gu[1] * u[1]);
+  // r . d2q / du dk for k = (f, k1, k2), then chained to Y
+  double Huk[2][3];
+  for (int n = 0; n < 2; ++n) {
+    Huk[n][0] = D * rr[n] + 2.0 * D1 * ru * u[n];
+    Huk[n][1] = c.f * (2.0 * ru * u[n] + s * rr[n]);
+    Huk[n][2] = c.f * (4.0 * s * ru * u[n] + s * s * rr[n]);
+  }
+  double HYk[3][3];
+  for (int j = 0; j < 3; ++j)
+    for (int k = 0; k < 3; ++k) HYk[j][k] = Huk[0][k] * B[0][j] + Huk[1][k] * B[1][j];
+  // JY columns: rho -> e_b, phi -> -[Y0]x e_b = e_b x Y0, intrinsics -> 0,
+  // dX -> R e_l (the rotated unit vectors)
+  double JY[3][12];
+  for (int j = 0; j < 3; ++j)
+    for (int i = 0; i < 12; ++i) JY[j][i] = 0.0;
+  const double Yv[3] = {Y.x, Y.y, Y.z};
+  for (int b = 0; b < 3; ++b) {
+    JY[b][b] = 1.0;
+    const V3 e = v3(b == 0, b == 1, b == 2);
+    const V3 col = cross(e, Y);
+    JY[0][3 + b] = col.x;
+    JY[1][3 + b] = col.y;
+    JY[2][3 + b] = col.z;
+    const V3 Re = quat_rotate(c.qv, c.qw, e);
+    JY[0][9 + b] = Re.x;
+    JY[1][9 + b] = Re.y;
+    JY[2][9 + b] = Re.z;
+  }
+  double T[3][12];  // HY JY, with H_Yk placed in the intrinsic columns
+  for (int j = 0; j < 3; ++j)
+    for (int i = 0; i < 12; ++i)
+      T[j][i] = (i >= 6 && i < 9) ? HYk[j][i - 6]
+                                  : HY[j][0] * JY[0][i] + HY[j][1] * JY[1][i] + HY[j][2] * JY[2][i];
+  for (int i = 0; i < 12; ++i)
+    for (int j = i; j < 12; ++j) {
+      double v;
+      if (i >= 6 && i < 9 && j >= 6 && j < 9) {
+        v = 0.0;  // H_kk: (f, k1) = s (r.u), (f, k2) = s^2 (r.u)
+        if (i == 6 && j == 7) v = s * ru;
+        if (i == 6 && j == 8) v = s * s * ru;
+      } else if (i >= 6 && i < 9) {
+        v = T[0][i] * JY[0][j] + T[1][i] * JY[1][j] + T[2][i] * JY[2][j];
+      } else {
+        v = JY[0][i] * T[0][j] + JY[1][i] * T[1][j] + JY[2][i] * T[2][j];
+      }
+      C[sym12(i, j)] = v;
+    }
+  // second derivatives of Y contracted with g
+  const V3 g = v3(gY[0], gY[1], gY[2]);
+  const double gdY = dot(g, Y);
+  for (int a2 = 0; a2 < 3; ++a2)
+    for (int b = a2; b < 3; ++b)
+      C[sym12(3 + a2, 3 + b)] += 0.5 * (gY[a2] * Yv[b] + gY[b] * Yv[a2]) - (a2 == b ? gdY : 0.0);
+  // [g]x entries: row a, column b
+  const double gx[3][3] = {{0.0, -g.z, g.y}, {g.z, 0.0, -g.x}, {-g.y, g.x, 0.0}};
+  for (int b = 0; b < 3; ++b)      // rho_b (row) - phi_a (column): (-1/2 [g]x)^T
+    for (int a2 = 0; a2 < 3; ++a2) C[sym12(b, 3 + a2)] += -0.5 * gx[a2][b];
+  for (int a2 = 0; a2 < 3; ++a2)   // phi_a (row) - dX_l (column): -[g]x R
+    for (int l = 0; l < 3; ++l) {
+      double v = 0.0;
+      for (int k = 0; k < 3; ++k) v += gx[a2][k] * JY[k][9 + l];
+      C[sym12(3 + a2, 9 + l)] -= v;
+    }
+}
+
 // Robust loss on the squared residual norm s (Huber when delta > 0):
 // returns rho(s) and writes rho'(s).
 __device__ __forceinline__ double robust_rho(double s, double delta, double* drho) {

@@ -126,6 +126,13 @@ struct Buffers {
   DevScalars* dev;
   ba_step_info* dinfo;
   GridSync* gsync;
+  // implicit-function adjoint (only with enable_backward; FP64)
+  double *adjA, *adjJ, *adjY;  // per position: [78] w (J^T J + C), [24] J, [27] W V^-1
+  double *adjU;                // [nc][81] exact camera blocks
+  double* adjS;                // [nnzb][81] reduced matrix (aliases S in FP64 mode)
+  double *adj_gt, *adj_vc, *adj_vp;  // tangent loss gradient, adjoint vector
+  DevScalars* adj_dev;         // lambda = 0 and the adjoint's error flags
+  ba_step_info* adj_info;
 };
 
 }  // namespace ba
@@ -152,6 +159,7 @@ struct ba_problem {
   double phase_ms[BA_NUM_PHASES] = {};
   int64_t phase_n[BA_NUM_PHASES] = {};
   bool phase_used[BA_NUM_PHASES] = {};
+  bool adj_grid_ok = false;  // the FP64 standard PCG fits the plan's grid
   ba_step_info* hinfo = nullptr;     // pinned host staging
   ba::DevScalars* hscal = nullptr;   // pinned host staging
 };

@@ -7,7 +7,8 @@
 //   - observation "positions": the observations sorted by (point, camera,
 //     original index), so every point's track is a contiguous, camera-sorted
 //     run;
-//   - point-aligned chunks of at most CHUNK positions (one workgroup each);
+//   - point-aligned chunks of at most CHUNK positions and at most CHUNK
+//     points (one workgroup each);
 //   - positions grouped by camera;
 //   - the upper block pattern of the reduced camera matrix (camera a <= b
 //     share a point), diagonal first in each row, plus its transpose lists;
@@ -79,7 +80,9 @@ std::string build_plan(int32_t nc, int32_t np, int64_t no, const int32_t* cidx, 
   {
     int32_t start = 0;
     for (int32_t j = 0; j < np; ++j) {
-      if (p.pt_ptr[j + 1] - start > CHUNK) {
+      // at most CHUNK positions and at most CHUNK points (unobserved points
+      // have no positions) per chunk
+      if (p.pt_ptr[j + 1] - start > CHUNK || j - p.chunk_pt.back() >= CHUNK) {
         p.chunk_ptr.push_back(p.pt_ptr[j]);
         p.chunk_pt.push_back(j);
         start = p.pt_ptr[j];

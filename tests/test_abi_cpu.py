@@ -75,7 +75,7 @@ def test_state_calls_before_bind_fail():
         info = B.ba_step_info()
         assert B.lib().ba_lm_step(h, ctypes.byref(info)) == B.BA_ESTATE
         assert B.lib().ba_set_observations(h, None, None) == B.BA_EINVAL
-        assert B.lib().ba_backward(h, None, None, None, None) == B.BA_EUNSUPPORTED
+        assert B.lib().ba_backward(h, None, None, None, None, None) == B.BA_ESTATE
     finally:
         B.ba_problem_destroy(h)
 
@@ -93,6 +93,33 @@ def test_block_pattern_matches_oracle(cfg, kw):
         assert B.lib().ba_export(h, B.BA_X_S_PTR, ptr.ctypes.data, ptr.nbytes) == B.BA_ESTATE
     finally:
         B.ba_problem_destroy(h)
+
+
+def test_backward_needs_squared_loss_and_enabled_buffers():
+    s = make_scene(0)
+    h = _create(s.n_cams, s.n_pts, s.cam_idx, s.pt_idx, huber_delta=1.0, enable_backward=1)
+    try:
+        assert B.lib().ba_backward(h, None, None, None, None, None) == B.BA_EUNSUPPORTED
+    finally:
+        B.ba_problem_destroy(h)
+
+
+def test_backward_buffers_add_to_the_workspace():
+    s = make_scene(3, n_cams=40, n_pts=2500)
+    h0 = _create(s.n_cams, s.n_pts, s.cam_idx, s.pt_idx)
+    h1 = _create(s.n_cams, s.n_pts, s.cam_idx, s.pt_idx, enable_backward=1)
+    h2 = _create(s.n_cams, s.n_pts, s.cam_idx, s.pt_idx, enable_backward=1, precision=B.BA_MIXED)
+    h3 = _create(s.n_cams, s.n_pts, s.cam_idx, s.pt_idx, precision=B.BA_MIXED)
+    try:
+        nc, np_, no, nz = s.n_cams, s.n_pts, s.n_obs, B.ba_problem_nnzb(h0)
+        extra = 8 * (no * (78 + 24 + 27) + nc * (81 + 9 + 9) + np_ * 3)
+        d64 = B.ba_problem_workspace_bytes(h1) - B.ba_problem_workspace_bytes(h0)
+        d32 = B.ba_problem_workspace_bytes(h2) - B.ba_problem_workspace_bytes(h3)
+        assert abs(d64 - extra) < 16 * 256
+        assert abs(d32 - extra - 8 * 81 * nz) < 16 * 256   # FP64 copy of S in mixed mode
+    finally:
+        for h in (h0, h1, h2, h3):
+            B.ba_problem_destroy(h)
 
 
 def test_workspace_grows_linearly_with_observations():
