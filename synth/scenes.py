@@ -29,6 +29,9 @@ synthetic scenes stand in for them):
        track length 2+Poisson(2), 5% loop-closure re-assignments, 10 iters.
     3  differentiable layer: trajectory generator with 128 cameras, 20,000
        points, track 2+Poisson(3), observation weights U(0.5,1.5).
+    4  preconditioner stream: scene `seed` of a stream, trajectory generator
+       with U{200..2000} cameras, 10^U(4,5) points, track 2+Poisson(3) capped
+       at 30 (about 5 observations per point), L2 loss.
 """
 from __future__ import annotations
 
@@ -45,6 +48,7 @@ CONFIG_NAMES = {
     1: "traj1000_pts200k_obs1M_huber",
     2: "laps10000_pts2M_obs8M",
     3: "traj128_pts20k_obs100k_weighted",
+    4: "stream_cams200-2000_pts1e4-1e5",
 }
 
 
@@ -409,6 +413,12 @@ def make_scene(cfg: int, seed: int = 0, noise_px: float = 1.0, perturb: bool = T
         cams, pts, cam_idx, pt_idx = _trajectory_scene(rng, nc, npt, tl)
         iters = 50
         fixed = np.array([0, 1], np.int32)
+    elif cfg == 4:
+        nc = n_cams or int(rng.integers(200, 2001))
+        npt = n_pts or int(round(10.0 ** rng.uniform(4.0, 5.0)))
+        tl = np.minimum(2 + rng.poisson(3.0, size=npt), max(2, min(30, nc // 3)))
+        cams, pts, cam_idx, pt_idx = _trajectory_scene(rng, nc, npt, tl)
+        iters = 5
     else:
         raise ValueError(f"unknown configuration {cfg}")
 
