@@ -80,7 +80,14 @@ typedef struct {
   int32_t enable_backward; /* nonzero: the workspace also holds the FP64 buffers
                               of ba_backward (about 1 KB per observation) */
   double adjoint_rtol;     /* relative residual of ba_backward's PCG solve */
+  int32_t precond;         /* BA_PRECOND_BLOCK_JACOBI, or BA_PRECOND_LEARNED: the
+                              block-Jacobi blocks corrected by the camera-graph
+                              network (ba_set_gnn_params); until parameters are
+                              set, and whenever its PCG misses cg_rtol, the step
+                              uses plain block-Jacobi */
 } ba_options;
+
+enum { BA_PRECOND_BLOCK_JACOBI = 0, BA_PRECOND_LEARNED = 1 };
 
 enum { BA_CG_PIPELINED = 0, BA_CG_STANDARD = 1 };
 
@@ -97,11 +104,13 @@ typedef struct {
   int32_t cg_iters;
   int32_t cg_breakdown; /* 1 if p^T S p <= 0 stopped the PCG */
   int32_t status;       /* ba_status of the step */
+  int32_t precond_used; /* 0 block-Jacobi, 1 learned, 2 learned then block-Jacobi
+                           (the learned PCG missed cg_rtol) */
 } ba_step_info;
 
 /* Fills *opt with the defaults: cam_dof 9, BA_FP64, squared loss, cg_rtol 1e-4,
  * cg_maxiter 250, lambda0 1e-4, lambda in [1e-12, 1e12], clamp [1e-6, 1e32],
- * BA_CG_PIPELINED, backward disabled, adjoint_rtol 1e-10. */
+ * BA_CG_PIPELINED, backward disabled, adjoint_rtol 1e-10, block-Jacobi. */
 void ba_default_options(ba_options* opt);
 
 /* Creates a problem from the observation pattern: observation k sees point
@@ -193,6 +202,52 @@ ba_status ba_solve(ba_problem* p, int32_t max_iters, double rel_decrease_tol, in
 ba_status ba_backward(ba_problem* p, const double* dL_dcams, const double* dL_dpts, double* dL_dobs,
                       double* dL_dw, ba_step_info* info);
 
+/* ---- learned correction of the block-Jacobi preconditioner ----------------
+ * The paper preconditions its PCG with a diagonal (block) preconditioner
+ * (Sec. IV-C-2).  With BA_PRECOND_LEARNED each 9x9 block is corrected from
+ * the camera co-visibility graph of the reduced system: with S_ii = L_i L_i^T,
+ * S^_ij = L_i^-1 S_ij L_j^-T, E_i = sum_j S^_ij S^_ij^T and a_ij = |S^_ij|_F,
+ * node inputs [upper(E_i), log(1 + tr E_i), log(1 + deg_i)] pass through an
+ * input layer and BA_GNN_LAYERS message-passing layers (weighted mean of the
+ * neighbours, weights a_ij / sum_j a_ij, width BA_GNN_HIDDEN, ReLU) to 45
+ * outputs o_i; C_i = strict lower(o_i) + diag(exp(o_i diag)) and
+ * M_i = L_i^-T C_i C_i^T L_i^-1 (SPD; zero outputs give block-Jacobi).
+ * Parameters: one float32 vector of ba_gnn_num_params() values, in the order
+ * W_in [64][47], b_in [64], per layer W_s [64][64], W_m [64][64], b [64],
+ * W_out [45][64], b_out [45] (row-major, output index first). */
+enum { BA_GNN_FEATURES = 47, BA_GNN_HIDDEN = 64, BA_GNN_OUTPUTS = 45, BA_GNN_LAYERS = 3 };
+int64_t ba_gnn_num_params(void);
+
+/* Copies the network parameters (device float32, ba_gnn_num_params values)
+ * into the problem; NULL returns to plain block-Jacobi.  Requires
+ * precond == BA_PRECOND_LEARNED at creation. */
+ba_status ba_set_gnn_params(ba_problem* p, const float* params);
+
+/* Training graphs.  A graph holds the network inputs of one reduced camera
+ * system (node features, E_i, neighbour weights) and the activations of a
+ * training pass, in a caller-provided device workspace.  ba_graph_create
+ * takes the camera pattern of a problem created with BA_PRECOND_LEARNED;
+ * ba_graph_build fills the inputs from that problem's most recent step (its
+ * damped reduced system), enqueued on the problem's stream. */
+typedef struct ba_graph ba_graph;
+ba_status ba_graph_create(const ba_problem* p, ba_graph** out);
+ba_status ba_graph_workspace_bytes(const ba_graph* g, size_t* bytes);
+ba_status ba_graph_bind(ba_graph* g, void* workspace, size_t bytes, void* hip_stream);
+ba_status ba_graph_build(ba_graph* g, ba_problem* p);
+/* Training loss of the graph's system for the given parameters,
+ *   loss = (1/n) sum_i tr(Mh_i G_i Mh_i) - 2 tr(Mh_i) + 9,
+ *   Mh_i = C_i C_i^T, G_i = I + E_i
+ * (the squared Frobenius distance of the block-normalised preconditioned
+ * operator to the identity, by block rows), and its gradient ADDED to grad
+ * (device float32).  *loss (host) receives the loss.  Synchronises the
+ * graph's stream. */
+ba_status ba_gnn_loss_grad(ba_graph* g, const float* params, float* grad, double* loss);
+/* One Adam step on device float32 vectors of n values (m, v: moments; step
+ * counts from 1), on the given stream. */
+ba_status ba_gnn_adam(int64_t n, float* params, const float* grad, float* m, float* v, int32_t step,
+                      float lr, float beta1, float beta2, float eps, void* hip_stream);
+void ba_graph_destroy(ba_graph* g);
+
 /* Host snapshot of (theta, lambda) for checkpoint / resume.  With host_blob ==
  * NULL, *bytes receives the size; otherwise *bytes must be at least that. */
 ba_status ba_get_state(const ba_problem* p, void* host_blob, size_t* bytes);
@@ -213,10 +268,13 @@ ba_status ba_set_state(ba_problem* p, const void* host_blob, size_t bytes);
  *   BA_X_DC        float64 [n_cams][9]; BA_X_DP float64 [n_pts][3] the step
  *   BA_X_ADJ_VC    float64 [n_cams][9]; BA_X_ADJ_VP float64 [n_pts][3] the
  *                  adjoint vector v of the last ba_backward
+ *   BA_X_PRECOND   float64 [n_cams][9][9] the preconditioner blocks of the
+ *                  last step (learned blocks when the network ran)
  * bytes must equal the field's size.  Synchronises the stream. */
 enum {
   BA_X_RESIDUAL = 1, BA_X_WEIGHT, BA_X_JC, BA_X_JP, BA_X_COST, BA_X_GRAD_C, BA_X_GRAD_P,
-  BA_X_V, BA_X_S_PTR, BA_X_S_COL, BA_X_S, BA_X_BS, BA_X_DC, BA_X_DP, BA_X_ADJ_VC, BA_X_ADJ_VP
+  BA_X_V, BA_X_S_PTR, BA_X_S_COL, BA_X_S, BA_X_BS, BA_X_DC, BA_X_DP, BA_X_ADJ_VC, BA_X_ADJ_VP,
+  BA_X_PRECOND
 };
 ba_status ba_export(const ba_problem* p, int32_t field, void* host_dst, size_t bytes);
 
@@ -226,11 +284,12 @@ ba_status ba_export(const ba_problem* p, int32_t field, void* host_dst, size_t b
  *   2 point damping and inverses, 3 per-observation Schur factors,
  *   4 camera gradient / right-hand side, 5 Schur blocks from the pair table,
  *   6 diagonal damping and block-Jacobi factors, 7 PCG, 8 back-substitution,
- *   9 camera retraction, 10 candidate cost, 11 acceptance.
+ *   9 camera retraction, 10 candidate cost, 11 acceptance, 12 learned
+ *   preconditioner (graph features and network).
  * ba_get_phase_times writes, for the first n phases, the summed milliseconds
  * (ms_out) and the number of launches (launches_out, may be NULL) since
  * profiling was last enabled. */
-enum { BA_NUM_PHASES = 12 };
+enum { BA_NUM_PHASES = 13 };
 ba_status ba_set_profiling(ba_problem* p, int32_t enable);
 ba_status ba_get_phase_times(const ba_problem* p, double* ms_out, int64_t* launches_out, int32_t n);
 

@@ -20,18 +20,24 @@ BA_OK, BA_EINVAL, BA_ENUMERIC, BA_EHIP, BA_ENOTCONV, BA_ESTATE, BA_EUNSUPPORTED 
 BA_FP64, BA_MIXED = 0, 1
 BA_CG_PIPELINED, BA_CG_STANDARD = 0, 1
 (BA_X_RESIDUAL, BA_X_WEIGHT, BA_X_JC, BA_X_JP, BA_X_COST, BA_X_GRAD_C, BA_X_GRAD_P, BA_X_V,
- BA_X_S_PTR, BA_X_S_COL, BA_X_S, BA_X_BS, BA_X_DC, BA_X_DP, BA_X_ADJ_VC, BA_X_ADJ_VP) = range(1, 17)
+ BA_X_S_PTR, BA_X_S_COL, BA_X_S, BA_X_BS, BA_X_DC, BA_X_DP, BA_X_ADJ_VC, BA_X_ADJ_VP,
+ BA_X_PRECOND) = range(1, 18)
+BA_PRECOND_BLOCK_JACOBI, BA_PRECOND_LEARNED = 0, 1
+BA_GNN_FEATURES, BA_GNN_HIDDEN, BA_GNN_OUTPUTS, BA_GNN_LAYERS = 47, 64, 45, 3
 
 EXPORTED_SYMBOLS = [
     "ba_default_options", "ba_problem_create", "ba_problem_workspace_bytes", "ba_problem_bind",
     "ba_set_observations", "ba_set_fixed_cameras", "ba_set_params", "ba_get_params",
     "ba_set_lambda", "ba_get_lambda", "ba_set_cg", "ba_lm_step", "ba_solve", "ba_backward",
     "ba_get_state", "ba_set_state", "ba_export", "ba_problem_nnzb", "ba_set_profiling",
-    "ba_get_phase_times", "ba_problem_destroy", "ba_last_error",
+    "ba_get_phase_times", "ba_problem_destroy", "ba_last_error", "ba_gnn_num_params",
+    "ba_set_gnn_params", "ba_graph_create", "ba_graph_workspace_bytes", "ba_graph_bind",
+    "ba_graph_build", "ba_gnn_loss_grad", "ba_gnn_adam", "ba_graph_destroy",
 ]
-BA_NUM_PHASES = 12
+BA_NUM_PHASES = 13
 PHASE_NAMES = ["linearize", "reduce_cost", "damp_points", "point_q", "camera_vec", "schur_pairs",
-               "camera_finish", "pcg", "backsub", "retract_cameras", "candidate_cost", "finalize"]
+               "camera_finish", "pcg", "backsub", "retract_cameras", "candidate_cost", "finalize",
+               "precond_net"]
 
 
 class BaError(RuntimeError):
@@ -45,7 +51,7 @@ class ba_options(C.Structure):
                 ("cg_rtol", C.c_double), ("cg_maxiter", C.c_int32), ("lambda0", C.c_double),
                 ("lambda_min", C.c_double), ("lambda_max", C.c_double), ("diag_min", C.c_double),
                 ("diag_max", C.c_double), ("cg_variant", C.c_int32), ("enable_backward", C.c_int32),
-                ("adjoint_rtol", C.c_double)]
+                ("adjoint_rtol", C.c_double), ("precond", C.c_int32)]
 
 
 class ba_step_info(C.Structure):
@@ -53,7 +59,7 @@ class ba_step_info(C.Structure):
                 ("lambda_used", C.c_double), ("lambda_next", C.c_double),
                 ("cg_rel_resid", C.c_double), ("pred", C.c_double), ("grad_inf", C.c_double),
                 ("accepted", C.c_int32), ("cg_iters", C.c_int32), ("cg_breakdown", C.c_int32),
-                ("status", C.c_int32)]
+                ("status", C.c_int32), ("precond_used", C.c_int32)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -95,10 +101,23 @@ def lib():
         L.ba_get_phase_times.argtypes = [P, P, P, C.c_int32]
         L.ba_problem_destroy.argtypes = [P]
         L.ba_problem_destroy.restype = None
+        L.ba_gnn_num_params.argtypes = []
+        L.ba_gnn_num_params.restype = C.c_int64
+        L.ba_set_gnn_params.argtypes = [P, P]
+        L.ba_graph_create.argtypes = [P, C.POINTER(P)]
+        L.ba_graph_workspace_bytes.argtypes = [P, C.POINTER(C.c_size_t)]
+        L.ba_graph_bind.argtypes = [P, P, C.c_size_t, P]
+        L.ba_graph_build.argtypes = [P, P]
+        L.ba_gnn_loss_grad.argtypes = [P, P, P, C.POINTER(C.c_double)]
+        L.ba_gnn_adam.argtypes = [C.c_int64, P, P, P, P, C.c_int32, C.c_float, C.c_float, C.c_float,
+                                  C.c_float, P]
+        L.ba_graph_destroy.argtypes = [P]
+        L.ba_graph_destroy.restype = None
         L.ba_last_error.argtypes = []
         L.ba_last_error.restype = C.c_char_p
         for name in EXPORTED_SYMBOLS:
-            if name not in ("ba_default_options", "ba_problem_destroy", "ba_last_error"):
+            if name not in ("ba_default_options", "ba_problem_destroy", "ba_last_error",
+                            "ba_gnn_num_params", "ba_graph_destroy"):
                 getattr(L, name).restype = S
         _lib = L
     return _lib
@@ -253,7 +272,7 @@ class Problem:
     def __init__(self, n_cams, n_pts, cam_idx, pt_idx, obs_xy, obs_w=None, *, precision=BA_FP64,
                  huber_delta=0.0, cg_rtol=1e-4, cg_maxiter=250, lambda0=1e-4, fixed_cams=None,
                  cams=None, pts=None, stream=None, cg_variant=BA_CG_PIPELINED,
-                 enable_backward=False, adjoint_rtol=1e-10):
+                 enable_backward=False, adjoint_rtol=1e-10, precond=BA_PRECOND_BLOCK_JACOBI):
         import torch
         self.torch = torch
         self.device = torch.device("cuda", torch.cuda.current_device())
@@ -266,6 +285,7 @@ class Problem:
         opt.cg_variant = cg_variant
         opt.enable_backward = 1 if enable_backward else 0
         opt.adjoint_rtol = adjoint_rtol
+        opt.precond = precond
         self.opt = opt
         self.n_cams, self.n_pts = int(n_cams), int(n_pts)
         self.n_obs = int(np.asarray(cam_idx).size)
@@ -362,6 +382,17 @@ class Problem:
         info = ba_backward(self.h, gc, gp, dx, dw)
         return dx, dw, info
 
+    def set_gnn_params(self, params):
+        """Learned preconditioner parameters (device float32 tensor of
+        gnn_num_params() values), or None for plain block-Jacobi."""
+        if params is None:
+            _check(lib().ba_set_gnn_params(self.h, None))
+            return
+        t = self.torch
+        self._gnn = params.detach().to(self.device, t.float32).contiguous()
+        self.stream.synchronize()
+        _check(lib().ba_set_gnn_params(self.h, self._gnn.data_ptr()))
+
     def set_profiling(self, enable: bool = True):
         ba_set_profiling(self.h, enable)
 
@@ -384,9 +415,59 @@ class Problem:
                   BA_X_S_PTR: ((nc + 1,), np.int64), BA_X_S_COL: ((nz,), np.int32),
                   BA_X_S: ((nz, 9, 9), np.float64), BA_X_BS: ((nc, 9), np.float64),
                   BA_X_DC: ((nc, 9), np.float64), BA_X_DP: ((np_, 3), np.float64),
-                  BA_X_ADJ_VC: ((nc, 9), np.float64), BA_X_ADJ_VP: ((np_, 3), np.float64)}
+                  BA_X_ADJ_VC: ((nc, 9), np.float64), BA_X_ADJ_VP: ((np_, 3), np.float64),
+                  BA_X_PRECOND: ((nc, 9, 9), np.float64)}
         shape, dt = shapes[field]
         return ba_export(self.h, field, np.zeros(shape, dt))
+
+
+# ---- learned preconditioner: graphs and training --------------------------------
+
+def gnn_num_params() -> int:
+    return int(lib().ba_gnn_num_params())
+
+
+class Graph:
+    """Network inputs of one reduced camera system (built from a problem
+    created with precond=BA_PRECOND_LEARNED after a step) plus training
+    activations, in a torch-owned device workspace."""
+
+    def __init__(self, problem: Problem, stream=None):
+        import torch
+        self.torch = torch
+        h = C.c_void_p()
+        _check(lib().ba_graph_create(problem.h, C.byref(h)))
+        self.h = h.value
+        n = C.c_size_t()
+        _check(lib().ba_graph_workspace_bytes(self.h, C.byref(n)))
+        self.workspace = torch.empty(n.value, dtype=torch.uint8, device=problem.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(problem.device)
+        _check(lib().ba_graph_bind(self.h, self.workspace.data_ptr(), n.value, self.stream.cuda_stream))
+        self.build(problem)
+
+    def build(self, problem: Problem):
+        _check(lib().ba_graph_build(self.h, problem.h))
+
+    def loss_grad(self, params, grad) -> float:
+        """Adds d loss / d params to grad (device float32); returns the loss."""
+        loss = C.c_double()
+        self.stream.synchronize()
+        _check(lib().ba_gnn_loss_grad(self.h, params.data_ptr(), grad.data_ptr(), C.byref(loss)))
+        return loss.value
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h:
+            lib().ba_graph_destroy(h)
+            self.h = None
+
+
+def gnn_adam(params, grad, m, v, step: int, lr: float = 1e-3, beta1: float = 0.9,
+             beta2: float = 0.999, eps: float = 1e-8, stream=None):
+    import torch
+    st = stream if stream is not None else torch.cuda.current_stream(params.device)
+    _check(lib().ba_gnn_adam(params.numel(), params.data_ptr(), grad.data_ptr(), m.data_ptr(),
+                             v.data_ptr(), step, lr, beta1, beta2, eps, st.cuda_stream))
 
 
 # ---- differentiable layer ------------------------------------------------------

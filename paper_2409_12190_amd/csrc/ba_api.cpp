@@ -7,11 +7,24 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "ba.h"
 #include "ba_adjoint.h"
 #include "ba_internal.h"
 #include "ba_kernels.h"
+#include "ba_precond.h"
+
+// A training graph: the camera pattern (host) and its device view.
+struct ba_graph {
+  int nc = 0;
+  int64_t nnzb = 0;
+  std::vector<int32_t> nbr_ptr, nbr, rev;
+  size_t ws_needed = 0;
+  bool bound = false;
+  hipStream_t stream = nullptr;
+  ba::GraphDev dev{};
+};
 
 namespace {
 
@@ -123,6 +136,20 @@ void carve(ba_problem* p, char* base, size_t* total) {
     b.adj_dev = c.take<ba::DevScalars>(1);
     b.adj_info = c.take<ba_step_info>(1);
   }
+  if (p->opt.precond == BA_PRECOND_LEARNED) {
+    const size_t ns = P.nbr.size();
+    b.pcLinv = c.take<double>(81 * nc);
+    b.pcMinvL = c.take<double>(81 * nc);
+    b.pc_params = c.take<float>(ba::GNN_NPARAM);
+    b.nbr_ptr = c.take<int32_t>(nc + 1);
+    b.nbr = c.take<int32_t>(ns);
+    b.nbr_blk = c.take<int32_t>(ns);
+    b.nbr_rev = c.take<int32_t>(ns);
+    b.gX = c.take<float>(nc * ba::GNN_F);
+    b.gE = c.take<float>(nc * 45);
+    b.gw = c.take<float>(ns);
+    b.gact = c.take<float>((2 * (ba::GNN_L + 1) + ba::GNN_L) * nc * ba::GNN_H);
+  }
   *total = c.off + 256;
 }
 
@@ -174,6 +201,39 @@ void collect_phase_times(ba_problem* p) {
     HIPCHK(call);                \
   } while (0)
 
+// Graph view of the learned preconditioner's buffers inside a problem
+// (inference only: no gradient buffers).
+ba::GraphDev problem_graph(const ba_problem* p) {
+  const ba::Buffers& b = p->b;
+  ba::GraphDev g{};
+  g.nc = p->plan.nc;
+  g.ns = (int)p->plan.nbr.size();
+  g.nbr_ptr = b.nbr_ptr;
+  g.nbr = b.nbr;
+  g.rev = b.nbr_rev;
+  g.X = b.gX;
+  g.E = b.gE;
+  g.w = b.gw;
+  const size_t blk = (size_t)g.nc * ba::GNN_H;
+  float* a = b.gact;
+  for (int l = 0; l <= ba::GNN_L; ++l) {
+    g.Z[l] = a;
+    a += blk;
+    g.H[l] = a;
+    a += blk;
+  }
+  for (int l = 0; l < ba::GNN_L; ++l) {
+    g.M[l] = a;
+    a += blk;
+  }
+  return g;
+}
+
+// Clears the PCG grid-barrier counters (a second PCG launch in one step).
+hipError_t reset_sync(ba_problem* p) {
+  return hipMemsetAsync(p->b.gsync, 0, sizeof(ba::GridSync), p->stream);
+}
+
 template <typename T>
 ba_status lm_step_impl(ba_problem* p, ba_step_info* out) {
   using namespace ba;
@@ -200,12 +260,41 @@ ba_status lm_step_impl(ba_problem* p, ba_step_info* out) {
   SchurArgs sa{b.slot_blk, b.slot_pb, b.slot_pe, b.slot_lead, b.pair_x, b.pair_y, b.blk_row,
                b.S_ptr, b.J, b.Q, b.w, b.S, b.Sdiag};
   PHASE(5, launch_schur_pairs<T>(sa, P.n_schur_wg, s));
-  CamFinishArgs cf{b.Sdiag, b.diagU, p->opt.diag_min, p->opt.diag_max, b.Minv, b.dev};
+  CamFinishArgs cf{b.Sdiag, b.diagU, p->opt.diag_min, p->opt.diag_max, b.Minv, b.dev, b.pcLinv};
   PHASE(6, launch_camera_finish<T>(cf, P.nc, s));
+  p->have_system = true;
+  const bool learned = p->opt.precond == BA_PRECOND_LEARNED && p->gnn_ready;
+  int32_t precond_used = 0;
+  if (learned) {
+    PcFeatureArgs fa{P.nc, b.nbr_ptr, b.nbr, b.nbr_blk, b.blk_row, b.S_col, b.S, b.pcLinv,
+                     b.gX, b.gE, b.gw};
+    const GraphDev gd = problem_graph(p);
+    auto infer = [&]() -> hipError_t {
+      hipError_t e = launch_pc_features<T>(fa, s);
+      if (e == hipSuccess) e = launch_gnn_forward(gd, b.pc_params, s);
+      if (e == hipSuccess) e = launch_gnn_output(gd, b.pc_params, b.pcLinv, b.pcMinvL, false, s);
+      return e;
+    };
+    PHASE(12, infer());
+    precond_used = 1;
+  }
   PcgArgs pa{P.nc, p->cg_maxiter, p->cg_rtol, b.S_ptr, b.T_ptr, b.pcg_row, b.item_ptr, b.item_e,
-             b.item_code, b.ucol_ptr, b.ucol, b.S, b.Sdiag, b.Minv, b.bS, b.x, b.zring, b.partA,
-             b.partB, b.dinfo, b.gsync, &b.dev->error};
-  PHASE(7, launch_pcg<T>(pa, P.pcg_grid, P.pcg_resident, p->opt.cg_variant == BA_CG_PIPELINED, s));
+             b.item_code, b.ucol_ptr, b.ucol, b.S, b.Sdiag, learned ? b.pcMinvL : b.Minv, b.bS, b.x,
+             b.zring, b.partA, b.partB, b.dinfo, b.gsync, &b.dev->error};
+  const bool pipe = p->opt.cg_variant == BA_CG_PIPELINED;
+  PHASE(7, launch_pcg<T>(pa, P.pcg_grid, P.pcg_resident, pipe, s));
+  if (learned && p->cg_rtol > 0.0) {
+    // the unpreconditioned residual judges the learned blocks: when the PCG
+    // missed its tolerance the step is solved again with block-Jacobi
+    HIPCHK(hipMemcpyAsync(p->hinfo, b.dinfo, sizeof(ba_step_info), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (!(p->hinfo->cg_rel_resid <= p->cg_rtol)) {
+      pa.Minv = b.Minv;
+      HIPCHK(reset_sync(p));
+      PHASE(7, launch_pcg<T>(pa, P.pcg_grid, P.pcg_resident, pipe, s));
+      precond_used = 2;
+    }
+  }
   BackArgs ba_{b.chunk_ptr, b.chunk_pt, b.pt_ptr, b.o_cam, b.o_pt, b.J, b.w, b.x, b.gp, b.Vinv,
                b.pts[cur], b.dp, b.pts[nxt], b.part_pred};
   PHASE(8, launch_backsub<T>(ba_, nchunk, s));
@@ -223,6 +312,7 @@ ba_status lm_step_impl(ba_problem* p, ba_step_info* out) {
   collect_phase_times(p);
 
   ba_step_info info = *p->hinfo;
+  info.precond_used = precond_used;
   const int32_t err = p->hscal->error;
   if (err != 0 || !std::isfinite(info.cost_before)) {
     // leave theta and lambda as they were
@@ -254,6 +344,32 @@ ba_status lm_step_impl(ba_problem* p, ba_step_info* out) {
   return BA_OK;
 }
 
+void graph_carve(ba_graph* g, char* base, size_t* total) {
+  Carver c{base};
+  const size_t nc = g->nc, ns = g->nbr.size(), blk = nc * ba::GNN_H;
+  ba::GraphDev& d = g->dev;
+  d.nc = g->nc;
+  d.ns = (int)ns;
+  d.nbr_ptr = c.take<int32_t>(nc + 1);
+  d.nbr = c.take<int32_t>(ns);
+  d.rev = c.take<int32_t>(ns);
+  d.X = c.take<float>(nc * ba::GNN_F);
+  d.E = c.take<float>(nc * 45);
+  d.w = c.take<float>(ns);
+  for (int l = 0; l <= ba::GNN_L; ++l) {
+    d.Z[l] = c.take<float>(blk);
+    d.H[l] = c.take<float>(blk);
+  }
+  for (int l = 0; l < ba::GNN_L; ++l) d.M[l] = c.take<float>(blk);
+  d.dO = c.take<float>(nc * ba::GNN_O);
+  d.dH = c.take<float>(blk);
+  d.dZ = c.take<float>(blk);
+  d.dM = c.take<float>(blk);
+  d.loss_part = c.take<double>(nc);
+  d.loss = c.take<double>(1);
+  *total = c.off + 256;
+}
+
 }  // namespace
 
 extern "C" {
@@ -273,6 +389,7 @@ void ba_default_options(ba_options* o) {
   o->cg_variant = BA_CG_PIPELINED;
   o->enable_backward = 0;
   o->adjoint_rtol = 1e-10;
+  o->precond = BA_PRECOND_BLOCK_JACOBI;
 }
 
 const char* ba_last_error(void) { return g_err.c_str(); }
@@ -293,6 +410,8 @@ ba_status ba_problem_create(const ba_options* opt, int32_t n_cams, int32_t n_pts
   if (!(o.lambda0 > 0.0) || !(o.lambda_min > 0.0) || !(o.lambda_max >= o.lambda_min))
     return fail(BA_EINVAL, "bad damping options");
   if (!(o.diag_min > 0.0) || !(o.diag_max >= o.diag_min)) return fail(BA_EINVAL, "bad clamp range");
+  if (o.precond != BA_PRECOND_BLOCK_JACOBI && o.precond != BA_PRECOND_LEARNED)
+    return fail(BA_EINVAL, "unknown preconditioner");
   ba_problem* p = new (std::nothrow) ba_problem();
   if (!p) return fail(BA_EINVAL, "out of host memory");
   p->opt = o;
@@ -368,6 +487,12 @@ ba_status ba_problem_bind(ba_problem* p, void* ws, size_t bytes, void* stream) {
   HIPCHK(upload(b.ucol_ptr, P.ucol_ptr, s));
   HIPCHK(upload(b.ucol, P.ucol, s));
   HIPCHK(upload(b.o_orig, P.o_orig, s));
+  if (p->opt.precond == BA_PRECOND_LEARNED) {
+    HIPCHK(upload(b.nbr_ptr, P.nbr_ptr, s));
+    HIPCHK(upload(b.nbr, P.nbr, s));
+    HIPCHK(upload(b.nbr_blk, P.nbr_blk, s));
+    HIPCHK(upload(b.nbr_rev, P.nbr_rev, s));
+  }
   HIPCHK(hipMemsetAsync(b.fixed, 0, P.nc, s));
   HIPCHK(hipMemsetAsync(b.gsync, 0, sizeof(ba::GridSync), s));
   HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&p->hinfo), sizeof(ba_step_info), hipHostMallocDefault));
@@ -542,7 +667,7 @@ ba_status ba_backward(ba_problem* p, const double* dL_dcams, const double* dL_dp
                   b.S_ptr, b.adjA, b.adjY, b.adjU, b.adjS, b.Sdiag};
   HIPCHK(launch_adj_schur(sa, P.n_schur_wg, s));
   // block-Jacobi factors of the undamped blocks (lambda = 0 in adj_dev)
-  CamFinishArgs cf{b.Sdiag, b.diagU, p->opt.diag_min, p->opt.diag_max, b.Minv, b.adj_dev};
+  CamFinishArgs cf{b.Sdiag, b.diagU, p->opt.diag_min, p->opt.diag_max, b.Minv, b.adj_dev, nullptr};
   HIPCHK(launch_camera_finish<double>(cf, P.nc, s));
   PcgArgs ga{P.nc, p->opt.cg_maxiter, p->opt.adjoint_rtol, b.S_ptr, b.T_ptr, b.pcg_row, b.item_ptr,
              b.item_e, b.item_code, b.ucol_ptr, b.ucol, b.adjS, b.Sdiag, b.Minv, b.bS, b.adj_vc,
@@ -565,6 +690,24 @@ ba_status ba_backward(ba_problem* p, const double* dL_dcams, const double* dL_dp
   out.status = st;
   if (info) *info = out;
   return st;
+}
+
+int64_t ba_gnn_num_params(void) { return ba::GNN_NPARAM; }
+
+ba_status ba_set_gnn_params(ba_problem* p, const float* params) {
+  if (!p) return fail(BA_EINVAL, "null problem");
+  if (p->opt.precond != BA_PRECOND_LEARNED)
+    return fail(BA_ESTATE, "create the problem with precond = BA_PRECOND_LEARNED");
+  if (!p->bound) return fail(BA_ESTATE, "problem is not bound");
+  if (!params) {
+    p->gnn_ready = false;
+    return BA_OK;
+  }
+  HIPCHK(hipMemcpyAsync(p->b.pc_params, params, sizeof(float) * ba::GNN_NPARAM,
+                        hipMemcpyDeviceToDevice, p->stream));
+  HIPCHK(hipStreamSynchronize(p->stream));
+  p->gnn_ready = true;
+  return BA_OK;
 }
 
 ba_status ba_get_state(const ba_problem* p, void* blob, size_t* bytes) {
@@ -680,6 +823,13 @@ ba_status ba_export(const ba_problem* p, int32_t field, void* dst, size_t bytes)
       HIPCHK(hipStreamSynchronize(p->stream));
       return BA_OK;
     }
+    case BA_X_PRECOND: {
+      if (!need(nc * 81 * sizeof(double))) return fail(BA_EINVAL, "size mismatch");
+      const bool learned = p->opt.precond == BA_PRECOND_LEARNED && p->gnn_ready;
+      HIPCHK(hipMemcpyAsync(dst, learned ? b.pcMinvL : b.Minv, bytes, hipMemcpyDeviceToHost, p->stream));
+      HIPCHK(hipStreamSynchronize(p->stream));
+      return BA_OK;
+    }
     case BA_X_ADJ_VC:
     case BA_X_ADJ_VP: {
       if (!p->opt.enable_backward) return fail(BA_ESTATE, "backward buffers are not enabled");
@@ -751,6 +901,85 @@ ba_status ba_get_phase_times(const ba_problem* p, double* ms, int64_t* n_out, in
   }
   return BA_OK;
 }
+
+ba_status ba_graph_create(const ba_problem* p, ba_graph** out) {
+  if (!p || !out) return fail(BA_EINVAL, "null argument");
+  *out = nullptr;
+  if (p->opt.precond != BA_PRECOND_LEARNED)
+    return fail(BA_ESTATE, "the problem was not created with BA_PRECOND_LEARNED");
+  ba_graph* g = new (std::nothrow) ba_graph();
+  if (!g) return fail(BA_EINVAL, "out of host memory");
+  g->nc = p->plan.nc;
+  g->nnzb = p->plan.nnzb;
+  g->nbr_ptr = p->plan.nbr_ptr;
+  g->nbr = p->plan.nbr;
+  g->rev = p->plan.nbr_rev;
+  graph_carve(g, nullptr, &g->ws_needed);
+  *out = g;
+  return BA_OK;
+}
+
+ba_status ba_graph_workspace_bytes(const ba_graph* g, size_t* bytes) {
+  if (!g || !bytes) return fail(BA_EINVAL, "null argument");
+  *bytes = g->ws_needed;
+  return BA_OK;
+}
+
+ba_status ba_graph_bind(ba_graph* g, void* ws, size_t bytes, void* stream) {
+  if (!g || !ws) return fail(BA_EINVAL, "null argument");
+  if (g->bound) return fail(BA_ESTATE, "graph already bound");
+  if (bytes < g->ws_needed) return fail(BA_EINVAL, "workspace too small");
+  if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(BA_EINVAL, "workspace not 256-byte aligned");
+  g->stream = reinterpret_cast<hipStream_t>(stream);
+  size_t total = 0;
+  graph_carve(g, reinterpret_cast<char*>(ws), &total);
+  HIPCHK(upload(const_cast<int32_t*>(g->dev.nbr_ptr), g->nbr_ptr, g->stream));
+  HIPCHK(upload(const_cast<int32_t*>(g->dev.nbr), g->nbr, g->stream));
+  HIPCHK(upload(const_cast<int32_t*>(g->dev.rev), g->rev, g->stream));
+  HIPCHK(hipStreamSynchronize(g->stream));
+  g->bound = true;
+  return BA_OK;
+}
+
+ba_status ba_graph_build(ba_graph* g, ba_problem* p) {
+  if (!g || !p) return fail(BA_EINVAL, "null argument");
+  if (!g->bound) return fail(BA_ESTATE, "graph is not bound");
+  if (p->opt.precond != BA_PRECOND_LEARNED || !p->bound)
+    return fail(BA_ESTATE, "the problem is not bound with BA_PRECOND_LEARNED");
+  if (p->plan.nc != g->nc || p->plan.nnzb != g->nnzb || p->plan.nbr != g->nbr)
+    return fail(BA_EINVAL, "the graph was created for another camera pattern");
+  if (!p->have_system) return fail(BA_ESTATE, "run ba_lm_step first (no reduced system yet)");
+  const ba::Buffers& b = p->b;
+  ba::PcFeatureArgs fa{g->nc, b.nbr_ptr, b.nbr, b.nbr_blk, b.blk_row, b.S_col, b.S, b.pcLinv,
+                       g->dev.X, g->dev.E, g->dev.w};
+  HIPCHK(p->opt.precision == BA_MIXED ? ba::launch_pc_features<float>(fa, p->stream)
+                                      : ba::launch_pc_features<double>(fa, p->stream));
+  HIPCHK(hipStreamSynchronize(p->stream));
+  return BA_OK;
+}
+
+ba_status ba_gnn_loss_grad(ba_graph* g, const float* params, float* grad, double* loss) {
+  if (!g || !params || !grad) return fail(BA_EINVAL, "null argument");
+  if (!g->bound) return fail(BA_ESTATE, "graph is not bound");
+  HIPCHK(ba::launch_gnn_forward(g->dev, params, g->stream));
+  HIPCHK(ba::launch_gnn_output(g->dev, params, nullptr, nullptr, true, g->stream));
+  HIPCHK(ba::launch_gnn_backward(g->dev, params, grad, g->stream));
+  double h = 0.0;
+  HIPCHK(hipMemcpyAsync(&h, g->dev.loss, sizeof(double), hipMemcpyDeviceToHost, g->stream));
+  HIPCHK(hipStreamSynchronize(g->stream));
+  if (loss) *loss = h;
+  return BA_OK;
+}
+
+ba_status ba_gnn_adam(int64_t n, float* params, const float* grad, float* m, float* v, int32_t step,
+                      float lr, float beta1, float beta2, float eps, void* stream) {
+  if (!params || !grad || !m || !v || n <= 0 || step < 1) return fail(BA_EINVAL, "bad argument");
+  HIPCHK(ba::launch_gnn_adam(n, params, grad, m, v, step, lr, beta1, beta2, eps,
+                             reinterpret_cast<hipStream_t>(stream)));
+  return BA_OK;
+}
+
+void ba_graph_destroy(ba_graph* g) { delete g; }
 
 void ba_problem_destroy(ba_problem* p) {
   if (!p) return;

@@ -60,6 +60,10 @@ struct Plan {
   // code (local column | flags), and the distinct block columns it reads.
   // pcg_resident: every lane group has at most PCG_IPG items.
   std::vector<int32_t> pcg_row, item_ptr, item_e, item_code, ucol_ptr, ucol;
+  // camera co-visibility graph (both directions of every off-diagonal block):
+  // neighbours of camera i are nbr[nbr_ptr[i] .. nbr_ptr[i+1]), through block
+  // nbr_blk; nbr_rev is the slot of the same block in the neighbour's list
+  std::vector<int32_t> nbr_ptr, nbr, nbr_blk, nbr_rev;
   int32_t max_ucol = 0, pcg_grid = 0;
   bool pcg_resident = false;
   int64_t nnzb = 0, n_pairs = 0;
@@ -133,6 +137,12 @@ struct Buffers {
   double *adj_gt, *adj_vc, *adj_vp;  // tangent loss gradient, adjoint vector
   DevScalars* adj_dev;         // lambda = 0 and the adjoint's error flags
   ba_step_info* adj_info;
+  // learned preconditioner (only with BA_PRECOND_LEARNED)
+  double *pcLinv, *pcMinvL;    // [nc][81] inverse Cholesky factors, learned blocks
+  float* pc_params;            // network parameters
+  int32_t *nbr_ptr, *nbr, *nbr_blk, *nbr_rev;
+  float *gX, *gE, *gw;         // network inputs
+  float* gact;                 // activations (inference)
 };
 
 }  // namespace ba
@@ -160,6 +170,8 @@ struct ba_problem {
   int64_t phase_n[BA_NUM_PHASES] = {};
   bool phase_used[BA_NUM_PHASES] = {};
   bool adj_grid_ok = false;  // the FP64 standard PCG fits the plan's grid
+  bool gnn_ready = false;    // learned preconditioner parameters are set
+  bool have_system = false;  // a step has formed the reduced system
   ba_step_info* hinfo = nullptr;     // pinned host staging
   ba::DevScalars* hscal = nullptr;   // pinned host staging
 };

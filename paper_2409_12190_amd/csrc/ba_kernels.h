@@ -58,6 +58,7 @@ struct CamFinishArgs {
   double dmin, dmax;
   double* Minv;
   DevScalars* dev;
+  double* Linv;   // optional: inverse Cholesky factors (lower, [nc][81])
 };
 
 struct PcgArgs {

@@ -406,6 +406,8 @@ __global__ __launch_bounds__(64) void k_camera_finish(CamFinishArgs a) {
         Li[k * 9 + i2] = -s / L[k * 9 + k];
       }
     }
+    if (a.Linv)
+      for (int q = 0; q < 81; ++q) a.Linv[81 * (size_t)cam + q] = Li[q];
     double* Mi = a.Minv + 81 * (size_t)cam;
     for (int r = 0; r < 9; ++r)
       for (int cc = 0; cc < 9; ++cc) {

@@ -234,6 +234,37 @@ std::string build_plan(int32_t nc, int32_t np, int64_t no, const int32_t* cidx, 
       }
   }
 
+  // camera co-visibility graph: for row i the off-diagonal upper blocks of
+  // row i, then the blocks (a, i), a < i; rev[s] is the slot of the same
+  // block seen from the other camera
+  {
+    p.nbr_ptr.assign(nc + 1, 0);
+    for (int32_t i = 0; i < nc; ++i)
+      p.nbr_ptr[i + 1] = p.nbr_ptr[i] + (p.S_ptr[i + 1] - p.S_ptr[i] - 1) + (p.T_ptr[i + 1] - p.T_ptr[i]);
+    const int32_t ns = p.nbr_ptr[nc];
+    p.nbr.resize(ns);
+    p.nbr_blk.resize(ns);
+    p.nbr_rev.resize(ns);
+    std::vector<int32_t> up_slot(p.nnzb, -1), lo_slot(p.nnzb, -1);
+    for (int32_t i = 0; i < nc; ++i) {
+      int32_t s = p.nbr_ptr[i];
+      for (int32_t e = p.S_ptr[i] + 1; e < p.S_ptr[i + 1]; ++e, ++s) {
+        p.nbr[s] = p.S_col[e];
+        p.nbr_blk[s] = e;
+        up_slot[e] = s;
+      }
+      for (int32_t t = p.T_ptr[i]; t < p.T_ptr[i + 1]; ++t, ++s) {
+        p.nbr[s] = p.T_src[t];
+        p.nbr_blk[s] = p.T_blk[t];
+        lo_slot[p.T_blk[t]] = s;
+      }
+    }
+    for (int32_t s = 0; s < ns; ++s) {
+      const int32_t e = p.nbr_blk[s];
+      p.nbr_rev[s] = up_slot[e] == s ? lo_slot[e] : up_slot[e];
+    }
+  }
+
   // PCG workgroups: contiguous row ranges.  First try ranges of at most
   // PCG_IPG * PCG_GROUPS items (block values register-resident); if that
   // needs more than PCG_MAX_GRID workgroups, split the items evenly over

@@ -1,0 +1,384 @@
+// gfx950 kernels of the learned correction of the block-Jacobi
+// preconditioner of the reduced camera system.
+//
+// The paper preconditions its PCG with a diagonal (block) preconditioner
+// (Sec. IV-C-2).  Here each 9x9 block of block-Jacobi is corrected from the
+// camera co-visibility graph of the system:
+//   S_ii = L_i L_i^T, S^_ij = L_i^-1 S_ij L_j^-T, E_i = sum_j S^_ij S^_ij^T,
+//   a_ij = |S^_ij|_F, w_ij = a_ij / sum_j a_ij;
+//   x_i = [upper(E_i), log(1 + tr E_i), log(1 + deg_i)]
+//   h0 = relu(W_in x + b_in); three layers h = relu(W_s h + W_m (sum_j w_ij h_j) + b)
+//   o = W_out h + b_out, C_i = strict lower(o) + diag(exp(o_diag)),
+//   M_i = L_i^-T C_i C_i^T L_i^-1  (o = 0: block-Jacobi).
+// Training loss of a system: (1/n) sum_i tr(Mh G Mh) - 2 tr(Mh) + 9 with
+// Mh = C C^T, G = I + E (the squared Frobenius distance of the normalised
+// preconditioned operator to I, block row by block row).
+//
+// All network arithmetic is FP32; every reduction runs in a fixed order
+// (no atomics), so training is bitwise reproducible.
+#include "ba_precond.h"
+
+namespace ba {
+
+namespace {
+
+__device__ __forceinline__ int up9(int r, int c) { return r * 9 - (r * (r - 1)) / 2 + (c - r); }
+__device__ __forceinline__ int lo9(int r, int c) { return (r * (r + 1)) / 2 + c; }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// graph features of camera i (one workgroup of 64 per camera).  Each slot's
+// normalised block is evaluated in the orientation of the stored upper block,
+// T = Linv_row S_e Linv_col^T, by the same code from both endpoints, so the
+// two endpoints see bit-identical weights.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(64) void k_pc_features(PcFeatureArgs a) {
+  __shared__ double red[47];
+  const int i = blockIdx.x, lane = threadIdx.x;
+  const int s0 = a.nbr_ptr[i], s1 = a.nbr_ptr[i + 1];
+  const T* __restrict__ Sv = reinterpret_cast<const T*>(a.S);
+  double e[45];
+  for (int q = 0; q < 45; ++q) e[q] = 0.0;
+  double asum = 0.0;
+  for (int s = s0 + lane; s < s1; s += 64) {
+    const int blk = a.nbr_blk[s];
+    const int ra = a.blk_row[blk], cb = a.S_col[blk];
+    const double* La = a.Linv + 81 * (size_t)ra;
+    const double* Lb = a.Linv + 81 * (size_t)cb;
+    const T* B = Sv + 81 * (size_t)blk;
+    double P[9][9];  // Linv_row S_e
+    for (int r = 0; r < 9; ++r)
+      for (int c = 0; c < 9; ++c) {
+        double v = 0.0;
+        for (int k = 0; k <= r; ++k) v += La[9 * r + k] * (double)B[9 * k + c];
+        P[r][c] = v;
+      }
+    double Tm[9][9];  // (Linv_row S_e) Linv_col^T
+    double fro = 0.0;
+    for (int r = 0; r < 9; ++r)
+      for (int c = 0; c < 9; ++c) {
+        double v = 0.0;
+        for (int k = 0; k <= c; ++k) v += P[r][k] * Lb[9 * c + k];
+        Tm[r][c] = v;
+        fro += v * v;
+      }
+    const bool up = (ra == i);
+    // S^_ij = T (upper slot) or T^T (lower slot); E_i += S^ S^^T
+    for (int r = 0; r < 9; ++r)
+      for (int c = r; c < 9; ++c) {
+        double v = 0.0;
+        if (up)
+          for (int k = 0; k < 9; ++k) v += Tm[r][k] * Tm[c][k];
+        else
+          for (int k = 0; k < 9; ++k) v += Tm[k][r] * Tm[k][c];
+        e[up9(r, c)] += v;
+      }
+    const double aw = sqrt(fro);
+    a.w[s] = (float)aw;  // normalised below
+    asum += aw;
+  }
+  for (int q = 0; q < 45; ++q) {
+    double v = e[q];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if (lane == 0) red[q] = v;
+  }
+  for (int o = 32; o > 0; o >>= 1) asum += __shfl_xor(asum, o, 64);
+  __syncthreads();
+  double tr = 0.0;
+  for (int r = 0; r < 9; ++r) tr += red[up9(r, r)];
+  if (lane < 45) {
+    a.E[45 * (size_t)i + lane] = (float)red[lane];
+    a.X[GNN_F * (size_t)i + lane] = (float)red[lane];
+  } else if (lane == 45) {
+    a.X[GNN_F * (size_t)i + 45] = (float)log1p(tr);
+  } else if (lane == 46) {
+    a.X[GNN_F * (size_t)i + 46] = (float)log1p((double)(s1 - s0));
+  }
+  // weights: a_ij / sum_j a_ij, recomputed in the same order by the same lane
+  for (int s = s0 + lane; s < s1; s += 64) a.w[s] = asum > 0.0 ? (float)((double)a.w[s] / asum) : 0.0f;
+}
+
+// ---------------------------------------------------------------------------
+// dense layer: Z[n][o] = b[o] + sum_k X[n][k] W1[o][k] + sum_k M[n][k] W2[o][k],
+// H = relu(Z); four rows x 64 outputs per workgroup
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_gnn_dense(int n, const float* __restrict__ X, int K1,
+                                                    const float* __restrict__ M, int K2,
+                                                    const float* __restrict__ W1,
+                                                    const float* __restrict__ W2,
+                                                    const float* __restrict__ b, int nout,
+                                                    float* __restrict__ Z, float* __restrict__ H) {
+  const int o = threadIdx.x & 63;
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= n || o >= nout) return;
+  float z = b[o];
+  const float* x = X + (size_t)row * K1;
+  const float* w1 = W1 + (size_t)o * K1;
+  for (int k = 0; k < K1; ++k) z = fmaf(x[k], w1[k], z);
+  if (M) {
+    const float* m = M + (size_t)row * K2;
+    const float* w2 = W2 + (size_t)o * K2;
+    for (int k = 0; k < K2; ++k) z = fmaf(m[k], w2[k], z);
+  }
+  Z[(size_t)row * nout + o] = z;
+  if (H) H[(size_t)row * nout + o] = fmaxf(z, 0.0f);
+}
+
+// weighted mean of the neighbours' hidden states: M_i = sum_s w_s H_nbr(s)
+__global__ __launch_bounds__(256) void k_gnn_aggregate(int n, const int32_t* __restrict__ nbr_ptr,
+                                                        const int32_t* __restrict__ nbr,
+                                                        const float* __restrict__ w,
+                                                        const float* __restrict__ H,
+                                                        float* __restrict__ M) {
+  const int f = threadIdx.x & 63;
+  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (i >= n) return;
+  float m = 0.0f;
+  for (int s = nbr_ptr[i]; s < nbr_ptr[i + 1]; ++s) m = fmaf(w[s], H[(size_t)nbr[s] * GNN_H + f], m);
+  M[(size_t)i * GNN_H + f] = m;
+}
+
+// transpose of the aggregation: dH_j += sum_s w_rev(s) dM_nbr(s)
+__global__ __launch_bounds__(256) void k_gnn_aggregate_t(int n, const int32_t* __restrict__ nbr_ptr,
+                                                          const int32_t* __restrict__ nbr,
+                                                          const int32_t* __restrict__ rev,
+                                                          const float* __restrict__ w,
+                                                          const float* __restrict__ dM,
+                                                          float* __restrict__ dH) {
+  const int f = threadIdx.x & 63;
+  const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (j >= n) return;
+  float acc = dH[(size_t)j * GNN_H + f];
+  for (int s = nbr_ptr[j]; s < nbr_ptr[j + 1]; ++s)
+    acc = fmaf(w[rev[s]], dM[(size_t)nbr[s] * GNN_H + f], acc);
+  dH[(size_t)j * GNN_H + f] = acc;
+}
+
+// ---------------------------------------------------------------------------
+// output layer, loss and its gradient with respect to the outputs, or the
+// preconditioner blocks (one workgroup of 64 per camera)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(64) void k_gnn_output(GraphDev g, const float* __restrict__ P,
+                                                    const double* __restrict__ Linv,
+                                                    double* __restrict__ Minv, int with_loss) {
+  __shared__ float o[45];
+  __shared__ float C[81], Mh[81], Gm[81], Q[81], Gam[81];
+  __shared__ double red[64];
+  const int i = blockIdx.x, t = threadIdx.x;
+  const float* h = g.H[GNN_L] + (size_t)i * GNN_H;
+  if (t < GNN_O) {
+    float v = P[GNN_OFF_BOUT + t];
+    const float* wr = P + GNN_OFF_WOUT + (size_t)t * GNN_H;
+    for (int k = 0; k < GNN_H; ++k) v = fmaf(wr[k], h[k], v);
+    o[t] = v;
+  }
+  __syncthreads();
+  for (int q = t; q < 81; q += 64) {
+    const int r = q / 9, c = q - 9 * r;
+    C[q] = c > r ? 0.0f : (c == r ? expf(o[lo9(r, r)]) : o[lo9(r, c)]);
+  }
+  __syncthreads();
+  for (int q = t; q < 81; q += 64) {  // Mh = C C^T
+    const int r = q / 9, c = q - 9 * r;
+    float v = 0.0f;
+    for (int k = 0; k < 9; ++k) v = fmaf(C[9 * r + k], C[9 * c + k], v);
+    Mh[q] = v;
+  }
+  __syncthreads();
+  if (Minv) {  // M_i = Linv^T Mh Linv in FP64
+    const double* Li = Linv + 81 * (size_t)i;
+    for (int q = t; q < 81; q += 64) {
+      const int r = q / 9, c = q - 9 * r;
+      double v = 0.0;
+      for (int k = 0; k < 9; ++k)
+        for (int l = 0; l < 9; ++l) v += Li[9 * k + r] * (double)Mh[9 * k + l] * Li[9 * l + c];
+      Minv[81 * (size_t)i + q] = v;
+    }
+  }
+  if (!with_loss) return;
+  const float* E = g.E + 45 * (size_t)i;
+  for (int q = t; q < 81; q += 64) {
+    const int r = q / 9, c = q - 9 * r;
+    Gm[q] = E[r <= c ? up9(r, c) : up9(c, r)] + (r == c ? 1.0f : 0.0f);
+  }
+  __syncthreads();
+  double part = 0.0;
+  for (int q = t; q < 81; q += 64) {  // Q = Mh G, loss terms tr(Q Mh) and tr(Mh)
+    const int r = q / 9, c = q - 9 * r;
+    float v = 0.0f;
+    for (int k = 0; k < 9; ++k) v = fmaf(Mh[9 * r + k], Gm[9 * k + c], v);
+    Q[q] = v;
+    part += (double)v * (double)Mh[9 * c + r] - (r == c ? 2.0 * (double)Mh[q] : 0.0);
+  }
+  red[t] = part;
+  __syncthreads();
+  if (t == 0) {
+    double s = 9.0;
+    for (int k = 0; k < 64; ++k) s += red[k];
+    g.loss_part[i] = s / g.nc;
+  }
+  const float inv_n = 1.0f / (float)g.nc;
+  for (int q = t; q < 81; q += 64) {  // Gam = (G Mh + Mh G - 2 I) / n = (Q^T + Q - 2 I) / n
+    const int r = q / 9, c = q - 9 * r;
+    Gam[q] = (Q[9 * c + r] + Q[q] - (r == c ? 2.0f : 0.0f)) * inv_n;
+  }
+  __syncthreads();
+  if (t < GNN_O) {  // dC = 2 Gam C on the lower triangle; chain through exp on the diagonal
+    int r = 0;
+    while (lo9(r + 1, 0) <= t) ++r;
+    const int c = t - lo9(r, 0);
+    float v = 0.0f;
+    for (int k = 0; k < 9; ++k) v = fmaf(Gam[9 * r + k], C[9 * k + c], v);
+    v *= 2.0f;
+    if (r == c) v *= C[9 * r + r];
+    g.dO[(size_t)i * GNN_O + t] = v;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_sum_loss(const double* __restrict__ part, int n,
+                                                  double* __restrict__ out) {
+  __shared__ double red[256];
+  double s = 0.0;
+  for (int k = threadIdx.x; k < n; k += 256) s += part[k];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double tot = 0.0;
+    for (int k = 0; k < 256; ++k) tot += red[k];
+    *out = tot;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// backward of a dense layer Z = X W^T (+ b):
+//   dW[o][k] += sum_n dZ[n][o] X[n][k], db[o] += sum_n dZ[n][o] (one thread
+//   per weight, rows in order), and dX[n][k] = sum_o dZ[n][o] W[o][k]
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_gnn_dW(int n, int nout, int K, const float* __restrict__ dZ,
+                                                 const float* __restrict__ X, float* __restrict__ dW,
+                                                 float* __restrict__ db) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx < nout * K) {
+    const int o = idx / K, k = idx - K * (idx / K);
+    float s = 0.0f;
+    for (int r = 0; r < n; ++r) s = fmaf(dZ[(size_t)r * nout + o], X[(size_t)r * K + k], s);
+    dW[idx] += s;
+  } else if (db && idx < nout * K + nout) {
+    const int o = idx - nout * K;
+    float s = 0.0f;
+    for (int r = 0; r < n; ++r) s += dZ[(size_t)r * nout + o];
+    db[o] += s;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_gnn_dX(int n, int nout, int K, const float* __restrict__ dZ,
+                                                 const float* __restrict__ W, float* __restrict__ dX,
+                                                 const float* __restrict__ Zmask) {
+  const int k = threadIdx.x & 63;
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= n || k >= K) return;
+  float s = 0.0f;
+  for (int o = 0; o < nout; ++o) s = fmaf(dZ[(size_t)row * nout + o], W[(size_t)o * K + k], s);
+  // with Zmask: the result is the gradient of the pre-activation of a relu layer
+  if (Zmask && !(Zmask[(size_t)row * K + k] > 0.0f)) s = 0.0f;
+  dX[(size_t)row * K + k] = s;
+}
+
+__global__ __launch_bounds__(256) void k_gnn_relu_mask(int n, const float* __restrict__ Z,
+                                                       float* __restrict__ d) {
+  const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (q < (int64_t)n * GNN_H && !(Z[q] > 0.0f)) d[q] = 0.0f;
+}
+
+__global__ __launch_bounds__(256) void k_gnn_adam(int64_t n, float* __restrict__ p,
+                                                  const float* __restrict__ g, float* __restrict__ m,
+                                                  float* __restrict__ v, float lr, float b1, float b2,
+                                                  float eps, float c1, float c2) {
+  const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (q >= n) return;
+  const float gq = g[q];
+  const float mq = b1 * m[q] + (1.0f - b1) * gq;
+  const float vq = b2 * v[q] + (1.0f - b2) * gq * gq;
+  m[q] = mq;
+  v[q] = vq;
+  p[q] -= lr * (mq / c1) / (sqrtf(vq / c2) + eps);
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+
+template <typename T>
+hipError_t launch_pc_features(const PcFeatureArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_pc_features<T>, dim3(a.nc), dim3(64), 0, s, a);
+  return hipGetLastError();
+}
+template hipError_t launch_pc_features<float>(const PcFeatureArgs&, hipStream_t);
+template hipError_t launch_pc_features<double>(const PcFeatureArgs&, hipStream_t);
+
+hipError_t launch_gnn_forward(const GraphDev& g, const float* P, hipStream_t s) {
+  const dim3 grid((g.nc + 3) / 4), blk(256);
+  hipLaunchKernelGGL(k_gnn_dense, grid, blk, 0, s, g.nc, g.X, GNN_F, (const float*)nullptr, 0,
+                     P + GNN_OFF_WIN, (const float*)nullptr, P + GNN_OFF_BIN, GNN_H, g.Z[0], g.H[0]);
+  for (int l = 0; l < GNN_L; ++l) {
+    const float* L0 = P + GNN_OFF_L0 + l * GNN_LAYER_SIZE;
+    hipLaunchKernelGGL(k_gnn_aggregate, grid, blk, 0, s, g.nc, g.nbr_ptr, g.nbr, g.w, g.H[l], g.M[l]);
+    hipLaunchKernelGGL(k_gnn_dense, grid, blk, 0, s, g.nc, g.H[l], GNN_H, g.M[l], GNN_H, L0,
+                       L0 + GNN_H * GNN_H, L0 + 2 * GNN_H * GNN_H, GNN_H, g.Z[l + 1], g.H[l + 1]);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_gnn_output(const GraphDev& g, const float* P, const double* Linv, double* Minv,
+                             bool with_loss, hipStream_t s) {
+  hipLaunchKernelGGL(k_gnn_output, dim3(g.nc), dim3(64), 0, s, g, P, Linv, Minv, with_loss ? 1 : 0);
+  if (with_loss) hipLaunchKernelGGL(k_sum_loss, dim3(1), dim3(256), 0, s, g.loss_part, g.nc, g.loss);
+  return hipGetLastError();
+}
+
+hipError_t launch_gnn_backward(const GraphDev& gin, const float* P, float* G, hipStream_t s) {
+  GraphDev g = gin;  // dZ / dH swap roles layer by layer
+  const int n = g.nc;
+  const dim3 rows((n + 3) / 4), blk(256);
+  auto wgrid = [](int nout, int K) { return dim3((nout * K + nout + 255) / 256); };
+  // output layer
+  hipLaunchKernelGGL(k_gnn_dW, wgrid(GNN_O, GNN_H), blk, 0, s, n, GNN_O, GNN_H, g.dO, g.H[GNN_L],
+                     G + GNN_OFF_WOUT, G + GNN_OFF_BOUT);
+  // dZ_L = (dO W_out) masked by relu of Z_L
+  hipLaunchKernelGGL(k_gnn_dX, rows, blk, 0, s, n, GNN_O, GNN_H, g.dO, P + GNN_OFF_WOUT, g.dZ,
+                     g.Z[GNN_L]);
+  for (int l = GNN_L - 1; l >= 0; --l) {
+    const int64_t off = GNN_OFF_L0 + l * GNN_LAYER_SIZE;
+    hipLaunchKernelGGL(k_gnn_dW, wgrid(GNN_H, GNN_H), blk, 0, s, n, GNN_H, GNN_H, g.dZ, g.H[l],
+                       G + off, G + off + 2 * GNN_H * GNN_H);
+    hipLaunchKernelGGL(k_gnn_dW, dim3((GNN_H * GNN_H + 255) / 256), blk, 0, s, n, GNN_H, GNN_H,
+                       g.dZ, g.M[l], G + off + GNN_H * GNN_H, (float*)nullptr);
+    // dM = dZ W_m, dH_l = dZ W_s + aggregation^T(dM), then the relu mask of Z_l
+    hipLaunchKernelGGL(k_gnn_dX, rows, blk, 0, s, n, GNN_H, GNN_H, g.dZ, P + off + GNN_H * GNN_H,
+                       g.dM, (const float*)nullptr);
+    hipLaunchKernelGGL(k_gnn_dX, rows, blk, 0, s, n, GNN_H, GNN_H, g.dZ, P + off, g.dH,
+                       (const float*)nullptr);
+    hipLaunchKernelGGL(k_gnn_aggregate_t, rows, blk, 0, s, n, g.nbr_ptr, g.nbr, g.rev, g.w, g.dM, g.dH);
+    hipLaunchKernelGGL(k_gnn_relu_mask, dim3((unsigned)(((int64_t)n * GNN_H + 255) / 256)), blk, 0, s,
+                       n, g.Z[l], g.dH);
+    // the masked dH_l is the next dZ
+    float* tmp = g.dZ;
+    g.dZ = g.dH;
+    g.dH = tmp;
+  }
+  hipLaunchKernelGGL(k_gnn_dW, wgrid(GNN_H, GNN_F), blk, 0, s, n, GNN_H, GNN_F, g.dZ, g.X,
+                     G + GNN_OFF_WIN, G + GNN_OFF_BIN);
+  return hipGetLastError();
+}
+
+hipError_t launch_gnn_adam(int64_t n, float* p, const float* g, float* m, float* v, int step, float lr,
+                           float b1, float b2, float eps, hipStream_t s) {
+  const float c1 = 1.0f - powf(b1, (float)step), c2 = 1.0f - powf(b2, (float)step);
+  hipLaunchKernelGGL(k_gnn_adam, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, p, g, m, v, lr,
+                     b1, b2, eps, c1, c2);
+  return hipGetLastError();
+}
+
+}  // namespace ba

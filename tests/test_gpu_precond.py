@@ -1,0 +1,139 @@
+"""GPU learned block-Jacobi correction (through the C ABI) against the
+oracle's network, and a small training run on the scene stream.
+
+Inputs: the seeded scene generator; expected values: the oracle only (its
+network, loss and gradient are pinned in test_oracle_precond.py).  The GPU
+network computes in FP32, the oracle in FP64: bounds below are relative.
+"""
+import numpy as np
+import pytest
+
+from oracle import precond_oracle as G
+from synth.scenes import make_scene
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2409_12190_amd import ba as B  # noqa: E402
+from paper_2409_12190_amd import precond_train as PT  # noqa: E402
+
+
+def problem(s, precision=B.BA_FP64, **kw):
+    print(f"[gpu] precond scene nc={s.n_cams} np={s.n_pts} no={s.n_obs} precision={precision}",
+          flush=True)
+    kw.setdefault("cg_maxiter", 1000)
+    return B.Problem.from_scene(s, precision=precision, precond=B.BA_PRECOND_LEARNED, **kw)
+
+
+def random_params(seed, out_scale=0.05):
+    rng = np.random.default_rng(seed)
+    theta = G.init_params(rng)
+    d = G.unpack(theta)
+    d["W_out"][:] = rng.normal(size=d["W_out"].shape) * out_scale
+    d["b_out"][:] = rng.normal(size=d["b_out"].shape) * out_scale
+    return G.pack(d)
+
+
+def oracle_graph(p, nc):
+    return G.system_graph(p.export(B.BA_X_S_PTR), p.export(B.BA_X_S_COL), p.export(B.BA_X_S), nc)
+
+
+@pytest.mark.parametrize("precision", [B.BA_FP64, B.BA_MIXED])
+def test_loss_and_gradient_match_oracle(precision):
+    s = make_scene(1, n_cams=40, n_pts=1500, seed=2)
+    p = problem(s, precision)
+    gr = PT.training_graph(p)
+    g = oracle_graph(p, s.n_cams)
+    theta = random_params(3)
+    pt = torch.tensor(theta, dtype=torch.float32, device="cuda")
+    grad = torch.zeros_like(pt)
+    loss = gr.loss_grad(pt, grad)
+    lo = G.loss(theta, g)
+    go = G.grad(theta, g)
+    print(f"  loss gpu {loss:.8f} oracle {lo:.8f}", flush=True)
+    assert abs(loss - lo) <= 1e-4 * abs(lo)
+    gg = grad.cpu().numpy().astype(np.float64)
+    assert np.linalg.norm(gg - go) <= 1e-3 * np.linalg.norm(go)
+    # gradients add up over calls
+    gr.loss_grad(pt, grad)
+    assert np.allclose(grad.cpu().numpy(), 2 * gg, rtol=1e-6, atol=1e-12)
+
+
+def test_learned_blocks_match_oracle():
+    s = make_scene(1, n_cams=40, n_pts=1500, seed=2)
+    a = problem(s)
+    a.lm_step()                                     # plain block-Jacobi: the reference system
+    g = oracle_graph(a, s.n_cams)
+    theta = random_params(4)
+    b = problem(s)                                  # same scene, same first system
+    b.set_gnn_params(torch.tensor(theta, dtype=torch.float32, device="cuda"))
+    info = b.lm_step()
+    assert info["precond_used"] in (1, 2)
+    Mg = b.export(B.BA_X_PRECOND)
+    Mo = G.precond_blocks(theta, g)
+    assert np.linalg.norm(Mg - Mo) <= 1e-5 * np.linalg.norm(Mo)
+
+
+def test_zero_output_layer_is_block_jacobi():
+    s = make_scene(3, n_cams=40, n_pts=2500)
+    a = problem(s, cg_variant=B.BA_CG_STANDARD)
+    b = problem(s, cg_variant=B.BA_CG_STANDARD)
+    b.set_gnn_params(PT.init_params(0))
+    for _ in range(3):
+        ia, ib = a.lm_step(), b.lm_step()
+        assert ib["precond_used"] == 1
+        assert ia["cg_iters"] == ib["cg_iters"]
+        assert abs(ia["cost_after"] - ib["cost_after"]) <= 1e-9 * ia["cost_after"]
+    Ma = a.export(B.BA_X_PRECOND)
+    Mb = b.export(B.BA_X_PRECOND)
+    assert np.abs(Ma - Mb).max() <= 1e-12 * np.abs(Ma).max()
+
+
+def test_bad_learned_blocks_fall_back_to_block_jacobi():
+    """A deliberately poor network (large random factors) misses the PCG
+    tolerance within the iteration cap; the step is then solved again with
+    block-Jacobi and matches a plain block-Jacobi run."""
+    s = make_scene(1, n_cams=60, n_pts=3000, seed=5)
+    a = problem(s, cg_maxiter=40, cg_variant=B.BA_CG_STANDARD)
+    b = problem(s, cg_maxiter=40, cg_variant=B.BA_CG_STANDARD)
+    b.set_gnn_params(torch.tensor(random_params(6, out_scale=3.0), dtype=torch.float32, device="cuda"))
+    ia, ib = a.lm_step(), b.lm_step()
+    print(f"  plain cg {ia['cg_iters']} learned-then-fallback cg {ib['cg_iters']} used {ib['precond_used']}",
+          flush=True)
+    if ib["precond_used"] == 2:
+        assert ib["cg_iters"] == ia["cg_iters"]
+        assert ib["cost_after"] == ia["cost_after"]
+    else:
+        assert ib["cg_rel_resid"] <= 1e-4
+
+
+def test_training_on_the_stream_lowers_the_loss_and_cg_iterations():
+    """Twelve small stream scenes (200-260 cameras, 6,000 points): train on
+    eight systems, evaluate on four held-out ones.  The held-out loss must
+    fall well below block-Jacobi's; the PCG iteration counts to 1e-6 are
+    reported and must not exceed block-Jacobi's on average."""
+    tr, te = [], []
+    for k in range(12):
+        s, p = PT.stream_problem(1000 + k, precision=B.BA_MIXED, n_cams=200 + 5 * k, n_pts=6000)
+        (tr if k < 8 else te).append((s, p))
+    graphs = [PT.training_graph(p) for _, p in tr]
+    test_graphs = [PT.training_graph(p) for _, p in te]
+    params = PT.init_params(0)
+    l0 = PT.mean_loss(test_graphs, params)
+    hist = PT.train(graphs, params, epochs=80, lr=2e-3, log=print)
+    l1 = PT.mean_loss(test_graphs, params)
+    print(f"  held-out loss {l0:.5f} -> {l1:.5f}; training {hist[0]:.5f} -> {hist[-1]:.5f}", flush=True)
+    assert hist[-1] < 0.8 * hist[0]
+    assert l1 < 0.8 * l0
+    its = []
+    for s, p in te:
+        it_bj, ms_bj, _ = PT.solve_first_step(s, p, None)
+        it_l, ms_l, used = PT.solve_first_step(s, p, params)
+        print(f"  held-out nc={s.n_cams}: cg block-Jacobi {it_bj} ({ms_bj:.2f} ms) "
+              f"learned {it_l} ({ms_l:.2f} ms) used {used}", flush=True)
+        its.append((it_bj, it_l))
+    its = np.array(its, dtype=float)
+    assert its[:, 1].mean() <= its[:, 0].mean()
