@@ -141,6 +141,7 @@ void carve(ba_problem* p, char* base, size_t* total) {
     b.pcLinv = c.take<double>(81 * nc);
     b.pcMinvL = c.take<double>(81 * nc);
     b.pc_params = c.take<float>(ba::GNN_NPARAM);
+    b.pc_wbf16 = c.take<short>(ba::GNN_NBF16);
     b.nbr_ptr = c.take<int32_t>(nc + 1);
     b.nbr = c.take<int32_t>(ns);
     b.nbr_blk = c.take<int32_t>(ns);
@@ -271,7 +272,7 @@ ba_status lm_step_impl(ba_problem* p, ba_step_info* out) {
     const GraphDev gd = problem_graph(p);
     auto infer = [&]() -> hipError_t {
       hipError_t e = launch_pc_features<T>(fa, s);
-      if (e == hipSuccess) e = launch_gnn_forward(gd, b.pc_params, s);
+      if (e == hipSuccess) e = launch_gnn_forward_bf16(gd, b.pc_params, b.pc_wbf16, s);
       if (e == hipSuccess) e = launch_gnn_output(gd, b.pc_params, b.pcLinv, b.pcMinvL, false, s);
       return e;
     };
@@ -705,6 +706,7 @@ ba_status ba_set_gnn_params(ba_problem* p, const float* params) {
   }
   HIPCHK(hipMemcpyAsync(p->b.pc_params, params, sizeof(float) * ba::GNN_NPARAM,
                         hipMemcpyDeviceToDevice, p->stream));
+  HIPCHK(ba::launch_gnn_weights_bf16(p->b.pc_params, p->b.pc_wbf16, p->stream));
   HIPCHK(hipStreamSynchronize(p->stream));
   p->gnn_ready = true;
   return BA_OK;

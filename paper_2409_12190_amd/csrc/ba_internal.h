@@ -140,6 +140,7 @@ struct Buffers {
   // learned preconditioner (only with BA_PRECOND_LEARNED)
   double *pcLinv, *pcMinvL;    // [nc][81] inverse Cholesky factors, learned blocks
   float* pc_params;            // network parameters
+  short* pc_wbf16;             // BF16 copies of the input and message-layer weights
   int32_t *nbr_ptr, *nbr, *nbr_blk, *nbr_rev;
   float *gX, *gE, *gw;         // network inputs
   float* gact;                 // activations (inference)

@@ -25,6 +25,10 @@ constexpr int64_t GNN_LAYER_SIZE = 2 * GNN_H * GNN_H + GNN_H;
 constexpr int64_t GNN_OFF_WOUT = GNN_OFF_L0 + GNN_L * GNN_LAYER_SIZE;
 constexpr int64_t GNN_OFF_BOUT = GNN_OFF_WOUT + GNN_O * GNN_H;
 constexpr int64_t GNN_NPARAM = GNN_OFF_BOUT + GNN_O;
+// BF16 copies of the input and message-layer weights, rows padded to K
+constexpr int GNN_KIN = 48;             // 47 inputs -> 3 k-steps of 16
+constexpr int GNN_KHID = 2 * GNN_H;     // [W_s | W_m]
+constexpr int64_t GNN_NBF16 = GNN_H * GNN_KIN + GNN_L * GNN_H * GNN_KHID;
 
 // Device view of one camera graph and its activations.
 struct GraphDev {
@@ -46,6 +50,9 @@ struct PcFeatureArgs {
 
 template <typename T> hipError_t launch_pc_features(const PcFeatureArgs&, hipStream_t);
 hipError_t launch_gnn_forward(const GraphDev&, const float* params, hipStream_t);
+// inference: BF16 matrix-core layers (weights converted once per parameter set)
+hipError_t launch_gnn_weights_bf16(const float* params, short* Wb, hipStream_t);
+hipError_t launch_gnn_forward_bf16(const GraphDev&, const float* params, const short* Wb, hipStream_t);
 // loss, d loss / d outputs (training) or the preconditioner blocks
 // M_i = Linv_i^T C_i C_i^T Linv_i (inference, Minv != nullptr)
 hipError_t launch_gnn_output(const GraphDev&, const float* params, const double* Linv, double* Minv,

@@ -307,8 +307,105 @@ __global__ __launch_bounds__(256) void k_gnn_adam(int64_t n, float* __restrict__
 }
 
 // ---------------------------------------------------------------------------
+// inference in BF16 on the matrix cores, FP32 accumulate: the same dense
+// layers as k_gnn_dense with inputs and weights rounded to bfloat16.
+// ---------------------------------------------------------------------------
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ short to_bf16(float f) {  // round to nearest even
+  uint32_t u = __float_as_uint(f);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (short)(u >> 16);
+}
+
+// weights of the input and message layers as BF16 rows padded to K:
+// [W_in | 0] (64 x 48), then per layer [W_s | W_m] (64 x 128)
+__global__ __launch_bounds__(256) void k_gnn_weights_bf16(const float* __restrict__ P,
+                                                          short* __restrict__ Wb) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  const int n_in = GNN_H * GNN_KIN;
+  if (q < n_in) {
+    const int o = q / GNN_KIN, k = q - GNN_KIN * (q / GNN_KIN);
+    Wb[q] = k < GNN_F ? to_bf16(P[GNN_OFF_WIN + o * GNN_F + k]) : (short)0;
+    return;
+  }
+  const int r = q - n_in;
+  if (r >= GNN_L * GNN_H * GNN_KHID) return;
+  const int l = r / (GNN_H * GNN_KHID), rr = r - l * (GNN_H * GNN_KHID);
+  const int o = rr / GNN_KHID, k = rr - GNN_KHID * (rr / GNN_KHID);
+  const float* L0 = P + GNN_OFF_L0 + l * GNN_LAYER_SIZE;
+  Wb[q] = to_bf16(k < GNN_H ? L0[o * GNN_H + k] : L0[GNN_H * GNN_H + o * GNN_H + (k - GNN_H)]);
+}
+
+// Z = [X | M] W^T + b, H = relu(Z); one wave per 16 rows, four 16x16 output
+// tiles, v_mfma_f32_16x16x16_bf16 (lane l: A row l%16, k 4(l/16)..+3; B
+// column l%16, same k; D rows 4(l/16)..+3 of column l%16)
+__global__ __launch_bounds__(256) void k_gnn_dense_bf16(int n, const float* __restrict__ X, int K1,
+                                                         const float* __restrict__ M,
+                                                         const short* __restrict__ Wb, int Kp,
+                                                         const float* __restrict__ b,
+                                                         float* __restrict__ Z, float* __restrict__ H) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r0 = (blockIdx.x * 4 + wave) * 16;
+  if (r0 >= n) return;
+  const int row = r0 + (lane & 15), kq = 4 * (lane >> 4);
+  f32x4 acc[4];
+  for (int t = 0; t < 4; ++t) acc[t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+  for (int kb = 0; kb < Kp; kb += 16) {
+    bf16x4 av;
+    for (int j = 0; j < 4; ++j) {
+      const int k = kb + kq + j;
+      float v = 0.0f;
+      if (row < n) {
+        if (k < K1) v = X[(size_t)row * K1 + k];
+        else if (M && k < K1 + GNN_H) v = M[(size_t)row * GNN_H + (k - K1)];
+      }
+      av[j] = to_bf16(v);
+    }
+    for (int t = 0; t < 4; ++t) {
+      const short* w = Wb + (size_t)(16 * t + (lane & 15)) * Kp + kb + kq;
+      const bf16x4 bv = {w[0], w[1], w[2], w[3]};
+      acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc[t], 0, 0, 0);
+    }
+  }
+  for (int t = 0; t < 4; ++t) {
+    const int col = 16 * t + (lane & 15);
+    for (int j = 0; j < 4; ++j) {
+      const int r = r0 + kq + j;
+      if (r < n) {
+        const float z = acc[t][j] + b[col];
+        Z[(size_t)r * GNN_H + col] = z;
+        H[(size_t)r * GNN_H + col] = fmaxf(z, 0.0f);
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
+
+hipError_t launch_gnn_weights_bf16(const float* P, short* Wb, hipStream_t s) {
+  const int n = GNN_H * GNN_KIN + GNN_L * GNN_H * GNN_KHID;
+  hipLaunchKernelGGL(k_gnn_weights_bf16, dim3((n + 255) / 256), dim3(256), 0, s, P, Wb);
+  return hipGetLastError();
+}
+
+hipError_t launch_gnn_forward_bf16(const GraphDev& g, const float* P, const short* Wb, hipStream_t s) {
+  const dim3 grid((g.nc + 63) / 64), blk(256);
+  hipLaunchKernelGGL(k_gnn_dense_bf16, grid, blk, 0, s, g.nc, g.X, GNN_F, (const float*)nullptr, Wb,
+                     GNN_KIN, P + GNN_OFF_BIN, g.Z[0], g.H[0]);
+  const dim3 rows((g.nc + 3) / 4);
+  for (int l = 0; l < GNN_L; ++l) {
+    const short* Wl = Wb + GNN_H * GNN_KIN + (size_t)l * GNN_H * GNN_KHID;
+    const float* bl = P + GNN_OFF_L0 + l * GNN_LAYER_SIZE + 2 * GNN_H * GNN_H;
+    hipLaunchKernelGGL(k_gnn_aggregate, rows, blk, 0, s, g.nc, g.nbr_ptr, g.nbr, g.w, g.H[l], g.M[l]);
+    hipLaunchKernelGGL(k_gnn_dense_bf16, grid, blk, 0, s, g.nc, g.H[l], GNN_H, g.M[l], Wl, GNN_KHID, bl,
+                       g.Z[l + 1], g.H[l + 1]);
+  }
+  return hipGetLastError();
+}
 
 template <typename T>
 hipError_t launch_pc_features(const PcFeatureArgs& a, hipStream_t s) {

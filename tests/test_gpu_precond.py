@@ -74,7 +74,11 @@ def test_learned_blocks_match_oracle():
     assert info["precond_used"] in (1, 2)
     Mg = b.export(B.BA_X_PRECOND)
     Mo = G.precond_blocks(theta, g)
-    assert np.linalg.norm(Mg - Mo) <= 1e-5 * np.linalg.norm(Mo)
+    # the step's network runs its layers in BF16 (FP32 accumulate)
+    err = np.linalg.norm(Mg - Mo) / np.linalg.norm(Mo)
+    dev = np.linalg.norm(Mo - np.linalg.inv(g["diag"])) / np.linalg.norm(Mo)
+    print(f"  learned blocks rel. error {err:.2e} (correction size {dev:.2e})", flush=True)
+    assert err <= 2e-2 * dev
 
 
 def test_zero_output_layer_is_block_jacobi():
