@@ -117,6 +117,7 @@ void carve(ba_problem* p, char* base, size_t* total) {
   b.part_pred = c.take<double>(2 * nch);
   b.part_gmax = c.take<double>(nch);
   b.part_linc = c.take<double>((nc + 255) / 256);
+  b.part_stage = c.take<double>(4 * ba::FINAL_STAGE_MAX);
   const size_t slots = (size_t)p->opt.cg_maxiter + 2;
   b.zring = c.take<double>(slots * nc * ba::ZSTRIDE);
   b.partA = c.take<double>(slots * P.pcg_grid * ba::PART_STRIDE);
@@ -258,7 +259,7 @@ ba_status lm_step_impl(ba_problem* p, ba_step_info* out) {
   PHASE(3, launch_point_q<T>(qa, s));
   CamVecArgs cv{b.cam_ptr, b.cam_obs, b.o_pt, b.J, b.w, b.r, b.ep, b.gc, b.bS, b.diagU};
   PHASE(4, launch_camera_vec<T>(cv, P.nc, s));
-  SchurArgs sa{b.slot_blk, b.slot_pb, b.slot_pe, b.slot_lead, b.pair_x, b.pair_y, b.blk_row,
+  SchurArgs sa{P.n_schur_wg, b.slot_blk, b.slot_pb, b.slot_pe, b.slot_lead, b.pair_x, b.pair_y, b.blk_row,
                b.S_ptr, b.J, b.Q, b.w, b.S, b.Sdiag};
   PHASE(5, launch_schur_pairs<T>(sa, P.n_schur_wg, s));
   CamFinishArgs cf{b.Sdiag, b.diagU, p->opt.diag_min, p->opt.diag_max, b.Minv, b.dev, b.pcLinv};
@@ -305,7 +306,7 @@ ba_status lm_step_impl(ba_problem* p, ba_step_info* out) {
               p->opt.huber_delta, b.part_cost_new};
   PHASE(10, launch_candidate_cost(co, nchunk, s));
   FinalArgs fa{nchunk, p->cam_blocks, P.nc, b.part_cost_new, b.part_pred, b.part_linc, b.part_gmax,
-               b.gc, p->opt.lambda_min, p->opt.lambda_max, b.dev, b.dinfo};
+               b.gc, p->opt.lambda_min, p->opt.lambda_max, b.dev, b.dinfo, b.part_stage, 0};
   PHASE(11, launch_finalize(fa, s));
   HIPCHK(hipMemcpyAsync(p->hinfo, b.dinfo, sizeof(ba_step_info), hipMemcpyDeviceToHost, s));
   HIPCHK(hipMemcpyAsync(p->hscal, b.dev, sizeof(DevScalars), hipMemcpyDeviceToHost, s));

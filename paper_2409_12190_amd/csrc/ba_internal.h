@@ -32,6 +32,7 @@ constexpr int ITEM_DIAG = 1 << 17;    //   diagonal block (FP64, indexed by came
 constexpr int BARRIER_FANIN = 16;
 constexpr int MAX_BARRIER_GROUPS = 128;
 constexpr int MAX_TRACK = CHUNK;
+constexpr int FINAL_STAGE_MAX = 256;  // workgroups of the first acceptance-reduction stage
 
 // Host-side symbolic analysis of the observation pattern (computed once per
 // problem; the paper caches its sparse-product table the same way, Sec. IV-B-1).
@@ -125,7 +126,7 @@ struct Buffers {
   // step
   double *x, *dp;
   // partial sums
-  double *part_cost, *part_cost_new, *part_pred, *part_gmax, *part_linc;
+  double *part_cost, *part_cost_new, *part_pred, *part_gmax, *part_linc, *part_stage;
   double *zring, *partA, *partB;  // PCG exchange rings, one slot per iteration
   DevScalars* dev;
   ba_step_info* dinfo;

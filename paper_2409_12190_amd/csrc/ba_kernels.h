@@ -45,6 +45,7 @@ struct CamVecArgs {
 };
 
 struct SchurArgs {
+  int nwg;  // workgroups of the slot table
   const int32_t *slot_blk, *slot_pb, *slot_pe, *slot_lead, *pair_x, *pair_y, *blk_row, *S_ptr;
   const void *J, *Q;
   const double* w;
@@ -101,6 +102,8 @@ struct FinalArgs {
   double lambda_min, lambda_max;
   DevScalars* dev;
   ba_step_info* info;
+  double* stage;  // [4][FINAL_STAGE_MAX]: per-workgroup partials of the first stage
+  int nstage;     // workgroups of the first stage
 };
 
 struct ObsArgs {
@@ -124,7 +127,7 @@ hipError_t launch_pcg(const PcgArgs&, int grid, bool resident, bool pipelined, h
 template <typename T> hipError_t launch_backsub(const BackArgs&, int nchunk, hipStream_t);
 hipError_t launch_retract_cameras(const RetractArgs&, int nblk, hipStream_t);
 hipError_t launch_candidate_cost(const CostArgs&, int nchunk, hipStream_t);
-hipError_t launch_finalize(const FinalArgs&, hipStream_t);
+hipError_t launch_finalize(FinalArgs, hipStream_t);
 hipError_t launch_set_observations(const ObsArgs&, hipStream_t);
 
 }  // namespace ba

@@ -246,8 +246,10 @@ __global__ __launch_bounds__(CAM_THREADS) void k_camera_vec(CamVecArgs a) {
   double gcv[9], bsv[9], du[9];
 #pragma unroll
   for (int q = 0; q < 9; ++q) gcv[q] = bsv[q] = du[q] = 0.0;
+  int xn = lo + threadIdx.x < hi ? a.cam_obs[lo + threadIdx.x] : 0;
   for (int i = lo + threadIdx.x; i < hi; i += blockDim.x) {
-    const int x = a.cam_obs[i];
+    const int x = xn;
+    if (i + (int)blockDim.x < hi) xn = a.cam_obs[i + blockDim.x];
     double Jc[2][9], Jp[2][3];
     load_J(Jall + (size_t)x * NJ, Jc, Jp);
     const double w = a.w[x];
@@ -303,8 +305,14 @@ __global__ __launch_bounds__(CAM_THREADS) void k_camera_vec(CamVecArgs a) {
 template <typename T>
 __global__ __launch_bounds__(SCHUR_THREADS) void k_schur_pairs(SchurArgs a) {
   __shared__ double part[SCHUR_SLOTS][81];
+  // workgroups are dispatched round-robin over the 8 XCDs: XCD k takes the
+  // k-th contiguous range of slot workgroups, so that neighbouring rows (which
+  // read the same observations) share that XCD's L2
+  const int per = (a.nwg + 7) / 8;
+  const int lw = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
+  if (lw >= a.nwg) return;
   const int slot = threadIdx.x / 9, col = threadIdx.x - 9 * (threadIdx.x / 9);
-  const size_t sbase = (size_t)blockIdx.x * SCHUR_SLOTS;
+  const size_t sbase = (size_t)lw * SCHUR_SLOTS;
   const T* __restrict__ Jall = reinterpret_cast<const T*>(a.J);
   const T* __restrict__ Qall = reinterpret_cast<const T*>(a.Q);
   if (slot < SCHUR_SLOTS) {
@@ -314,8 +322,19 @@ __global__ __launch_bounds__(SCHUR_THREADS) void k_schur_pairs(SchurArgs a) {
     for (int r = 0; r < 9; ++r) acc[r] = 0.0;
     if (e >= 0) {
       const int pb = a.slot_pb[sbase + slot], pe = a.slot_pe[sbase + slot];
+      // the next pair's indices are fetched while this pair is processed
+      int xn = 0, yn = 0;
+      if (pb < pe) {
+        xn = a.pair_x[pb];
+        yn = a.pair_y[pb];
+      }
+#pragma unroll 2
       for (int i = pb; i < pe; ++i) {
-        const int x = a.pair_x[i], y = a.pair_y[i];
+        const int x = xn, y = yn;
+        if (i + 1 < pe) {
+          xn = a.pair_x[i + 1];
+          yn = a.pair_y[i + 1];
+        }
         const T* Jx = Jall + (size_t)x * NJ;
         const T* Jy = Jall + (size_t)y * NJ;
         const T* Qx = Qall + (size_t)x * 6;
@@ -1021,21 +1040,45 @@ __global__ __launch_bounds__(CHUNK) void k_candidate_cost(CostArgs a) {
   if (threadIdx.x == 0) a.part_cost_new[c] = s;
 }
 
-// acceptance and the trust-region damping update (one workgroup)
-__global__ __launch_bounds__(256) void k_finalize(FinalArgs a) {
+// acceptance reduction, first stage: workgroup w reduces a contiguous slice
+// of the chunk partials (candidate cost, the two predicted-reduction terms,
+// gradient max) and of gc (max |.|) into stage[q][w]; fixed order
+__global__ __launch_bounds__(256) void k_final_stage(FinalArgs a) {
   __shared__ double red[4];
-  const double Fn = block_sum_array(a.part_cost_new, a.nchunk, red);
-  double q = 0.0, lp = 0.0;
-  for (int i = threadIdx.x; i < a.nchunk; i += blockDim.x) {
+  const int w = blockIdx.x, G = gridDim.x;
+  const int lo = (int)((int64_t)a.nchunk * w / G), hi = (int)((int64_t)a.nchunk * (w + 1) / G);
+  double f = 0.0, q = 0.0, lp = 0.0, gm = 0.0;
+  for (int i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+    f += a.part_cost_new[i];
     q += a.part_pred[2 * (size_t)i];
     lp += a.part_pred[2 * (size_t)i + 1];
+    gm = fmax(gm, a.part_gmax[i]);
   }
+  const int n9 = 9 * a.nc;
+  const int glo = (int)((int64_t)n9 * w / G), ghi = (int)((int64_t)n9 * (w + 1) / G);
+  for (int i = glo + threadIdx.x; i < ghi; i += blockDim.x) gm = fmax(gm, fabs(a.gc[i]));
+  f = block_sum(f, red);
   q = block_sum(q, red);
   lp = block_sum(lp, red);
+  gm = block_max(gm, red);
+  if (threadIdx.x == 0) {
+    a.stage[w] = f;
+    a.stage[FINAL_STAGE_MAX + w] = q;
+    a.stage[2 * FINAL_STAGE_MAX + w] = lp;
+    a.stage[3 * FINAL_STAGE_MAX + w] = gm;
+  }
+}
+
+// acceptance and the trust-region damping update (one workgroup, from the
+// first stage's partials)
+__global__ __launch_bounds__(256) void k_finalize(FinalArgs a) {
+  __shared__ double red[4];
+  const double Fn = block_sum_array(a.stage, a.nstage, red);
+  const double q = block_sum_array(a.stage + FINAL_STAGE_MAX, a.nstage, red);
+  const double lp = block_sum_array(a.stage + 2 * FINAL_STAGE_MAX, a.nstage, red);
   const double lc = block_sum_array(a.part_linc, a.ncamblk, red);
   double gm = 0.0;
-  for (int i = threadIdx.x; i < a.nchunk; i += blockDim.x) gm = fmax(gm, a.part_gmax[i]);
-  for (int i = threadIdx.x; i < 9 * a.nc; i += blockDim.x) gm = fmax(gm, fabs(a.gc[i]));
+  for (int i = threadIdx.x; i < a.nstage; i += blockDim.x) gm = fmax(gm, a.stage[3 * FINAL_STAGE_MAX + i]);
   gm = block_max(gm, red);
   if (threadIdx.x == 0) {
     DevScalars* dev = a.dev;
@@ -1116,7 +1159,8 @@ template hipError_t launch_camera_vec<double>(const CamVecArgs&, int, hipStream_
 
 template <typename T>
 hipError_t launch_schur_pairs(const SchurArgs& a, int nwg, hipStream_t s) {
-  hipLaunchKernelGGL(k_schur_pairs<T>, dim3(nwg), dim3(SCHUR_THREADS), 0, s, a);
+  const int per = (nwg + 7) / 8;
+  hipLaunchKernelGGL(k_schur_pairs<T>, dim3(8 * per), dim3(SCHUR_THREADS), 0, s, a);
   return hipGetLastError();
 }
 template hipError_t launch_schur_pairs<float>(const SchurArgs&, int, hipStream_t);
@@ -1179,7 +1223,12 @@ hipError_t launch_candidate_cost(const CostArgs& a, int nchunk, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_finalize(const FinalArgs& a, hipStream_t s) {
+hipError_t launch_finalize(FinalArgs a, hipStream_t s) {
+  int g = (a.nchunk + 1023) / 1024;
+  if (g < 1) g = 1;
+  if (g > FINAL_STAGE_MAX) g = FINAL_STAGE_MAX;
+  a.nstage = g;
+  hipLaunchKernelGGL(k_final_stage, dim3(g), dim3(256), 0, s, a);
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, a);
   return hipGetLastError();
 }

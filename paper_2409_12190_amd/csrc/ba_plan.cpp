@@ -183,7 +183,8 @@ std::string build_plan(int32_t nc, int32_t np, int64_t no, const int32_t* cidx, 
   }
   // chunks: a block of P pairs gets min(SCHUR_SLOTS, ceil(P / SCHUR_CHUNK))
   // chunks (at least one); blocks are packed into workgroups of SCHUR_SLOTS
-  // slots, largest first, next-fit
+  // slots next-fit in block order, so that a workgroup works on the blocks of
+  // one or a few consecutive rows (shared observation data stays in cache)
   {
     std::vector<int32_t> nch(p.nnzb);
     std::vector<int32_t> order(p.nnzb);
@@ -192,7 +193,6 @@ std::string build_plan(int32_t nc, int32_t np, int64_t no, const int32_t* cidx, 
       nch[e] = std::max(1, std::min(SCHUR_SLOTS, (P + SCHUR_CHUNK - 1) / SCHUR_CHUNK));
       order[e] = (int32_t)e;
     }
-    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return nch[a] > nch[b]; });
     p.slot_blk.clear();
     int32_t used = SCHUR_SLOTS;
     for (int32_t e : order) {
