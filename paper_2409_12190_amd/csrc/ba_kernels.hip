@@ -524,6 +524,46 @@ __device__ __forceinline__ bool grid_barrier(GridSync* gs, int* error) {
   return failed == 0;
 }
 
+// The pipelined PCG synchronises through the dot-product records themselves:
+// before the first barrier every workgroup fills its records of all
+// iteration slots with a NaN pattern that arithmetic never produces; in
+// iteration i a workgroup publishes its three partials only after its m
+// columns have reached memory, and the readers poll the records until no
+// word holds the pattern.  One memory round trip replaces the barrier's
+// atomics and the separate read of the partials.  Bounded like the
+// barrier: on timeout the sticky error flag is raised.
+constexpr unsigned long long PCG_PENDING = 0x7FF4DEADBEEF0000ull;
+
+__device__ __forceinline__ void clear_record(double* p) {
+  __hip_atomic_store(reinterpret_cast<unsigned long long*>(p), PCG_PENDING, __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Thread t < G waits for workgroup t's three partials of slot `rec`; returns
+// false on timeout (error flag raised).
+__device__ __forceinline__ bool poll_record(const double* rec, double& v0, double& v1, double& v2,
+                                            int* error) {
+  const unsigned long long* r = reinterpret_cast<const unsigned long long*>(rec);
+  long spins = 0;
+  while (true) {
+    const unsigned long long a0 = __hip_atomic_load(r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned long long a1 = __hip_atomic_load(r + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned long long a2 = __hip_atomic_load(r + 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (a0 != PCG_PENDING && a1 != PCG_PENDING && a2 != PCG_PENDING) {
+      v0 = __longlong_as_double((long long)a0);
+      v1 = __longlong_as_double((long long)a1);
+      v2 = __longlong_as_double((long long)a2);
+      return true;
+    }
+    if (++spins > BARRIER_SPIN_LIMIT ||
+        (__hip_atomic_load(error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & ERR_BARRIER)) {
+      atomicOr(error, (int)ERR_BARRIER);
+      return false;
+    }
+    __builtin_amdgcn_s_sleep(1);
+  }
+}
+
 // Block values of a lane group's items (row `comp` of each block, or column
 // `comp` of a transposed upper block), with the item's LDS column slot and
 // local row.
@@ -842,12 +882,16 @@ __global__ __launch_bounds__(PCG_THREADS) void k_pcg_pipelined(PcgArgs a) {
   }
   s_bb = block_sum(s_bb, red);
   if (tid == 0) publish(a.partB + (size_t)B * PART_STRIDE, s_bb);
+  // this workgroup's dot-product records of every iteration slot: pending
+  for (int q = tid; q < 3 * (a.maxiter + 1); q += nt)
+    clear_record(a.partA + (size_t)(q / 3) * pstride + (size_t)B * PART_STRIDE + (q - 3 * (q / 3)));
   bool ok = grid_barrier(a.gs, a.error);
   pcg_fetch_z(a, a.zring, ub, nuc, zl);
   double t0 = 0.0;
   for (int i = tid; i < G; i += nt) t0 += a.partB[(size_t)i * PART_STRIDE];
   const double bnorm = sqrt(block_sum(t0, red));
   pcg_spmv<T, RES>(a, ib, i0, i1, nr, L, rptr, it, zl, seg, ws);
+  __shared__ int poll_failed;
   double rnorm = bnorm, gamma_old = 1.0, alpha_old = 1.0;
   int iters = 0, breakdown = 0;
   for (int i = 0; ok && bnorm > 0.0 && i <= a.maxiter; ++i) {
@@ -874,6 +918,9 @@ __global__ __launch_bounds__(PCG_THREADS) void k_pcg_pipelined(PcgArgs a) {
       red3[tid >> 6][1] = s_d;
       red3[tid >> 6][2] = s_r;
     }
+    // the m columns must have reached memory before the partials are seen
+    __builtin_amdgcn_s_waitcnt(0);
+    if (tid == 0) poll_failed = 0;
     __syncthreads();
     double* pa = a.partA + (size_t)i * pstride;
     if (tid < 3) {
@@ -881,16 +928,15 @@ __global__ __launch_bounds__(PCG_THREADS) void k_pcg_pipelined(PcgArgs a) {
       for (int w2 = 0; w2 < PCG_THREADS / 64; ++w2) v += red3[w2][tid];
       publish(pa + (size_t)B * PART_STRIDE + tid, v);
     }
-    ok = grid_barrier(a.gs, a.error);
-    if (!ok) break;
-    // the partials and the m columns arrive in the same memory round trip
-    pcg_fetch_z(a, zk, ub, nuc, zl);
     double tg = 0.0, td = 0.0, tr = 0.0;
-    for (int w2 = tid; w2 < G; w2 += nt) {
-      tg += pa[(size_t)w2 * PART_STRIDE];
-      td += pa[(size_t)w2 * PART_STRIDE + 1];
-      tr += pa[(size_t)w2 * PART_STRIDE + 2];
+    if (tid < G && !poll_record(pa + (size_t)tid * PART_STRIDE, tg, td, tr, a.error)) poll_failed = 1;
+    __syncthreads();
+    if (poll_failed) {
+      ok = false;
+      break;
     }
+    // every workgroup's m columns are in memory now
+    pcg_fetch_z(a, zk, ub, nuc, zl);
     const double gamma = block_sum(tg, red);
     const double delta = block_sum(td, red);
     const double rr = block_sum(tr, red);
