@@ -46,10 +46,10 @@ def kernel_bytes(name, scene, nnzb, n_pairs, es, cg_iters):
         return np_ * (48 + 24 + 48 + 24)
     if name == "point_q":      # point index, Jp, w in; Q out; Vinv per point
         return no * (4 + 6 * es + 8 + 6 * es) + np_ * 48
-    if name == "camera_vec":   # indices, J, w, r in; ep per point; gc, bS, diagU out
-        return no * (4 + 4 + 24 * es + 8 + 16) + np_ * 24 + nc * 216
-    if name == "schur_pairs":  # pair table; J, Q, w per observation; S blocks out
-        return n_pairs * 8 + no * (24 * es + 6 * es + 8) + nnz_off * 81 * es + nc * 648
+    if name == "schur_pairs":  # pair table; J, Q, w, r per observation; ep per point;
+        # S blocks and the camera vectors (gc, bS, diag U) out
+        return (n_pairs * 8 + no * (24 * es + 6 * es + 8 + 16 + 4) + np_ * 24
+                + nnz_off * 81 * es + nc * (648 + 216))
     if name == "camera_finish":  # diagonal blocks and diagU in; damped blocks, inverses out
         return nc * (648 + 72 + 648 + 648)
     if name == "pcg":          # per CG iteration: S (upper blocks, symmetric diagonal),

@@ -257,12 +257,12 @@ ba_status lm_step_impl(ba_problem* p, ba_step_info* out) {
   PHASE(2, launch_damp_points(da, s));
   PointQArgs qa{P.no, b.o_pt, b.J, b.w, b.Vinv, b.Q};
   PHASE(3, launch_point_q<T>(qa, s));
-  CamVecArgs cv{b.cam_ptr, b.cam_obs, b.o_pt, b.J, b.w, b.r, b.ep, b.gc, b.bS, b.diagU};
-  PHASE(4, launch_camera_vec<T>(cv, P.nc, s));
+  // the camera vectors (gradient, right-hand side term, diag U) come from
+  // the self pairs of the Schur kernel's diagonal blocks
   SchurArgs sa{P.n_schur_wg, b.slot_blk, b.slot_pb, b.slot_pe, b.slot_lead, b.pair_x, b.pair_y, b.blk_row,
-               b.S_ptr, b.J, b.Q, b.w, b.S, b.Sdiag};
+               b.S_ptr, b.J, b.Q, b.w, b.S, b.Sdiag, b.o_pt, b.r, b.ep, b.gc, b.bS, b.diagU};
   PHASE(5, launch_schur_pairs<T>(sa, P.n_schur_wg, s));
-  CamFinishArgs cf{b.Sdiag, b.diagU, p->opt.diag_min, p->opt.diag_max, b.Minv, b.dev, b.pcLinv};
+  CamFinishArgs cf{b.Sdiag, b.diagU, p->opt.diag_min, p->opt.diag_max, b.Minv, b.dev, b.pcLinv, b.gc, b.bS};
   PHASE(6, launch_camera_finish<T>(cf, P.nc, s));
   p->have_system = true;
   const bool learned = p->opt.precond == BA_PRECOND_LEARNED && p->gnn_ready;
@@ -669,7 +669,8 @@ ba_status ba_backward(ba_problem* p, const double* dL_dcams, const double* dL_dp
                   b.S_ptr, b.adjA, b.adjY, b.adjU, b.adjS, b.Sdiag};
   HIPCHK(launch_adj_schur(sa, P.n_schur_wg, s));
   // block-Jacobi factors of the undamped blocks (lambda = 0 in adj_dev)
-  CamFinishArgs cf{b.Sdiag, b.diagU, p->opt.diag_min, p->opt.diag_max, b.Minv, b.adj_dev, nullptr};
+  CamFinishArgs cf{b.Sdiag, b.diagU, p->opt.diag_min, p->opt.diag_max, b.Minv, b.adj_dev, nullptr,
+                   nullptr, nullptr};
   HIPCHK(launch_camera_finish<double>(cf, P.nc, s));
   PcgArgs ga{P.nc, p->opt.cg_maxiter, p->opt.adjoint_rtol, b.S_ptr, b.T_ptr, b.pcg_row, b.item_ptr,
              b.item_e, b.item_code, b.ucol_ptr, b.ucol, b.adjS, b.Sdiag, b.Minv, b.bS, b.adj_vc,

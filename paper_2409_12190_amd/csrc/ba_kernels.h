@@ -37,13 +37,6 @@ struct PointQArgs {
   void* Q;
 };
 
-struct CamVecArgs {
-  const int32_t *cam_ptr, *cam_obs, *o_pt;
-  const void* J;
-  const double *w, *r, *ep;
-  double *gc, *bS, *diagU;
-};
-
 struct SchurArgs {
   int nwg;  // workgroups of the slot table
   const int32_t *slot_blk, *slot_pb, *slot_pe, *slot_lead, *pair_x, *pair_y, *blk_row, *S_ptr;
@@ -51,6 +44,10 @@ struct SchurArgs {
   const double* w;
   void* S;
   double* Sdiag;
+  // camera vectors from the self pairs of the diagonal blocks
+  const int32_t* o_pt;
+  const double *r, *ep;
+  double *gc, *bS, *diagU;
 };
 
 struct CamFinishArgs {
@@ -60,6 +57,8 @@ struct CamFinishArgs {
   double* Minv;
   DevScalars* dev;
   double* Linv;   // optional: inverse Cholesky factors (lower, [nc][81])
+  const double* gc;  // optional: bS -= gc (completes the right-hand side)
+  double* bS;
 };
 
 struct PcgArgs {
@@ -118,7 +117,6 @@ template <typename T> hipError_t launch_linearize(const LinArgs&, int nchunk, hi
 hipError_t launch_reduce_cost(const double* part, int n, DevScalars* dev, hipStream_t);
 hipError_t launch_damp_points(const DampArgs&, hipStream_t);
 template <typename T> hipError_t launch_point_q(const PointQArgs&, hipStream_t);
-template <typename T> hipError_t launch_camera_vec(const CamVecArgs&, int nc, hipStream_t);
 template <typename T> hipError_t launch_schur_pairs(const SchurArgs&, int nwg, hipStream_t);
 template <typename T> hipError_t launch_camera_finish(const CamFinishArgs&, int nc, hipStream_t);
 template <typename T> int pcg_max_grid(bool resident, bool pipelined);

@@ -232,64 +232,6 @@ __global__ __launch_bounds__(256) void k_point_q(PointQArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// camera vectors (one workgroup per camera a):
-//   gc_a = sum w Jc^T r,   diagU_a = diag(sum w Jc^T Jc),
-//   bS_a = -gc_a + sum w Jc^T Jp ep_j   (ep_j = Vinv_j gp_j)
-// reduced over the workgroup in a fixed order.
-// ---------------------------------------------------------------------------
-template <typename T>
-__global__ __launch_bounds__(CAM_THREADS) void k_camera_vec(CamVecArgs a) {
-  __shared__ double red[CAM_THREADS / 64][27];
-  const int cam = blockIdx.x;
-  const int lo = a.cam_ptr[cam], hi = a.cam_ptr[cam + 1];
-  const T* __restrict__ Jall = reinterpret_cast<const T*>(a.J);
-  double gcv[9], bsv[9], du[9];
-#pragma unroll
-  for (int q = 0; q < 9; ++q) gcv[q] = bsv[q] = du[q] = 0.0;
-  int xn = lo + threadIdx.x < hi ? a.cam_obs[lo + threadIdx.x] : 0;
-  for (int i = lo + threadIdx.x; i < hi; i += blockDim.x) {
-    const int x = xn;
-    if (i + (int)blockDim.x < hi) xn = a.cam_obs[i + blockDim.x];
-    double Jc[2][9], Jp[2][3];
-    load_J(Jall + (size_t)x * NJ, Jc, Jp);
-    const double w = a.w[x];
-    const double rx = a.r[2 * (size_t)x], ry = a.r[2 * (size_t)x + 1];
-    const double* ep = a.ep + 3 * (size_t)a.o_pt[x];
-    const double e0 = Jp[0][0] * ep[0] + Jp[0][1] * ep[1] + Jp[0][2] * ep[2];
-    const double e1 = Jp[1][0] * ep[0] + Jp[1][1] * ep[1] + Jp[1][2] * ep[2];
-#pragma unroll
-    for (int m = 0; m < 9; ++m) {
-      gcv[m] += w * (Jc[0][m] * rx + Jc[1][m] * ry);
-      bsv[m] += w * (Jc[0][m] * e0 + Jc[1][m] * e1);
-      du[m] += w * (Jc[0][m] * Jc[0][m] + Jc[1][m] * Jc[1][m]);
-    }
-  }
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-#pragma unroll
-  for (int q = 0; q < 9; ++q) {
-    const double g = wave_sum(gcv[q]);
-    const double b = wave_sum(bsv[q]);
-    const double u = wave_sum(du[q]);
-    if (lane == 0) {
-      red[wid][q] = g;
-      red[wid][9 + q] = b;
-      red[wid][18 + q] = u;
-    }
-  }
-  __syncthreads();
-  if (threadIdx.x < 27) {
-    double s = 0.0;
-    for (int w2 = 0; w2 < CAM_THREADS / 64; ++w2) s += red[w2][threadIdx.x];
-    const int q = threadIdx.x % 9;
-    if (threadIdx.x < 9) a.gc[9 * (size_t)cam + q] = s;
-    else if (threadIdx.x < 18) a.bS[9 * (size_t)cam + q] = s;  // completed below with -gc
-    else a.diagU[9 * (size_t)cam + q] = s;
-  }
-  __syncthreads();
-  if (threadIdx.x < 9) a.bS[9 * (size_t)cam + threadIdx.x] -= a.gc[9 * (size_t)cam + threadIdx.x];
-}
-
-// ---------------------------------------------------------------------------
 // Schur blocks from the pair table (Sec. IV-B-1 numeric phase on the cached
 // table): for block (a, b) and pairs (x, y) sharing a point, x in camera a,
 // y in camera b,
@@ -300,11 +242,18 @@ __global__ __launch_bounds__(CAM_THREADS) void k_camera_vec(CamVecArgs a) {
 // The chunks of one block sit in consecutive slots of one workgroup and are
 // summed in slot order through LDS: no atomics, fixed summation order.
 // Off-diagonal blocks go to S (precision T); diagonal blocks, still to be
-// damped, to the FP64 buffer Sdiag.
+// damped, to the FP64 buffer Sdiag.  The self pairs (x, x) of a diagonal
+// block visit every observation of its camera once, so the same lanes also
+// form the camera vectors
+//   gc_a = sum w Jc^T r,  diagU_a = diag(sum w Jc^T Jc),
+//   bS_a + gc_a = sum w Jc^T Jp ep_j   (ep_j = Vinv_j gp_j),
+// which saves a pass over the observations in camera order.
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(SCHUR_THREADS) void k_schur_pairs(SchurArgs a) {
-  __shared__ double part[SCHUR_SLOTS][81];
+  // per slot: the 81 block values, then (diagonal blocks) the camera vectors
+  // gc, sum w Jc^T Jp ep and diag U of the slot's self pairs
+  __shared__ double part[SCHUR_SLOTS][81 + 27];
   // workgroups are dispatched round-robin over the 8 XCDs: XCD k takes the
   // k-th contiguous range of slot workgroups, so that neighbouring rows (which
   // read the same observations) share that XCD's L2
@@ -320,6 +269,7 @@ __global__ __launch_bounds__(SCHUR_THREADS) void k_schur_pairs(SchurArgs a) {
     double acc[9];
 #pragma unroll
     for (int r = 0; r < 9; ++r) acc[r] = 0.0;
+    double vg = 0.0, vb = 0.0, vu = 0.0;  // column `col` of the camera vectors
     if (e >= 0) {
       const int pb = a.slot_pb[sbase + slot], pe = a.slot_pe[sbase + slot];
       // the next pair's indices are fetched while this pair is processed
@@ -357,22 +307,53 @@ __global__ __launch_bounds__(SCHUR_THREADS) void k_schur_pairs(SchurArgs a) {
 #pragma unroll
         for (int r = 0; r < 9; ++r) acc[r] += (double)Jx[r] * g0 + (double)Jx[9 + r] * g1;
       }
+      if (a.S_ptr[a.blk_row[e]] == e) {
+        // each observation of the camera is the self pair of exactly one
+        // chunk of the diagonal block: the camera vectors of Alg. 1
+        // (gradient J^T W r, the Schur right-hand side term, diag of U)
+        for (int i = pb; i < pe; ++i) {
+          const int x = a.pair_x[i];
+          if (a.pair_y[i] != x) continue;
+          const T* Jx = Jall + (size_t)x * NJ;
+          const double wx = a.w[x];
+          const double c0 = (double)Jx[col], c1 = (double)Jx[9 + col];
+          const double* ep = a.ep + 3 * (size_t)a.o_pt[x];
+          const double e0 = (double)Jx[18] * ep[0] + (double)Jx[19] * ep[1] + (double)Jx[20] * ep[2];
+          const double e1 = (double)Jx[21] * ep[0] + (double)Jx[22] * ep[1] + (double)Jx[23] * ep[2];
+          vg += wx * (c0 * a.r[2 * (size_t)x] + c1 * a.r[2 * (size_t)x + 1]);
+          vb += wx * (c0 * e0 + c1 * e1);
+          vu += wx * (c0 * c0 + c1 * c1);
+        }
+      }
     }
 #pragma unroll
     for (int r = 0; r < 9; ++r) part[slot][r * 9 + col] = acc[r];
+    part[slot][81 + col] = vg;
+    part[slot][90 + col] = vb;
+    part[slot][99 + col] = vu;
   }
   __syncthreads();
   // every lead slot sums its block's chunk partials in slot order
-  for (int t = threadIdx.x; t < SCHUR_SLOTS * 81; t += blockDim.x) {
-    const int s = t / 81, q = t - 81 * (t / 81);
+  for (int t = threadIdx.x; t < SCHUR_SLOTS * 108; t += blockDim.x) {
+    const int s = t / 108, q = t - 108 * (t / 108);
     const int n = a.slot_lead[sbase + s];
     if (n == 0) continue;
-    double v = 0.0;
-    for (int k = 0; k < n; ++k) v += part[s + k][q];
     const int e = a.slot_blk[sbase + s];
     const int row = a.blk_row[e];
-    if (a.S_ptr[row] == e) a.Sdiag[81 * (size_t)row + q] = v;
-    else reinterpret_cast<T*>(a.S)[81 * (size_t)e + q] = (T)v;
+    const bool diag = a.S_ptr[row] == e;
+    if (q >= 81 && !diag) continue;
+    double v = 0.0;
+    for (int k = 0; k < n; ++k) v += part[s + k][q];
+    if (q < 81) {
+      if (diag) a.Sdiag[81 * (size_t)row + q] = v;
+      else reinterpret_cast<T*>(a.S)[81 * (size_t)e + q] = (T)v;
+    } else if (q < 90) {
+      a.gc[9 * (size_t)row + (q - 81)] = v;
+    } else if (q < 99) {
+      a.bS[9 * (size_t)row + (q - 90)] = v;  // - gc, added by the camera finish
+    } else {
+      a.diagU[9 * (size_t)row + (q - 99)] = v;
+    }
   }
 }
 
@@ -387,6 +368,8 @@ __global__ __launch_bounds__(64) void k_camera_finish(CamFinishArgs a) {
   __shared__ double Sd[81];
   const int cam = blockIdx.x;
   const double lam = a.dev->lambda;
+  // right-hand side of the reduced system: bS = -gc + sum w Jc^T Jp ep
+  if (a.gc && threadIdx.x < 9) a.bS[9 * (size_t)cam + threadIdx.x] -= a.gc[9 * (size_t)cam + threadIdx.x];
   for (int q = threadIdx.x; q < 81; q += blockDim.x) {
     double v = a.Sdiag[81 * (size_t)cam + q];
     const int r = q / 9;
@@ -1194,14 +1177,6 @@ hipError_t launch_point_q(const PointQArgs& a, hipStream_t s) {
 }
 template hipError_t launch_point_q<float>(const PointQArgs&, hipStream_t);
 template hipError_t launch_point_q<double>(const PointQArgs&, hipStream_t);
-
-template <typename T>
-hipError_t launch_camera_vec(const CamVecArgs& a, int nc, hipStream_t s) {
-  hipLaunchKernelGGL(k_camera_vec<T>, dim3(nc), dim3(CAM_THREADS), 0, s, a);
-  return hipGetLastError();
-}
-template hipError_t launch_camera_vec<float>(const CamVecArgs&, int, hipStream_t);
-template hipError_t launch_camera_vec<double>(const CamVecArgs&, int, hipStream_t);
 
 template <typename T>
 hipError_t launch_schur_pairs(const SchurArgs& a, int nwg, hipStream_t s) {
