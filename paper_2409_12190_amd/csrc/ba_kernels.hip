@@ -47,6 +47,31 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
   return s;
 }
 
+// Three sums over the workgroup in one exchange (fixed order); results
+// valid in every thread.  sh: >= 3 * blockDim/64 doubles.
+__device__ __forceinline__ void block_sum3(double& a, double& b, double& c, double* sh) {
+  a = wave_sum(a);
+  b = wave_sum(b);
+  c = wave_sum(c);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+  __syncthreads();
+  if (lane == 0) {
+    sh[3 * wid] = a;
+    sh[3 * wid + 1] = b;
+    sh[3 * wid + 2] = c;
+  }
+  __syncthreads();
+  double x = 0.0, y = 0.0, z = 0.0;
+  for (int i = 0; i < nw; ++i) {
+    x += sh[3 * i];
+    y += sh[3 * i + 1];
+    z += sh[3 * i + 2];
+  }
+  a = x;
+  b = y;
+  c = z;
+}
+
 __device__ __forceinline__ double block_max(double v, double* sh) {
   v = wave_max(v);
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
@@ -875,6 +900,7 @@ __global__ __launch_bounds__(PCG_THREADS) void k_pcg_pipelined(PcgArgs a) {
   const double bnorm = sqrt(block_sum(t0, red));
   pcg_spmv<T, RES>(a, ib, i0, i1, nr, L, rptr, it, zl, seg, ws);
   __shared__ int poll_failed;
+  __shared__ double red3s[3 * (PCG_THREADS / 64)];
   double rnorm = bnorm, gamma_old = 1.0, alpha_old = 1.0;
   int iters = 0, breakdown = 0;
   for (int i = 0; ok && bnorm > 0.0 && i <= a.maxiter; ++i) {
@@ -920,9 +946,8 @@ __global__ __launch_bounds__(PCG_THREADS) void k_pcg_pipelined(PcgArgs a) {
     }
     // every workgroup's m columns are in memory now
     pcg_fetch_z(a, zk, ub, nuc, zl);
-    const double gamma = block_sum(tg, red);
-    const double delta = block_sum(td, red);
-    const double rr = block_sum(tr, red);
+    block_sum3(tg, td, tr, red3s);
+    const double gamma = tg, delta = td, rr = tr;
     iters = i;
     rnorm = sqrt(rr);
     if (rnorm <= a.rtol * bnorm || i == a.maxiter) break;
