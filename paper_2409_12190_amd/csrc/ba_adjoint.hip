@@ -210,27 +210,35 @@ __global__ __launch_bounds__(CAM_THREADS) void k_adj_camera(AdjCameraArgs a) {
 // reduced camera matrix of H from the pair table (the numeric phase of the
 // same cached table as the forward step):
 //   S_ab = [a = b] U_a - sum_{pairs (x, y)} Y_x W_y^T,
-// 9 lanes per chunk of pairs, lane = output column, chunks of one block
-// summed in slot order through LDS.
+// SCHUR_LANES lanes per chunk of pairs, lane k owning output columns
+// 3k..3k+2; chunks of one block summed in slot order through LDS.
 __global__ __launch_bounds__(SCHUR_THREADS) void k_adj_schur(AdjSchurArgs a) {
   __shared__ double part[SCHUR_SLOTS][81];
-  const int slot = threadIdx.x / 9, col = threadIdx.x - 9 * (threadIdx.x / 9);
+  const int slot = threadIdx.x / SCHUR_LANES;
+  const int c0 = 3 * (threadIdx.x - SCHUR_LANES * slot);
   const size_t sbase = (size_t)blockIdx.x * SCHUR_SLOTS;
   if (slot < SCHUR_SLOTS) {
     const int e = a.slot_blk[sbase + slot];
-    double acc[9];
-    for (int r = 0; r < 9; ++r) acc[r] = 0.0;
+    double acc[9][3];
+    for (int r = 0; r < 9; ++r)
+      for (int c = 0; c < 3; ++c) acc[r][c] = 0.0;
     if (e >= 0) {
       const int pb = a.slot_pb[sbase + slot], pe = a.slot_pe[sbase + slot];
       for (int i = pb; i < pe; ++i) {
         const int x = a.pair_x[i], y = a.pair_y[i];
         const double* Y = a.Y + 27 * (size_t)x;
         const double* Ay = a.A + 78 * (size_t)y;
-        const double w0 = Ay[sym12(col, 9)], w1 = Ay[sym12(col, 10)], w2 = Ay[sym12(col, 11)];
-        for (int r = 0; r < 9; ++r) acc[r] += Y[3 * r] * w0 + Y[3 * r + 1] * w1 + Y[3 * r + 2] * w2;
+        double wv[3][3];
+        for (int c = 0; c < 3; ++c)
+          for (int t = 0; t < 3; ++t) wv[t][c] = Ay[sym12(c0 + c, 9 + t)];
+        for (int r = 0; r < 9; ++r) {
+          const double y0 = Y[3 * r], y1 = Y[3 * r + 1], y2 = Y[3 * r + 2];
+          for (int c = 0; c < 3; ++c) acc[r][c] += y0 * wv[0][c] + y1 * wv[1][c] + y2 * wv[2][c];
+        }
       }
     }
-    for (int r = 0; r < 9; ++r) part[slot][r * 9 + col] = acc[r];
+    for (int r = 0; r < 9; ++r)
+      for (int c = 0; c < 3; ++c) part[slot][r * 9 + c0 + c] = acc[r][c];
   }
   __syncthreads();
   for (int t = threadIdx.x; t < SCHUR_SLOTS * 81; t += blockDim.x) {

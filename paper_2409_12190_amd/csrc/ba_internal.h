@@ -16,8 +16,9 @@ constexpr int D = 9;            // camera tangent size (6 pose + f, k1, k2)
 constexpr int NJ = 24;          // stored Jacobian values per observation: Jc 2x9, then Jp 2x3
 constexpr int CHUNK = 256;      // observations per point-aligned chunk (= its block size)
 constexpr int SCHUR_THREADS = 256;
-constexpr int SCHUR_SLOTS = SCHUR_THREADS / 9;  // 28 pair chunks per workgroup, 9 lanes each
-constexpr int SCHUR_CHUNK = 16;                 // target pairs per chunk
+constexpr int SCHUR_LANES = 3;                            // lanes per pair chunk (3 block columns each)
+constexpr int SCHUR_SLOTS = SCHUR_THREADS / SCHUR_LANES;  // 85 pair chunks per workgroup
+constexpr int SCHUR_CHUNK = 16;                           // target pairs per chunk
 constexpr int CAM_THREADS = 128;
 constexpr int PCG_THREADS = 1024;
 constexpr int PCG_RMAX = 48;          // block rows owned by one PCG workgroup

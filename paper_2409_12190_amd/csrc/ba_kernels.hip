@@ -262,123 +262,238 @@ __global__ __launch_bounds__(256) void k_point_q(PointQArgs a) {
 // y in camera b,
 //   S_ab  = -sum Jc_x^T (Q_x (w_y Jp_y)^T) Jc_y                  (a < b)
 //   S_aa' = sum Jc_x^T ([x = y] w_x I - Q_x (w_y Jp_y)^T) Jc_y   (undamped)
-// Each workgroup holds SCHUR_SLOTS chunk slots; 9 lanes share a chunk, lane
-// c accumulating column c of the block over the chunk's pairs in registers.
-// The chunks of one block sit in consecutive slots of one workgroup and are
-// summed in slot order through LDS: no atomics, fixed summation order.
-// Off-diagonal blocks go to S (precision T); diagonal blocks, still to be
-// damped, to the FP64 buffer Sdiag.  The self pairs (x, x) of a diagonal
-// block visit every observation of its camera once, so the same lanes also
-// form the camera vectors
+// Each workgroup holds SCHUR_SLOTS chunk slots; SCHUR_LANES = 3 lanes share a
+// chunk, lane k accumulating columns 3k..3k+2 of the block (27 values) over
+// the chunk's pairs in registers, with the next pair's rows loaded while the
+// current one is multiplied.  The chunks of one block sit in consecutive
+// slots of one workgroup and are summed in slot order through LDS: no
+// atomics, fixed summation order.  Off-diagonal blocks go to S (precision T);
+// diagonal blocks, still to be damped, to the FP64 buffer Sdiag.  The self
+// pairs (x, x) of a diagonal block visit every observation of its camera
+// once, so the same lanes also form the camera vectors
 //   gc_a = sum w Jc^T r,  diagU_a = diag(sum w Jc^T Jc),
 //   bS_a + gc_a = sum w Jc^T Jp ep_j   (ep_j = Vinv_j gp_j),
 // which saves a pass over the observations in camera order.
 // ---------------------------------------------------------------------------
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+
+// the values of pair (x, y) one lane needs (columns c0..c0+2)
+template <typename T> struct PairRows {
+  T jx[18];  // Jc of x (both rows)
+  T jy[6];   // Jc of y: row 0 then row 1 at columns c0..c0+2
+  T py[6];   // Jp of y
+  T q[6];    // Q of x
+  double w;  // weight of y
+};
+
+__device__ __forceinline__ void load_rows(PairRows<float>& v, const float* J, const float* Q,
+                                          const double* w, int x, int y, int c0) {
+  const float* jx = J + (size_t)x * NJ;  // 96-byte rows: 16-byte aligned
+  const float* jy = J + (size_t)y * NJ;
+  const float* qx = Q + (size_t)x * 6;   // 24-byte rows: 8-byte aligned
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const f32x4 t = *reinterpret_cast<const f32x4*>(jx + 4 * k);
+    v.jx[4 * k] = t.x;
+    v.jx[4 * k + 1] = t.y;
+    v.jx[4 * k + 2] = t.z;
+    v.jx[4 * k + 3] = t.w;
+  }
+  {
+    const f32x2 t = *reinterpret_cast<const f32x2*>(jx + 16);
+    v.jx[16] = t.x;
+    v.jx[17] = t.y;
+  }
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const f32x2 t = *reinterpret_cast<const f32x2*>(jy + 18 + 2 * k);
+    v.py[2 * k] = t.x;
+    v.py[2 * k + 1] = t.y;
+    const f32x2 u = *reinterpret_cast<const f32x2*>(qx + 2 * k);
+    v.q[2 * k] = u.x;
+    v.q[2 * k + 1] = u.y;
+  }
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    v.jy[k] = jy[c0 + k];
+    v.jy[3 + k] = jy[9 + c0 + k];
+  }
+  v.w = w[y];
+}
+
+__device__ __forceinline__ void load_rows(PairRows<double>& v, const double* J, const double* Q,
+                                          const double* w, int x, int y, int c0) {
+  const double* jx = J + (size_t)x * NJ;  // 192-byte rows
+  const double* jy = J + (size_t)y * NJ;
+  const double* qx = Q + (size_t)x * 6;   // 48-byte rows
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    const f64x2 t = *reinterpret_cast<const f64x2*>(jx + 2 * k);
+    v.jx[2 * k] = t.x;
+    v.jx[2 * k + 1] = t.y;
+  }
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const f64x2 t = *reinterpret_cast<const f64x2*>(jy + 18 + 2 * k);
+    v.py[2 * k] = t.x;
+    v.py[2 * k + 1] = t.y;
+    const f64x2 u = *reinterpret_cast<const f64x2*>(qx + 2 * k);
+    v.q[2 * k] = u.x;
+    v.q[2 * k + 1] = u.y;
+  }
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    v.jy[k] = jy[c0 + k];
+    v.jy[3 + k] = jy[9 + c0 + k];
+  }
+  v.w = w[y];
+}
+
+// acc[r][c] += (Jc_x^T M Jc_y)[r][c0 + c],
+// M = [x = y] w_y I - w_y Q_x Jp_y^T
+template <typename T>
+__device__ __forceinline__ void pair_update(double (&acc)[9][3], const PairRows<T>& v, bool self) {
+  double M[2][2];
+#pragma unroll
+  for (int i2 = 0; i2 < 2; ++i2)
+#pragma unroll
+    for (int k2 = 0; k2 < 2; ++k2)
+      M[i2][k2] = -v.w * ((double)v.q[3 * i2] * (double)v.py[3 * k2] +
+                          (double)v.q[3 * i2 + 1] * (double)v.py[3 * k2 + 1] +
+                          (double)v.q[3 * i2 + 2] * (double)v.py[3 * k2 + 2]);
+  if (self) {
+    M[0][0] += v.w;
+    M[1][1] += v.w;
+  }
+  double g0[3], g1[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const double a0 = (double)v.jy[c], a1 = (double)v.jy[3 + c];
+    g0[c] = M[0][0] * a0 + M[0][1] * a1;
+    g1[c] = M[1][0] * a0 + M[1][1] * a1;
+  }
+#pragma unroll
+  for (int r = 0; r < 9; ++r) {
+    const double j0 = (double)v.jx[r], j1 = (double)v.jx[9 + r];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) acc[r][c] += j0 * g0[c] + j1 * g1[c];
+  }
+}
+
 template <typename T>
 __global__ __launch_bounds__(SCHUR_THREADS) void k_schur_pairs(SchurArgs a) {
-  // per slot: the 81 block values, then (diagonal blocks) the camera vectors
-  // gc, sum w Jc^T Jp ep and diag U of the slot's self pairs
-  __shared__ double part[SCHUR_SLOTS][81 + 27];
+  // per slot: the 81 block values; afterwards (diagonal blocks) the camera
+  // vectors gc, sum w Jc^T Jp ep and diag U of the slot's self pairs
+  __shared__ double part[SCHUR_SLOTS][81];
   // workgroups are dispatched round-robin over the 8 XCDs: XCD k takes the
   // k-th contiguous range of slot workgroups, so that neighbouring rows (which
   // read the same observations) share that XCD's L2
   const int per = (a.nwg + 7) / 8;
   const int lw = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
   if (lw >= a.nwg) return;
-  const int slot = threadIdx.x / 9, col = threadIdx.x - 9 * (threadIdx.x / 9);
+  const int slot = threadIdx.x / SCHUR_LANES;
+  const int c0 = 3 * (threadIdx.x - SCHUR_LANES * slot);
   const size_t sbase = (size_t)lw * SCHUR_SLOTS;
   const T* __restrict__ Jall = reinterpret_cast<const T*>(a.J);
   const T* __restrict__ Qall = reinterpret_cast<const T*>(a.Q);
+  double vg[3] = {0.0, 0.0, 0.0}, vb[3] = {0.0, 0.0, 0.0}, vu[3] = {0.0, 0.0, 0.0};
+  bool diag_slot = false;
   if (slot < SCHUR_SLOTS) {
     const int e = a.slot_blk[sbase + slot];
-    double acc[9];
+    double acc[9][3];
 #pragma unroll
-    for (int r = 0; r < 9; ++r) acc[r] = 0.0;
-    double vg = 0.0, vb = 0.0, vu = 0.0;  // column `col` of the camera vectors
-    if (e >= 0) {
-      const int pb = a.slot_pb[sbase + slot], pe = a.slot_pe[sbase + slot];
-      // the next pair's indices are fetched while this pair is processed
-      int xn = 0, yn = 0;
-      if (pb < pe) {
-        xn = a.pair_x[pb];
-        yn = a.pair_y[pb];
-      }
+    for (int r = 0; r < 9; ++r)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) acc[r][c] = 0.0;
+    const int pb = e >= 0 ? a.slot_pb[sbase + slot] : 0;
+    const int pe = e >= 0 ? a.slot_pe[sbase + slot] : 0;
+    // (a camera without observations has an empty diagonal block: zeros)
+    diag_slot = e >= 0 && a.S_ptr[a.blk_row[e]] == e;
+    if (pb < pe) {
+      // software pipeline: rows of pair i + 1 and indices of pair i + 2 are
+      // in flight while pair i is multiplied (indices clamped to the chunk)
+      int x = a.pair_x[pb], y = a.pair_y[pb];
+      PairRows<T> cur;
+      load_rows(cur, Jall, Qall, a.w, x, y, c0);
+      int xn = a.pair_x[min(pb + 1, pe - 1)], yn = a.pair_y[min(pb + 1, pe - 1)];
 #pragma unroll 2
       for (int i = pb; i < pe; ++i) {
-        const int x = xn, y = yn;
-        if (i + 1 < pe) {
-          xn = a.pair_x[i + 1];
-          yn = a.pair_y[i + 1];
-        }
-        const T* Jx = Jall + (size_t)x * NJ;
-        const T* Jy = Jall + (size_t)y * NJ;
-        const T* Qx = Qall + (size_t)x * 6;
-        const double wy = a.w[y];
-        double M[2][2];
-#pragma unroll
-        for (int i2 = 0; i2 < 2; ++i2)
-#pragma unroll
-          for (int k2 = 0; k2 < 2; ++k2)
-            M[i2][k2] = -wy * ((double)Qx[3 * i2] * (double)Jy[18 + 3 * k2] +
-                               (double)Qx[3 * i2 + 1] * (double)Jy[19 + 3 * k2] +
-                               (double)Qx[3 * i2 + 2] * (double)Jy[20 + 3 * k2]);
-        if (x == y) {
-          M[0][0] += wy;
-          M[1][1] += wy;
-        }
-        const double c0 = (double)Jy[col], c1 = (double)Jy[9 + col];
-        const double g0 = M[0][0] * c0 + M[0][1] * c1;
-        const double g1 = M[1][0] * c0 + M[1][1] * c1;
-#pragma unroll
-        for (int r = 0; r < 9; ++r) acc[r] += (double)Jx[r] * g0 + (double)Jx[9 + r] * g1;
+        PairRows<T> nxt;
+        load_rows(nxt, Jall, Qall, a.w, xn, yn, c0);
+        const int i2 = min(i + 2, pe - 1);
+        const int xa = a.pair_x[i2], ya = a.pair_y[i2];
+        pair_update(acc, cur, x == y);
+        cur = nxt;
+        x = xn;
+        y = yn;
+        xn = xa;
+        yn = ya;
       }
-      if (a.S_ptr[a.blk_row[e]] == e) {
+      if (diag_slot) {
         // each observation of the camera is the self pair of exactly one
         // chunk of the diagonal block: the camera vectors of Alg. 1
         // (gradient J^T W r, the Schur right-hand side term, diag of U)
         for (int i = pb; i < pe; ++i) {
-          const int x = a.pair_x[i];
-          if (a.pair_y[i] != x) continue;
-          const T* Jx = Jall + (size_t)x * NJ;
-          const double wx = a.w[x];
-          const double c0 = (double)Jx[col], c1 = (double)Jx[9 + col];
-          const double* ep = a.ep + 3 * (size_t)a.o_pt[x];
+          const int xs = a.pair_x[i];
+          if (a.pair_y[i] != xs) continue;
+          const T* Jx = Jall + (size_t)xs * NJ;
+          const double wx = a.w[xs];
+          const double* ep = a.ep + 3 * (size_t)a.o_pt[xs];
           const double e0 = (double)Jx[18] * ep[0] + (double)Jx[19] * ep[1] + (double)Jx[20] * ep[2];
           const double e1 = (double)Jx[21] * ep[0] + (double)Jx[22] * ep[1] + (double)Jx[23] * ep[2];
-          vg += wx * (c0 * a.r[2 * (size_t)x] + c1 * a.r[2 * (size_t)x + 1]);
-          vb += wx * (c0 * e0 + c1 * e1);
-          vu += wx * (c0 * c0 + c1 * c1);
+          const double r0 = a.r[2 * (size_t)xs], r1 = a.r[2 * (size_t)xs + 1];
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            const double j0 = (double)Jx[c0 + c], j1 = (double)Jx[9 + c0 + c];
+            vg[c] += wx * (j0 * r0 + j1 * r1);
+            vb[c] += wx * (j0 * e0 + j1 * e1);
+            vu[c] += wx * (j0 * j0 + j1 * j1);
+          }
         }
       }
     }
 #pragma unroll
-    for (int r = 0; r < 9; ++r) part[slot][r * 9 + col] = acc[r];
-    part[slot][81 + col] = vg;
-    part[slot][90 + col] = vb;
-    part[slot][99 + col] = vu;
+    for (int r = 0; r < 9; ++r)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) part[slot][r * 9 + c0 + c] = acc[r][c];
   }
   __syncthreads();
   // every lead slot sums its block's chunk partials in slot order
-  for (int t = threadIdx.x; t < SCHUR_SLOTS * 108; t += blockDim.x) {
-    const int s = t / 108, q = t - 108 * (t / 108);
+  for (int t = threadIdx.x; t < SCHUR_SLOTS * 81; t += blockDim.x) {
+    const int s = t / 81, q = t - 81 * (t / 81);
+    const int n = a.slot_lead[sbase + s];
+    if (n == 0) continue;
+    double v = 0.0;
+    for (int k = 0; k < n; ++k) v += part[s + k][q];
+    const int e = a.slot_blk[sbase + s];
+    const int row = a.blk_row[e];
+    if (a.S_ptr[row] == e) a.Sdiag[81 * (size_t)row + q] = v;
+    else reinterpret_cast<T*>(a.S)[81 * (size_t)e + q] = (T)v;
+  }
+  // camera vectors of the diagonal blocks, through the same LDS
+  if (!__syncthreads_or(diag_slot)) return;
+  if (diag_slot)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      part[slot][c0 + c] = vg[c];
+      part[slot][9 + c0 + c] = vb[c];
+      part[slot][18 + c0 + c] = vu[c];
+    }
+  __syncthreads();
+  for (int t = threadIdx.x; t < SCHUR_SLOTS * 27; t += blockDim.x) {
+    const int s = t / 27, q = t - 27 * (t / 27);
     const int n = a.slot_lead[sbase + s];
     if (n == 0) continue;
     const int e = a.slot_blk[sbase + s];
     const int row = a.blk_row[e];
-    const bool diag = a.S_ptr[row] == e;
-    if (q >= 81 && !diag) continue;
+    if (a.S_ptr[row] != e) continue;
     double v = 0.0;
     for (int k = 0; k < n; ++k) v += part[s + k][q];
-    if (q < 81) {
-      if (diag) a.Sdiag[81 * (size_t)row + q] = v;
-      else reinterpret_cast<T*>(a.S)[81 * (size_t)e + q] = (T)v;
-    } else if (q < 90) {
-      a.gc[9 * (size_t)row + (q - 81)] = v;
-    } else if (q < 99) {
-      a.bS[9 * (size_t)row + (q - 90)] = v;  // - gc, added by the camera finish
-    } else {
-      a.diagU[9 * (size_t)row + (q - 99)] = v;
-    }
+    if (q < 9) a.gc[9 * (size_t)row + q] = v;
+    else if (q < 18) a.bS[9 * (size_t)row + (q - 9)] = v;  // - gc, added by the camera finish
+    else a.diagU[9 * (size_t)row + (q - 18)] = v;
   }
 }
 
