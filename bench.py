@@ -82,12 +82,18 @@ def iteration_bytes(scene, nnzb, es, cg_iters):
     return b_obs + b_par + b_s + b_pc + b_vec
 
 
-def source_digest():
-    """Digest of the kernel sources: HBM traffic counters recorded for other
-    sources no longer describe the kernels."""
+KERNEL_SOURCES = {
+    "pcg": ("ba_pcg.hip", "ba_reduce.h", "ba_kernels.h", "ba_internal.h"),
+}
+DEFAULT_SOURCES = ("ba_kernels.hip", "ba_reduce.h", "ba_kernels.h", "ba_internal.h", "ba_device.h")
+
+
+def source_digest(kernel="pcg"):
+    """Digest of a kernel's sources: HBM traffic counters recorded for other
+    sources no longer describe the kernel."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("ba_kernels.hip", "ba_kernels.h", "ba_internal.h", "ba_device.h"):
+    for f in KERNEL_SOURCES.get(kernel, DEFAULT_SOURCES):
         with open(os.path.join(ROOT, "paper_2409_12190_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -106,7 +112,7 @@ def recorded_traffic(workload, kernel):
             if ":" in line and not line.startswith("#"):
                 k, v = line.split(":", 1)
                 vals[k.strip()] = v.strip()
-    if vals.get("source_digest") != source_digest():
+    if vals.get("source_digest") != source_digest(kernel):
         return None
     try:
         return float(vals["bytes_per_launch"])

@@ -16,79 +16,9 @@
 #include "ba_device.h"
 #include "ba_internal.h"
 #include "ba_kernels.h"
+#include "ba_reduce.h"
 
 namespace ba {
-
-// ---------------------------------------------------------------------------
-// reduction helpers
-// ---------------------------------------------------------------------------
-
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
-
-__device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-  return v;
-}
-
-// Sum over the workgroup; result valid in every thread.  sh: >= blockDim/64 doubles.
-__device__ __forceinline__ double block_sum(double v, double* sh) {
-  v = wave_sum(v);
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
-  __syncthreads();
-  if (lane == 0) sh[wid] = v;
-  __syncthreads();
-  double s = 0.0;
-  for (int i = 0; i < nw; ++i) s += sh[i];
-  return s;
-}
-
-// Three sums over the workgroup in one exchange (fixed order); results
-// valid in every thread.  sh: >= 3 * blockDim/64 doubles.
-__device__ __forceinline__ void block_sum3(double& a, double& b, double& c, double* sh) {
-  a = wave_sum(a);
-  b = wave_sum(b);
-  c = wave_sum(c);
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
-  __syncthreads();
-  if (lane == 0) {
-    sh[3 * wid] = a;
-    sh[3 * wid + 1] = b;
-    sh[3 * wid + 2] = c;
-  }
-  __syncthreads();
-  double x = 0.0, y = 0.0, z = 0.0;
-  for (int i = 0; i < nw; ++i) {
-    x += sh[3 * i];
-    y += sh[3 * i + 1];
-    z += sh[3 * i + 2];
-  }
-  a = x;
-  b = y;
-  c = z;
-}
-
-__device__ __forceinline__ double block_max(double v, double* sh) {
-  v = wave_max(v);
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
-  __syncthreads();
-  if (lane == 0) sh[wid] = v;
-  __syncthreads();
-  double s = 0.0;
-  for (int i = 0; i < nw; ++i) s = fmax(s, sh[i]);
-  return s;
-}
-
-// Sum of arr[0..n) by one workgroup in a fixed order; valid in every thread.
-__device__ __forceinline__ double block_sum_array(const double* __restrict__ arr, int n, double* sh) {
-  double s = 0.0;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) s += arr[i];
-  return block_sum(s, sh);
-}
 
 template <typename T>
 __device__ __forceinline__ void load_J(const T* __restrict__ J, double Jc[2][9], double Jp[2][3]) {
@@ -561,546 +491,6 @@ __global__ __launch_bounds__(64) void k_camera_finish(CamFinishArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// block-Jacobi preconditioned conjugate gradients on S x = bS (Sec. IV-C-2),
-// one cooperative launch for the whole solve (the paper removes per-iteration
-// launch overhead by replaying a captured PCG iteration, App. B; here the
-// iterations never leave the GPU).
-//
-// Workgroup B owns the contiguous block rows [wg_row[B], wg_row[B+1]), chosen
-// on the host so that workgroups hold similar numbers of (row, block) items.
-// Its own-row vectors and block-Jacobi factors stay in LDS for the whole
-// solve.  The items are split into SPMV_GROUPS contiguous ranges; 9 lanes
-// share an item, lane `comp` holding row `comp` of the block (column `comp`
-// for a transposed upper block).  When every range has at most PCG_IPG items
-// (RES = true) the lanes keep their block values in registers for the whole
-// solve; otherwise they are streamed in batches of PCG_IPG each iteration.
-//
-// Values other workgroups read (the preconditioned residual z, by column,
-// and the dot-product partials) are written once per iteration into a fresh
-// ring slot with agent-scope (write-through) stores and read after a barrier
-// with ordinary cached loads, so iterations need no cache flush.  Dots are
-// reduced from the per-workgroup partials in a fixed order, identically in
-// every workgroup, so every workgroup takes the same branch.  Standard PCG
-// recurrence; the product S p_k is formed as S z_k + beta q_{k-1}, so the
-// direction update and the product share one barrier (two per iteration).
-// ---------------------------------------------------------------------------
-constexpr int SPMV_GROUPS = PCG_THREADS / 9;
-constexpr long BARRIER_SPIN_LIMIT = 1L << 21;
-
-__device__ __forceinline__ void publish(double* p, double v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__device__ __forceinline__ unsigned agent_add(unsigned* p, unsigned v) {
-  return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__device__ __forceinline__ void agent_store(unsigned* p, unsigned v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Grid-wide barrier of a co-resident grid without cache flushes: every wave
-// waits for its own memory operations to complete, one thread per workgroup
-// arrives on its group's counter (BARRIER_FANIN workgroups per group), the
-// last of a group arrives on the top counter, and the last overall advances
-// the generation the others poll.  The wait is bounded: on timeout the sticky
-// error flag is raised, and once it is set every later barrier returns at
-// once, so the kernel always terminates.
-__device__ __forceinline__ bool grid_barrier(GridSync* gs, int* error) {
-  __builtin_amdgcn_s_waitcnt(0);
-  __syncthreads();
-  __shared__ int failed;
-  if (threadIdx.x == 0) {
-    int f = __hip_atomic_load(error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & ERR_BARRIER;
-    if (!f && gridDim.x > 1) {
-      const unsigned gen = __hip_atomic_load(&gs->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      const unsigned grp = blockIdx.x / BARRIER_FANIN;
-      const unsigned ngrp = (gridDim.x + BARRIER_FANIN - 1) / BARRIER_FANIN;
-      const unsigned gsz = min((unsigned)BARRIER_FANIN, gridDim.x - grp * BARRIER_FANIN);
-      bool last = false;
-      if (agent_add(&gs->group[grp].count, 1u) == gsz - 1) {
-        agent_store(&gs->group[grp].count, 0u);
-        __builtin_amdgcn_s_waitcnt(0);
-        if (agent_add(&gs->count, 1u) == ngrp - 1) {
-          agent_store(&gs->count, 0u);
-          __builtin_amdgcn_s_waitcnt(0);
-          agent_add(&gs->gen, 1u);
-          last = true;
-        }
-      }
-      if (!last) {
-        long spins = 0;
-        while (__hip_atomic_load(&gs->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen) {
-          if (++spins > BARRIER_SPIN_LIMIT ||
-              (__hip_atomic_load(error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & ERR_BARRIER)) {
-            atomicOr(error, (int)ERR_BARRIER);
-            f = 1;
-            break;
-          }
-          __builtin_amdgcn_s_sleep(1);
-        }
-      }
-    }
-    failed = f;
-  }
-  __syncthreads();
-  return failed == 0;
-}
-
-// The pipelined PCG synchronises through the dot-product records themselves:
-// before the first barrier every workgroup fills its records of all
-// iteration slots with a NaN pattern that arithmetic never produces; in
-// iteration i a workgroup publishes its three partials only after its m
-// columns have reached memory, and the readers poll the records until no
-// word holds the pattern.  One memory round trip replaces the barrier's
-// atomics and the separate read of the partials.  Bounded like the
-// barrier: on timeout the sticky error flag is raised.
-constexpr unsigned long long PCG_PENDING = 0x7FF4DEADBEEF0000ull;
-
-__device__ __forceinline__ void clear_record(double* p) {
-  __hip_atomic_store(reinterpret_cast<unsigned long long*>(p), PCG_PENDING, __ATOMIC_RELAXED,
-                     __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Thread t < G waits for workgroup t's three partials of slot `rec`; returns
-// false on timeout (error flag raised).
-__device__ __forceinline__ bool poll_record(const double* rec, double& v0, double& v1, double& v2,
-                                            int* error) {
-  const unsigned long long* r = reinterpret_cast<const unsigned long long*>(rec);
-  long spins = 0;
-  while (true) {
-    const unsigned long long a0 = __hip_atomic_load(r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const unsigned long long a1 = __hip_atomic_load(r + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const unsigned long long a2 = __hip_atomic_load(r + 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (a0 != PCG_PENDING && a1 != PCG_PENDING && a2 != PCG_PENDING) {
-      v0 = __longlong_as_double((long long)a0);
-      v1 = __longlong_as_double((long long)a1);
-      v2 = __longlong_as_double((long long)a2);
-      return true;
-    }
-    if (++spins > BARRIER_SPIN_LIMIT ||
-        (__hip_atomic_load(error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & ERR_BARRIER)) {
-      atomicOr(error, (int)ERR_BARRIER);
-      return false;
-    }
-    __builtin_amdgcn_s_sleep(1);
-  }
-}
-
-// Block values of a lane group's items (row `comp` of each block, or column
-// `comp` of a transposed upper block), with the item's LDS column slot and
-// local row.
-struct PcgItems {
-  double v[PCG_IPG][9];
-  int lc[PCG_IPG], rl[PCG_IPG];
-};
-
-template <typename T>
-__device__ __forceinline__ void pcg_load_items(const PcgArgs& a, int ib, int k0, int k1, const int* rptr,
-                                               int comp, PcgItems& it) {
-  const T* __restrict__ S = reinterpret_cast<const T*>(a.S);
-  int row = 0;
-  while (rptr[row + 1] <= k0) ++row;
-#pragma unroll
-  for (int kk = 0; kk < PCG_IPG; ++kk) {
-    const int i = k0 + kk;
-    if (i < k1) {
-      while (rptr[row + 1] <= i) ++row;
-      const int code = a.item_code[ib + i];
-      const int e = a.item_e[ib + i];
-      it.lc[kk] = code & 0xFFFF;
-      it.rl[kk] = row;
-      if (code & ITEM_DIAG) {
-        const double* Bp = a.Sdiag + (size_t)e * 81 + comp * 9;
-#pragma unroll
-        for (int m = 0; m < 9; ++m) it.v[kk][m] = Bp[m];
-      } else if (code & ITEM_TRANS) {
-        const T* Bp = S + (size_t)e * 81 + comp;
-#pragma unroll
-        for (int m = 0; m < 9; ++m) it.v[kk][m] = (double)Bp[9 * m];
-      } else {
-        const T* Bp = S + (size_t)e * 81 + comp * 9;
-#pragma unroll
-        for (int m = 0; m < 9; ++m) it.v[kk][m] = (double)Bp[m];
-      }
-    } else {
-      it.lc[kk] = 0;
-      it.rl[kk] = -1;
-    }
-  }
-}
-
-// y[own rows] = S z, with z's needed block columns already in LDS (zl).
-// Each group keeps a running sum per row and stores it at seg[row + group];
-// row `row` was touched exactly by groups rptr[row]/L .. (rptr[row+1]-1)/L,
-// whose partials are then summed by 8 lanes per output (strided, then a
-// 3-step butterfly): fixed order.
-template <typename T, bool RES>
-__device__ __forceinline__ void pcg_spmv(const PcgArgs& a, int ib, int i0, int i1, int nr, int L,
-                                         const int* rptr, PcgItems& it, const double* zl, double* seg,
-                                         double* y) {
-  const int g = threadIdx.x / 9, comp = threadIdx.x - 9 * (threadIdx.x / 9);
-  if (g < SPMV_GROUPS) {
-    double acc = 0.0;
-    int cur = -1;
-    for (int k0 = i0; k0 < i1; k0 += PCG_IPG) {
-      if (!RES) pcg_load_items<T>(a, ib, k0, i1, rptr, comp, it);
-#pragma unroll
-      for (int kk = 0; kk < PCG_IPG; ++kk) {
-        const int rl = it.rl[kk];
-        if (rl < 0) continue;
-        if (rl != cur) {
-          if (cur >= 0) seg[(cur + g) * 9 + comp] = acc;
-          acc = 0.0;
-          cur = rl;
-        }
-        const double* zc = zl + it.lc[kk] * 9;
-#pragma unroll
-        for (int m = 0; m < 9; ++m) acc += it.v[kk][m] * zc[m];
-      }
-    }
-    if (cur >= 0) seg[(cur + g) * 9 + comp] = acc;
-  }
-  __syncthreads();
-  const int nout = nr * 9;
-  for (int base = 0; base < nout * 8; base += blockDim.x) {
-    const int t = base + threadIdx.x, o = t >> 3, sub = t & 7;
-    double s = 0.0;
-    if (o < nout) {
-      const int row = o / 9, cp = o - 9 * row;
-      const int g0 = rptr[row] / L, g1 = (rptr[row + 1] - 1) / L;
-      for (int gg = g0 + sub; gg <= g1; gg += 8) s += seg[(row + gg) * 9 + cp];
-    }
-    s += __shfl_xor(s, 1, 64);
-    s += __shfl_xor(s, 2, 64);
-    s += __shfl_xor(s, 4, 64);
-    if (o < nout && sub == 0) y[o] = s;
-  }
-  __syncthreads();
-}
-
-// fetch the block columns this workgroup reads from ring slot zk into LDS
-__device__ __forceinline__ void pcg_fetch_z(const PcgArgs& a, const double* zk, int ub, int nuc,
-                                            double* zl) {
-  for (int u = threadIdx.x; u < nuc * 9; u += blockDim.x) {
-    const int j = u / 9;
-    zl[u] = zk[(size_t)a.ucol[ub + j] * ZSTRIDE + (u - 9 * j)];
-  }
-}
-
-template <typename T, bool RES>
-__global__ __launch_bounds__(PCG_THREADS) void k_pcg_standard(PcgArgs a) {
-  __shared__ double xs[PCG_RMAX * 9], rs[PCG_RMAX * 9], ps[PCG_RMAX * 9];
-  __shared__ double qs[PCG_RMAX * 9], zs[PCG_RMAX * 9], ys[PCG_RMAX * 9];
-  __shared__ double Ml[PCG_RMAX * 81];
-  __shared__ double zl[PCG_ZCOLS * 9];
-  __shared__ double seg[(PCG_RMAX + SPMV_GROUPS) * 9];
-  __shared__ int rptr[PCG_RMAX + 1];
-  __shared__ double red[PCG_THREADS / 64];
-  const int G = gridDim.x, B = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
-  const int r0 = a.wg_row[B], nr = a.wg_row[B + 1] - r0;
-  const int n9 = nr * 9;
-  const int ib = a.item_ptr[B], nitems = a.item_ptr[B + 1] - ib;
-  const int ub = a.ucol_ptr[B], nuc = a.ucol_ptr[B + 1] - ub;
-  const size_t zstride = (size_t)a.nc * ZSTRIDE, pstride = (size_t)G * PART_STRIDE;
-  const int g = tid / 9, comp = tid - 9 * (tid / 9);
-  const int L = max(1, (nitems + SPMV_GROUPS - 1) / SPMV_GROUPS);
-  const int i0 = g < SPMV_GROUPS ? min(nitems, g * L) : nitems;
-  const int i1 = g < SPMV_GROUPS ? min(nitems, i0 + L) : nitems;
-  if (tid == 0) {
-    rptr[0] = 0;
-    for (int i = 0; i < nr; ++i)
-      rptr[i + 1] = rptr[i] + (a.S_ptr[r0 + i + 1] - a.S_ptr[r0 + i]) +
-                    (a.T_ptr[r0 + i + 1] - a.T_ptr[r0 + i]);
-  }
-  for (int i = tid; i < n9; i += nt) {
-    rs[i] = a.b[9 * (size_t)r0 + i];
-    xs[i] = 0.0;
-  }
-  for (int i = tid; i < nr * 81; i += nt) Ml[i] = a.Minv[81 * (size_t)r0 + i];
-  __syncthreads();
-  PcgItems it;
-  if (RES && i0 < i1) pcg_load_items<T>(a, ib, i0, i1, rptr, comp, it);
-  else {
-#pragma unroll
-    for (int kk = 0; kk < PCG_IPG; ++kk) it.rl[kk] = -1, it.lc[kk] = 0;
-  }
-
-  // z0 = M b, p0 = z0
-  double s_bb = 0.0, s_rz = 0.0;
-  for (int i = tid; i < n9; i += nt) {
-    const int row = i / 9, cp = i - 9 * row;
-    double z = 0.0;
-#pragma unroll
-    for (int m = 0; m < 9; ++m) z += Ml[row * 81 + cp * 9 + m] * rs[row * 9 + m];
-    zs[i] = z;
-    ps[i] = z;
-    publish(a.zring + (size_t)(r0 + row) * ZSTRIDE + cp, z);
-    s_bb += rs[i] * rs[i];
-    s_rz += rs[i] * z;
-  }
-  s_bb = block_sum(s_bb, red);
-  s_rz = block_sum(s_rz, red);
-  if (tid == 0) {
-    publish(a.partA + (size_t)B * PART_STRIDE, s_bb);
-    publish(a.partA + (size_t)B * PART_STRIDE + 1, s_rz);
-  }
-  bool ok = grid_barrier(a.gs, a.error);
-  pcg_fetch_z(a, a.zring, ub, nuc, zl);
-  double t0 = 0.0, t1 = 0.0;
-  for (int i = tid; i < G; i += nt) {
-    t0 += a.partA[(size_t)i * PART_STRIDE];
-    t1 += a.partA[(size_t)i * PART_STRIDE + 1];
-  }
-  const double bb = block_sum(t0, red);
-  double rz = block_sum(t1, red);
-  const double bnorm = sqrt(bb);
-  double rnorm = bnorm;
-  int iters = 0, breakdown = 0;
-  if (ok && bnorm > 0.0) {
-    // q0 = S z0 (= S p0)
-    pcg_spmv<T, RES>(a, ib, i0, i1, nr, L, rptr, it, zl, seg, ys);
-    double s_pq = 0.0;
-    for (int i = tid; i < n9; i += nt) {
-      qs[i] = ys[i];
-      s_pq += ps[i] * ys[i];
-    }
-    s_pq = block_sum(s_pq, red);
-    if (tid == 0) publish(a.partB + (size_t)B * PART_STRIDE, s_pq);
-    ok = grid_barrier(a.gs, a.error);
-    t0 = 0.0;
-    for (int i = tid; i < G; i += nt) t0 += a.partB[(size_t)i * PART_STRIDE];
-    double pq = block_sum(t0, red);
-    if (ok && !(pq > 0.0)) breakdown = 1;
-    double alpha = rz / pq;
-    for (int k = 1; ok && !breakdown && k <= a.maxiter; ++k) {
-      for (int i = tid; i < n9; i += nt) {
-        xs[i] += alpha * ps[i];
-        rs[i] -= alpha * qs[i];
-      }
-      __syncthreads();
-      double* zk = a.zring + (size_t)k * zstride;
-      double s_rr = 0.0, s_rz2 = 0.0;
-      for (int i = tid; i < n9; i += nt) {
-        const int row = i / 9, cp = i - 9 * row;
-        double z = 0.0;
-#pragma unroll
-        for (int m = 0; m < 9; ++m) z += Ml[row * 81 + cp * 9 + m] * rs[row * 9 + m];
-        zs[i] = z;
-        publish(zk + (size_t)(r0 + row) * ZSTRIDE + cp, z);
-        s_rr += rs[i] * rs[i];
-        s_rz2 += rs[i] * z;
-      }
-      s_rr = block_sum(s_rr, red);
-      s_rz2 = block_sum(s_rz2, red);
-      double* pa = a.partA + (size_t)k * pstride;
-      if (tid == 0) {
-        publish(pa + (size_t)B * PART_STRIDE, s_rr);
-        publish(pa + (size_t)B * PART_STRIDE + 1, s_rz2);
-      }
-      ok = grid_barrier(a.gs, a.error);
-      if (!ok) break;
-      // the partials and the z columns arrive in the same memory round trip
-      pcg_fetch_z(a, zk, ub, nuc, zl);
-      t0 = 0.0;
-      t1 = 0.0;
-      for (int i = tid; i < G; i += nt) {
-        t0 += pa[(size_t)i * PART_STRIDE];
-        t1 += pa[(size_t)i * PART_STRIDE + 1];
-      }
-      const double rr = block_sum(t0, red);
-      const double rz_new = block_sum(t1, red);
-      iters = k;
-      rnorm = sqrt(rr);
-      if (rnorm <= a.rtol * bnorm) break;
-      const double beta = rz_new / rz;
-      rz = rz_new;
-      for (int i = tid; i < n9; i += nt) ps[i] = zs[i] + beta * ps[i];
-      pcg_spmv<T, RES>(a, ib, i0, i1, nr, L, rptr, it, zl, seg, ys);
-      s_pq = 0.0;
-      for (int i = tid; i < n9; i += nt) {
-        const double q = ys[i] + beta * qs[i];
-        qs[i] = q;
-        s_pq += ps[i] * q;
-      }
-      s_pq = block_sum(s_pq, red);
-      double* pb = a.partB + (size_t)k * pstride;
-      if (tid == 0) publish(pb + (size_t)B * PART_STRIDE, s_pq);
-      ok = grid_barrier(a.gs, a.error);
-      if (!ok) break;
-      t0 = 0.0;
-      for (int i = tid; i < G; i += nt) t0 += pb[(size_t)i * PART_STRIDE];
-      pq = block_sum(t0, red);
-      if (!(pq > 0.0)) {
-        breakdown = 1;
-        break;
-      }
-      alpha = rz / pq;
-    }
-  }
-  for (int i = tid; i < n9; i += nt) a.x[9 * (size_t)r0 + i] = xs[i];
-  if (B == 0 && tid == 0) {
-    a.info->cg_iters = iters;
-    a.info->cg_breakdown = breakdown;
-    a.info->cg_rel_resid = bnorm > 0.0 ? rnorm / bnorm : 0.0;
-  }
-}
-
-// Pipelined PCG (Ghysels and Vanroose, "Hiding global synchronization
-// latency in the preconditioned Conjugate Gradient algorithm", 2014): the
-// same Krylov iterates as the standard recurrence in exact arithmetic, with
-// the three dot products of an iteration reduced together and the product
-// n = S m computed after the same barrier, so each iteration needs one grid
-// barrier and one memory round trip.  Its attainable accuracy is lower than
-// the standard recurrence's (relative residuals below ~1e-10 may not be
-// reached), which is why the standard kernel stays selectable.
-template <typename T, bool RES>
-__global__ __launch_bounds__(PCG_THREADS) void k_pcg_pipelined(PcgArgs a) {
-  __shared__ double xs[PCG_RMAX * 9], rs[PCG_RMAX * 9], us[PCG_RMAX * 9], ws[PCG_RMAX * 9];
-  __shared__ double ms_[PCG_RMAX * 9], ns[PCG_RMAX * 9], zs[PCG_RMAX * 9], qs[PCG_RMAX * 9];
-  __shared__ double ss[PCG_RMAX * 9], ps[PCG_RMAX * 9];
-  __shared__ double Ml[PCG_RMAX * 81];
-  __shared__ double zl[PCG_ZCOLS * 9];
-  __shared__ double seg[(PCG_RMAX + SPMV_GROUPS) * 9];
-  __shared__ int rptr[PCG_RMAX + 1];
-  __shared__ double red[PCG_THREADS / 64];
-  const int G = gridDim.x, B = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
-  const int r0 = a.wg_row[B], nr = a.wg_row[B + 1] - r0;
-  const int n9 = nr * 9;
-  const int ib = a.item_ptr[B], nitems = a.item_ptr[B + 1] - ib;
-  const int ub = a.ucol_ptr[B], nuc = a.ucol_ptr[B + 1] - ub;
-  const size_t zstride = (size_t)a.nc * ZSTRIDE, pstride = (size_t)G * PART_STRIDE;
-  const int g = tid / 9, comp = tid - 9 * (tid / 9);
-  const int L = max(1, (nitems + SPMV_GROUPS - 1) / SPMV_GROUPS);
-  const int i0 = g < SPMV_GROUPS ? min(nitems, g * L) : nitems;
-  const int i1 = g < SPMV_GROUPS ? min(nitems, i0 + L) : nitems;
-  if (tid == 0) {
-    rptr[0] = 0;
-    for (int i = 0; i < nr; ++i)
-      rptr[i + 1] = rptr[i] + (a.S_ptr[r0 + i + 1] - a.S_ptr[r0 + i]) +
-                    (a.T_ptr[r0 + i + 1] - a.T_ptr[r0 + i]);
-  }
-  for (int i = tid; i < n9; i += nt) {
-    rs[i] = a.b[9 * (size_t)r0 + i];
-    xs[i] = 0.0;
-  }
-  for (int i = tid; i < nr * 81; i += nt) Ml[i] = a.Minv[81 * (size_t)r0 + i];
-  __syncthreads();
-  PcgItems it;
-  if (RES && i0 < i1) pcg_load_items<T>(a, ib, i0, i1, rptr, comp, it);
-  else {
-#pragma unroll
-    for (int kk = 0; kk < PCG_IPG; ++kk) it.rl[kk] = -1, it.lc[kk] = 0;
-  }
-  // u0 = M b, published in slot 0; w0 = S u0
-  double s_bb = 0.0;
-  for (int i = tid; i < n9; i += nt) {
-    const int row = i / 9, cp = i - 9 * row;
-    double u = 0.0;
-#pragma unroll
-    for (int m = 0; m < 9; ++m) u += Ml[row * 81 + cp * 9 + m] * rs[row * 9 + m];
-    us[i] = u;
-    publish(a.zring + (size_t)(r0 + row) * ZSTRIDE + cp, u);
-    s_bb += rs[i] * rs[i];
-  }
-  s_bb = block_sum(s_bb, red);
-  if (tid == 0) publish(a.partB + (size_t)B * PART_STRIDE, s_bb);
-  // this workgroup's dot-product records of every iteration slot: pending
-  for (int q = tid; q < 3 * (a.maxiter + 1); q += nt)
-    clear_record(a.partA + (size_t)(q / 3) * pstride + (size_t)B * PART_STRIDE + (q - 3 * (q / 3)));
-  bool ok = grid_barrier(a.gs, a.error);
-  pcg_fetch_z(a, a.zring, ub, nuc, zl);
-  double t0 = 0.0;
-  for (int i = tid; i < G; i += nt) t0 += a.partB[(size_t)i * PART_STRIDE];
-  const double bnorm = sqrt(block_sum(t0, red));
-  pcg_spmv<T, RES>(a, ib, i0, i1, nr, L, rptr, it, zl, seg, ws);
-  __shared__ int poll_failed;
-  __shared__ double red3s[3 * (PCG_THREADS / 64)];
-  double rnorm = bnorm, gamma_old = 1.0, alpha_old = 1.0;
-  int iters = 0, breakdown = 0;
-  for (int i = 0; ok && bnorm > 0.0 && i <= a.maxiter; ++i) {
-    // local: partial dots of r, u, w; m = M w published in slot i + 1
-    double* zk = a.zring + (size_t)(i + 1) * zstride;
-    double s_g = 0.0, s_d = 0.0, s_r = 0.0;
-    for (int k = tid; k < n9; k += nt) {
-      const int row = k / 9, cp = k - 9 * row;
-      double m = 0.0;
-#pragma unroll
-      for (int q = 0; q < 9; ++q) m += Ml[row * 81 + cp * 9 + q] * ws[row * 9 + q];
-      ms_[k] = m;
-      publish(zk + (size_t)(r0 + row) * ZSTRIDE + cp, m);
-      s_g += rs[k] * us[k];
-      s_d += ws[k] * us[k];
-      s_r += rs[k] * rs[k];
-    }
-    s_g = wave_sum(s_g);
-    s_d = wave_sum(s_d);
-    s_r = wave_sum(s_r);
-    __shared__ double red3[PCG_THREADS / 64][3];
-    if ((tid & 63) == 0) {
-      red3[tid >> 6][0] = s_g;
-      red3[tid >> 6][1] = s_d;
-      red3[tid >> 6][2] = s_r;
-    }
-    // the m columns must have reached memory before the partials are seen
-    __builtin_amdgcn_s_waitcnt(0);
-    if (tid == 0) poll_failed = 0;
-    __syncthreads();
-    double* pa = a.partA + (size_t)i * pstride;
-    if (tid < 3) {
-      double v = 0.0;
-      for (int w2 = 0; w2 < PCG_THREADS / 64; ++w2) v += red3[w2][tid];
-      publish(pa + (size_t)B * PART_STRIDE + tid, v);
-    }
-    double tg = 0.0, td = 0.0, tr = 0.0;
-    if (tid < G && !poll_record(pa + (size_t)tid * PART_STRIDE, tg, td, tr, a.error)) poll_failed = 1;
-    __syncthreads();
-    if (poll_failed) {
-      ok = false;
-      break;
-    }
-    // every workgroup's m columns are in memory now
-    pcg_fetch_z(a, zk, ub, nuc, zl);
-    block_sum3(tg, td, tr, red3s);
-    const double gamma = tg, delta = td, rr = tr;
-    iters = i;
-    rnorm = sqrt(rr);
-    if (rnorm <= a.rtol * bnorm || i == a.maxiter) break;
-    const double beta = i > 0 ? gamma / gamma_old : 0.0;
-    const double den = i > 0 ? delta - beta * gamma / alpha_old : delta;
-    if (!(den > 0.0)) {
-      breakdown = 1;
-      break;
-    }
-    const double alpha = gamma / den;
-    pcg_spmv<T, RES>(a, ib, i0, i1, nr, L, rptr, it, zl, seg, ns);
-    for (int k = tid; k < n9; k += nt) {
-      const double z = ns[k] + beta * zs[k];
-      const double q = ms_[k] + beta * qs[k];
-      const double sv = ws[k] + beta * ss[k];
-      const double pv = us[k] + beta * ps[k];
-      zs[k] = z;
-      qs[k] = q;
-      ss[k] = sv;
-      ps[k] = pv;
-      xs[k] += alpha * pv;
-      rs[k] -= alpha * sv;
-      us[k] -= alpha * q;
-      ws[k] -= alpha * z;
-    }
-    __syncthreads();
-    gamma_old = gamma;
-    alpha_old = alpha;
-  }
-  for (int i = tid; i < n9; i += nt) a.x[9 * (size_t)r0 + i] = xs[i];
-  if (B == 0 && tid == 0) {
-    a.info->cg_iters = iters;
-    a.info->cg_breakdown = breakdown;
-    a.info->cg_rel_resid = bnorm > 0.0 ? rnorm / bnorm : 0.0;
-  }
-}
-
-// ---------------------------------------------------------------------------
 // back-substitution and the predicted reduction (one workgroup per chunk):
 //   dp_j = Vinv_j (-gp_j - sum_x w_x Jp_x^T Jc_x dc_{c_x}),
 //   pred partials: gp_j . dp_j and sum_x w_x |Jc_x dc + Jp_x dp_j|^2,
@@ -1334,37 +724,6 @@ hipError_t launch_camera_finish(const CamFinishArgs& a, int nc, hipStream_t s) {
 }
 template hipError_t launch_camera_finish<float>(const CamFinishArgs&, int, hipStream_t);
 template hipError_t launch_camera_finish<double>(const CamFinishArgs&, int, hipStream_t);
-
-template <typename T>
-static const void* pcg_kernel(bool resident, bool pipelined) {
-  if (pipelined)
-    return resident ? reinterpret_cast<const void*>(k_pcg_pipelined<T, true>)
-                    : reinterpret_cast<const void*>(k_pcg_pipelined<T, false>);
-  return resident ? reinterpret_cast<const void*>(k_pcg_standard<T, true>)
-                  : reinterpret_cast<const void*>(k_pcg_standard<T, false>);
-}
-
-template <typename T>
-int pcg_max_grid(bool resident, bool pipelined) {
-  int dev = 0, ncu = 0, per = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return 0;
-  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, pcg_kernel<T>(resident, pipelined),
-                                                   PCG_THREADS, 0) != hipSuccess)
-    return 0;
-  return ncu * per;
-}
-template int pcg_max_grid<float>(bool, bool);
-template int pcg_max_grid<double>(bool, bool);
-
-template <typename T>
-hipError_t launch_pcg(const PcgArgs& a, int grid, bool resident, bool pipelined, hipStream_t s) {
-  void* args[] = {const_cast<PcgArgs*>(&a)};
-  return hipLaunchCooperativeKernel(pcg_kernel<T>(resident, pipelined), dim3(grid), dim3(PCG_THREADS),
-                                    args, 0, s);
-}
-template hipError_t launch_pcg<float>(const PcgArgs&, int, bool, bool, hipStream_t);
-template hipError_t launch_pcg<double>(const PcgArgs&, int, bool, bool, hipStream_t);
 
 template <typename T>
 hipError_t launch_backsub(const BackArgs& a, int nchunk, hipStream_t s) {
