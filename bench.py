@@ -40,15 +40,17 @@ def kernel_bytes(name, scene, nnzb, n_pairs, es, cg_iters):
     es = bytes per stored Jacobian / Q / S value (8 FP64, 4 mixed)."""
     no, nc, np_ = scene.n_obs, scene.n_cams, scene.n_pts
     nnz_off = nnzb - nc
-    if name == "linearize":   # obs xy, w, indices in; r, w, J out; V, gp per point
-        return no * (16 + 8 + 4 + 4 + 16 + 8 + 24 * es) + nc * 80 + np_ * (24 + 72)
-    if name == "damp_points":  # V, gp in; Vinv, ep out
+    if name == "linearize":   # obs xy, w, indices in; r, w, observation row (Jc, Jp, Q, w) and
+        # record (r, w, e) out; cameras and points in; V, gp, Vinv, ep per point out
+        return (no * (16 + 8 + 4 + 4 + 16 + 8 + 31 * es + 40) + nc * 80
+                + np_ * (24 + 48 + 24 + 48 + 24))
+    if name == "damp_points":  # V, gp in; Vinv, ep out (after a rejected step)
         return np_ * (48 + 24 + 48 + 24)
-    if name == "point_q":      # point index, Jp, w in; Q out; Vinv per point
-        return no * (4 + 6 * es + 8 + 6 * es) + np_ * 48
-    if name == "schur_pairs":  # pair table; J, Q, w, r per observation; ep per point;
-        # S blocks and the camera vectors (gc, bS, diag U) out
-        return (n_pairs * 8 + no * (24 * es + 6 * es + 8 + 16 + 4) + np_ * 24
+    if name == "point_q":      # point index, Jp, w in; Q, w, e out; Vinv, ep per point
+        return no * (4 + 6 * es + 8 + 7 * es + 16) + np_ * (48 + 24)
+    if name == "schur_pairs":  # pair steps; observation rows (Jc, Jp, Q, w) and records
+        # (r, w, e) once each; S blocks and the camera vectors (gc, bS, diag U) out
+        return (n_pairs * 8 + no * (31 * es + 40)
                 + nnz_off * 81 * es + nc * (648 + 216))
     if name == "camera_finish":  # diagonal blocks and diagU in; damped blocks, inverses out
         return nc * (648 + 72 + 648 + 648)

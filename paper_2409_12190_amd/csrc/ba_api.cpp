@@ -81,6 +81,8 @@ void carve(ba_problem* p, char* base, size_t* total) {
   b.slot_pb = c.take<int32_t>(P.slot_pb.size());
   b.slot_pe = c.take<int32_t>(P.slot_pe.size());
   b.slot_lead = c.take<int32_t>(P.slot_lead.size());
+  b.stab = c.take<int32_t>(P.stab.size());
+  b.swptr = c.take<int32_t>(P.swptr.size());
   b.blk_row = c.take<int32_t>(nnzb);
   b.pcg_row = c.take<int32_t>(P.pcg_row.size());
   b.item_ptr = c.take<int32_t>(P.item_ptr.size());
@@ -97,6 +99,7 @@ void carve(ba_problem* p, char* base, size_t* total) {
     b.pts[i] = c.take<double>(3 * np);
   }
   b.r = c.take<double>(2 * no);
+  b.rec = c.take<double>(8 * no);
   b.w = c.take<double>(no);
   b.J = c.take<char>(no * ba::NJ * es);
   b.V = c.take<double>(6 * np);
@@ -105,7 +108,6 @@ void carve(ba_problem* p, char* base, size_t* total) {
   b.diagU = c.take<double>(9 * nc);
   b.Vinv = c.take<double>(6 * np);
   b.ep = c.take<double>(3 * np);
-  b.Q = c.take<char>(no * 6 * es);
   b.S = c.take<char>(nnzb * 81 * es);
   b.Sdiag = c.take<double>(81 * nc);
   b.bS = c.take<double>(9 * nc);
@@ -247,20 +249,24 @@ ba_status lm_step_impl(ba_problem* p, ba_step_info* out) {
   const double lam_before = p->lambda;
 
   if (!p->lin_valid) {
+    // linearisation with the point elimination of the current lambda
     LinArgs la{b.chunk_ptr, b.chunk_pt, b.pt_ptr, b.o_cam, b.o_pt, b.fixed, b.o_xy, b.o_w,
                b.cams[cur], b.pts[cur], p->opt.huber_delta, b.r, b.w, b.J, b.V, b.gp,
-               b.part_cost, b.part_gmax};
+               b.part_cost, b.part_gmax, b.rec, p->opt.diag_min, p->opt.diag_max, b.Vinv, b.ep,
+               b.dev, b.gsync};
     PHASE(0, launch_linearize<T>(la, nchunk, s));
     PHASE(1, launch_reduce_cost(b.part_cost, nchunk, b.dev, s));
+  } else {
+    // same linearisation, new lambda (after a rejected step): damp again
+    DampArgs da{P.np, b.V, b.gp, p->opt.diag_min, p->opt.diag_max, b.Vinv, b.ep, b.dev, b.gsync};
+    PHASE(2, launch_damp_points(da, s));
+    PointQArgs qa{P.no, b.o_pt, b.w, b.Vinv, b.ep, b.J, b.rec};
+    PHASE(3, launch_point_q<T>(qa, s));
   }
-  DampArgs da{P.np, b.V, b.gp, p->opt.diag_min, p->opt.diag_max, b.Vinv, b.ep, b.dev, b.gsync};
-  PHASE(2, launch_damp_points(da, s));
-  PointQArgs qa{P.no, b.o_pt, b.J, b.w, b.Vinv, b.Q};
-  PHASE(3, launch_point_q<T>(qa, s));
   // the camera vectors (gradient, right-hand side term, diag U) come from
   // the self pairs of the Schur kernel's diagonal blocks
-  SchurArgs sa{P.n_schur_wg, b.slot_blk, b.slot_pb, b.slot_pe, b.slot_lead, b.pair_x, b.pair_y, b.blk_row,
-               b.S_ptr, b.J, b.Q, b.w, b.S, b.Sdiag, b.o_pt, b.r, b.ep, b.gc, b.bS, b.diagU};
+  SchurArgs sa{P.n_schur_wg, b.slot_blk, b.slot_lead, b.blk_row, b.S_ptr, b.stab, b.swptr,
+               b.J, b.rec, b.S, b.Sdiag, b.gc, b.bS, b.diagU};
   PHASE(5, launch_schur_pairs<T>(sa, P.n_schur_wg, s));
   CamFinishArgs cf{b.Sdiag, b.diagU, p->opt.diag_min, p->opt.diag_max, b.Minv, b.dev, b.pcLinv, b.gc, b.bS};
   PHASE(6, launch_camera_finish<T>(cf, P.nc, s));
@@ -482,6 +488,8 @@ ba_status ba_problem_bind(ba_problem* p, void* ws, size_t bytes, void* stream) {
   HIPCHK(upload(b.slot_pe, P.slot_pe, s));
   HIPCHK(upload(b.slot_lead, P.slot_lead, s));
   HIPCHK(upload(b.blk_row, P.blk_row, s));
+  HIPCHK(upload(b.stab, P.stab, s));
+  HIPCHK(upload(b.swptr, P.swptr, s));
   HIPCHK(upload(b.pcg_row, P.pcg_row, s));
   HIPCHK(upload(b.item_ptr, P.item_ptr, s));
   HIPCHK(upload(b.item_e, P.item_e, s));

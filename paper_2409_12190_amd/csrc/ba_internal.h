@@ -13,12 +13,24 @@
 namespace ba {
 
 constexpr int D = 9;            // camera tangent size (6 pose + f, k1, k2)
-constexpr int NJ = 24;          // stored Jacobian values per observation: Jc 2x9, then Jp 2x3
+// One row of NJ values (precision T) per observation: Jc 2x9 at [0, 18),
+// Jp 2x3 at [JP, JP + 6) (written by the linearisation), the Schur factor
+// Q = w Jp Vinv (2x3) at [JQ, JQ + 6), the weight w at JW and one zero
+// (written by the point elimination): a 128-byte line in mixed precision,
+// so one Schur pair reads two lines, and each kernel writes whole 32-byte
+// sectors.
+constexpr int NJ = 32;
+constexpr int JP = 18;
+constexpr int JQ = 24;
+constexpr int JW = 30;
 constexpr int CHUNK = 256;      // observations per point-aligned chunk (= its block size)
 constexpr int SCHUR_THREADS = 256;
-constexpr int SCHUR_LANES = 3;                            // lanes per pair chunk (3 block columns each)
-constexpr int SCHUR_SLOTS = SCHUR_THREADS / SCHUR_LANES;  // 85 pair chunks per workgroup
-constexpr int SCHUR_CHUNK = 16;                           // target pairs per chunk
+constexpr int SCHUR_LANES = 3;         // lanes per pair chunk (3 block columns each)
+constexpr int SCHUR_WAVE_SLOTS = 21;   // pair chunks per wavefront (63 lanes)
+constexpr int SCHUR_WAVES = SCHUR_THREADS / 64;
+constexpr int SCHUR_SLOTS = SCHUR_WAVES * SCHUR_WAVE_SLOTS;  // 84 pair chunks per workgroup
+constexpr int SCHUR_ROWS = 2 * SCHUR_WAVE_SLOTS;  // staged observation rows per wavefront step
+constexpr int SCHUR_CHUNK = 16;        // target pairs per chunk
 constexpr int CAM_THREADS = 128;
 constexpr int PCG_THREADS = 1024;
 constexpr int PCG_RMAX = 48;          // block rows owned by one PCG workgroup
@@ -56,6 +68,12 @@ struct Plan {
   // Schur workgroups: SCHUR_SLOTS chunk slots each; slot -> (block, pair range,
   // number of slots of the block when this slot is the block's first, else 0)
   std::vector<int32_t> slot_blk, slot_pb, slot_pe, slot_lead;
+  // the same chunks as wavefront steps: wavefront v of Schur workgroup g
+  // runs steps [swptr[4g + v], swptr[4g + v + 1]); step t lists the pair of
+  // each of the wavefront's 21 slots, stab[SCHUR_ROWS t + 2s] = x,
+  // stab[SCHUR_ROWS t + 2s + 1] = y, or -2 - x for a self pair (x, x), or
+  // -1 twice when slot s has no pair at that step
+  std::vector<int32_t> stab, swptr;
   std::vector<int32_t> blk_row;  // block -> its row (camera a)
   // PCG workgroup decomposition: workgroup g owns rows [pcg_row[g],
   // pcg_row[g+1]); its (row, block) items in row order with block index and
@@ -107,7 +125,7 @@ struct Buffers {
   // plan
   int32_t *o_cam, *o_pt, *pt_ptr, *chunk_ptr, *chunk_pt, *cam_ptr, *cam_obs;
   int32_t *S_ptr, *S_col, *T_ptr, *T_blk, *T_src;
-  int32_t *pair_x, *pair_y, *slot_blk, *slot_pb, *slot_pe, *slot_lead, *blk_row;
+  int32_t *pair_x, *pair_y, *slot_blk, *slot_pb, *slot_pe, *slot_lead, *blk_row, *stab, *swptr;
   int32_t *pcg_row, *item_ptr, *item_e, *item_code, *ucol_ptr, *ucol;
   int64_t* o_orig;
   uint8_t* fixed;
@@ -117,11 +135,14 @@ struct Buffers {
   double *cams[2], *pts[2];
   // linearisation
   double *r, *w;
-  void* J;  // float or double [no][NJ]
+  void* J;  // float or double [no][NJ] (layout above)
+  // [no][8] FP64 per observation: r0, r1, w, 0 (linearisation), then
+  // e = Jp ep: e0, e1, 0, 0 (point elimination); the camera vectors of the
+  // Schur kernel's self pairs read it
+  double* rec;
   double *V, *gp, *gc, *diagU;
   // damped quantities
   double *Vinv, *ep;
-  void* Q;  // float or double [no][6]: w Jp Vinv of each observation
   void* S;  // float or double [nnzb][81]; diagonal blocks live in Sdiag
   double *Sdiag, *bS, *Minv;  // FP64 diagonal blocks (damped in place), rhs, block-Jacobi inverse
   // step

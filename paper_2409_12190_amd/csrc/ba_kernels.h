@@ -18,6 +18,12 @@ struct LinArgs {
   double *r, *w;
   void* J;
   double *V, *gp, *part_cost, *part_gmax;
+  double* rec;
+  // point elimination of the same pass (damping with the current lambda)
+  double dmin, dmax;
+  double *Vinv, *ep;
+  DevScalars* dev;
+  GridSync* gs;
 };
 
 struct DampArgs {
@@ -32,21 +38,19 @@ struct DampArgs {
 struct PointQArgs {
   int64_t no;
   const int32_t* o_pt;
-  const void* J;
-  const double *w, *Vinv;
-  void* Q;
+  const double *w, *Vinv, *ep;
+  void* J;      // reads Jp of each row, writes Q, w into it
+  double* rec;  // writes e = Jp ep
 };
 
 struct SchurArgs {
   int nwg;  // workgroups of the slot table
-  const int32_t *slot_blk, *slot_pb, *slot_pe, *slot_lead, *pair_x, *pair_y, *blk_row, *S_ptr;
-  const void *J, *Q;
-  const double* w;
+  const int32_t *slot_blk, *slot_lead, *blk_row, *S_ptr, *stab, *swptr;
+  const void* J;
+  const double* rec;
   void* S;
   double* Sdiag;
   // camera vectors from the self pairs of the diagonal blocks
-  const int32_t* o_pt;
-  const double *r, *ep;
   double *gc, *bS, *diagU;
 };
 

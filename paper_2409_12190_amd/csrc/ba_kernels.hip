@@ -27,8 +27,80 @@ __device__ __forceinline__ void load_J(const T* __restrict__ J, double Jc[2][9],
 #pragma unroll
     for (int m = 0; m < 9; ++m) Jc[i][m] = (double)J[i * 9 + m];
 #pragma unroll
-    for (int m = 0; m < 3; ++m) Jp[i][m] = (double)J[18 + i * 3 + m];
+    for (int m = 0; m < 3; ++m) Jp[i][m] = (double)J[JP + i * 3 + m];
   }
+}
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+
+// Jc and Jp into an observation row (values [0, 24): whole 16-byte stores;
+// rows are 16-byte aligned)
+__device__ __forceinline__ void store_row(float* J, const double Jc[2][9], const double Jp[2][3]) {
+  float v[24];
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+#pragma unroll
+    for (int m = 0; m < 9; ++m) v[i * 9 + m] = (float)Jc[i][m];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) v[JP + i * 3 + m] = (float)Jp[i][m];
+  }
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    f32x4 t;
+    t.x = v[4 * k];
+    t.y = v[4 * k + 1];
+    t.z = v[4 * k + 2];
+    t.w = v[4 * k + 3];
+    *reinterpret_cast<f32x4*>(J + 4 * k) = t;
+  }
+}
+
+__device__ __forceinline__ void store_row(double* J, const double Jc[2][9], const double Jp[2][3]) {
+  double v[24];
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+#pragma unroll
+    for (int m = 0; m < 9; ++m) v[i * 9 + m] = Jc[i][m];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) v[JP + i * 3 + m] = Jp[i][m];
+  }
+#pragma unroll
+  for (int k = 0; k < 12; ++k) {
+    f64x2 t;
+    t.x = v[2 * k];
+    t.y = v[2 * k + 1];
+    *reinterpret_cast<f64x2*>(J + 2 * k) = t;
+  }
+}
+
+// Q, w and a zero into values [JQ, NJ) of an observation row
+__device__ __forceinline__ void store_q(float* J, const double Q[6], double w) {
+  f32x4 t;
+  t.x = (float)Q[0];
+  t.y = (float)Q[1];
+  t.z = (float)Q[2];
+  t.w = (float)Q[3];
+  *reinterpret_cast<f32x4*>(J + JQ) = t;
+  t.x = (float)Q[4];
+  t.y = (float)Q[5];
+  t.z = (float)w;
+  t.w = 0.0f;
+  *reinterpret_cast<f32x4*>(J + JQ + 4) = t;
+}
+
+__device__ __forceinline__ void store_q(double* J, const double Q[6], double w) {
+  f64x2 t;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    t.x = Q[2 * k];
+    t.y = Q[2 * k + 1];
+    *reinterpret_cast<f64x2*>(J + JQ + 2 * k) = t;
+  }
+  t.x = w;
+  t.y = 0.0;
+  *reinterpret_cast<f64x2*>(J + JW) = t;
 }
 
 __device__ __forceinline__ void load_sym3(const double* __restrict__ s, double M[3][3]) {
@@ -38,10 +110,83 @@ __device__ __forceinline__ void load_sym3(const double* __restrict__ s, double M
 }
 
 // ---------------------------------------------------------------------------
-// observation pass 1: residual, Jacobian blocks, robust weight, cost, and the
-// point-keyed blocks V_j = sum w Jp^T Jp, gp_j = sum w Jp^T r
-// (Alg. 1 first two lines; Sec. IV-A-2 batched Jacobian values).
-// One workgroup per point-aligned chunk; segmented sums in LDS, fixed order.
+// damped point block V*_j = V_j + lambda clamp(diag V_j) (Eq. 2 with the
+// clamp of Sec. IV-B-3), its inverse (adjugate / determinant, FP64) and
+// ep_j = V*_j^-1 gp_j; the determinant test flags a block that is not
+// positive definite.  Returns the inverse as its upper triangle.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void damp_point(const double v[6], const double g[3], double lam, double dmin,
+                                           double dmax, double vi[6], double e[3], int* error) {
+  const double m00 = v[0] + lam * fmin(fmax(v[0], dmin), dmax);
+  const double m11 = v[3] + lam * fmin(fmax(v[3], dmin), dmax);
+  const double m22 = v[5] + lam * fmin(fmax(v[5], dmin), dmax);
+  const double m01 = v[1], m02 = v[2], m12 = v[4];
+  const double c00 = m11 * m22 - m12 * m12;
+  const double c01 = m02 * m12 - m01 * m22;
+  const double c02 = m01 * m12 - m02 * m11;
+  const double c11 = m00 * m22 - m02 * m02;
+  const double c12 = m01 * m02 - m00 * m12;
+  const double c22 = m00 * m11 - m01 * m01;
+  const double det = m00 * c00 + m01 * c01 + m02 * c02;
+  if (!(det > 0.0) || !isfinite(det)) atomicOr(error, (int)ERR_POINT_BLOCK);
+  const double id = 1.0 / det;
+  vi[0] = c00 * id; vi[1] = c01 * id; vi[2] = c02 * id;
+  vi[3] = c11 * id; vi[4] = c12 * id; vi[5] = c22 * id;
+  e[0] = (c00 * g[0] + c01 * g[1] + c02 * g[2]) * id;
+  e[1] = (c01 * g[0] + c11 * g[1] + c12 * g[2]) * id;
+  e[2] = (c02 * g[0] + c12 * g[1] + c22 * g[2]) * id;
+}
+
+// the PCG grid barrier of this step starts from a clean state (threads
+// 0..MAX_BARRIER_GROUPS of the first workgroup)
+__device__ __forceinline__ void reset_grid_sync(GridSync* gs, int j) {
+  if (j <= MAX_BARRIER_GROUPS) {
+    if (j == 0) {
+      gs->count = 0u;
+      gs->gen = 0u;
+    } else {
+      gs->group[j - 1].count = 0u;
+    }
+  }
+}
+
+// Q_x = w Jp_x V*^-1 and e_x = Jp_x ep_j of one observation
+__device__ __forceinline__ void point_factors(const double Jp[2][3], double w, const double vi[6],
+                                              const double ep[3], double Q[6], double e[2]) {
+  double Vi[3][3];
+  load_sym3(vi, Vi);
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+#pragma unroll
+    for (int m = 0; m < 3; ++m) Q[3 * i + m] = w * (Jp[i][0] * Vi[0][m] + Jp[i][1] * Vi[1][m] + Jp[i][2] * Vi[2][m]);
+    e[i] = Jp[i][0] * ep[0] + Jp[i][1] * ep[1] + Jp[i][2] * ep[2];
+  }
+}
+
+__device__ __forceinline__ void store_rec(double* rec, double r0, double r1, double w, double e0, double e1) {
+  f64x2* rc = reinterpret_cast<f64x2*>(rec);
+  f64x2 t;
+  t.x = r0;
+  t.y = r1;
+  rc[0] = t;
+  t.x = w;
+  t.y = 0.0;
+  rc[1] = t;
+  t.x = e0;
+  t.y = e1;
+  rc[2] = t;
+  t.x = 0.0;
+  t.y = 0.0;
+  rc[3] = t;
+}
+
+// ---------------------------------------------------------------------------
+// observation pass: residual, Jacobian blocks, robust weight, cost, the
+// point-keyed blocks V_j = sum w Jp^T Jp, gp_j = sum w Jp^T r (Alg. 1 first
+// two lines; Sec. IV-A-2 batched Jacobian values), and, with the current
+// lambda, the point elimination: V*_j^-1, ep_j and per observation the Schur
+// factor Q_x and e_x.  One workgroup per point-aligned chunk; segmented sums
+// in LDS, fixed order.  Every observation row and record is written whole.
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(CHUNK) void k_linearize(LinArgs a) {
@@ -51,18 +196,24 @@ __global__ __launch_bounds__(CHUNK) void k_linearize(LinArgs a) {
   const int x0 = a.chunk_ptr[c], x1 = a.chunk_ptr[c + 1];
   const int t = threadIdx.x;
   const int x = x0 + t;
+  if (c == 0) reset_grid_sync(a.gs, t);
   double cost = 0.0;
+  double Jp[2][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
+  double rx = 0.0, ry = 0.0, w = 0.0;
+  int pj = 0;
   if (x < x1) {
-    const int ci = a.o_cam[x], pj = a.o_pt[x];
+    const int ci = a.o_cam[x];
+    pj = a.o_pt[x];
     const Camera cam = load_camera(a.cams + 10 * (size_t)ci);
     const double* P = a.pts + 3 * (size_t)pj;
-    double Jc[2][9], Jp[2][3];
+    double Jc[2][9];
     const Proj pr = project_jac(cam, v3(P[0], P[1], P[2]), Jc, Jp);
-    const double rx = pr.px - a.o_xy[2 * (size_t)x], ry = pr.py - a.o_xy[2 * (size_t)x + 1];
+    rx = pr.px - a.o_xy[2 * (size_t)x];
+    ry = pr.py - a.o_xy[2 * (size_t)x + 1];
     double drho;
     const double rho = robust_rho(rx * rx + ry * ry, a.huber, &drho);
     const double om = a.o_w[x];
-    const double w = om * drho;
+    w = om * drho;
     cost = 0.5 * om * rho;
     if (a.fixed[ci]) {
 #pragma unroll
@@ -73,14 +224,7 @@ __global__ __launch_bounds__(CHUNK) void k_linearize(LinArgs a) {
     a.r[2 * (size_t)x] = rx;
     a.r[2 * (size_t)x + 1] = ry;
     a.w[x] = w;
-    T* J = reinterpret_cast<T*>(a.J) + (size_t)x * NJ;
-#pragma unroll
-    for (int i = 0; i < 2; ++i) {
-#pragma unroll
-      for (int m = 0; m < 9; ++m) J[i * 9 + m] = (T)Jc[i][m];
-#pragma unroll
-      for (int m = 0; m < 3; ++m) J[18 + i * 3 + m] = (T)Jp[i][m];
-    }
+    store_row(reinterpret_cast<T*>(a.J) + (size_t)x * NJ, Jc, Jp);
     sh[0][t] = w * (Jp[0][0] * Jp[0][0] + Jp[1][0] * Jp[1][0]);
     sh[1][t] = w * (Jp[0][0] * Jp[0][1] + Jp[1][0] * Jp[1][1]);
     sh[2][t] = w * (Jp[0][0] * Jp[0][2] + Jp[1][0] * Jp[1][2]);
@@ -94,7 +238,11 @@ __global__ __launch_bounds__(CHUNK) void k_linearize(LinArgs a) {
   __syncthreads();
   double gmax = 0.0;
   const int j0 = a.chunk_pt[c], j1 = a.chunk_pt[c + 1];
-  for (int j = j0 + t; j < j1; j += blockDim.x) {
+  const double lam = a.dev->lambda;
+  // a chunk holds at most CHUNK points: one per thread
+  const int j = j0 + t;
+  double vi[6], ep[3];
+  if (j < j1) {
     double s[9];
 #pragma unroll
     for (int q = 0; q < 9; ++q) s[q] = 0.0;
@@ -106,7 +254,39 @@ __global__ __launch_bounds__(CHUNK) void k_linearize(LinArgs a) {
     for (int q = 0; q < 6; ++q) a.V[6 * (size_t)j + q] = s[q];
 #pragma unroll
     for (int q = 0; q < 3; ++q) a.gp[3 * (size_t)j + q] = s[6 + q];
-    gmax = fmax(gmax, fmax(fabs(s[6]), fmax(fabs(s[7]), fabs(s[8]))));
+    gmax = fmax(fabs(s[6]), fmax(fabs(s[7]), fabs(s[8])));
+    damp_point(s, s + 6, lam, a.dmin, a.dmax, vi, ep, &a.dev->error);
+#pragma unroll
+    for (int q = 0; q < 6; ++q) a.Vinv[6 * (size_t)j + q] = vi[q];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) a.ep[3 * (size_t)j + q] = ep[q];
+  }
+  __syncthreads();  // the observation sums are consumed: sh holds the points now
+  if (j < j1) {
+#pragma unroll
+    for (int q = 0; q < 6; ++q) sh[q][t] = vi[q];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) sh[6 + q][t] = ep[q];
+  }
+  __syncthreads();
+  if (x < x1) {
+    const int k = pj - j0;
+    double pv[6], pe[3], Q[6], e[2];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) pv[q] = sh[q][k];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) pe[q] = sh[6 + q][k];
+    // from Jp as stored (precision T), like every other reader of the row:
+    // both sides of the Schur pair product and the right-hand side then use
+    // one rounding of Jp, which keeps the reduced system symmetric
+    double Jq[2][3];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int m = 0; m < 3; ++m) Jq[i][m] = (double)(T)Jp[i][m];
+    point_factors(Jq, w, pv, pe, Q, e);
+    store_q(reinterpret_cast<T*>(a.J) + (size_t)x * NJ, Q, w);
+    store_rec(a.rec + 8 * (size_t)x, rx, ry, w, e[0], e[1]);
   }
   const double tot = block_sum(cost, red);
   const double gm = block_max(gmax, red);
@@ -131,59 +311,52 @@ __global__ __launch_bounds__(256) void k_reduce_cost(const double* __restrict__ 
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_damp_points(DampArgs a) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j <= MAX_BARRIER_GROUPS) {  // the PCG grid barrier of this step starts from a clean state
-    if (j == 0) {
-      a.gs->count = 0u;
-      a.gs->gen = 0u;
-    } else {
-      a.gs->group[j - 1].count = 0u;
-    }
-  }
+  reset_grid_sync(a.gs, j);
   if (j >= a.np) return;
-  const double lam = a.dev->lambda;
-  const double* v = a.V + 6 * (size_t)j;
-  const double m00 = v[0] + lam * fmin(fmax(v[0], a.dmin), a.dmax);
-  const double m11 = v[3] + lam * fmin(fmax(v[3], a.dmin), a.dmax);
-  const double m22 = v[5] + lam * fmin(fmax(v[5], a.dmin), a.dmax);
-  const double m01 = v[1], m02 = v[2], m12 = v[4];
-  const double c00 = m11 * m22 - m12 * m12;
-  const double c01 = m02 * m12 - m01 * m22;
-  const double c02 = m01 * m12 - m02 * m11;
-  const double c11 = m00 * m22 - m02 * m02;
-  const double c12 = m01 * m02 - m00 * m12;
-  const double c22 = m00 * m11 - m01 * m01;
-  const double det = m00 * c00 + m01 * c01 + m02 * c02;
-  if (!(det > 0.0) || !isfinite(det)) atomicOr(&a.dev->error, (int)ERR_POINT_BLOCK);
-  const double id = 1.0 / det;
-  double* o = a.Vinv + 6 * (size_t)j;
-  o[0] = c00 * id; o[1] = c01 * id; o[2] = c02 * id;
-  o[3] = c11 * id; o[4] = c12 * id; o[5] = c22 * id;
-  const double* g = a.gp + 3 * (size_t)j;
-  double* e = a.ep + 3 * (size_t)j;
-  e[0] = (c00 * g[0] + c01 * g[1] + c02 * g[2]) * id;
-  e[1] = (c01 * g[0] + c11 * g[1] + c12 * g[2]) * id;
-  e[2] = (c02 * g[0] + c12 * g[1] + c22 * g[2]) * id;
+  double v[6], g[3], vi[6], e[3];
+#pragma unroll
+  for (int q = 0; q < 6; ++q) v[q] = a.V[6 * (size_t)j + q];
+#pragma unroll
+  for (int q = 0; q < 3; ++q) g[q] = a.gp[3 * (size_t)j + q];
+  damp_point(v, g, a.dev->lambda, a.dmin, a.dmax, vi, e, &a.dev->error);
+#pragma unroll
+  for (int q = 0; q < 6; ++q) a.Vinv[6 * (size_t)j + q] = vi[q];
+#pragma unroll
+  for (int q = 0; q < 3; ++q) a.ep[3 * (size_t)j + q] = e[q];
 }
 
 // ---------------------------------------------------------------------------
 // per-observation factor of the Schur product: Q_x = w_x Jp_x Vinv_j (2x3),
-// stored in the Jacobian precision (one thread per observation).
+// stored in the Jacobian precision into the observation's row with w, and
+// e_x = Jp_x ep_j (FP64, for the Schur right-hand side) into its record
+// (one thread per observation).
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(256) void k_point_q(PointQArgs a) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   if (x >= a.no) return;
-  const T* J = reinterpret_cast<const T*>(a.J) + (size_t)x * NJ + 18;
-  double Vi[3][3];
-  load_sym3(a.Vinv + 6 * (size_t)a.o_pt[x], Vi);
+  T* row = reinterpret_cast<T*>(a.J) + (size_t)x * NJ;
+  const int j = a.o_pt[x];
+  double Jq[2][3], vi[6], pe[3], Q[6], e[2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int m = 0; m < 3; ++m) Jq[i][m] = (double)row[JP + 3 * i + m];
+#pragma unroll
+  for (int q = 0; q < 6; ++q) vi[q] = a.Vinv[6 * (size_t)j + q];
+#pragma unroll
+  for (int q = 0; q < 3; ++q) pe[q] = a.ep[3 * (size_t)j + q];
   const double w = a.w[x];
-  T* Q = reinterpret_cast<T*>(a.Q) + (size_t)x * 6;
-#pragma unroll
-  for (int i = 0; i < 2; ++i) {
-    const double j0 = (double)J[3 * i], j1 = (double)J[3 * i + 1], j2 = (double)J[3 * i + 2];
-#pragma unroll
-    for (int m = 0; m < 3; ++m) Q[3 * i + m] = (T)(w * (j0 * Vi[0][m] + j1 * Vi[1][m] + j2 * Vi[2][m]));
-  }
+  point_factors(Jq, w, vi, pe, Q, e);
+  store_q(row, Q, w);
+  f64x2* rc = reinterpret_cast<f64x2*>(a.rec + 8 * (size_t)x + 4);
+  f64x2 t;
+  t.x = e[0];
+  t.y = e[1];
+  rc[0] = t;
+  t.x = 0.0;
+  t.y = 0.0;
+  rc[1] = t;
 }
 
 // ---------------------------------------------------------------------------
@@ -192,121 +365,90 @@ __global__ __launch_bounds__(256) void k_point_q(PointQArgs a) {
 // y in camera b,
 //   S_ab  = -sum Jc_x^T (Q_x (w_y Jp_y)^T) Jc_y                  (a < b)
 //   S_aa' = sum Jc_x^T ([x = y] w_x I - Q_x (w_y Jp_y)^T) Jc_y   (undamped)
-// Each workgroup holds SCHUR_SLOTS chunk slots; SCHUR_LANES = 3 lanes share a
-// chunk, lane k accumulating columns 3k..3k+2 of the block (27 values) over
-// the chunk's pairs in registers, with the next pair's rows loaded while the
-// current one is multiplied.  The chunks of one block sit in consecutive
-// slots of one workgroup and are summed in slot order through LDS: no
-// atomics, fixed summation order.  Off-diagonal blocks go to S (precision T);
-// diagonal blocks, still to be damped, to the FP64 buffer Sdiag.  The self
-// pairs (x, x) of a diagonal block visit every observation of its camera
-// once, so the same lanes also form the camera vectors
+// Each workgroup holds SCHUR_SLOTS chunk slots, SCHUR_WAVE_SLOTS per
+// wavefront; SCHUR_LANES = 3 lanes share a chunk, lane k accumulating
+// columns 3k..3k+2 of the block (27 values) in registers.  A wavefront
+// advances its 21 chunks in lockstep steps: at each step the whole
+// wavefront stages the two observation rows of every chunk's current pair
+// in LDS with contiguous 16-byte loads (8 lanes per 128-byte row), the next
+// step's rows being in flight while the current pair is multiplied out of
+// LDS; so every row costs one cache line instead of a broadcast load per
+// value.  The chunks of one block sit in consecutive slots of one workgroup
+// and are summed in slot order through LDS: no atomics, fixed summation
+// order.  Off-diagonal blocks go to S (precision T); diagonal blocks, still
+// to be damped, to the FP64 buffer Sdiag.  The self pairs (x, x) of a
+// diagonal block visit every observation of its camera once, so the same
+// lanes also form the camera vectors
 //   gc_a = sum w Jc^T r,  diagU_a = diag(sum w Jc^T Jc),
-//   bS_a + gc_a = sum w Jc^T Jp ep_j   (ep_j = Vinv_j gp_j),
-// which saves a pass over the observations in camera order.
+//   bS_a + gc_a = sum w Jc^T e,  e = Jp ep_j,
+// from the observation's FP64 record, staged in place of the (repeated) y
+// row: this saves a pass over the observations in camera order.
 // ---------------------------------------------------------------------------
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-typedef float f32x2 __attribute__((ext_vector_type(2)));
-typedef double f64x2 __attribute__((ext_vector_type(2)));
-
-// the values of pair (x, y) one lane needs (columns c0..c0+2)
-template <typename T> struct PairRows {
-  T jx[18];  // Jc of x (both rows)
-  T jy[6];   // Jc of y: row 0 then row 1 at columns c0..c0+2
-  T py[6];   // Jp of y
-  T q[6];    // Q of x
-  double w;  // weight of y
+template <typename T> struct SchurStage {
+  static constexpr int ROW_BYTES = NJ * (int)sizeof(T);          // 128 or 256
+  static constexpr int PIECES = ROW_BYTES / 16;                   // 16-byte pieces per row
+  static constexpr int EPP = 16 / (int)sizeof(T);                 // values per piece
+  static constexpr int LOADS = (SCHUR_ROWS * PIECES + 63) / 64;   // staging loads per lane
+  static constexpr int WAVE_BYTES = SCHUR_ROWS * ROW_BYTES;
 };
 
-__device__ __forceinline__ void load_rows(PairRows<float>& v, const float* J, const float* Q,
-                                          const double* w, int x, int y, int c0) {
-  const float* jx = J + (size_t)x * NJ;  // 96-byte rows: 16-byte aligned
-  const float* jy = J + (size_t)y * NJ;
-  const float* qx = Q + (size_t)x * 6;   // 24-byte rows: 8-byte aligned
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const f32x4 t = *reinterpret_cast<const f32x4*>(jx + 4 * k);
-    v.jx[4 * k] = t.x;
-    v.jx[4 * k + 1] = t.y;
-    v.jx[4 * k + 2] = t.z;
-    v.jx[4 * k + 3] = t.w;
-  }
-  {
-    const f32x2 t = *reinterpret_cast<const f32x2*>(jx + 16);
-    v.jx[16] = t.x;
-    v.jx[17] = t.y;
-  }
-#pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    const f32x2 t = *reinterpret_cast<const f32x2*>(jy + 18 + 2 * k);
-    v.py[2 * k] = t.x;
-    v.py[2 * k + 1] = t.y;
-    const f32x2 u = *reinterpret_cast<const f32x2*>(qx + 2 * k);
-    v.q[2 * k] = u.x;
-    v.q[2 * k + 1] = u.y;
-  }
-#pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    v.jy[k] = jy[c0 + k];
-    v.jy[3 + k] = jy[9 + c0 + k];
-  }
-  v.w = w[y];
+constexpr int SCHUR_PART_BYTES = SCHUR_SLOTS * 81 * 8;
+constexpr int schur_lds_bytes(int stage) { return stage > SCHUR_PART_BYTES ? stage : SCHUR_PART_BYTES; }
+
+// piece p of staged row r lives at piece p ^ (slot & 7): the rows of the
+// wavefront's slots start in different banks
+__device__ __forceinline__ int stage_piece(int r, int p) { return p ^ ((r >> 1) & 7); }
+
+template <typename T>
+__device__ __forceinline__ T stage_val(const unsigned char* st, int r, int e) {
+  constexpr int EPP = SchurStage<T>::EPP;
+  return *reinterpret_cast<const T*>(st + r * SchurStage<T>::ROW_BYTES + stage_piece(r, e / EPP) * 16 +
+                                     (e % EPP) * (int)sizeof(T));
 }
 
-__device__ __forceinline__ void load_rows(PairRows<double>& v, const double* J, const double* Q,
-                                          const double* w, int x, int y, int c0) {
-  const double* jx = J + (size_t)x * NJ;  // 192-byte rows
-  const double* jy = J + (size_t)y * NJ;
-  const double* qx = Q + (size_t)x * 6;   // 48-byte rows
-#pragma unroll
-  for (int k = 0; k < 9; ++k) {
-    const f64x2 t = *reinterpret_cast<const f64x2*>(jx + 2 * k);
-    v.jx[2 * k] = t.x;
-    v.jx[2 * k + 1] = t.y;
+// 16-byte piece p of staged row r, as EPP values
+template <typename T>
+__device__ __forceinline__ void stage_piece_vals(const unsigned char* st, int r, int p, T* out) {
+  const unsigned char* src = st + r * SchurStage<T>::ROW_BYTES + stage_piece(r, p) * 16;
+  if constexpr (sizeof(T) == 4) {
+    const f32x4 t = *reinterpret_cast<const f32x4*>(src);
+    out[0] = t.x;
+    out[1] = t.y;
+    out[2] = t.z;
+    out[3] = t.w;
+  } else {
+    const f64x2 t = *reinterpret_cast<const f64x2*>(src);
+    out[0] = t.x;
+    out[1] = t.y;
   }
-#pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    const f64x2 t = *reinterpret_cast<const f64x2*>(jy + 18 + 2 * k);
-    v.py[2 * k] = t.x;
-    v.py[2 * k + 1] = t.y;
-    const f64x2 u = *reinterpret_cast<const f64x2*>(qx + 2 * k);
-    v.q[2 * k] = u.x;
-    v.q[2 * k + 1] = u.y;
-  }
-#pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    v.jy[k] = jy[c0 + k];
-    v.jy[3 + k] = jy[9 + c0 + k];
-  }
-  v.w = w[y];
 }
 
 // acc[r][c] += (Jc_x^T M Jc_y)[r][c0 + c],
 // M = [x = y] w_y I - w_y Q_x Jp_y^T
 template <typename T>
-__device__ __forceinline__ void pair_update(double (&acc)[9][3], const PairRows<T>& v, bool self) {
+__device__ __forceinline__ void pair_update(double (&acc)[9][3], const T (&jx)[20], const T (&q)[8],
+                                            const T (&jy)[6], const T (&py)[6], double w, bool self) {
   double M[2][2];
 #pragma unroll
   for (int i2 = 0; i2 < 2; ++i2)
 #pragma unroll
     for (int k2 = 0; k2 < 2; ++k2)
-      M[i2][k2] = -v.w * ((double)v.q[3 * i2] * (double)v.py[3 * k2] +
-                          (double)v.q[3 * i2 + 1] * (double)v.py[3 * k2 + 1] +
-                          (double)v.q[3 * i2 + 2] * (double)v.py[3 * k2 + 2]);
+      M[i2][k2] = -w * ((double)q[3 * i2] * (double)py[3 * k2] + (double)q[3 * i2 + 1] * (double)py[3 * k2 + 1] +
+                        (double)q[3 * i2 + 2] * (double)py[3 * k2 + 2]);
   if (self) {
-    M[0][0] += v.w;
-    M[1][1] += v.w;
+    M[0][0] += w;
+    M[1][1] += w;
   }
   double g0[3], g1[3];
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    const double a0 = (double)v.jy[c], a1 = (double)v.jy[3 + c];
+    const double a0 = (double)jy[c], a1 = (double)jy[3 + c];
     g0[c] = M[0][0] * a0 + M[0][1] * a1;
     g1[c] = M[1][0] * a0 + M[1][1] * a1;
   }
 #pragma unroll
   for (int r = 0; r < 9; ++r) {
-    const double j0 = (double)v.jx[r], j1 = (double)v.jx[9 + r];
+    const double j0 = (double)jx[r], j1 = (double)jx[9 + r];
 #pragma unroll
     for (int c = 0; c < 3; ++c) acc[r][c] += j0 * g0[c] + j1 * g1[c];
   }
@@ -314,76 +456,135 @@ __device__ __forceinline__ void pair_update(double (&acc)[9][3], const PairRows<
 
 template <typename T>
 __global__ __launch_bounds__(SCHUR_THREADS) void k_schur_pairs(SchurArgs a) {
-  // per slot: the 81 block values; afterwards (diagonal blocks) the camera
-  // vectors gc, sum w Jc^T Jp ep and diag U of the slot's self pairs
-  __shared__ double part[SCHUR_SLOTS][81];
+  using SS = SchurStage<T>;
+  // staging rows during the steps; per slot the 81 block values afterwards,
+  // then (diagonal blocks) the camera vectors
+  __shared__ __align__(16) unsigned char lds[schur_lds_bytes(SCHUR_WAVES * SS::WAVE_BYTES)];
+  double(*part)[81] = reinterpret_cast<double(*)[81]>(lds);
   // workgroups are dispatched round-robin over the 8 XCDs: XCD k takes the
   // k-th contiguous range of slot workgroups, so that neighbouring rows (which
   // read the same observations) share that XCD's L2
   const int per = (a.nwg + 7) / 8;
   const int lw = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
   if (lw >= a.nwg) return;
-  const int slot = threadIdx.x / SCHUR_LANES;
-  const int c0 = 3 * (threadIdx.x - SCHUR_LANES * slot);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int s = lane / SCHUR_LANES;              // slot within the wavefront (s < 21 computes)
+  const int c0 = 3 * (lane - SCHUR_LANES * s);
+  const bool computes = s < SCHUR_WAVE_SLOTS;
+  const int slot = wave * SCHUR_WAVE_SLOTS + s;  // slot within the workgroup
   const size_t sbase = (size_t)lw * SCHUR_SLOTS;
-  const T* __restrict__ Jall = reinterpret_cast<const T*>(a.J);
-  const T* __restrict__ Qall = reinterpret_cast<const T*>(a.Q);
-  double vg[3] = {0.0, 0.0, 0.0}, vb[3] = {0.0, 0.0, 0.0}, vu[3] = {0.0, 0.0, 0.0};
+  unsigned char* st = lds + wave * SS::WAVE_BYTES;
+  const unsigned char* __restrict__ Jb = reinterpret_cast<const unsigned char*>(a.J);
+  const unsigned char* __restrict__ Rb = reinterpret_cast<const unsigned char*>(a.rec);
+
   bool diag_slot = false;
-  if (slot < SCHUR_SLOTS) {
+  if (computes) {
     const int e = a.slot_blk[sbase + slot];
-    double acc[9][3];
-#pragma unroll
-    for (int r = 0; r < 9; ++r)
-#pragma unroll
-      for (int c = 0; c < 3; ++c) acc[r][c] = 0.0;
-    const int pb = e >= 0 ? a.slot_pb[sbase + slot] : 0;
-    const int pe = e >= 0 ? a.slot_pe[sbase + slot] : 0;
     // (a camera without observations has an empty diagonal block: zeros)
     diag_slot = e >= 0 && a.S_ptr[a.blk_row[e]] == e;
-    if (pb < pe) {
-      // software pipeline: rows of pair i + 1 and indices of pair i + 2 are
-      // in flight while pair i is multiplied (indices clamped to the chunk)
-      int x = a.pair_x[pb], y = a.pair_y[pb];
-      PairRows<T> cur;
-      load_rows(cur, Jall, Qall, a.w, x, y, c0);
-      int xn = a.pair_x[min(pb + 1, pe - 1)], yn = a.pair_y[min(pb + 1, pe - 1)];
-#pragma unroll 2
-      for (int i = pb; i < pe; ++i) {
-        PairRows<T> nxt;
-        load_rows(nxt, Jall, Qall, a.w, xn, yn, c0);
-        const int i2 = min(i + 2, pe - 1);
-        const int xa = a.pair_x[i2], ya = a.pair_y[i2];
-        pair_update(acc, cur, x == y);
-        cur = nxt;
-        x = xn;
-        y = yn;
-        xn = xa;
-        yn = ya;
-      }
-      if (diag_slot) {
-        // each observation of the camera is the self pair of exactly one
-        // chunk of the diagonal block: the camera vectors of Alg. 1
-        // (gradient J^T W r, the Schur right-hand side term, diag of U)
-        for (int i = pb; i < pe; ++i) {
-          const int xs = a.pair_x[i];
-          if (a.pair_y[i] != xs) continue;
-          const T* Jx = Jall + (size_t)xs * NJ;
-          const double wx = a.w[xs];
-          const double* ep = a.ep + 3 * (size_t)a.o_pt[xs];
-          const double e0 = (double)Jx[18] * ep[0] + (double)Jx[19] * ep[1] + (double)Jx[20] * ep[2];
-          const double e1 = (double)Jx[21] * ep[0] + (double)Jx[22] * ep[1] + (double)Jx[23] * ep[2];
-          const double r0 = a.r[2 * (size_t)xs], r1 = a.r[2 * (size_t)xs + 1];
+  }
+  const int t0 = a.swptr[(size_t)lw * SCHUR_WAVES + wave];
+  const int nt = a.swptr[(size_t)lw * SCHUR_WAVES + wave + 1] - t0;
+  const int* __restrict__ tab = a.stab + (size_t)t0 * SCHUR_ROWS;
+
+  // staging: lane `lane` moves piece (64 k + lane) % PIECES of row
+  // (64 k + lane) / PIECES for k < LOADS.  Every load is issued without a
+  // branch (inactive slots read row 0, rows past SCHUR_ROWS repeat the last
+  // one), so the compiler's wait counting keeps the next step's loads in
+  // flight across the multiplication of the current one.
+  int code[SS::LOADS];
+  f32x4 buf[SS::LOADS];
+  auto fetch_codes = [&](int t) {
+#pragma unroll
+    for (int k = 0; k < SS::LOADS; ++k) {
+      const int r = min((64 * k + lane) / SS::PIECES, SCHUR_ROWS - 1);
+      code[k] = tab[(size_t)t * SCHUR_ROWS + r];
+    }
+  };
+  auto fetch_rows = [&]() {
+#pragma unroll
+    for (int k = 0; k < SS::LOADS; ++k) {
+      const int q = 64 * k + lane, r = q / SS::PIECES, p = q % SS::PIECES;
+      const int c = code[k];
+      const int x = c >= 0 ? c : (c < -1 ? -2 - c : 0);
+      const bool rec = c < -1 && (r & 1) && p < 4;  // self pair: the record replaces the y row
+      const unsigned char* src = rec ? Rb + (size_t)x * 64 + p * 16 : Jb + (size_t)x * SS::ROW_BYTES + p * 16;
+      buf[k] = *reinterpret_cast<const f32x4*>(src);
+    }
+  };
+  auto stage_rows = [&]() {
+#pragma unroll
+    for (int k = 0; k < SS::LOADS; ++k) {
+      const int q = 64 * k + lane, r = q / SS::PIECES, p = q % SS::PIECES;
+      if (r < SCHUR_ROWS) *reinterpret_cast<f32x4*>(st + r * SS::ROW_BYTES + stage_piece(r, p) * 16) = buf[k];
+    }
+  };
+
+  double acc[9][3];
+#pragma unroll
+  for (int r = 0; r < 9; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) acc[r][c] = 0.0;
+  double vg[3] = {0.0, 0.0, 0.0}, vb[3] = {0.0, 0.0, 0.0}, vu[3] = {0.0, 0.0, 0.0};
+
+  const int ys = min(2 * s + 1, SCHUR_ROWS - 1);  // this lane's y code (lane 63 reads a valid one)
+  if (nt > 0) {
+    fetch_codes(0);
+    fetch_rows();
+    int ycode = computes ? tab[ys] : -1;
+    fetch_codes(min(1, nt - 1));
+    stage_rows();
+    for (int t = 0; t < nt; ++t) {
+      // rows of step t + 1 in flight, codes of step t + 2 requested (steps
+      // past the last repeat it: loaded, never staged)
+      fetch_rows();
+      fetch_codes(min(t + 2, nt - 1));
+      const int yn = tab[(size_t)min(t + 1, nt - 1) * SCHUR_ROWS + ys];
+      const int ycode_next = computes ? yn : -1;
+      __builtin_amdgcn_wave_barrier();
+      if (computes && ycode != -1) {
+        const bool self = ycode < -1;
+        const int rx = 2 * s, ry = self ? rx : rx + 1;
+        T jx[20], q[8], jy[6], py[6];
+#pragma unroll
+        for (int p = 0; p < 20 / SS::EPP; ++p) stage_piece_vals<T>(st, rx, p, jx + p * SS::EPP);
+#pragma unroll
+        for (int p = 0; p < 8 / SS::EPP; ++p) stage_piece_vals<T>(st, rx, JQ / SS::EPP + p, q + p * SS::EPP);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          jy[c] = stage_val<T>(st, ry, c0 + c);
+          jy[3 + c] = stage_val<T>(st, ry, 9 + c0 + c);
+        }
+#pragma unroll
+        for (int m = 0; m < 6; ++m) py[m] = stage_val<T>(st, ry, JP + m);
+        const double w = (double)stage_val<T>(st, ry, JW);
+        pair_update<T>(acc, jx, q, jy, py, w, self);
+        if (self) {
+          // the record r0, r1, w, 0, e0, e1 staged in row rx + 1 (FP64)
+          double rv[6];
+#pragma unroll
+          for (int p = 0; p < 3; ++p) {
+            const f64x2 v = *reinterpret_cast<const f64x2*>(st + (rx + 1) * SS::ROW_BYTES + stage_piece(rx + 1, p) * 16);
+            rv[2 * p] = v.x;
+            rv[2 * p + 1] = v.y;
+          }
+          const double r0 = rv[0], r1 = rv[1], wx = rv[2], e0 = rv[4], e1 = rv[5];
 #pragma unroll
           for (int c = 0; c < 3; ++c) {
-            const double j0 = (double)Jx[c0 + c], j1 = (double)Jx[9 + c0 + c];
+            const double j0 = (double)jy[c], j1 = (double)jy[3 + c];
             vg[c] += wx * (j0 * r0 + j1 * r1);
             vb[c] += wx * (j0 * e0 + j1 * e1);
             vu[c] += wx * (j0 * j0 + j1 * j1);
           }
         }
       }
+      __builtin_amdgcn_wave_barrier();
+      if (t + 1 < nt) stage_rows();
+      ycode = ycode_next;
     }
+  }
+  __syncthreads();  // the staging area becomes the partial-sum area
+  if (computes) {
 #pragma unroll
     for (int r = 0; r < 9; ++r)
 #pragma unroll
@@ -392,15 +593,15 @@ __global__ __launch_bounds__(SCHUR_THREADS) void k_schur_pairs(SchurArgs a) {
   __syncthreads();
   // every lead slot sums its block's chunk partials in slot order
   for (int t = threadIdx.x; t < SCHUR_SLOTS * 81; t += blockDim.x) {
-    const int s = t / 81, q = t - 81 * (t / 81);
-    const int n = a.slot_lead[sbase + s];
+    const int sl = t / 81, qq = t - 81 * (t / 81);
+    const int n = a.slot_lead[sbase + sl];
     if (n == 0) continue;
     double v = 0.0;
-    for (int k = 0; k < n; ++k) v += part[s + k][q];
-    const int e = a.slot_blk[sbase + s];
+    for (int k = 0; k < n; ++k) v += part[sl + k][qq];
+    const int e = a.slot_blk[sbase + sl];
     const int row = a.blk_row[e];
-    if (a.S_ptr[row] == e) a.Sdiag[81 * (size_t)row + q] = v;
-    else reinterpret_cast<T*>(a.S)[81 * (size_t)e + q] = (T)v;
+    if (a.S_ptr[row] == e) a.Sdiag[81 * (size_t)row + qq] = v;
+    else reinterpret_cast<T*>(a.S)[81 * (size_t)e + qq] = (T)v;
   }
   // camera vectors of the diagonal blocks, through the same LDS
   if (!__syncthreads_or(diag_slot)) return;
@@ -413,17 +614,17 @@ __global__ __launch_bounds__(SCHUR_THREADS) void k_schur_pairs(SchurArgs a) {
     }
   __syncthreads();
   for (int t = threadIdx.x; t < SCHUR_SLOTS * 27; t += blockDim.x) {
-    const int s = t / 27, q = t - 27 * (t / 27);
-    const int n = a.slot_lead[sbase + s];
+    const int sl = t / 27, qq = t - 27 * (t / 27);
+    const int n = a.slot_lead[sbase + sl];
     if (n == 0) continue;
-    const int e = a.slot_blk[sbase + s];
+    const int e = a.slot_blk[sbase + sl];
     const int row = a.blk_row[e];
     if (a.S_ptr[row] != e) continue;
     double v = 0.0;
-    for (int k = 0; k < n; ++k) v += part[s + k][q];
-    if (q < 9) a.gc[9 * (size_t)row + q] = v;
-    else if (q < 18) a.bS[9 * (size_t)row + (q - 9)] = v;  // - gc, added by the camera finish
-    else a.diagU[9 * (size_t)row + (q - 18)] = v;
+    for (int k = 0; k < n; ++k) v += part[sl + k][qq];
+    if (qq < 9) a.gc[9 * (size_t)row + qq] = v;
+    else if (qq < 18) a.bS[9 * (size_t)row + (qq - 9)] = v;  // - gc, added by the camera finish
+    else a.diagU[9 * (size_t)row + (qq - 18)] = v;
   }
 }
 

@@ -214,6 +214,36 @@ std::string build_plan(int32_t nc, int32_t np, int64_t no, const int32_t* cidx, 
       used += n;
     }
     p.n_schur_wg = (int32_t)(p.slot_blk.size() / SCHUR_SLOTS);
+    // wavefront steps: a wavefront takes as many steps as its longest chunk
+    p.swptr.assign((size_t)p.n_schur_wg * SCHUR_WAVES + 1, 0);
+    int64_t steps = 0;
+    for (int32_t g = 0; g < p.n_schur_wg; ++g)
+      for (int v = 0; v < SCHUR_WAVES; ++v) {
+        int32_t n = 0;
+        for (int s = 0; s < SCHUR_WAVE_SLOTS; ++s) {
+          const size_t k = (size_t)g * SCHUR_SLOTS + v * SCHUR_WAVE_SLOTS + s;
+          if (p.slot_blk[k] >= 0) n = std::max(n, p.slot_pe[k] - p.slot_pb[k]);
+        }
+        if (steps + n > INT32_MAX / SCHUR_ROWS) return "Schur step table too large";
+        p.swptr[(size_t)g * SCHUR_WAVES + v] = (int32_t)steps;
+        steps += n;
+      }
+    p.swptr.back() = (int32_t)steps;
+    p.stab.assign((size_t)steps * SCHUR_ROWS, -1);
+    for (int32_t g = 0; g < p.n_schur_wg; ++g)
+      for (int v = 0; v < SCHUR_WAVES; ++v) {
+        const size_t t0 = p.swptr[(size_t)g * SCHUR_WAVES + v];
+        for (int s = 0; s < SCHUR_WAVE_SLOTS; ++s) {
+          const size_t k = (size_t)g * SCHUR_SLOTS + v * SCHUR_WAVE_SLOTS + s;
+          if (p.slot_blk[k] < 0) continue;
+          for (int32_t i = p.slot_pb[k]; i < p.slot_pe[k]; ++i) {
+            const size_t row = (t0 + (size_t)(i - p.slot_pb[k])) * SCHUR_ROWS;
+            const int32_t x = p.pair_x[i], y = p.pair_y[i];
+            p.stab[row + 2 * s] = x;
+            p.stab[row + 2 * s + 1] = x == y ? -2 - x : y;
+          }
+        }
+      }
   }
 
   // transpose lists: row b receives upper blocks (a, b) with a < b, ascending a

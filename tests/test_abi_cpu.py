@@ -128,9 +128,9 @@ def test_workspace_grows_linearly_with_observations():
     h2 = _create(s.n_cams, s.n_pts, s.cam_idx, s.pt_idx, precision=B.BA_MIXED)
     try:
         b64, b32 = B.ba_problem_workspace_bytes(h1), B.ba_problem_workspace_bytes(h2)
-        # FP32 storage of the Jacobian blocks, the per-observation Schur
-        # factors and S saves 4 bytes per stored value
-        saved = s.n_obs * (24 + 6) * 4 + B.ba_problem_nnzb(h1) * 81 * 4
+        # FP32 storage of the observation rows (Jacobian blocks, Schur
+        # factor, weight: 32 values) and of S saves 4 bytes per stored value
+        saved = s.n_obs * 32 * 4 + B.ba_problem_nnzb(h1) * 81 * 4
         assert abs((b64 - b32) - saved) < 64 * 256
     finally:
         B.ba_problem_destroy(h1)
