@@ -99,9 +99,12 @@ void carve(ba_problem* p, char* base, size_t* total) {
     b.pts[i] = c.take<double>(3 * np);
   }
   b.r = c.take<double>(2 * no);
-  b.rec = c.take<double>(8 * no);
   b.w = c.take<double>(no);
+  // observation rows, then the records (in the same 64-byte units: the Schur
+  // step table addresses both from J; 32 doubles of padding after the last
+  // record, which the staging reads past)
   b.J = c.take<char>(no * ba::NJ * es);
+  b.rec = c.take<double>(8 * no + 32);
   b.V = c.take<double>(6 * np);
   b.gp = c.take<double>(3 * np);
   b.gc = c.take<double>(9 * nc);
@@ -265,8 +268,8 @@ ba_status lm_step_impl(ba_problem* p, ba_step_info* out) {
   }
   // the camera vectors (gradient, right-hand side term, diag U) come from
   // the self pairs of the Schur kernel's diagonal blocks
-  SchurArgs sa{P.n_schur_wg, b.slot_blk, b.slot_lead, b.blk_row, b.S_ptr, b.stab, b.swptr,
-               b.J, b.rec, b.S, b.Sdiag, b.gc, b.bS, b.diagU};
+  SchurArgs sa{P.n_schur_wg, p->rec_unit, b.slot_blk, b.slot_lead, b.blk_row, b.S_ptr, b.stab, b.swptr,
+               b.J, b.S, b.Sdiag, b.gc, b.bS, b.diagU};
   PHASE(5, launch_schur_pairs<T>(sa, P.n_schur_wg, s));
   CamFinishArgs cf{b.Sdiag, b.diagU, p->opt.diag_min, p->opt.diag_max, b.Minv, b.dev, b.pcLinv, b.gc, b.bS};
   PHASE(6, launch_camera_finish<T>(cf, P.nc, s));
@@ -488,7 +491,18 @@ ba_status ba_problem_bind(ba_problem* p, void* ws, size_t bytes, void* stream) {
   HIPCHK(upload(b.slot_pe, P.slot_pe, s));
   HIPCHK(upload(b.slot_lead, P.slot_lead, s));
   HIPCHK(upload(b.blk_row, P.blk_row, s));
-  HIPCHK(upload(b.stab, P.stab, s));
+  // step table in 64-byte units from J: observation x's row at x * row
+  // units, its record (self pairs, y side) at rec_unit + x, -1 unchanged
+  const int64_t row_units = (int64_t)ba::NJ * (int64_t)elem_bytes(p) / 64;
+  const int64_t rec_unit = (reinterpret_cast<char*>(b.rec) - reinterpret_cast<char*>(b.J)) / 64;
+  if (rec_unit + (int64_t)P.no > INT32_MAX) return fail(BA_EUNSUPPORTED, "observation rows exceed 2^31 units");
+  p->rec_unit = (int32_t)rec_unit;
+  std::vector<int32_t> units(P.stab.size());
+  for (size_t i = 0; i < units.size(); ++i) {
+    const int32_t c = P.stab[i];
+    units[i] = c >= 0 ? (int32_t)(c * row_units) : (c == -1 ? -1 : (int32_t)(rec_unit + (-2 - c)));
+  }
+  HIPCHK(upload(b.stab, units, s));
   HIPCHK(upload(b.swptr, P.swptr, s));
   HIPCHK(upload(b.pcg_row, P.pcg_row, s));
   HIPCHK(upload(b.item_ptr, P.item_ptr, s));

@@ -72,7 +72,8 @@ struct Plan {
   // runs steps [swptr[4g + v], swptr[4g + v + 1]); step t lists the pair of
   // each of the wavefront's 21 slots, stab[SCHUR_ROWS t + 2s] = x,
   // stab[SCHUR_ROWS t + 2s + 1] = y, or -2 - x for a self pair (x, x), or
-  // -1 twice when slot s has no pair at that step
+  // -1 twice when slot s has no pair at that step (uploaded in 64-byte
+  // units of the observation rows and records)
   std::vector<int32_t> stab, swptr;
   std::vector<int32_t> blk_row;  // block -> its row (camera a)
   // PCG workgroup decomposition: workgroup g owns rows [pcg_row[g],
@@ -196,6 +197,7 @@ struct ba_problem {
   bool adj_grid_ok = false;  // the FP64 standard PCG fits the plan's grid
   bool gnn_ready = false;    // learned preconditioner parameters are set
   bool have_system = false;  // a step has formed the reduced system
+  int32_t rec_unit = 0;      // records' first 64-byte unit counted from J
   ba_step_info* hinfo = nullptr;     // pinned host staging
   ba::DevScalars* hscal = nullptr;   // pinned host staging
 };

@@ -44,10 +44,12 @@ struct PointQArgs {
 };
 
 struct SchurArgs {
-  int nwg;  // workgroups of the slot table
+  int nwg;       // workgroups of the slot table
+  int rec_unit;  // first 64-byte unit of the records, counted from J
+  // stab: step table in 64-byte units from J (rows, or records for the y
+  // side of self pairs; -1: no pair)
   const int32_t *slot_blk, *slot_lead, *blk_row, *S_ptr, *stab, *swptr;
   const void* J;
-  const double* rec;
   void* S;
   double* Sdiag;
   // camera vectors from the self pairs of the diagonal blocks

@@ -450,7 +450,7 @@ __device__ __forceinline__ void pair_update(double (&acc)[9][3], const T (&jx)[2
   for (int r = 0; r < 9; ++r) {
     const double j0 = (double)jx[r], j1 = (double)jx[9 + r];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) acc[r][c] += j0 * g0[c] + j1 * g1[c];
+    for (int c = 0; c < 3; ++c) acc[r][c] = fma(j1, g1[c], fma(j0, g0[c], acc[r][c]));
   }
 }
 
@@ -475,7 +475,6 @@ __global__ __launch_bounds__(SCHUR_THREADS) void k_schur_pairs(SchurArgs a) {
   const size_t sbase = (size_t)lw * SCHUR_SLOTS;
   unsigned char* st = lds + wave * SS::WAVE_BYTES;
   const unsigned char* __restrict__ Jb = reinterpret_cast<const unsigned char*>(a.J);
-  const unsigned char* __restrict__ Rb = reinterpret_cast<const unsigned char*>(a.rec);
 
   bool diag_slot = false;
   if (computes) {
@@ -489,9 +488,10 @@ __global__ __launch_bounds__(SCHUR_THREADS) void k_schur_pairs(SchurArgs a) {
 
   // staging: lane `lane` moves piece (64 k + lane) % PIECES of row
   // (64 k + lane) / PIECES for k < LOADS.  Every load is issued without a
-  // branch (inactive slots read row 0, rows past SCHUR_ROWS repeat the last
-  // one), so the compiler's wait counting keeps the next step's loads in
-  // flight across the multiplication of the current one.
+  // branch (a slot without a pair reads unit 0, rows past SCHUR_ROWS repeat
+  // the last one, a record's pieces past its end read the next records), so
+  // the compiler's wait counting keeps the next step's loads in flight
+  // across the multiplication of the current one.
   int code[SS::LOADS];
   f32x4 buf[SS::LOADS];
   auto fetch_codes = [&](int t) {
@@ -504,12 +504,8 @@ __global__ __launch_bounds__(SCHUR_THREADS) void k_schur_pairs(SchurArgs a) {
   auto fetch_rows = [&]() {
 #pragma unroll
     for (int k = 0; k < SS::LOADS; ++k) {
-      const int q = 64 * k + lane, r = q / SS::PIECES, p = q % SS::PIECES;
-      const int c = code[k];
-      const int x = c >= 0 ? c : (c < -1 ? -2 - c : 0);
-      const bool rec = c < -1 && (r & 1) && p < 4;  // self pair: the record replaces the y row
-      const unsigned char* src = rec ? Rb + (size_t)x * 64 + p * 16 : Jb + (size_t)x * SS::ROW_BYTES + p * 16;
-      buf[k] = *reinterpret_cast<const f32x4*>(src);
+      const int p = (64 * k + lane) % SS::PIECES;
+      buf[k] = *reinterpret_cast<const f32x4*>(Jb + (size_t)max(code[k], 0) * 64 + p * 16);
     }
   };
   auto stage_rows = [&]() {
@@ -543,7 +539,7 @@ __global__ __launch_bounds__(SCHUR_THREADS) void k_schur_pairs(SchurArgs a) {
       const int ycode_next = computes ? yn : -1;
       __builtin_amdgcn_wave_barrier();
       if (computes && ycode != -1) {
-        const bool self = ycode < -1;
+        const bool self = ycode >= a.rec_unit;
         const int rx = 2 * s, ry = self ? rx : rx + 1;
         T jx[20], q[8], jy[6], py[6];
 #pragma unroll
