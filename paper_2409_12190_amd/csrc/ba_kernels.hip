@@ -476,11 +476,23 @@ __global__ __launch_bounds__(SCHUR_THREADS) void k_schur_pairs(SchurArgs a) {
   unsigned char* st = lds + wave * SS::WAVE_BYTES;
   const unsigned char* __restrict__ Jb = reinterpret_cast<const unsigned char*>(a.J);
 
+  // per slot, for the reduction: number of chunks when the slot leads its
+  // block (else 0) and the destination: block e of S, or -1 - row for the
+  // diagonal block of camera row (Sdiag)
+  __shared__ int slot_n[SCHUR_SLOTS], slot_dst[SCHUR_SLOTS];
   bool diag_slot = false;
   if (computes) {
     const int e = a.slot_blk[sbase + slot];
-    // (a camera without observations has an empty diagonal block: zeros)
-    diag_slot = e >= 0 && a.S_ptr[a.blk_row[e]] == e;
+    int row = 0;
+    if (e >= 0) {
+      row = a.blk_row[e];
+      // (a camera without observations has an empty diagonal block: zeros)
+      diag_slot = a.S_ptr[row] == e;
+    }
+    if (c0 == 0) {
+      slot_n[slot] = a.slot_lead[sbase + slot];
+      slot_dst[slot] = diag_slot ? -1 - row : e;
+    }
   }
   const int t0 = a.swptr[(size_t)lw * SCHUR_WAVES + wave];
   const int nt = a.swptr[(size_t)lw * SCHUR_WAVES + wave + 1] - t0;
@@ -590,14 +602,13 @@ __global__ __launch_bounds__(SCHUR_THREADS) void k_schur_pairs(SchurArgs a) {
   // every lead slot sums its block's chunk partials in slot order
   for (int t = threadIdx.x; t < SCHUR_SLOTS * 81; t += blockDim.x) {
     const int sl = t / 81, qq = t - 81 * (t / 81);
-    const int n = a.slot_lead[sbase + sl];
+    const int n = slot_n[sl];
     if (n == 0) continue;
     double v = 0.0;
     for (int k = 0; k < n; ++k) v += part[sl + k][qq];
-    const int e = a.slot_blk[sbase + sl];
-    const int row = a.blk_row[e];
-    if (a.S_ptr[row] == e) a.Sdiag[81 * (size_t)row + qq] = v;
-    else reinterpret_cast<T*>(a.S)[81 * (size_t)e + qq] = (T)v;
+    const int dst = slot_dst[sl];
+    if (dst < 0) a.Sdiag[81 * (size_t)(-1 - dst) + qq] = v;
+    else reinterpret_cast<T*>(a.S)[81 * (size_t)dst + qq] = (T)v;
   }
   // camera vectors of the diagonal blocks, through the same LDS
   if (!__syncthreads_or(diag_slot)) return;
@@ -611,16 +622,14 @@ __global__ __launch_bounds__(SCHUR_THREADS) void k_schur_pairs(SchurArgs a) {
   __syncthreads();
   for (int t = threadIdx.x; t < SCHUR_SLOTS * 27; t += blockDim.x) {
     const int sl = t / 27, qq = t - 27 * (t / 27);
-    const int n = a.slot_lead[sbase + sl];
-    if (n == 0) continue;
-    const int e = a.slot_blk[sbase + sl];
-    const int row = a.blk_row[e];
-    if (a.S_ptr[row] != e) continue;
+    const int n = slot_n[sl], dst = slot_dst[sl];
+    if (n == 0 || dst >= 0) continue;
+    const size_t row = (size_t)(-1 - dst);
     double v = 0.0;
     for (int k = 0; k < n; ++k) v += part[sl + k][qq];
-    if (qq < 9) a.gc[9 * (size_t)row + qq] = v;
-    else if (qq < 18) a.bS[9 * (size_t)row + (qq - 9)] = v;  // - gc, added by the camera finish
-    else a.diagU[9 * (size_t)row + (qq - 18)] = v;
+    if (qq < 9) a.gc[9 * row + qq] = v;
+    else if (qq < 18) a.bS[9 * row + (qq - 9)] = v;  // - gc, added by the camera finish
+    else a.diagU[9 * row + (qq - 18)] = v;
   }
 }
 
