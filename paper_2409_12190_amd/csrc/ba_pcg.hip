@@ -188,9 +188,8 @@ __device__ __forceinline__ void pcg_load_items(const PcgArgs& a, int ib, int k0,
 // whose partials are then summed by 8 lanes per output (strided, then a
 // 3-step butterfly): fixed order.
 template <typename T, bool RES>
-__device__ __forceinline__ void pcg_spmv(const PcgArgs& a, int ib, int i0, int i1, int nr, int L,
-                                         const int* rptr, PcgItems& it, const double* zl, double* seg,
-                                         double* y) {
+__device__ __forceinline__ void pcg_spmv_segments(const PcgArgs& a, int ib, int i0, int i1, const int* rptr,
+                                                  PcgItems& it, const double* zl, double* seg) {
   const int g = threadIdx.x / 9, comp = threadIdx.x - 9 * (threadIdx.x / 9);
   if (g < SPMV_GROUPS) {
     double acc = 0.0;
@@ -214,19 +213,35 @@ __device__ __forceinline__ void pcg_spmv(const PcgArgs& a, int ib, int i0, int i
     if (cur >= 0) seg[(cur + g) * 9 + comp] = acc;
   }
   __syncthreads();
+}
+
+// Output o of the product from the group partials (after
+// pcg_spmv_segments): valid in lane sub == 0 of each group of 8 lanes, for
+// o = (base + threadIdx.x) / 8 < nr * 9.
+__device__ __forceinline__ double pcg_spmv_output(int o, int sub, int nr, int L, const int* rptr,
+                                                  const double* seg) {
+  double s = 0.0;
+  if (o < nr * 9) {
+    const int row = o / 9, cp = o - 9 * row;
+    const int g0 = rptr[row] / L, g1 = (rptr[row + 1] - 1) / L;
+    for (int gg = g0 + sub; gg <= g1; gg += 8) s += seg[(row + gg) * 9 + cp];
+  }
+  s += __shfl_xor(s, 1, 64);
+  s += __shfl_xor(s, 2, 64);
+  s += __shfl_xor(s, 4, 64);
+  return s;
+}
+
+template <typename T, bool RES>
+__device__ __forceinline__ void pcg_spmv(const PcgArgs& a, int ib, int i0, int i1, int nr, int L,
+                                         const int* rptr, PcgItems& it, const double* zl, double* seg,
+                                         double* y) {
+  pcg_spmv_segments<T, RES>(a, ib, i0, i1, rptr, it, zl, seg);
   const int nout = nr * 9;
   for (int base = 0; base < nout * 8; base += blockDim.x) {
     const int t = base + threadIdx.x, o = t >> 3, sub = t & 7;
-    double s = 0.0;
-    if (o < nout) {
-      const int row = o / 9, cp = o - 9 * row;
-      const int g0 = rptr[row] / L, g1 = (rptr[row + 1] - 1) / L;
-      for (int gg = g0 + sub; gg <= g1; gg += 8) s += seg[(row + gg) * 9 + cp];
-    }
-    s += __shfl_xor(s, 1, 64);
-    s += __shfl_xor(s, 2, 64);
-    s += __shfl_xor(s, 4, 64);
-    if (o < nout && sub == 0) y[o] = s;
+    const double v = pcg_spmv_output(o, sub, nr, L, rptr, seg);
+    if (o < nout && sub == 0) y[o] = v;
   }
   __syncthreads();
 }
@@ -409,7 +424,7 @@ __global__ __launch_bounds__(PCG_THREADS) void k_pcg_standard(PcgArgs a) {
 template <typename T, bool RES>
 __global__ __launch_bounds__(PCG_THREADS) void k_pcg_pipelined(PcgArgs a) {
   __shared__ double xs[PCG_RMAX * 9], rs[PCG_RMAX * 9], us[PCG_RMAX * 9], ws[PCG_RMAX * 9];
-  __shared__ double ms_[PCG_RMAX * 9], ns[PCG_RMAX * 9], zs[PCG_RMAX * 9], qs[PCG_RMAX * 9];
+  __shared__ double ms_[PCG_RMAX * 9], zs[PCG_RMAX * 9], qs[PCG_RMAX * 9];
   __shared__ double ss[PCG_RMAX * 9], ps[PCG_RMAX * 9];
   __shared__ double Ml[PCG_RMAX * 81];
   __shared__ double zl[PCG_ZCOLS * 9];
@@ -432,9 +447,15 @@ __global__ __launch_bounds__(PCG_THREADS) void k_pcg_pipelined(PcgArgs a) {
       rptr[i + 1] = rptr[i] + (a.S_ptr[r0 + i + 1] - a.S_ptr[r0 + i]) +
                     (a.T_ptr[r0 + i + 1] - a.T_ptr[r0 + i]);
   }
+  // the recurrences of the first iteration read z, q, s, p with beta = 0:
+  // they must hold zeros, not whatever the LDS held before (0 * NaN = NaN)
   for (int i = tid; i < n9; i += nt) {
     rs[i] = a.b[9 * (size_t)r0 + i];
     xs[i] = 0.0;
+    zs[i] = 0.0;
+    qs[i] = 0.0;
+    ss[i] = 0.0;
+    ps[i] = 0.0;
   }
   for (int i = tid; i < nr * 81; i += nt) Ml[i] = a.Minv[81 * (size_t)r0 + i];
   __syncthreads();
@@ -506,6 +527,17 @@ __global__ __launch_bounds__(PCG_THREADS) void k_pcg_pipelined(PcgArgs a) {
     }
     double tg = 0.0, td = 0.0, tr = 0.0;
     if (tid < G && !poll_record(pa + (size_t)tid * PART_STRIDE, tg, td, tr, a.error)) poll_failed = 1;
+    // the workgroup partials summed in a fixed order (wavefront butterflies,
+    // then the wavefronts in order), one exchange that is also the barrier
+    // after the poll
+    tg = wave_sum(tg);
+    td = wave_sum(td);
+    tr = wave_sum(tr);
+    if ((tid & 63) == 0) {
+      red3s[3 * (tid >> 6)] = tg;
+      red3s[3 * (tid >> 6) + 1] = td;
+      red3s[3 * (tid >> 6) + 2] = tr;
+    }
     __syncthreads();
     if (poll_failed) {
       ok = false;
@@ -513,8 +545,13 @@ __global__ __launch_bounds__(PCG_THREADS) void k_pcg_pipelined(PcgArgs a) {
     }
     // every workgroup's m columns are in memory now
     pcg_fetch_z(a, zk, ub, nuc, zl);
-    block_sum3(tg, td, tr, red3s);
-    const double gamma = tg, delta = td, rr = tr;
+    double gamma = 0.0, delta = 0.0, rr = 0.0;
+#pragma unroll 2
+    for (int w2 = 0; w2 < PCG_THREADS / 64; ++w2) {
+      gamma += red3s[3 * w2];
+      delta += red3s[3 * w2 + 1];
+      rr += red3s[3 * w2 + 2];
+    }
     iters = i;
     rnorm = sqrt(rr);
     if (rnorm <= a.rtol * bnorm || i == a.maxiter) break;
@@ -525,20 +562,26 @@ __global__ __launch_bounds__(PCG_THREADS) void k_pcg_pipelined(PcgArgs a) {
       break;
     }
     const double alpha = gamma / den;
-    pcg_spmv<T, RES>(a, ib, i0, i1, nr, L, rptr, it, zl, seg, ns);
-    for (int k = tid; k < n9; k += nt) {
-      const double z = ns[k] + beta * zs[k];
-      const double q = ms_[k] + beta * qs[k];
-      const double sv = ws[k] + beta * ss[k];
-      const double pv = us[k] + beta * ps[k];
-      zs[k] = z;
-      qs[k] = q;
-      ss[k] = sv;
-      ps[k] = pv;
-      xs[k] += alpha * pv;
-      rs[k] -= alpha * sv;
-      us[k] -= alpha * q;
-      ws[k] -= alpha * z;
+    __syncthreads();  // zl complete
+    pcg_spmv_segments<T, RES>(a, ib, i0, i1, rptr, it, zl, seg);
+    // n = S m, output by output, straight into the vector updates
+    for (int base = 0; base < n9 * 8; base += nt) {
+      const int t = base + tid, k = t >> 3, sub = t & 7;
+      const double nk = pcg_spmv_output(k, sub, nr, L, rptr, seg);
+      if (k < n9 && sub == 0) {
+        const double z = nk + beta * zs[k];
+        const double q = ms_[k] + beta * qs[k];
+        const double sv = ws[k] + beta * ss[k];
+        const double pv = us[k] + beta * ps[k];
+        zs[k] = z;
+        qs[k] = q;
+        ss[k] = sv;
+        ps[k] = pv;
+        xs[k] += alpha * pv;
+        rs[k] -= alpha * sv;
+        us[k] -= alpha * q;
+        ws[k] -= alpha * z;
+      }
     }
     __syncthreads();
     gamma_old = gamma;
