@@ -170,6 +170,34 @@ def test_pipelined_and_standard_pcg_agree(name):
             assert abs(ia["cost_after"] - ib["cost_after"]) <= 1e-6 * ib["cost_after"]
 
 
+def test_streamed_pcg_path_matches_oracle():
+    """Dense co-visibility (400 ring cameras, nearly every pair sharing points):
+    each block row holds more blocks than the lanes of a PCG workgroup keep
+    in registers, so the PCG streams its blocks every iteration.  FP64
+    parity with a converged solve (standard recurrence), and both
+    recurrences at the default tolerance within the oracle's envelope (no
+    breakdown, full Krylov runs)."""
+    s = make_scene(0, n_cams=400, n_pts=40000)
+    # blocks of each block row (both triangles and the diagonal); a PCG
+    # workgroup's 1024 // 9 lane groups keep at most 3 blocks each in registers
+    cov = [set() for _ in range(s.n_cams)]
+    cams = s.cam_idx.reshape(s.n_pts, -1)
+    for row in cams:
+        for a in row:
+            cov[a].update(row.tolist())
+    assert max(len(c) for c in cov) > 3 * (1024 // 9)
+    run_parity(s, 3)
+    o = orc(s)
+    runs = {v: gpu(s, cg_variant=v) for v in (B.BA_CG_PIPELINED, B.BA_CG_STANDARD)}
+    for it in range(3):
+        io = o.lm_step()
+        for v, g in runs.items():
+            ig = g.lm_step()
+            assert ig["status"] == 0 and ig["cg_breakdown"] == 0, (v, it)
+            assert ig["cg_iters"] > 5 and ig["cg_rel_resid"] <= 1e-4, (v, it, ig["cg_iters"])
+            assert abs(ig["cost_after"] - io["cost_after"]) <= 1e-5 * io["cost_after"], (v, it)
+
+
 @pytest.mark.parametrize("variant", [B.BA_CG_PIPELINED, B.BA_CG_STANDARD])
 @pytest.mark.parametrize("precision", [B.BA_FP64, B.BA_MIXED])
 def test_pcg_meets_its_tolerance_on_the_exported_system(precision, variant):
