@@ -90,6 +90,9 @@ void carve(ba_problem* p, char* base, size_t* total) {
   b.item_code = c.take<int32_t>(P.item_code.size());
   b.ucol_ptr = c.take<int32_t>(P.ucol_ptr.size());
   b.ucol = c.take<int32_t>(P.ucol.size());
+  b.sitem_ptr = c.take<int32_t>(P.sitem_ptr.size());
+  b.sitem_col = c.take<int32_t>(P.sitem_col.size());
+  b.blk_pos = c.take<int32_t>(P.blk_pos.size());
   b.o_orig = c.take<int64_t>(no);
   b.fixed = c.take<uint8_t>(nc);
   b.o_xy = c.take<double>(2 * no);
@@ -112,6 +115,10 @@ void carve(ba_problem* p, char* base, size_t* total) {
   b.Vinv = c.take<double>(6 * np);
   b.ep = c.take<double>(3 * np);
   b.S = c.take<char>(nnzb * 81 * es);
+  // streamed PCG plans in mixed precision: one FP32 copy of each off-diagonal
+  // block per (row, block) item
+  const bool stream = !P.pcg_resident && p->opt.precision == BA_MIXED;
+  b.SI = c.take<char>(stream ? P.sitem_col.size() * ba::SI_STRIDE * 4 : 0);
   b.Sdiag = c.take<double>(81 * nc);
   b.bS = c.take<double>(9 * nc);
   b.Minv = c.take<double>(81 * nc);
@@ -241,6 +248,12 @@ hipError_t reset_sync(ba_problem* p) {
   return hipMemsetAsync(p->b.gsync, 0, sizeof(ba::GridSync), p->stream);
 }
 
+// mixed-precision plans whose PCG streams its blocks (each off-diagonal
+// block copied per (row, block) item by the Schur kernel)
+bool streamed(const ba_problem* p) {
+  return !p->plan.pcg_resident && p->opt.precision == BA_MIXED;
+}
+
 template <typename T>
 ba_status lm_step_impl(ba_problem* p, ba_step_info* out) {
   using namespace ba;
@@ -270,6 +283,10 @@ ba_status lm_step_impl(ba_problem* p, ba_step_info* out) {
   // the self pairs of the Schur kernel's diagonal blocks
   SchurArgs sa{P.n_schur_wg, p->rec_unit, b.slot_blk, b.slot_lead, b.blk_row, b.S_ptr, b.stab, b.swptr,
                b.J, b.S, b.Sdiag, b.gc, b.bS, b.diagU};
+  if (streamed(p)) {
+    sa.blk_pos = b.blk_pos;
+    sa.SI = b.SI;
+  }
   PHASE(5, launch_schur_pairs<T>(sa, P.n_schur_wg, s));
   CamFinishArgs cf{b.Sdiag, b.diagU, p->opt.diag_min, p->opt.diag_max, b.Minv, b.dev, b.pcLinv, b.gc, b.bS};
   PHASE(6, launch_camera_finish<T>(cf, P.nc, s));
@@ -292,6 +309,11 @@ ba_status lm_step_impl(ba_problem* p, ba_step_info* out) {
   PcgArgs pa{P.nc, p->cg_maxiter, p->cg_rtol, b.S_ptr, b.T_ptr, b.pcg_row, b.item_ptr, b.item_e,
              b.item_code, b.ucol_ptr, b.ucol, b.S, b.Sdiag, learned ? b.pcMinvL : b.Minv, b.bS, b.x,
              b.zring, b.partA, b.partB, b.dinfo, b.gsync, &b.dev->error};
+  if (streamed(p)) {
+    pa.sitem_ptr = b.sitem_ptr;
+    pa.sitem_col = b.sitem_col;
+    pa.SI = b.SI;
+  }
   const bool pipe = p->opt.cg_variant == BA_CG_PIPELINED;
   PHASE(7, launch_pcg<T>(pa, P.pcg_grid, P.pcg_resident, pipe, s));
   if (learned && p->cg_rtol > 0.0) {
@@ -510,6 +532,9 @@ ba_status ba_problem_bind(ba_problem* p, void* ws, size_t bytes, void* stream) {
   HIPCHK(upload(b.item_code, P.item_code, s));
   HIPCHK(upload(b.ucol_ptr, P.ucol_ptr, s));
   HIPCHK(upload(b.ucol, P.ucol, s));
+  HIPCHK(upload(b.sitem_ptr, P.sitem_ptr, s));
+  HIPCHK(upload(b.sitem_col, P.sitem_col, s));
+  HIPCHK(upload(b.blk_pos, P.blk_pos, s));
   HIPCHK(upload(b.o_orig, P.o_orig, s));
   if (p->opt.precond == BA_PRECOND_LEARNED) {
     HIPCHK(upload(b.nbr_ptr, P.nbr_ptr, s));

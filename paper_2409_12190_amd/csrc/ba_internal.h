@@ -46,6 +46,8 @@ constexpr int BARRIER_FANIN = 16;
 constexpr int MAX_BARRIER_GROUPS = 128;
 constexpr int MAX_TRACK = CHUNK;
 constexpr int FINAL_STAGE_MAX = 256;  // workgroups of the first acceptance-reduction stage
+constexpr int SI_STRIDE = 88;         // values per block of the streamed PCG copy of S (81 + zeros:
+                                      // whole 32-byte sectors in FP32)
 
 // Host-side symbolic analysis of the observation pattern (computed once per
 // problem; the paper caches its sparse-product table the same way, Sec. IV-B-1).
@@ -81,6 +83,12 @@ struct Plan {
   // code (local column | flags), and the distinct block columns it reads.
   // pcg_resident: every lane group has at most PCG_IPG items.
   std::vector<int32_t> pcg_row, item_ptr, item_e, item_code, ucol_ptr, ucol;
+  // streamed plans (not pcg_resident): the off-diagonal items again, in the
+  // same order without the diagonal ones, numbered globally; each has its
+  // own copy of its block (SI, oriented for its row); sitem_col is the
+  // item's local column; blk_pos[2e], blk_pos[2e + 1] are the streamed items
+  // of upper block e as stored and transposed (-1 for diagonal blocks)
+  std::vector<int32_t> sitem_ptr, sitem_col, blk_pos;
   // camera co-visibility graph (both directions of every off-diagonal block):
   // neighbours of camera i are nbr[nbr_ptr[i] .. nbr_ptr[i+1]), through block
   // nbr_blk; nbr_rev is the slot of the same block in the neighbour's list
@@ -128,6 +136,8 @@ struct Buffers {
   int32_t *S_ptr, *S_col, *T_ptr, *T_blk, *T_src;
   int32_t *pair_x, *pair_y, *slot_blk, *slot_pb, *slot_pe, *slot_lead, *blk_row, *stab, *swptr;
   int32_t *pcg_row, *item_ptr, *item_e, *item_code, *ucol_ptr, *ucol;
+  int32_t *sitem_ptr, *sitem_col, *blk_pos;
+  void* SI;  // streamed plans: [n_sitems][SI_STRIDE] (precision T)
   int64_t* o_orig;
   uint8_t* fixed;
   // observations (sorted by position)

@@ -54,6 +54,10 @@ struct SchurArgs {
   double* Sdiag;
   // camera vectors from the self pairs of the diagonal blocks
   double *gc, *bS, *diagU;
+  // streamed PCG plans: each off-diagonal block also written to its two
+  // streamed items (as stored and transposed; null otherwise)
+  const int32_t* blk_pos = nullptr;
+  void* SI = nullptr;
 };
 
 struct CamFinishArgs {
@@ -78,6 +82,11 @@ struct PcgArgs {
   ba_step_info* info;
   GridSync* gs;
   int* error;
+  // streamed plans (mixed precision): per-workgroup streamed items, their
+  // local columns and blocks
+  const int32_t* sitem_ptr = nullptr;
+  const int32_t* sitem_col = nullptr;
+  const void* SI = nullptr;
 };
 
 struct BackArgs {

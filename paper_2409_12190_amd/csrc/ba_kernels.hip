@@ -389,7 +389,10 @@ template <typename T> struct SchurStage {
   static constexpr int PIECES = ROW_BYTES / 16;                   // 16-byte pieces per row
   static constexpr int EPP = 16 / (int)sizeof(T);                 // values per piece
   static constexpr int LOADS = (SCHUR_ROWS * PIECES + 63) / 64;   // staging loads per lane
-  static constexpr int WAVE_BYTES = SCHUR_ROWS * ROW_BYTES;
+  // room for every piece the lanes move (rows past SCHUR_ROWS included), so
+  // that the LDS stores need no lane-dependent branch: such a branch inside
+  // the lockstep loop lets the compiler restructure it into a divergent nest
+  static constexpr int WAVE_BYTES = LOADS * 64 * 16;
 };
 
 constexpr int SCHUR_PART_BYTES = SCHUR_SLOTS * 81 * 8;
@@ -479,7 +482,7 @@ __global__ __launch_bounds__(SCHUR_THREADS) void k_schur_pairs(SchurArgs a) {
   // per slot, for the reduction: number of chunks when the slot leads its
   // block (else 0) and the destination: block e of S, or -1 - row for the
   // diagonal block of camera row (Sdiag)
-  __shared__ int slot_n[SCHUR_SLOTS], slot_dst[SCHUR_SLOTS];
+  __shared__ int slot_n[SCHUR_SLOTS], slot_dst[SCHUR_SLOTS], slot_pn[SCHUR_SLOTS], slot_pt[SCHUR_SLOTS];
   bool diag_slot = false;
   if (computes) {
     const int e = a.slot_blk[sbase + slot];
@@ -490,8 +493,13 @@ __global__ __launch_bounds__(SCHUR_THREADS) void k_schur_pairs(SchurArgs a) {
       diag_slot = a.S_ptr[row] == e;
     }
     if (c0 == 0) {
-      slot_n[slot] = a.slot_lead[sbase + slot];
+      const int n = a.slot_lead[sbase + slot];
+      slot_n[slot] = n;
       slot_dst[slot] = diag_slot ? -1 - row : e;
+      if (a.SI && n > 0 && !diag_slot) {
+        slot_pn[slot] = a.blk_pos[2 * (size_t)e];
+        slot_pt[slot] = a.blk_pos[2 * (size_t)e + 1];
+      }
     }
   }
   const int t0 = a.swptr[(size_t)lw * SCHUR_WAVES + wave];
@@ -524,7 +532,7 @@ __global__ __launch_bounds__(SCHUR_THREADS) void k_schur_pairs(SchurArgs a) {
 #pragma unroll
     for (int k = 0; k < SS::LOADS; ++k) {
       const int q = 64 * k + lane, r = q / SS::PIECES, p = q % SS::PIECES;
-      if (r < SCHUR_ROWS) *reinterpret_cast<f32x4*>(st + r * SS::ROW_BYTES + stage_piece(r, p) * 16) = buf[k];
+      *reinterpret_cast<f32x4*>(st + r * SS::ROW_BYTES + stage_piece(r, p) * 16) = buf[k];
     }
   };
 
@@ -607,8 +615,22 @@ __global__ __launch_bounds__(SCHUR_THREADS) void k_schur_pairs(SchurArgs a) {
     double v = 0.0;
     for (int k = 0; k < n; ++k) v += part[sl + k][qq];
     const int dst = slot_dst[sl];
-    if (dst < 0) a.Sdiag[81 * (size_t)(-1 - dst) + qq] = v;
-    else reinterpret_cast<T*>(a.S)[81 * (size_t)dst + qq] = (T)v;
+    if (dst < 0) {
+      a.Sdiag[81 * (size_t)(-1 - dst) + qq] = v;
+    } else {
+      reinterpret_cast<T*>(a.S)[81 * (size_t)dst + qq] = (T)v;
+      if (a.SI) {
+        T* si = reinterpret_cast<T*>(a.SI);
+        const size_t pn = (size_t)slot_pn[sl] * SI_STRIDE, pt = (size_t)slot_pt[sl] * SI_STRIDE;
+        const int r = qq / 9, c = qq - 9 * r;
+        si[pn + qq] = (T)v;
+        si[pt + 9 * c + r] = (T)v;
+        if (qq < SI_STRIDE - 81) {
+          si[pn + 81 + qq] = (T)0;
+          si[pt + 81 + qq] = (T)0;
+        }
+      }
+    }
   }
   // camera vectors of the diagonal blocks, through the same LDS
   if (!__syncthreads_or(diag_slot)) return;

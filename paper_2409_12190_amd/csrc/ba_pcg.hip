@@ -596,11 +596,307 @@ __global__ __launch_bounds__(PCG_THREADS) void k_pcg_pipelined(PcgArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// Pipelined PCG with streamed blocks (mixed precision; plans whose block rows
+// do not fit the lanes' registers, e.g. the 10,000-camera scene).  Each
+// off-diagonal (row, block) item has its own FP32 copy of its block, oriented
+// for its row and padded to SI_STRIDE values (written by the Schur kernel),
+// the items of a workgroup contiguous in row order.  The items are split into
+// STREAM_GROUPS contiguous ranges, STREAM_WAVE_GROUPS nine-lane groups per
+// wavefront.  At each step a wavefront stages the current block of each of
+// its groups in LDS with 16-byte loads, 8 lanes per 128 bytes (the next
+// step's blocks already in flight), and lane `comp` of a group multiplies
+// row `comp` of its block with the block column of the multiplied vector;
+// running sums per row go to the same (row + group) segments as in the
+// resident kernels.  The FP64 diagonal blocks are applied by the thread that
+// owns each vector element, from its registers.  Thread k owns element k of
+// the workgroup's rows and keeps every recurrence vector in registers; w, m
+// and the product n also pass through LDS for the 9x9 block products.
+// ---------------------------------------------------------------------------
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+
+constexpr int STREAM_WAVE_GROUPS = 7;
+constexpr int STREAM_GROUPS = (PCG_THREADS / 64) * STREAM_WAVE_GROUPS;
+constexpr int STREAM_PIECES = SI_STRIDE * 4 / 16;  // 16-byte pieces per FP32 block
+constexpr int STREAM_LOADS = (STREAM_WAVE_GROUPS * STREAM_PIECES + 63) / 64;
+// a wavefront's staging area holds every piece its lanes move, so that the
+// LDS stores need no lane-dependent branch (such a branch inside the
+// lockstep loop lets the compiler restructure it into a divergent nest)
+constexpr int STREAM_WAVE_BYTES = STREAM_LOADS * 64 * 16;
+
+// nl[k] = sum over the streamed items of row k / 9 of (block row k % 9) .
+// (block column of the vector in zl), k < nr * 9; every thread of the
+// workgroup calls it (barriers inside).
+__device__ __forceinline__ void stream_spmv(const PcgArgs& a, int sib, int nitems, int L, int nr,
+                                            const int* rptr, const double* zl, double* seg,
+                                            unsigned char* st, double* nl) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int gl = lane / 9, comp = lane - 9 * gl;
+  const bool computes = gl < STREAM_WAVE_GROUPS;
+  const int g = wave * STREAM_WAVE_GROUPS + gl;
+  const int i0 = computes ? min(nitems, g * L) : nitems;
+  const int i1 = computes ? min(nitems, i0 + L) : nitems;
+  unsigned char* wst = st + wave * STREAM_WAVE_BYTES;
+  if (nitems > 0) {
+    const unsigned char* __restrict__ SIb =
+        reinterpret_cast<const unsigned char*>(a.SI) + (size_t)sib * SI_STRIDE * 4;
+    const int* __restrict__ scol = a.sitem_col + sib;
+    // lane `lane` moves piece (64 j + lane) % STREAM_PIECES of the block of
+    // group (64 j + lane) / STREAM_PIECES of its wavefront; loads are issued
+    // without branches (items clamped to the workgroup's last one)
+    auto fetch = [&](f32x4_t (&buf)[STREAM_LOADS], int k) {
+#pragma unroll
+      for (int j = 0; j < STREAM_LOADS; ++j) {
+        const int q = 64 * j + lane;
+        const int gg = min(q / STREAM_PIECES, STREAM_WAVE_GROUPS - 1), pc = q % STREAM_PIECES;
+        const int item = min(min(nitems, (wave * STREAM_WAVE_GROUPS + gg) * L) + k, nitems - 1);
+        buf[j] = *reinterpret_cast<const f32x4_t*>(SIb + (size_t)item * (SI_STRIDE * 4) + pc * 16);
+      }
+    };
+    auto stage = [&](const f32x4_t (&buf)[STREAM_LOADS]) {
+#pragma unroll
+      for (int j = 0; j < STREAM_LOADS; ++j) *reinterpret_cast<f32x4_t*>(wst + (64 * j + lane) * 16) = buf[j];
+    };
+    double acc = 0.0;
+    int cur = -1, row = 0;
+    auto multiply = [&](int k, int col) {
+      __builtin_amdgcn_wave_barrier();
+      const int ik = i0 + k;
+      if (computes && ik < i1) {
+        while (rptr[row + 1] <= ik) ++row;
+        if (row != cur) {
+          if (cur >= 0) seg[(cur + g) * 9 + comp] = acc;
+          acc = 0.0;
+          cur = row;
+        }
+        const float* blk = reinterpret_cast<const float*>(wst + gl * SI_STRIDE * 4) + comp * 9;
+        const double* zc = zl + col * 9;
+#pragma unroll
+        for (int m = 0; m < 9; ++m) acc += (double)blk[m] * zc[m];
+      }
+      __builtin_amdgcn_wave_barrier();
+    };
+    // the blocks of steps k + 1 and k + 2 in flight while step k is
+    // multiplied (past the last step the last one is loaded again, never
+    // staged)
+    f32x4_t A[STREAM_LOADS], Bf[STREAM_LOADS];
+    fetch(A, 0);
+    fetch(Bf, min(1, L - 1));
+    int col = scol[min(i0, nitems - 1)];
+    stage(A);
+    for (int k = 0; k < L; k += 2) {
+      // (when L is odd the last pass's second half multiplies nothing:
+      // every group's range ends by step L - 1)
+      fetch(A, min(k + 2, L - 1));
+      int col_next = scol[min(i0 + k + 1, nitems - 1)];
+      multiply(k, col);
+      if (k + 1 < L) stage(Bf);
+      col = col_next;
+      fetch(Bf, min(k + 3, L - 1));
+      col_next = scol[min(i0 + k + 2, nitems - 1)];
+      multiply(k + 1, col);
+      if (k + 2 < L) stage(A);
+      col = col_next;
+    }
+    if (cur >= 0) seg[(cur + g) * 9 + comp] = acc;
+  }
+  __syncthreads();
+  // outputs: the groups rptr[row] / L .. (rptr[row + 1] - 1) / L touched row
+  // `row` (none when the row has no off-diagonal block); 8 lanes per output,
+  // strided then a 3-step butterfly: fixed order
+  const int nout = nr * 9;
+  for (int base = 0; base < nout * 8; base += blockDim.x) {
+    const int t = base + threadIdx.x, o = t >> 3, sub = t & 7;
+    double sum = 0.0;
+    if (o < nout) {
+      const int row = o / 9, cp = o - 9 * row;
+      if (rptr[row + 1] > rptr[row]) {
+        const int g0 = rptr[row] / L, g1 = (rptr[row + 1] - 1) / L;
+        for (int gg = g0 + sub; gg <= g1; gg += 8) sum += seg[(row + gg) * 9 + cp];
+      }
+    }
+    sum += __shfl_xor(sum, 1, 64);
+    sum += __shfl_xor(sum, 2, 64);
+    sum += __shfl_xor(sum, 4, 64);
+    if (o < nout && sub == 0) nl[o] = sum;
+  }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(PCG_THREADS) void k_pcg_stream(PcgArgs a) {
+  __shared__ double Ml[PCG_RMAX * 81];
+  __shared__ double zl[PCG_ZCOLS * 9];
+  __shared__ double wl[PCG_RMAX * 9], ml[PCG_RMAX * 9], nl[PCG_RMAX * 9];
+  __shared__ double seg[(PCG_RMAX + STREAM_GROUPS) * 9];
+  __shared__ __align__(16) unsigned char st[(PCG_THREADS / 64) * STREAM_WAVE_BYTES];
+  __shared__ int rptr[PCG_RMAX + 1];
+  __shared__ double red[PCG_THREADS / 64];
+  __shared__ double red3[PCG_THREADS / 64][3];
+  __shared__ double red3s[3 * (PCG_THREADS / 64)];
+  __shared__ int poll_failed;
+  const int G = gridDim.x, B = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
+  const int r0 = a.wg_row[B], nr = a.wg_row[B + 1] - r0;
+  const int n9 = nr * 9;
+  const int sib = a.sitem_ptr[B], nitems = a.sitem_ptr[B + 1] - sib;
+  const int ub = a.ucol_ptr[B], nuc = a.ucol_ptr[B + 1] - ub;
+  const size_t zstride = (size_t)a.nc * ZSTRIDE, pstride = (size_t)G * PART_STRIDE;
+  const int L = max(1, (nitems + STREAM_GROUPS - 1) / STREAM_GROUPS);
+  if (tid == 0) {
+    rptr[0] = 0;
+    for (int i = 0; i < nr; ++i)
+      rptr[i + 1] = rptr[i] + (a.S_ptr[r0 + i + 1] - a.S_ptr[r0 + i] - 1) +
+                    (a.T_ptr[r0 + i + 1] - a.T_ptr[r0 + i]);
+  }
+  // thread tid owns element tid of the workgroup's rows
+  const bool own = tid < n9;
+  const int row = own ? tid / 9 : 0, cp = own ? tid - 9 * row : 0;
+  double x = 0.0, r = 0.0, u = 0.0, w = 0.0, m = 0.0, z = 0.0, q = 0.0, s = 0.0, p = 0.0;
+  // row cp of the FP64 diagonal block of row `row` (read when applied)
+  const double* drow = a.Sdiag + 81 * (size_t)(r0 + row) + cp * 9;
+  if (own) {
+    r = a.b[9 * (size_t)r0 + tid];
+    nl[tid] = r;
+  }
+  for (int i = tid; i < nr * 81; i += nt) Ml[i] = a.Minv[81 * (size_t)r0 + i];
+  __syncthreads();
+  // u0 = M b, published in slot 0; w0 = S u0
+  double s_bb = 0.0;
+  if (own) {
+    double v = 0.0;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) v += Ml[row * 81 + cp * 9 + k] * nl[row * 9 + k];
+    u = v;
+    ml[tid] = u;
+    publish(a.zring + (size_t)(r0 + row) * ZSTRIDE + cp, u);
+    s_bb = r * r;
+  }
+  s_bb = block_sum(s_bb, red);  // (its barriers also complete ml)
+  if (tid == 0) publish(a.partB + (size_t)B * PART_STRIDE, s_bb);
+  double nd = 0.0;  // diagonal part of the product
+  if (own) {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) nd += drow[k] * ml[row * 9 + k];
+  }
+  for (int k = tid; k < 3 * (a.maxiter + 1); k += nt)
+    clear_record(a.partA + (size_t)(k / 3) * pstride + (size_t)B * PART_STRIDE + (k - 3 * (k / 3)));
+  bool ok = grid_barrier(a.gs, a.error);
+  pcg_fetch_z(a, a.zring, ub, nuc, zl);
+  double t0 = 0.0;
+  for (int i = tid; i < G; i += nt) t0 += a.partB[(size_t)i * PART_STRIDE];
+  const double bnorm = sqrt(block_sum(t0, red));  // (its barriers complete zl)
+  stream_spmv(a, sib, nitems, L, nr, rptr, zl, seg, st, nl);
+  if (own) {
+    w = nl[tid] + nd;
+    wl[tid] = w;
+  }
+  __syncthreads();
+  double rnorm = bnorm, gamma_old = 1.0, alpha_old = 1.0;
+  int iters = 0, breakdown = 0;
+  for (int i = 0; ok && bnorm > 0.0 && i <= a.maxiter; ++i) {
+    // local: partial dots of r, u, w; m = M w published in slot i + 1
+    double* zk = a.zring + (size_t)(i + 1) * zstride;
+    double s_g = 0.0, s_d = 0.0, s_r = 0.0;
+    if (own) {
+      double v = 0.0;
+#pragma unroll
+      for (int k = 0; k < 9; ++k) v += Ml[row * 81 + cp * 9 + k] * wl[row * 9 + k];
+      m = v;
+      ml[tid] = m;
+      publish(zk + (size_t)(r0 + row) * ZSTRIDE + cp, m);
+      s_g = r * u;
+      s_d = w * u;
+      s_r = r * r;
+    }
+    s_g = wave_sum(s_g);
+    s_d = wave_sum(s_d);
+    s_r = wave_sum(s_r);
+    if ((tid & 63) == 0) {
+      red3[tid >> 6][0] = s_g;
+      red3[tid >> 6][1] = s_d;
+      red3[tid >> 6][2] = s_r;
+    }
+    // the m columns must have reached memory before the partials are seen
+    __builtin_amdgcn_s_waitcnt(0);
+    if (tid == 0) poll_failed = 0;
+    __syncthreads();
+    double* pa = a.partA + (size_t)i * pstride;
+    if (tid < 3) {
+      double v = 0.0;
+      for (int w2 = 0; w2 < PCG_THREADS / 64; ++w2) v += red3[w2][tid];
+      publish(pa + (size_t)B * PART_STRIDE + tid, v);
+    }
+    // the diagonal part of n = S m while the other workgroups catch up
+    nd = 0.0;
+    if (own) {
+#pragma unroll
+      for (int k = 0; k < 9; ++k) nd += drow[k] * ml[row * 9 + k];
+    }
+    double tg = 0.0, td = 0.0, tr = 0.0;
+    if (tid < G && !poll_record(pa + (size_t)tid * PART_STRIDE, tg, td, tr, a.error)) poll_failed = 1;
+    tg = wave_sum(tg);
+    td = wave_sum(td);
+    tr = wave_sum(tr);
+    if ((tid & 63) == 0) {
+      red3s[3 * (tid >> 6)] = tg;
+      red3s[3 * (tid >> 6) + 1] = td;
+      red3s[3 * (tid >> 6) + 2] = tr;
+    }
+    __syncthreads();
+    if (poll_failed) {
+      ok = false;
+      break;
+    }
+    // every workgroup's m columns are in memory now
+    pcg_fetch_z(a, zk, ub, nuc, zl);
+    double gamma = 0.0, delta = 0.0, rr = 0.0;
+#pragma unroll 2
+    for (int w2 = 0; w2 < PCG_THREADS / 64; ++w2) {
+      gamma += red3s[3 * w2];
+      delta += red3s[3 * w2 + 1];
+      rr += red3s[3 * w2 + 2];
+    }
+    iters = i;
+    rnorm = sqrt(rr);
+    if (rnorm <= a.rtol * bnorm || i == a.maxiter) break;
+    const double beta = i > 0 ? gamma / gamma_old : 0.0;
+    const double den = i > 0 ? delta - beta * gamma / alpha_old : delta;
+    if (!(den > 0.0)) {
+      breakdown = 1;
+      break;
+    }
+    const double alpha = gamma / den;
+    __syncthreads();  // zl complete
+    stream_spmv(a, sib, nitems, L, nr, rptr, zl, seg, st, nl);
+    if (own) {
+      const double n = nl[tid] + nd;
+      z = n + beta * z;
+      q = m + beta * q;
+      s = w + beta * s;
+      p = u + beta * p;
+      x += alpha * p;
+      r -= alpha * s;
+      u -= alpha * q;
+      w -= alpha * z;
+      wl[tid] = w;
+    }
+    __syncthreads();
+    gamma_old = gamma;
+    alpha_old = alpha;
+  }
+  if (own) a.x[9 * (size_t)r0 + tid] = x;
+  if (B == 0 && tid == 0) {
+    a.info->cg_iters = iters;
+    a.info->cg_breakdown = breakdown;
+    a.info->cg_rel_resid = bnorm > 0.0 ? rnorm / bnorm : 0.0;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
 
 template <typename T>
 static const void* pcg_kernel(bool resident, bool pipelined) {
+  if (sizeof(T) == 4 && pipelined && !resident) return reinterpret_cast<const void*>(k_pcg_stream);
   if (pipelined)
     return resident ? reinterpret_cast<const void*>(k_pcg_pipelined<T, true>)
                     : reinterpret_cast<const void*>(k_pcg_pipelined<T, false>);
@@ -623,6 +919,8 @@ template int pcg_max_grid<double>(bool, bool);
 
 template <typename T>
 hipError_t launch_pcg(const PcgArgs& a, int grid, bool resident, bool pipelined, hipStream_t s) {
+  if (sizeof(T) == 4 && pipelined && !resident && (!a.SI || !a.sitem_ptr || !a.sitem_col))
+    return hipErrorInvalidValue;  // the streamed kernel needs the per-item blocks
   void* args[] = {const_cast<PcgArgs*>(&a)};
   return hipLaunchCooperativeKernel(pcg_kernel<T>(resident, pipelined), dim3(grid), dim3(PCG_THREADS),
                                     args, 0, s);

@@ -336,6 +336,9 @@ std::string build_plan(int32_t nc, int32_t np, int64_t no, const int32_t* cidx, 
     }
     p.item_ptr.assign(p.pcg_grid + 1, 0);
     p.ucol_ptr.assign(p.pcg_grid + 1, 0);
+    p.sitem_ptr.assign(p.pcg_resident ? 0 : p.pcg_grid + 1, 0);
+    p.sitem_col.clear();
+    p.blk_pos.assign(p.pcg_resident ? 0 : 2 * (size_t)p.nnzb, -1);
     p.item_e.clear();
     p.item_code.clear();
     p.ucol.clear();
@@ -366,6 +369,19 @@ std::string build_plan(int32_t nc, int32_t np, int64_t no, const int32_t* cidx, 
         }
       }
       p.item_ptr[g + 1] = (int32_t)p.item_e.size();
+      if (!p.pcg_resident) {
+        for (int32_t a = r0; a < r1; ++a) {
+          for (int32_t e = p.S_ptr[a] + 1; e < p.S_ptr[a + 1]; ++e) {
+            p.blk_pos[2 * (size_t)e] = (int32_t)p.sitem_col.size();
+            p.sitem_col.push_back(local(p.S_col[e]));
+          }
+          for (int32_t t = p.T_ptr[a]; t < p.T_ptr[a + 1]; ++t) {
+            p.blk_pos[2 * (size_t)p.T_blk[t] + 1] = (int32_t)p.sitem_col.size();
+            p.sitem_col.push_back(local(p.T_src[t]));
+          }
+        }
+        p.sitem_ptr[g + 1] = (int32_t)p.sitem_col.size();
+      }
       p.ucol.insert(p.ucol.end(), uc.begin(), uc.end());
       p.ucol_ptr[g + 1] = (int32_t)p.ucol.size();
     }
