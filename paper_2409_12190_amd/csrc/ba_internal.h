@@ -46,8 +46,8 @@ constexpr int BARRIER_FANIN = 16;
 constexpr int MAX_BARRIER_GROUPS = 128;
 constexpr int MAX_TRACK = CHUNK;
 constexpr int FINAL_STAGE_MAX = 256;  // workgroups of the first acceptance-reduction stage
-constexpr int SI_STRIDE = 88;         // values per block of the streamed PCG copy of S (81 + zeros:
-                                      // whole 32-byte sectors in FP32)
+constexpr int SI_STRIDE = 84;         // values per block of the streamed PCG copy of S (81 + zeros:
+                                      // 16-byte aligned blocks in FP32)
 
 // Host-side symbolic analysis of the observation pattern (computed once per
 // problem; the paper caches its sparse-product table the same way, Sec. IV-B-1).
