@@ -37,6 +37,16 @@ namespace ba {
 // direction update and the product share one barrier (two per iteration).
 // ---------------------------------------------------------------------------
 constexpr int SPMV_GROUPS = PCG_THREADS / 9;
+
+// Workgroup b of the grid runs on XCD b % 8 (round-robin dispatch); it takes
+// the row range of index xcd_block(b): each XCD gets a contiguous run of row
+// ranges, so the z columns a workgroup reads come mostly from workgroups of
+// its own XCD, whose write-through stores leave the lines in that XCD's L2.
+// A bijection of [0, G).
+__device__ __forceinline__ int xcd_block(int b, int G) {
+  const int x = b & 7, n8 = G >> 3, rem = G & 7;
+  return x * n8 + min(x, rem) + (b >> 3);
+}
 constexpr long BARRIER_SPIN_LIMIT = 1L << 21;
 
 __device__ __forceinline__ void publish(double* p, double v) {
@@ -264,7 +274,7 @@ __global__ __launch_bounds__(PCG_THREADS) void k_pcg_standard(PcgArgs a) {
   __shared__ double seg[(PCG_RMAX + SPMV_GROUPS) * 9];
   __shared__ int rptr[PCG_RMAX + 1];
   __shared__ double red[PCG_THREADS / 64];
-  const int G = gridDim.x, B = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
+  const int G = gridDim.x, B = xcd_block(blockIdx.x, gridDim.x), tid = threadIdx.x, nt = blockDim.x;
   const int r0 = a.wg_row[B], nr = a.wg_row[B + 1] - r0;
   const int n9 = nr * 9;
   const int ib = a.item_ptr[B], nitems = a.item_ptr[B + 1] - ib;
@@ -431,7 +441,7 @@ __global__ __launch_bounds__(PCG_THREADS) void k_pcg_pipelined(PcgArgs a) {
   __shared__ double seg[(PCG_RMAX + SPMV_GROUPS) * 9];
   __shared__ int rptr[PCG_RMAX + 1];
   __shared__ double red[PCG_THREADS / 64];
-  const int G = gridDim.x, B = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
+  const int G = gridDim.x, B = xcd_block(blockIdx.x, gridDim.x), tid = threadIdx.x, nt = blockDim.x;
   const int r0 = a.wg_row[B], nr = a.wg_row[B + 1] - r0;
   const int n9 = nr * 9;
   const int ib = a.item_ptr[B], nitems = a.item_ptr[B + 1] - ib;
@@ -733,7 +743,7 @@ __global__ __launch_bounds__(PCG_THREADS) void k_pcg_stream(PcgArgs a) {
   __shared__ double red3[PCG_THREADS / 64][3];
   __shared__ double red3s[3 * (PCG_THREADS / 64)];
   __shared__ int poll_failed;
-  const int G = gridDim.x, B = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
+  const int G = gridDim.x, B = xcd_block(blockIdx.x, gridDim.x), tid = threadIdx.x, nt = blockDim.x;
   const int r0 = a.wg_row[B], nr = a.wg_row[B + 1] - r0;
   const int n9 = nr * 9;
   const int sib = a.sitem_ptr[B], nitems = a.sitem_ptr[B + 1] - sib;
