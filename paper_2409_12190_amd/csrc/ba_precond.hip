@@ -17,6 +17,7 @@
 // All network arithmetic is FP32; every reduction runs in a fixed order
 // (no atomics), so training is bitwise reproducible.
 #include "ba_precond.h"
+#include "ba_reduce.h"
 
 namespace ba {
 
@@ -33,71 +34,102 @@ __device__ __forceinline__ int lo9(int r, int c) { return (r * (r + 1)) / 2 + c;
 // T = Linv_row S_e Linv_col^T, by the same code from both endpoints, so the
 // two endpoints see bit-identical weights.
 // ---------------------------------------------------------------------------
+// One workgroup of PC_FEAT_WAVES wavefronts per camera i; wavefront v takes
+// the camera's neighbour slots v, v + PC_FEAT_WAVES, ...: the lanes share one
+// block at a time through LDS (entry (r, c) of each 9x9 product per lane),
+// and the wavefronts' partial sums of E_i are added in wavefront order.
+constexpr int PC_FEAT_WAVES = 4;
+
 template <typename T>
-__global__ __launch_bounds__(64) void k_pc_features(PcFeatureArgs a) {
-  __shared__ double red[47];
-  const int i = blockIdx.x, lane = threadIdx.x;
+__global__ __launch_bounds__(64 * PC_FEAT_WAVES) void k_pc_features(PcFeatureArgs a) {
+  __shared__ double sm[PC_FEAT_WAVES][5][81];  // block, Linv of its row, of its column, products
+  __shared__ double es[PC_FEAT_WAVES][45];
+  __shared__ double as_[PC_FEAT_WAVES];
+  const int i = blockIdx.x, wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  double* Bv = sm[wave][0];
+  double* La = sm[wave][1];
+  double* Lb = sm[wave][2];
+  double* Pm = sm[wave][3];
+  double* Tm = sm[wave][4];
   const int s0 = a.nbr_ptr[i], s1 = a.nbr_ptr[i + 1];
   const T* __restrict__ Sv = reinterpret_cast<const T*>(a.S);
-  double e[45];
-  for (int q = 0; q < 45; ++q) e[q] = 0.0;
-  double asum = 0.0;
-  for (int s = s0 + lane; s < s1; s += 64) {
-    const int blk = a.nbr_blk[s];
+  // entry of E_i this lane accumulates (lanes < 45)
+  int er = 0, ec = 0;
+  if (lane < 45) {
+    while (up9(er, 8) < lane) ++er;
+    ec = er + (lane - up9(er, er));
+  }
+  double e_acc = 0.0, asum = 0.0;
+  const int rounds = (s1 - s0 + PC_FEAT_WAVES - 1) / PC_FEAT_WAVES;
+  for (int it = 0; it < rounds; ++it) {
+    const int sl = s0 + it * PC_FEAT_WAVES + wave;
+    const bool valid = sl < s1;
+    const int slot = valid ? sl : s0;
+    const int blk = a.nbr_blk[slot];
     const int ra = a.blk_row[blk], cb = a.S_col[blk];
-    const double* La = a.Linv + 81 * (size_t)ra;
-    const double* Lb = a.Linv + 81 * (size_t)cb;
-    const T* B = Sv + 81 * (size_t)blk;
-    double P[9][9];  // Linv_row S_e
-    for (int r = 0; r < 9; ++r)
-      for (int c = 0; c < 9; ++c) {
-        double v = 0.0;
-        for (int k = 0; k <= r; ++k) v += La[9 * r + k] * (double)B[9 * k + c];
-        P[r][c] = v;
-      }
-    double Tm[9][9];  // (Linv_row S_e) Linv_col^T
+    for (int q = lane; q < 81; q += 64) {
+      Bv[q] = (double)Sv[81 * (size_t)blk + q];
+      La[q] = a.Linv[81 * (size_t)ra + q];
+      Lb[q] = a.Linv[81 * (size_t)cb + q];
+    }
+    __syncthreads();
+    // P = Linv_row S_e (lower-triangular factor)
+    for (int q = lane; q < 81; q += 64) {
+      const int r = q / 9, c = q - 9 * r;
+      double v = 0.0;
+      for (int k = 0; k <= r; ++k) v += La[9 * r + k] * Bv[9 * k + c];
+      Pm[q] = v;
+    }
+    __syncthreads();
+    // T = P Linv_col^T: the normalised block as stored
     double fro = 0.0;
-    for (int r = 0; r < 9; ++r)
-      for (int c = 0; c < 9; ++c) {
-        double v = 0.0;
-        for (int k = 0; k <= c; ++k) v += P[r][k] * Lb[9 * c + k];
-        Tm[r][c] = v;
-        fro += v * v;
-      }
-    const bool up = (ra == i);
-    // S^_ij = T (upper slot) or T^T (lower slot); E_i += S^ S^^T
-    for (int r = 0; r < 9; ++r)
-      for (int c = r; c < 9; ++c) {
+    for (int q = lane; q < 81; q += 64) {
+      const int r = q / 9, c = q - 9 * r;
+      double v = 0.0;
+      for (int k = 0; k <= c; ++k) v += Pm[9 * r + k] * Lb[9 * c + k];
+      Tm[q] = v;
+      fro += v * v;
+    }
+    __syncthreads();
+    fro = wave_sum(fro);
+    if (valid) {
+      // S^_ij = T (camera i is the block's row) or T^T: E_i += S^ S^^T
+      const bool up = ra == i;
+      if (lane < 45) {
         double v = 0.0;
         if (up)
-          for (int k = 0; k < 9; ++k) v += Tm[r][k] * Tm[c][k];
+          for (int k = 0; k < 9; ++k) v += Tm[9 * er + k] * Tm[9 * ec + k];
         else
-          for (int k = 0; k < 9; ++k) v += Tm[k][r] * Tm[k][c];
-        e[up9(r, c)] += v;
+          for (int k = 0; k < 9; ++k) v += Tm[9 * k + er] * Tm[9 * k + ec];
+        e_acc += v;
       }
-    const double aw = sqrt(fro);
-    a.w[s] = (float)aw;  // normalised below
-    asum += aw;
+      const double aw = sqrt(fro);
+      if (lane == 0) a.w[sl] = (float)aw;  // normalised below
+      asum += aw;
+    }
+    __syncthreads();
   }
-  for (int q = 0; q < 45; ++q) {
-    double v = e[q];
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    if (lane == 0) red[q] = v;
-  }
-  for (int o = 32; o > 0; o >>= 1) asum += __shfl_xor(asum, o, 64);
+  if (lane < 45) es[wave][lane] = e_acc;
+  if (lane == 0) as_[wave] = asum;
   __syncthreads();
-  double tr = 0.0;
-  for (int r = 0; r < 9; ++r) tr += red[up9(r, r)];
-  if (lane < 45) {
-    a.E[45 * (size_t)i + lane] = (float)red[lane];
-    a.X[GNN_F * (size_t)i + lane] = (float)red[lane];
-  } else if (lane == 45) {
+  double tot = 0.0, tr = 0.0;
+  for (int v = 0; v < PC_FEAT_WAVES; ++v) tot += as_[v];
+  for (int r = 0; r < 9; ++r)
+    for (int v = 0; v < PC_FEAT_WAVES; ++v) tr += es[v][up9(r, r)];
+  const int t = threadIdx.x;
+  if (t < 45) {
+    double e = 0.0;
+    for (int v = 0; v < PC_FEAT_WAVES; ++v) e += es[v][t];
+    a.E[45 * (size_t)i + t] = (float)e;
+    a.X[GNN_F * (size_t)i + t] = (float)e;
+  } else if (t == 45) {
     a.X[GNN_F * (size_t)i + 45] = (float)log1p(tr);
-  } else if (lane == 46) {
+  } else if (t == 46) {
     a.X[GNN_F * (size_t)i + 46] = (float)log1p((double)(s1 - s0));
   }
-  // weights: a_ij / sum_j a_ij, recomputed in the same order by the same lane
-  for (int s = s0 + lane; s < s1; s += 64) a.w[s] = asum > 0.0 ? (float)((double)a.w[s] / asum) : 0.0f;
+  // weights: a_ij / sum_j a_ij (each slot written above by its wavefront's lane 0)
+  __syncthreads();
+  for (int sl = s0 + t; sl < s1; sl += blockDim.x) a.w[sl] = tot > 0.0 ? (float)((double)a.w[sl] / tot) : 0.0f;
 }
 
 // ---------------------------------------------------------------------------
@@ -136,6 +168,7 @@ __global__ __launch_bounds__(256) void k_gnn_aggregate(int n, const int32_t* __r
   const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (i >= n) return;
   float m = 0.0f;
+#pragma unroll 4
   for (int s = nbr_ptr[i]; s < nbr_ptr[i + 1]; ++s) m = fmaf(w[s], H[(size_t)nbr[s] * GNN_H + f], m);
   M[(size_t)i * GNN_H + f] = m;
 }
@@ -338,20 +371,21 @@ __global__ __launch_bounds__(256) void k_gnn_weights_bf16(const float* __restric
   Wb[q] = to_bf16(k < GNN_H ? L0[o * GNN_H + k] : L0[GNN_H * GNN_H + o * GNN_H + (k - GNN_H)]);
 }
 
-// Z = [X | M] W^T + b, H = relu(Z); one wave per 16 rows, four 16x16 output
-// tiles, v_mfma_f32_16x16x16_bf16 (lane l: A row l%16, k 4(l/16)..+3; B
-// column l%16, same k; D rows 4(l/16)..+3 of column l%16)
+// Z = [X | M] W^T + b, H = relu(Z); one workgroup per 16 rows, one 16x16
+// output tile per wavefront, v_mfma_f32_16x16x16_bf16 (lane l: A row l%16,
+// k 4(l/16)..+3; B column l%16, same k; D rows 4(l/16)..+3 of column l%16)
 __global__ __launch_bounds__(256) void k_gnn_dense_bf16(int n, const float* __restrict__ X, int K1,
                                                          const float* __restrict__ M,
                                                          const short* __restrict__ Wb, int Kp,
                                                          const float* __restrict__ b,
                                                          float* __restrict__ Z, float* __restrict__ H) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int r0 = (blockIdx.x * 4 + wave) * 16;
+  // wavefront (workgroup, w) computes output rows r0..r0+15, columns
+  // 16 t .. 16 t + 15 with t = w (4 wavefronts cover the 64 columns)
+  const int lane = threadIdx.x & 63, t = threadIdx.x >> 6;
+  const int r0 = blockIdx.x * 16;
   if (r0 >= n) return;
   const int row = r0 + (lane & 15), kq = 4 * (lane >> 4);
-  f32x4 acc[4];
-  for (int t = 0; t < 4; ++t) acc[t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+  f32x4 acc = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
   for (int kb = 0; kb < Kp; kb += 16) {
     bf16x4 av;
     for (int j = 0; j < 4; ++j) {
@@ -363,21 +397,17 @@ __global__ __launch_bounds__(256) void k_gnn_dense_bf16(int n, const float* __re
       }
       av[j] = to_bf16(v);
     }
-    for (int t = 0; t < 4; ++t) {
-      const short* w = Wb + (size_t)(16 * t + (lane & 15)) * Kp + kb + kq;
-      const bf16x4 bv = {w[0], w[1], w[2], w[3]};
-      acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc[t], 0, 0, 0);
-    }
+    const short* w = Wb + (size_t)(16 * t + (lane & 15)) * Kp + kb + kq;
+    const bf16x4 bv = {w[0], w[1], w[2], w[3]};
+    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc, 0, 0, 0);
   }
-  for (int t = 0; t < 4; ++t) {
-    const int col = 16 * t + (lane & 15);
-    for (int j = 0; j < 4; ++j) {
-      const int r = r0 + kq + j;
-      if (r < n) {
-        const float z = acc[t][j] + b[col];
-        Z[(size_t)r * GNN_H + col] = z;
-        H[(size_t)r * GNN_H + col] = fmaxf(z, 0.0f);
-      }
+  const int col = 16 * t + (lane & 15);
+  for (int j = 0; j < 4; ++j) {
+    const int r = r0 + kq + j;
+    if (r < n) {
+      const float z = acc[j] + b[col];
+      Z[(size_t)r * GNN_H + col] = z;
+      H[(size_t)r * GNN_H + col] = fmaxf(z, 0.0f);
     }
   }
 }
@@ -393,7 +423,7 @@ hipError_t launch_gnn_weights_bf16(const float* P, short* Wb, hipStream_t s) {
 }
 
 hipError_t launch_gnn_forward_bf16(const GraphDev& g, const float* P, const short* Wb, hipStream_t s) {
-  const dim3 grid((g.nc + 63) / 64), blk(256);
+  const dim3 grid((g.nc + 15) / 16), blk(256);
   hipLaunchKernelGGL(k_gnn_dense_bf16, grid, blk, 0, s, g.nc, g.X, GNN_F, (const float*)nullptr, Wb,
                      GNN_KIN, P + GNN_OFF_BIN, g.Z[0], g.H[0]);
   const dim3 rows((g.nc + 3) / 4);
@@ -409,7 +439,7 @@ hipError_t launch_gnn_forward_bf16(const GraphDev& g, const float* P, const shor
 
 template <typename T>
 hipError_t launch_pc_features(const PcFeatureArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_pc_features<T>, dim3(a.nc), dim3(64), 0, s, a);
+  hipLaunchKernelGGL(k_pc_features<T>, dim3(a.nc), dim3(64 * PC_FEAT_WAVES), 0, s, a);
   return hipGetLastError();
 }
 template hipError_t launch_pc_features<float>(const PcFeatureArgs&, hipStream_t);
