@@ -42,15 +42,18 @@ constexpr int PC_FEAT_WAVES = 4;
 
 template <typename T>
 __global__ __launch_bounds__(64 * PC_FEAT_WAVES) void k_pc_features(PcFeatureArgs a) {
-  __shared__ double sm[PC_FEAT_WAVES][5][81];  // block, Linv of its row, of its column, products
+  // block, the neighbour's Linv, products (rows of 128: every lane stores
+  // entries lane and lane + 64 without a branch)
+  __shared__ double sm[PC_FEAT_WAVES][4][128];
+  __shared__ double Li[81];                    // this camera's Linv
   __shared__ double es[PC_FEAT_WAVES][45];
   __shared__ double as_[PC_FEAT_WAVES];
   const int i = blockIdx.x, wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   double* Bv = sm[wave][0];
-  double* La = sm[wave][1];
-  double* Lb = sm[wave][2];
-  double* Pm = sm[wave][3];
-  double* Tm = sm[wave][4];
+  double* Ln = sm[wave][1];
+  double* Pm = sm[wave][2];
+  double* Tm = sm[wave][3];
+  for (int q = threadIdx.x; q < 81; q += blockDim.x) Li[q] = a.Linv[81 * (size_t)i + q];
   const int s0 = a.nbr_ptr[i], s1 = a.nbr_ptr[i + 1];
   const T* __restrict__ Sv = reinterpret_cast<const T*>(a.S);
   // entry of E_i this lane accumulates (lanes < 45)
@@ -61,18 +64,36 @@ __global__ __launch_bounds__(64 * PC_FEAT_WAVES) void k_pc_features(PcFeatureArg
   }
   double e_acc = 0.0, asum = 0.0;
   const int rounds = (s1 - s0 + PC_FEAT_WAVES - 1) / PC_FEAT_WAVES;
+  // the next round's block and neighbour factor are loaded into registers
+  // while the current one is processed (entries lane and lane + 64)
+  int nblk = 0, nra = 0, ncb = 0;
+  double pb0 = 0.0, pb1 = 0.0, pl0 = 0.0, pl1 = 0.0;
+  auto prefetch = [&](int it) {
+    const int sl = min(s0 + it * PC_FEAT_WAVES + wave, s1 - 1);
+    nblk = a.nbr_blk[sl];
+    nra = a.blk_row[nblk];
+    ncb = a.S_col[nblk];
+    const int other = nra == i ? ncb : nra;
+    pb0 = (double)Sv[81 * (size_t)nblk + lane];
+    pl0 = a.Linv[81 * (size_t)other + lane];
+    const int q1 = min(lane + 64, 80);
+    pb1 = (double)Sv[81 * (size_t)nblk + q1];
+    pl1 = a.Linv[81 * (size_t)other + q1];
+  };
+  if (rounds > 0) prefetch(0);
   for (int it = 0; it < rounds; ++it) {
     const int sl = s0 + it * PC_FEAT_WAVES + wave;
     const bool valid = sl < s1;
-    const int slot = valid ? sl : s0;
-    const int blk = a.nbr_blk[slot];
-    const int ra = a.blk_row[blk], cb = a.S_col[blk];
-    for (int q = lane; q < 81; q += 64) {
-      Bv[q] = (double)Sv[81 * (size_t)blk + q];
-      La[q] = a.Linv[81 * (size_t)ra + q];
-      Lb[q] = a.Linv[81 * (size_t)cb + q];
-    }
+    const int ra = nra, cb = ncb;
+    const bool up = ra == i;  // camera i is the block's row (else its column)
+    Bv[lane] = pb0;
+    Ln[lane] = pl0;
+    Bv[lane + 64] = pb1;
+    Ln[lane + 64] = pl1;
+    if (it + 1 < rounds) prefetch(it + 1);
     __syncthreads();
+    const double* La = up ? Li : Ln;  // Linv of the block's row camera
+    const double* Lb = up ? Ln : Li;  // and of its column camera
     // P = Linv_row S_e (lower-triangular factor)
     for (int q = lane; q < 81; q += 64) {
       const int r = q / 9, c = q - 9 * r;
@@ -94,7 +115,6 @@ __global__ __launch_bounds__(64 * PC_FEAT_WAVES) void k_pc_features(PcFeatureArg
     fro = wave_sum(fro);
     if (valid) {
       // S^_ij = T (camera i is the block's row) or T^T: E_i += S^ S^^T
-      const bool up = ra == i;
       if (lane < 45) {
         double v = 0.0;
         if (up)
