@@ -291,6 +291,10 @@ ba_status ba_export(const ba_problem* p, int32_t field, void* host_dst, size_t b
  * profiling was last enabled. */
 enum { BA_NUM_PHASES = 13 };
 ba_status ba_set_profiling(ba_problem* p, int32_t enable);
+/* As ba_set_profiling, but events are recorded only around the phases whose
+ * bit (1 << phase) is set in mask (0: off); fewer events disturb the timed
+ * steps less.  ba_set_profiling(p, 1) is ba_set_profiling_mask(p, all). */
+ba_status ba_set_profiling_mask(ba_problem* p, uint32_t mask);
 ba_status ba_get_phase_times(const ba_problem* p, double* ms_out, int64_t* launches_out, int32_t n);
 
 /* Number of stored upper blocks of the reduced camera matrix (incl. diagonal). */

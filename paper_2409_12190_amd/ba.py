@@ -30,7 +30,7 @@ EXPORTED_SYMBOLS = [
     "ba_set_observations", "ba_set_fixed_cameras", "ba_set_params", "ba_get_params",
     "ba_set_lambda", "ba_get_lambda", "ba_set_cg", "ba_lm_step", "ba_solve", "ba_backward",
     "ba_get_state", "ba_set_state", "ba_export", "ba_problem_nnzb", "ba_set_profiling",
-    "ba_get_phase_times", "ba_problem_destroy", "ba_last_error", "ba_gnn_num_params",
+    "ba_set_profiling_mask", "ba_get_phase_times", "ba_problem_destroy", "ba_last_error", "ba_gnn_num_params",
     "ba_set_gnn_params", "ba_graph_create", "ba_graph_workspace_bytes", "ba_graph_bind",
     "ba_graph_build", "ba_gnn_loss_grad", "ba_gnn_adam", "ba_graph_destroy",
 ]
@@ -98,6 +98,7 @@ def lib():
         L.ba_export.argtypes = [P, C.c_int32, P, C.c_size_t]
         L.ba_problem_nnzb.argtypes = [P, C.POINTER(C.c_int64)]
         L.ba_set_profiling.argtypes = [P, C.c_int32]
+        L.ba_set_profiling_mask.argtypes = [P, C.c_uint32]
         L.ba_get_phase_times.argtypes = [P, P, P, C.c_int32]
         L.ba_problem_destroy.argtypes = [P]
         L.ba_problem_destroy.restype = None
@@ -249,6 +250,10 @@ def ba_set_profiling(h: int, enable: bool):
     _check(lib().ba_set_profiling(h, 1 if enable else 0))
 
 
+def ba_set_profiling_mask(h: int, mask: int):
+    _check(lib().ba_set_profiling_mask(h, mask))
+
+
 def ba_get_phase_times(h: int):
     ms = np.zeros(BA_NUM_PHASES)
     n = np.zeros(BA_NUM_PHASES, np.int64)
@@ -393,8 +398,13 @@ class Problem:
         self.stream.synchronize()
         _check(lib().ba_set_gnn_params(self.h, self._gnn.data_ptr()))
 
-    def set_profiling(self, enable: bool = True):
-        ba_set_profiling(self.h, enable)
+    def set_profiling(self, enable: bool = True, phases=None):
+        """Events around every phase (enable), or only around the named
+        phases (PHASE_NAMES entries)."""
+        if phases is None:
+            ba_set_profiling(self.h, enable)
+        else:
+            ba_set_profiling_mask(self.h, sum(1 << PHASE_NAMES.index(n) for n in phases) if enable else 0)
 
     def phase_times(self) -> dict:
         ms, n = ba_get_phase_times(self.h)

@@ -186,14 +186,15 @@ struct Phase {
   ba_problem* p;
   int id;
   Phase(ba_problem* pp, int i) : p(pp), id(i) {
-    if (p->profiling) (void)hipEventRecord(p->ev[id][0], p->stream);
+    if (on()) (void)hipEventRecord(p->ev[id][0], p->stream);
   }
   ~Phase() {
-    if (p->profiling) {
+    if (on()) {
       (void)hipEventRecord(p->ev[id][1], p->stream);
       p->phase_used[id] = true;
     }
   }
+  bool on() const { return p->profiling && (p->profile_mask >> id & 1u); }
 };
 
 void collect_phase_times(ba_problem* p) {
@@ -929,8 +930,13 @@ ba_status ba_export(const ba_problem* p, int32_t field, void* dst, size_t bytes)
 }
 
 ba_status ba_set_profiling(ba_problem* p, int32_t enable) {
+  return ba_set_profiling_mask(p, enable ? (1u << BA_NUM_PHASES) - 1u : 0u);
+}
+
+ba_status ba_set_profiling_mask(ba_problem* p, uint32_t mask) {
   if (!p) return fail(BA_EINVAL, "null problem");
   if (!p->bound) return fail(BA_ESTATE, "problem is not bound");
+  const bool enable = mask != 0;
   if (enable && !p->ev[0][0]) {
     for (int i = 0; i < BA_NUM_PHASES; ++i)
       for (int k = 0; k < 2; ++k) HIPCHK(hipEventCreate(&p->ev[i][k]));
@@ -940,7 +946,8 @@ ba_status ba_set_profiling(ba_problem* p, int32_t enable) {
     p->phase_n[i] = 0;
     p->phase_used[i] = false;
   }
-  p->profiling = enable != 0;
+  p->profiling = enable;
+  p->profile_mask = mask;
   return BA_OK;
 }
 

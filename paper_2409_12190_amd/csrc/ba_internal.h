@@ -208,6 +208,7 @@ struct ba_problem {
   bool gnn_ready = false;    // learned preconditioner parameters are set
   bool have_system = false;  // a step has formed the reduced system
   int32_t rec_unit = 0;      // records' first 64-byte unit counted from J
+  uint32_t profile_mask = 0;  // phases bracketed by events while profiling
   ba_step_info* hinfo = nullptr;     // pinned host staging
   ba::DevScalars* hscal = nullptr;   // pinned host staging
 };
