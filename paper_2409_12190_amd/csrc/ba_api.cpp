@@ -90,9 +90,17 @@ void carve(ba_problem* p, char* base, size_t* total) {
   b.item_code = c.take<int32_t>(P.item_code.size());
   b.ucol_ptr = c.take<int32_t>(P.ucol_ptr.size());
   b.ucol = c.take<int32_t>(P.ucol.size());
+  b.srow = c.take<int32_t>(P.srow.size());
   b.sitem_ptr = c.take<int32_t>(P.sitem_ptr.size());
   b.sitem_col = c.take<int32_t>(P.sitem_col.size());
   b.blk_pos = c.take<int32_t>(P.blk_pos.size());
+  b.vcol_ptr = c.take<int32_t>(P.vcol_ptr.size());
+  b.vcol = c.take<int32_t>(P.vcol.size());
+  b.vbase = c.take<int32_t>(P.vbase.size());
+  b.in_ptr = c.take<int32_t>(P.in_ptr.size());
+  b.in_off = c.take<int32_t>(P.in_off.size());
+  b.src_ptr = c.take<int32_t>(P.src_ptr.size());
+  b.src = c.take<int32_t>(P.src.size());
   b.o_orig = c.take<int64_t>(no);
   b.fixed = c.take<uint8_t>(nc);
   b.o_xy = c.take<double>(2 * no);
@@ -115,8 +123,8 @@ void carve(ba_problem* p, char* base, size_t* total) {
   b.Vinv = c.take<double>(6 * np);
   b.ep = c.take<double>(3 * np);
   b.S = c.take<char>(nnzb * 81 * es);
-  // streamed PCG plans in mixed precision: one FP32 copy of each off-diagonal
-  // block per (row, block) item
+  // streamed PCG plans in mixed precision: one FP32 copy of each upper
+  // off-diagonal block
   const bool stream = !P.pcg_resident && p->opt.precision == BA_MIXED;
   b.SI = c.take<char>(stream ? P.sitem_col.size() * ba::SI_STRIDE * 4 : 0);
   b.Sdiag = c.take<double>(81 * nc);
@@ -132,8 +140,10 @@ void carve(ba_problem* p, char* base, size_t* total) {
   b.part_stage = c.take<double>(4 * ba::FINAL_STAGE_MAX);
   const size_t slots = (size_t)p->opt.cg_maxiter + 2;
   b.zring = c.take<double>(slots * nc * ba::ZSTRIDE);
-  b.partA = c.take<double>(slots * P.pcg_grid * ba::PART_STRIDE);
-  b.partB = c.take<double>(slots * P.pcg_grid * ba::PART_STRIDE);
+  b.partA = c.take<double>(slots * std::max(P.pcg_grid, P.sgrid) * ba::PART_STRIDE);
+  b.partB = c.take<double>(slots * std::max(P.pcg_grid, P.sgrid) * ba::PART_STRIDE);
+  b.rring = c.take<double>(stream ? slots * (size_t)P.rstride : 0);
+  b.rflag = c.take<double>(stream ? slots * (size_t)P.sgrid : 0);
   b.dev = c.take<ba::DevScalars>(1);
   b.dinfo = c.take<ba_step_info>(1);
   b.gsync = c.take<ba::GridSync>(1);
@@ -310,13 +320,26 @@ ba_status lm_step_impl(ba_problem* p, ba_step_info* out) {
   PcgArgs pa{P.nc, p->cg_maxiter, p->cg_rtol, b.S_ptr, b.T_ptr, b.pcg_row, b.item_ptr, b.item_e,
              b.item_code, b.ucol_ptr, b.ucol, b.S, b.Sdiag, learned ? b.pcMinvL : b.Minv, b.bS, b.x,
              b.zring, b.partA, b.partB, b.dinfo, b.gsync, &b.dev->error};
-  if (streamed(p)) {
+  const bool pipe = p->opt.cg_variant == BA_CG_PIPELINED;
+  int pcg_grid = P.pcg_grid;
+  if (streamed(p) && pipe) {
+    pa.wg_row = b.srow;
     pa.sitem_ptr = b.sitem_ptr;
     pa.sitem_col = b.sitem_col;
     pa.SI = b.SI;
+    pa.vcol_ptr = b.vcol_ptr;
+    pa.vcol = b.vcol;
+    pa.vbase = b.vbase;
+    pa.in_ptr = b.in_ptr;
+    pa.in_off = b.in_off;
+    pa.src_ptr = b.src_ptr;
+    pa.src = b.src;
+    pa.rstride = P.rstride;
+    pa.rring = b.rring;
+    pa.rflag = b.rflag;
+    pcg_grid = P.sgrid;
   }
-  const bool pipe = p->opt.cg_variant == BA_CG_PIPELINED;
-  PHASE(7, launch_pcg<T>(pa, P.pcg_grid, P.pcg_resident, pipe, s));
+  PHASE(7, launch_pcg<T>(pa, pcg_grid, P.pcg_resident, pipe, s));
   if (learned && p->cg_rtol > 0.0) {
     // the unpreconditioned residual judges the learned blocks: when the PCG
     // missed its tolerance the step is solved again with block-Jacobi
@@ -325,7 +348,7 @@ ba_status lm_step_impl(ba_problem* p, ba_step_info* out) {
     if (!(p->hinfo->cg_rel_resid <= p->cg_rtol)) {
       pa.Minv = b.Minv;
       HIPCHK(reset_sync(p));
-      PHASE(7, launch_pcg<T>(pa, P.pcg_grid, P.pcg_resident, pipe, s));
+      PHASE(7, launch_pcg<T>(pa, pcg_grid, P.pcg_resident, pipe, s));
       precond_used = 2;
     }
   }
@@ -533,9 +556,17 @@ ba_status ba_problem_bind(ba_problem* p, void* ws, size_t bytes, void* stream) {
   HIPCHK(upload(b.item_code, P.item_code, s));
   HIPCHK(upload(b.ucol_ptr, P.ucol_ptr, s));
   HIPCHK(upload(b.ucol, P.ucol, s));
+  HIPCHK(upload(b.srow, P.srow, s));
   HIPCHK(upload(b.sitem_ptr, P.sitem_ptr, s));
   HIPCHK(upload(b.sitem_col, P.sitem_col, s));
   HIPCHK(upload(b.blk_pos, P.blk_pos, s));
+  HIPCHK(upload(b.vcol_ptr, P.vcol_ptr, s));
+  HIPCHK(upload(b.vcol, P.vcol, s));
+  HIPCHK(upload(b.vbase, P.vbase, s));
+  HIPCHK(upload(b.in_ptr, P.in_ptr, s));
+  HIPCHK(upload(b.in_off, P.in_off, s));
+  HIPCHK(upload(b.src_ptr, P.src_ptr, s));
+  HIPCHK(upload(b.src, P.src, s));
   HIPCHK(upload(b.o_orig, P.o_orig, s));
   if (p->opt.precond == BA_PRECOND_LEARNED) {
     HIPCHK(upload(b.nbr_ptr, P.nbr_ptr, s));
@@ -554,11 +585,11 @@ ba_status ba_problem_bind(ba_problem* p, void* ws, size_t bytes, void* stream) {
   const int maxg = p->opt.precision == BA_MIXED ? ba::pcg_max_grid<float>(P.pcg_resident, pipe)
                                                 : ba::pcg_max_grid<double>(P.pcg_resident, pipe);
   if (maxg <= 0) return fail(BA_EHIP, "cooperative occupancy query failed");
-  p->pcg_grid = P.pcg_grid;
+  p->pcg_grid = streamed(p) && pipe ? P.sgrid : P.pcg_grid;
   if (p->pcg_grid > maxg || p->pcg_grid > ba::MAX_BARRIER_GROUPS * ba::BARRIER_FANIN)
     return fail(BA_EUNSUPPORTED, "too many cameras for one co-resident PCG grid");
   p->adj_grid_ok = p->opt.enable_backward &&
-                   p->pcg_grid <= ba::pcg_max_grid<double>(P.pcg_resident, false);
+                   P.pcg_grid <= ba::pcg_max_grid<double>(P.pcg_resident, false);
   p->bound = true;
   return BA_OK;
 }

@@ -48,6 +48,8 @@ constexpr int MAX_TRACK = CHUNK;
 constexpr int FINAL_STAGE_MAX = 256;  // workgroups of the first acceptance-reduction stage
 constexpr int SI_STRIDE = 84;         // values per block of the streamed PCG copy of S (81 + zeros:
                                       // 16-byte aligned blocks in FP32)
+constexpr int STREAM_RMAX = 96;       // block rows owned by one streamed-PCG workgroup
+constexpr int STREAM_COLS = 448;      // distinct upper block columns of one streamed-PCG workgroup
 
 // Host-side symbolic analysis of the observation pattern (computed once per
 // problem; the paper caches its sparse-product table the same way, Sec. IV-B-1).
@@ -83,12 +85,21 @@ struct Plan {
   // code (local column | flags), and the distinct block columns it reads.
   // pcg_resident: every lane group has at most PCG_IPG items.
   std::vector<int32_t> pcg_row, item_ptr, item_e, item_code, ucol_ptr, ucol;
-  // streamed plans (not pcg_resident): the off-diagonal items again, in the
-  // same order without the diagonal ones, numbered globally; each has its
-  // own copy of its block (SI, oriented for its row); sitem_col is the
-  // item's local column; blk_pos[2e], blk_pos[2e + 1] are the streamed items
-  // of upper block e as stored and transposed (-1 for diagonal blocks)
-  std::vector<int32_t> sitem_ptr, sitem_col, blk_pos;
+  // streamed plans (not pcg_resident) have a decomposition of their own,
+  // balanced by upper blocks: workgroup g owns rows [srow[g], srow[g+1]);
+  // its upper off-diagonal blocks, in row order, are the streamed items
+  // sitem_ptr[g] .. sitem_ptr[g+1] (numbered globally, each with an FP32
+  // copy SI), item i in block column vcol[vcol_ptr[g] + sitem_col[i]];
+  // blk_pos[e] is the item of upper block e (-1 for diagonal blocks).  The
+  // column sums for other workgroups' rows go to exchange slot
+  // vbase[g] + 9 j (doubles; each workgroup's slots start on a 128-byte
+  // line) of a ring slot of rstride doubles; row b adds the slots
+  // in_off[in_ptr[b] .. in_ptr[b+1]) (ascending sending workgroup), and
+  // workgroup g waits for the workgroups src[src_ptr[g] .. src_ptr[g+1]).
+  std::vector<int32_t> srow, sitem_ptr, sitem_col, blk_pos, vcol_ptr, vcol, vbase;
+  std::vector<int32_t> in_ptr, in_off, src_ptr, src;
+  int64_t rstride = 0;
+  int32_t sgrid = 0, max_vcol = 0;
   // camera co-visibility graph (both directions of every off-diagonal block):
   // neighbours of camera i are nbr[nbr_ptr[i] .. nbr_ptr[i+1]), through block
   // nbr_blk; nbr_rev is the slot of the same block in the neighbour's list
@@ -136,7 +147,8 @@ struct Buffers {
   int32_t *S_ptr, *S_col, *T_ptr, *T_blk, *T_src;
   int32_t *pair_x, *pair_y, *slot_blk, *slot_pb, *slot_pe, *slot_lead, *blk_row, *stab, *swptr;
   int32_t *pcg_row, *item_ptr, *item_e, *item_code, *ucol_ptr, *ucol;
-  int32_t *sitem_ptr, *sitem_col, *blk_pos;
+  int32_t *srow, *sitem_ptr, *sitem_col, *blk_pos, *vcol_ptr, *vcol, *vbase;
+  int32_t *in_ptr, *in_off, *src_ptr, *src;
   void* SI;  // streamed plans: [n_sitems][SI_STRIDE] (precision T)
   int64_t* o_orig;
   uint8_t* fixed;
@@ -161,6 +173,7 @@ struct Buffers {
   // partial sums
   double *part_cost, *part_cost_new, *part_pred, *part_gmax, *part_linc, *part_stage;
   double *zring, *partA, *partB;  // PCG exchange rings, one slot per iteration
+  double *rring, *rflag;          // streamed plans: column-sum exchange slots and flags
   DevScalars* dev;
   ba_step_info* dinfo;
   GridSync* gsync;

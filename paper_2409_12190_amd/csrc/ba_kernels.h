@@ -82,11 +82,18 @@ struct PcgArgs {
   ba_step_info* info;
   GridSync* gs;
   int* error;
-  // streamed plans (mixed precision): per-workgroup streamed items, their
-  // local columns and blocks
+  // streamed plans (mixed precision; wg_row is then the streamed
+  // decomposition): per-workgroup upper blocks, their local columns and FP32
+  // copies; the columns, exchange slots, incoming slots per row and sending
+  // workgroups; exchange ring (maxiter + 2 slots of rstride doubles) and
+  // flags (maxiter + 2 per workgroup)
   const int32_t* sitem_ptr = nullptr;
   const int32_t* sitem_col = nullptr;
   const void* SI = nullptr;
+  const int32_t *vcol_ptr = nullptr, *vcol = nullptr, *vbase = nullptr;
+  const int32_t *in_ptr = nullptr, *in_off = nullptr, *src_ptr = nullptr, *src = nullptr;
+  int64_t rstride = 0;
+  double *rring = nullptr, *rflag = nullptr;
 };
 
 struct BackArgs {

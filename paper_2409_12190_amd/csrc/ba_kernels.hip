@@ -482,7 +482,7 @@ __global__ __launch_bounds__(SCHUR_THREADS) void k_schur_pairs(SchurArgs a) {
   // per slot, for the reduction: number of chunks when the slot leads its
   // block (else 0) and the destination: block e of S, or -1 - row for the
   // diagonal block of camera row (Sdiag)
-  __shared__ int slot_n[SCHUR_SLOTS], slot_dst[SCHUR_SLOTS], slot_pn[SCHUR_SLOTS], slot_pt[SCHUR_SLOTS];
+  __shared__ int slot_n[SCHUR_SLOTS], slot_dst[SCHUR_SLOTS], slot_pn[SCHUR_SLOTS];
   bool diag_slot = false;
   if (computes) {
     const int e = a.slot_blk[sbase + slot];
@@ -496,10 +496,7 @@ __global__ __launch_bounds__(SCHUR_THREADS) void k_schur_pairs(SchurArgs a) {
       const int n = a.slot_lead[sbase + slot];
       slot_n[slot] = n;
       slot_dst[slot] = diag_slot ? -1 - row : e;
-      if (a.SI && n > 0 && !diag_slot) {
-        slot_pn[slot] = a.blk_pos[2 * (size_t)e];
-        slot_pt[slot] = a.blk_pos[2 * (size_t)e + 1];
-      }
+      if (a.SI && n > 0 && !diag_slot) slot_pn[slot] = a.blk_pos[e];
     }
   }
   const int t0 = a.swptr[(size_t)lw * SCHUR_WAVES + wave];
@@ -621,14 +618,9 @@ __global__ __launch_bounds__(SCHUR_THREADS) void k_schur_pairs(SchurArgs a) {
       reinterpret_cast<T*>(a.S)[81 * (size_t)dst + qq] = (T)v;
       if (a.SI) {
         T* si = reinterpret_cast<T*>(a.SI);
-        const size_t pn = (size_t)slot_pn[sl] * SI_STRIDE, pt = (size_t)slot_pt[sl] * SI_STRIDE;
-        const int r = qq / 9, c = qq - 9 * r;
+        const size_t pn = (size_t)slot_pn[sl] * SI_STRIDE;
         si[pn + qq] = (T)v;
-        si[pt + 9 * c + r] = (T)v;
-        if (qq < SI_STRIDE - 81) {
-          si[pn + 81 + qq] = (T)0;
-          si[pt + 81 + qq] = (T)0;
-        }
+        if (qq < SI_STRIDE - 81) si[pn + 81 + qq] = (T)0;
       }
     }
   }

@@ -256,13 +256,18 @@ __device__ __forceinline__ void pcg_spmv(const PcgArgs& a, int ib, int i0, int i
   __syncthreads();
 }
 
+// fetch block columns cols[0 .. n) from ring slot zk into LDS
+__device__ __forceinline__ void fetch_cols(const int32_t* cols, const double* zk, int n, double* zl) {
+  for (int u = threadIdx.x; u < n * 9; u += blockDim.x) {
+    const int j = u / 9;
+    zl[u] = zk[(size_t)cols[j] * ZSTRIDE + (u - 9 * j)];
+  }
+}
+
 // fetch the block columns this workgroup reads from ring slot zk into LDS
 __device__ __forceinline__ void pcg_fetch_z(const PcgArgs& a, const double* zk, int ub, int nuc,
                                             double* zl) {
-  for (int u = threadIdx.x; u < nuc * 9; u += blockDim.x) {
-    const int j = u / 9;
-    zl[u] = zk[(size_t)a.ucol[ub + j] * ZSTRIDE + (u - 9 * j)];
-  }
+  fetch_cols(a.ucol + ub, zk, nuc, zl);
 }
 
 template <typename T, bool RES>
@@ -607,24 +612,37 @@ __global__ __launch_bounds__(PCG_THREADS) void k_pcg_pipelined(PcgArgs a) {
 
 // ---------------------------------------------------------------------------
 // Pipelined PCG with streamed blocks (mixed precision; plans whose block rows
-// do not fit the lanes' registers, e.g. the 10,000-camera scene).  Each
-// off-diagonal (row, block) item has its own FP32 copy of its block, oriented
-// for its row and padded to SI_STRIDE values (written by the Schur kernel),
-// the items of a workgroup contiguous in row order.  The items are split into
-// STREAM_GROUPS contiguous ranges, STREAM_WAVE_GROUPS nine-lane groups per
-// wavefront.  At each step a wavefront stages the current block of each of
-// its groups in LDS with 16-byte loads, 8 lanes per 128 bytes (the next
-// step's blocks already in flight), and lane `comp` of a group multiplies
-// row `comp` of its block with the block column of the multiplied vector;
-// running sums per row go to the same (row + group) segments as in the
-// resident kernels.  The FP64 diagonal blocks are applied by the thread that
-// owns each vector element, from its registers.  Thread k owns element k of
-// the workgroup's rows and keeps every recurrence vector in registers; w, m
-// and the product n also pass through LDS for the 9x9 block products.
+// do not fit the lanes' registers, e.g. the 10,000-camera scene).  Each upper
+// off-diagonal block S_ab (a < b) is read once per product, by the workgroup
+// that owns row a, from an FP32 copy padded to SI_STRIDE values (written by
+// the Schur kernel; a workgroup's blocks contiguous in row order).  These
+// plans have their own row decomposition, balanced by upper blocks.
+//
+// The blocks are split into STREAM_GROUPS contiguous ranges,
+// STREAM_WAVE_GROUPS nine-lane groups per wavefront.  At each step a
+// wavefront stages the current block of each of its groups in LDS with
+// 16-byte loads, 8 lanes per 128 bytes (the next two steps' blocks in
+// flight), and lane `comp` of a group forms from the one staged block
+//   (S_ab v_b)[comp]    (row comp): running sum of row a, per (row + group)
+//                       segment as in the resident kernels;
+//   (S_ab^T v_a)[comp]  (column comp): added to the workgroup's LDS sum for
+//                       block column b (one per distinct column).
+// The column sums of the workgroup's own rows join its row sums; the others
+// go to the owner of b through a write-once exchange slot per (workgroup,
+// column) and product, after which the workgroup raises its flag of that
+// product.  An owner waits for the flags of the workgroups that send to it
+// and adds their slots in a fixed order.  The LDS column sums take their
+// terms in arrival order, so the last bits of a product may differ from run
+// to run.
+//
+// The FP64 diagonal blocks are applied by the thread that owns each vector
+// element.  Thread k owns element k of the workgroup's rows and keeps every
+// recurrence vector and its row of the block-Jacobi factor in registers; w, m
+// and the product n also pass through LDS.
 // ---------------------------------------------------------------------------
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
 
-constexpr int STREAM_WAVE_GROUPS = 7;
+constexpr int STREAM_WAVE_GROUPS = 6;
 constexpr int STREAM_GROUPS = (PCG_THREADS / 64) * STREAM_WAVE_GROUPS;
 constexpr int STREAM_PIECES = SI_STRIDE * 4 / 16;  // 16-byte pieces per FP32 block
 constexpr int STREAM_LOADS = (STREAM_WAVE_GROUPS * STREAM_PIECES + 63) / 64;
@@ -633,23 +651,48 @@ constexpr int STREAM_LOADS = (STREAM_WAVE_GROUPS * STREAM_PIECES + 63) / 64;
 // lockstep loop lets the compiler restructure it into a divergent nest)
 constexpr int STREAM_WAVE_BYTES = STREAM_LOADS * 64 * 16;
 
-// nl[k] = sum over the streamed items of row k / 9 of (block row k % 9) .
-// (block column of the vector in zl), k < nr * 9; every thread of the
-// workgroup calls it (barriers inside).
-__device__ __forceinline__ void stream_spmv(const PcgArgs& a, int sib, int nitems, int L, int nr,
-                                            const int* rptr, const double* zl, double* seg,
-                                            unsigned char* st, double* nl) {
+// the exchange flag of workgroup `w`'s product `k`: wait until it is raised
+__device__ __forceinline__ bool poll_flag(const double* f, int* error) {
+  const unsigned long long* r = reinterpret_cast<const unsigned long long*>(f);
+  long spins = 0;
+  while (__hip_atomic_load(r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == PCG_PENDING) {
+    if (++spins > BARRIER_SPIN_LIMIT ||
+        (__hip_atomic_load(error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & ERR_BARRIER)) {
+      atomicOr(error, (int)ERR_BARRIER);
+      return false;
+    }
+    __builtin_amdgcn_s_sleep(1);
+  }
+  return true;
+}
+
+// Per-workgroup constants of the streamed product.
+struct StreamCtx {
+  int B, G, r0, nr, sib, nitems, L, vb, nvc;
+  size_t vbase;
+};
+
+// nl[k] = (S v)[row k / 9 of the workgroup, component k % 9] without the
+// diagonal block, k < nr * 9, for the block columns of v in zl (the columns
+// of the workgroup's upper blocks) and its own rows in ml; product `slot`
+// of the solve (exchange slot and flag).  Every thread of the workgroup
+// calls it (barriers inside); tl must be zero on entry and is zero on exit.
+__device__ __forceinline__ bool stream_spmv(const PcgArgs& a, const StreamCtx& c, int slot,
+                                            const int* rptr, const int* lcol, const double* zl,
+                                            const double* ml, double* tl, double* seg,
+                                            unsigned char* st, double* nl, int* poll_failed) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int gl = lane / 9, comp = lane - 9 * gl;
   const bool computes = gl < STREAM_WAVE_GROUPS;
   const int g = wave * STREAM_WAVE_GROUPS + gl;
+  const int nitems = c.nitems, L = c.L;
   const int i0 = computes ? min(nitems, g * L) : nitems;
   const int i1 = computes ? min(nitems, i0 + L) : nitems;
   unsigned char* wst = st + wave * STREAM_WAVE_BYTES;
   if (nitems > 0) {
     const unsigned char* __restrict__ SIb =
-        reinterpret_cast<const unsigned char*>(a.SI) + (size_t)sib * SI_STRIDE * 4;
-    const int* __restrict__ scol = a.sitem_col + sib;
+        reinterpret_cast<const unsigned char*>(a.SI) + (size_t)c.sib * SI_STRIDE * 4;
+    const int* __restrict__ scol = a.sitem_col + c.sib;
     // lane `lane` moves piece (64 j + lane) % STREAM_PIECES of the block of
     // group (64 j + lane) / STREAM_PIECES of its wavefront; loads are issued
     // without branches (items clamped to the workgroup's last one)
@@ -678,10 +721,17 @@ __device__ __forceinline__ void stream_spmv(const PcgArgs& a, int sib, int nitem
           acc = 0.0;
           cur = row;
         }
-        const float* blk = reinterpret_cast<const float*>(wst + gl * SI_STRIDE * 4) + comp * 9;
+        const float* blk = reinterpret_cast<const float*>(wst + gl * SI_STRIDE * 4);
         const double* zc = zl + col * 9;
+        const double* va = ml + row * 9;
 #pragma unroll
-        for (int m = 0; m < 9; ++m) acc += (double)blk[m] * zc[m];
+        for (int m = 0; m < 9; ++m) acc += (double)blk[comp * 9 + m] * zc[m];
+        // (the two products one after the other: fewer live registers)
+        __builtin_amdgcn_sched_barrier(0);
+        double t = 0.0;
+#pragma unroll
+        for (int m = 0; m < 9; ++m) t += (double)blk[m * 9 + comp] * va[m];
+        atomicAdd(tl + col * 9 + comp, t);
       }
       __builtin_amdgcn_wave_barrier();
     };
@@ -710,15 +760,27 @@ __device__ __forceinline__ void stream_spmv(const PcgArgs& a, int sib, int nitem
     if (cur >= 0) seg[(cur + g) * 9 + comp] = acc;
   }
   __syncthreads();
+  // column sums of other workgroups' rows to their exchange slots
+  double* rk = a.rring + (size_t)slot * a.rstride + c.vbase;
+  for (int u = threadIdx.x; u < c.nvc * 9; u += blockDim.x) {
+    const int j = u / 9, b = a.vcol[c.vb + j];
+    if (b < c.r0 || b >= c.r0 + c.nr) publish(rk + u, tl[u]);
+  }
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (threadIdx.x == 0) publish(a.rflag + (size_t)slot * c.G + c.B, 1.0);
   // outputs: the groups rptr[row] / L .. (rptr[row + 1] - 1) / L touched row
-  // `row` (none when the row has no off-diagonal block); 8 lanes per output,
-  // strided then a 3-step butterfly: fixed order
-  const int nout = nr * 9;
+  // `row` (none when the row has no upper block); 8 lanes per output,
+  // strided then a 3-step butterfly: fixed order; then the row's own column
+  // sum, when one of the workgroup's blocks lies in its column
+  const int nout = c.nr * 9;
   for (int base = 0; base < nout * 8; base += blockDim.x) {
     const int t = base + threadIdx.x, o = t >> 3, sub = t & 7;
     double sum = 0.0;
+    int row = 0, cp = 0;
     if (o < nout) {
-      const int row = o / 9, cp = o - 9 * row;
+      row = o / 9;
+      cp = o - 9 * row;
       if (rptr[row + 1] > rptr[row]) {
         const int g0 = rptr[row] / L, g1 = (rptr[row + 1] - 1) / L;
         for (int gg = g0 + sub; gg <= g1; gg += 8) sum += seg[(row + gg) * 9 + cp];
@@ -727,53 +789,90 @@ __device__ __forceinline__ void stream_spmv(const PcgArgs& a, int sib, int nitem
     sum += __shfl_xor(sum, 1, 64);
     sum += __shfl_xor(sum, 2, 64);
     sum += __shfl_xor(sum, 4, 64);
-    if (o < nout && sub == 0) nl[o] = sum;
+    if (o < nout && sub == 0) nl[o] = lcol[row] >= 0 ? sum + tl[lcol[row] * 9 + cp] : sum;
   }
+  // wait for the workgroups that send to this one
+  const int s0 = a.src_ptr[c.B], ns = a.src_ptr[c.B + 1] - s0;
+  for (int t = threadIdx.x; t < ns; t += blockDim.x)
+    if (!poll_flag(a.rflag + (size_t)slot * c.G + a.src[s0 + t], a.error)) *poll_failed = 1;
   __syncthreads();
+  // their slots, in the fixed order of each row's list; tl cleared
+  if (!*poll_failed && threadIdx.x < nout) {
+    const int row = threadIdx.x / 9, cp = threadIdx.x - 9 * row;
+    const int gr = c.r0 + row;
+    const double* rs = a.rring + (size_t)slot * a.rstride + cp;
+    const int k0 = a.in_ptr[gr], k1 = a.in_ptr[gr + 1];
+    double sum = 0.0;
+#pragma unroll 4
+    for (int k = k0; k < k1; ++k) sum += rs[a.in_off[k]];
+    nl[threadIdx.x] += sum;
+  }
+  for (int u = threadIdx.x; u < c.nvc * 9; u += blockDim.x) tl[u] = 0.0;
+  __syncthreads();
+  return *poll_failed == 0;
 }
 
 __global__ __launch_bounds__(PCG_THREADS) void k_pcg_stream(PcgArgs a) {
-  __shared__ double Ml[PCG_RMAX * 81];
-  __shared__ double zl[PCG_ZCOLS * 9];
-  __shared__ double wl[PCG_RMAX * 9], ml[PCG_RMAX * 9], nl[PCG_RMAX * 9];
-  __shared__ double seg[(PCG_RMAX + STREAM_GROUPS) * 9];
+  __shared__ double zl[STREAM_COLS * 9], tl[STREAM_COLS * 9];
+  __shared__ double wl[STREAM_RMAX * 9], ml[STREAM_RMAX * 9], nl[STREAM_RMAX * 9];
+  // x, p and s of the owned elements (owner thread only: fewer live
+  // registers across the product)
+  __shared__ double xl[STREAM_RMAX * 9], pl[STREAM_RMAX * 9], sl[STREAM_RMAX * 9];
+  __shared__ double seg[(STREAM_RMAX + STREAM_GROUPS) * 9];
   __shared__ __align__(16) unsigned char st[(PCG_THREADS / 64) * STREAM_WAVE_BYTES];
-  __shared__ int rptr[PCG_RMAX + 1];
+  __shared__ int rptr[STREAM_RMAX + 1], lcol[STREAM_RMAX];
   __shared__ double red[PCG_THREADS / 64];
   __shared__ double red3[PCG_THREADS / 64][3];
   __shared__ double red3s[3 * (PCG_THREADS / 64)];
   __shared__ int poll_failed;
   const int G = gridDim.x, B = xcd_block(blockIdx.x, gridDim.x), tid = threadIdx.x, nt = blockDim.x;
-  const int r0 = a.wg_row[B], nr = a.wg_row[B + 1] - r0;
-  const int n9 = nr * 9;
-  const int sib = a.sitem_ptr[B], nitems = a.sitem_ptr[B + 1] - sib;
-  const int ub = a.ucol_ptr[B], nuc = a.ucol_ptr[B + 1] - ub;
+  StreamCtx c;
+  c.B = B;
+  c.G = G;
+  c.r0 = a.wg_row[B];
+  c.nr = a.wg_row[B + 1] - c.r0;
+  c.sib = a.sitem_ptr[B];
+  c.nitems = a.sitem_ptr[B + 1] - c.sib;
+  c.L = max(1, (c.nitems + STREAM_GROUPS - 1) / STREAM_GROUPS);
+  c.vb = a.vcol_ptr[B];
+  c.nvc = a.vcol_ptr[B + 1] - c.vb;
+  c.vbase = (size_t)a.vbase[B];
+  const int r0 = c.r0, nr = c.nr, n9 = nr * 9;
   const size_t zstride = (size_t)a.nc * ZSTRIDE, pstride = (size_t)G * PART_STRIDE;
-  const int L = max(1, (nitems + STREAM_GROUPS - 1) / STREAM_GROUPS);
   if (tid == 0) {
     rptr[0] = 0;
-    for (int i = 0; i < nr; ++i)
-      rptr[i + 1] = rptr[i] + (a.S_ptr[r0 + i + 1] - a.S_ptr[r0 + i] - 1) +
-                    (a.T_ptr[r0 + i + 1] - a.T_ptr[r0 + i]);
+    for (int i = 0; i < nr; ++i) rptr[i + 1] = rptr[i] + (a.S_ptr[r0 + i + 1] - a.S_ptr[r0 + i] - 1);
+    poll_failed = 0;
+  }
+  for (int i = tid; i < nr; i += nt) lcol[i] = -1;
+  for (int u = tid; u < c.nvc * 9; u += nt) tl[u] = 0.0;
+  __syncthreads();
+  for (int j = tid; j < c.nvc; j += nt) {
+    const int b = a.vcol[c.vb + j];
+    if (b >= r0 && b < r0 + nr) lcol[b - r0] = j;
   }
   // thread tid owns element tid of the workgroup's rows
   const bool own = tid < n9;
   const int row = own ? tid / 9 : 0, cp = own ? tid - 9 * row : 0;
-  double x = 0.0, r = 0.0, u = 0.0, w = 0.0, m = 0.0, z = 0.0, q = 0.0, s = 0.0, p = 0.0;
-  // row cp of the FP64 diagonal block of row `row` (read when applied)
+  double r = 0.0, u = 0.0, w = 0.0, m = 0.0, z = 0.0, q = 0.0;
+  // row cp of the FP64 diagonal block of row `row` and of its block-Jacobi
+  // factor (both read when applied)
   const double* drow = a.Sdiag + 81 * (size_t)(r0 + row) + cp * 9;
+  const double* Mr = a.Minv + 81 * (size_t)(r0 + row) + cp * 9;
   if (own) {
     r = a.b[9 * (size_t)r0 + tid];
     nl[tid] = r;
+    xl[tid] = 0.0;
+    pl[tid] = 0.0;
+    sl[tid] = 0.0;
   }
-  for (int i = tid; i < nr * 81; i += nt) Ml[i] = a.Minv[81 * (size_t)r0 + i];
   __syncthreads();
   // u0 = M b, published in slot 0; w0 = S u0
   double s_bb = 0.0;
   if (own) {
     double v = 0.0;
 #pragma unroll
-    for (int k = 0; k < 9; ++k) v += Ml[row * 81 + cp * 9 + k] * nl[row * 9 + k];
+    for (int k = 0; k < 9; ++k) v += Mr[k] * nl[row * 9 + k];
     u = v;
     ml[tid] = u;
     publish(a.zring + (size_t)(r0 + row) * ZSTRIDE + cp, u);
@@ -788,12 +887,13 @@ __global__ __launch_bounds__(PCG_THREADS) void k_pcg_stream(PcgArgs a) {
   }
   for (int k = tid; k < 3 * (a.maxiter + 1); k += nt)
     clear_record(a.partA + (size_t)(k / 3) * pstride + (size_t)B * PART_STRIDE + (k - 3 * (k / 3)));
+  for (int k = tid; k < a.maxiter + 2; k += nt) clear_record(a.rflag + (size_t)k * G + B);
   bool ok = grid_barrier(a.gs, a.error);
-  pcg_fetch_z(a, a.zring, ub, nuc, zl);
+  fetch_cols(a.vcol + c.vb, a.zring, c.nvc, zl);
   double t0 = 0.0;
   for (int i = tid; i < G; i += nt) t0 += a.partB[(size_t)i * PART_STRIDE];
   const double bnorm = sqrt(block_sum(t0, red));  // (its barriers complete zl)
-  stream_spmv(a, sib, nitems, L, nr, rptr, zl, seg, st, nl);
+  if (ok) ok = stream_spmv(a, c, 0, rptr, lcol, zl, ml, tl, seg, st, nl, &poll_failed);
   if (own) {
     w = nl[tid] + nd;
     wl[tid] = w;
@@ -808,7 +908,7 @@ __global__ __launch_bounds__(PCG_THREADS) void k_pcg_stream(PcgArgs a) {
     if (own) {
       double v = 0.0;
 #pragma unroll
-      for (int k = 0; k < 9; ++k) v += Ml[row * 81 + cp * 9 + k] * wl[row * 9 + k];
+      for (int k = 0; k < 9; ++k) v += Mr[k] * wl[row * 9 + k];
       m = v;
       ml[tid] = m;
       publish(zk + (size_t)(r0 + row) * ZSTRIDE + cp, m);
@@ -826,7 +926,6 @@ __global__ __launch_bounds__(PCG_THREADS) void k_pcg_stream(PcgArgs a) {
     }
     // the m columns must have reached memory before the partials are seen
     __builtin_amdgcn_s_waitcnt(0);
-    if (tid == 0) poll_failed = 0;
     __syncthreads();
     double* pa = a.partA + (size_t)i * pstride;
     if (tid < 3) {
@@ -856,7 +955,7 @@ __global__ __launch_bounds__(PCG_THREADS) void k_pcg_stream(PcgArgs a) {
       break;
     }
     // every workgroup's m columns are in memory now
-    pcg_fetch_z(a, zk, ub, nuc, zl);
+    fetch_cols(a.vcol + c.vb, zk, c.nvc, zl);
     double gamma = 0.0, delta = 0.0, rr = 0.0;
 #pragma unroll 2
     for (int w2 = 0; w2 < PCG_THREADS / 64; ++w2) {
@@ -875,14 +974,19 @@ __global__ __launch_bounds__(PCG_THREADS) void k_pcg_stream(PcgArgs a) {
     }
     const double alpha = gamma / den;
     __syncthreads();  // zl complete
-    stream_spmv(a, sib, nitems, L, nr, rptr, zl, seg, st, nl);
+    if (!stream_spmv(a, c, i + 1, rptr, lcol, zl, ml, tl, seg, st, nl, &poll_failed)) {
+      ok = false;
+      break;
+    }
     if (own) {
       const double n = nl[tid] + nd;
       z = n + beta * z;
       q = m + beta * q;
-      s = w + beta * s;
-      p = u + beta * p;
-      x += alpha * p;
+      const double s = w + beta * sl[tid];
+      sl[tid] = s;
+      const double p = u + beta * pl[tid];
+      pl[tid] = p;
+      xl[tid] += alpha * p;
       r -= alpha * s;
       u -= alpha * q;
       w -= alpha * z;
@@ -892,7 +996,7 @@ __global__ __launch_bounds__(PCG_THREADS) void k_pcg_stream(PcgArgs a) {
     gamma_old = gamma;
     alpha_old = alpha;
   }
-  if (own) a.x[9 * (size_t)r0 + tid] = x;
+  if (own) a.x[9 * (size_t)r0 + tid] = xl[tid];
   if (B == 0 && tid == 0) {
     a.info->cg_iters = iters;
     a.info->cg_breakdown = breakdown;
@@ -929,8 +1033,10 @@ template int pcg_max_grid<double>(bool, bool);
 
 template <typename T>
 hipError_t launch_pcg(const PcgArgs& a, int grid, bool resident, bool pipelined, hipStream_t s) {
-  if (sizeof(T) == 4 && pipelined && !resident && (!a.SI || !a.sitem_ptr || !a.sitem_col))
-    return hipErrorInvalidValue;  // the streamed kernel needs the per-item blocks
+  if (sizeof(T) == 4 && pipelined && !resident &&
+      (!a.SI || !a.sitem_ptr || !a.sitem_col || !a.vcol_ptr || !a.vcol || !a.vbase || !a.in_ptr ||
+       !a.in_off || !a.src_ptr || !a.src || !a.rring || !a.rflag))
+    return hipErrorInvalidValue;  // the streamed kernel needs its decomposition and exchange
   void* args[] = {const_cast<PcgArgs*>(&a)};
   return hipLaunchCooperativeKernel(pcg_kernel<T>(resident, pipelined), dim3(grid), dim3(PCG_THREADS),
                                     args, 0, s);

@@ -336,9 +336,6 @@ std::string build_plan(int32_t nc, int32_t np, int64_t no, const int32_t* cidx, 
     }
     p.item_ptr.assign(p.pcg_grid + 1, 0);
     p.ucol_ptr.assign(p.pcg_grid + 1, 0);
-    p.sitem_ptr.assign(p.pcg_resident ? 0 : p.pcg_grid + 1, 0);
-    p.sitem_col.clear();
-    p.blk_pos.assign(p.pcg_resident ? 0 : 2 * (size_t)p.nnzb, -1);
     p.item_e.clear();
     p.item_code.clear();
     p.ucol.clear();
@@ -369,19 +366,6 @@ std::string build_plan(int32_t nc, int32_t np, int64_t no, const int32_t* cidx, 
         }
       }
       p.item_ptr[g + 1] = (int32_t)p.item_e.size();
-      if (!p.pcg_resident) {
-        for (int32_t a = r0; a < r1; ++a) {
-          for (int32_t e = p.S_ptr[a] + 1; e < p.S_ptr[a + 1]; ++e) {
-            p.blk_pos[2 * (size_t)e] = (int32_t)p.sitem_col.size();
-            p.sitem_col.push_back(local(p.S_col[e]));
-          }
-          for (int32_t t = p.T_ptr[a]; t < p.T_ptr[a + 1]; ++t) {
-            p.blk_pos[2 * (size_t)p.T_blk[t] + 1] = (int32_t)p.sitem_col.size();
-            p.sitem_col.push_back(local(p.T_src[t]));
-          }
-        }
-        p.sitem_ptr[g + 1] = (int32_t)p.sitem_col.size();
-      }
       p.ucol.insert(p.ucol.end(), uc.begin(), uc.end());
       p.ucol_ptr[g + 1] = (int32_t)p.ucol.size();
     }
@@ -390,6 +374,111 @@ std::string build_plan(int32_t nc, int32_t np, int64_t no, const int32_t* cidx, 
                     "a PCG workgroup would read %d block columns; at most %d are supported",
                     p.max_ucol, PCG_ZCOLS);
       return msg;
+    }
+  }
+
+  // Streamed plans: a decomposition of their own.  Each upper block is read
+  // once per product, by the owner of its row, so rows are weighted by their
+  // upper blocks (8 each) plus the column sums they receive (at most one per
+  // lower block); at most STREAM_RMAX rows per workgroup.
+  p.srow.clear();
+  p.sitem_ptr.clear();
+  p.sitem_col.clear();
+  p.blk_pos.clear();
+  p.vcol_ptr.clear();
+  p.vcol.clear();
+  p.vbase.clear();
+  p.in_ptr.clear();
+  p.in_off.clear();
+  p.src_ptr.clear();
+  p.src.clear();
+  p.rstride = 0;
+  p.sgrid = 0;
+  p.max_vcol = 0;
+  if (!p.pcg_resident) {
+    std::vector<int64_t> wgt(nc);
+    int64_t total = 0;
+    for (int32_t a = 0; a < nc; ++a) {
+      wgt[a] = 8 * (int64_t)(p.S_ptr[a + 1] - p.S_ptr[a]) + (p.T_ptr[a + 1] - p.T_ptr[a]);
+      total += wgt[a];
+    }
+    // the row cap can leave more ranges than workgroups: raise the target
+    for (int64_t target = (total + PCG_MAX_GRID - 1) / PCG_MAX_GRID;; target += target / 16 + 1) {
+      p.srow.assign(1, 0);
+      int64_t items = 0;
+      int32_t nrow = 0;
+      for (int32_t a = 0; a < nc; ++a) {
+        if (nrow > 0 && (nrow == STREAM_RMAX || items >= target)) {
+          p.srow.push_back(a);
+          items = 0;
+          nrow = 0;
+        }
+        items += wgt[a];
+        ++nrow;
+      }
+      p.srow.push_back(nc);
+      if ((int32_t)p.srow.size() - 1 <= PCG_MAX_GRID) break;
+    }
+    const int32_t G = p.sgrid = (int32_t)p.srow.size() - 1;
+    std::vector<int32_t> owner(nc);
+    for (int32_t g = 0; g < G; ++g)
+      for (int32_t a = p.srow[g]; a < p.srow[g + 1]; ++a) owner[a] = g;
+    p.sitem_ptr.assign(G + 1, 0);
+    p.vcol_ptr.assign(G + 1, 0);
+    p.vbase.assign(G, 0);
+    p.blk_pos.assign((size_t)p.nnzb, -1);
+    int64_t off = 0;
+    std::vector<int32_t> vc;
+    for (int32_t g = 0; g < G; ++g) {
+      const int32_t r0 = p.srow[g], r1 = p.srow[g + 1];
+      vc.clear();
+      for (int32_t a = r0; a < r1; ++a)
+        for (int32_t e = p.S_ptr[a] + 1; e < p.S_ptr[a + 1]; ++e) vc.push_back(p.S_col[e]);
+      std::sort(vc.begin(), vc.end());
+      vc.erase(std::unique(vc.begin(), vc.end()), vc.end());
+      p.max_vcol = std::max(p.max_vcol, (int32_t)vc.size());
+      for (int32_t a = r0; a < r1; ++a)
+        for (int32_t e = p.S_ptr[a] + 1; e < p.S_ptr[a + 1]; ++e) {
+          p.blk_pos[e] = (int32_t)p.sitem_col.size();
+          p.sitem_col.push_back(
+              (int32_t)(std::lower_bound(vc.begin(), vc.end(), p.S_col[e]) - vc.begin()));
+        }
+      p.sitem_ptr[g + 1] = (int32_t)p.sitem_col.size();
+      off = (off + 15) & ~(int64_t)15;
+      p.vbase[g] = (int32_t)std::min<int64_t>(off, INT32_MAX);
+      off += 9 * (int64_t)vc.size();
+      p.vcol.insert(p.vcol.end(), vc.begin(), vc.end());
+      p.vcol_ptr[g + 1] = (int32_t)p.vcol.size();
+    }
+    p.rstride = (off + 15) & ~(int64_t)15;
+    if (p.max_vcol > STREAM_COLS) {
+      std::snprintf(msg, sizeof msg,
+                    "a streamed PCG workgroup would touch %d block columns; at most %d are supported",
+                    p.max_vcol, STREAM_COLS);
+      return msg;
+    }
+    if (p.rstride > INT32_MAX) return "the streamed PCG exchange slots exceed 2^31 values";
+    // incoming slots of every row, ascending sending workgroup; the senders
+    // of every workgroup
+    p.in_ptr.assign(nc + 1, 0);
+    for (int32_t g = 0; g < G; ++g)
+      for (int32_t j = p.vcol_ptr[g]; j < p.vcol_ptr[g + 1]; ++j)
+        if (owner[p.vcol[j]] != g) p.in_ptr[p.vcol[j] + 1]++;
+    for (int32_t b = 0; b < nc; ++b) p.in_ptr[b + 1] += p.in_ptr[b];
+    p.in_off.resize(p.in_ptr[nc]);
+    std::vector<int32_t> fill(p.in_ptr.begin(), p.in_ptr.end() - 1);
+    std::vector<std::vector<int32_t>> senders(G);
+    for (int32_t g = 0; g < G; ++g)
+      for (int32_t j = p.vcol_ptr[g]; j < p.vcol_ptr[g + 1]; ++j) {
+        const int32_t b = p.vcol[j], o = owner[b];
+        if (o == g) continue;
+        p.in_off[fill[b]++] = p.vbase[g] + 9 * (j - p.vcol_ptr[g]);
+        if (senders[o].empty() || senders[o].back() != g) senders[o].push_back(g);
+      }
+    p.src_ptr.assign(G + 1, 0);
+    for (int32_t g = 0; g < G; ++g) {
+      p.src.insert(p.src.end(), senders[g].begin(), senders[g].end());
+      p.src_ptr[g + 1] = (int32_t)p.src.size();
     }
   }
   return std::string();
