@@ -50,6 +50,7 @@ constexpr int SI_STRIDE = 84;         // values per block of the streamed PCG co
                                       // 16-byte aligned blocks in FP32)
 constexpr int STREAM_RMAX = 96;       // block rows owned by one streamed-PCG workgroup
 constexpr int STREAM_COLS = 448;      // distinct upper block columns of one streamed-PCG workgroup
+constexpr int STREAM_IN_MAX = 2048;   // received column sums of a streamed-PCG workgroup listed in LDS
 
 // Host-side symbolic analysis of the observation pattern (computed once per
 // problem; the paper caches its sparse-product table the same way, Sec. IV-B-1).

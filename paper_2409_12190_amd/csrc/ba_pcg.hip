@@ -666,21 +666,34 @@ __device__ __forceinline__ bool poll_flag(const double* f, int* error) {
   return true;
 }
 
+// A workgroup-uniform FP64 value held in scalar registers.
+__device__ __forceinline__ double uniform(double v) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)b);
+  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(b >> 32));
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
 // Per-workgroup constants of the streamed product.
 struct StreamCtx {
-  int B, G, r0, nr, sib, nitems, L, vb, nvc;
+  int B, G, r0, nr, sib, nitems, L, vb, nvc, ib, src;  // src: this thread's sender (t < senders)
   size_t vbase;
 };
 
 // nl[k] = (S v)[row k / 9 of the workgroup, component k % 9] without the
 // diagonal block, k < nr * 9, for the block columns of v in zl (the columns
-// of the workgroup's upper blocks) and its own rows in ml; product `slot`
-// of the solve (exchange slot and flag).  Every thread of the workgroup
-// calls it (barriers inside); tl must be zero on entry and is zero on exit.
+// vcl of the workgroup's upper blocks) and its own rows in ml; product
+// `slot` of the solve (exchange slot and flag).  The received column sums of
+// row i are listed at ipl[i] .. ipl[i+1] (the first STREAM_IN_MAX in inl).
+// After the blocks, the owning thread's row of the block-Jacobi factor is
+// loaded into Mr (its latency hidden by the exchange).  Every thread of the workgroup calls it (barriers inside);
+// tl must be zero on entry and is zero on exit.
 __device__ __forceinline__ bool stream_spmv(const PcgArgs& a, const StreamCtx& c, int slot,
-                                            const int* rptr, const int* lcol, const double* zl,
+                                            const int* rptr, const int* lcol, const int* vcl,
+                                            const int* ipl, const int* inl, const double* zl,
                                             const double* ml, double* tl, double* seg,
-                                            unsigned char* st, double* nl, int* poll_failed) {
+                                            unsigned char* st, double* nl, int* poll_failed,
+                                            double (&Mr)[9]) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int gl = lane / 9, comp = lane - 9 * gl;
   const bool computes = gl < STREAM_WAVE_GROUPS;
@@ -760,10 +773,18 @@ __device__ __forceinline__ bool stream_spmv(const PcgArgs& a, const StreamCtx& c
     if (cur >= 0) seg[(cur + g) * 9 + comp] = acc;
   }
   __syncthreads();
+  const int nout = c.nr * 9;
+  {
+    // (assigned in every thread: the previous values are dead here)
+    const int o = min((int)threadIdx.x, nout - 1);
+    const size_t q = 81 * (size_t)(c.r0 + o / 9) + 9 * (o % 9);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) Mr[k] = a.Minv[q + k];
+  }
   // column sums of other workgroups' rows to their exchange slots
   double* rk = a.rring + (size_t)slot * a.rstride + c.vbase;
   for (int u = threadIdx.x; u < c.nvc * 9; u += blockDim.x) {
-    const int j = u / 9, b = a.vcol[c.vb + j];
+    const int j = u / 9, b = vcl[j];
     if (b < c.r0 || b >= c.r0 + c.nr) publish(rk + u, tl[u]);
   }
   __builtin_amdgcn_s_waitcnt(0);
@@ -773,7 +794,6 @@ __device__ __forceinline__ bool stream_spmv(const PcgArgs& a, const StreamCtx& c
   // `row` (none when the row has no upper block); 8 lanes per output,
   // strided then a 3-step butterfly: fixed order; then the row's own column
   // sum, when one of the workgroup's blocks lies in its column
-  const int nout = c.nr * 9;
   for (int base = 0; base < nout * 8; base += blockDim.x) {
     const int t = base + threadIdx.x, o = t >> 3, sub = t & 7;
     double sum = 0.0;
@@ -791,20 +811,17 @@ __device__ __forceinline__ bool stream_spmv(const PcgArgs& a, const StreamCtx& c
     sum += __shfl_xor(sum, 4, 64);
     if (o < nout && sub == 0) nl[o] = lcol[row] >= 0 ? sum + tl[lcol[row] * 9 + cp] : sum;
   }
-  // wait for the workgroups that send to this one
-  const int s0 = a.src_ptr[c.B], ns = a.src_ptr[c.B + 1] - s0;
-  for (int t = threadIdx.x; t < ns; t += blockDim.x)
-    if (!poll_flag(a.rflag + (size_t)slot * c.G + a.src[s0 + t], a.error)) *poll_failed = 1;
+  // wait for the workgroups that send to this one (thread t for sender t)
+  if (c.src >= 0 && !poll_flag(a.rflag + (size_t)slot * c.G + c.src, a.error)) *poll_failed = 1;
   __syncthreads();
   // their slots, in the fixed order of each row's list; tl cleared
   if (!*poll_failed && threadIdx.x < nout) {
     const int row = threadIdx.x / 9, cp = threadIdx.x - 9 * row;
-    const int gr = c.r0 + row;
     const double* rs = a.rring + (size_t)slot * a.rstride + cp;
-    const int k0 = a.in_ptr[gr], k1 = a.in_ptr[gr + 1];
+    const int k0 = ipl[row], k1 = ipl[row + 1];
     double sum = 0.0;
 #pragma unroll 4
-    for (int k = k0; k < k1; ++k) sum += rs[a.in_off[k]];
+    for (int k = k0; k < k1; ++k) sum += rs[k < STREAM_IN_MAX ? inl[k] : a.in_off[c.ib + k]];
     nl[threadIdx.x] += sum;
   }
   for (int u = threadIdx.x; u < c.nvc * 9; u += blockDim.x) tl[u] = 0.0;
@@ -814,13 +831,19 @@ __device__ __forceinline__ bool stream_spmv(const PcgArgs& a, const StreamCtx& c
 
 __global__ __launch_bounds__(PCG_THREADS) void k_pcg_stream(PcgArgs a) {
   __shared__ double zl[STREAM_COLS * 9], tl[STREAM_COLS * 9];
-  __shared__ double wl[STREAM_RMAX * 9], ml[STREAM_RMAX * 9], nl[STREAM_RMAX * 9];
+  // w and the product n of the owned elements live in zl's memory: w is read
+  // (m = M w) before the columns are fetched, n is written after the blocks
+  // have been multiplied and read before the next fetch
+  double* const wl = zl;
+  double* const nl = zl + STREAM_RMAX * 9;
+  __shared__ double ml[STREAM_RMAX * 9];
   // x, p and s of the owned elements (owner thread only: fewer live
   // registers across the product)
   __shared__ double xl[STREAM_RMAX * 9], pl[STREAM_RMAX * 9], sl[STREAM_RMAX * 9];
   __shared__ double seg[(STREAM_RMAX + STREAM_GROUPS) * 9];
   __shared__ __align__(16) unsigned char st[(PCG_THREADS / 64) * STREAM_WAVE_BYTES];
-  __shared__ int rptr[STREAM_RMAX + 1], lcol[STREAM_RMAX];
+  __shared__ int rptr[STREAM_RMAX + 1], lcol[STREAM_RMAX], ipl[STREAM_RMAX + 1];
+  __shared__ int vcl[STREAM_COLS], inl[STREAM_IN_MAX];
   __shared__ double red[PCG_THREADS / 64];
   __shared__ double red3[PCG_THREADS / 64][3];
   __shared__ double red3s[3 * (PCG_THREADS / 64)];
@@ -837,6 +860,11 @@ __global__ __launch_bounds__(PCG_THREADS) void k_pcg_stream(PcgArgs a) {
   c.vb = a.vcol_ptr[B];
   c.nvc = a.vcol_ptr[B + 1] - c.vb;
   c.vbase = (size_t)a.vbase[B];
+  c.ib = a.in_ptr[c.r0];
+  {
+    const int s0 = a.src_ptr[B], ns = a.src_ptr[B + 1] - s0;
+    c.src = tid < ns ? a.src[s0 + tid] : -1;
+  }
   const int r0 = c.r0, nr = c.nr, n9 = nr * 9;
   const size_t zstride = (size_t)a.nc * ZSTRIDE, pstride = (size_t)G * PART_STRIDE;
   if (tid == 0) {
@@ -845,20 +873,25 @@ __global__ __launch_bounds__(PCG_THREADS) void k_pcg_stream(PcgArgs a) {
     poll_failed = 0;
   }
   for (int i = tid; i < nr; i += nt) lcol[i] = -1;
+  for (int i = tid; i <= nr; i += nt) ipl[i] = a.in_ptr[r0 + i] - c.ib;
+  for (int k = tid; k < min(a.in_ptr[r0 + nr] - c.ib, STREAM_IN_MAX); k += nt) inl[k] = a.in_off[c.ib + k];
+  for (int j = tid; j < c.nvc; j += nt) vcl[j] = a.vcol[c.vb + j];
   for (int u = tid; u < c.nvc * 9; u += nt) tl[u] = 0.0;
   __syncthreads();
   for (int j = tid; j < c.nvc; j += nt) {
-    const int b = a.vcol[c.vb + j];
+    const int b = vcl[j];
     if (b >= r0 && b < r0 + nr) lcol[b - r0] = j;
   }
-  // thread tid owns element tid of the workgroup's rows
+  // thread tid owns element tid of the workgroup's rows; Mr holds its row
+  // of the block-Jacobi factor, drow points to its row of the FP64 diagonal
+  // block (read when applied, while the workgroups synchronise)
   const bool own = tid < n9;
   const int row = own ? tid / 9 : 0, cp = own ? tid - 9 * row : 0;
   double r = 0.0, u = 0.0, w = 0.0, m = 0.0, z = 0.0, q = 0.0;
-  // row cp of the FP64 diagonal block of row `row` and of its block-Jacobi
-  // factor (both read when applied)
   const double* drow = a.Sdiag + 81 * (size_t)(r0 + row) + cp * 9;
-  const double* Mr = a.Minv + 81 * (size_t)(r0 + row) + cp * 9;
+  double Mr[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) Mr[k] = own ? a.Minv[81 * (size_t)(r0 + row) + cp * 9 + k] : 0.0;
   if (own) {
     r = a.b[9 * (size_t)r0 + tid];
     nl[tid] = r;
@@ -889,11 +922,11 @@ __global__ __launch_bounds__(PCG_THREADS) void k_pcg_stream(PcgArgs a) {
     clear_record(a.partA + (size_t)(k / 3) * pstride + (size_t)B * PART_STRIDE + (k - 3 * (k / 3)));
   for (int k = tid; k < a.maxiter + 2; k += nt) clear_record(a.rflag + (size_t)k * G + B);
   bool ok = grid_barrier(a.gs, a.error);
-  fetch_cols(a.vcol + c.vb, a.zring, c.nvc, zl);
+  fetch_cols(vcl, a.zring, c.nvc, zl);
   double t0 = 0.0;
   for (int i = tid; i < G; i += nt) t0 += a.partB[(size_t)i * PART_STRIDE];
-  const double bnorm = sqrt(block_sum(t0, red));  // (its barriers complete zl)
-  if (ok) ok = stream_spmv(a, c, 0, rptr, lcol, zl, ml, tl, seg, st, nl, &poll_failed);
+  const double bnorm = uniform(sqrt(block_sum(t0, red)));  // (its barriers complete zl)
+  if (ok) ok = stream_spmv(a, c, 0, rptr, lcol, vcl, ipl, inl, zl, ml, tl, seg, st, nl, &poll_failed, Mr);
   if (own) {
     w = nl[tid] + nd;
     wl[tid] = w;
@@ -954,8 +987,9 @@ __global__ __launch_bounds__(PCG_THREADS) void k_pcg_stream(PcgArgs a) {
       ok = false;
       break;
     }
-    // every workgroup's m columns are in memory now
-    fetch_cols(a.vcol + c.vb, zk, c.nvc, zl);
+    // every workgroup's m columns are in memory now (w is no longer needed
+    // in zl's memory)
+    fetch_cols(vcl, zk, c.nvc, zl);
     double gamma = 0.0, delta = 0.0, rr = 0.0;
 #pragma unroll 2
     for (int w2 = 0; w2 < PCG_THREADS / 64; ++w2) {
@@ -963,6 +997,10 @@ __global__ __launch_bounds__(PCG_THREADS) void k_pcg_stream(PcgArgs a) {
       delta += red3s[3 * w2 + 1];
       rr += red3s[3 * w2 + 2];
     }
+    // (identical in every thread: scalar registers)
+    gamma = uniform(gamma);
+    delta = uniform(delta);
+    rr = uniform(rr);
     iters = i;
     rnorm = sqrt(rr);
     if (rnorm <= a.rtol * bnorm || i == a.maxiter) break;
@@ -974,7 +1012,7 @@ __global__ __launch_bounds__(PCG_THREADS) void k_pcg_stream(PcgArgs a) {
     }
     const double alpha = gamma / den;
     __syncthreads();  // zl complete
-    if (!stream_spmv(a, c, i + 1, rptr, lcol, zl, ml, tl, seg, st, nl, &poll_failed)) {
+    if (!stream_spmv(a, c, i + 1, rptr, lcol, vcl, ipl, inl, zl, ml, tl, seg, st, nl, &poll_failed, Mr)) {
       ok = false;
       break;
     }

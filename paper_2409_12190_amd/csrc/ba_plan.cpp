@@ -379,8 +379,10 @@ std::string build_plan(int32_t nc, int32_t np, int64_t no, const int32_t* cidx, 
 
   // Streamed plans: a decomposition of their own.  Each upper block is read
   // once per product, by the owner of its row, so rows are weighted by their
-  // upper blocks (8 each) plus the column sums they receive (at most one per
-  // lower block); at most STREAM_RMAX rows per workgroup.
+  // upper blocks (16 each) plus the column sums they receive (at most one per
+  // lower block); contiguous ranges of at most STREAM_RMAX rows, at most
+  // PCG_MAX_GRID of them, with the smallest largest weight (bisection on the
+  // cap of a greedy split).
   p.srow.clear();
   p.sitem_ptr.clear();
   p.sitem_col.clear();
@@ -397,27 +399,39 @@ std::string build_plan(int32_t nc, int32_t np, int64_t no, const int32_t* cidx, 
   p.max_vcol = 0;
   if (!p.pcg_resident) {
     std::vector<int64_t> wgt(nc);
-    int64_t total = 0;
+    int64_t total = 0, wmax = 0;
     for (int32_t a = 0; a < nc; ++a) {
-      wgt[a] = 8 * (int64_t)(p.S_ptr[a + 1] - p.S_ptr[a]) + (p.T_ptr[a + 1] - p.T_ptr[a]);
+      wgt[a] = 16 * (int64_t)(p.S_ptr[a + 1] - p.S_ptr[a]) + (p.T_ptr[a + 1] - p.T_ptr[a]);
       total += wgt[a];
+      wmax = std::max(wmax, wgt[a]);
     }
-    // the row cap can leave more ranges than workgroups: raise the target
-    for (int64_t target = (total + PCG_MAX_GRID - 1) / PCG_MAX_GRID;; target += target / 16 + 1) {
-      p.srow.assign(1, 0);
+    auto split = [&](int64_t cap, std::vector<int32_t>& rows) {
+      rows.assign(1, 0);
       int64_t items = 0;
       int32_t nrow = 0;
       for (int32_t a = 0; a < nc; ++a) {
-        if (nrow > 0 && (nrow == STREAM_RMAX || items >= target)) {
-          p.srow.push_back(a);
+        if (nrow > 0 && (nrow == STREAM_RMAX || items + wgt[a] > cap)) {
+          rows.push_back(a);
           items = 0;
           nrow = 0;
         }
         items += wgt[a];
         ++nrow;
       }
-      p.srow.push_back(nc);
-      if ((int32_t)p.srow.size() - 1 <= PCG_MAX_GRID) break;
+      rows.push_back(nc);
+      return (int32_t)rows.size() - 1;
+    };
+    int64_t lo = wmax, hi = total;
+    while (lo < hi) {
+      const int64_t mid = lo + (hi - lo) / 2;
+      if (split(mid, p.srow) <= PCG_MAX_GRID)
+        hi = mid;
+      else
+        lo = mid + 1;
+    }
+    if (split(lo, p.srow) > PCG_MAX_GRID) {
+      std::snprintf(msg, sizeof msg, "the streamed PCG needs more than %d workgroups", PCG_MAX_GRID);
+      return msg;
     }
     const int32_t G = p.sgrid = (int32_t)p.srow.size() - 1;
     std::vector<int32_t> owner(nc);
