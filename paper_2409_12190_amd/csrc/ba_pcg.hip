@@ -256,11 +256,12 @@ __device__ __forceinline__ void pcg_spmv(const PcgArgs& a, int ib, int i0, int i
   __syncthreads();
 }
 
-// fetch block columns cols[0 .. n) from ring slot zk into LDS
-__device__ __forceinline__ void fetch_cols(const int32_t* cols, const double* zk, int n, double* zl) {
+// fetch block columns cols[0 .. n) from ring slot zk into LDS (as D)
+template <typename D>
+__device__ __forceinline__ void fetch_cols(const int32_t* cols, const double* zk, int n, D* zl) {
   for (int u = threadIdx.x; u < n * 9; u += blockDim.x) {
     const int j = u / 9;
-    zl[u] = zk[(size_t)cols[j] * ZSTRIDE + (u - 9 * j)];
+    zl[u] = (D)zk[(size_t)cols[j] * ZSTRIDE + (u - 9 * j)];
   }
 }
 
@@ -680,20 +681,42 @@ struct StreamCtx {
   size_t vbase;
 };
 
+// Lane `lane` of wavefront `wave` loads piece (64 j + lane) % STREAM_PIECES
+// of the step-k block of group (64 j + lane) / STREAM_PIECES of its
+// wavefront; loads are issued without branches (items clamped to the
+// workgroup's last one).  The workgroup must have items.
+__device__ __forceinline__ void stream_fetch(const PcgArgs& a, const StreamCtx& c,
+                                             f32x4_t (&buf)[STREAM_LOADS], int k) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const unsigned char* __restrict__ SIb =
+      reinterpret_cast<const unsigned char*>(a.SI) + (size_t)c.sib * SI_STRIDE * 4;
+#pragma unroll
+  for (int j = 0; j < STREAM_LOADS; ++j) {
+    const int q = 64 * j + lane;
+    const int gg = min(q / STREAM_PIECES, STREAM_WAVE_GROUPS - 1), pc = q % STREAM_PIECES;
+    const int item = min(min(c.nitems, (wave * STREAM_WAVE_GROUPS + gg) * c.L) + k, c.nitems - 1);
+    buf[j] = *reinterpret_cast<const f32x4_t*>(SIb + (size_t)item * (SI_STRIDE * 4) + pc * 16);
+  }
+}
+
 // nl[k] = (S v)[row k / 9 of the workgroup, component k % 9] without the
 // diagonal block, k < nr * 9, for the block columns of v in zl (the columns
 // vcl of the workgroup's upper blocks) and its own rows in ml; product
 // `slot` of the solve (exchange slot and flag).  The received column sums of
 // row i are listed at ipl[i] .. ipl[i+1] (the first STREAM_IN_MAX in inl).
-// After the blocks, the owning thread's row of the block-Jacobi factor is
-// loaded into Mr (its latency hidden by the exchange).  Every thread of the workgroup calls it (barriers inside);
+// The blocks of steps 0 and 1 are in A and Bf on entry (loaded by the caller
+// or by the previous product, the blocks being the same); on exit they hold
+// them again for the next product.  After the blocks, the owning thread's
+// row of the block-Jacobi factor is loaded into Mr (its latency hidden by
+// the exchange).  Every thread of the workgroup calls it (barriers inside);
 // tl must be zero on entry and is zero on exit.
 __device__ __forceinline__ bool stream_spmv(const PcgArgs& a, const StreamCtx& c, int slot,
                                             const int* rptr, const int* lcol, const int* vcl,
                                             const int* ipl, const int* inl, const double* zl,
                                             const double* ml, double* tl, double* seg,
                                             unsigned char* st, double* nl, int* poll_failed,
-                                            double (&Mr)[9]) {
+                                            double (&Mr)[9], f32x4_t (&A)[STREAM_LOADS],
+                                            f32x4_t (&Bf)[STREAM_LOADS]) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int gl = lane / 9, comp = lane - 9 * gl;
   const bool computes = gl < STREAM_WAVE_GROUPS;
@@ -703,21 +726,8 @@ __device__ __forceinline__ bool stream_spmv(const PcgArgs& a, const StreamCtx& c
   const int i1 = computes ? min(nitems, i0 + L) : nitems;
   unsigned char* wst = st + wave * STREAM_WAVE_BYTES;
   if (nitems > 0) {
-    const unsigned char* __restrict__ SIb =
-        reinterpret_cast<const unsigned char*>(a.SI) + (size_t)c.sib * SI_STRIDE * 4;
     const int* __restrict__ scol = a.sitem_col + c.sib;
-    // lane `lane` moves piece (64 j + lane) % STREAM_PIECES of the block of
-    // group (64 j + lane) / STREAM_PIECES of its wavefront; loads are issued
-    // without branches (items clamped to the workgroup's last one)
-    auto fetch = [&](f32x4_t (&buf)[STREAM_LOADS], int k) {
-#pragma unroll
-      for (int j = 0; j < STREAM_LOADS; ++j) {
-        const int q = 64 * j + lane;
-        const int gg = min(q / STREAM_PIECES, STREAM_WAVE_GROUPS - 1), pc = q % STREAM_PIECES;
-        const int item = min(min(nitems, (wave * STREAM_WAVE_GROUPS + gg) * L) + k, nitems - 1);
-        buf[j] = *reinterpret_cast<const f32x4_t*>(SIb + (size_t)item * (SI_STRIDE * 4) + pc * 16);
-      }
-    };
+    auto fetch = [&](f32x4_t (&buf)[STREAM_LOADS], int k) { stream_fetch(a, c, buf, k); };
     auto stage = [&](const f32x4_t (&buf)[STREAM_LOADS]) {
 #pragma unroll
       for (int j = 0; j < STREAM_LOADS; ++j) *reinterpret_cast<f32x4_t*>(wst + (64 * j + lane) * 16) = buf[j];
@@ -751,9 +761,6 @@ __device__ __forceinline__ bool stream_spmv(const PcgArgs& a, const StreamCtx& c
     // the blocks of steps k + 1 and k + 2 in flight while step k is
     // multiplied (past the last step the last one is loaded again, never
     // staged)
-    f32x4_t A[STREAM_LOADS], Bf[STREAM_LOADS];
-    fetch(A, 0);
-    fetch(Bf, min(1, L - 1));
     int col = scol[min(i0, nitems - 1)];
     stage(A);
     for (int k = 0; k < L; k += 2) {
@@ -770,6 +777,9 @@ __device__ __forceinline__ bool stream_spmv(const PcgArgs& a, const StreamCtx& c
       if (k + 2 < L) stage(A);
       col = col_next;
     }
+    // the first two steps of the next product
+    fetch(A, 0);
+    fetch(Bf, min(1, L - 1));
     if (cur >= 0) seg[(cur + g) * 9 + comp] = acc;
   }
   __syncthreads();
@@ -867,6 +877,12 @@ __global__ __launch_bounds__(PCG_THREADS) void k_pcg_stream(PcgArgs a) {
   }
   const int r0 = c.r0, nr = c.nr, n9 = nr * 9;
   const size_t zstride = (size_t)a.nc * ZSTRIDE, pstride = (size_t)G * PART_STRIDE;
+  // the first two steps' blocks of every product, loaded early
+  f32x4_t A[STREAM_LOADS], Bf[STREAM_LOADS];
+  if (c.nitems > 0) {
+    stream_fetch(a, c, A, 0);
+    stream_fetch(a, c, Bf, min(1, c.L - 1));
+  }
   if (tid == 0) {
     rptr[0] = 0;
     for (int i = 0; i < nr; ++i) rptr[i + 1] = rptr[i] + (a.S_ptr[r0 + i + 1] - a.S_ptr[r0 + i] - 1);
@@ -926,7 +942,7 @@ __global__ __launch_bounds__(PCG_THREADS) void k_pcg_stream(PcgArgs a) {
   double t0 = 0.0;
   for (int i = tid; i < G; i += nt) t0 += a.partB[(size_t)i * PART_STRIDE];
   const double bnorm = uniform(sqrt(block_sum(t0, red)));  // (its barriers complete zl)
-  if (ok) ok = stream_spmv(a, c, 0, rptr, lcol, vcl, ipl, inl, zl, ml, tl, seg, st, nl, &poll_failed, Mr);
+  if (ok) ok = stream_spmv(a, c, 0, rptr, lcol, vcl, ipl, inl, zl, ml, tl, seg, st, nl, &poll_failed, Mr, A, Bf);
   if (own) {
     w = nl[tid] + nd;
     wl[tid] = w;
@@ -1012,7 +1028,7 @@ __global__ __launch_bounds__(PCG_THREADS) void k_pcg_stream(PcgArgs a) {
     }
     const double alpha = gamma / den;
     __syncthreads();  // zl complete
-    if (!stream_spmv(a, c, i + 1, rptr, lcol, vcl, ipl, inl, zl, ml, tl, seg, st, nl, &poll_failed, Mr)) {
+    if (!stream_spmv(a, c, i + 1, rptr, lcol, vcl, ipl, inl, zl, ml, tl, seg, st, nl, &poll_failed, Mr, A, Bf)) {
       ok = false;
       break;
     }

@@ -379,7 +379,7 @@ std::string build_plan(int32_t nc, int32_t np, int64_t no, const int32_t* cidx, 
 
   // Streamed plans: a decomposition of their own.  Each upper block is read
   // once per product, by the owner of its row, so rows are weighted by their
-  // upper blocks (16 each) plus the column sums they receive (at most one per
+  // upper blocks (64 each) plus the column sums they receive (at most one per
   // lower block); contiguous ranges of at most STREAM_RMAX rows, at most
   // PCG_MAX_GRID of them, with the smallest largest weight (bisection on the
   // cap of a greedy split).
@@ -401,7 +401,7 @@ std::string build_plan(int32_t nc, int32_t np, int64_t no, const int32_t* cidx, 
     std::vector<int64_t> wgt(nc);
     int64_t total = 0, wmax = 0;
     for (int32_t a = 0; a < nc; ++a) {
-      wgt[a] = 16 * (int64_t)(p.S_ptr[a + 1] - p.S_ptr[a]) + (p.T_ptr[a + 1] - p.T_ptr[a]);
+      wgt[a] = 64 * (int64_t)(p.S_ptr[a + 1] - p.S_ptr[a]) + (p.T_ptr[a + 1] - p.T_ptr[a]);
       total += wgt[a];
       wmax = std::max(wmax, wgt[a]);
     }
