@@ -125,7 +125,7 @@ void carve(ba_problem* p, char* base, size_t* total) {
   b.S = c.take<char>(nnzb * 81 * es);
   // streamed PCG plans in mixed precision: one FP32 copy of each upper
   // off-diagonal block
-  const bool stream = !P.pcg_resident && p->opt.precision == BA_MIXED;
+  const bool stream = !P.pcg_resident && p->opt.precision == BA_MIXED && P.sgrid > 0;
   b.SI = c.take<char>(stream ? P.sitem_col.size() * ba::SI_STRIDE * 4 : 0);
   b.Sdiag = c.take<double>(81 * nc);
   b.bS = c.take<double>(9 * nc);
@@ -259,10 +259,10 @@ hipError_t reset_sync(ba_problem* p) {
   return hipMemsetAsync(p->b.gsync, 0, sizeof(ba::GridSync), p->stream);
 }
 
-// mixed-precision plans whose PCG streams its blocks (each off-diagonal
-// block copied per (row, block) item by the Schur kernel)
+// mixed-precision plans whose PCG streams its blocks (an FP32 copy of each
+// upper off-diagonal block written by the Schur kernel)
 bool streamed(const ba_problem* p) {
-  return !p->plan.pcg_resident && p->opt.precision == BA_MIXED;
+  return !p->plan.pcg_resident && p->opt.precision == BA_MIXED && p->plan.sgrid > 0;
 }
 
 template <typename T>
@@ -582,8 +582,9 @@ ba_status ba_problem_bind(ba_problem* p, void* ws, size_t bytes, void* stream) {
   HIPCHK(hipMemcpyAsync(b.dev, p->hscal, sizeof(ba::DevScalars), hipMemcpyHostToDevice, s));
   HIPCHK(hipStreamSynchronize(s));
   const bool pipe = p->opt.cg_variant == BA_CG_PIPELINED;
-  const int maxg = p->opt.precision == BA_MIXED ? ba::pcg_max_grid<float>(P.pcg_resident, pipe)
-                                                : ba::pcg_max_grid<double>(P.pcg_resident, pipe);
+  const int maxg = p->opt.precision == BA_MIXED
+                       ? ba::pcg_max_grid<float>(P.pcg_resident, pipe, streamed(p) && pipe)
+                       : ba::pcg_max_grid<double>(P.pcg_resident, pipe);
   if (maxg <= 0) return fail(BA_EHIP, "cooperative occupancy query failed");
   p->pcg_grid = streamed(p) && pipe ? P.sgrid : P.pcg_grid;
   if (p->pcg_grid > maxg || p->pcg_grid > ba::MAX_BARRIER_GROUPS * ba::BARRIER_FANIN)

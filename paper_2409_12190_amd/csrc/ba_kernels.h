@@ -141,7 +141,7 @@ hipError_t launch_damp_points(const DampArgs&, hipStream_t);
 template <typename T> hipError_t launch_point_q(const PointQArgs&, hipStream_t);
 template <typename T> hipError_t launch_schur_pairs(const SchurArgs&, int nwg, hipStream_t);
 template <typename T> hipError_t launch_camera_finish(const CamFinishArgs&, int nc, hipStream_t);
-template <typename T> int pcg_max_grid(bool resident, bool pipelined);
+template <typename T> int pcg_max_grid(bool resident, bool pipelined, bool stream = false);
 template <typename T>
 hipError_t launch_pcg(const PcgArgs&, int grid, bool resident, bool pipelined, hipStream_t);
 template <typename T> hipError_t launch_backsub(const BackArgs&, int nchunk, hipStream_t);

@@ -47,6 +47,14 @@ __device__ __forceinline__ int xcd_block(int b, int G) {
   const int x = b & 7, n8 = G >> 3, rem = G & 7;
   return x * n8 + min(x, rem) + (b >> 3);
 }
+// A workgroup-uniform FP64 value held in scalar registers.
+__device__ __forceinline__ double uniform(double v) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)b);
+  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(b >> 32));
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
 constexpr long BARRIER_SPIN_LIMIT = 1L << 21;
 
 __device__ __forceinline__ void publish(double* p, double v) {
@@ -446,6 +454,7 @@ __global__ __launch_bounds__(PCG_THREADS) void k_pcg_pipelined(PcgArgs a) {
   __shared__ double zl[PCG_ZCOLS * 9];
   __shared__ double seg[(PCG_RMAX + SPMV_GROUPS) * 9];
   __shared__ int rptr[PCG_RMAX + 1];
+  __shared__ int ucl[PCG_ZCOLS];  // the block columns read (global index)
   __shared__ double red[PCG_THREADS / 64];
   const int G = gridDim.x, B = xcd_block(blockIdx.x, gridDim.x), tid = threadIdx.x, nt = blockDim.x;
   const int r0 = a.wg_row[B], nr = a.wg_row[B + 1] - r0;
@@ -474,6 +483,7 @@ __global__ __launch_bounds__(PCG_THREADS) void k_pcg_pipelined(PcgArgs a) {
     ps[i] = 0.0;
   }
   for (int i = tid; i < nr * 81; i += nt) Ml[i] = a.Minv[81 * (size_t)r0 + i];
+  for (int j = tid; j < nuc; j += nt) ucl[j] = a.ucol[ub + j];
   __syncthreads();
   PcgItems it;
   if (RES && i0 < i1) pcg_load_items<T>(a, ib, i0, i1, rptr, comp, it);
@@ -498,7 +508,7 @@ __global__ __launch_bounds__(PCG_THREADS) void k_pcg_pipelined(PcgArgs a) {
   for (int q = tid; q < 3 * (a.maxiter + 1); q += nt)
     clear_record(a.partA + (size_t)(q / 3) * pstride + (size_t)B * PART_STRIDE + (q - 3 * (q / 3)));
   bool ok = grid_barrier(a.gs, a.error);
-  pcg_fetch_z(a, a.zring, ub, nuc, zl);
+  fetch_cols(ucl, a.zring, nuc, zl);
   double t0 = 0.0;
   for (int i = tid; i < G; i += nt) t0 += a.partB[(size_t)i * PART_STRIDE];
   const double bnorm = sqrt(block_sum(t0, red));
@@ -560,7 +570,7 @@ __global__ __launch_bounds__(PCG_THREADS) void k_pcg_pipelined(PcgArgs a) {
       break;
     }
     // every workgroup's m columns are in memory now
-    pcg_fetch_z(a, zk, ub, nuc, zl);
+    fetch_cols(ucl, zk, nuc, zl);
     double gamma = 0.0, delta = 0.0, rr = 0.0;
 #pragma unroll 2
     for (int w2 = 0; w2 < PCG_THREADS / 64; ++w2) {
@@ -568,6 +578,10 @@ __global__ __launch_bounds__(PCG_THREADS) void k_pcg_pipelined(PcgArgs a) {
       delta += red3s[3 * w2 + 1];
       rr += red3s[3 * w2 + 2];
     }
+    // (identical in every thread: scalar registers)
+    gamma = uniform(gamma);
+    delta = uniform(delta);
+    rr = uniform(rr);
     iters = i;
     rnorm = sqrt(rr);
     if (rnorm <= a.rtol * bnorm || i == a.maxiter) break;
@@ -665,14 +679,6 @@ __device__ __forceinline__ bool poll_flag(const double* f, int* error) {
     __builtin_amdgcn_s_sleep(1);
   }
   return true;
-}
-
-// A workgroup-uniform FP64 value held in scalar registers.
-__device__ __forceinline__ double uniform(double v) {
-  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
-  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)b);
-  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(b >> 32));
-  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
 // Per-workgroup constants of the streamed product.
@@ -1063,8 +1069,8 @@ __global__ __launch_bounds__(PCG_THREADS) void k_pcg_stream(PcgArgs a) {
 // ---------------------------------------------------------------------------
 
 template <typename T>
-static const void* pcg_kernel(bool resident, bool pipelined) {
-  if (sizeof(T) == 4 && pipelined && !resident) return reinterpret_cast<const void*>(k_pcg_stream);
+static const void* pcg_kernel(bool resident, bool pipelined, bool stream) {
+  if (sizeof(T) == 4 && pipelined && !resident && stream) return reinterpret_cast<const void*>(k_pcg_stream);
   if (pipelined)
     return resident ? reinterpret_cast<const void*>(k_pcg_pipelined<T, true>)
                     : reinterpret_cast<const void*>(k_pcg_pipelined<T, false>);
@@ -1073,27 +1079,30 @@ static const void* pcg_kernel(bool resident, bool pipelined) {
 }
 
 template <typename T>
-int pcg_max_grid(bool resident, bool pipelined) {
+int pcg_max_grid(bool resident, bool pipelined, bool stream) {
   int dev = 0, ncu = 0, per = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
   if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, pcg_kernel<T>(resident, pipelined),
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, pcg_kernel<T>(resident, pipelined, stream),
                                                    PCG_THREADS, 0) != hipSuccess)
     return 0;
   return ncu * per;
 }
-template int pcg_max_grid<float>(bool, bool);
-template int pcg_max_grid<double>(bool, bool);
+template int pcg_max_grid<float>(bool, bool, bool);
+template int pcg_max_grid<double>(bool, bool, bool);
 
+// The streamed kernel runs when the arguments carry the streamed
+// decomposition (mixed precision, pipelined recurrence, blocks not
+// register-resident); such plans without it read the stored blocks per item.
 template <typename T>
 hipError_t launch_pcg(const PcgArgs& a, int grid, bool resident, bool pipelined, hipStream_t s) {
-  if (sizeof(T) == 4 && pipelined && !resident &&
-      (!a.SI || !a.sitem_ptr || !a.sitem_col || !a.vcol_ptr || !a.vcol || !a.vbase || !a.in_ptr ||
-       !a.in_off || !a.src_ptr || !a.src || !a.rring || !a.rflag))
+  const bool stream = sizeof(T) == 4 && pipelined && !resident && a.SI;
+  if (stream && (!a.sitem_ptr || !a.sitem_col || !a.vcol_ptr || !a.vcol || !a.vbase || !a.in_ptr ||
+                 !a.in_off || !a.src_ptr || !a.src || !a.rring || !a.rflag))
     return hipErrorInvalidValue;  // the streamed kernel needs its decomposition and exchange
   void* args[] = {const_cast<PcgArgs*>(&a)};
-  return hipLaunchCooperativeKernel(pcg_kernel<T>(resident, pipelined), dim3(grid), dim3(PCG_THREADS),
-                                    args, 0, s);
+  return hipLaunchCooperativeKernel(pcg_kernel<T>(resident, pipelined, stream), dim3(grid),
+                                    dim3(PCG_THREADS), args, 0, s);
 }
 template hipError_t launch_pcg<float>(const PcgArgs&, int, bool, bool, hipStream_t);
 template hipError_t launch_pcg<double>(const PcgArgs&, int, bool, bool, hipStream_t);

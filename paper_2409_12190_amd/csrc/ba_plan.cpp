@@ -434,9 +434,6 @@ std::string build_plan(int32_t nc, int32_t np, int64_t no, const int32_t* cidx, 
       return msg;
     }
     const int32_t G = p.sgrid = (int32_t)p.srow.size() - 1;
-    std::vector<int32_t> owner(nc);
-    for (int32_t g = 0; g < G; ++g)
-      for (int32_t a = p.srow[g]; a < p.srow[g + 1]; ++a) owner[a] = g;
     p.sitem_ptr.assign(G + 1, 0);
     p.vcol_ptr.assign(G + 1, 0);
     p.vbase.assign(G, 0);
@@ -465,13 +462,22 @@ std::string build_plan(int32_t nc, int32_t np, int64_t no, const int32_t* cidx, 
       p.vcol_ptr[g + 1] = (int32_t)p.vcol.size();
     }
     p.rstride = (off + 15) & ~(int64_t)15;
-    if (p.max_vcol > STREAM_COLS) {
-      std::snprintf(msg, sizeof msg,
-                    "a streamed PCG workgroup would touch %d block columns; at most %d are supported",
-                    p.max_vcol, STREAM_COLS);
-      return msg;
-    }
-    if (p.rstride > INT32_MAX) return "the streamed PCG exchange slots exceed 2^31 values";
+  }
+  if (!p.pcg_resident && (p.max_vcol > STREAM_COLS || p.rstride > INT32_MAX)) {
+    // beyond the streamed kernel's LDS column capacity: no streamed
+    // decomposition (the mixed solve then reads the stored blocks per item)
+    const int32_t mv = p.max_vcol;
+    for (auto* v : {&p.srow, &p.sitem_ptr, &p.sitem_col, &p.blk_pos, &p.vcol_ptr, &p.vcol, &p.vbase})
+      v->clear();
+    p.rstride = 0;
+    p.sgrid = 0;
+    p.max_vcol = mv;
+  }
+  if (p.sgrid > 0) {
+    const int32_t G = p.sgrid;
+    std::vector<int32_t> owner(nc);
+    for (int32_t g = 0; g < G; ++g)
+      for (int32_t a = p.srow[g]; a < p.srow[g + 1]; ++a) owner[a] = g;
     // incoming slots of every row, ascending sending workgroup; the senders
     // of every workgroup
     p.in_ptr.assign(nc + 1, 0);

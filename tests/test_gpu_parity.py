@@ -204,6 +204,22 @@ def test_streamed_pcg_path_matches_oracle():
             assert abs(ig["cost_after"] - io["cost_after"]) <= forms[f] * io["cost_after"], (f, it)
 
 
+def test_mixed_pcg_beyond_streamed_column_capacity_matches_oracle():
+    """500 ring cameras: a streamed workgroup would need more distinct block
+    columns than the streamed kernel holds in LDS, so the mixed solve reads
+    the stored FP32 blocks per (row, block) item instead; within the
+    mixed-mode bound of the oracle, no breakdown."""
+    s = make_scene(0, n_cams=500, n_pts=50000)
+    o = orc(s)
+    g = gpu(s, precision=B.BA_MIXED, cg_variant=B.BA_CG_PIPELINED)
+    for it in range(2):
+        io, ig = o.lm_step(), g.lm_step()
+        assert ig["status"] == 0 and ig["cg_breakdown"] == 0, it
+        # (the oracle needs 5 and 8 CG iterations on these two steps)
+        assert abs(ig["cg_iters"] - io["cg_iters"]) <= 2 and ig["cg_rel_resid"] <= 1e-4, (it, ig["cg_iters"])
+        assert abs(ig["cost_after"] - io["cost_after"]) <= 1e-4 * io["cost_after"], it
+
+
 @pytest.mark.parametrize("variant", [B.BA_CG_PIPELINED, B.BA_CG_STANDARD])
 @pytest.mark.parametrize("precision", [B.BA_FP64, B.BA_MIXED])
 def test_pcg_meets_its_tolerance_on_the_exported_system(precision, variant):
