@@ -651,9 +651,9 @@ __global__ __launch_bounds__(PCG_THREADS) void k_pcg_pipelined(PcgArgs a) {
 // to run.
 //
 // The FP64 diagonal blocks are applied by the thread that owns each vector
-// element.  Thread k owns element k of the workgroup's rows and keeps every
-// recurrence vector and its row of the block-Jacobi factor in registers; w, m
-// and the product n also pass through LDS.
+// element.  Thread k owns element k of the workgroup's rows and keeps r, u,
+// w, m, z, q and its row of the block-Jacobi factor in registers, x, p and s
+// in LDS; w, m and the product n also pass through LDS.
 // ---------------------------------------------------------------------------
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
 
@@ -666,7 +666,7 @@ constexpr int STREAM_LOADS = (STREAM_WAVE_GROUPS * STREAM_PIECES + 63) / 64;
 // lockstep loop lets the compiler restructure it into a divergent nest)
 constexpr int STREAM_WAVE_BYTES = STREAM_LOADS * 64 * 16;
 
-// the exchange flag of workgroup `w`'s product `k`: wait until it is raised
+// wait until the exchange flag at f (one sender, one product) is raised
 __device__ __forceinline__ bool poll_flag(const double* f, int* error) {
   const unsigned long long* r = reinterpret_cast<const unsigned long long*>(f);
   long spins = 0;
