@@ -54,8 +54,8 @@ struct SchurArgs {
   double* Sdiag;
   // camera vectors from the self pairs of the diagonal blocks
   double *gc, *bS, *diagU;
-  // streamed PCG plans: each off-diagonal block also written to its two
-  // streamed items (as stored and transposed; null otherwise)
+  // streamed PCG plans: each upper off-diagonal block also written to its
+  // streamed copy blk_pos[e], padded to SI_STRIDE values (null otherwise)
   const int32_t* blk_pos = nullptr;
   void* SI = nullptr;
 };
