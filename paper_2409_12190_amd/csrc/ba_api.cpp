@@ -123,9 +123,10 @@ void carve(ba_problem* p, char* base, size_t* total) {
   b.Vinv = c.take<double>(6 * np);
   b.ep = c.take<double>(3 * np);
   b.S = c.take<char>(nnzb * 81 * es);
-  // streamed PCG plans in mixed precision: one FP32 copy of each upper
-  // off-diagonal block
-  const bool stream = !P.pcg_resident && p->opt.precision == BA_MIXED && P.sgrid > 0;
+  // streamed PCG plans (mixed precision, pipelined recurrence): one FP32
+  // copy of each upper off-diagonal block, the column-sum exchange
+  const bool stream = !P.pcg_resident && p->opt.precision == BA_MIXED && P.sgrid > 0 &&
+                      p->opt.cg_variant == BA_CG_PIPELINED;
   b.SI = c.take<char>(stream ? P.sitem_col.size() * ba::SI_STRIDE * 4 : 0);
   b.Sdiag = c.take<double>(81 * nc);
   b.bS = c.take<double>(9 * nc);
@@ -259,10 +260,11 @@ hipError_t reset_sync(ba_problem* p) {
   return hipMemsetAsync(p->b.gsync, 0, sizeof(ba::GridSync), p->stream);
 }
 
-// mixed-precision plans whose PCG streams its blocks (an FP32 copy of each
-// upper off-diagonal block written by the Schur kernel)
+// mixed-precision plans whose pipelined PCG streams its blocks (an FP32 copy
+// of each upper off-diagonal block written by the Schur kernel)
 bool streamed(const ba_problem* p) {
-  return !p->plan.pcg_resident && p->opt.precision == BA_MIXED && p->plan.sgrid > 0;
+  return !p->plan.pcg_resident && p->opt.precision == BA_MIXED && p->plan.sgrid > 0 &&
+         p->opt.cg_variant == BA_CG_PIPELINED;
 }
 
 template <typename T>
@@ -322,7 +324,7 @@ ba_status lm_step_impl(ba_problem* p, ba_step_info* out) {
              b.zring, b.partA, b.partB, b.dinfo, b.gsync, &b.dev->error};
   const bool pipe = p->opt.cg_variant == BA_CG_PIPELINED;
   int pcg_grid = P.pcg_grid;
-  if (streamed(p) && pipe) {
+  if (streamed(p)) {
     pa.wg_row = b.srow;
     pa.sitem_ptr = b.sitem_ptr;
     pa.sitem_col = b.sitem_col;
@@ -583,10 +585,10 @@ ba_status ba_problem_bind(ba_problem* p, void* ws, size_t bytes, void* stream) {
   HIPCHK(hipStreamSynchronize(s));
   const bool pipe = p->opt.cg_variant == BA_CG_PIPELINED;
   const int maxg = p->opt.precision == BA_MIXED
-                       ? ba::pcg_max_grid<float>(P.pcg_resident, pipe, streamed(p) && pipe)
+                       ? ba::pcg_max_grid<float>(P.pcg_resident, pipe, streamed(p))
                        : ba::pcg_max_grid<double>(P.pcg_resident, pipe);
   if (maxg <= 0) return fail(BA_EHIP, "cooperative occupancy query failed");
-  p->pcg_grid = streamed(p) && pipe ? P.sgrid : P.pcg_grid;
+  p->pcg_grid = streamed(p) ? P.sgrid : P.pcg_grid;
   if (p->pcg_grid > maxg || p->pcg_grid > ba::MAX_BARRIER_GROUPS * ba::BARRIER_FANIN)
     return fail(BA_EUNSUPPORTED, "too many cameras for one co-resident PCG grid");
   p->adj_grid_ok = p->opt.enable_backward &&
