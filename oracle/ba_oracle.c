@@ -33,8 +33,17 @@
  *   LM control    accept iff F' < F, F' finite, pred > 0;
  *                 ratio > 0.75 -> lambda/2; ratio <= 0.25 or reject -> 16 lambda.
  *   PCG           x0 = 0, relative tolerance on the recursively updated residual.
+ *   stopping      orc_solve: lambda_max rejection, plateau of relative decrease,
+ *                 gradient norm, iteration cap (Sec. V, StopOnPlateau).
+ *
+ * Threads: loops over independent units (observations, points, cameras, rows
+ * of the reduced system) run under OpenMP; every sum keeps one fixed order
+ * (each output accumulated by one thread in the order of the sequential
+ * loop, scalar totals summed sequentially from per-unit terms), so results
+ * are bitwise the same for every thread count.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -63,8 +72,15 @@ typedef struct orc_ctx {
     uint8_t *fixed;
     double *cams, *pts;
     double lambda;
-    /* observation lists per point and per camera, in input order */
-    int64_t *pt_ptr, *pt_obs, *cam_ptr, *cam_obs;
+    /* observation lists per point and per camera, in input order; and per
+     * camera ordered by (point, input order), the order in which the
+     * point-by-point Schur accumulation reaches a camera's blocks */
+    int64_t *pt_ptr, *pt_obs, *cam_ptr, *cam_obs, *cam_obs_pt;
+    /* transposed pattern: for column b the upper blocks (a, b), a < b,
+     * ascending a */
+    int64_t *T_ptr, *T_blk;
+    int32_t *T_row;
+    double *term; /* per-observation scratch for sequential totals */
     /* linearisation at the current parameters */
     int have_lin;
     double F;
@@ -342,6 +358,31 @@ static void build_pattern(orc_ctx *c)
     free(cols);
     free(cnt);
     free(cap);
+    /* column lists of the off-diagonal upper blocks, rows ascending */
+    c->T_ptr = xcalloc((size_t)c->nc + 1, sizeof(int64_t));
+    for (int32_t a = 0; a < c->nc; ++a)
+        for (int64_t e = c->S_ptr[a] + 1; e < c->S_ptr[a + 1]; ++e) c->T_ptr[c->S_col[e] + 1]++;
+    for (int32_t b = 0; b < c->nc; ++b) c->T_ptr[b + 1] += c->T_ptr[b];
+    c->T_blk = xcalloc((size_t)c->T_ptr[c->nc], sizeof(int64_t));
+    c->T_row = xcalloc((size_t)c->T_ptr[c->nc], sizeof(int32_t));
+    int64_t *fill = xcalloc((size_t)c->nc, sizeof(int64_t));
+    for (int32_t a = 0; a < c->nc; ++a)
+        for (int64_t e = c->S_ptr[a] + 1; e < c->S_ptr[a + 1]; ++e) {
+            const int32_t b = c->S_col[e];
+            c->T_blk[c->T_ptr[b] + fill[b]] = e;
+            c->T_row[c->T_ptr[b] + fill[b]++] = a;
+        }
+    free(fill);
+    /* per camera, its observations by (point, input order) */
+    c->cam_obs_pt = xcalloc((size_t)c->no, sizeof(int64_t));
+    fill = xcalloc((size_t)c->nc, sizeof(int64_t));
+    for (int32_t j = 0; j < c->np; ++j)
+        for (int64_t x = c->pt_ptr[j]; x < c->pt_ptr[j + 1]; ++x) {
+            const int64_t k = c->pt_obs[x];
+            const int32_t a = c->cidx[k];
+            c->cam_obs_pt[c->cam_ptr[a] + fill[a]++] = k;
+        }
+    free(fill);
 }
 
 static int64_t find_block(const orc_ctx *c, int32_t a, int32_t b)
@@ -392,6 +433,7 @@ orc_ctx *orc_create(const orc_options *o, int32_t nc, int32_t np, int64_t no,
     c->gc = xcalloc((size_t)nc * d, sizeof(double));
     c->gp = xcalloc((size_t)np * 3, sizeof(double));
     c->Vinv = xcalloc((size_t)np * 9, sizeof(double));
+    c->term = xcalloc((size_t)no, sizeof(double));
     build_pattern(c);
     c->S = xcalloc((size_t)c->nnzb * d * d, sizeof(double));
     c->bS = xcalloc((size_t)nc * d, sizeof(double));
@@ -406,7 +448,8 @@ void orc_destroy(orc_ctx *c)
     void *p[] = {c->cidx, c->pidx, c->obs, c->ow, c->fixed, c->cams, c->pts, c->pt_ptr,
                  c->pt_obs, c->cam_ptr, c->cam_obs, c->r, c->w, c->Jc, c->Jp, c->U, c->V,
                  c->gc, c->gp, c->S_ptr, c->S_col, c->S, c->bS, c->Vinv, c->dc, c->dp,
-                 c->cams_new, c->pts_new};
+                 c->cams_new, c->pts_new, c->cam_obs_pt, c->T_ptr, c->T_blk, c->T_row,
+                 c->term};
     for (size_t i = 0; i < sizeof(p) / sizeof(p[0]); ++i) free(p[i]);
     free(c);
 }
@@ -435,7 +478,8 @@ int64_t orc_nnzb(const orc_ctx *c) { return c->nnzb; }
 /* F = 1/2 sum_k omega_k rho(|r_k|^2) at the given parameters (Eq. 1). */
 double orc_cost(const orc_ctx *c, const double *cams, const double *pts)
 {
-    double F = 0.0;
+    double *term = c->term;
+#pragma omp parallel for schedule(static)
     for (int64_t k = 0; k < c->no; ++k) {
         double pix[2];
         orc_project(cams + 10 * (int64_t)c->cidx[k], pts + 3 * (int64_t)c->pidx[k], c->o.d, pix,
@@ -443,8 +487,10 @@ double orc_cost(const orc_ctx *c, const double *cams, const double *pts)
         const double rx = pix[0] - c->obs[2 * k], ry = pix[1] - c->obs[2 * k + 1];
         double rho, drho;
         robust(rx * rx + ry * ry, c->o.huber_delta, &rho, &drho);
-        F += 0.5 * c->ow[k] * rho;
+        term[k] = 0.5 * c->ow[k] * rho;
     }
+    double F = 0.0;
+    for (int64_t k = 0; k < c->no; ++k) F += term[k];
     return F;
 }
 
@@ -453,7 +499,8 @@ double orc_cost(const orc_ctx *c, const double *cams, const double *pts)
 static void linearize(orc_ctx *c)
 {
     const int d = c->o.d;
-    double F = 0.0;
+    double *term = c->term;
+#pragma omp parallel for schedule(static)
     for (int64_t k = 0; k < c->no; ++k) {
         double pix[2];
         double *Jc = c->Jc + (size_t)k * 2 * d, *Jp = c->Jp + (size_t)k * 6;
@@ -465,26 +512,44 @@ static void linearize(orc_ctx *c)
         double rho, drho;
         robust(c->r[2 * k] * c->r[2 * k] + c->r[2 * k + 1] * c->r[2 * k + 1], c->o.huber_delta,
                &rho, &drho);
-        F += 0.5 * c->ow[k] * rho;
+        term[k] = 0.5 * c->ow[k] * rho;
         c->w[k] = c->ow[k] * drho;
     }
+    double F = 0.0;
+    for (int64_t k = 0; k < c->no; ++k) F += term[k];
     c->F = F;
-    memset(c->U, 0, sizeof(double) * c->nc * d * d);
-    memset(c->V, 0, sizeof(double) * c->np * 9);
-    memset(c->gc, 0, sizeof(double) * c->nc * d);
-    memset(c->gp, 0, sizeof(double) * c->np * 3);
-    for (int64_t k = 0; k < c->no; ++k) {
-        const double *Jc = c->Jc + (size_t)k * 2 * d, *Jp = c->Jp + (size_t)k * 6;
-        const double *r = c->r + 2 * k, w = c->w[k];
-        double *U = c->U + (size_t)c->cidx[k] * d * d, *V = c->V + (size_t)c->pidx[k] * 9;
-        double *gc = c->gc + (size_t)c->cidx[k] * d, *gp = c->gp + (size_t)c->pidx[k] * 3;
-        for (int i = 0; i < d; ++i) {
-            for (int j = 0; j < d; ++j) U[i * d + j] += w * (Jc[i] * Jc[j] + Jc[d + i] * Jc[d + j]);
-            gc[i] += w * (Jc[i] * r[0] + Jc[d + i] * r[1]);
+    /* camera blocks U_a and gradients g_a: sums over the camera's
+     * observations in input order */
+#pragma omp parallel for schedule(dynamic, 8)
+    for (int32_t a = 0; a < c->nc; ++a) {
+        double *U = c->U + (size_t)a * d * d, *gc = c->gc + (size_t)a * d;
+        memset(U, 0, sizeof(double) * d * d);
+        memset(gc, 0, sizeof(double) * d);
+        for (int64_t x = c->cam_ptr[a]; x < c->cam_ptr[a + 1]; ++x) {
+            const int64_t k = c->cam_obs[x];
+            const double *Jc = c->Jc + (size_t)k * 2 * d;
+            const double *r = c->r + 2 * k, w = c->w[k];
+            for (int i = 0; i < d; ++i) {
+                for (int j = 0; j < d; ++j) U[i * d + j] += w * (Jc[i] * Jc[j] + Jc[d + i] * Jc[d + j]);
+                gc[i] += w * (Jc[i] * r[0] + Jc[d + i] * r[1]);
+            }
         }
-        for (int i = 0; i < 3; ++i) {
-            for (int j = 0; j < 3; ++j) V[i * 3 + j] += w * (Jp[i] * Jp[j] + Jp[3 + i] * Jp[3 + j]);
-            gp[i] += w * (Jp[i] * r[0] + Jp[3 + i] * r[1]);
+    }
+    /* point blocks V_j and gradients g_j: sums over the point's track in
+     * input order */
+#pragma omp parallel for schedule(static)
+    for (int32_t j = 0; j < c->np; ++j) {
+        double *V = c->V + (size_t)j * 9, *gp = c->gp + (size_t)j * 3;
+        memset(V, 0, sizeof(double) * 9);
+        memset(gp, 0, sizeof(double) * 3);
+        for (int64_t x = c->pt_ptr[j]; x < c->pt_ptr[j + 1]; ++x) {
+            const int64_t k = c->pt_obs[x];
+            const double *Jp = c->Jp + (size_t)k * 6;
+            const double *r = c->r + 2 * k, w = c->w[k];
+            for (int i = 0; i < 3; ++i) {
+                for (int m = 0; m < 3; ++m) V[i * 3 + m] += w * (Jp[i] * Jp[m] + Jp[3 + i] * Jp[3 + m]);
+                gp[i] += w * (Jp[i] * r[0] + Jp[3 + i] * r[1]);
+            }
         }
     }
     c->have_lin = 1;
@@ -505,37 +570,41 @@ static double clampd(double x, double lo, double hi) { return x < lo ? lo : (x >
 /* damped system, Schur complement, PCG, back-substitution                  */
 /* ------------------------------------------------------------------------ */
 
-/* S = blockdiag(U*) - sum_j W_j V*_j^{-1} W_j^T,  b_S = -g_c + sum_j W_j V*_j^{-1} g_p,j */
+/* S = blockdiag(U*) - sum_j W_j V*_j^{-1} W_j^T,  b_S = -g_c + sum_j W_j V*_j^{-1} g_p,j
+ *
+ * Each row a of S (and b_S[a]) is built by one thread, visiting the
+ * camera's observations by (point, input order) and each observed point's
+ * track in input order: the order in which a loop over the points,
+ * ascending, reaches the blocks of row a. */
 static int schur(orc_ctx *c, double lambda)
 {
     const int d = c->o.d, dd = d * d;
-    memset(c->S, 0, sizeof(double) * c->nnzb * dd);
+    int bad = 0;
+#pragma omp parallel for schedule(static) reduction(| : bad)
+    for (int32_t j = 0; j < c->np; ++j) {
+        double Vs[9];
+        memcpy(Vs, c->V + (size_t)j * 9, sizeof Vs);
+        for (int i = 0; i < 3; ++i)
+            Vs[i * 4] += lambda * clampd(Vs[i * 4], c->o.diag_min, c->o.diag_max);
+        const double det = inverse3(Vs, c->Vinv + (size_t)j * 9);
+        if (!(det > 0) || !isfinite(det)) bad = 1;
+    }
+    if (bad) return -1;
+#pragma omp parallel for schedule(dynamic, 4)
     for (int32_t a = 0; a < c->nc; ++a) {
+        memset(c->S + (size_t)c->S_ptr[a] * dd, 0, sizeof(double) * (c->S_ptr[a + 1] - c->S_ptr[a]) * dd);
         double *Saa = c->S + (size_t)c->S_ptr[a] * dd; /* the diagonal is a row's first block */
         const double *U = c->U + (size_t)a * dd;
         for (int i = 0; i < dd; ++i) Saa[i] = U[i];
         for (int i = 0; i < d; ++i)
             Saa[i * d + i] += lambda * clampd(U[i * d + i], c->o.diag_min, c->o.diag_max);
         for (int i = 0; i < d; ++i) c->bS[a * d + i] = -c->gc[a * d + i];
-    }
-    double *W = malloc(sizeof(double) * 16 * 3), *W2 = malloc(sizeof(double) * 16 * 3);
-    double Y[16 * 3];
-    for (int32_t j = 0; j < c->np; ++j) {
-        double Vs[9];
-        memcpy(Vs, c->V + (size_t)j * 9, sizeof Vs);
-        for (int i = 0; i < 3; ++i)
-            Vs[i * 4] += lambda * clampd(Vs[i * 4], c->o.diag_min, c->o.diag_max);
-        double *Vi = c->Vinv + (size_t)j * 9;
-        const double det = inverse3(Vs, Vi);
-        if (!(det > 0) || !isfinite(det)) {
-            free(W);
-            free(W2);
-            return -1;
-        }
-        const double *gp = c->gp + (size_t)j * 3;
-        for (int64_t x = c->pt_ptr[j]; x < c->pt_ptr[j + 1]; ++x) {
-            const int64_t k = c->pt_obs[x];
-            const int32_t a = c->cidx[k];
+        double W[16 * 3], W2[16 * 3], Y[16 * 3];
+        for (int64_t q = c->cam_ptr[a]; q < c->cam_ptr[a + 1]; ++q) {
+            const int64_t k = c->cam_obs_pt[q];
+            const int32_t j = c->pidx[k];
+            const double *Vi = c->Vinv + (size_t)j * 9;
+            const double *gp = c->gp + (size_t)j * 3;
             block_W(c, k, W);
             /* Y = W V*^{-1} */
             for (int i = 0; i < d; ++i)
@@ -556,25 +625,31 @@ static int schur(orc_ctx *c, double lambda)
             }
         }
     }
-    free(W);
-    free(W2);
     return 0;
 }
 
-/* y = S x using the stored upper block triangle and its transpose */
+/* y = S x using the stored upper block triangle and its transpose.  Output
+ * block a is summed by one thread: first S_ra^T x_r for the blocks (r, a),
+ * r < a, ascending r, then S_ab x_b along row a -- the order in which a loop
+ * over the rows, ascending, reaches y_a. */
 static void spmv(const orc_ctx *c, const double *x, double *y)
 {
     const int d = c->o.d, dd = d * d;
-    memset(y, 0, sizeof(double) * c->nc * d);
+#pragma omp parallel for schedule(dynamic, 16)
     for (int32_t a = 0; a < c->nc; ++a) {
+        double *ya = y + (size_t)a * d;
+        memset(ya, 0, sizeof(double) * d);
+        for (int64_t t = c->T_ptr[a]; t < c->T_ptr[a + 1]; ++t) {
+            const double *B = c->S + (size_t)c->T_blk[t] * dd;
+            const double *xr = x + (size_t)c->T_row[t] * d;
+            for (int i = 0; i < d; ++i)
+                for (int m = 0; m < d; ++m) ya[m] += B[i * d + m] * xr[i];
+        }
         for (int64_t e = c->S_ptr[a]; e < c->S_ptr[a + 1]; ++e) {
             const int32_t b = c->S_col[e];
             const double *B = c->S + (size_t)e * dd;
             for (int i = 0; i < d; ++i)
-                for (int m = 0; m < d; ++m) y[a * d + i] += B[i * d + m] * x[b * d + m];
-            if (b != a)
-                for (int i = 0; i < d; ++i)
-                    for (int m = 0; m < d; ++m) y[b * d + m] += B[i * d + m] * x[a * d + i];
+                for (int m = 0; m < d; ++m) ya[i] += B[i * d + m] * x[b * d + m];
         }
     }
 }
@@ -592,11 +667,14 @@ static int pcg(orc_ctx *c, double rtol, int32_t maxiter, orc_step_info *info)
     const int d = c->o.d, dd = d * d;
     const int64_t n = (int64_t)c->nc * d;
     double *L = malloc(sizeof(double) * c->nc * dd);
+    int bad = 0;
+#pragma omp parallel for schedule(static) reduction(| : bad)
     for (int32_t a = 0; a < c->nc; ++a)
-        if (cholesky(d, c->S + (size_t)c->S_ptr[a] * dd, L + (size_t)a * dd)) {
-            free(L);
-            return -1;
-        }
+        if (cholesky(d, c->S + (size_t)c->S_ptr[a] * dd, L + (size_t)a * dd)) bad = 1;
+    if (bad) {
+        free(L);
+        return -1;
+    }
     double *x = c->dc, *r = malloc(sizeof(double) * n), *z = malloc(sizeof(double) * n);
     double *p = malloc(sizeof(double) * n), *q = malloc(sizeof(double) * n);
     memset(x, 0, sizeof(double) * n);
@@ -605,6 +683,7 @@ static int pcg(orc_ctx *c, double rtol, int32_t maxiter, orc_step_info *info)
     int32_t it = 0, breakdown = 0;
     double rnorm = bnorm;
     if (bnorm > 0) {
+#pragma omp parallel for schedule(static)
         for (int32_t a = 0; a < c->nc; ++a) cholesky_solve(d, L + (size_t)a * dd, r + a * d, z + a * d);
         memcpy(p, z, sizeof(double) * n);
         double rz = dot(n, r, z);
@@ -616,6 +695,7 @@ static int pcg(orc_ctx *c, double rtol, int32_t maxiter, orc_step_info *info)
                 break;
             }
             const double alpha = rz / pq;
+#pragma omp parallel for schedule(static)
             for (int64_t i = 0; i < n; ++i) {
                 x[i] += alpha * p[i];
                 r[i] -= alpha * q[i];
@@ -623,11 +703,13 @@ static int pcg(orc_ctx *c, double rtol, int32_t maxiter, orc_step_info *info)
             it = k;
             rnorm = sqrt(dot(n, r, r));
             if (rnorm <= rtol * bnorm) break;
+#pragma omp parallel for schedule(static)
             for (int32_t a = 0; a < c->nc; ++a)
                 cholesky_solve(d, L + (size_t)a * dd, r + a * d, z + a * d);
             const double rz_new = dot(n, r, z);
             const double beta = rz_new / rz;
             rz = rz_new;
+#pragma omp parallel for schedule(static)
             for (int64_t i = 0; i < n; ++i) p[i] = z[i] + beta * p[i];
         }
     }
@@ -646,8 +728,9 @@ static int pcg(orc_ctx *c, double rtol, int32_t maxiter, orc_step_info *info)
 static void back_substitute(orc_ctx *c)
 {
     const int d = c->o.d;
-    double W[16 * 3];
+#pragma omp parallel for schedule(static)
     for (int32_t j = 0; j < c->np; ++j) {
+        double W[16 * 3];
         double t[3] = {-c->gp[j * 3], -c->gp[j * 3 + 1], -c->gp[j * 3 + 2]};
         for (int64_t x = c->pt_ptr[j]; x < c->pt_ptr[j + 1]; ++x) {
             const int64_t k = c->pt_obs[x];
@@ -663,11 +746,12 @@ static void back_substitute(orc_ctx *c)
 }
 
 /* pred = F - m(delta) for the Gauss-Newton model m(delta) = F + g^T delta + 1/2 |J delta|_W^2 */
-static double predicted_reduction(const orc_ctx *c)
+static double predicted_reduction(orc_ctx *c)
 {
     const int d = c->o.d;
     double lin = dot((int64_t)c->nc * d, c->gc, c->dc) + dot((int64_t)c->np * 3, c->gp, c->dp);
-    double quad = 0.0;
+    double *term = c->term;
+#pragma omp parallel for schedule(static)
     for (int64_t k = 0; k < c->no; ++k) {
         const double *Jc = c->Jc + (size_t)k * 2 * d, *Jp = c->Jp + (size_t)k * 6;
         const double *dc = c->dc + (size_t)c->cidx[k] * d, *dp = c->dp + (size_t)c->pidx[k] * 3;
@@ -677,8 +761,10 @@ static double predicted_reduction(const orc_ctx *c)
             for (int m = 0; m < d; ++m) e[i] += Jc[i * d + m] * dc[m];
             for (int m = 0; m < 3; ++m) e[i] += Jp[i * 3 + m] * dp[m];
         }
-        quad += c->w[k] * (e[0] * e[0] + e[1] * e[1]);
+        term[k] = c->w[k] * (e[0] * e[0] + e[1] * e[1]);
     }
+    double quad = 0.0;
+    for (int64_t k = 0; k < c->no; ++k) quad += term[k];
     return -lin - 0.5 * quad;
 }
 
@@ -709,6 +795,21 @@ int orc_compute_step(orc_ctx *c, double rtol, int32_t maxiter, orc_step_info *in
     return 0;
 }
 
+/* Trust-region update of the damping (Sec. V: TrustRegion(up=2, down=0.5**4)
+ * acting on the trust radius 1/lambda): a step whose actual reduction is
+ * more than 3/4 of the predicted one doubles the radius (lambda / 2, not
+ * below lambda_min); a rejected step, or a ratio of at most 1/4, shrinks it
+ * sixteen-fold (16 lambda, not above lambda_max); in between lambda stays.
+ * The 1/4 and 3/4 thresholds are this oracle's reading (the paper gives
+ * only the factors). */
+double orc_lambda_update(int accepted, double ratio, double lambda, double lambda_min,
+                         double lambda_max)
+{
+    if (!accepted || !(ratio > 0.25)) return fmin(16.0 * lambda, lambda_max);
+    if (ratio > 0.75) return fmax(0.5 * lambda, lambda_min);
+    return lambda;
+}
+
 /* One LM iteration (Alg. 1): step, candidate theta' = theta (+) delta, its
  * cost, acceptance and the trust-region update of lambda. */
 int orc_lm_step(orc_ctx *c, double rtol, int32_t maxiter, orc_step_info *info)
@@ -716,6 +817,7 @@ int orc_lm_step(orc_ctx *c, double rtol, int32_t maxiter, orc_step_info *info)
     int st = orc_compute_step(c, rtol, maxiter, info);
     if (st) return st;
     const int d = c->o.d;
+#pragma omp parallel for schedule(static)
     for (int32_t a = 0; a < c->nc; ++a) {
         if (c->fixed[a]) memcpy(c->cams_new + 10 * a, c->cams + 10 * a, sizeof(double) * 10);
         else orc_retract_camera(c->cams + 10 * a, c->dc + (size_t)a * d, d, c->cams_new + 10 * a);
@@ -726,8 +828,7 @@ int orc_lm_step(orc_ctx *c, double rtol, int32_t maxiter, orc_step_info *info)
     const double ratio = (c->F - Fn) / info->pred;
     const int accept = isfinite(Fn) && Fn < c->F && info->pred > 0;
     info->accepted = accept;
-    if (!accept || ratio <= 0.25) c->lambda = fmin(16.0 * c->lambda, c->o.lambda_max);
-    else if (ratio > 0.75) c->lambda = fmax(0.5 * c->lambda, c->o.lambda_min);
+    c->lambda = orc_lambda_update(accept, ratio, c->lambda, c->o.lambda_min, c->o.lambda_max);
     info->lambda_next = c->lambda;
     if (accept) {
         double *t = c->cams;
@@ -740,6 +841,55 @@ int orc_lm_step(orc_ctx *c, double rtol, int32_t maxiter, orc_step_info *info)
     }
     return 0;
 }
+
+/* Repeated LM iterations with the stopping rules of Sec. V (StopOnPlateau):
+ * after each iteration, in this order,
+ *   - a rejected step whose damping was lambda_max already: stop, -4 ("not
+ *     converged", reason 4);
+ *   - plateau_steps consecutive iterations whose relative decrease
+ *     (F - F') / F is below rel_tol (a rejected step decreases by 0): stop,
+ *     reason 2;
+ *   - |g|_inf <= 1e-12 (1 + F) at the iteration's linearisation point: stop,
+ *     reason 3;
+ *   - max_iters iterations: stop, reason 1.
+ * infos (max_iters entries, may be NULL) receive each iteration's report;
+ * *done the number of iterations run, *reason the rule that stopped. */
+int orc_solve(orc_ctx *c, int32_t max_iters, double rel_tol, int32_t plateau_steps, double rtol,
+              int32_t maxiter, orc_step_info *infos, int32_t *done, int32_t *reason)
+{
+    int32_t n = 0, flat = 0, why = 0;
+    int ret = 0;
+    for (int32_t it = 0; it < max_iters && why == 0; ++it) {
+        orc_step_info info;
+        const int st = orc_lm_step(c, rtol, maxiter, &info);
+        if (infos) infos[it] = info;
+        if (st) {
+            ret = st;
+            why = 5;
+            break;
+        }
+        ++n;
+        const double dec = info.accepted ? (info.cost_before - info.cost_after) / info.cost_before : 0.0;
+        flat = dec < rel_tol ? flat + 1 : 0;
+        if (!info.accepted && info.lambda_used >= c->o.lambda_max) {
+            ret = -4;
+            why = 4;
+        } else if (flat >= plateau_steps) {
+            why = 2;
+        } else if (info.grad_inf <= 1e-12 * (1.0 + info.cost_before)) {
+            why = 3;
+        } else if (it + 1 == max_iters) {
+            why = 1;
+        }
+    }
+    if (done) *done = n;
+    if (reason) *reason = why;
+    return ret;
+}
+
+/* Number of threads of the parallel loops (n >= 1). */
+void orc_set_threads(int32_t n) { omp_set_num_threads(n > 0 ? n : 1); }
+int32_t orc_get_threads(void) { return omp_get_max_threads(); }
 
 /* ------------------------------------------------------------------------ */
 /* read-back of intermediate quantities (for parity tests)                   */

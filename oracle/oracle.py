@@ -19,10 +19,11 @@ _LIB_PATH = os.path.join(_HERE, "libba_oracle.so")
 
 
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (plain -O2, no fast-math, no FMA contraction)."""
+    """Compile the oracle with gcc (-O3 for the generic x86-64 target, OpenMP,
+    no fast-math, no FMA contraction: every sum keeps its written order)."""
     if force or not os.path.exists(_LIB_PATH):
         tmp = _LIB_PATH + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared",
+        subprocess.check_call(["gcc", "-O3", "-std=gnu99", "-fPIC", "-shared", "-fopenmp",
                                "-ffp-contract=off", "-Wall", "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
@@ -78,6 +79,15 @@ def lib():
         L.orc_obs_second_order.argtypes = [P, C.c_int64, P, P, P]
         L.orc_backward.argtypes = [P, P, P, P, P, P, P]
         L.orc_backward.restype = C.c_int
+        L.orc_lambda_update.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double, C.c_double]
+        L.orc_lambda_update.restype = C.c_double
+        L.orc_solve.argtypes = [P, C.c_int32, C.c_double, C.c_int32, C.c_double, C.c_int32,
+                                C.POINTER(StepInfo), C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+        L.orc_solve.restype = C.c_int
+        L.orc_set_threads.argtypes = [C.c_int32]
+        L.orc_set_threads.restype = None
+        L.orc_get_threads.argtypes = []
+        L.orc_get_threads.restype = C.c_int32
         _lib = L
     return _lib
 
@@ -103,6 +113,24 @@ def retract_camera(cam, delta, d: int = 9):
     out = np.zeros(10)
     lib().orc_retract_camera(_p(cam), _p(delta), d, _p(out))
     return out
+
+
+def lambda_update(accepted: bool, ratio: float, lam: float, lam_min: float = 1e-12,
+                  lam_max: float = 1e12) -> float:
+    """The oracle's trust-region damping rule for one step."""
+    return lib().orc_lambda_update(1 if accepted else 0, ratio, lam, lam_min, lam_max)
+
+
+def set_threads(n: int):
+    """Threads of the oracle's parallel loops (results do not depend on it)."""
+    lib().orc_set_threads(int(n))
+
+
+def get_threads() -> int:
+    return int(lib().orc_get_threads())
+
+
+STOP_NAMES = {0: "none", 1: "max_iters", 2: "plateau", 3: "gradient", 4: "lambda_max", 5: "error"}
 
 
 @dataclass
@@ -193,6 +221,18 @@ class Oracle:
         info = StepInfo()
         lib().orc_lm_step(self._h, rtol, maxiter, C.byref(info))
         return info.as_dict()
+
+    def solve(self, max_iters: int, rel_tol: float = 1e-6, plateau_steps: int = 5,
+              rtol: float = -1.0, maxiter: int = -1):
+        """LM iterations with the stopping rules of Sec. V; returns
+        (status, infos, stop reason name)."""
+        infos = (StepInfo * max(1, max_iters))()
+        done = C.c_int32()
+        why = C.c_int32()
+        st = lib().orc_solve(self._h, max_iters, rel_tol, plateau_steps, rtol, maxiter, infos,
+                             C.byref(done), C.byref(why))
+        n = done.value + (1 if why.value == 5 else 0)
+        return st, [infos[i].as_dict() for i in range(n)], STOP_NAMES[why.value]
 
     def linearization(self):
         r = np.zeros((self.no, 2))

@@ -376,3 +376,127 @@ def test_zero_gradient_gives_zero_step():
     dc, dp, _ = o.step()
     assert info["grad_inf"] < 1e-8
     assert np.abs(dc).max() < 1e-10 and np.abs(dp).max() < 1e-10
+
+
+# --------------------------------------------------------------------------
+# trust-region damping and the stopping rules (Sec. V: TrustRegion(up=2,
+# down=0.5**4), StopOnPlateau)
+# --------------------------------------------------------------------------
+
+# (accepted, ratio, lambda) -> lambda after the step.  The factors are the
+# paper's: the trust radius 1/lambda grows by up = 2 (lambda halves) and
+# shrinks by down = 1/16 (lambda x 16); the thresholds 1/4 and 3/4 on the
+# ratio of actual to predicted reduction, the lower branch taking the tie at
+# exactly 1/4 and a rejection counting as a shrink, are the reading the
+# oracle takes where the paper gives no values.
+LAMBDA_TABLE = [
+    (True, 0.10, 1e-3, 1.6e-2),
+    (True, 0.25, 1e-3, 1.6e-2),
+    (True, 0.50, 1e-3, 1e-3),
+    (True, 0.75, 1e-3, 1e-3),
+    (True, 0.80, 1e-3, 5e-4),
+    (True, 1.70, 4.0, 2.0),
+    (False, 0.90, 1e-3, 1.6e-2),
+    (False, -3.0, 2.0, 32.0),
+    (True, 0.90, 1.5e-12, 1e-12),   # halving clamped at lambda_min
+    (False, 0.90, 1e11, 1e12),      # growth clamped at lambda_max
+    (True, 0.10, 1e12, 1e12),
+]
+
+
+@pytest.mark.parametrize("accepted,ratio,lam,expect", LAMBDA_TABLE)
+def test_trust_region_damping_rule(accepted, ratio, lam, expect):
+    got = O.lambda_update(accepted, ratio, lam, 1e-12, 1e12)
+    assert got == pytest.approx(expect, rel=1e-15)
+
+
+def test_lm_damping_follows_the_rule_on_accepted_and_rejected_steps():
+    """Every step of an LM run moves lambda by the factor the table above
+    fixes for its own ratio of actual to predicted reduction; the run must
+    visit all three branches (halve, keep, x16)."""
+    s = make_scene(0, seed=1)
+    o = O.Oracle.from_scene(s)
+    o.lam = 1e-9
+    seen = set()
+    for _ in range(40):
+        info = o.lm_step()
+        lam, nxt = info["lambda_used"], info["lambda_next"]
+        ratio = (info["cost_before"] - info["cost_after"]) / info["pred"]
+        if not info["accepted"] or ratio <= 0.25:
+            assert nxt == min(16 * lam, 1e12)
+            seen.add("x16")
+        elif ratio > 0.75:
+            assert nxt == max(lam / 2, 1e-12)
+            seen.add("half")
+        else:
+            assert nxt == lam
+            seen.add("keep")
+    assert {"x16", "half"} <= seen
+
+
+def test_solve_stops_at_the_first_plateau_of_five_flat_steps():
+    s = make_scene(0, seed=6)
+    o = O.Oracle.from_scene(s)
+    st, infos, why = o.solve(60, rel_tol=1e-6, plateau_steps=5)
+    assert st == 0 and why in ("plateau", "gradient")
+    dec = [(i["cost_before"] - i["cost_after"]) / i["cost_before"] if i["accepted"] else 0.0
+           for i in infos]
+    flat = [d < 1e-6 for d in dec]
+    runs = 0
+    for n, f in enumerate(flat):
+        runs = runs + 1 if f else 0
+        g_ok = infos[n]["grad_inf"] <= 1e-12 * (1 + infos[n]["cost_before"])
+        if runs >= 5 or g_ok:
+            assert n == len(infos) - 1, "solve ran past a stopping rule"
+            assert why == ("plateau" if runs >= 5 else "gradient")
+            break
+    else:
+        pytest.fail("no stopping rule held at the last iteration")
+    assert all(i["cost_after"] < i["cost_before"] for i in infos if i["accepted"])
+
+
+def test_solve_noise_free_scene_converges_then_stops():
+    """Noise-free observations: the solve reaches the zero-cost optimum (up to
+    round-off) and then stops by a rule, not by the iteration cap."""
+    s = make_scene(0, noise_px=0.0)
+    o = O.Oracle.from_scene(s)
+    st, infos, why = o.solve(60, rel_tol=1e-6, plateau_steps=5)
+    assert st == 0 and why in ("plateau", "gradient") and len(infos) < 60
+    assert o.cost() <= 1e-20 * s.n_obs
+
+
+def test_solve_iteration_cap():
+    s = make_scene(0, seed=7)
+    o = O.Oracle.from_scene(s)
+    st, infos, why = o.solve(3, rel_tol=1e-6, plateau_steps=5)
+    assert st == 0 and why == "max_iters" and len(infos) == 3
+
+
+def test_solve_reports_rejection_at_lambda_max():
+    """Noise-free scene with lambda capped at its start value: once the
+    optimum is reached, round-off rejections grow lambda to the cap, and the
+    first rejection there ends the solve as not converged, leaving theta as
+    it was before that step."""
+    s = make_scene(0, noise_px=0.0)
+    opt = O.OracleOptions(lambda0=1e-4, lambda_min=1e-12, lambda_max=1e-4)
+    o = O.Oracle.from_scene(s, options=opt)
+    st, infos, why = o.solve(60, rel_tol=0.0, plateau_steps=5)
+    assert why == "lambda_max" and st == -4
+    assert not infos[-1]["accepted"] and infos[-1]["lambda_used"] == 1e-4
+    assert all(i["lambda_used"] <= 1e-4 for i in infos)
+    assert all(i["accepted"] or i["lambda_used"] < 1e-4 for i in infos[:-1])
+    assert o.cost() == infos[-1]["cost_before"]
+
+
+def test_thread_count_does_not_change_results():
+    s = make_scene(3, n_cams=24, n_pts=600)
+    out = []
+    for n in (1, 3, 8):
+        O.set_threads(n)
+        o = O.Oracle.from_scene(s)
+        infos = [o.lm_step() for _ in range(3)]
+        out.append((infos, o.get_params()))
+    O.set_threads(os.cpu_count() or 1)
+    for infos, (c, p) in out[1:]:
+        assert infos == out[0][0]
+        assert np.array_equal(c, out[0][1][0]) and np.array_equal(p, out[0][1][1])
