@@ -33,6 +33,8 @@
  *   LM control    accept iff F' < F, F' finite, pred > 0;
  *                 ratio > 0.75 -> lambda/2; ratio <= 0.25 or reject -> 16 lambda.
  *   PCG           x0 = 0, relative tolerance on the recursively updated residual.
+ *   direct solve  the paper's Cholesky alternative (Sec. IV-C-1) applied to the
+ *                 reduced camera system, assembled dense: S = L L^T.
  *   stopping      orc_solve: lambda_max rejection, plateau of relative decrease,
  *                 gradient norm, iteration cap (Sec. V, StopOnPlateau).
  *
@@ -55,6 +57,8 @@ typedef struct {
     int32_t cg_maxiter;
     double lambda0, lambda_min, lambda_max;
     double diag_min, diag_max;
+    int32_t solver;       /* 0: block-Jacobi PCG; 1: dense Cholesky of the
+                             reduced camera system (Sec. IV-C-1) */
 } orc_options;
 
 typedef struct {
@@ -776,6 +780,42 @@ static double grad_inf(const orc_ctx *c)
     return g;
 }
 
+static int dense_spd_solve(int n, const double *A, const double *b, double *x);
+
+/* The reduced camera system solved by factorisation instead of PCG (the
+ * paper's Cholesky alternative, Sec. IV-C-1): S assembled dense from its
+ * upper blocks and their transposes, S = L L^T, then L y = b_S and
+ * L^T dc = y.  Reports |b_S - S dc| / |b_S| as the relative residual. */
+static int dense_step(orc_ctx *c, orc_step_info *info)
+{
+    const int d = c->o.d, dd = d * d;
+    const int64_t n = (int64_t)c->nc * d;
+    double *A = xcalloc((size_t)(n * n), sizeof(double));
+    for (int32_t a = 0; a < c->nc; ++a)
+        for (int64_t e = c->S_ptr[a]; e < c->S_ptr[a + 1]; ++e) {
+            const int32_t b = c->S_col[e];
+            const double *B = c->S + (size_t)e * dd;
+            for (int i = 0; i < d; ++i)
+                for (int m = 0; m < d; ++m) {
+                    A[(size_t)(a * d + i) * n + b * d + m] = B[i * d + m];
+                    A[(size_t)(b * d + m) * n + a * d + i] = B[i * d + m];
+                }
+        }
+    const int st = dense_spd_solve((int)n, A, c->bS, c->dc);
+    double rr = 0.0, bb = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        double s = c->bS[i];
+        for (int64_t q = 0; q < n; ++q) s -= A[(size_t)(i * n + q)] * c->dc[q];
+        rr += s * s;
+        bb += c->bS[i] * c->bS[i];
+    }
+    info->cg_iters = 0;
+    info->cg_breakdown = 0;
+    info->cg_rel_resid = bb > 0 ? sqrt(rr / bb) : 0.0;
+    free(A);
+    return st;
+}
+
 /* The step of one LM iteration at the current lambda, without accepting it:
  * linearise (if needed), damp, reduce onto the cameras, PCG, back-substitute,
  * predicted reduction.  rtol < 0 / maxiter < 0 take the options' values. */
@@ -788,8 +828,11 @@ int orc_compute_step(orc_ctx *c, double rtol, int32_t maxiter, orc_step_info *in
     info->grad_inf = grad_inf(c);
     if (!isfinite(c->F)) return info->status = -2;
     if (schur(c, c->lambda)) return info->status = -2;
-    if (pcg(c, rtol < 0 ? c->o.cg_rtol : rtol, maxiter < 0 ? c->o.cg_maxiter : maxiter, info))
+    if (c->o.solver == 1) {
+        if (dense_step(c, info)) return info->status = -2;
+    } else if (pcg(c, rtol < 0 ? c->o.cg_rtol : rtol, maxiter < 0 ? c->o.cg_maxiter : maxiter, info)) {
         return info->status = -2;
+    }
     back_substitute(c);
     info->pred = predicted_reduction(c);
     return 0;

@@ -32,7 +32,8 @@ def build(force: bool = True) -> str:
 class Options(C.Structure):
     _fields_ = [("d", C.c_int32), ("huber_delta", C.c_double), ("cg_rtol", C.c_double),
                 ("cg_maxiter", C.c_int32), ("lambda0", C.c_double), ("lambda_min", C.c_double),
-                ("lambda_max", C.c_double), ("diag_min", C.c_double), ("diag_max", C.c_double)]
+                ("lambda_max", C.c_double), ("diag_min", C.c_double), ("diag_max", C.c_double),
+                ("solver", C.c_int32)]
 
 
 class StepInfo(C.Structure):
@@ -144,10 +145,12 @@ class OracleOptions:
     lambda_max: float = 1e12
     diag_min: float = 1e-6
     diag_max: float = 1e32
+    solver: int = 0   # 0 PCG, 1 dense Cholesky of the reduced camera system
 
     def c(self) -> Options:
         return Options(self.d, self.huber_delta, self.cg_rtol, self.cg_maxiter, self.lambda0,
-                       self.lambda_min, self.lambda_max, self.diag_min, self.diag_max)
+                       self.lambda_min, self.lambda_max, self.diag_min, self.diag_max,
+                       self.solver)
 
 
 class Oracle:

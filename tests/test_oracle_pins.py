@@ -235,6 +235,41 @@ def test_schur_pcg_step_matches_dense_solve(lam, fixed):
     assert abs(info["pred"] - pred) <= 1e-9 * abs(pred)
 
 
+@pytest.mark.parametrize("lam,fixed", [(1e-2, []), (1e-6, [0])])
+def test_cholesky_step_matches_dense_solve(lam, fixed):
+    """The direct solve (dense Cholesky of the reduced camera system) gives
+    the step of a LAPACK solve of the full damped normal equations built
+    from complex-step Jacobians, with no CG tolerance involved."""
+    s = _weighted_tiny(seed=2)
+    s.fixed_cams = np.array(fixed, np.int32)
+    o = O.Oracle.from_scene(s, options=O.OracleOptions(huber_delta=s.huber_delta, solver=1))
+    o.lam = lam
+    info = o.compute_step()
+    dc, dp, _ = o.step()
+    J, r, w, F = DR.dense_system(s.cams0, s.pts0, s.cam_idx, s.pt_idx, s.obs, s.obs_w,
+                                 s.huber_delta, fixed=fixed)
+    delta, A, g = DR.dense_step(J, r, w, lam)
+    got = np.concatenate([dc.reshape(-1), dp.reshape(-1)])
+    assert np.linalg.norm(got - delta) <= 1e-10 * np.linalg.norm(delta)
+    assert info["cg_iters"] == 0 and info["cg_rel_resid"] <= 1e-13
+    pred = -(g @ delta) - 0.5 * delta @ (A @ delta)
+    assert abs(info["pred"] - pred) <= 1e-9 * abs(pred)
+
+
+def test_cholesky_lm_run_matches_converged_pcg_run():
+    """Ten LM iterations with the direct solve follow those of a PCG run
+    converged to 1e-14 (the same steps up to round-off)."""
+    s = make_scene(0, seed=8)
+    a = O.Oracle.from_scene(s, options=O.OracleOptions(solver=1))
+    b = O.Oracle.from_scene(s, options=O.OracleOptions(cg_rtol=1e-14, cg_maxiter=2000))
+    for it in range(10):
+        ia, ib = a.lm_step(), b.lm_step()
+        assert abs(ia["cost_after"] - ib["cost_after"]) <= 1e-10 * ib["cost_after"], it
+        if abs(ib["cost_before"] - ib["cost_after"]) <= 1e-11 * ib["cost_before"]:
+            break
+        assert ia["accepted"] == ib["accepted"]
+
+
 def test_schur_blocks_match_dense_elimination():
     s = _weighted_tiny(seed=4)
     o = O.Oracle.from_scene(s)
