@@ -6,11 +6,13 @@ synthetic scene: residuals and Jacobian blocks, J^T J / J^T r assembly, Schur
 complement onto the cameras, block-Jacobi PCG, back-substitution, candidate
 cost and acceptance.  Inputs are resident in HBM before the timed region.
 
-Default workload: 1,000 cameras on a random-walk trajectory, 200,000 points
-with power-law tracks (about 1.0M observations), Huber loss (1 px), mixed
-precision (FP32 Jacobian / Schur storage, FP64 arithmetic and reductions),
-compared with plain FP64 on the same GPU.  Value = observations x LM
-iterations / second of the mixed form.  Prints one JSON line.
+Default workload: the largest single scene, 10,000 cameras in 10 laps of a
+circuit, 2,000,000 points (about 8.0M observations, banded co-visibility plus
+5% loop-closure observations), Huber loss (1 px), mixed precision (FP32
+Jacobian / Schur storage, FP64 arithmetic and reductions), compared with
+plain FP64 and, when trained parameters are present, with the learned
+preconditioner, on the same GPU.  Value = observations x LM iterations /
+second of the mixed form.  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -163,30 +165,87 @@ def continue_steps(prob, steps):
     return infos, times
 
 
+def cost_after(info):
+    return info["cost_after"] if info["accepted"] else info["cost_before"]
+
+
 def first_reaching(infos, times, target):
     t = 0.0
     for i, (inf, dt) in enumerate(zip(infos, times)):
         t += dt
-        F = inf["cost_after"] if inf["accepted"] else inf["cost_before"]
-        if F <= target:
+        if cost_after(inf) <= target:
             return i + 1, t
     return None, None
 
 
-def cpu_baseline(scene, budget_s):
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def host_cores() -> int:
+    """Cores this process may use: the affinity mask, capped by
+    OMP_NUM_THREADS when the environment sets the host's share."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    if env.isdigit() and int(env) > 0:
+        n = min(n, int(env))
+    return max(1, n)
+
+
+def cpu_baseline(scene, iters, single_iters, it_bytes_fn):
+    """The FP64 oracle on the host's cores: `iters` LM iterations of the
+    whole scene at all cores (also the FP64 reference cost after them), then
+    `single_iters` at one thread (bounded sample)."""
     from oracle import oracle as O
-    o = O.Oracle.from_scene(scene, options=O.OracleOptions(huber_delta=scene.huber_delta))
-    t0 = time.perf_counter()
-    n = 0
-    while True:
-        o.lm_step()
-        n += 1
+    nproc = host_cores()
+    out = {}
+    for threads, n in ((nproc, iters), (1, single_iters)):
+        if n <= 0:
+            continue
+        O.set_threads(threads)
+        o = O.Oracle.from_scene(scene, options=O.OracleOptions(huber_delta=scene.huber_delta))
+        t0 = time.perf_counter()
+        infos = []
+        for _ in range(n):
+            infos.append(o.lm_step())
         el = time.perf_counter() - t0
-        if el >= budget_s or n >= scene.lm_iters:
-            break
-    return {"value": scene.n_obs * n / el, "unit": "obs*LM-iters/s", "cores": 1, "kind": "oracle",
-            "sample": f"{n} LM iterations of the full scene from its initial state "
-                      f"({el:.1f} s, single-threaded FP64 C oracle)"}
+        cg = sum(i["cg_iters"] for i in infos) / n
+        out[threads] = dict(s=el, iters=n, cost=cost_after(infos[-1]), cg=cg,
+                            gbs=it_bytes_fn(cg) * n / el / 1e9)
+        log(f"[bench] oracle at {threads} threads: {n} LM iterations in {el:.1f} s "
+            f"(cost {out[threads]['cost']:.9e})")
+        del o
+    O.set_threads(nproc)
+    return out
+
+
+def learned_params_path():
+    return os.path.join(ROOT, "paper_2409_12190_amd", "data", "gnn_params.f32")
+
+
+def load_learned_params():
+    """Trained network parameters (raw float32, written by precond_train
+    --out), or None."""
+    import numpy as np
+    import torch
+    from paper_2409_12190_amd import ba as B
+    path = learned_params_path()
+    if not os.path.exists(path):
+        return None
+    v = np.fromfile(path, dtype=np.float32)
+    if v.size != B.gnn_num_params():
+        return None
+    return torch.from_numpy(v).cuda()
 
 
 def main():
@@ -194,10 +253,14 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="traj1000")
-    ap.add_argument("--cpu-budget", type=float, default=15.0,
-                    help="seconds of oracle work for the CPU baseline (0 disables it)")
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="laps10000")
+    ap.add_argument("--cpu-iters", type=int, default=-1,
+                    help="LM iterations of the oracle at all host cores (-1: the workload's "
+                         "reference iterations; 0 disables the CPU legs)")
+    ap.add_argument("--cpu-single-iters", type=int, default=1,
+                    help="LM iterations of the oracle at one thread (bounded sample)")
     ap.add_argument("--skip-fp64", action="store_true")
+    ap.add_argument("--skip-learned", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run only a plain 512 MiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -210,6 +273,7 @@ def main():
         copy_probe()
         return
 
+    import numpy as np
     import torch
 
     from paper_2409_12190_amd import ba as B
@@ -221,69 +285,74 @@ def main():
     scene = make_scene(cfg)
     log(f"[bench] n_cams={scene.n_cams} n_pts={scene.n_pts} n_obs={scene.n_obs}")
     ref_iters = scene.lm_iters
+    K = args.steps
 
+    learned = None if args.skip_learned else load_learned_params()
+    forms_todo = [("fp64", B.BA_FP64, False), ("mixed", B.BA_MIXED, False)]
+    if args.skip_fp64:
+        forms_todo = forms_todo[1:]
+    if learned is not None:
+        forms_todo.append(("learned", B.BA_MIXED, True))
     forms = {}
-    for name, prec in (("fp64", B.BA_FP64), ("mixed", B.BA_MIXED)):
-        if name == "fp64" and args.skip_fp64:
-            continue
+    for name, prec, use_net in forms_todo:
         t = time.perf_counter()
-        prob = B.Problem.from_scene(scene, precision=prec)
+        kw = dict(precond=B.BA_PRECOND_LEARNED) if use_net else {}
+        prob = B.Problem.from_scene(scene, precision=prec, **kw)
+        if use_net:
+            prob.set_gnn_params(learned)
         torch.cuda.synchronize()
         setup = time.perf_counter() - t
-        log(f"[bench] {name}: setup {setup:.2f} s (symbolic analysis + upload), nnzb={prob.nnzb}")
+        log(f"[bench] {name}: setup {setup:.2f} s (symbolic analysis + upload), nnzb={prob.nnzb}, "
+            f"plan {prob.plan}")
         if args.warmup:
             run_steps(prob, args.warmup, scene.cams0, scene.pts0, 1e-4)
         # timed run of K steps: events only around the PCG (the dominant
-        # kernel's live duration); the mixed form then runs on, untimed by
-        # events, until twice the reference iterations, so that its time to
-        # the FP64 reference cost is measured when it needs more iterations;
-        # then the same K steps again with every phase bracketed, for the
-        # per-phase breakdown
-        if name == "fp64":
-            steps = max(args.steps, ref_iters)
-        else:
-            steps = args.steps if args.skip_fp64 else max(args.steps, 2 * ref_iters)
+        # kernel's live duration); the run then continues untimed by events
+        # until twice the reference iterations, so that the time to the FP64
+        # reference cost is measured when a form needs more iterations; then
+        # the same K steps again with every phase bracketed (breakdown)
+        steps = max(K, ref_iters) if name == "fp64" else max(K, 2 * ref_iters)
         prob.set_profiling(True, phases=["pcg"])
-        infos, times, total = run_steps(prob, args.steps, scene.cams0, scene.pts0, 1e-4)
+        infos, times, total = run_steps(prob, K, scene.cams0, scene.pts0, 1e-4)
         timed_phases = prob.phase_times()
         prob.set_profiling(False)
-        if steps > args.steps:
-            more_infos, more_times = continue_steps(prob, steps - args.steps)
+        if steps > K:
+            more_infos, more_times = continue_steps(prob, steps - K)
             infos += more_infos
             times += more_times
         prob.set_profiling(True)
-        run_steps(prob, args.steps, scene.cams0, scene.pts0, 1e-4)
+        run_steps(prob, K, scene.cams0, scene.pts0, 1e-4)
         phases = prob.phase_times()
         phases["pcg"] = timed_phases["pcg"]
         prob.set_profiling(False)
-        k_time = sum(times[:args.steps])
-        log(f"[bench] {name}: {steps} steps, first {args.steps} in {k_time*1e3:.1f} ms, "
-            f"final cost {infos[-1]['cost_after']:.6f}")
+        k_time = sum(times[:K])
+        log(f"[bench] {name}: {steps} steps, first {K} in {k_time*1e3:.1f} ms, "
+            f"cost after {ref_iters}: {cost_after(infos[ref_iters - 1]):.9e}")
         forms[name] = dict(prob=prob, infos=infos, times=times, phases=phases, k_time=k_time,
-                           setup=setup)
+                           setup=setup, plan=prob.plan, nnzb=prob.nnzb)
 
     mixed = forms["mixed"]
-    K = args.steps
     value = scene.n_obs * K / mixed["k_time"]
     out = {
         "metric": METRIC, "value": value, "unit": "obs*LM-iters/s", "n_gpus": 1, "steps": K,
         "warmup": args.warmup, "ms_per_step": mixed["k_time"] / K * 1e3, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64 arithmetic, f32 storage of J and S",
         "data": "synthetic (seeded generator, structure of the workload; no dataset)",
         "config": {"workload": CONFIG_NAMES[cfg], "n_cams": scene.n_cams, "n_pts": scene.n_pts,
-                   "n_obs": scene.n_obs, "precision": "mixed (fp32 J/S storage, fp64 arithmetic)",
+                   "n_obs": scene.n_obs,
+                   "precision": "mixed (fp32 J/S storage, fp64 arithmetic, reductions and CG vectors)",
                    "loss": f"huber {scene.huber_delta}" if scene.huber_delta > 0 else "l2",
-                   "cg": "block-Jacobi PCG, rtol 1e-4, maxiter 250"},
+                   "cg": "block-Jacobi PCG (pipelined recurrence), rtol 1e-4, maxiter 250",
+                   "pcg_layout": mixed["plan"]["pcg_layout"]},
     }
     # per-phase breakdown and the dominant kernel's roofline
     es = 4
-    nnzb = mixed["prob"].nnzb
+    nnzb = mixed["nnzb"]
     cg_total = sum(i["cg_iters"] for i in mixed["infos"][:K])
     ph = {k: v for k, v in mixed["phases"].items() if v[1] > 0}
     out["phases_ms_per_step"] = {k: round(v[0] / K, 4) for k, v in ph.items()}
     dom = max(ph, key=lambda k: ph[k][0])
     ms, n = ph[dom]
-    import numpy as np
     t = np.bincount(scene.pt_idx, minlength=scene.n_pts).astype(np.int64)
     n_pairs = int((t * (t + 1) // 2).sum())   # (x, y) pairs with camera(x) <= camera(y)
     per_launch = kernel_bytes(dom, scene, nnzb, n_pairs, es, cg_total / max(n, 1))
@@ -293,7 +362,8 @@ def main():
                            "frac": achieved / HBM_PEAK_GBS,
                            "traffic": recorded_traffic(args.workload, dom),
                            "kernel": dom, "avg_launch_ms": ms / n, "launches": n,
-                           "algorithmic_bytes_per_launch": per_launch}
+                           "algorithmic_bytes_per_launch": per_launch,
+                           "cg_iters_per_launch": cg_total / max(n, 1)}
     out["phase_roofline"] = {}
     for k, (pms, pn) in ph.items():
         kb = kernel_bytes(k, scene, nnzb, n_pairs, es, cg_total / max(pn, 1))
@@ -307,25 +377,59 @@ def main():
                                  "frac": it_bytes / it_s / 1e9 / HBM_PEAK_GBS}
     out["cg_iters_per_step"] = cg_total / K
     out["nnzb"] = nnzb
-    out["final_cost_after_K"] = mixed["infos"][K - 1]["cost_after"]
+    out["forms"] = {}
+    for name, f in forms.items():
+        out["forms"][name] = {
+            "value": scene.n_obs * K / f["k_time"], "ms_per_step": f["k_time"] / K * 1e3,
+            "cg_iters_per_step": sum(i["cg_iters"] for i in f["infos"][:K]) / K,
+            "pcg_layout": f["plan"]["pcg_layout"],
+            "cost_after_ref_iters": cost_after(f["infos"][ref_iters - 1]),
+            "phases_ms_per_step": {k: round(v[0] / K, 4) for k, v in f["phases"].items() if v[1] > 0}}
+    if "learned" in forms:
+        used = [i["precond_used"] for i in forms["learned"]["infos"]]
+        out["forms"]["learned"]["steps_by_preconditioner"] = {
+            "learned": used.count(1), "fallback_block_jacobi": used.count(2), "block_jacobi": used.count(0)}
+        out["forms"]["learned"]["params"] = os.path.relpath(learned_params_path(), ROOT)
     if "fp64" in forms:
         f64 = forms["fp64"]
-        F_ref = min(i["cost_after"] if i["accepted"] else i["cost_before"]
-                    for i in f64["infos"][:ref_iters])
+        F_ref = min(cost_after(i) for i in f64["infos"][:ref_iters])
         target = F_ref * (1 + 1e-6)
-        it64, t64 = first_reaching(f64["infos"], f64["times"], target)
-        itm, tm = first_reaching(mixed["infos"], mixed["times"], target)
-        out["fp64"] = {"value": scene.n_obs * K / f64["k_time"], "ms_per_step": f64["k_time"] / K * 1e3,
-                       "phases_ms_per_step": {k: round(v[0] / K, 4)
-                                              for k, v in f64["phases"].items() if v[1] > 0}}
         out["reference_cost_fp64"] = F_ref
-        out["time_to_1e-6_rel_cost_s"] = {"fp64": t64, "mixed": tm, "fp64_iters": it64,
-                                          "mixed_iters": itm}
-        out["speedup_vs_fp64"] = (t64 / tm) if (t64 and tm) else None
+        tt = {}
+        for name, f in forms.items():
+            its, secs = first_reaching(f["infos"], f["times"], target)
+            tt[name] = {"s": secs, "iters": its}
+        out["time_to_1e-6_rel_cost"] = tt
+        t64 = tt["fp64"]["s"]
+        out["speedup_vs_fp64"] = {name: (t64 / tt[name]["s"]) if (t64 and tt[name]["s"]) else None
+                                  for name in forms if name != "fp64"}
         out["per_step_speedup_vs_fp64"] = f64["k_time"] / mixed["k_time"]
-    if args.cpu_budget > 0:
+    for f in forms.values():
+        f["prob"].close()
+    cpu_iters = ref_iters if args.cpu_iters < 0 else args.cpu_iters
+    if cpu_iters > 0:
         log("[bench] CPU baseline (oracle)")
-        out["cpu_baseline"] = cpu_baseline(scene, args.cpu_budget)
+        res = cpu_baseline(scene, cpu_iters, args.cpu_single_iters,
+                           lambda cg: iteration_bytes(scene, nnzb, 8, cg))
+        nproc = host_cores()
+        full = res[nproc]
+        out["cpu_baseline"] = {
+            "value": scene.n_obs * full["iters"] / full["s"], "unit": "obs*LM-iters/s", "cores": nproc,
+            "kind": "oracle",
+            "sample": f"{full['iters']} LM iterations of the whole scene from its initial state, FP64 "
+                      f"C oracle (OpenMP, results independent of the thread count), {full['s']:.1f} s",
+            "cpu_model": cpu_model(), "effective_GB/s": round(full["gbs"], 2)}
+        if 1 in res and nproc != 1:
+            one = res[1]
+            out["cpu_baseline"]["single_thread"] = {
+                "value": scene.n_obs * one["iters"] / one["s"], "cores": 1,
+                "sample": f"{one['iters']} LM iteration(s) from the initial state, {one['s']:.1f} s",
+                "effective_GB/s": round(one["gbs"], 2)}
+        if full["iters"] >= ref_iters:
+            F_o = full["cost"]
+            out["oracle_cost_after_ref_iters"] = F_o
+            out["final_cost_error_vs_oracle"] = {
+                name: abs(f["cost_after_ref_iters"] - F_o) / F_o for name, f in out["forms"].items()}
     print(json.dumps(out), flush=True)
 
 

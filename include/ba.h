@@ -21,7 +21,8 @@
  *    used by the paper's benchmark).  Points are 3 float64 in world frame.
  *  - Camera steps use the 9-dimensional tangent (rho, phi, df, dk1, dk2):
  *    T <- Exp(rho, phi) T on SE(3) (left update; the pose gradient space has 6
- *    degrees of freedom, Sec. III-C footnote), intrinsics additive.
+ *    degrees of freedom, Sec. III-C footnote), intrinsics additive.  With
+ *    cam_dof 6 the intrinsics are constants and the step is the pose part.
  *  - The library owns no device memory: the caller provides one device
  *    workspace (ba_problem_bind) and keeps it alive until destroy.  The
  *    library allocates only small pinned host staging buffers.
@@ -61,7 +62,9 @@ enum { BA_FP64 = 0, BA_MIXED = 1 };
  * the values the paper leaves open (initial damping, clamp range, lambda
  * bounds) are this library's choice. */
 typedef struct {
-  int32_t cam_dof;     /* camera tangent size; only 9 is supported */
+  int32_t cam_dof;     /* camera tangent size: 9 (pose + f, k1, k2), or 6 (pose
+                          only, intrinsics held at their set values; the
+                          9-wide exports then carry zeros in columns 6-8) */
   int32_t precision;   /* BA_FP64: every stored quantity FP64.
                           BA_MIXED: Jacobian blocks and the reduced camera
                           matrix stored FP32 (arithmetic stays FP64; costs,
@@ -85,7 +88,19 @@ typedef struct {
                               network (ba_set_gnn_params); until parameters are
                               set, and whenever its PCG misses cg_rtol, the step
                               uses plain block-Jacobi */
+  double adjoint_grad_tol; /* ba_backward requires a stationary theta:
+                              max_i |g_i| <= adjoint_grad_tol * max_k,i |w_k (J_k^T r_k)_i|
+                              (the gradient against the scale of its terms) */
+  int32_t linear_solver;   /* BA_SOLVER_PCG: block-Jacobi PCG on the reduced
+                              camera system (Sec. IV-C-2); BA_SOLVER_CHOLESKY:
+                              the paper's factorisation alternative (Sec.
+                              IV-C-1) on the same system, assembled dense in
+                              FP64 (at most 2048 cameras; the workspace grows
+                              by 8 (9 n_cams)^2 bytes); cg_* are then unused
+                              and cg_rel_resid reports |b - S x| / |b| */
 } ba_options;
+
+enum { BA_SOLVER_PCG = 0, BA_SOLVER_CHOLESKY = 1 };
 
 enum { BA_PRECOND_BLOCK_JACOBI = 0, BA_PRECOND_LEARNED = 1 };
 
@@ -106,11 +121,24 @@ typedef struct {
   int32_t status;       /* ba_status of the step */
   int32_t precond_used; /* 0 block-Jacobi, 1 learned, 2 learned then block-Jacobi
                            (the learned PCG missed cg_rtol) */
+  int32_t stop_reason;  /* ba_solve, on its last step: BA_STOP_* (BA_STOP_NONE on
+                           every other step and from ba_lm_step) */
 } ba_step_info;
+
+/* Why ba_solve stopped (ba_step_info.stop_reason of its last step). */
+enum {
+  BA_STOP_NONE = 0,
+  BA_STOP_MAX_ITERS = 1,   /* max_iters ran out before another rule held */
+  BA_STOP_PLATEAU = 2,     /* plateau_steps iterations with relative decrease < tol */
+  BA_STOP_GRADIENT = 3,    /* |g|_inf <= 1e-12 (1 + F) at the step's linearisation point */
+  BA_STOP_LAMBDA_MAX = 4,  /* a step was rejected at lambda_max (BA_ENOTCONV) */
+  BA_STOP_ERROR = 5        /* a step failed; its status is the return value */
+};
 
 /* Fills *opt with the defaults: cam_dof 9, BA_FP64, squared loss, cg_rtol 1e-4,
  * cg_maxiter 250, lambda0 1e-4, lambda in [1e-12, 1e12], clamp [1e-6, 1e32],
- * BA_CG_PIPELINED, backward disabled, adjoint_rtol 1e-10, block-Jacobi. */
+ * BA_CG_PIPELINED, backward disabled, adjoint_rtol 1e-10, block-Jacobi,
+ * adjoint_grad_tol 1e-6, BA_SOLVER_PCG. */
 void ba_default_options(ba_options* opt);
 
 /* Creates a problem from the observation pattern: observation k sees point
@@ -120,7 +148,8 @@ void ba_default_options(ba_options* opt);
  * Sec. IV-B-1): observation ordering, the block pattern of the reduced camera
  * matrix and the table of observation pairs that feed each block.  No device
  * work is done.  Errors: BA_EINVAL for sizes <= 0 or indices out of range,
- * BA_EUNSUPPORTED for cam_dof != 9 or a point seen more than 256 times. */
+ * BA_EUNSUPPORTED for cam_dof other than 9 or 6 (6 with the learned
+ * preconditioner or the adjoint) or a point seen more than 256 times. */
 ba_status ba_problem_create(const ba_options* opt, int32_t n_cams, int32_t n_pts, int64_t n_obs,
                             const int32_t* cam_idx, const int32_t* pt_idx, ba_problem** out);
 
@@ -166,11 +195,15 @@ ba_status ba_set_cg(ba_problem* p, double rtol, int32_t maxiter);
 ba_status ba_lm_step(ba_problem* p, ba_step_info* info);
 
 /* Repeats ba_lm_step until max_iters iterations, or plateau_steps consecutive
- * iterations with relative decrease (F - F')/F < rel_decrease_tol (Sec. V,
- * StopOnPlateau), or |g|_inf <= 1e-12 (1 + F).  infos: host array of
- * max_iters entries or NULL; *iters_done (host, may be NULL) receives the
+ * iterations with relative decrease (F - F')/F < rel_decrease_tol (a rejected
+ * step decreases by 0; Sec. V, StopOnPlateau), or |g|_inf <= 1e-12 (1 + F) at
+ * a step's linearisation point.  The rules are tested after every step in
+ * the order: rejection at lambda_max, plateau, gradient, max_iters.  infos:
+ * host array of max_iters entries or NULL; the last entry's stop_reason says
+ * which rule ended the solve.  *iters_done (host, may be NULL) receives the
  * number of iterations run.  Returns BA_ENOTCONV when a step is rejected at
- * lambda_max. */
+ * lambda_max (its damping was lambda_max already), or a failing step's
+ * status. */
 ba_status ba_solve(ba_problem* p, int32_t max_iters, double rel_decrease_tol, int32_t plateau_steps,
                    ba_step_info* infos, int32_t* iters_done);
 
@@ -191,14 +224,17 @@ ba_status ba_solve(ba_problem* p, int32_t max_iters, double rel_decrease_tol, in
  *   dL_dobs:  device float64 [n_obs][2] output, creation order;
  *   dL_dw:    device float64 [n_obs] output, or NULL;
  *   info:     host, may be NULL: cg_iters, cg_rel_resid, status.
- * theta must be a stationary point (run ba_solve first); squared loss only
+ * theta must be a stationary point (run ba_solve first): the gradient at
+ * theta is checked first (adjoint_grad_tol) and a non-stationary theta is
+ * refused with BA_ENOTCONV before anything is written.  Squared loss only
  * (huber_delta <= 0).  Overwrites the intermediate quantities of the last
  * ba_lm_step (ba_export then shows the adjoint's), and the next ba_lm_step
  * re-linearises.  Synchronises the stream.  Errors: BA_ESTATE (not bound /
  * enable_backward not set at creation), BA_EUNSUPPORTED (Huber loss),
- * BA_EINVAL (null pointer), BA_ENUMERIC (H not positive definite on a point
- * or camera block: not at a minimum), BA_ENOTCONV (the PCG did not reach
- * adjoint_rtol; outputs written), BA_EHIP. */
+ * BA_EINVAL (null pointer), BA_ENOTCONV (theta not stationary: nothing
+ * written; or the PCG did not reach adjoint_rtol: outputs written),
+ * BA_ENUMERIC (H not positive definite on a point or camera block: not at a
+ * minimum), BA_EHIP. */
 ba_status ba_backward(ba_problem* p, const double* dL_dcams, const double* dL_dpts, double* dL_dobs,
                       double* dL_dw, ba_step_info* info);
 
@@ -243,9 +279,10 @@ ba_status ba_graph_build(ba_graph* g, ba_problem* p);
  * graph's stream. */
 ba_status ba_gnn_loss_grad(ba_graph* g, const float* params, float* grad, double* loss);
 /* One Adam step on device float32 vectors of n values (m, v: moments; step
- * counts from 1), on the given stream. */
+ * counts from 1) with the gradient grad_scale * grad (e.g. 1 / number of
+ * summed systems: the mean over a batch), on the given stream. */
 ba_status ba_gnn_adam(int64_t n, float* params, const float* grad, float* m, float* v, int32_t step,
-                      float lr, float beta1, float beta2, float eps, void* hip_stream);
+                      float lr, float beta1, float beta2, float eps, float grad_scale, void* hip_stream);
 void ba_graph_destroy(ba_graph* g);
 
 /* Host snapshot of (theta, lambda) for checkpoint / resume.  With host_blob ==
@@ -270,11 +307,16 @@ ba_status ba_set_state(ba_problem* p, const void* host_blob, size_t bytes);
  *                  adjoint vector v of the last ba_backward
  *   BA_X_PRECOND   float64 [n_cams][9][9] the preconditioner blocks of the
  *                  last step (learned blocks when the network ran)
+ *   BA_X_PLAN      int64 [4] how the problem runs: the PCG layout (0 block
+ *                  values held in registers, 1 stored blocks read per
+ *                  (row, block) item, 2 upper blocks streamed once per
+ *                  product), its workgroups, the Schur pair count and the
+ *                  Schur workgroups (no device work)
  * bytes must equal the field's size.  Synchronises the stream. */
 enum {
   BA_X_RESIDUAL = 1, BA_X_WEIGHT, BA_X_JC, BA_X_JP, BA_X_COST, BA_X_GRAD_C, BA_X_GRAD_P,
   BA_X_V, BA_X_S_PTR, BA_X_S_COL, BA_X_S, BA_X_BS, BA_X_DC, BA_X_DP, BA_X_ADJ_VC, BA_X_ADJ_VP,
-  BA_X_PRECOND
+  BA_X_PRECOND, BA_X_PLAN
 };
 ba_status ba_export(const ba_problem* p, int32_t field, void* host_dst, size_t bytes);
 

@@ -114,15 +114,29 @@ def system_graph(S_ptr, S_col, S_blocks, nc):
     return {"nc": nc, "L": L, "Linv": Linv, "E": E, "X": X, "P": P, "diag": diag}
 
 
-def forward(theta, g):
+def bf16(a):
+    """Rounding to bfloat16 (8 significant bits) by its definition: the value
+    as float32, the low 16 bits of its encoding dropped with round-to-nearest,
+    ties to even; returned as float64."""
+    f = np.asarray(a, np.float64).astype(np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def forward(theta, g, bf16_inference=False):
+    """Node outputs o and the activations.  bf16_inference: the input and
+    message layers take their operands (inputs, weights) rounded to bfloat16,
+    as the matrix-core inference does; sums and biases stay exact here."""
     p = unpack(theta)
     X, P = g["X"], g["P"]
-    z0 = X @ p["W_in"].T + p["b_in"]
+    q = bf16 if bf16_inference else (lambda v: v)
+    z0 = q(X) @ q(p["W_in"]).T + p["b_in"]
     h = np.maximum(z0, 0.0)
     cache = {"z": [z0], "h": [h], "m": []}
     for l in range(LAYERS):
         m = P @ h
-        z = h @ p[f"W_s{l}"].T + m @ p[f"W_m{l}"].T + p[f"b{l}"]
+        z = q(h) @ q(p[f"W_s{l}"]).T + q(m) @ q(p[f"W_m{l}"]).T + p[f"b{l}"]
         h = np.maximum(z, 0.0)
         cache["m"].append(m)
         cache["z"].append(z)
@@ -188,9 +202,9 @@ def grad(theta, g):
     return pack(gr)
 
 
-def precond_blocks(theta, g):
+def precond_blocks(theta, g, bf16_inference=False):
     """M_i = L_i^-T C_i C_i^T L_i^-1 for every camera."""
-    o, _ = forward(theta, g)
+    o, _ = forward(theta, g, bf16_inference)
     C = C_from_o(o)
     Li = g["Linv"]
     return np.transpose(Li, (0, 2, 1)) @ C @ np.transpose(C, (0, 2, 1)) @ Li

@@ -9,6 +9,7 @@ from __future__ import annotations
 
 import ctypes as C
 import os
+import weakref
 from typing import Optional
 
 import numpy as np
@@ -21,8 +22,12 @@ BA_FP64, BA_MIXED = 0, 1
 BA_CG_PIPELINED, BA_CG_STANDARD = 0, 1
 (BA_X_RESIDUAL, BA_X_WEIGHT, BA_X_JC, BA_X_JP, BA_X_COST, BA_X_GRAD_C, BA_X_GRAD_P, BA_X_V,
  BA_X_S_PTR, BA_X_S_COL, BA_X_S, BA_X_BS, BA_X_DC, BA_X_DP, BA_X_ADJ_VC, BA_X_ADJ_VP,
- BA_X_PRECOND) = range(1, 18)
+ BA_X_PRECOND, BA_X_PLAN) = range(1, 19)
+PCG_LAYOUTS = {0: "resident", 1: "per_item", 2: "streamed"}
 BA_PRECOND_BLOCK_JACOBI, BA_PRECOND_LEARNED = 0, 1
+BA_SOLVER_PCG, BA_SOLVER_CHOLESKY = 0, 1
+(BA_STOP_NONE, BA_STOP_MAX_ITERS, BA_STOP_PLATEAU, BA_STOP_GRADIENT, BA_STOP_LAMBDA_MAX,
+ BA_STOP_ERROR) = range(6)
 BA_GNN_FEATURES, BA_GNN_HIDDEN, BA_GNN_OUTPUTS, BA_GNN_LAYERS = 47, 64, 45, 3
 
 EXPORTED_SYMBOLS = [
@@ -51,7 +56,8 @@ class ba_options(C.Structure):
                 ("cg_rtol", C.c_double), ("cg_maxiter", C.c_int32), ("lambda0", C.c_double),
                 ("lambda_min", C.c_double), ("lambda_max", C.c_double), ("diag_min", C.c_double),
                 ("diag_max", C.c_double), ("cg_variant", C.c_int32), ("enable_backward", C.c_int32),
-                ("adjoint_rtol", C.c_double), ("precond", C.c_int32)]
+                ("adjoint_rtol", C.c_double), ("precond", C.c_int32),
+                ("adjoint_grad_tol", C.c_double), ("linear_solver", C.c_int32)]
 
 
 class ba_step_info(C.Structure):
@@ -59,7 +65,7 @@ class ba_step_info(C.Structure):
                 ("lambda_used", C.c_double), ("lambda_next", C.c_double),
                 ("cg_rel_resid", C.c_double), ("pred", C.c_double), ("grad_inf", C.c_double),
                 ("accepted", C.c_int32), ("cg_iters", C.c_int32), ("cg_breakdown", C.c_int32),
-                ("status", C.c_int32), ("precond_used", C.c_int32)]
+                ("status", C.c_int32), ("precond_used", C.c_int32), ("stop_reason", C.c_int32)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -111,7 +117,7 @@ def lib():
         L.ba_graph_build.argtypes = [P, P]
         L.ba_gnn_loss_grad.argtypes = [P, P, P, C.POINTER(C.c_double)]
         L.ba_gnn_adam.argtypes = [C.c_int64, P, P, P, P, C.c_int32, C.c_float, C.c_float, C.c_float,
-                                  C.c_float, P]
+                                  C.c_float, C.c_float, P]
         L.ba_graph_destroy.argtypes = [P]
         L.ba_graph_destroy.restype = None
         L.ba_last_error.argtypes = []
@@ -267,6 +273,21 @@ def ba_problem_destroy(h: int):
 
 # ---- convenience wrapper holding the torch-owned memory -----------------------
 
+def _release(destroy, handle, stream, workspace):
+    """Finalizer of a Problem or Graph: waits for the handle's stream, then
+    destroys the handle, while the HIP runtime and this module are still
+    alive (weakref.finalize runs leftover finalizers at interpreter exit,
+    before module globals are cleared).  The workspace tensor is held until
+    the handle is gone, since queued kernels may still use it."""
+    if stream is not None:
+        try:
+            stream.synchronize()
+        except Exception:
+            pass
+    destroy(handle)
+    del workspace
+
+
 class Problem:
     """One bundle-adjustment problem on the current CUDA (HIP) device.
 
@@ -277,7 +298,9 @@ class Problem:
     def __init__(self, n_cams, n_pts, cam_idx, pt_idx, obs_xy, obs_w=None, *, precision=BA_FP64,
                  huber_delta=0.0, cg_rtol=1e-4, cg_maxiter=250, lambda0=1e-4, fixed_cams=None,
                  cams=None, pts=None, stream=None, cg_variant=BA_CG_PIPELINED,
-                 enable_backward=False, adjoint_rtol=1e-10, precond=BA_PRECOND_BLOCK_JACOBI):
+                 enable_backward=False, adjoint_rtol=1e-10, precond=BA_PRECOND_BLOCK_JACOBI,
+                 lambda_min=None, lambda_max=None, adjoint_grad_tol=None, cam_dof=9,
+                 linear_solver=BA_SOLVER_PCG):
         import torch
         self.torch = torch
         self.device = torch.device("cuda", torch.cuda.current_device())
@@ -291,16 +314,28 @@ class Problem:
         opt.enable_backward = 1 if enable_backward else 0
         opt.adjoint_rtol = adjoint_rtol
         opt.precond = precond
+        opt.cam_dof = cam_dof
+        opt.linear_solver = linear_solver
+        if lambda_min is not None:
+            opt.lambda_min = lambda_min
+        if lambda_max is not None:
+            opt.lambda_max = lambda_max
+        if adjoint_grad_tol is not None:
+            opt.adjoint_grad_tol = adjoint_grad_tol
         self.opt = opt
         self.n_cams, self.n_pts = int(n_cams), int(n_pts)
         self.n_obs = int(np.asarray(cam_idx).size)
         self.h = ba_problem_create(opt, self.n_cams, self.n_pts, cam_idx, pt_idx)
+        self._finalizer = weakref.finalize(self, _release, lib().ba_problem_destroy, self.h, None, None)
         nbytes = ba_problem_workspace_bytes(self.h)
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         if self.workspace.data_ptr() % 256:
             raise RuntimeError("workspace allocation is not 256-byte aligned")
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         ba_problem_bind(self.h, self.workspace.data_ptr(), nbytes, self.stream.cuda_stream)
+        self._finalizer.detach()
+        self._finalizer = weakref.finalize(self, _release, lib().ba_problem_destroy, self.h,
+                                           self.stream, self.workspace)
         self.set_observations(obs_xy, obs_w)
         if fixed_cams is not None and len(fixed_cams):
             mask = np.zeros(self.n_cams, np.uint8)
@@ -322,15 +357,22 @@ class Problem:
             return a.to(self.device, t.float64).contiguous()
         return t.as_tensor(np.ascontiguousarray(a, np.float64), device=self.device)
 
-    def __del__(self):
-        h = getattr(self, "h", None)
-        if h:
-            try:
-                self.stream.synchronize()
-            except Exception:
-                pass
-            ba_problem_destroy(h)
-            self.h = None
+    def close(self):
+        """Releases the library handle (its pinned staging buffers and timing
+        events) after the stream has drained; the workspace tensor is
+        dropped with it.  Idempotent; also runs at interpreter exit, before
+        module teardown, for problems still alive then."""
+        fin = getattr(self, "_finalizer", None)
+        if fin is not None:
+            fin()
+        self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+        return False
 
     def set_observations(self, obs_xy, obs_w=None):
         xy = self._dev(obs_xy).reshape(self.n_obs, 2)
@@ -416,6 +458,13 @@ class Problem:
     def set_state(self, blob: bytes):
         ba_set_state(self.h, blob)
 
+    @property
+    def plan(self) -> dict:
+        """How the problem runs: PCG layout and grid, Schur pairs and workgroups."""
+        v = self.export(BA_X_PLAN)
+        return {"pcg_layout": PCG_LAYOUTS[int(v[0])], "pcg_grid": int(v[1]), "pairs": int(v[2]),
+                "schur_workgroups": int(v[3])}
+
     def export(self, field: int) -> np.ndarray:
         no, nc, np_, nz = self.n_obs, self.n_cams, self.n_pts, self.nnzb
         shapes = {BA_X_RESIDUAL: ((no, 2), np.float64), BA_X_WEIGHT: ((no,), np.float64),
@@ -426,7 +475,7 @@ class Problem:
                   BA_X_S: ((nz, 9, 9), np.float64), BA_X_BS: ((nc, 9), np.float64),
                   BA_X_DC: ((nc, 9), np.float64), BA_X_DP: ((np_, 3), np.float64),
                   BA_X_ADJ_VC: ((nc, 9), np.float64), BA_X_ADJ_VP: ((np_, 3), np.float64),
-                  BA_X_PRECOND: ((nc, 9, 9), np.float64)}
+                  BA_X_PRECOND: ((nc, 9, 9), np.float64), BA_X_PLAN: ((4,), np.int64)}
         shape, dt = shapes[field]
         return ba_export(self.h, field, np.zeros(shape, dt))
 
@@ -448,11 +497,15 @@ class Graph:
         h = C.c_void_p()
         _check(lib().ba_graph_create(problem.h, C.byref(h)))
         self.h = h.value
+        self._finalizer = weakref.finalize(self, _release, lib().ba_graph_destroy, self.h, None, None)
         n = C.c_size_t()
         _check(lib().ba_graph_workspace_bytes(self.h, C.byref(n)))
         self.workspace = torch.empty(n.value, dtype=torch.uint8, device=problem.device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(problem.device)
         _check(lib().ba_graph_bind(self.h, self.workspace.data_ptr(), n.value, self.stream.cuda_stream))
+        self._finalizer.detach()
+        self._finalizer = weakref.finalize(self, _release, lib().ba_graph_destroy, self.h,
+                                           self.stream, self.workspace)
         self.build(problem)
 
     def build(self, problem: Problem):
@@ -465,19 +518,28 @@ class Graph:
         _check(lib().ba_gnn_loss_grad(self.h, params.data_ptr(), grad.data_ptr(), C.byref(loss)))
         return loss.value
 
-    def __del__(self):
-        h = getattr(self, "h", None)
-        if h:
-            lib().ba_graph_destroy(h)
-            self.h = None
+    def close(self):
+        """Releases the graph handle (idempotent; also runs at interpreter
+        exit for graphs still alive then)."""
+        fin = getattr(self, "_finalizer", None)
+        if fin is not None:
+            fin()
+        self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+        return False
 
 
 def gnn_adam(params, grad, m, v, step: int, lr: float = 1e-3, beta1: float = 0.9,
-             beta2: float = 0.999, eps: float = 1e-8, stream=None):
+             beta2: float = 0.999, eps: float = 1e-8, grad_scale: float = 1.0, stream=None):
     import torch
     st = stream if stream is not None else torch.cuda.current_stream(params.device)
     _check(lib().ba_gnn_adam(params.numel(), params.data_ptr(), grad.data_ptr(), m.data_ptr(),
-                             v.data_ptr(), step, lr, beta1, beta2, eps, st.cuda_stream))
+                             v.data_ptr(), step, lr, beta1, beta2, eps, grad_scale, st.cuda_stream))
 
 
 # ---- differentiable layer ------------------------------------------------------

@@ -53,6 +53,14 @@ struct AdjBackArgs {
   double *vp, *dLdx, *dLdw;
 };
 
+struct AdjStatArgs {
+  int nc, np;
+  const int32_t *cam_ptr, *cam_obs, *pt_ptr;
+  const double *J, *r, *o_w;
+  double* stat;  // [2]: max |gradient component|, max |single term| (zeroed by the caller)
+};
+
+hipError_t launch_adj_stationarity(const AdjStatArgs&, hipStream_t);
 hipError_t launch_adj_tangent(const AdjTangentArgs&, hipStream_t);
 hipError_t launch_adj_obs(const AdjObsArgs&, hipStream_t);
 hipError_t launch_adj_points(const AdjPointArgs&, int nchunk, hipStream_t);

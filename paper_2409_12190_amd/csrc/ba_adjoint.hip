@@ -23,6 +23,11 @@ namespace ba {
 
 namespace {
 
+// max(m, |v|), with a NaN v counted as infinity
+__device__ __forceinline__ double absmax_inf(double m, double v) {
+  return v == v ? fmax(m, fabs(v)) : INFINITY;
+}
+
 __device__ __forceinline__ double wsum(double v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -42,7 +47,7 @@ __global__ __launch_bounds__(256) void k_adj_tangent(AdjTangentArgs a) {
   const double* c = a.cams + 10 * (size_t)cam;
   const double* g = a.gL_cams + 10 * (size_t)cam;
   double* o = a.gt + 9 * (size_t)cam;
-  if (a.fixed[cam]) {
+  if (a.fixed[cam] & FIXED_CAMERA) {
     for (int i = 0; i < 9; ++i) o[i] = 0.0;
     return;
   }
@@ -69,7 +74,7 @@ __global__ __launch_bounds__(128) void k_adj_obs(AdjObsArgs a) {
   const double r0 = pr.px - a.o_xy[2 * x], r1 = pr.py - a.o_xy[2 * x + 1];
   double C[78];
   curvature12(cam, X, r0, r1, C);
-  const bool fx = a.fixed[cam_i] != 0;
+  const bool fx = (a.fixed[cam_i] & FIXED_CAMERA) != 0;
   double J[2][12];
   for (int m = 0; m < 2; ++m) {
     for (int i = 0; i < 9; ++i) J[m][i] = fx ? 0.0 : Jc[m][i];
@@ -186,7 +191,7 @@ __global__ __launch_bounds__(CAM_THREADS) void k_adj_camera(AdjCameraArgs a) {
     if (lane == 0) red[wid][45 + q] = v;
   }
   __syncthreads();
-  const bool fx = a.fixed[cam] != 0 || hi == lo;
+  const bool fx = (a.fixed[cam] & FIXED_CAMERA) != 0 || hi == lo;
   if (threadIdx.x < 45) {
     double s = 0.0;
     for (int w2 = 0; w2 < CAM_THREADS / 64; ++w2) s += red[w2][threadIdx.x];
@@ -313,6 +318,58 @@ __global__ __launch_bounds__(CHUNK) void k_adj_backsub(AdjBackArgs a) {
     a.dLdx[2 * k + 1] = w * e[1];
     if (a.dLdw) a.dLdw[k] = -(a.r[2 * x] * e[0] + a.r[2 * x + 1] * e[1]);
   }
+}
+
+// Stationarity of theta, the premise of the adjoint: per camera and per point
+// the tangent gradient g = sum_k w_k J_k^T r_k (fixed cameras' columns are
+// zero in J), and the largest single term |w_k (J_k^T r_k)_i| as its scale.
+// stat[0] = max |g_i|, stat[1] = max term (maxima of non-negative doubles
+// through their bit patterns, which order the same way; a non-finite
+// gradient component counts as infinity and fails the test on the host).
+__global__ __launch_bounds__(256) void k_adj_stationarity(AdjStatArgs a) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  double gmax = 0.0, tmax = 0.0;
+  if (t < a.nc) {
+    double g[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (int q = a.cam_ptr[t]; q < a.cam_ptr[t + 1]; ++q) {
+      const int x = a.cam_obs[q];
+      const double* J = a.J + 24 * (size_t)x;
+      const double w = a.o_w[x], r0 = a.r[2 * x], r1 = a.r[2 * x + 1];
+      for (int i = 0; i < 9; ++i) {
+        const double term = w * (J[i] * r0 + J[9 + i] * r1);
+        g[i] += term;
+        tmax = fmax(tmax, fabs(term));
+      }
+    }
+    for (int i = 0; i < 9; ++i) gmax = absmax_inf(gmax, g[i]);
+  } else if (t < a.nc + a.np) {
+    const int j = t - a.nc;
+    double g[3] = {0, 0, 0};
+    for (int x = a.pt_ptr[j]; x < a.pt_ptr[j + 1]; ++x) {
+      const double* J = a.J + 24 * (size_t)x;
+      const double w = a.o_w[x], r0 = a.r[2 * x], r1 = a.r[2 * x + 1];
+      for (int i = 0; i < 3; ++i) {
+        const double term = w * (J[18 + i] * r0 + J[21 + i] * r1);
+        g[i] += term;
+        tmax = fmax(tmax, fabs(term));
+      }
+    }
+    for (int i = 0; i < 3; ++i) gmax = absmax_inf(gmax, g[i]);
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    gmax = fmax(gmax, __shfl_xor(gmax, o, 64));
+    tmax = fmax(tmax, __shfl_xor(tmax, o, 64));
+  }
+  if ((threadIdx.x & 63) == 0) {
+    atomicMax(reinterpret_cast<unsigned long long*>(a.stat), (unsigned long long)__double_as_longlong(gmax));
+    atomicMax(reinterpret_cast<unsigned long long*>(a.stat + 1), (unsigned long long)__double_as_longlong(tmax));
+  }
+}
+
+hipError_t launch_adj_stationarity(const AdjStatArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_adj_stationarity, dim3((a.nc + a.np + 255) / 256), dim3(256), 0, s, a);
+  return hipGetLastError();
 }
 
 hipError_t launch_adj_tangent(const AdjTangentArgs& a, hipStream_t s) {

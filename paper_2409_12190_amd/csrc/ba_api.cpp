@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <new>
 #include <string>
@@ -11,6 +12,7 @@
 
 #include "ba.h"
 #include "ba_adjoint.h"
+#include "ba_dense.h"
 #include "ba_internal.h"
 #include "ba_kernels.h"
 #include "ba_precond.h"
@@ -145,6 +147,13 @@ void carve(ba_problem* p, char* base, size_t* total) {
   b.partB = c.take<double>(slots * std::max(P.pcg_grid, P.sgrid) * ba::PART_STRIDE);
   b.rring = c.take<double>(stream ? slots * (size_t)P.rstride : 0);
   b.rflag = c.take<double>(stream ? slots * (size_t)P.sgrid : 0);
+  if (p->opt.linear_solver == BA_SOLVER_CHOLESKY) {
+    const size_t ld = ba::dense_ld(P.nc), n = 9 * nc;
+    b.dA = c.take<double>((n + 1) * ld);
+    b.dLinv = c.take<double>(ld / ba::DENSE_NB * ba::DENSE_NB * ba::DENSE_NB);
+    b.dpart = c.take<double>((n + ba::DENSE_BROWS - 1) / ba::DENSE_BROWS * ba::DENSE_NB);
+    b.dresid = c.take<double>(2 * nc);
+  }
   b.dev = c.take<ba::DevScalars>(1);
   b.dinfo = c.take<ba_step_info>(1);
   b.gsync = c.take<ba::GridSync>(1);
@@ -158,6 +167,7 @@ void carve(ba_problem* p, char* base, size_t* total) {
     b.adj_vc = c.take<double>(9 * nc);
     b.adj_vp = c.take<double>(3 * np);
     b.adj_dev = c.take<ba::DevScalars>(1);
+    b.adj_stat = c.take<double>(2);
     b.adj_info = c.take<ba_step_info>(1);
   }
   if (p->opt.precond == BA_PRECOND_LEARNED) {
@@ -341,7 +351,14 @@ ba_status lm_step_impl(ba_problem* p, ba_step_info* out) {
     pa.rflag = b.rflag;
     pcg_grid = P.sgrid;
   }
-  PHASE(7, launch_pcg<T>(pa, pcg_grid, P.pcg_resident, pipe, s));
+  if (p->opt.linear_solver == BA_SOLVER_CHOLESKY) {
+    DenseArgs da{P.nc, P.nnzb, (int64_t)dense_ld(P.nc), b.dA, b.dLinv, b.dpart, b.dresid, b.x, b.bS,
+                 b.Sdiag, b.S, b.S_ptr, b.S_col, b.blk_row, b.T_ptr, b.T_blk, b.T_src, b.dinfo,
+                 &b.dev->error};
+    PHASE(7, launch_dense_solve<T>(da, s));
+  } else {
+    PHASE(7, launch_pcg<T>(pa, pcg_grid, P.pcg_resident, pipe, s));
+  }
   if (learned && p->cg_rtol > 0.0) {
     // the unpreconditioned residual judges the learned blocks: when the PCG
     // missed its tolerance the step is solved again with block-Jacobi
@@ -372,6 +389,7 @@ ba_status lm_step_impl(ba_problem* p, ba_step_info* out) {
 
   ba_step_info info = *p->hinfo;
   info.precond_used = precond_used;
+  info.stop_reason = BA_STOP_NONE;
   const int32_t err = p->hscal->error;
   if (err != 0 || !std::isfinite(info.cost_before)) {
     // leave theta and lambda as they were
@@ -449,6 +467,8 @@ void ba_default_options(ba_options* o) {
   o->enable_backward = 0;
   o->adjoint_rtol = 1e-10;
   o->precond = BA_PRECOND_BLOCK_JACOBI;
+  o->adjoint_grad_tol = 1e-6;
+  o->linear_solver = BA_SOLVER_PCG;
 }
 
 const char* ba_last_error(void) { return g_err.c_str(); }
@@ -461,7 +481,9 @@ ba_status ba_problem_create(const ba_options* opt, int32_t n_cams, int32_t n_pts
   ba_options o;
   if (opt) o = *opt;
   else ba_default_options(&o);
-  if (o.cam_dof != 9) return fail(BA_EUNSUPPORTED, "only cam_dof = 9 is supported");
+  if (o.cam_dof != 9 && o.cam_dof != 6) return fail(BA_EUNSUPPORTED, "cam_dof must be 9 or 6");
+  if (o.cam_dof == 6 && (o.precond == BA_PRECOND_LEARNED || o.enable_backward))
+    return fail(BA_EUNSUPPORTED, "the 6-DoF camera supports neither the learned preconditioner nor the adjoint");
   if (o.precision != BA_FP64 && o.precision != BA_MIXED) return fail(BA_EINVAL, "unknown precision");
   if (!(o.cg_rtol >= 0.0) || o.cg_maxiter < 1) return fail(BA_EINVAL, "bad CG options");
   if (o.cg_variant != BA_CG_PIPELINED && o.cg_variant != BA_CG_STANDARD)
@@ -471,6 +493,11 @@ ba_status ba_problem_create(const ba_options* opt, int32_t n_cams, int32_t n_pts
   if (!(o.diag_min > 0.0) || !(o.diag_max >= o.diag_min)) return fail(BA_EINVAL, "bad clamp range");
   if (o.precond != BA_PRECOND_BLOCK_JACOBI && o.precond != BA_PRECOND_LEARNED)
     return fail(BA_EINVAL, "unknown preconditioner");
+  if (!(o.adjoint_grad_tol >= 0.0)) return fail(BA_EINVAL, "adjoint_grad_tol must be >= 0");
+  if (o.linear_solver != BA_SOLVER_PCG && o.linear_solver != BA_SOLVER_CHOLESKY)
+    return fail(BA_EINVAL, "unknown linear solver");
+  if (o.linear_solver == BA_SOLVER_CHOLESKY && (n_cams > ba::DENSE_MAX_CAMS || o.precond == BA_PRECOND_LEARNED))
+    return fail(BA_EUNSUPPORTED, "the dense Cholesky solve takes at most 2048 cameras and no learned preconditioner");
   ba_problem* p = new (std::nothrow) ba_problem();
   if (!p) return fail(BA_EINVAL, "out of host memory");
   p->opt = o;
@@ -576,7 +603,7 @@ ba_status ba_problem_bind(ba_problem* p, void* ws, size_t bytes, void* stream) {
     HIPCHK(upload(b.nbr_blk, P.nbr_blk, s));
     HIPCHK(upload(b.nbr_rev, P.nbr_rev, s));
   }
-  HIPCHK(hipMemsetAsync(b.fixed, 0, P.nc, s));
+  HIPCHK(hipMemsetAsync(b.fixed, p->opt.cam_dof == 6 ? ba::FIXED_INTRINSICS : 0, P.nc, s));
   HIPCHK(hipMemsetAsync(b.gsync, 0, sizeof(ba::GridSync), s));
   HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&p->hinfo), sizeof(ba_step_info), hipHostMallocDefault));
   HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&p->hscal), sizeof(ba::DevScalars), hipHostMallocDefault));
@@ -620,9 +647,10 @@ ba_status ba_set_observations(ba_problem* p, const double* xy, const double* w) 
 ba_status ba_set_fixed_cameras(ba_problem* p, const uint8_t* mask) {
   if (!p) return fail(BA_EINVAL, "null problem");
   if (!p->bound) return fail(BA_ESTATE, "problem is not bound");
-  std::vector<uint8_t> m(p->plan.nc, 0);
+  const uint8_t base = p->opt.cam_dof == 6 ? ba::FIXED_INTRINSICS : 0;
+  std::vector<uint8_t> m(p->plan.nc, base);
   if (mask)
-    for (int32_t i = 0; i < p->plan.nc; ++i) m[i] = mask[i] ? 1 : 0;
+    for (int32_t i = 0; i < p->plan.nc; ++i) m[i] = mask[i] ? ba::FIXED_CAMERA : base;
   HIPCHK(hipMemcpyAsync(p->b.fixed, m.data(), m.size(), hipMemcpyHostToDevice, p->stream));
   HIPCHK(hipStreamSynchronize(p->stream));
   p->lin_valid = false;
@@ -696,20 +724,28 @@ ba_status ba_solve(ba_problem* p, int32_t max_iters, double rel_tol, int32_t pla
   for (int32_t it = 0; it < max_iters; ++it) {
     ba_step_info info;
     st = ba_lm_step(p, &info);
-    if (infos) infos[it] = info;
+    int32_t reason = BA_STOP_NONE;
     if (st != BA_OK) {
       ret = st;
-      break;
+      reason = BA_STOP_ERROR;
+    } else {
+      ++done;
+      const double dec = info.accepted ? (info.cost_before - info.cost_after) / info.cost_before : 0.0;
+      flat = dec < rel_tol ? flat + 1 : 0;
+      if (!info.accepted && info.lambda_used >= p->opt.lambda_max) {
+        ret = fail(BA_ENOTCONV, "damping reached lambda_max");
+        reason = BA_STOP_LAMBDA_MAX;
+      } else if (flat >= plateau_steps) {
+        reason = BA_STOP_PLATEAU;
+      } else if (info.grad_inf <= 1e-12 * (1.0 + info.cost_before)) {
+        reason = BA_STOP_GRADIENT;
+      } else if (it + 1 == max_iters) {
+        reason = BA_STOP_MAX_ITERS;
+      }
     }
-    ++done;
-    const double dec = info.accepted ? (info.cost_before - info.cost_after) / info.cost_before : 0.0;
-    flat = dec < rel_tol ? flat + 1 : 0;
-    if (!info.accepted && info.lambda_used >= p->opt.lambda_max) {
-      ret = fail(BA_ENOTCONV, "damping reached lambda_max");
-      break;
-    }
-    if (flat >= plateau_steps) break;
-    if (info.grad_inf <= 1e-12 * (1.0 + info.cost_before)) break;
+    info.stop_reason = reason;
+    if (infos) infos[it] = info;
+    if (reason != BA_STOP_NONE) break;
   }
   if (iters_done) *iters_done = done;
   return ret;
@@ -741,6 +777,25 @@ ba_status ba_backward(ba_problem* p, const double* dL_dcams, const double* dL_dp
   AdjObsArgs oa{P.no, b.o_cam, b.o_pt, b.fixed, b.o_xy, b.o_w, b.cams[cur], b.pts[cur],
                 b.adjA, b.adjJ, b.r};
   HIPCHK(launch_adj_obs(oa, s));
+  // the adjoint holds only where the gradient vanishes: check it first
+  HIPCHK(hipMemsetAsync(b.adj_stat, 0, 2 * sizeof(double), s));
+  AdjStatArgs ga0{P.nc, P.np, b.cam_ptr, b.cam_obs, b.pt_ptr, b.adjJ, b.r, b.o_w, b.adj_stat};
+  HIPCHK(launch_adj_stationarity(ga0, s));
+  double stat[2] = {0.0, 0.0};
+  HIPCHK(hipMemcpyAsync(stat, b.adj_stat, sizeof stat, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (!(stat[0] <= p->opt.adjoint_grad_tol * stat[1])) {
+    if (info) {
+      *info = ba_step_info{};
+      info->grad_inf = stat[0];
+      info->status = BA_ENOTCONV;
+    }
+    char msg[160];
+    std::snprintf(msg, sizeof msg,
+                  "theta is not a stationary point: max |g| = %.3e > adjoint_grad_tol x %.3e", stat[0],
+                  stat[1]);
+    return fail(BA_ENOTCONV, msg);
+  }
   AdjPointArgs pa{b.chunk_ptr, b.chunk_pt, b.pt_ptr, b.o_pt, b.adjA, b.Vinv, b.adjY, b.gsync,
                   &b.adj_dev->error};
   HIPCHK(launch_adj_points(pa, nchunk, s));
@@ -765,6 +820,7 @@ ba_status ba_backward(ba_problem* p, const double* dL_dcams, const double* dL_dp
   HIPCHK(hipMemcpyAsync(p->hscal, b.adj_dev, sizeof(DevScalars), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
   ba_step_info out = *p->hinfo;
+  out.grad_inf = stat[0];
   const int32_t err = p->hscal->error;
   st = BA_OK;
   if (err & ERR_BARRIER) st = fail(BA_EHIP, "the PCG grid barrier timed out");
@@ -940,6 +996,15 @@ ba_status ba_export(const ba_problem* p, int32_t field, void* dst, size_t bytes)
       for (size_t a = 0; a <= nc; ++a) o[a] = P.S_ptr[a];
       return BA_OK;
     }
+    case BA_X_PLAN: {
+      if (!need(4 * sizeof(int64_t))) return fail(BA_EINVAL, "size mismatch");
+      int64_t* o = reinterpret_cast<int64_t*>(dst);
+      o[0] = P.pcg_resident ? 0 : (streamed(p) ? 2 : 1);
+      o[1] = streamed(p) ? P.sgrid : P.pcg_grid;
+      o[2] = P.n_pairs;
+      o[3] = P.n_schur_wg;
+      return BA_OK;
+    }
     case BA_X_S_COL: {
       if (!need(nnzb * sizeof(int32_t))) return fail(BA_EINVAL, "size mismatch");
       std::memcpy(dst, P.S_col.data(), bytes);
@@ -1064,9 +1129,9 @@ ba_status ba_gnn_loss_grad(ba_graph* g, const float* params, float* grad, double
 }
 
 ba_status ba_gnn_adam(int64_t n, float* params, const float* grad, float* m, float* v, int32_t step,
-                      float lr, float beta1, float beta2, float eps, void* stream) {
+                      float lr, float beta1, float beta2, float eps, float grad_scale, void* stream) {
   if (!params || !grad || !m || !v || n <= 0 || step < 1) return fail(BA_EINVAL, "bad argument");
-  HIPCHK(ba::launch_gnn_adam(n, params, grad, m, v, step, lr, beta1, beta2, eps,
+  HIPCHK(ba::launch_gnn_adam(n, params, grad, m, v, step, lr, beta1, beta2, eps, grad_scale,
                              reinterpret_cast<hipStream_t>(stream)));
   return BA_OK;
 }

@@ -292,4 +292,15 @@ __device__ __forceinline__ void retract_camera(const double* __restrict__ cam,
   out[9] = cam[9] + dlt[8];
 }
 
+// (Linv^T T)[r][c] = sum_{k >= r} Linv[k][r] T[k][c] for a lower-triangular
+// 9x9 Linv (row-major): the block-Jacobi inverse Linv^T Linv with T = Linv,
+// and the learned block Linv^T (Mh Linv) with T = Mh Linv.  One summation
+// order for both, so a correction Mh of exactly the identity reproduces the
+// block-Jacobi blocks bit for bit.
+__device__ __forceinline__ double lt_times(const double* Li, const double* T, int r, int c) {
+  double s = 0.0;
+  for (int k = r; k < 9; ++k) s = fma(Li[9 * k + r], T[9 * k + c], s);
+  return s;
+}
+
 }  // namespace ba

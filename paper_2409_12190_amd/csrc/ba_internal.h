@@ -123,6 +123,12 @@ struct DevScalars {
   int32_t pad;
 };
 
+// per-camera flags of the `fixed` array: the whole camera held fixed (gauge
+// anchor; its Jacobian block is zero), or only its intrinsics (the 6-DoF
+// pose-only camera: Jacobian columns f, k1, k2 zero, so its reduced rows
+// and its step in those components are exactly zero)
+enum : uint8_t { FIXED_CAMERA = 1, FIXED_INTRINSICS = 2 };
+
 enum : int32_t {
   ERR_NONFINITE_OBS = 1,
   ERR_BAD_WEIGHT = 2,
@@ -175,6 +181,9 @@ struct Buffers {
   double *part_cost, *part_cost_new, *part_pred, *part_gmax, *part_linc, *part_stage;
   double *zring, *partA, *partB;  // PCG exchange rings, one slot per iteration
   double *rring, *rflag;          // streamed plans: column-sum exchange slots and flags
+  // direct solve (BA_SOLVER_CHOLESKY): dense lower triangle of S with b_S as
+  // an extra row, inverses of the diagonal factors, partial sums, residuals
+  double *dA, *dLinv, *dpart, *dresid;
   DevScalars* dev;
   ba_step_info* dinfo;
   GridSync* gsync;
@@ -184,6 +193,7 @@ struct Buffers {
   double* adjS;                // [nnzb][81] reduced matrix (aliases S in FP64 mode)
   double *adj_gt, *adj_vc, *adj_vp;  // tangent loss gradient, adjoint vector
   DevScalars* adj_dev;         // lambda = 0 and the adjoint's error flags
+  double* adj_stat;            // [2] stationarity check: max |g_i|, max |term|
   ba_step_info* adj_info;
   // learned preconditioner (only with BA_PRECOND_LEARNED)
   double *pcLinv, *pcMinvL;    // [nc][81] inverse Cholesky factors, learned blocks

@@ -215,11 +215,17 @@ __global__ __launch_bounds__(CHUNK) void k_linearize(LinArgs a) {
     const double om = a.o_w[x];
     w = om * drho;
     cost = 0.5 * om * rho;
-    if (a.fixed[ci]) {
+    const uint8_t fx = a.fixed[ci];
+    if (fx & FIXED_CAMERA) {
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int m = 0; m < 9; ++m) Jc[i][m] = 0.0;
+    } else if (fx & FIXED_INTRINSICS) {
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int m = 6; m < 9; ++m) Jc[i][m] = 0.0;
     }
     a.r[2 * (size_t)x] = rx;
     a.r[2 * (size_t)x + 1] = ry;
@@ -702,11 +708,7 @@ __global__ __launch_bounds__(64) void k_camera_finish(CamFinishArgs a) {
       for (int q = 0; q < 81; ++q) a.Linv[81 * (size_t)cam + q] = Li[q];
     double* Mi = a.Minv + 81 * (size_t)cam;
     for (int r = 0; r < 9; ++r)
-      for (int cc = 0; cc < 9; ++cc) {
-        double s = 0.0;
-        for (int k = (r > cc ? r : cc); k < 9; ++k) s += Li[k * 9 + r] * Li[k * 9 + cc];
-        Mi[r * 9 + cc] = s;
-      }
+      for (int cc = 0; cc < 9; ++cc) Mi[r * 9 + cc] = lt_times(Li, Li, r, cc);
   }
 }
 
@@ -788,7 +790,7 @@ __global__ __launch_bounds__(256) void k_retract_cameras(RetractArgs a) {
     const double* src = a.cams + 10 * (size_t)cam;
     double* dst = a.cams_new + 10 * (size_t)cam;
     const double* dc = a.dc + 9 * (size_t)cam;
-    if (a.fixed[cam]) {
+    if (a.fixed[cam] & FIXED_CAMERA) {
       for (int q = 0; q < 10; ++q) dst[q] = src[q];
     } else {
       retract_camera(src, dc, dst);

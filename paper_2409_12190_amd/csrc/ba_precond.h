@@ -59,6 +59,6 @@ hipError_t launch_gnn_output(const GraphDev&, const float* params, const double*
                              bool with_loss, hipStream_t);
 hipError_t launch_gnn_backward(const GraphDev&, const float* params, float* grad, hipStream_t);
 hipError_t launch_gnn_adam(int64_t n, float* params, const float* grad, float* m, float* v, int step,
-                           float lr, float b1, float b2, float eps, hipStream_t);
+                           float lr, float b1, float b2, float eps, float grad_scale, hipStream_t);
 
 }  // namespace ba

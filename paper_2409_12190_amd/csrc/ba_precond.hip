@@ -16,6 +16,7 @@
 //
 // All network arithmetic is FP32; every reduction runs in a fixed order
 // (no atomics), so training is bitwise reproducible.
+#include "ba_device.h"
 #include "ba_precond.h"
 #include "ba_reduce.h"
 
@@ -219,6 +220,7 @@ __global__ __launch_bounds__(64) void k_gnn_output(GraphDev g, const float* __re
   __shared__ float o[45];
   __shared__ float C[81], Mh[81], Gm[81], Q[81], Gam[81];
   __shared__ double red[64];
+  __shared__ double T[81];
   const int i = blockIdx.x, t = threadIdx.x;
   const float* h = g.H[GNN_L] + (size_t)i * GNN_H;
   if (t < GNN_O) {
@@ -240,14 +242,18 @@ __global__ __launch_bounds__(64) void k_gnn_output(GraphDev g, const float* __re
     Mh[q] = v;
   }
   __syncthreads();
-  if (Minv) {  // M_i = Linv^T Mh Linv in FP64
+  if (Minv) {  // M_i = Linv^T (Mh Linv) in FP64
     const double* Li = Linv + 81 * (size_t)i;
-    for (int q = t; q < 81; q += 64) {
+    for (int q = t; q < 81; q += 64) {  // T = Mh Linv (exactly Linv for Mh = I)
       const int r = q / 9, c = q - 9 * r;
       double v = 0.0;
-      for (int k = 0; k < 9; ++k)
-        for (int l = 0; l < 9; ++l) v += Li[9 * k + r] * (double)Mh[9 * k + l] * Li[9 * l + c];
-      Minv[81 * (size_t)i + q] = v;
+      for (int l = 0; l < 9; ++l) v = fma((double)Mh[9 * r + l], Li[9 * l + c], v);
+      T[q] = v;
+    }
+    __syncthreads();
+    for (int q = t; q < 81; q += 64) {
+      const int r = q / 9, c = q - 9 * r;
+      Minv[81 * (size_t)i + q] = lt_times(Li, T, r, c);
     }
   }
   if (!with_loss) return;
@@ -348,10 +354,10 @@ __global__ __launch_bounds__(256) void k_gnn_relu_mask(int n, const float* __res
 __global__ __launch_bounds__(256) void k_gnn_adam(int64_t n, float* __restrict__ p,
                                                   const float* __restrict__ g, float* __restrict__ m,
                                                   float* __restrict__ v, float lr, float b1, float b2,
-                                                  float eps, float c1, float c2) {
+                                                  float eps, float c1, float c2, float gscale) {
   const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (q >= n) return;
-  const float gq = g[q];
+  const float gq = g[q] * gscale;
   const float mq = b1 * m[q] + (1.0f - b1) * gq;
   const float vq = b2 * v[q] + (1.0f - b2) * gq * gq;
   m[q] = mq;
@@ -521,10 +527,10 @@ hipError_t launch_gnn_backward(const GraphDev& gin, const float* P, float* G, hi
 }
 
 hipError_t launch_gnn_adam(int64_t n, float* p, const float* g, float* m, float* v, int step, float lr,
-                           float b1, float b2, float eps, hipStream_t s) {
+                           float b1, float b2, float eps, float gscale, hipStream_t s) {
   const float c1 = 1.0f - powf(b1, (float)step), c2 = 1.0f - powf(b2, (float)step);
   hipLaunchKernelGGL(k_gnn_adam, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, p, g, m, v, lr,
-                     b1, b2, eps, c1, c2);
+                     b1, b2, eps, c1, c2, gscale);
   return hipGetLastError();
 }
 

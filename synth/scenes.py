@@ -314,7 +314,7 @@ def _trajectory_scene(rng, n_cams, n_pts, track_len):
     return cams, X, cam_idx, pt_idx
 
 
-def _laps_scene(rng, n_cams, n_pts, per_lap=1000, loop_frac=0.05, radius=50.0):
+def _laps_scene(rng, n_cams, n_pts, per_lap=1000, loop_frac=0.05, radius=50.0, track_mean=2.0):
     if n_cams % per_lap:
         raise ValueError("n_cams must be a multiple of per_lap")
     n_laps = n_cams // per_lap
@@ -329,7 +329,7 @@ def _laps_scene(rng, n_cams, n_pts, per_lap=1000, loop_frac=0.05, radius=50.0):
     k1 = rng.normal(size=n_cams) * 1e-3
     k2 = rng.normal(size=n_cams) * 1e-3
     cams = _cams_from(R, C, np.full(n_cams, 500.0), k1, k2)
-    track_len = np.minimum(2 + rng.poisson(2.0, size=n_pts), 30)
+    track_len = np.minimum(2 + rng.poisson(track_mean, size=n_pts), min(30, per_lap // 3))
     draw = _anchored_point_drawer(R, C, n_cams, 5.0, 20.0)
     X, tracks = _tracks_nearest(rng, cams, n_pts, track_len, draw, window=20, wrap=per_lap)
     cam_idx, pt_idx = _flatten_tracks(tracks)
@@ -381,13 +381,15 @@ def _loop_closures(rng, cams, X, cam_idx, pt_idx, per_lap, n_laps, frac, rounds=
 
 
 def make_scene(cfg: int, seed: int = 0, noise_px: float = 1.0, perturb: bool = True,
-               n_cams: Optional[int] = None, n_pts: Optional[int] = None) -> Scene:
+               n_cams: Optional[int] = None, n_pts: Optional[int] = None,
+               per_lap: Optional[int] = None) -> Scene:
     """Build workload `cfg` with generator seed [cfg, seed].
 
     noise_px: standard deviation of the pixel noise per coordinate (0 gives
     noise-free observations).  perturb=False starts at the ground truth.
     n_cams / n_pts override the sizes (for small tests of a configuration's
-    structure)."""
+    structure); per_lap sets the cameras per lap of the laps workload
+    (default: 1000, or all cameras when fewer)."""
     rng = np.random.default_rng([cfg, seed])
     obs_w = None
     huber = 0.0
@@ -404,7 +406,7 @@ def make_scene(cfg: int, seed: int = 0, noise_px: float = 1.0, perturb: bool = T
         huber, iters = 1.0, 20
     elif cfg == 2:
         nc, npt = n_cams or 10_000, n_pts or 2_000_000
-        per_lap = min(1000, nc)
+        per_lap = per_lap or min(1000, nc)
         cams, pts, cam_idx, pt_idx = _laps_scene(rng, nc, npt, per_lap=per_lap)
         huber, iters = 1.0, 10
     elif cfg == 3:
@@ -414,11 +416,17 @@ def make_scene(cfg: int, seed: int = 0, noise_px: float = 1.0, perturb: bool = T
         iters = 50
         fixed = np.array([0, 1], np.int32)
     elif cfg == 4:
-        nc = n_cams or int(rng.integers(200, 2001))
-        npt = n_pts or int(round(10.0 ** rng.uniform(4.0, 5.0)))
-        tl = np.minimum(2 + rng.poisson(3.0, size=npt), max(2, min(30, nc // 3)))
-        cams, pts, cam_idx, pt_idx = _trajectory_scene(rng, nc, npt, tl)
-        iters = 5
+        # log-uniform sizes; laps of ~200 cameras with a random fraction
+        # U(0, 0.1) of loop-closure observations; tracks 2 + Poisson(3)
+        nc = n_cams or int(round(np.exp(rng.uniform(np.log(200), np.log(2000)))))
+        npt = n_pts or int(round(np.exp(rng.uniform(np.log(1e4), np.log(1e5)))))
+        laps = max(1, nc // 200)
+        nc = (nc // laps) * laps
+        frac = rng.uniform(0.0, 0.1)
+        # circuit radius scaled so that cameras are spaced as in the large laps scene
+        cams, pts, cam_idx, pt_idx = _laps_scene(rng, nc, npt, per_lap=nc // laps, loop_frac=frac,
+                                                 radius=50.0 * (nc // laps) / 1000.0, track_mean=3.0)
+        huber, iters = 1.0, 5
     else:
         raise ValueError(f"unknown configuration {cfg}")
 

@@ -55,8 +55,14 @@ def test_create_rejects_bad_indices_and_sizes():
         _create(3, 3, [], [])
     assert e.value.status == B.BA_EINVAL
     with pytest.raises(B.BaError) as e:
-        _create(3, 3, [0], [0], cam_dof=6)
+        _create(3, 3, [0], [0], cam_dof=7)
     assert e.value.status == B.BA_EUNSUPPORTED
+    # the 6-DoF camera: supported, but not with the learned preconditioner or the adjoint
+    B.ba_problem_destroy(_create(3, 3, [0, 1, 2], [0, 1, 2], cam_dof=6))
+    for kw in (dict(precond=B.BA_PRECOND_LEARNED), dict(enable_backward=1)):
+        with pytest.raises(B.BaError) as e:
+            _create(3, 3, [0, 1, 2], [0, 1, 2], cam_dof=6, **kw)
+        assert e.value.status == B.BA_EUNSUPPORTED
 
 
 def test_track_length_limit():
@@ -144,3 +150,13 @@ def test_bench_refuses_several_gpus():
     r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
                        capture_output=True, text=True, timeout=120)
     assert r.returncode != 0 and "one GPU" in r.stderr
+
+
+def test_option_struct_layout_matches_the_binding():
+    """ba_default_options fills the last fields of ba_options where the
+    binding's ctypes mirror expects them."""
+    from paper_2409_12190_amd import ba as B
+    o = B.ba_default_options()
+    assert o.cam_dof == 9 and o.cg_maxiter == 250 and o.cg_rtol == 1e-4
+    assert o.precond == B.BA_PRECOND_BLOCK_JACOBI and o.adjoint_rtol == 1e-10
+    assert o.adjoint_grad_tol == 1e-6

@@ -40,9 +40,13 @@ def orc(scene, **kw):
     return O.Oracle.from_scene(scene, options=opt)
 
 
-def rel(a, b):
-    a, b = np.asarray(a), np.asarray(b)
-    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+def close(got, ref, tol, what=""):
+    """Element by element: |got - ref| <= tol * max|ref| for every entry (a
+    wrong small entry is not hidden by a norm over the whole array)."""
+    got, ref = np.asarray(got, np.float64), np.asarray(ref, np.float64)
+    assert got.shape == ref.shape, (what, got.shape, ref.shape)
+    scale = float(np.abs(ref).max()) if ref.size else 0.0
+    np.testing.assert_allclose(got, ref, rtol=0, atol=tol * scale, err_msg=what)
 
 
 SMALL = {
@@ -62,16 +66,22 @@ def scene_of(name, **kw):
 def test_linearization_matches_oracle(name):
     s = scene_of(name)
     g, o = gpu(s), orc(s)
-    g.lm_step()
+    ig = g.lm_step()
     r, w, Jc, Jp, F = o.linearization()
-    assert rel(g.export(B.BA_X_RESIDUAL), r) < 1e-12
-    assert rel(g.export(B.BA_X_WEIGHT), w) < 1e-13
-    assert rel(g.export(B.BA_X_JC), Jc) < 1e-13
-    assert rel(g.export(B.BA_X_JP), Jp) < 1e-13
+    close(g.export(B.BA_X_RESIDUAL), r, 1e-12, "r")
+    # Huber weights delta / |r| inherit the residuals' relative error
+    close(g.export(B.BA_X_WEIGHT), w, 1e-12, "w")
+    Jc_g = g.export(B.BA_X_JC)
+    close(Jc_g, Jc, 1e-13, "Jc")
+    # each column of Jc on its own scale (the intrinsic columns are small)
+    for col in range(9):
+        close(Jc_g[:, :, col], Jc[:, :, col], 1e-12, f"Jc column {col}")
+    close(g.export(B.BA_X_JP), Jp, 1e-13, "Jp")
+    assert abs(ig["cost_before"] - F) <= 1e-12 * F
     U, V, gc, gp = o.normal()
-    assert rel(g.export(B.BA_X_V), V) < 1e-12
-    assert rel(g.export(B.BA_X_GRAD_P), gp) < 1e-11
-    assert rel(g.export(B.BA_X_GRAD_C), gc) < 1e-11
+    close(g.export(B.BA_X_V), V, 1e-12, "V")
+    close(g.export(B.BA_X_GRAD_P), gp, 1e-11, "gp")
+    close(g.export(B.BA_X_GRAD_C), gc, 1e-11, "gc")
 
 
 @pytest.mark.parametrize("name", list(SMALL))
@@ -85,11 +95,14 @@ def test_schur_system_and_step_match_oracle(name):
     assert np.array_equal(g.export(B.BA_X_S_PTR), ptr)
     assert np.array_equal(g.export(B.BA_X_S_COL), col)
     Sg = g.export(B.BA_X_S)
-    assert rel(Sg, S) < 1e-10
-    assert rel(g.export(B.BA_X_BS), bS) < 1e-10
+    close(Sg, S, 1e-10, "S")
+    # every block on its own scale: a wrong off-diagonal block cannot hide
+    for e in range(0, len(S), max(1, len(S) // 200)):
+        close(Sg[e], S[e], 1e-9, f"S block {e}")
+    close(g.export(B.BA_X_BS), bS, 1e-10, "bS")
     dc, dp, _ = o.step()
-    assert rel(g.export(B.BA_X_DC), dc) < 1e-8
-    assert rel(g.export(B.BA_X_DP), dp) < 1e-8
+    close(g.export(B.BA_X_DC), dc, 1e-8, "dc")
+    close(g.export(B.BA_X_DP), dp, 1e-8, "dp")
     assert info_g["cg_iters"] == info_o["cg_iters"] == 15
     assert abs(info_g["pred"] - info_o["pred"]) <= 1e-9 * abs(info_o["pred"])
     assert abs(info_g["cost_after"] - info_o["cost_after"]) <= 1e-9 * info_o["cost_after"]
@@ -137,8 +150,8 @@ def test_first_iterations_parameters_match_oracle():
     g, o, out = run_parity(s, 3)
     c_g, p_g = g.get_params()
     c_o, p_o = o.get_params()
-    assert rel(c_g.cpu().numpy(), c_o) < 1e-9
-    assert rel(p_g.cpu().numpy(), p_o) < 1e-9
+    close(c_g.cpu().numpy(), c_o, 1e-9, "cameras")
+    close(p_g.cpu().numpy(), p_o, 1e-9, "points")
 
 
 @pytest.mark.parametrize("name", ["cfg1_small", "cfg3_small"])
@@ -356,38 +369,253 @@ def test_state_round_trip_resumes():
     b = gpu(s)
     b.set_state(blob)
     got = [b.lm_step()["cost_before"] for _ in range(3)]
-    np.testing.assert_allclose(got, ref, rtol=1e-10)
+    # every kernel reduces in a fixed order: resuming is bit-exact
+    assert got == ref
 
 
-def test_solve_stops_on_plateau():
+@pytest.mark.parametrize("name", ["cfg0", "cfg3_small"])
+def test_solve_matches_oracle_stop_rule(name):
+    """ba_solve against the oracle's solve with the same stopping rules
+    (Sec. V, StopOnPlateau): both sides solve each step's system to a
+    relative residual of 1e-12, so the iterates agree and both stop at the
+    same iteration for the same reason, at the same final cost."""
+    s = scene_of(name)
+    g = gpu(s, cg_rtol=1e-12, cg_maxiter=PARITY_MAXITER, cg_variant=B.BA_CG_STANDARD)
+    o = orc(s, cg_rtol=1e-12, cg_maxiter=PARITY_MAXITER)
+    st_o, infos_o, why_o = o.solve(60, rel_tol=1e-6, plateau_steps=5)
+    st_g, infos_g = g.solve(60, rel_tol=1e-6, plateau_steps=5)
+    why_g = O.STOP_NAMES[infos_g[-1]["stop_reason"]]
+    print(f"  oracle {len(infos_o)} iterations ({why_o}), GPU {len(infos_g)} ({why_g})", flush=True)
+    assert st_o == 0 and st_g == B.BA_OK
+    assert why_g == why_o and len(infos_g) == len(infos_o)
+    assert all(i["stop_reason"] == B.BA_STOP_NONE for i in infos_g[:-1])
+    F_o = o.cost()
+    c, p = g.get_params()
+    F_g = infos_g[-1]["cost_after"] if infos_g[-1]["accepted"] else infos_g[-1]["cost_before"]
+    assert abs(F_g - F_o) <= 1e-9 * F_o
+    assert abs(o.cost(c.cpu().numpy(), p.cpu().numpy()) - F_o) <= 1e-9 * F_o
+
+
+def test_solve_iteration_cap_and_lambda_max():
+    """The iteration cap and the rejection at lambda_max end ba_solve with
+    the oracle's stop reason and status."""
     s = scene_of("cfg0")
     g = gpu(s)
-    st, infos = g.solve(60, rel_tol=1e-6, plateau_steps=5)
-    assert st == B.BA_OK
-    assert len(infos) < 60
-    costs = [i["cost_before"] for i in infos]
-    assert costs[-1] <= costs[0]
+    st, infos = g.solve(3, rel_tol=1e-6, plateau_steps=5)
+    assert st == B.BA_OK and len(infos) == 3 and infos[-1]["stop_reason"] == B.BA_STOP_MAX_ITERS
+    # noise-free with lambda capped at its start value (the oracle's pin)
+    s0 = make_scene(0, noise_px=0.0)
+    g = gpu(s0, lambda0=1e-4, lambda_max=1e-4)
+    o = orc(s0, lambda0=1e-4, lambda_max=1e-4)
+    st_o, infos_o, why_o = o.solve(60, rel_tol=0.0, plateau_steps=5)
+    st_g, infos_g = g.solve(60, rel_tol=0.0, plateau_steps=5)
+    assert why_o == "lambda_max" and st_o == -4
+    assert st_g == B.BA_ENOTCONV and infos_g[-1]["stop_reason"] == B.BA_STOP_LAMBDA_MAX
+    assert not infos_g[-1]["accepted"] and infos_g[-1]["lambda_used"] == 1e-4
+
+
+@pytest.mark.parametrize("precision", [B.BA_FP64, B.BA_MIXED])
+def test_pose_only_camera_matches_oracle(precision):
+    """The 6-DoF camera (intrinsics held; Sec. III-C footnote): FP64 LM
+    iterations match the oracle's 6-parameter solve within 1e-9 per
+    iteration (converged CG both sides; mixed precision within 1e-4), the
+    Jacobian's pose columns match, and f, k1, k2 never move."""
+    s = scene_of("cfg0")
+    kw = dict(cg_rtol=1e-12, cg_maxiter=PARITY_MAXITER, cg_variant=B.BA_CG_STANDARD)
+    g = gpu(s, precision=precision, cam_dof=6, **kw)
+    o = orc(s, d=6, cg_rtol=1e-12, cg_maxiter=PARITY_MAXITER)
+    tol = 1e-9 if precision == B.BA_FP64 else 1e-4
+    for it in range(6):
+        io, ig = o.lm_step(), g.lm_step()
+        assert ig["status"] == 0
+        assert abs(ig["cost_before"] - io["cost_before"]) <= tol * io["cost_before"], it
+        assert abs(ig["cost_after"] - io["cost_after"]) <= tol * io["cost_after"], it
+        dc = g.export(B.BA_X_DC)
+        assert np.all(dc[:, 6:] == 0.0), it
+        if it == 0 and precision == B.BA_FP64:
+            dco, _, _ = o.step()
+            close(dc[:, :6], dco, 1e-7, "pose step")
+        if abs(io["cost_before"] - io["cost_after"]) <= 1e-11 * io["cost_before"]:
+            break
+        assert ig["accepted"] == io["accepted"] and ig["lambda_next"] == io["lambda_next"], it
+    c, _ = g.get_params()
+    assert np.array_equal(c.cpu().numpy()[:, 7:], s.cams0[:, 7:])
+    # Jacobian at the current point: pose columns match the 6-parameter oracle
+    g.set_params(*o.get_params())
+    g.lm_step()
+    r, w, Jc, Jp, F = o.linearization()
+    Jg = g.export(B.BA_X_JC)
+    assert np.all(Jg[:, :, 6:] == 0.0)
+    close(Jg[:, :, :6], Jc, 1e-12 if precision == B.BA_FP64 else 1e-6, "Jc pose columns")
+
+
+def test_plan_export_names_the_pcg_layout():
+    s = scene_of("cfg1_small")
+    g = gpu(s)
+    pl = g.plan
+    t = np.bincount(s.pt_idx, minlength=s.n_pts).astype(np.int64)
+    assert pl["pairs"] == int((t * (t + 1) // 2).sum())
+    assert pl["pcg_layout"] == "resident" and 1 <= pl["pcg_grid"] <= 256
+
+
+# --------------------------------------------------------------------------
+# full-size workloads, in the benchmark's launch configuration
+# --------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def traj1000():
+    return make_scene(1)
 
 
 @pytest.mark.slow
-def test_full_size_trajectory_scene_matches_oracle():
+def test_full_size_trajectory_fp64_steps_match_oracle(traj1000):
     """The 1,000-camera / 200,000-point / ~1M-observation Huber scene at full
-    size, in the benchmark's launch configuration (default PCG tolerance):
-    the cost sequence stays in the oracle's envelope, and sampled Jacobian
-    blocks and residuals of the third linearisation point match the
-    oracle's."""
-    s = make_scene(1)
-    g, o = gpu(s, precision=B.BA_FP64), orc(s)
+    size, FP64, both sides converged to a relative CG residual of 1e-12
+    (standard recurrence): for LM steps 1-3 the reduced system S and b_S,
+    the step (dc, dp), the costs, the accept flags and lambda match the
+    oracle element by element."""
+    s = traj1000
+    g = gpu(s, cg_rtol=1e-12, cg_maxiter=PARITY_MAXITER, cg_variant=B.BA_CG_STANDARD)
+    o = orc(s, cg_rtol=1e-12, cg_maxiter=PARITY_MAXITER)
+    assert g.plan["pcg_layout"] == "resident"
+    for it in range(3):
+        io, ig = o.lm_step(), g.lm_step()
+        print(f"  step {it}: cost {ig['cost_after']:.12e} / {io['cost_after']:.12e} "
+              f"cg {ig['cg_iters']} / {io['cg_iters']}", flush=True)
+        assert ig["status"] == 0
+        assert abs(ig["cost_before"] - io["cost_before"]) <= 1e-9 * io["cost_before"], it
+        assert abs(ig["cost_after"] - io["cost_after"]) <= 1e-9 * io["cost_after"], it
+        assert abs(ig["pred"] - io["pred"]) <= 1e-8 * abs(io["pred"]), it
+        assert ig["accepted"] == io["accepted"] and ig["lambda_next"] == io["lambda_next"], it
+        ptr, col, S, bS = o.schur()
+        assert np.array_equal(g.export(B.BA_X_S_PTR), ptr) and np.array_equal(g.export(B.BA_X_S_COL), col)
+        close(g.export(B.BA_X_S), S, 1e-10, f"S step {it}")
+        close(g.export(B.BA_X_BS), bS, 1e-10, f"bS step {it}")
+        dc, dp, _ = o.step()
+        close(g.export(B.BA_X_DC), dc, 1e-7, f"dc step {it}")
+        close(g.export(B.BA_X_DP), dp, 1e-7, f"dp step {it}")
+
+
+@pytest.mark.slow
+def test_full_size_trajectory_mixed_tracks_oracle(traj1000):
+    """The benchmark's form on the same scene: mixed precision, pipelined
+    PCG at rtol 1e-4 with register-resident blocks.  Stated bound: the
+    first three iterations' costs within 1e-4 relative of the FP64 oracle's
+    (default tolerance both), every accepted step lowers the cost, and each
+    PCG solve meets its tolerance."""
+    s = traj1000
+    g, o = gpu(s, precision=B.BA_MIXED), orc(s)
+    assert g.plan["pcg_layout"] == "resident"
+    for it in range(3):
+        io, ig = o.lm_step(), g.lm_step()
+        print(f"  step {it}: cost {ig['cost_after']:.9e} / {io['cost_after']:.9e} "
+              f"cg {ig['cg_iters']} / {io['cg_iters']}", flush=True)
+        assert ig["status"] == 0 and ig["cg_breakdown"] == 0
+        # (the oracle too reaches the 250-iteration cap on the third step)
+        assert ig["cg_rel_resid"] <= 1e-4 or ig["cg_iters"] == 250
+        assert abs(ig["cost_before"] - io["cost_before"]) <= 1e-4 * io["cost_before"], it
+        assert abs(ig["cost_after"] - io["cost_after"]) <= 1e-4 * io["cost_after"], it
+        if ig["accepted"]:
+            assert ig["cost_after"] < ig["cost_before"]
+
+
+def spmv_upper(ptr, col, S, x):
+    """y = S x from the upper block triangle (numpy, vectorised)."""
+    nc = len(ptr) - 1
+    row = np.repeat(np.arange(nc), np.diff(ptr))
+    y = np.zeros_like(x)
+    np.add.at(y, row, np.einsum("eij,ej->ei", S, x[col]))
+    off = row != col
+    np.add.at(y, col[off], np.einsum("eji,ej->ei", S[off], x[row[off]]))
+    return y
+
+
+@pytest.fixture(scope="module")
+def laps10000():
+    return make_scene(2)
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("precision", [B.BA_MIXED, B.BA_FP64])
+def test_full_size_laps_scene_tracks_oracle(laps10000, precision):
+    """The 10,000-camera / 2,000,000-point / ~8M-observation laps scene with
+    loop closures, at full size in the benchmark's launch configuration
+    (pipelined PCG, rtol 1e-4; mixed precision streams each upper block once
+    per product, FP64 reads its stored blocks per item).  Two LM steps
+    against the oracle: costs within the stated bound (mixed 1e-4, FP64
+    1e-5 relative), and the PCG step meets its tolerance on the exported
+    system (the residual property checked here in numpy)."""
+    s = laps10000
+    g, o = gpu(s, precision=precision), orc(s)
+    want = "streamed" if precision == B.BA_MIXED else "per_item"
+    assert g.plan["pcg_layout"] == want, g.plan
+    tol = 1e-4 if precision == B.BA_MIXED else 1e-5
     for it in range(2):
         io, ig = o.lm_step(), g.lm_step()
-        assert abs(ig["cost_before"] - io["cost_before"]) <= 1e-9 * io["cost_before"] if it == 0 else True
-    # continue both from the GPU's parameters so the linearisation points coincide
-    c, p = g.get_params()
-    o.set_params(c.cpu().numpy(), p.cpu().numpy())
-    r_o, w_o, Jc_o, Jp_o, F_o = o.linearization()
-    ig = g.lm_step()
-    assert abs(ig["cost_before"] - F_o) <= 1e-12 * F_o
-    idx = np.random.default_rng(0).choice(s.n_obs, 5000, replace=False)
-    assert rel(g.export(B.BA_X_JC)[idx], Jc_o[idx]) < 1e-12
-    assert rel(g.export(B.BA_X_JP)[idx], Jp_o[idx]) < 1e-12
-    assert rel(g.export(B.BA_X_RESIDUAL)[idx], r_o[idx]) < 1e-10
+        print(f"  step {it}: cost {ig['cost_after']:.9e} / {io['cost_after']:.9e} "
+              f"cg {ig['cg_iters']} / {io['cg_iters']}", flush=True)
+        assert ig["status"] == 0 and ig["cg_breakdown"] == 0
+        assert abs(ig["cost_before"] - io["cost_before"]) <= tol * io["cost_before"], it
+        assert abs(ig["cost_after"] - io["cost_after"]) <= tol * io["cost_after"], it
+        assert ig["accepted"] == io["accepted"]
+        ptr, col = g.export(B.BA_X_S_PTR), g.export(B.BA_X_S_COL)
+        S, bS, dc = g.export(B.BA_X_S), g.export(B.BA_X_BS), g.export(B.BA_X_DC)
+        res = np.linalg.norm(spmv_upper(ptr, col, S, dc) - bS) / np.linalg.norm(bS)
+        assert res <= 1.05e-4 and abs(res - ig["cg_rel_resid"]) <= 1e-5, (it, res, ig["cg_rel_resid"])
+        del S
+
+
+# --------------------------------------------------------------------------
+# direct solve of the reduced camera system (Sec. IV-C-1, Cholesky)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("name", ["cfg0", "cfg3_small", "cfg3"])
+def test_cholesky_solve_matches_oracle(name):
+    """BA_SOLVER_CHOLESKY against the oracle's dense Cholesky solve: the step
+    (dc, dp) element by element within 1e-10 of its largest entry, the same
+    costs, accept flags and damping for every LM iteration, and the solve's
+    residual |b - S x| / |b| at round-off level."""
+    s = make_scene(3) if name == "cfg3" else scene_of(name)
+    g = gpu(s, linear_solver=B.BA_SOLVER_CHOLESKY)
+    o = orc(s, solver=1)
+    for it in range(6):
+        io, ig = o.lm_step(), g.lm_step()
+        print(f"  iter {it}: cost {ig['cost_after']:.12e} / {io['cost_after']:.12e} "
+              f"resid {ig['cg_rel_resid']:.2e}", flush=True)
+        assert ig["status"] == 0 and ig["cg_iters"] == 0
+        assert ig["cg_rel_resid"] <= 1e-11, it
+        if it == 0:
+            dc, dp, _ = o.step()
+            close(g.export(B.BA_X_DC), dc, 1e-10, "dc")
+            close(g.export(B.BA_X_DP), dp, 1e-10, "dp")
+        assert abs(ig["cost_before"] - io["cost_before"]) <= 1e-9 * io["cost_before"], it
+        assert abs(ig["cost_after"] - io["cost_after"]) <= 1e-9 * io["cost_after"], it
+        if abs(io["cost_before"] - io["cost_after"]) <= 1e-11 * io["cost_before"]:
+            break
+        assert ig["accepted"] == io["accepted"] and ig["lambda_next"] == io["lambda_next"], it
+
+
+def test_cholesky_solve_mixed_precision_and_timing():
+    """Mixed precision (FP32 off-diagonal blocks widened into the FP64
+    factorisation) tracks the FP64 oracle within 1e-4 over 5 iterations;
+    the per-step times of the direct solve and the PCG are printed."""
+    s = make_scene(3)
+    g = gpu(s, precision=B.BA_MIXED, linear_solver=B.BA_SOLVER_CHOLESKY)
+    o = orc(s, solver=1)
+    for it in range(5):
+        io, ig = o.lm_step(), g.lm_step()
+        assert ig["status"] == 0 and ig["cg_rel_resid"] <= 1e-6
+        assert abs(ig["cost_after"] - io["cost_after"]) <= 1e-4 * io["cost_after"], it
+    times = {}
+    for solver in (B.BA_SOLVER_CHOLESKY, B.BA_SOLVER_PCG):
+        p = gpu(s, linear_solver=solver)
+        p.lm_step()
+        p.set_profiling(True, phases=["pcg"])
+        p.set_params(s.cams0, s.pts0)
+        p.set_lambda(1e-4)
+        for _ in range(5):
+            p.lm_step()
+        times[solver] = p.phase_times()["pcg"][0] / 5
+        p.close()
+    print(f"  linear solve per LM step, 128 cameras: Cholesky {times[B.BA_SOLVER_CHOLESKY]:.3f} ms, "
+          f"PCG {times[B.BA_SOLVER_PCG]:.3f} ms", flush=True)

@@ -63,6 +63,12 @@ def test_loss_and_gradient_match_oracle(precision):
 
 
 def test_learned_blocks_match_oracle():
+    """The step's network runs its input and message layers on the matrix
+    cores with bfloat16 operands (FP32 sums).  Against the oracle's network
+    with the same operands rounded to bfloat16 (sums exact) the blocks agree
+    to FP32 summation plus the rare operand that FP32 and exact sums round to
+    neighbouring bfloat16 values (bound: 1e-2 of the correction's size); the
+    distance to the unrounded network is printed for scale."""
     s = make_scene(1, n_cams=40, n_pts=1500, seed=2)
     a = problem(s)
     a.lm_step()                                     # plain block-Jacobi: the reference system
@@ -73,33 +79,30 @@ def test_learned_blocks_match_oracle():
     info = b.lm_step()
     assert info["precond_used"] in (1, 2)
     Mg = b.export(B.BA_X_PRECOND)
-    Mo = G.precond_blocks(theta, g)
-    # the step's network runs its four hidden layers in BF16 (8-bit mantissa,
-    # FP32 accumulate): the correction to block-Jacobi carries a few percent
-    # of rounding (measured 2.3%); a wrong operand layout would be O(1)
-    err = np.linalg.norm(Mg - Mo) / np.linalg.norm(Mo)
+    Mo = G.precond_blocks(theta, g, bf16_inference=True)
+    Mx = G.precond_blocks(theta, g)
     dev = np.linalg.norm(Mo - np.linalg.inv(g["diag"])) / np.linalg.norm(Mo)
-    print(f"  learned blocks rel. error {err:.2e} (correction size {dev:.2e})", flush=True)
-    assert err <= 6e-2 * dev
+    err = np.linalg.norm(Mg - Mo) / np.linalg.norm(Mo)
+    err_x = np.linalg.norm(Mg - Mx) / np.linalg.norm(Mx)
+    print(f"  learned blocks rel. error {err:.2e} vs bf16 oracle, {err_x:.2e} vs exact network "
+          f"(correction size {dev:.2e})", flush=True)
+    assert err <= 1e-2 * dev
 
 
 def test_zero_output_layer_is_block_jacobi():
-    """A zero output layer gives the block-Jacobi blocks (to rounding: the
-    two paths sum the same products in different orders).  On the same first
-    system the PCG iteration counts then agree (to one iteration at a
-    rounding edge) and the loosely converged (rtol 1e-4) steps agree within
-    the CG round-off envelope (1e-6 relative cost)."""
+    """A zero output layer gives C = I, so M_i = L_i^-T L_i^-1: the learned
+    path's blocks equal the block-Jacobi blocks bit for bit, and the PCG and
+    LM iterates are then identical (three steps)."""
     s = make_scene(3, n_cams=40, n_pts=2500)
     a = problem(s, cg_variant=B.BA_CG_STANDARD)
     b = problem(s, cg_variant=B.BA_CG_STANDARD)
     b.set_gnn_params(PT.init_params(0))
-    ia, ib = a.lm_step(), b.lm_step()
-    assert ib["precond_used"] == 1
-    Ma = a.export(B.BA_X_PRECOND)
-    Mb = b.export(B.BA_X_PRECOND)
-    assert np.abs(Ma - Mb).max() <= 1e-12 * np.abs(Ma).max()
-    assert abs(ia["cg_iters"] - ib["cg_iters"]) <= 1
-    assert abs(ia["cost_after"] - ib["cost_after"]) <= 1e-6 * ia["cost_after"]
+    for it in range(3):
+        ia, ib = a.lm_step(), b.lm_step()
+        assert ib["precond_used"] == 1
+        assert np.array_equal(a.export(B.BA_X_PRECOND), b.export(B.BA_X_PRECOND)), it
+        assert ia["cg_iters"] == ib["cg_iters"] and ia["cost_after"] == ib["cost_after"], it
+        assert np.array_equal(a.export(B.BA_X_DC), b.export(B.BA_X_DC)), it
 
 
 def test_bad_learned_blocks_fall_back_to_block_jacobi():
@@ -120,34 +123,56 @@ def test_bad_learned_blocks_fall_back_to_block_jacobi():
         assert ib["cg_rel_resid"] <= 1e-4
 
 
-def test_training_on_the_stream_lowers_the_loss_and_cg_iterations():
-    """Twelve small stream scenes (200-260 cameras, 6,000 points): train on
-    eight systems, evaluate on four held-out ones.  The training and held-out
-    losses must fall by at least 10% from block-Jacobi's (the closed-form
-    block optimum gains 4-9% in PCG iterations, so the achievable loss drop
-    is modest); the PCG iteration counts to 1e-6 are reported and may not
-    exceed block-Jacobi's by more than 2% on average."""
+def closed_form_losses(p, n_cams):
+    """Loss at block-Jacobi (Mh = I) and at the best block-diagonal
+    correction (Mh = G^-1) of the problem's last system, from the oracle."""
+    g = oracle_graph(p, n_cams)
+    Gm = np.eye(9) + g["E"]
+    l0 = float(np.mean(np.trace(g["E"], axis1=1, axis2=2)))
+    lopt = float(np.mean(9.0 - np.trace(np.linalg.inv(Gm), axis1=1, axis2=2)))
+    return l0, lopt
+
+
+def test_training_on_the_stream_gains_over_block_jacobi():
+    """Stream scenes (laps of ~200 cameras with loop closures): train on the
+    systems of LM steps 1-5 of eight scenes, evaluate the five systems of
+    four held-out scenes.  The held-out loss must close at least half of the
+    gap between block-Jacobi and the closed-form block optimum; solving each
+    held-out system to 1e-6, the learned blocks need fewer PCG iterations
+    than block-Jacobi in total, and less wall-clock with the network's
+    inference included."""
     tr, te = [], []
     for k in range(12):
-        s, p = PT.stream_problem(1000 + k, precision=B.BA_MIXED, n_cams=200 + 5 * k, n_pts=6000)
+        s, p = PT.stream_problem(1000 + k, precision=B.BA_MIXED, n_cams=400 + 20 * k, n_pts=12000)
         (tr if k < 8 else te).append((s, p))
-    graphs = [PT.training_graph(p) for _, p in tr]
-    test_graphs = [PT.training_graph(p) for _, p in te]
+    graphs = sum((PT.training_graphs(p, 5) for _, p in tr), [])
+    test_graphs, gaps = [], []
+    for s, p in te:
+        for _ in range(5):
+            test_graphs.append(PT.training_graph(p))
+            gaps.append(closed_form_losses(p, s.n_cams))
     params = PT.init_params(0)
     l0 = PT.mean_loss(test_graphs, params)
-    hist = PT.train(graphs, params, epochs=150, lr=3e-3, log=print)
+    hist = PT.train(graphs, params, epochs=200, lr=3e-3, log=print)
     l1 = PT.mean_loss(test_graphs, params)
-    print(f"  held-out loss {l0:.5f} -> {l1:.5f}; training {hist[0]:.5f} -> {hist[-1]:.5f}", flush=True)
-    assert hist[-1] < 0.9 * hist[0]
-    assert l1 < 0.9 * l0
-    its = []
-    for s, p in te:
-        it_bj, ms_bj, _ = PT.solve_first_step(s, p, None)
-        it_l, ms_l, used = PT.solve_first_step(s, p, params)
-        print(f"  held-out nc={s.n_cams}: cg block-Jacobi {it_bj} ({ms_bj:.2f} ms) "
-              f"learned {it_l} ({ms_l:.2f} ms) used {used}", flush=True)
-        its.append((it_bj, it_l))
-    its = np.array(its, dtype=float)
-    print(f"  mean PCG iterations: block-Jacobi {its[:, 0].mean():.1f}, learned {its[:, 1].mean():.1f} "
-          f"({100 * (1 - its[:, 1].mean() / its[:, 0].mean()):+.1f}% fewer)", flush=True)
-    assert its[:, 1].mean() <= 1.02 * its[:, 0].mean()
+    l_id, l_opt = np.mean(gaps, axis=0)
+    print(f"  held-out loss {l0:.5f} -> {l1:.5f} (closed-form block optimum {l_opt:.5f}); "
+          f"training {hist[0]:.5f} -> {hist[-1]:.5f}", flush=True)
+    assert abs(l0 - l_id) <= 1e-3 * l_id
+    assert l0 - l1 >= 0.5 * (l0 - l_opt)
+    rows = []
+    for k in range(8, 12):
+        rows += PT.evaluate_scene(1000 + k, params, steps=5, n_cams=400 + 20 * k, n_pts=12000)
+    cg_bj = sum(r["cg_bj"] for r in rows)
+    cg_l = sum(r["cg_learned"] for r in rows)
+    ms_bj = sum(r["ms_bj"] for r in rows)
+    ms_l = sum(r["ms_learned"] for r in rows)
+    for r in rows:
+        print(f"  scene {r['scene']} step {r['step']}: cg FP64 {r['cg_fp64']} mixed {r['cg_bj']} "
+              f"learned {r['cg_learned']}; ms {r['ms_fp64']:.3f} / {r['ms_bj']:.3f} / "
+              f"{r['ms_learned']:.3f}", flush=True)
+    print(f"  held-out totals: PCG iterations block-Jacobi {cg_bj}, learned {cg_l}; "
+          f"ms block-Jacobi {ms_bj:.2f}, learned (network included) {ms_l:.2f}", flush=True)
+    assert all(r["resid_learned"] <= 1e-6 and r["used"] == 1 for r in rows)
+    assert cg_l < cg_bj
+    assert ms_l < ms_bj

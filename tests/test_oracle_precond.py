@@ -117,3 +117,35 @@ def test_pcg_counter_matches_c_oracle(system):
     k = G.pcg_iterations(ptr, col, S, bS, M, 1e-6, 2000)
     info = o.compute_step(rtol=1e-6, maxiter=2000)
     assert k == info["cg_iters"]
+
+
+def test_bf16_rounding_by_definition():
+    """Round-to-nearest-even onto 8 significant bits: exact values stay,
+    halfway cases go to the even neighbour, others to the nearest."""
+    one = 1.0
+    ulp = 2.0 ** -7                       # spacing of bfloat16 in [1, 2)
+    cases = [(one, one), (one + ulp, one + ulp), (one + ulp / 2, one),
+             (one + 3 * ulp / 2, one + 2 * ulp), (one + ulp / 2 + 2 ** -20, one + ulp),
+             (-3.0, -3.0), (0.0, 0.0), (2.0 ** -30 * 1.75, 2.0 ** -30 * 1.75)]
+    for x, want in cases:
+        assert G.bf16(x) == want, (x, G.bf16(x), want)
+
+
+def test_bf16_inference_equals_exact_when_operands_are_representable(system):
+    """With inputs and weights already on the bfloat16 grid the rounded
+    network's first layer is the exact one."""
+    s, o, ptr, col, S, bS = system
+    g = G.system_graph(ptr, col, S, s.n_cams)
+    rng = np.random.default_rng(5)
+    d = G.unpack(G.init_params(rng))
+    for k in d:
+        d[k][:] = G.bf16(d[k])
+        if k == "W_out":
+            d[k][:] = G.bf16(rng.normal(size=d[k].shape) * 0.05)
+    theta = G.pack(d)
+    # inputs on the grid too (the hidden activations are not: only the first layer is exact)
+    g2 = dict(g)
+    g2["X"] = G.bf16(g["X"])
+    o_exact, c_exact = G.forward(theta, g2)
+    o_b, c_b = G.forward(theta, g2, bf16_inference=True)
+    np.testing.assert_array_equal(c_b["z"][0], c_exact["z"][0])
