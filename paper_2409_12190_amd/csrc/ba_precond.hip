@@ -438,6 +438,62 @@ __global__ __launch_bounds__(256) void k_gnn_dense_bf16(int n, const float* __re
   }
 }
 
+// One message-passing layer of the inference, aggregation fused:
+//   M = sum_s w_s H_nbr(s) for the workgroup's 16 rows (into LDS), then
+//   Z = [H | M] [W_s | W_m]^T + b, H' = relu(Z) on the matrix cores as in
+//   k_gnn_dense_bf16 (the aggregated messages never go to memory).
+__global__ __launch_bounds__(256) void k_gnn_layer_bf16(int n, const int32_t* __restrict__ nbr_ptr,
+                                                         const int32_t* __restrict__ nbr,
+                                                         const float* __restrict__ wgt,
+                                                         const float* __restrict__ Hin,
+                                                         const short* __restrict__ Wb,
+                                                         const float* __restrict__ b,
+                                                         float* __restrict__ Hout) {
+  __shared__ float Ms[16][GNN_H + 4];
+  const int r0 = blockIdx.x * 16;
+  {
+    // thread t: row t / 16 of the workgroup, features 4 (t % 16) .. + 3
+    const int lr = threadIdx.x >> 4, f = 4 * (threadIdx.x & 15);
+    const int i = r0 + lr;
+    float m0 = 0.0f, m1 = 0.0f, m2 = 0.0f, m3 = 0.0f;
+    if (i < n) {
+      for (int s = nbr_ptr[i]; s < nbr_ptr[i + 1]; ++s) {
+        const float ws = wgt[s];
+        const float4 h = *reinterpret_cast<const float4*>(Hin + (size_t)nbr[s] * GNN_H + f);
+        m0 = fmaf(ws, h.x, m0);
+        m1 = fmaf(ws, h.y, m1);
+        m2 = fmaf(ws, h.z, m2);
+        m3 = fmaf(ws, h.w, m3);
+      }
+    }
+    Ms[lr][f] = m0;
+    Ms[lr][f + 1] = m1;
+    Ms[lr][f + 2] = m2;
+    Ms[lr][f + 3] = m3;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, t = threadIdx.x >> 6;
+  const int row = r0 + (lane & 15), kq = 4 * (lane >> 4);
+  f32x4 acc = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+  for (int kb = 0; kb < GNN_KHID; kb += 16) {
+    bf16x4 av;
+    for (int j = 0; j < 4; ++j) {
+      const int k = kb + kq + j;
+      float v = 0.0f;
+      if (row < n) v = k < GNN_H ? Hin[(size_t)row * GNN_H + k] : Ms[lane & 15][k - GNN_H];
+      av[j] = to_bf16(v);
+    }
+    const short* w = Wb + (size_t)(16 * t + (lane & 15)) * GNN_KHID + kb + kq;
+    const bf16x4 bv = {w[0], w[1], w[2], w[3]};
+    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc, 0, 0, 0);
+  }
+  const int col = 16 * t + (lane & 15);
+  for (int j = 0; j < 4; ++j) {
+    const int r = r0 + kq + j;
+    if (r < n) Hout[(size_t)r * GNN_H + col] = fmaxf(acc[j] + b[col], 0.0f);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
@@ -452,13 +508,11 @@ hipError_t launch_gnn_forward_bf16(const GraphDev& g, const float* P, const shor
   const dim3 grid((g.nc + 15) / 16), blk(256);
   hipLaunchKernelGGL(k_gnn_dense_bf16, grid, blk, 0, s, g.nc, g.X, GNN_F, (const float*)nullptr, Wb,
                      GNN_KIN, P + GNN_OFF_BIN, g.Z[0], g.H[0]);
-  const dim3 rows((g.nc + 3) / 4);
   for (int l = 0; l < GNN_L; ++l) {
     const short* Wl = Wb + GNN_H * GNN_KIN + (size_t)l * GNN_H * GNN_KHID;
     const float* bl = P + GNN_OFF_L0 + l * GNN_LAYER_SIZE + 2 * GNN_H * GNN_H;
-    hipLaunchKernelGGL(k_gnn_aggregate, rows, blk, 0, s, g.nc, g.nbr_ptr, g.nbr, g.w, g.H[l], g.M[l]);
-    hipLaunchKernelGGL(k_gnn_dense_bf16, grid, blk, 0, s, g.nc, g.H[l], GNN_H, g.M[l], Wl, GNN_KHID, bl,
-                       g.Z[l + 1], g.H[l + 1]);
+    hipLaunchKernelGGL(k_gnn_layer_bf16, grid, blk, 0, s, g.nc, g.nbr_ptr, g.nbr, g.w, g.H[l], Wl, bl,
+                       g.H[l + 1]);
   }
   return hipGetLastError();
 }
