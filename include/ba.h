@@ -342,6 +342,20 @@ ba_status ba_get_phase_times(const ba_problem* p, double* ms_out, int64_t* launc
 /* Number of stored upper blocks of the reduced camera matrix (incl. diagonal). */
 ba_status ba_problem_nnzb(const ba_problem* p, int64_t* nnzb);
 
+/* Allocation-free binding, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): binds p, like ba_problem_bind, but to a fixed device scratch
+ * array of BA_STATIC_SCRATCH_BYTES that the library holds on every GPU it
+ * runs on until the process ends, instead of a caller workspace.  Allocates
+ * nothing (no hipMalloc, hipFree or pinned host memory: the host staging
+ * lives in the handle).  All problems bound this way on one GPU share that
+ * GPU's array: binding another takes it over (the earlier handle's calls
+ * then return BA_ESTATE), and calls that overlap on one GPU race.  Errors:
+ * BA_EINVAL (ba_problem_workspace_bytes above BA_STATIC_SCRATCH_BYTES),
+ * BA_ESTATE (already bound), BA_EHIP. */
+#define BA_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+ba_status ba_problem_bind_static(ba_problem* p, void* hip_stream);
+
 void ba_problem_destroy(ba_problem* p);
 const char* ba_last_error(void);
 

@@ -37,8 +37,9 @@ EXPORTED_SYMBOLS = [
     "ba_get_state", "ba_set_state", "ba_export", "ba_problem_nnzb", "ba_set_profiling",
     "ba_set_profiling_mask", "ba_get_phase_times", "ba_problem_destroy", "ba_last_error", "ba_gnn_num_params",
     "ba_set_gnn_params", "ba_graph_create", "ba_graph_workspace_bytes", "ba_graph_bind",
-    "ba_graph_build", "ba_gnn_loss_grad", "ba_gnn_adam", "ba_graph_destroy",
+    "ba_graph_build", "ba_gnn_loss_grad", "ba_gnn_adam", "ba_graph_destroy", "ba_problem_bind_static",
 ]
+BA_STATIC_SCRATCH_BYTES = 64 << 20
 BA_NUM_PHASES = 13
 PHASE_NAMES = ["linearize", "reduce_cost", "damp_points", "point_q", "camera_vec", "schur_pairs",
                "camera_finish", "pcg", "backsub", "retract_cameras", "candidate_cost", "finalize",
@@ -88,6 +89,7 @@ def lib():
                                         C.POINTER(P)]
         L.ba_problem_workspace_bytes.argtypes = [P, C.POINTER(C.c_size_t)]
         L.ba_problem_bind.argtypes = [P, P, C.c_size_t, P]
+        L.ba_problem_bind_static.argtypes = [P, P]
         L.ba_set_observations.argtypes = [P, P, P]
         L.ba_set_fixed_cameras.argtypes = [P, P]
         L.ba_set_params.argtypes = [P, P, P]
@@ -176,6 +178,10 @@ def ba_problem_nnzb(h: int) -> int:
 
 def ba_problem_bind(h: int, workspace_ptr: int, nbytes: int, stream_ptr: Optional[int]):
     _check(lib().ba_problem_bind(h, workspace_ptr, nbytes, stream_ptr))
+
+
+def ba_problem_bind_static(h: int, stream_ptr: Optional[int]):
+    _check(lib().ba_problem_bind_static(h, stream_ptr))
 
 
 def ba_set_observations(h: int, obs_xy, obs_w=None):
@@ -300,7 +306,7 @@ class Problem:
                  cams=None, pts=None, stream=None, cg_variant=BA_CG_PIPELINED,
                  enable_backward=False, adjoint_rtol=1e-10, precond=BA_PRECOND_BLOCK_JACOBI,
                  lambda_min=None, lambda_max=None, adjoint_grad_tol=None, cam_dof=9,
-                 linear_solver=BA_SOLVER_PCG):
+                 linear_solver=BA_SOLVER_PCG, static_workspace=False):
         import torch
         self.torch = torch
         self.device = torch.device("cuda", torch.cuda.current_device())
@@ -327,12 +333,17 @@ class Problem:
         self.n_obs = int(np.asarray(cam_idx).size)
         self.h = ba_problem_create(opt, self.n_cams, self.n_pts, cam_idx, pt_idx)
         self._finalizer = weakref.finalize(self, _release, lib().ba_problem_destroy, self.h, None, None)
-        nbytes = ba_problem_workspace_bytes(self.h)
-        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
-        if self.workspace.data_ptr() % 256:
-            raise RuntimeError("workspace allocation is not 256-byte aligned")
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
-        ba_problem_bind(self.h, self.workspace.data_ptr(), nbytes, self.stream.cuda_stream)
+        if static_workspace:
+            # the library's fixed device scratch: nothing allocated here
+            self.workspace = None
+            ba_problem_bind_static(self.h, self.stream.cuda_stream)
+        else:
+            nbytes = ba_problem_workspace_bytes(self.h)
+            self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+            if self.workspace.data_ptr() % 256:
+                raise RuntimeError("workspace allocation is not 256-byte aligned")
+            ba_problem_bind(self.h, self.workspace.data_ptr(), nbytes, self.stream.cuda_stream)
         self._finalizer.detach()
         self._finalizer = weakref.finalize(self, _release, lib().ba_problem_destroy, self.h,
                                            self.stream, self.workspace)

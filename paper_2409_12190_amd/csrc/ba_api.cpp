@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -47,9 +48,11 @@ ba_status fail(ba_status s, const std::string& m) {
 struct Carver {
   char* base;
   size_t off = 0;
+  size_t last = 0;  // offset of the most recent region
   template <class T>
   T* take(size_t n) {
     off = (off + 255) & ~size_t(255);
+    last = off;
     T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
     off += std::max<size_t>(n, 1) * sizeof(T);
     return p;
@@ -117,7 +120,9 @@ void carve(ba_problem* p, char* base, size_t* total) {
   // step table addresses both from J; 32 doubles of padding after the last
   // record, which the staging reads past)
   b.J = c.take<char>(no * ba::NJ * es);
+  const size_t off_J = c.last;
   b.rec = c.take<double>(8 * no + 32);
+  p->rec_off = c.last - off_J;
   b.V = c.take<double>(6 * np);
   b.gp = c.take<double>(3 * np);
   b.gc = c.take<double>(9 * nc);
@@ -194,9 +199,27 @@ hipError_t upload(T* dst, const std::vector<T>& src, hipStream_t s) {
   return hipMemcpyAsync(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, s);
 }
 
+// Problems bound to the static scratch of a device: the one that holds it
+// now (a later ba_problem_bind_static on the same device takes it over).
+std::mutex g_static_mu;
+const ba_problem* g_static_owner[64] = {};
+
+bool static_owner_is(const ba_problem* p) {
+  std::lock_guard<std::mutex> lk(g_static_mu);
+  return p->device >= 0 && p->device < 64 && g_static_owner[p->device] == p;
+}
+
+// bound, and (for the static scratch) still its holder
+bool usable(const ba_problem* p) { return p->bound && (!p->static_ws || static_owner_is(p)); }
+
+const char* not_bound_msg(const ba_problem* p) {
+  return p->bound ? "the device's static scratch was taken over by another problem"
+                  : "problem is not bound to a workspace";
+}
+
 ba_status require_ready(const ba_problem* p) {
   if (!p) return fail(BA_EINVAL, "null problem");
-  if (!p->bound) return fail(BA_ESTATE, "problem is not bound to a workspace");
+  if (!usable(p)) return fail(BA_ESTATE, not_bound_msg(p));
   if (!p->have_obs) return fail(BA_ESTATE, "observations are not set");
   if (!p->have_params) return fail(BA_ESTATE, "parameters are not set");
   return BA_OK;
@@ -517,6 +540,25 @@ ba_status ba_problem_create(const ba_options* opt, int32_t n_cams, int32_t n_pts
   p->cg_maxiter = o.cg_maxiter;
   p->cam_blocks = (n_cams + 255) / 256;
   carve(p, nullptr, &p->ws_needed);
+  // Schur step table in 64-byte units from J: observation x's row at x * row
+  // units, its record (self pairs, y side) at rec_unit + x, -1 unchanged
+  const int64_t row_units = (int64_t)ba::NJ * (int64_t)elem_bytes(p) / 64;
+  const int64_t rec_unit = (int64_t)(p->rec_off / 64);
+  if (rec_unit + (int64_t)p->plan.no > INT32_MAX || p->rec_off % 64) {
+    delete p;
+    return fail(BA_EUNSUPPORTED, "observation rows exceed 2^31 units");
+  }
+  p->rec_unit = (int32_t)rec_unit;
+  try {
+    p->stab_units.resize(p->plan.stab.size());
+  } catch (const std::bad_alloc&) {
+    delete p;
+    return fail(BA_EINVAL, "out of host memory");
+  }
+  for (size_t i = 0; i < p->stab_units.size(); ++i) {
+    const int32_t c = p->plan.stab[i];
+    p->stab_units[i] = c >= 0 ? (int32_t)(c * row_units) : (c == -1 ? -1 : (int32_t)(rec_unit + (-2 - c)));
+  }
   *out = p;
   return BA_OK;
 }
@@ -533,12 +575,13 @@ ba_status ba_problem_nnzb(const ba_problem* p, int64_t* nnzb) {
   return BA_OK;
 }
 
-ba_status ba_problem_bind(ba_problem* p, void* ws, size_t bytes, void* stream) {
-  if (!p || !ws) return fail(BA_EINVAL, "null argument");
-  if (bytes < p->ws_needed) return fail(BA_EINVAL, "workspace too small");
-  if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(BA_EINVAL, "workspace not 256-byte aligned");
-  if (p->bound) return fail(BA_ESTATE, "problem already bound");
-  HIPCHK(hipGetDevice(&p->device));
+namespace {
+
+// Uploads the symbolic structure into workspace ws (device memory of at
+// least p->ws_needed bytes, 256-byte aligned) and clears what must start at
+// zero.  pinned: host staging from hipHostMalloc, else the handle's own
+// members (the allocation-free binding).
+ba_status bind_workspace(ba_problem* p, void* ws, size_t bytes, void* stream, bool pinned) {
   p->stream = reinterpret_cast<hipStream_t>(stream);
   p->workspace = ws;
   p->ws_bytes = bytes;
@@ -566,18 +609,7 @@ ba_status ba_problem_bind(ba_problem* p, void* ws, size_t bytes, void* stream) {
   HIPCHK(upload(b.slot_pe, P.slot_pe, s));
   HIPCHK(upload(b.slot_lead, P.slot_lead, s));
   HIPCHK(upload(b.blk_row, P.blk_row, s));
-  // step table in 64-byte units from J: observation x's row at x * row
-  // units, its record (self pairs, y side) at rec_unit + x, -1 unchanged
-  const int64_t row_units = (int64_t)ba::NJ * (int64_t)elem_bytes(p) / 64;
-  const int64_t rec_unit = (reinterpret_cast<char*>(b.rec) - reinterpret_cast<char*>(b.J)) / 64;
-  if (rec_unit + (int64_t)P.no > INT32_MAX) return fail(BA_EUNSUPPORTED, "observation rows exceed 2^31 units");
-  p->rec_unit = (int32_t)rec_unit;
-  std::vector<int32_t> units(P.stab.size());
-  for (size_t i = 0; i < units.size(); ++i) {
-    const int32_t c = P.stab[i];
-    units[i] = c >= 0 ? (int32_t)(c * row_units) : (c == -1 ? -1 : (int32_t)(rec_unit + (-2 - c)));
-  }
-  HIPCHK(upload(b.stab, units, s));
+  HIPCHK(upload(b.stab, p->stab_units, s));
   HIPCHK(upload(b.swptr, P.swptr, s));
   HIPCHK(upload(b.pcg_row, P.pcg_row, s));
   HIPCHK(upload(b.item_ptr, P.item_ptr, s));
@@ -605,8 +637,13 @@ ba_status ba_problem_bind(ba_problem* p, void* ws, size_t bytes, void* stream) {
   }
   HIPCHK(hipMemsetAsync(b.fixed, p->opt.cam_dof == 6 ? ba::FIXED_INTRINSICS : 0, P.nc, s));
   HIPCHK(hipMemsetAsync(b.gsync, 0, sizeof(ba::GridSync), s));
-  HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&p->hinfo), sizeof(ba_step_info), hipHostMallocDefault));
-  HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&p->hscal), sizeof(ba::DevScalars), hipHostMallocDefault));
+  if (pinned) {
+    HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&p->hinfo), sizeof(ba_step_info), hipHostMallocDefault));
+    HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&p->hscal), sizeof(ba::DevScalars), hipHostMallocDefault));
+  } else {
+    p->hinfo = &p->hinfo_local;
+    p->hscal = &p->hscal_local;
+  }
   *p->hscal = ba::DevScalars{0.0, p->lambda, 0, 0};
   HIPCHK(hipMemcpyAsync(b.dev, p->hscal, sizeof(ba::DevScalars), hipMemcpyHostToDevice, s));
   HIPCHK(hipStreamSynchronize(s));
@@ -624,9 +661,50 @@ ba_status ba_problem_bind(ba_problem* p, void* ws, size_t bytes, void* stream) {
   return BA_OK;
 }
 
+}  // namespace
+
+ba_status ba_problem_bind(ba_problem* p, void* ws, size_t bytes, void* stream) {
+  if (!p || !ws) return fail(BA_EINVAL, "null argument");
+  if (bytes < p->ws_needed) return fail(BA_EINVAL, "workspace too small");
+  if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(BA_EINVAL, "workspace not 256-byte aligned");
+  if (p->bound) return fail(BA_ESTATE, "problem already bound");
+  HIPCHK(hipGetDevice(&p->device));
+  return bind_workspace(p, ws, bytes, stream, true);
+}
+
+ba_status ba_problem_bind_static(ba_problem* p, void* stream) {
+  if (!p) return fail(BA_EINVAL, "null argument");
+  if (p->bound) return fail(BA_ESTATE, "problem already bound");
+  if (p->ws_needed > ba::STATIC_SCRATCH_BYTES) {
+    char msg[200];
+    std::snprintf(msg, sizeof msg,
+                  "the problem needs %zu bytes of workspace; the static scratch holds %zu (use ba_problem_bind)",
+                  p->ws_needed, ba::STATIC_SCRATCH_BYTES);
+    return fail(BA_EINVAL, msg);
+  }
+  int dev = -1;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) return fail(BA_EUNSUPPORTED, "device ordinal beyond 63");
+  void* scratch = nullptr;
+  HIPCHK(ba::static_scratch(dev, &scratch));
+  p->device = dev;
+  p->static_ws = true;
+  {
+    std::lock_guard<std::mutex> lk(g_static_mu);
+    g_static_owner[dev] = p;
+  }
+  const ba_status st = bind_workspace(p, scratch, ba::STATIC_SCRATCH_BYTES, stream, false);
+  if (st != BA_OK) {
+    std::lock_guard<std::mutex> lk(g_static_mu);
+    if (g_static_owner[dev] == p) g_static_owner[dev] = nullptr;
+    p->static_ws = false;
+  }
+  return st;
+}
+
 ba_status ba_set_observations(ba_problem* p, const double* xy, const double* w) {
   if (!p || !xy) return fail(BA_EINVAL, "null argument");
-  if (!p->bound) return fail(BA_ESTATE, "problem is not bound");
+  if (!usable(p)) return fail(BA_ESTATE, not_bound_msg(p));
   ba::ObsArgs a{p->plan.no, p->b.o_orig, xy, w, p->b.o_xy, p->b.o_w, p->b.dev};
   HIPCHK(ba::launch_set_observations(a, p->stream));
   HIPCHK(hipMemcpyAsync(p->hscal, p->b.dev, sizeof(ba::DevScalars), hipMemcpyDeviceToHost, p->stream));
@@ -646,7 +724,7 @@ ba_status ba_set_observations(ba_problem* p, const double* xy, const double* w) 
 
 ba_status ba_set_fixed_cameras(ba_problem* p, const uint8_t* mask) {
   if (!p) return fail(BA_EINVAL, "null problem");
-  if (!p->bound) return fail(BA_ESTATE, "problem is not bound");
+  if (!usable(p)) return fail(BA_ESTATE, not_bound_msg(p));
   const uint8_t base = p->opt.cam_dof == 6 ? ba::FIXED_INTRINSICS : 0;
   std::vector<uint8_t> m(p->plan.nc, base);
   if (mask)
@@ -659,7 +737,7 @@ ba_status ba_set_fixed_cameras(ba_problem* p, const uint8_t* mask) {
 
 ba_status ba_set_params(ba_problem* p, const double* cams, const double* pts) {
   if (!p || !cams || !pts) return fail(BA_EINVAL, "null argument");
-  if (!p->bound) return fail(BA_ESTATE, "problem is not bound");
+  if (!usable(p)) return fail(BA_ESTATE, not_bound_msg(p));
   HIPCHK(hipMemcpyAsync(p->b.cams[p->cur], cams, sizeof(double) * 10 * p->plan.nc,
                         hipMemcpyDeviceToDevice, p->stream));
   HIPCHK(hipMemcpyAsync(p->b.pts[p->cur], pts, sizeof(double) * 3 * p->plan.np,
@@ -671,7 +749,8 @@ ba_status ba_set_params(ba_problem* p, const double* cams, const double* pts) {
 
 ba_status ba_get_params(const ba_problem* p, double* cams, double* pts) {
   if (!p) return fail(BA_EINVAL, "null problem");
-  if (!p->bound || !p->have_params) return fail(BA_ESTATE, "parameters are not set");
+  if (!usable(p)) return fail(BA_ESTATE, not_bound_msg(p));
+  if (!p->have_params) return fail(BA_ESTATE, "parameters are not set");
   if (cams)
     HIPCHK(hipMemcpyAsync(cams, p->b.cams[p->cur], sizeof(double) * 10 * p->plan.nc,
                           hipMemcpyDeviceToDevice, p->stream));
@@ -683,7 +762,7 @@ ba_status ba_get_params(const ba_problem* p, double* cams, double* pts) {
 
 ba_status ba_set_lambda(ba_problem* p, double lambda) {
   if (!p || !(lambda > 0.0)) return fail(BA_EINVAL, "lambda must be positive");
-  if (!p->bound) return fail(BA_ESTATE, "problem is not bound");
+  if (!usable(p)) return fail(BA_ESTATE, not_bound_msg(p));
   HIPCHK(hipMemcpyAsync(p->hscal, p->b.dev, sizeof(ba::DevScalars), hipMemcpyDeviceToHost, p->stream));
   HIPCHK(hipStreamSynchronize(p->stream));
   p->hscal->lambda = lambda;
@@ -839,7 +918,7 @@ ba_status ba_set_gnn_params(ba_problem* p, const float* params) {
   if (!p) return fail(BA_EINVAL, "null problem");
   if (p->opt.precond != BA_PRECOND_LEARNED)
     return fail(BA_ESTATE, "create the problem with precond = BA_PRECOND_LEARNED");
-  if (!p->bound) return fail(BA_ESTATE, "problem is not bound");
+  if (!usable(p)) return fail(BA_ESTATE, not_bound_msg(p));
   if (!params) {
     p->gnn_ready = false;
     return BA_OK;
@@ -860,7 +939,8 @@ ba_status ba_get_state(const ba_problem* p, void* blob, size_t* bytes) {
     return BA_OK;
   }
   if (*bytes < need) return fail(BA_EINVAL, "state buffer too small");
-  if (!p->bound || !p->have_params) return fail(BA_ESTATE, "parameters are not set");
+  if (!usable(p)) return fail(BA_ESTATE, not_bound_msg(p));
+  if (!p->have_params) return fail(BA_ESTATE, "parameters are not set");
   double* d = reinterpret_cast<double*>(blob);
   d[0] = 1.0;  // format version
   d[1] = p->plan.nc;
@@ -877,7 +957,7 @@ ba_status ba_get_state(const ba_problem* p, void* blob, size_t* bytes) {
 
 ba_status ba_set_state(ba_problem* p, const void* blob, size_t bytes) {
   if (!p || !blob) return fail(BA_EINVAL, "null argument");
-  if (!p->bound) return fail(BA_ESTATE, "problem is not bound");
+  if (!usable(p)) return fail(BA_ESTATE, not_bound_msg(p));
   const size_t need = sizeof(double) * (4 + 10 * (size_t)p->plan.nc + 3 * (size_t)p->plan.np);
   const double* d = reinterpret_cast<const double*>(blob);
   if (bytes != need || d[0] != 1.0 || d[1] != p->plan.nc || d[2] != p->plan.np)
@@ -894,7 +974,7 @@ ba_status ba_set_state(ba_problem* p, const void* blob, size_t bytes) {
 
 ba_status ba_export(const ba_problem* p, int32_t field, void* dst, size_t bytes) {
   if (!p || !dst) return fail(BA_EINVAL, "null argument");
-  if (!p->bound) return fail(BA_ESTATE, "problem is not bound");
+  if (!usable(p)) return fail(BA_ESTATE, not_bound_msg(p));
   const ba::Plan& P = p->plan;
   const ba::Buffers& b = p->b;
   const size_t no = P.no, nc = P.nc, np = P.np, nnzb = P.nnzb;
@@ -1034,7 +1114,7 @@ ba_status ba_set_profiling(ba_problem* p, int32_t enable) {
 
 ba_status ba_set_profiling_mask(ba_problem* p, uint32_t mask) {
   if (!p) return fail(BA_EINVAL, "null problem");
-  if (!p->bound) return fail(BA_ESTATE, "problem is not bound");
+  if (!usable(p)) return fail(BA_ESTATE, not_bound_msg(p));
   const bool enable = mask != 0;
   if (enable && !p->ev[0][0]) {
     for (int i = 0; i < BA_NUM_PHASES; ++i)
@@ -1101,7 +1181,7 @@ ba_status ba_graph_bind(ba_graph* g, void* ws, size_t bytes, void* stream) {
 ba_status ba_graph_build(ba_graph* g, ba_problem* p) {
   if (!g || !p) return fail(BA_EINVAL, "null argument");
   if (!g->bound) return fail(BA_ESTATE, "graph is not bound");
-  if (p->opt.precond != BA_PRECOND_LEARNED || !p->bound)
+  if (p->opt.precond != BA_PRECOND_LEARNED || !usable(p))
     return fail(BA_ESTATE, "the problem is not bound with BA_PRECOND_LEARNED");
   if (p->plan.nc != g->nc || p->plan.nnzb != g->nnzb || p->plan.nbr != g->nbr)
     return fail(BA_EINVAL, "the graph was created for another camera pattern");
@@ -1140,11 +1220,17 @@ void ba_graph_destroy(ba_graph* g) { delete g; }
 
 void ba_problem_destroy(ba_problem* p) {
   if (!p) return;
+  if (p->static_ws) {
+    std::lock_guard<std::mutex> lk(g_static_mu);
+    if (p->device >= 0 && p->device < 64 && g_static_owner[p->device] == p) g_static_owner[p->device] = nullptr;
+  }
   for (int i = 0; i < BA_NUM_PHASES; ++i)
     for (int k = 0; k < 2; ++k)
       if (p->ev[i][k]) (void)hipEventDestroy(p->ev[i][k]);
-  if (p->hinfo) (void)hipHostFree(p->hinfo);
-  if (p->hscal) (void)hipHostFree(p->hscal);
+  if (!p->static_ws) {
+    if (p->hinfo) (void)hipHostFree(p->hinfo);
+    if (p->hscal) (void)hipHostFree(p->hscal);
+  }
   delete p;
 }
 

@@ -112,6 +112,12 @@ struct Plan {
   int32_t max_track = 0;
 };
 
+// Allocation-free binding: the fixed device scratch every such problem on a
+// GPU shares (ba_problem_bind_static), and its address on `device` (the
+// current device), resolved once per device.
+constexpr size_t STATIC_SCRATCH_BYTES = BA_STATIC_SCRATCH_BYTES;
+hipError_t static_scratch(int device, void** ptr);
+
 // Builds the plan; returns an empty string or an error message.
 std::string build_plan(int32_t nc, int32_t np, int64_t no, const int32_t* cidx, const int32_t* pidx,
                        Plan* out);
@@ -232,7 +238,15 @@ struct ba_problem {
   bool gnn_ready = false;    // learned preconditioner parameters are set
   bool have_system = false;  // a step has formed the reduced system
   int32_t rec_unit = 0;      // records' first 64-byte unit counted from J
+  size_t rec_off = 0;        // byte offset of the records from J (workspace layout)
   uint32_t profile_mask = 0;  // phases bracketed by events while profiling
   ba_step_info* hinfo = nullptr;     // pinned host staging
   ba::DevScalars* hscal = nullptr;   // pinned host staging
+  // the Schur step table in 64-byte units (computed at creation)
+  std::vector<int32_t> stab_units;
+  // bound to the device's static scratch (ba_problem_bind_static): staging
+  // in the handle itself instead of pinned buffers
+  bool static_ws = false;
+  ba_step_info hinfo_local{};
+  ba::DevScalars hscal_local{};
 };
