@@ -116,7 +116,7 @@ def timed_solve(problem: B.Problem, blob: bytes, rtol: float, maxiter: int, para
     return best
 
 
-def evaluate_scene(seed: int, params, steps: int = 5, rtol: float = 1e-6, maxiter: int = 1000,
+def evaluate_scene(seed: int, params, steps: int = 5, rtol: float = 1e-6, maxiter: int = 3000,
                    n_cams=None, n_pts=None):
     """Rows (step, cg and ms of FP64 block-Jacobi, mixed block-Jacobi, learned)
     for LM steps 1..steps of held-out scene `seed`: the trajectory is the
