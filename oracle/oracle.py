@@ -15,6 +15,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "ba_oracle.c")
+_SRC_PGO = os.path.join(_HERE, "pgo_oracle.c")
 _LIB_PATH = os.path.join(_HERE, "libba_oracle.so")
 
 
@@ -24,7 +25,7 @@ def build(force: bool = True) -> str:
     if force or not os.path.exists(_LIB_PATH):
         tmp = _LIB_PATH + ".tmp"
         subprocess.check_call(["gcc", "-O3", "-std=gnu99", "-fPIC", "-shared", "-fopenmp",
-                               "-ffp-contract=off", "-Wall", "-o", tmp, _SRC, "-lm"])
+                               "-ffp-contract=off", "-Wall", "-o", tmp, _SRC, _SRC_PGO, "-lm"])
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
 
@@ -299,3 +300,120 @@ class Oracle:
         if st != 0:
             raise RuntimeError(f"oracle backward failed ({st})")
         return dx, dw, vc, vp
+
+
+# ---- pose graph optimisation (pgo_oracle.c) ------------------------------------
+
+class PgoOptions(C.Structure):
+    _fields_ = [("cg_rtol", C.c_double), ("cg_maxiter", C.c_int32), ("lambda0", C.c_double),
+                ("lambda_min", C.c_double), ("lambda_max", C.c_double), ("diag_min", C.c_double),
+                ("diag_max", C.c_double), ("solver", C.c_int32)]
+
+
+def _pgo_lib():
+    L = lib()
+    if not getattr(L, "_pgo_bound", False):
+        P = C.c_void_p
+        L.orc_pgo_create.restype = P
+        L.orc_pgo_create.argtypes = [C.POINTER(PgoOptions), C.c_int32, C.c_int32, P, P, P, P, P]
+        L.orc_pgo_destroy.argtypes = [P]
+        L.orc_pgo_set_poses.argtypes = [P, P]
+        L.orc_pgo_get_poses.argtypes = [P, P]
+        L.orc_pgo_set_lambda.argtypes = [P, C.c_double]
+        L.orc_pgo_nnzb.argtypes = [P]
+        L.orc_pgo_nnzb.restype = C.c_int64
+        L.orc_pgo_cost.argtypes = [P, P]
+        L.orc_pgo_cost.restype = C.c_double
+        L.orc_pgo_lm_step.argtypes = [P, C.c_double, C.c_int32, C.POINTER(StepInfo)]
+        L.orc_pgo_get_system.argtypes = [P, P, P, P, P, P]
+        L.orc_pgo_edge.argtypes = [P, P, P, P, P]
+        L.orc_pgo_retract.argtypes = [P, P, P]
+        L.orc_se3_jl_inv.argtypes = [P, P]
+        L._pgo_bound = True
+    return L
+
+
+def pgo_edge(Zi, Zj, T):
+    """(r[6], d r / d delta_j [6, 6]) of one edge (d r / d delta_i = -that)."""
+    Zi, Zj, T = (np.ascontiguousarray(a, np.float64) for a in (Zi, Zj, T))
+    r = np.zeros(6)
+    J = np.zeros((6, 6))
+    _pgo_lib().orc_pgo_edge(_p(Zi), _p(Zj), _p(T), _p(r), _p(J))
+    return r, J
+
+
+def pgo_retract(Z, delta):
+    Z, delta = np.ascontiguousarray(Z, np.float64), np.ascontiguousarray(delta, np.float64)
+    out = np.zeros(7)
+    _pgo_lib().orc_pgo_retract(_p(Z), _p(delta), _p(out))
+    return out
+
+
+def se3_jl_inv(xi):
+    xi = np.ascontiguousarray(xi, np.float64)
+    out = np.zeros((6, 6))
+    _pgo_lib().orc_se3_jl_inv(_p(xi), _p(out))
+    return out
+
+
+class PgoOracle:
+    """One pose graph held by the C oracle."""
+
+    def __init__(self, graph, cg_rtol=1e-4, cg_maxiter=250, lambda0=1e-4, lambda_min=1e-12,
+                 lambda_max=1e12, diag_min=1e-6, diag_max=1e32, solver=0):
+        self._opt = PgoOptions(cg_rtol, cg_maxiter, lambda0, lambda_min, lambda_max, diag_min,
+                               diag_max, solver)
+        self.n, self.m = int(graph.n_poses), int(graph.n_edges)
+        self._i = np.ascontiguousarray(graph.ei, np.int32)
+        self._j = np.ascontiguousarray(graph.ej, np.int32)
+        self._T = np.ascontiguousarray(graph.T, np.float64)
+        self._O = np.ascontiguousarray(graph.omega, np.float64)
+        fx = np.zeros(self.n, np.uint8)
+        if graph.fixed is not None and len(graph.fixed):
+            fx[np.asarray(graph.fixed)] = 1
+        self._fx = fx
+        self._h = _pgo_lib().orc_pgo_create(C.byref(self._opt), self.n, self.m, _p(self._i), _p(self._j),
+                                            _p(self._T), _p(self._O), _p(self._fx))
+        self.set_poses(graph.poses0)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            _pgo_lib().orc_pgo_destroy(h)
+            self._h = None
+
+    def set_poses(self, Z):
+        Z = np.ascontiguousarray(Z, np.float64)
+        _pgo_lib().orc_pgo_set_poses(self._h, _p(Z))
+
+    def get_poses(self):
+        Z = np.zeros((self.n, 7))
+        _pgo_lib().orc_pgo_get_poses(self._h, _p(Z))
+        return Z
+
+    @property
+    def lam(self):
+        raise AttributeError("write-only")
+
+    @lam.setter
+    def lam(self, v):
+        _pgo_lib().orc_pgo_set_lambda(self._h, float(v))
+
+    def cost(self, Z=None):
+        Z = self.get_poses() if Z is None else np.ascontiguousarray(Z, np.float64)
+        return _pgo_lib().orc_pgo_cost(self._h, _p(Z))
+
+    def lm_step(self, rtol: float = -1.0, maxiter: int = -1) -> dict:
+        info = StepInfo()
+        _pgo_lib().orc_pgo_lm_step(self._h, rtol, maxiter, C.byref(info))
+        return info.as_dict()
+
+    def system(self):
+        nnzb = int(_pgo_lib().orc_pgo_nnzb(self._h))
+        ptr = np.zeros(self.n + 1, np.int64)
+        col = np.zeros(nnzb, np.int32)
+        H = np.zeros((nnzb, 6, 6))
+        g = np.zeros((self.n, 6))
+        dx = np.zeros((self.n, 6))
+        _pgo_lib().orc_pgo_get_system(self._h, _p(ptr), _p(col), _p(H), _p(g), _p(dx))
+        return ptr, col, H, g, dx
