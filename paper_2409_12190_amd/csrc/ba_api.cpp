@@ -130,11 +130,11 @@ void carve(ba_problem* p, char* base, size_t* total) {
   b.Vinv = c.take<double>(6 * np);
   b.ep = c.take<double>(3 * np);
   b.S = c.take<char>(nnzb * 81 * es);
-  // streamed PCG plans (mixed precision, pipelined recurrence): one FP32
-  // copy of each upper off-diagonal block, the column-sum exchange
-  const bool stream = !P.pcg_resident && p->opt.precision == BA_MIXED && P.sgrid > 0 &&
-                      p->opt.cg_variant == BA_CG_PIPELINED;
-  b.SI = c.take<char>(stream ? P.sitem_col.size() * ba::SI_STRIDE * 4 : 0);
+  // streamed PCG plans (pipelined recurrence): one copy of each upper
+  // off-diagonal block in the storage precision, the column-sum exchange
+  const bool stream = !P.pcg_resident && P.sgrid > 0 && p->opt.cg_variant == BA_CG_PIPELINED &&
+                      p->opt.linear_solver == BA_SOLVER_PCG;
+  b.SI = c.take<char>(stream ? P.sitem_col.size() * ba::SI_STRIDE * es : 0);
   b.Sdiag = c.take<double>(81 * nc);
   b.bS = c.take<double>(9 * nc);
   b.Minv = c.take<double>(81 * nc);
@@ -293,11 +293,11 @@ hipError_t reset_sync(ba_problem* p) {
   return hipMemsetAsync(p->b.gsync, 0, sizeof(ba::GridSync), p->stream);
 }
 
-// mixed-precision plans whose pipelined PCG streams its blocks (an FP32 copy
-// of each upper off-diagonal block written by the Schur kernel)
+// plans whose pipelined PCG streams its blocks (a copy of each upper
+// off-diagonal block, in the storage precision, written by the Schur kernel)
 bool streamed(const ba_problem* p) {
-  return !p->plan.pcg_resident && p->opt.precision == BA_MIXED && p->plan.sgrid > 0 &&
-         p->opt.cg_variant == BA_CG_PIPELINED;
+  return !p->plan.pcg_resident && p->plan.sgrid > 0 && p->opt.cg_variant == BA_CG_PIPELINED &&
+         p->opt.linear_solver == BA_SOLVER_PCG;
 }
 
 template <typename T>
@@ -650,7 +650,7 @@ ba_status bind_workspace(ba_problem* p, void* ws, size_t bytes, void* stream, bo
   const bool pipe = p->opt.cg_variant == BA_CG_PIPELINED;
   const int maxg = p->opt.precision == BA_MIXED
                        ? ba::pcg_max_grid<float>(P.pcg_resident, pipe, streamed(p))
-                       : ba::pcg_max_grid<double>(P.pcg_resident, pipe);
+                       : ba::pcg_max_grid<double>(P.pcg_resident, pipe, streamed(p));
   if (maxg <= 0) return fail(BA_EHIP, "cooperative occupancy query failed");
   p->pcg_grid = streamed(p) ? P.sgrid : P.pcg_grid;
   if (p->pcg_grid > maxg || p->pcg_grid > ba::MAX_BARRIER_GROUPS * ba::BARRIER_FANIN)

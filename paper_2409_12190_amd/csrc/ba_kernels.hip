@@ -303,10 +303,10 @@ __global__ __launch_bounds__(CHUNK) void k_linearize(LinArgs a) {
 }
 
 // F = sum of the chunk partials (fixed order), and the gradient max over points.
-__global__ __launch_bounds__(256) void k_reduce_cost(const double* __restrict__ part, int n,
-                                                     DevScalars* dev) {
-  __shared__ double red[4];
-  const double F = block_sum_array(part, n, red);
+__global__ __launch_bounds__(1024) void k_reduce_cost(const double* __restrict__ part, int n,
+                                                      DevScalars* dev) {
+  __shared__ double red[16];
+  const double F = block_sum_array4(part, n, red);
   if (threadIdx.x == 0) dev->F = F;
 }
 
@@ -912,7 +912,7 @@ template hipError_t launch_linearize<float>(const LinArgs&, int, hipStream_t);
 template hipError_t launch_linearize<double>(const LinArgs&, int, hipStream_t);
 
 hipError_t launch_reduce_cost(const double* part, int n, DevScalars* dev, hipStream_t s) {
-  hipLaunchKernelGGL(k_reduce_cost, dim3(1), dim3(256), 0, s, part, n, dev);
+  hipLaunchKernelGGL(k_reduce_cost, dim3(1), dim3(1024), 0, s, part, n, dev);
   return hipGetLastError();
 }
 

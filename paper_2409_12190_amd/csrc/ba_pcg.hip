@@ -626,18 +626,20 @@ __global__ __launch_bounds__(PCG_THREADS) void k_pcg_pipelined(PcgArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// Pipelined PCG with streamed blocks (mixed precision; plans whose block rows
-// do not fit the lanes' registers, e.g. the 10,000-camera scene).  Each upper
-// off-diagonal block S_ab (a < b) is read once per product, by the workgroup
-// that owns row a, from an FP32 copy padded to SI_STRIDE values (written by
-// the Schur kernel; a workgroup's blocks contiguous in row order).  These
-// plans have their own row decomposition, balanced by upper blocks.
+// Pipelined PCG with streamed blocks (plans whose block rows do not fit the
+// lanes' registers, e.g. the 10,000-camera scene).  Each upper off-diagonal
+// block S_ab (a < b) is read once per product, by the workgroup that owns row
+// a, from a copy in the storage precision T padded to SI_STRIDE values
+// (written by the Schur kernel; a workgroup's blocks contiguous in row
+// order).  These plans have their own row decomposition, balanced by upper
+// blocks.
 //
-// The blocks are split into STREAM_GROUPS contiguous ranges,
-// STREAM_WAVE_GROUPS nine-lane groups per wavefront.  At each step a
-// wavefront stages the current block of each of its groups in LDS with
-// 16-byte loads, 8 lanes per 128 bytes (the next two steps' blocks in
-// flight), and lane `comp` of a group forms from the one staged block
+// The blocks are split into StreamShape<T>::groups contiguous ranges,
+// StreamShape<T>::wave_groups nine-lane groups per wavefront (6 for FP32
+// blocks, 3 for FP64: either way a wavefront stages 126 16-byte pieces per
+// step).  At each step a wavefront stages the current block of each of its
+// groups in LDS with 16-byte loads (the next two steps' blocks in flight),
+// and lane `comp` of a group forms from the one staged block
 //   (S_ab v_b)[comp]    (row comp): running sum of row a, per (row + group)
 //                       segment as in the resident kernels;
 //   (S_ab^T v_a)[comp]  (column comp): added to the workgroup's LDS sum for
@@ -657,10 +659,17 @@ __global__ __launch_bounds__(PCG_THREADS) void k_pcg_pipelined(PcgArgs a) {
 // ---------------------------------------------------------------------------
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
 
-constexpr int STREAM_WAVE_GROUPS = 6;
-constexpr int STREAM_GROUPS = (PCG_THREADS / 64) * STREAM_WAVE_GROUPS;
-constexpr int STREAM_PIECES = SI_STRIDE * 4 / 16;  // 16-byte pieces per FP32 block
-constexpr int STREAM_LOADS = (STREAM_WAVE_GROUPS * STREAM_PIECES + 63) / 64;
+template <typename T>
+struct StreamShape {
+  static constexpr int wave_groups = sizeof(T) == 4 ? 6 : 3;  // nine-lane groups per wavefront
+  static constexpr int groups = (PCG_THREADS / 64) * wave_groups;
+  static constexpr int pieces = SI_STRIDE * (int)sizeof(T) / 16;  // 16-byte pieces per block
+  static constexpr int loads = (wave_groups * pieces + 63) / 64;
+};
+constexpr int STREAM_LOADS = 2;
+static_assert(StreamShape<float>::loads == STREAM_LOADS && StreamShape<double>::loads == STREAM_LOADS,
+              "both block precisions stage two 16-byte pieces per lane and step");
+constexpr int STREAM_GROUPS_MAX = StreamShape<float>::groups;
 // a wavefront's staging area holds every piece its lanes move, so that the
 // LDS stores need no lane-dependent branch (such a branch inside the
 // lockstep loop lets the compiler restructure it into a divergent nest)
@@ -687,21 +696,23 @@ struct StreamCtx {
   size_t vbase;
 };
 
-// Lane `lane` of wavefront `wave` loads piece (64 j + lane) % STREAM_PIECES
-// of the step-k block of group (64 j + lane) / STREAM_PIECES of its
+// Lane `lane` of wavefront `wave` loads piece (64 j + lane) % pieces
+// of the step-k block of group (64 j + lane) / pieces of its
 // wavefront; loads are issued without branches (items clamped to the
 // workgroup's last one).  The workgroup must have items.
+template <typename T>
 __device__ __forceinline__ void stream_fetch(const PcgArgs& a, const StreamCtx& c,
                                              f32x4_t (&buf)[STREAM_LOADS], int k) {
+  using Sh = StreamShape<T>;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const unsigned char* __restrict__ SIb =
-      reinterpret_cast<const unsigned char*>(a.SI) + (size_t)c.sib * SI_STRIDE * 4;
+      reinterpret_cast<const unsigned char*>(a.SI) + (size_t)c.sib * SI_STRIDE * sizeof(T);
 #pragma unroll
   for (int j = 0; j < STREAM_LOADS; ++j) {
     const int q = 64 * j + lane;
-    const int gg = min(q / STREAM_PIECES, STREAM_WAVE_GROUPS - 1), pc = q % STREAM_PIECES;
-    const int item = min(min(c.nitems, (wave * STREAM_WAVE_GROUPS + gg) * c.L) + k, c.nitems - 1);
-    buf[j] = *reinterpret_cast<const f32x4_t*>(SIb + (size_t)item * (SI_STRIDE * 4) + pc * 16);
+    const int gg = min(q / Sh::pieces, Sh::wave_groups - 1), pc = q % Sh::pieces;
+    const int item = min(min(c.nitems, (wave * Sh::wave_groups + gg) * c.L) + k, c.nitems - 1);
+    buf[j] = *reinterpret_cast<const f32x4_t*>(SIb + (size_t)item * (SI_STRIDE * sizeof(T)) + pc * 16);
   }
 }
 
@@ -716,6 +727,7 @@ __device__ __forceinline__ void stream_fetch(const PcgArgs& a, const StreamCtx& 
 // row of the block-Jacobi factor is loaded into Mr (its latency hidden by
 // the exchange).  Every thread of the workgroup calls it (barriers inside);
 // tl must be zero on entry and is zero on exit.
+template <typename T>
 __device__ __forceinline__ bool stream_spmv(const PcgArgs& a, const StreamCtx& c, int slot,
                                             const int* rptr, const int* lcol, const int* vcl,
                                             const int* ipl, const int* inl, const double* zl,
@@ -723,17 +735,18 @@ __device__ __forceinline__ bool stream_spmv(const PcgArgs& a, const StreamCtx& c
                                             unsigned char* st, double* nl, int* poll_failed,
                                             double (&Mr)[9], f32x4_t (&A)[STREAM_LOADS],
                                             f32x4_t (&Bf)[STREAM_LOADS]) {
+  using Sh = StreamShape<T>;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int gl = lane / 9, comp = lane - 9 * gl;
-  const bool computes = gl < STREAM_WAVE_GROUPS;
-  const int g = wave * STREAM_WAVE_GROUPS + gl;
+  const bool computes = gl < Sh::wave_groups;
+  const int g = wave * Sh::wave_groups + gl;
   const int nitems = c.nitems, L = c.L;
   const int i0 = computes ? min(nitems, g * L) : nitems;
   const int i1 = computes ? min(nitems, i0 + L) : nitems;
   unsigned char* wst = st + wave * STREAM_WAVE_BYTES;
   if (nitems > 0) {
     const int* __restrict__ scol = a.sitem_col + c.sib;
-    auto fetch = [&](f32x4_t (&buf)[STREAM_LOADS], int k) { stream_fetch(a, c, buf, k); };
+    auto fetch = [&](f32x4_t (&buf)[STREAM_LOADS], int k) { stream_fetch<T>(a, c, buf, k); };
     auto stage = [&](const f32x4_t (&buf)[STREAM_LOADS]) {
 #pragma unroll
       for (int j = 0; j < STREAM_LOADS; ++j) *reinterpret_cast<f32x4_t*>(wst + (64 * j + lane) * 16) = buf[j];
@@ -750,7 +763,7 @@ __device__ __forceinline__ bool stream_spmv(const PcgArgs& a, const StreamCtx& c
           acc = 0.0;
           cur = row;
         }
-        const float* blk = reinterpret_cast<const float*>(wst + gl * SI_STRIDE * 4);
+        const T* blk = reinterpret_cast<const T*>(wst + gl * SI_STRIDE * sizeof(T));
         const double* zc = zl + col * 9;
         const double* va = ml + row * 9;
 #pragma unroll
@@ -845,6 +858,7 @@ __device__ __forceinline__ bool stream_spmv(const PcgArgs& a, const StreamCtx& c
   return *poll_failed == 0;
 }
 
+template <typename T>
 __global__ __launch_bounds__(PCG_THREADS) void k_pcg_stream(PcgArgs a) {
   __shared__ double zl[STREAM_COLS * 9], tl[STREAM_COLS * 9];
   // w and the product n of the owned elements live in zl's memory: w is read
@@ -856,7 +870,7 @@ __global__ __launch_bounds__(PCG_THREADS) void k_pcg_stream(PcgArgs a) {
   // x, p and s of the owned elements (owner thread only: fewer live
   // registers across the product)
   __shared__ double xl[STREAM_RMAX * 9], pl[STREAM_RMAX * 9], sl[STREAM_RMAX * 9];
-  __shared__ double seg[(STREAM_RMAX + STREAM_GROUPS) * 9];
+  __shared__ double seg[(STREAM_RMAX + STREAM_GROUPS_MAX) * 9];
   __shared__ __align__(16) unsigned char st[(PCG_THREADS / 64) * STREAM_WAVE_BYTES];
   __shared__ int rptr[STREAM_RMAX + 1], lcol[STREAM_RMAX], ipl[STREAM_RMAX + 1];
   __shared__ int vcl[STREAM_COLS], inl[STREAM_IN_MAX];
@@ -872,7 +886,7 @@ __global__ __launch_bounds__(PCG_THREADS) void k_pcg_stream(PcgArgs a) {
   c.nr = a.wg_row[B + 1] - c.r0;
   c.sib = a.sitem_ptr[B];
   c.nitems = a.sitem_ptr[B + 1] - c.sib;
-  c.L = max(1, (c.nitems + STREAM_GROUPS - 1) / STREAM_GROUPS);
+  c.L = max(1, (c.nitems + StreamShape<T>::groups - 1) / StreamShape<T>::groups);
   c.vb = a.vcol_ptr[B];
   c.nvc = a.vcol_ptr[B + 1] - c.vb;
   c.vbase = (size_t)a.vbase[B];
@@ -886,8 +900,8 @@ __global__ __launch_bounds__(PCG_THREADS) void k_pcg_stream(PcgArgs a) {
   // the first two steps' blocks of every product, loaded early
   f32x4_t A[STREAM_LOADS], Bf[STREAM_LOADS];
   if (c.nitems > 0) {
-    stream_fetch(a, c, A, 0);
-    stream_fetch(a, c, Bf, min(1, c.L - 1));
+    stream_fetch<T>(a, c, A, 0);
+    stream_fetch<T>(a, c, Bf, min(1, c.L - 1));
   }
   if (tid == 0) {
     rptr[0] = 0;
@@ -948,7 +962,7 @@ __global__ __launch_bounds__(PCG_THREADS) void k_pcg_stream(PcgArgs a) {
   double t0 = 0.0;
   for (int i = tid; i < G; i += nt) t0 += a.partB[(size_t)i * PART_STRIDE];
   const double bnorm = uniform(sqrt(block_sum(t0, red)));  // (its barriers complete zl)
-  if (ok) ok = stream_spmv(a, c, 0, rptr, lcol, vcl, ipl, inl, zl, ml, tl, seg, st, nl, &poll_failed, Mr, A, Bf);
+  if (ok) ok = stream_spmv<T>(a, c, 0, rptr, lcol, vcl, ipl, inl, zl, ml, tl, seg, st, nl, &poll_failed, Mr, A, Bf);
   if (own) {
     w = nl[tid] + nd;
     wl[tid] = w;
@@ -1034,7 +1048,7 @@ __global__ __launch_bounds__(PCG_THREADS) void k_pcg_stream(PcgArgs a) {
     }
     const double alpha = gamma / den;
     __syncthreads();  // zl complete
-    if (!stream_spmv(a, c, i + 1, rptr, lcol, vcl, ipl, inl, zl, ml, tl, seg, st, nl, &poll_failed, Mr, A, Bf)) {
+    if (!stream_spmv<T>(a, c, i + 1, rptr, lcol, vcl, ipl, inl, zl, ml, tl, seg, st, nl, &poll_failed, Mr, A, Bf)) {
       ok = false;
       break;
     }
@@ -1070,7 +1084,7 @@ __global__ __launch_bounds__(PCG_THREADS) void k_pcg_stream(PcgArgs a) {
 
 template <typename T>
 static const void* pcg_kernel(bool resident, bool pipelined, bool stream) {
-  if (sizeof(T) == 4 && pipelined && !resident && stream) return reinterpret_cast<const void*>(k_pcg_stream);
+  if (pipelined && !resident && stream) return reinterpret_cast<const void*>(k_pcg_stream<T>);
   if (pipelined)
     return resident ? reinterpret_cast<const void*>(k_pcg_pipelined<T, true>)
                     : reinterpret_cast<const void*>(k_pcg_pipelined<T, false>);
@@ -1092,11 +1106,11 @@ template int pcg_max_grid<float>(bool, bool, bool);
 template int pcg_max_grid<double>(bool, bool, bool);
 
 // The streamed kernel runs when the arguments carry the streamed
-// decomposition (mixed precision, pipelined recurrence, blocks not
-// register-resident); such plans without it read the stored blocks per item.
+// decomposition (pipelined recurrence, blocks not register-resident); such
+// plans without it read the stored blocks per item.
 template <typename T>
 hipError_t launch_pcg(const PcgArgs& a, int grid, bool resident, bool pipelined, hipStream_t s) {
-  const bool stream = sizeof(T) == 4 && pipelined && !resident && a.SI;
+  const bool stream = pipelined && !resident && a.SI;
   if (stream && (!a.sitem_ptr || !a.sitem_col || !a.vcol_ptr || !a.vcol || !a.vbase || !a.in_ptr ||
                  !a.in_off || !a.src_ptr || !a.src || !a.rring || !a.rflag))
     return hipErrorInvalidValue;  // the streamed kernel needs its decomposition and exchange

@@ -76,4 +76,21 @@ __device__ __forceinline__ double block_sum_array(const double* __restrict__ arr
   return block_sum(s, sh);
 }
 
+// The same for long arrays: four strided loads in flight per thread (four
+// running sums, added in a fixed order at the end), then the workgroup tree.
+__device__ __forceinline__ double block_sum_array4(const double* __restrict__ arr, int n, double* sh) {
+  const int nt = blockDim.x;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int i = threadIdx.x;
+  for (; i + 3 * nt < n; i += 4 * nt) {
+    const double a0 = arr[i], a1 = arr[i + nt], a2 = arr[i + 2 * nt], a3 = arr[i + 3 * nt];
+    s0 += a0;
+    s1 += a1;
+    s2 += a2;
+    s3 += a3;
+  }
+  for (; i < n; i += nt) s0 += arr[i];
+  return block_sum((s0 + s1) + (s2 + s3), sh);
+}
+
 }  // namespace ba

@@ -187,10 +187,10 @@ def test_streamed_pcg_path_matches_oracle():
     """Dense co-visibility (400 ring cameras, nearly every pair sharing points):
     each block row holds more blocks than the lanes of a PCG workgroup keep
     in registers, so the PCG streams its blocks every iteration.  FP64
-    parity with a converged solve (standard recurrence), and both
-    recurrences at the default tolerance within the oracle's envelope (no
-    breakdown, full Krylov runs), in FP64 and with the mixed-precision
-    streamed kernel."""
+    parity with a converged solve (standard recurrence, stored blocks read
+    per item), and both recurrences at the default tolerance within the
+    oracle's envelope (no breakdown, full Krylov runs): the pipelined one
+    runs the streamed kernel with FP64 or FP32 block copies."""
     s = make_scene(0, n_cams=400, n_pts=40000)
     # blocks of each block row (both triangles and the diagonal); a PCG
     # workgroup's 1024 // 9 lane groups keep at most 3 blocks each in registers
@@ -204,11 +204,14 @@ def test_streamed_pcg_path_matches_oracle():
     o = orc(s)
     # (precision, recurrence) -> bound on the cost after each step, relative
     # to the oracle's: FP64 within the oracle's own envelope; mixed precision
-    # (FP32 blocks: the streamed kernel with the pipelined recurrence, the
-    # per-item kernel with the standard one) within the mixed-mode bound
+    # within the mixed-mode bound (the streamed kernel with the pipelined
+    # recurrence, the per-item kernel with the standard one, both precisions)
     forms = {(B.BA_FP64, B.BA_CG_PIPELINED): 1e-5, (B.BA_FP64, B.BA_CG_STANDARD): 1e-5,
              (B.BA_MIXED, B.BA_CG_PIPELINED): 1e-4, (B.BA_MIXED, B.BA_CG_STANDARD): 1e-4}
     runs = {f: gpu(s, precision=f[0], cg_variant=f[1]) for f in forms}
+    for f, g in runs.items():
+        want = "streamed" if f[1] == B.BA_CG_PIPELINED else "per_item"
+        assert g.plan["pcg_layout"] == want, (f, g.plan)
     for it in range(3):
         io = o.lm_step()
         for f, g in runs.items():
@@ -540,15 +543,14 @@ def laps10000():
 def test_full_size_laps_scene_tracks_oracle(laps10000, precision):
     """The 10,000-camera / 2,000,000-point / ~8M-observation laps scene with
     loop closures, at full size in the benchmark's launch configuration
-    (pipelined PCG, rtol 1e-4; mixed precision streams each upper block once
-    per product, FP64 reads its stored blocks per item).  Two LM steps
+    (pipelined PCG, rtol 1e-4; both precisions stream each upper block once
+    per product from a copy in their storage precision).  Two LM steps
     against the oracle: costs within the stated bound (mixed 1e-4, FP64
     1e-5 relative), and the PCG step meets its tolerance on the exported
     system (the residual property checked here in numpy)."""
     s = laps10000
     g, o = gpu(s, precision=precision), orc(s)
-    want = "streamed" if precision == B.BA_MIXED else "per_item"
-    assert g.plan["pcg_layout"] == want, g.plan
+    assert g.plan["pcg_layout"] == "streamed", g.plan
     tol = 1e-4 if precision == B.BA_MIXED else 1e-5
     for it in range(2):
         io, ig = o.lm_step(), g.lm_step()
