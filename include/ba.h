@@ -356,6 +356,48 @@ ba_status ba_problem_nnzb(const ba_problem* p, int64_t* nnzb);
 #define BA_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
 ba_status ba_problem_bind_static(ba_problem* p, void* hip_stream);
 
+/* ---- pose graph optimisation (Sec. IV-D, Eq. 4 and 5) ----------------------
+ * Z* = argmin 1/2 sum_e r_e^T Omega_e r_e over poses zeta, one residual per
+ * edge e = (i, j): r_e = Log(zeta_i^-1 zeta_j T_e^-1) in R^6 (translation
+ * part first), T_e the measured relative pose zeta_i^-1 zeta_j.  Poses and
+ * measurements are 7 float64 [tx ty tz qx qy qz qw] (unit quaternion,
+ * scalar last) for the transform [R(q) t; 0 1]; steps are the 6-vector
+ * (rho, phi) of the left update zeta <- Exp(rho, phi) zeta.  A pose graph is
+ * a ba_problem: the same LM iteration (ba_lm_step, ba_solve: linearise,
+ * clamped damping, block-Jacobi PCG or dense Cholesky, retraction,
+ * acceptance, damping update) runs on the 6x6-block system
+ * H = sum J^T Omega J, g = sum J^T Omega r directly (nothing to eliminate),
+ * the blocks held as 9x9 camera blocks with zero rows and columns 6-8.
+ * Also valid on pose graphs: ba_problem_workspace_bytes, ba_problem_bind,
+ * ba_problem_bind_static, ba_set_fixed_cameras (the mask fixes poses: gauge
+ * anchors), ba_set_lambda, ba_get_lambda, ba_set_cg, ba_get_state,
+ * ba_set_state (no points), ba_problem_nnzb, the profiling calls (phases 0
+ * linearise, 1 cost, 5 block assembly, 6, 7, 9 retraction, 10 candidate,
+ * 11) and ba_export of BA_X_COST, BA_X_GRAD_C, BA_X_S_PTR, BA_X_S_COL, BA_X_S,
+ * BA_X_BS, BA_X_DC (9-wide rows, the last 3 entries zero), BA_X_PRECOND and
+ * BA_X_PLAN.  The observation and point entry points return BA_EINVAL. */
+
+/* Creates a pose graph of n_poses poses and n_edges edges ei[e] -> ej[e]
+ * (host int32 arrays, copied; several edges may join the same two poses).
+ * opt: cam_dof is ignored; huber_delta must be <= 0, precond block-Jacobi
+ * and enable_backward 0 (else BA_EUNSUPPORTED).  Errors: BA_EINVAL (sizes
+ * <= 0, endpoint out of range, an edge from a pose to itself),
+ * BA_EUNSUPPORTED (more than 2^29 edges, options above). */
+ba_status ba_pgo_create(const ba_options* opt, int32_t n_poses, int64_t n_edges, const int32_t* ei,
+                        const int32_t* ej, ba_problem** out);
+/* Measurements: T device float64 [n_edges][7]; omega device float64
+ * [n_edges][6][6] information matrices (row-major, in the (rho, phi) order
+ * of r), or NULL for identities.  Copied.  Errors: BA_EINVAL for non-finite
+ * values, a quaternion with | |q|^2 - 1 | > 1e-10, or an information matrix
+ * that is not exactly symmetric or has a diagonal entry <= 0 (one stream
+ * synchronisation). */
+ba_status ba_pgo_set_edges(ba_problem* p, const double* T, const double* omega);
+/* Sets / reads the poses: device float64 [n_poses][7].  set copies and
+ * invalidates the linearisation; a retracted pose carries a renormalised
+ * quaternion of either sign. */
+ba_status ba_pgo_set_poses(ba_problem* p, const double* poses);
+ba_status ba_pgo_get_poses(const ba_problem* p, double* poses);
+
 void ba_problem_destroy(ba_problem* p);
 const char* ba_last_error(void);
 

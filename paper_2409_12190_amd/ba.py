@@ -38,6 +38,7 @@ EXPORTED_SYMBOLS = [
     "ba_set_profiling_mask", "ba_get_phase_times", "ba_problem_destroy", "ba_last_error", "ba_gnn_num_params",
     "ba_set_gnn_params", "ba_graph_create", "ba_graph_workspace_bytes", "ba_graph_bind",
     "ba_graph_build", "ba_gnn_loss_grad", "ba_gnn_adam", "ba_graph_destroy", "ba_problem_bind_static",
+    "ba_pgo_create", "ba_pgo_set_edges", "ba_pgo_set_poses", "ba_pgo_get_poses",
 ]
 BA_STATIC_SCRATCH_BYTES = 64 << 20
 BA_NUM_PHASES = 13
@@ -122,6 +123,10 @@ def lib():
                                   C.c_float, C.c_float, P]
         L.ba_graph_destroy.argtypes = [P]
         L.ba_graph_destroy.restype = None
+        L.ba_pgo_create.argtypes = [C.POINTER(ba_options), C.c_int32, C.c_int64, P, P, C.POINTER(P)]
+        L.ba_pgo_set_edges.argtypes = [P, P, P]
+        L.ba_pgo_set_poses.argtypes = [P, P]
+        L.ba_pgo_get_poses.argtypes = [P, P]
         L.ba_last_error.argtypes = []
         L.ba_last_error.restype = C.c_char_p
         for name in EXPORTED_SYMBOLS:
@@ -162,6 +167,29 @@ def ba_problem_create(opt: ba_options, n_cams: int, n_pts: int, cam_idx, pt_idx)
     _check(lib().ba_problem_create(C.byref(opt), n_cams, n_pts, ci.size, ci.ctypes.data,
                                    pi.ctypes.data, C.byref(h)))
     return h.value
+
+
+def ba_pgo_create(opt: ba_options, n_poses: int, ei, ej) -> int:
+    a = np.ascontiguousarray(ei, np.int32)
+    b = np.ascontiguousarray(ej, np.int32)
+    if a.shape != b.shape:
+        raise ValueError("ei and ej differ in length")
+    h = C.c_void_p()
+    _check(lib().ba_pgo_create(C.byref(opt), int(n_poses), int(a.size), a.ctypes.data, b.ctypes.data,
+                               C.byref(h)))
+    return h.value
+
+
+def ba_pgo_set_edges(h: int, T, omega=None):
+    _check(lib().ba_pgo_set_edges(h, _ptr(T), _ptr(omega)))
+
+
+def ba_pgo_set_poses(h: int, poses):
+    _check(lib().ba_pgo_set_poses(h, _ptr(poses)))
+
+
+def ba_pgo_get_poses(h: int, poses):
+    _check(lib().ba_pgo_get_poses(h, _ptr(poses)))
 
 
 def ba_problem_workspace_bytes(h: int) -> int:
@@ -489,6 +517,108 @@ class Problem:
                   BA_X_PRECOND: ((nc, 9, 9), np.float64), BA_X_PLAN: ((4,), np.int64)}
         shape, dt = shapes[field]
         return ba_export(self.h, field, np.zeros(shape, dt))
+
+
+class PoseGraph:
+    """One pose graph (ba_pgo_create) on the current CUDA (HIP) device.
+
+    ei / ej: host integer arrays of the edges' endpoints; T [m, 7] measured
+    relative poses and omega [m, 6, 6] information matrices (or None);
+    poses [n, 7]; fixed: indices of fixed poses.  The LM iteration is the
+    library's (lm_step, solve); the methods mirror Problem's."""
+
+    def __init__(self, n_poses, ei, ej, T, omega=None, poses=None, *, fixed=None, precision=BA_FP64,
+                 cg_rtol=1e-4, cg_maxiter=250, lambda0=1e-4, lambda_min=None, lambda_max=None,
+                 cg_variant=BA_CG_PIPELINED, linear_solver=BA_SOLVER_PCG, stream=None,
+                 static_workspace=False):
+        import torch
+        self.torch = torch
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        opt = ba_default_options()
+        opt.precision = precision
+        opt.cg_rtol = cg_rtol
+        opt.cg_maxiter = cg_maxiter
+        opt.lambda0 = lambda0
+        opt.cg_variant = cg_variant
+        opt.linear_solver = linear_solver
+        if lambda_min is not None:
+            opt.lambda_min = lambda_min
+        if lambda_max is not None:
+            opt.lambda_max = lambda_max
+        self.opt = opt
+        self.n_poses = int(n_poses)
+        self.n_edges = int(np.asarray(ei).size)
+        self.h = ba_pgo_create(opt, self.n_poses, ei, ej)
+        self._finalizer = weakref.finalize(self, _release, lib().ba_problem_destroy, self.h, None, None)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        if static_workspace:
+            self.workspace = None
+            ba_problem_bind_static(self.h, self.stream.cuda_stream)
+        else:
+            nbytes = ba_problem_workspace_bytes(self.h)
+            self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+            if self.workspace.data_ptr() % 256:
+                raise RuntimeError("workspace allocation is not 256-byte aligned")
+            ba_problem_bind(self.h, self.workspace.data_ptr(), nbytes, self.stream.cuda_stream)
+        self._finalizer.detach()
+        self._finalizer = weakref.finalize(self, _release, lib().ba_problem_destroy, self.h,
+                                           self.stream, self.workspace)
+        self.set_edges(T, omega)
+        if fixed is not None and len(fixed):
+            mask = np.zeros(self.n_poses, np.uint8)
+            mask[np.asarray(fixed)] = 1
+            ba_set_fixed_cameras(self.h, mask)
+        if poses is not None:
+            self.set_poses(poses)
+
+    @classmethod
+    def from_graph(cls, g, **kw):
+        """From a synth.posegraph.PoseGraph (its initial estimate and fixed poses)."""
+        kw.setdefault("fixed", g.fixed)
+        return cls(g.n_poses, g.ei, g.ej, g.T, g.omega, g.poses0, **kw)
+
+    _dev = Problem._dev
+    close = Problem.close
+    __enter__ = Problem.__enter__
+    __exit__ = Problem.__exit__
+    set_lambda = Problem.set_lambda
+    lam = Problem.lam
+    set_cg = Problem.set_cg
+    lm_step = Problem.lm_step
+    solve = Problem.solve
+    get_state = Problem.get_state
+    set_state = Problem.set_state
+    set_profiling = Problem.set_profiling
+    phase_times = Problem.phase_times
+    plan = Problem.plan
+    nnzb = Problem.nnzb
+
+    def set_edges(self, T, omega=None):
+        t = self._dev(T).reshape(self.n_edges, 7)
+        o = None if omega is None else self._dev(omega).reshape(self.n_edges, 6, 6)
+        self.stream.synchronize()
+        ba_pgo_set_edges(self.h, t, o)
+
+    def set_poses(self, poses):
+        z = self._dev(poses).reshape(self.n_poses, 7)
+        self.stream.synchronize()
+        ba_pgo_set_poses(self.h, z)
+        self.stream.synchronize()
+
+    def get_poses(self):
+        t = self.torch
+        z = t.empty((self.n_poses, 7), dtype=t.float64, device=self.device)
+        ba_pgo_get_poses(self.h, z)
+        self.stream.synchronize()
+        return z
+
+    def export(self, field: int) -> np.ndarray:
+        nc, nz = self.n_poses, self.nnzb
+        shapes = {BA_X_COST: (1,), BA_X_GRAD_C: (nc, 9), BA_X_S_PTR: (nc + 1,), BA_X_S_COL: (nz,),
+                  BA_X_S: (nz, 9, 9), BA_X_BS: (nc, 9), BA_X_DC: (nc, 9), BA_X_PRECOND: (nc, 9, 9),
+                  BA_X_PLAN: (4,)}
+        dt = {BA_X_S_PTR: np.int64, BA_X_S_COL: np.int32, BA_X_PLAN: np.int64}.get(field, np.float64)
+        return ba_export(self.h, field, np.zeros(shapes[field], dt))
 
 
 # ---- learned preconditioner: graphs and training --------------------------------

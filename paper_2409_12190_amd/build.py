@@ -12,10 +12,10 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libba.so")
 
-SOURCES = ["ba_kernels.hip", "ba_pcg.hip", "ba_adjoint.hip", "ba_precond.hip", "ba_dense.hip", "ba_static.hip", "ba_api.cpp",
+SOURCES = ["ba_kernels.hip", "ba_pcg.hip", "ba_adjoint.hip", "ba_precond.hip", "ba_dense.hip", "ba_static.hip", "ba_pgo.hip", "ba_api.cpp",
            "ba_plan.cpp"]
 HEADERS = ["ba_device.h", "ba_reduce.h", "ba_internal.h", "ba_kernels.h", "ba_adjoint.h", "ba_precond.h",
-           "ba_dense.h"]
+           "ba_dense.h", "ba_pgo.h"]
 
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950",

@@ -8,6 +8,7 @@
 #include <cstring>
 #include <mutex>
 #include <new>
+#include <stdexcept>
 #include <string>
 #include <vector>
 
@@ -16,6 +17,7 @@
 #include "ba_dense.h"
 #include "ba_internal.h"
 #include "ba_kernels.h"
+#include "ba_pgo.h"
 #include "ba_precond.h"
 
 // A training graph: the camera pattern (host) and its device view.
@@ -65,16 +67,19 @@ void carve(ba_problem* p, char* base, size_t* total) {
   Carver c{base};
   const ba::Plan& P = p->plan;
   ba::Buffers& b = p->b;
-  const size_t nc = P.nc, np = P.np, no = P.no, nnzb = P.nnzb;
-  const size_t nch = P.chunk_ptr.size() - 1;
+  const size_t nc = P.nc, nnzb = P.nnzb;
+  // a pose graph keeps its plan's observation and point tables (two
+  // observations per edge) but none of their values
+  const size_t np = p->pgo ? 0 : P.np, no = p->pgo ? 0 : P.no;
+  const size_t nch = std::max<size_t>(P.chunk_ptr.size() - 1, (size_t)ba::pgo_chunks(p->n_edges));
   const size_t es = elem_bytes(p);
-  b.o_cam = c.take<int32_t>(no);
-  b.o_pt = c.take<int32_t>(no);
-  b.pt_ptr = c.take<int32_t>(np + 1);
+  b.o_cam = c.take<int32_t>(P.o_cam.size());
+  b.o_pt = c.take<int32_t>(P.o_pt.size());
+  b.pt_ptr = c.take<int32_t>(P.pt_ptr.size());
   b.chunk_ptr = c.take<int32_t>(nch + 1);
   b.chunk_pt = c.take<int32_t>(nch + 1);
   b.cam_ptr = c.take<int32_t>(nc + 1);
-  b.cam_obs = c.take<int32_t>(no);
+  b.cam_obs = c.take<int32_t>(P.cam_obs.size());
   b.S_ptr = c.take<int32_t>(nc + 1);
   b.S_col = c.take<int32_t>(nnzb);
   b.T_ptr = c.take<int32_t>(nc + 1);
@@ -106,7 +111,7 @@ void carve(ba_problem* p, char* base, size_t* total) {
   b.in_off = c.take<int32_t>(P.in_off.size());
   b.src_ptr = c.take<int32_t>(P.src_ptr.size());
   b.src = c.take<int32_t>(P.src.size());
-  b.o_orig = c.take<int64_t>(no);
+  b.o_orig = c.take<int64_t>(P.o_orig.size());
   b.fixed = c.take<uint8_t>(nc);
   b.o_xy = c.take<double>(2 * no);
   b.o_w = c.take<double>(no);
@@ -190,6 +195,16 @@ void carve(ba_problem* p, char* base, size_t* total) {
     b.gw = c.take<float>(ns);
     b.gact = c.take<float>((2 * (ba::GNN_L + 1) + ba::GNN_L) * nc * ba::GNN_H);
   }
+  if (p->pgo) {
+    const size_t m = p->n_edges;
+    b.pg_ei = c.take<int32_t>(m);
+    b.pg_ej = c.take<int32_t>(m);
+    b.pg_ptr = c.take<int32_t>(p->pg_ptr.size());
+    b.pg_code = c.take<int32_t>(p->pg_code.size());
+    b.pg_T = c.take<double>(8 * m);
+    b.pg_om = c.take<double>(36 * m);
+    b.pg_rec = c.take<double>(ba::PGO_REC * m);
+  }
   *total = c.off + 256;
 }
 
@@ -220,10 +235,13 @@ const char* not_bound_msg(const ba_problem* p) {
 ba_status require_ready(const ba_problem* p) {
   if (!p) return fail(BA_EINVAL, "null problem");
   if (!usable(p)) return fail(BA_ESTATE, not_bound_msg(p));
-  if (!p->have_obs) return fail(BA_ESTATE, "observations are not set");
-  if (!p->have_params) return fail(BA_ESTATE, "parameters are not set");
+  if (!p->have_obs) return fail(BA_ESTATE, p->pgo ? "measurements are not set" : "observations are not set");
+  if (!p->have_params) return fail(BA_ESTATE, p->pgo ? "poses are not set" : "parameters are not set");
   return BA_OK;
 }
+
+// points held in the parameter state (none for a pose graph)
+size_t point_count(const ba_problem* p) { return p->pgo ? 0 : (size_t)p->plan.np; }
 
 // Event-bracketed launch of one phase when profiling is on.
 struct Phase {
@@ -306,11 +324,23 @@ ba_status lm_step_impl(ba_problem* p, ba_step_info* out) {
   const Plan& P = p->plan;
   Buffers& b = p->b;
   hipStream_t s = p->stream;
-  const int nchunk = (int)P.chunk_ptr.size() - 1;
+  const int nchunk = p->pgo ? pgo_chunks(p->n_edges) : (int)P.chunk_ptr.size() - 1;
   const int cur = p->cur, nxt = p->cur ^ 1;
   const double lam_before = p->lambda;
 
-  if (!p->lin_valid) {
+  if (p->pgo) {
+    // pose graph: per-edge residuals, Jacobians and records, then the
+    // damped system's blocks straight from the records (no points)
+    if (!p->lin_valid) {
+      PgoLinArgs la{p->n_edges, b.pg_ei, b.pg_ej, b.cams[cur], b.pg_T, b.pg_om, b.pg_rec, b.part_cost,
+                    b.part_gmax};
+      PHASE(0, launch_pgo_linearize(la, s));
+      PHASE(1, launch_reduce_cost(b.part_cost, nchunk, b.dev, s));
+    }
+    PgoAsmArgs aa{b.blk_row, b.S_col, b.pg_ptr, b.pg_code, b.fixed, b.pg_rec, b.S, b.Sdiag, b.gc, b.bS,
+                  b.diagU, streamed(p) ? b.blk_pos : nullptr, streamed(p) ? b.SI : nullptr};
+    PHASE(5, launch_pgo_assemble<T>(aa, P.nnzb, s));
+  } else if (!p->lin_valid) {
     // linearisation with the point elimination of the current lambda
     LinArgs la{b.chunk_ptr, b.chunk_pt, b.pt_ptr, b.o_cam, b.o_pt, b.fixed, b.o_xy, b.o_w,
                b.cams[cur], b.pts[cur], p->opt.huber_delta, b.r, b.w, b.J, b.V, b.gp,
@@ -325,15 +355,17 @@ ba_status lm_step_impl(ba_problem* p, ba_step_info* out) {
     PointQArgs qa{P.no, b.o_pt, b.w, b.Vinv, b.ep, b.J, b.rec};
     PHASE(3, launch_point_q<T>(qa, s));
   }
-  // the camera vectors (gradient, right-hand side term, diag U) come from
-  // the self pairs of the Schur kernel's diagonal blocks
-  SchurArgs sa{P.n_schur_wg, p->rec_unit, b.slot_blk, b.slot_lead, b.blk_row, b.S_ptr, b.stab, b.swptr,
-               b.J, b.S, b.Sdiag, b.gc, b.bS, b.diagU};
-  if (streamed(p)) {
-    sa.blk_pos = b.blk_pos;
-    sa.SI = b.SI;
+  if (!p->pgo) {
+    // the camera vectors (gradient, right-hand side term, diag U) come from
+    // the self pairs of the Schur kernel's diagonal blocks
+    SchurArgs sa{P.n_schur_wg, p->rec_unit, b.slot_blk, b.slot_lead, b.blk_row, b.S_ptr, b.stab, b.swptr,
+                 b.J, b.S, b.Sdiag, b.gc, b.bS, b.diagU};
+    if (streamed(p)) {
+      sa.blk_pos = b.blk_pos;
+      sa.SI = b.SI;
+    }
+    PHASE(5, launch_schur_pairs<T>(sa, P.n_schur_wg, s));
   }
-  PHASE(5, launch_schur_pairs<T>(sa, P.n_schur_wg, s));
   CamFinishArgs cf{b.Sdiag, b.diagU, p->opt.diag_min, p->opt.diag_max, b.Minv, b.dev, b.pcLinv, b.gc, b.bS};
   PHASE(6, launch_camera_finish<T>(cf, P.nc, s));
   p->have_system = true;
@@ -394,14 +426,22 @@ ba_status lm_step_impl(ba_problem* p, ba_step_info* out) {
       precond_used = 2;
     }
   }
-  BackArgs ba_{b.chunk_ptr, b.chunk_pt, b.pt_ptr, b.o_cam, b.o_pt, b.J, b.w, b.x, b.gp, b.Vinv,
-               b.pts[cur], b.dp, b.pts[nxt], b.part_pred};
-  PHASE(8, launch_backsub<T>(ba_, nchunk, s));
-  RetractArgs ra{P.nc, b.fixed, b.cams[cur], b.x, b.gc, b.cams[nxt], b.part_linc};
-  PHASE(9, launch_retract_cameras(ra, p->cam_blocks, s));
-  CostArgs co{b.chunk_ptr, b.o_cam, b.o_pt, b.o_xy, b.o_w, b.cams[nxt], b.pts[nxt],
-              p->opt.huber_delta, b.part_cost_new};
-  PHASE(10, launch_candidate_cost(co, nchunk, s));
+  if (p->pgo) {
+    RetractArgs ra{P.nc, b.fixed, b.cams[cur], b.x, b.gc, b.cams[nxt], b.part_linc};
+    PHASE(9, launch_retract_cameras(ra, p->cam_blocks, s));
+    PgoCandArgs ca{p->n_edges, b.pg_ei, b.pg_ej, b.cams[nxt], b.pg_T, b.pg_om, b.pg_rec, b.x,
+                   b.part_cost_new, b.part_pred};
+    PHASE(10, launch_pgo_candidate(ca, s));
+  } else {
+    BackArgs ba_{b.chunk_ptr, b.chunk_pt, b.pt_ptr, b.o_cam, b.o_pt, b.J, b.w, b.x, b.gp, b.Vinv,
+                 b.pts[cur], b.dp, b.pts[nxt], b.part_pred};
+    PHASE(8, launch_backsub<T>(ba_, nchunk, s));
+    RetractArgs ra{P.nc, b.fixed, b.cams[cur], b.x, b.gc, b.cams[nxt], b.part_linc};
+    PHASE(9, launch_retract_cameras(ra, p->cam_blocks, s));
+    CostArgs co{b.chunk_ptr, b.o_cam, b.o_pt, b.o_xy, b.o_w, b.cams[nxt], b.pts[nxt],
+                p->opt.huber_delta, b.part_cost_new};
+    PHASE(10, launch_candidate_cost(co, nchunk, s));
+  }
   FinalArgs fa{nchunk, p->cam_blocks, P.nc, b.part_cost_new, b.part_pred, b.part_linc, b.part_gmax,
                b.gc, p->opt.lambda_min, p->opt.lambda_max, b.dev, b.dinfo, b.part_stage, 0};
   PHASE(11, launch_finalize(fa, s));
@@ -431,6 +471,7 @@ ba_status lm_step_impl(ba_problem* p, ba_step_info* out) {
     }
     std::string why = !std::isfinite(info.cost_before) ? "non-finite cost at the current parameters"
                       : (err & ERR_POINT_BLOCK)        ? "a damped point block is not positive definite"
+                      : p->pgo                         ? "a damped diagonal pose block is not positive definite"
                                                        : "a diagonal camera block is not positive definite";
     return fail(BA_ENUMERIC, why);
   }
@@ -472,6 +513,61 @@ void graph_carve(ba_graph* g, char* base, size_t* total) {
 
 }  // namespace
 
+namespace {
+
+// Option checks shared by bundle-adjustment and pose-graph problems.
+ba_status check_options(const ba_options& o, int32_t n_cams) {
+  if (o.precision != BA_FP64 && o.precision != BA_MIXED) return fail(BA_EINVAL, "unknown precision");
+  if (!(o.cg_rtol >= 0.0) || o.cg_maxiter < 1) return fail(BA_EINVAL, "bad CG options");
+  if (o.cg_variant != BA_CG_PIPELINED && o.cg_variant != BA_CG_STANDARD)
+    return fail(BA_EINVAL, "unknown CG variant");
+  if (!(o.lambda0 > 0.0) || !(o.lambda_min > 0.0) || !(o.lambda_max >= o.lambda_min))
+    return fail(BA_EINVAL, "bad damping options");
+  if (!(o.diag_min > 0.0) || !(o.diag_max >= o.diag_min)) return fail(BA_EINVAL, "bad clamp range");
+  if (o.precond != BA_PRECOND_BLOCK_JACOBI && o.precond != BA_PRECOND_LEARNED)
+    return fail(BA_EINVAL, "unknown preconditioner");
+  if (!(o.adjoint_grad_tol >= 0.0)) return fail(BA_EINVAL, "adjoint_grad_tol must be >= 0");
+  if (o.linear_solver != BA_SOLVER_PCG && o.linear_solver != BA_SOLVER_CHOLESKY)
+    return fail(BA_EINVAL, "unknown linear solver");
+  if (o.linear_solver == BA_SOLVER_CHOLESKY && (n_cams > ba::DENSE_MAX_CAMS || o.precond == BA_PRECOND_LEARNED))
+    return fail(BA_EUNSUPPORTED, "the dense Cholesky solve takes at most 2048 cameras and no learned preconditioner");
+  return BA_OK;
+}
+
+// Sizes the workspace and the Schur step table of a planned problem; takes
+// ownership of p (deleted on failure).
+ba_status finish_create(ba_problem* p, ba_problem** out) {
+  const ba_options& o = p->opt;
+  p->lambda = o.lambda0;
+  p->cg_rtol = o.cg_rtol;
+  p->cg_maxiter = o.cg_maxiter;
+  p->cam_blocks = (p->plan.nc + 255) / 256;
+  carve(p, nullptr, &p->ws_needed);
+  // Schur step table in 64-byte units from J: observation x's row at x * row
+  // units, its record (self pairs, y side) at rec_unit + x, -1 unchanged
+  const int64_t row_units = (int64_t)ba::NJ * (int64_t)elem_bytes(p) / 64;
+  const int64_t rec_unit = (int64_t)(p->rec_off / 64);
+  if (rec_unit + (int64_t)p->plan.no > INT32_MAX || p->rec_off % 64) {
+    delete p;
+    return fail(BA_EUNSUPPORTED, "observation rows exceed 2^31 units");
+  }
+  p->rec_unit = (int32_t)rec_unit;
+  try {
+    p->stab_units.resize(p->plan.stab.size());
+  } catch (const std::bad_alloc&) {
+    delete p;
+    return fail(BA_EINVAL, "out of host memory");
+  }
+  for (size_t i = 0; i < p->stab_units.size(); ++i) {
+    const int32_t c = p->plan.stab[i];
+    p->stab_units[i] = c >= 0 ? (int32_t)(c * row_units) : (c == -1 ? -1 : (int32_t)(rec_unit + (-2 - c)));
+  }
+  *out = p;
+  return BA_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 void ba_default_options(ba_options* o) {
@@ -507,20 +603,8 @@ ba_status ba_problem_create(const ba_options* opt, int32_t n_cams, int32_t n_pts
   if (o.cam_dof != 9 && o.cam_dof != 6) return fail(BA_EUNSUPPORTED, "cam_dof must be 9 or 6");
   if (o.cam_dof == 6 && (o.precond == BA_PRECOND_LEARNED || o.enable_backward))
     return fail(BA_EUNSUPPORTED, "the 6-DoF camera supports neither the learned preconditioner nor the adjoint");
-  if (o.precision != BA_FP64 && o.precision != BA_MIXED) return fail(BA_EINVAL, "unknown precision");
-  if (!(o.cg_rtol >= 0.0) || o.cg_maxiter < 1) return fail(BA_EINVAL, "bad CG options");
-  if (o.cg_variant != BA_CG_PIPELINED && o.cg_variant != BA_CG_STANDARD)
-    return fail(BA_EINVAL, "unknown CG variant");
-  if (!(o.lambda0 > 0.0) || !(o.lambda_min > 0.0) || !(o.lambda_max >= o.lambda_min))
-    return fail(BA_EINVAL, "bad damping options");
-  if (!(o.diag_min > 0.0) || !(o.diag_max >= o.diag_min)) return fail(BA_EINVAL, "bad clamp range");
-  if (o.precond != BA_PRECOND_BLOCK_JACOBI && o.precond != BA_PRECOND_LEARNED)
-    return fail(BA_EINVAL, "unknown preconditioner");
-  if (!(o.adjoint_grad_tol >= 0.0)) return fail(BA_EINVAL, "adjoint_grad_tol must be >= 0");
-  if (o.linear_solver != BA_SOLVER_PCG && o.linear_solver != BA_SOLVER_CHOLESKY)
-    return fail(BA_EINVAL, "unknown linear solver");
-  if (o.linear_solver == BA_SOLVER_CHOLESKY && (n_cams > ba::DENSE_MAX_CAMS || o.precond == BA_PRECOND_LEARNED))
-    return fail(BA_EUNSUPPORTED, "the dense Cholesky solve takes at most 2048 cameras and no learned preconditioner");
+  const ba_status st = check_options(o, n_cams);
+  if (st != BA_OK) return st;
   ba_problem* p = new (std::nothrow) ba_problem();
   if (!p) return fail(BA_EINVAL, "out of host memory");
   p->opt = o;
@@ -535,32 +619,91 @@ ba_status ba_problem_create(const ba_options* opt, int32_t n_cams, int32_t n_pts
     const bool unsup = err.find("at most") != std::string::npos;
     return fail(unsup ? BA_EUNSUPPORTED : BA_EINVAL, err);
   }
-  p->lambda = o.lambda0;
-  p->cg_rtol = o.cg_rtol;
-  p->cg_maxiter = o.cg_maxiter;
-  p->cam_blocks = (n_cams + 255) / 256;
-  carve(p, nullptr, &p->ws_needed);
-  // Schur step table in 64-byte units from J: observation x's row at x * row
-  // units, its record (self pairs, y side) at rec_unit + x, -1 unchanged
-  const int64_t row_units = (int64_t)ba::NJ * (int64_t)elem_bytes(p) / 64;
-  const int64_t rec_unit = (int64_t)(p->rec_off / 64);
-  if (rec_unit + (int64_t)p->plan.no > INT32_MAX || p->rec_off % 64) {
-    delete p;
-    return fail(BA_EUNSUPPORTED, "observation rows exceed 2^31 units");
+  return finish_create(p, out);
+}
+
+ba_status ba_pgo_create(const ba_options* opt, int32_t n_poses, int64_t n_edges, const int32_t* ei,
+                        const int32_t* ej, ba_problem** out) {
+  if (!out) return fail(BA_EINVAL, "out is null");
+  *out = nullptr;
+  if (!ei || !ej) return fail(BA_EINVAL, "edge arrays must not be null");
+  if (n_poses <= 0 || n_edges <= 0) return fail(BA_EINVAL, "a pose graph needs poses and edges");
+  if (n_edges > (int64_t)(INT32_MAX / 4)) return fail(BA_EUNSUPPORTED, "at most 2^29 edges");
+  for (int64_t e = 0; e < n_edges; ++e) {
+    if (ei[e] < 0 || ei[e] >= n_poses || ej[e] < 0 || ej[e] >= n_poses)
+      return fail(BA_EINVAL, "edge endpoint out of range");
+    if (ei[e] == ej[e]) return fail(BA_EINVAL, "an edge joins a pose to itself");
   }
-  p->rec_unit = (int32_t)rec_unit;
+  ba_options o;
+  if (opt) o = *opt;
+  else ba_default_options(&o);
+  if (o.precond != BA_PRECOND_BLOCK_JACOBI || o.enable_backward || o.huber_delta > 0.0)
+    return fail(BA_EUNSUPPORTED,
+                "pose graphs take the squared loss, block-Jacobi preconditioning and no adjoint");
+  o.cam_dof = 6;
+  const ba_status st = check_options(o, n_poses);
+  if (st != BA_OK) return st;
+  ba_problem* p = new (std::nothrow) ba_problem();
+  if (!p) return fail(BA_EINVAL, "out of host memory");
+  p->opt = o;
+  p->pgo = true;
+  p->n_edges = n_edges;
+  std::string err;
   try {
-    p->stab_units.resize(p->plan.stab.size());
+    // edge e as point e seen by its two poses: the plan's block pattern is
+    // then the diagonal plus one block per joined pair of poses
+    const int64_t no = 2 * n_edges;
+    std::vector<int32_t> cidx(no), pidx(no);
+    for (int64_t e = 0; e < n_edges; ++e) {
+      cidx[2 * e] = ei[e];
+      cidx[2 * e + 1] = ej[e];
+      pidx[2 * e] = pidx[2 * e + 1] = (int32_t)e;
+    }
+    err = ba::build_plan(n_poses, (int32_t)n_edges, no, cidx.data(), pidx.data(), &p->plan);
+    if (err.empty()) {
+      ba::Plan& P = p->plan;
+      // no points to eliminate: the Schur tables are not needed
+      for (auto* v : {&P.pair_x, &P.pair_y, &P.slot_blk, &P.slot_pb, &P.slot_pe, &P.slot_lead, &P.stab,
+                      &P.swptr})
+        std::vector<int32_t>().swap(*v);
+      P.n_pairs = 0;
+      P.n_schur_wg = 0;
+      p->pg_ei.assign(ei, ei + n_edges);
+      p->pg_ej.assign(ej, ej + n_edges);
+      // each block's edges in ascending edge order
+      std::vector<int32_t> cnt(P.nnzb + 1, 0), blk(n_edges);
+      for (int64_t e = 0; e < n_edges; ++e) {
+        const int32_t a = std::min(ei[e], ej[e]), b = std::max(ei[e], ej[e]);
+        const int32_t* rb = P.S_col.data() + P.S_ptr[a] + 1;
+        const int32_t* re = P.S_col.data() + P.S_ptr[a + 1];
+        const int32_t* it = std::lower_bound(rb, re, b);
+        if (it == re || *it != b) throw std::logic_error("edge block missing from the plan");
+        blk[e] = (int32_t)(it - P.S_col.data());
+        cnt[P.S_ptr[ei[e]] + 1]++;
+        cnt[P.S_ptr[ej[e]] + 1]++;
+        cnt[blk[e] + 1]++;
+      }
+      p->pg_ptr.assign(P.nnzb + 1, 0);
+      for (int64_t k = 0; k < P.nnzb; ++k) p->pg_ptr[k + 1] = p->pg_ptr[k] + cnt[k + 1];
+      p->pg_code.assign(p->pg_ptr[P.nnzb], 0);
+      std::vector<int32_t> fill(p->pg_ptr.begin(), p->pg_ptr.end() - 1);
+      for (int64_t e = 0; e < n_edges; ++e) {
+        p->pg_code[fill[P.S_ptr[ei[e]]]++] = (int32_t)(2 * e + 1);
+        p->pg_code[fill[P.S_ptr[ej[e]]]++] = (int32_t)(2 * e);
+        p->pg_code[fill[blk[e]]++] = (int32_t)(2 * e);
+      }
+    }
   } catch (const std::bad_alloc&) {
+    err = "out of host memory";
+  } catch (const std::logic_error& x) {
+    err = x.what();
+  }
+  if (!err.empty()) {
     delete p;
-    return fail(BA_EINVAL, "out of host memory");
+    const bool unsup = err.find("at most") != std::string::npos;
+    return fail(unsup ? BA_EUNSUPPORTED : BA_EINVAL, err);
   }
-  for (size_t i = 0; i < p->stab_units.size(); ++i) {
-    const int32_t c = p->plan.stab[i];
-    p->stab_units[i] = c >= 0 ? (int32_t)(c * row_units) : (c == -1 ? -1 : (int32_t)(rec_unit + (-2 - c)));
-  }
-  *out = p;
-  return BA_OK;
+  return finish_create(p, out);
 }
 
 ba_status ba_problem_workspace_bytes(const ba_problem* p, size_t* bytes) {
@@ -635,6 +778,14 @@ ba_status bind_workspace(ba_problem* p, void* ws, size_t bytes, void* stream, bo
     HIPCHK(upload(b.nbr_blk, P.nbr_blk, s));
     HIPCHK(upload(b.nbr_rev, P.nbr_rev, s));
   }
+  if (p->pgo) {
+    HIPCHK(upload(b.pg_ei, p->pg_ei, s));
+    HIPCHK(upload(b.pg_ej, p->pg_ej, s));
+    HIPCHK(upload(b.pg_ptr, p->pg_ptr, s));
+    HIPCHK(upload(b.pg_code, p->pg_code, s));
+    // the poses' rows carry zero intrinsics
+    for (int i = 0; i < 2; ++i) HIPCHK(hipMemsetAsync(b.cams[i], 0, sizeof(double) * 10 * P.nc, s));
+  }
   HIPCHK(hipMemsetAsync(b.fixed, p->opt.cam_dof == 6 ? ba::FIXED_INTRINSICS : 0, P.nc, s));
   HIPCHK(hipMemsetAsync(b.gsync, 0, sizeof(ba::GridSync), s));
   if (pinned) {
@@ -704,6 +855,7 @@ ba_status ba_problem_bind_static(ba_problem* p, void* stream) {
 
 ba_status ba_set_observations(ba_problem* p, const double* xy, const double* w) {
   if (!p || !xy) return fail(BA_EINVAL, "null argument");
+  if (p->pgo) return fail(BA_EINVAL, "a pose graph takes ba_pgo_set_edges");
   if (!usable(p)) return fail(BA_ESTATE, not_bound_msg(p));
   ba::ObsArgs a{p->plan.no, p->b.o_orig, xy, w, p->b.o_xy, p->b.o_w, p->b.dev};
   HIPCHK(ba::launch_set_observations(a, p->stream));
@@ -737,6 +889,7 @@ ba_status ba_set_fixed_cameras(ba_problem* p, const uint8_t* mask) {
 
 ba_status ba_set_params(ba_problem* p, const double* cams, const double* pts) {
   if (!p || !cams || !pts) return fail(BA_EINVAL, "null argument");
+  if (p->pgo) return fail(BA_EINVAL, "a pose graph takes ba_pgo_set_poses");
   if (!usable(p)) return fail(BA_ESTATE, not_bound_msg(p));
   HIPCHK(hipMemcpyAsync(p->b.cams[p->cur], cams, sizeof(double) * 10 * p->plan.nc,
                         hipMemcpyDeviceToDevice, p->stream));
@@ -749,6 +902,7 @@ ba_status ba_set_params(ba_problem* p, const double* cams, const double* pts) {
 
 ba_status ba_get_params(const ba_problem* p, double* cams, double* pts) {
   if (!p) return fail(BA_EINVAL, "null problem");
+  if (p->pgo) return fail(BA_EINVAL, "a pose graph takes ba_pgo_get_poses");
   if (!usable(p)) return fail(BA_ESTATE, not_bound_msg(p));
   if (!p->have_params) return fail(BA_ESTATE, "parameters are not set");
   if (cams)
@@ -757,6 +911,51 @@ ba_status ba_get_params(const ba_problem* p, double* cams, double* pts) {
   if (pts)
     HIPCHK(hipMemcpyAsync(pts, p->b.pts[p->cur], sizeof(double) * 3 * p->plan.np,
                           hipMemcpyDeviceToDevice, p->stream));
+  return BA_OK;
+}
+
+ba_status ba_pgo_set_edges(ba_problem* p, const double* T, const double* omega) {
+  if (!p || !T) return fail(BA_EINVAL, "null argument");
+  if (!p->pgo) return fail(BA_EINVAL, "not a pose graph");
+  if (!usable(p)) return fail(BA_ESTATE, not_bound_msg(p));
+  ba::PgoEdgeArgs a{p->n_edges, T, omega, p->b.pg_T, p->b.pg_om, p->b.dev};
+  HIPCHK(ba::launch_pgo_set_edges(a, p->stream));
+  HIPCHK(hipMemcpyAsync(p->hscal, p->b.dev, sizeof(ba::DevScalars), hipMemcpyDeviceToHost, p->stream));
+  HIPCHK(hipStreamSynchronize(p->stream));
+  const int32_t err = p->hscal->error;
+  if (err) {
+    p->hscal->error = 0;
+    HIPCHK(hipMemcpyAsync(p->b.dev, p->hscal, sizeof(ba::DevScalars), hipMemcpyHostToDevice, p->stream));
+    HIPCHK(hipStreamSynchronize(p->stream));
+    p->have_obs = false;
+    return fail(BA_EINVAL, (err & ba::ERR_NONFINITE_OBS)
+                               ? "non-finite measurement or information matrix"
+                               : "measurement quaternion not of unit norm, or information matrix not "
+                                 "symmetric with a positive diagonal");
+  }
+  p->have_obs = true;
+  p->lin_valid = false;
+  return BA_OK;
+}
+
+ba_status ba_pgo_set_poses(ba_problem* p, const double* poses) {
+  if (!p || !poses) return fail(BA_EINVAL, "null argument");
+  if (!p->pgo) return fail(BA_EINVAL, "not a pose graph");
+  if (!usable(p)) return fail(BA_ESTATE, not_bound_msg(p));
+  HIPCHK(hipMemcpy2DAsync(p->b.cams[p->cur], 10 * sizeof(double), poses, 7 * sizeof(double),
+                          7 * sizeof(double), p->plan.nc, hipMemcpyDeviceToDevice, p->stream));
+  p->have_params = true;
+  p->lin_valid = false;
+  return BA_OK;
+}
+
+ba_status ba_pgo_get_poses(const ba_problem* p, double* poses) {
+  if (!p || !poses) return fail(BA_EINVAL, "null argument");
+  if (!p->pgo) return fail(BA_EINVAL, "not a pose graph");
+  if (!usable(p)) return fail(BA_ESTATE, not_bound_msg(p));
+  if (!p->have_params) return fail(BA_ESTATE, "poses are not set");
+  HIPCHK(hipMemcpy2DAsync(poses, 7 * sizeof(double), p->b.cams[p->cur], 10 * sizeof(double),
+                          7 * sizeof(double), p->plan.nc, hipMemcpyDeviceToDevice, p->stream));
   return BA_OK;
 }
 
@@ -933,7 +1132,8 @@ ba_status ba_set_gnn_params(ba_problem* p, const float* params) {
 
 ba_status ba_get_state(const ba_problem* p, void* blob, size_t* bytes) {
   if (!p || !bytes) return fail(BA_EINVAL, "null argument");
-  const size_t need = sizeof(double) * (4 + 10 * (size_t)p->plan.nc + 3 * (size_t)p->plan.np);
+  const size_t np = point_count(p);
+  const size_t need = sizeof(double) * (4 + 10 * (size_t)p->plan.nc + 3 * np);
   if (!blob) {
     *bytes = need;
     return BA_OK;
@@ -944,12 +1144,13 @@ ba_status ba_get_state(const ba_problem* p, void* blob, size_t* bytes) {
   double* d = reinterpret_cast<double*>(blob);
   d[0] = 1.0;  // format version
   d[1] = p->plan.nc;
-  d[2] = p->plan.np;
+  d[2] = (double)np;
   d[3] = p->lambda;
   HIPCHK(hipMemcpyAsync(d + 4, p->b.cams[p->cur], sizeof(double) * 10 * p->plan.nc,
                         hipMemcpyDeviceToHost, p->stream));
-  HIPCHK(hipMemcpyAsync(d + 4 + 10 * (size_t)p->plan.nc, p->b.pts[p->cur],
-                        sizeof(double) * 3 * p->plan.np, hipMemcpyDeviceToHost, p->stream));
+  if (np)
+    HIPCHK(hipMemcpyAsync(d + 4 + 10 * (size_t)p->plan.nc, p->b.pts[p->cur], sizeof(double) * 3 * np,
+                          hipMemcpyDeviceToHost, p->stream));
   HIPCHK(hipStreamSynchronize(p->stream));
   *bytes = need;
   return BA_OK;
@@ -958,14 +1159,16 @@ ba_status ba_get_state(const ba_problem* p, void* blob, size_t* bytes) {
 ba_status ba_set_state(ba_problem* p, const void* blob, size_t bytes) {
   if (!p || !blob) return fail(BA_EINVAL, "null argument");
   if (!usable(p)) return fail(BA_ESTATE, not_bound_msg(p));
-  const size_t need = sizeof(double) * (4 + 10 * (size_t)p->plan.nc + 3 * (size_t)p->plan.np);
+  const size_t np = point_count(p);
+  const size_t need = sizeof(double) * (4 + 10 * (size_t)p->plan.nc + 3 * np);
   const double* d = reinterpret_cast<const double*>(blob);
-  if (bytes != need || d[0] != 1.0 || d[1] != p->plan.nc || d[2] != p->plan.np)
+  if (bytes != need || d[0] != 1.0 || d[1] != p->plan.nc || d[2] != (double)np)
     return fail(BA_EINVAL, "state blob does not match this problem");
   HIPCHK(hipMemcpyAsync(p->b.cams[p->cur], d + 4, sizeof(double) * 10 * p->plan.nc,
                         hipMemcpyHostToDevice, p->stream));
-  HIPCHK(hipMemcpyAsync(p->b.pts[p->cur], d + 4 + 10 * (size_t)p->plan.nc,
-                        sizeof(double) * 3 * p->plan.np, hipMemcpyHostToDevice, p->stream));
+  if (np)
+    HIPCHK(hipMemcpyAsync(p->b.pts[p->cur], d + 4 + 10 * (size_t)p->plan.nc, sizeof(double) * 3 * np,
+                          hipMemcpyHostToDevice, p->stream));
   HIPCHK(hipStreamSynchronize(p->stream));
   p->have_params = true;
   p->lin_valid = false;
@@ -988,6 +1191,10 @@ ba_status ba_export(const ba_problem* p, int32_t field, void* dst, size_t bytes)
   };
   std::vector<char> h;
   double* out = reinterpret_cast<double*>(dst);
+  if (p->pgo && (field == BA_X_RESIDUAL || field == BA_X_WEIGHT || field == BA_X_JC || field == BA_X_JP ||
+                 field == BA_X_GRAD_P || field == BA_X_V || field == BA_X_DP || field == BA_X_ADJ_VC ||
+                 field == BA_X_ADJ_VP))
+    return fail(BA_EINVAL, "a pose graph has no observation or point fields");
   switch (field) {
     case BA_X_RESIDUAL:
     case BA_X_WEIGHT: {

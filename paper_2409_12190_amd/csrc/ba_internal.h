@@ -208,6 +208,10 @@ struct Buffers {
   int32_t *nbr_ptr, *nbr, *nbr_blk, *nbr_rev;
   float *gX, *gE, *gw;         // network inputs
   float* gact;                 // activations (inference)
+  // pose graphs: edge endpoints, measurements [m][8], information [m][36],
+  // per-edge records (A, b), and each stored block's edge list
+  int32_t *pg_ei, *pg_ej, *pg_ptr, *pg_code;
+  double *pg_T, *pg_om, *pg_rec;
 };
 
 }  // namespace ba
@@ -249,4 +253,11 @@ struct ba_problem {
   bool static_ws = false;
   ba_step_info hinfo_local{};
   ba::DevScalars hscal_local{};
+  // pose graph (ba_pgo_create): n_edges edges i -> j; the camera rows hold
+  // the poses and the plan is that of two observations per edge; pg_ptr /
+  // pg_code list each stored block's edges (2 e + 1 when the block's row is
+  // the edge's first pose, else 2 e)
+  bool pgo = false;
+  int64_t n_edges = 0;
+  std::vector<int32_t> pg_ei, pg_ej, pg_ptr, pg_code;
 };

@@ -160,3 +160,28 @@ def test_option_struct_layout_matches_the_binding():
     assert o.cam_dof == 9 and o.cg_maxiter == 250 and o.cg_rtol == 1e-4
     assert o.precond == B.BA_PRECOND_BLOCK_JACOBI and o.adjoint_rtol == 1e-10
     assert o.adjoint_grad_tol == 1e-6
+
+
+def test_pose_graph_create_validates_and_matches_the_oracle_pattern():
+    from synth.posegraph import make_pose_graph
+    o = B.ba_default_options()
+    for ei, ej in (([0, 1], [1, 4]), ([0, -1], [1, 2]), ([0, 2], [1, 2])):
+        with pytest.raises(B.BaError) as e:
+            B.ba_pgo_create(o, 4, ei, ej)
+        assert e.value.status == B.BA_EINVAL
+    for k, v in (("huber_delta", 1.0), ("precond", B.BA_PRECOND_LEARNED), ("enable_backward", 1)):
+        oo = B.ba_default_options()
+        setattr(oo, k, v)
+        with pytest.raises(B.BaError) as e:
+            B.ba_pgo_create(oo, 4, [0, 1], [1, 2])
+        assert e.value.status == B.BA_EUNSUPPORTED
+    g = make_pose_graph(1, rings=5, per_ring=7)
+    h = B.ba_pgo_create(o, g.n_poses, g.ei, g.ej)
+    try:
+        assert B.ba_problem_nnzb(h) == O.PgoOracle(g).system()[1].size
+        assert B.ba_problem_workspace_bytes(h) > 0
+        with pytest.raises(B.BaError) as e:
+            B.ba_lm_step(h)
+        assert e.value.status == B.BA_ESTATE
+    finally:
+        B.ba_problem_destroy(h)
