@@ -86,8 +86,9 @@ typedef struct {
   int32_t precond;         /* BA_PRECOND_BLOCK_JACOBI, or BA_PRECOND_LEARNED: the
                               block-Jacobi blocks corrected by the camera-graph
                               network (ba_set_gnn_params); until parameters are
-                              set, and whenever its PCG misses cg_rtol, the step
-                              uses plain block-Jacobi */
+                              set, and whenever its PCG fails (breaks down, or
+                              ends with a non-finite relative residual or one
+                              >= 1), the step uses plain block-Jacobi */
   double adjoint_grad_tol; /* ba_backward requires a stationary theta:
                               max_i |g_i| <= adjoint_grad_tol * max_k,i |w_k (J_k^T r_k)_i|
                               (the gradient against the scale of its terms) */
@@ -120,7 +121,7 @@ typedef struct {
   int32_t cg_breakdown; /* 1 if p^T S p <= 0 stopped the PCG */
   int32_t status;       /* ba_status of the step */
   int32_t precond_used; /* 0 block-Jacobi, 1 learned, 2 learned then block-Jacobi
-                           (the learned PCG missed cg_rtol) */
+                           (the learned PCG failed, see ba_options.precond) */
   int32_t stop_reason;  /* ba_solve, on its last step: BA_STOP_* (BA_STOP_NONE on
                            every other step and from ba_lm_step) */
 } ba_step_info;

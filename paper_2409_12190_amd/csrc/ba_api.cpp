@@ -414,12 +414,16 @@ ba_status lm_step_impl(ba_problem* p, ba_step_info* out) {
   } else {
     PHASE(7, launch_pcg<T>(pa, pcg_grid, P.pcg_resident, pipe, s));
   }
-  if (learned && p->cg_rtol > 0.0) {
-    // the unpreconditioned residual judges the learned blocks: when the PCG
-    // missed its tolerance the step is solved again with block-Jacobi
+  if (learned) {
+    // the learned blocks are trusted unless their PCG failed: a breakdown,
+    // a non-finite residual, or no reduction of the unpreconditioned
+    // residual at all; then the step is solved again with block-Jacobi.  A
+    // learned solve that reaches the iteration cap is an inexact step like
+    // any other (the trust region judges it).
     HIPCHK(hipMemcpyAsync(p->hinfo, b.dinfo, sizeof(ba_step_info), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
-    if (!(p->hinfo->cg_rel_resid <= p->cg_rtol)) {
+    const ba_step_info& li = *p->hinfo;
+    if (li.cg_breakdown || !(li.cg_rel_resid < 1.0)) {
       pa.Minv = b.Minv;
       HIPCHK(reset_sync(p));
       PHASE(7, launch_pcg<T>(pa, pcg_grid, P.pcg_resident, pipe, s));
