@@ -103,10 +103,12 @@ def source_digest(kernel="pcg"):
     return h.hexdigest()[:16]
 
 
-def recorded_traffic(workload, kernel):
+def recorded_traffic(workload, kernel, cg_iters=None):
     """Per-launch HBM bytes of a kernel from the counter summary under
     profiles/ (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy's reading),
-    or None when the summary is absent or was taken on other sources."""
+    or None when the summary is absent or was taken on other sources.  A
+    summary that gives bytes per CG iteration is scaled to the launch's
+    cg_iters."""
     path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.txt")
     if not os.path.exists(path):
         return None
@@ -119,6 +121,8 @@ def recorded_traffic(workload, kernel):
     if vals.get("source_digest") != source_digest(kernel):
         return None
     try:
+        if cg_iters is not None and "bytes_per_cg_iteration" in vals:
+            return float(vals["bytes_per_cg_iteration"]) * cg_iters
         return float(vals["bytes_per_launch"])
     except (KeyError, ValueError):
         return None
@@ -360,7 +364,7 @@ def main():
         achieved = per_launch / (ms / n * 1e-3) / 1e9
         out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                            "frac": achieved / HBM_PEAK_GBS,
-                           "traffic": recorded_traffic(args.workload, dom),
+                           "traffic": recorded_traffic(args.workload, dom, cg_total / max(n, 1)),
                            "kernel": dom, "avg_launch_ms": ms / n, "launches": n,
                            "algorithmic_bytes_per_launch": per_launch,
                            "cg_iters_per_launch": cg_total / max(n, 1)}
