@@ -13,10 +13,10 @@
 // accurate near 0 and pi.  Jl^-1 of SE(3) is evaluated in closed form,
 //   Jl^-1 = [[P, -P Q P], [0, P]],
 // P = Jl^-1 of SO(3) = I - phi^/2 + a phi^2, a = (1 - (th/2) cot(th/2)) / th^2,
-// and Q(rho, phi) the coupling block of the SE(3) left Jacobian (Barfoot and
-// Furgale, "Associating Uncertainty with Three-Dimensional Poses for Use in
-// Estimation Problems", Eq. 102), with series for its coefficients at small
-// angles.
+// and Q(rho, phi) the coupling block of the SE(3) left Jacobian in closed
+// form (Barfoot and Furgale, "Associating Uncertainty with Three-Dimensional
+// Poses for Use in Estimation Problems", 2014), with series for its
+// coefficients at small angles.
 #include <hip/hip_runtime.h>
 
 #include "ba_device.h"
