@@ -99,9 +99,19 @@ typedef struct {
                               FP64 (at most 2048 cameras; the workspace grows
                               by 8 (9 n_cams)^2 bytes); cg_* are then unused
                               and cg_rel_resid reports |b - S x| / |b| */
+  int32_t camera_order;    /* BA_ORDER_BANDWIDTH: the library renumbers the
+                              cameras internally (reverse Cuthill-McKee order of
+                              their co-visibility graph) so that the reduced
+                              matrix's blocks lie near its diagonal and the
+                              PCG's workgroups exchange with few others; every
+                              entry point still takes and returns cameras in
+                              the caller's order.  BA_ORDER_GIVEN: the caller's
+                              order is used as is */
 } ba_options;
 
 enum { BA_SOLVER_PCG = 0, BA_SOLVER_CHOLESKY = 1 };
+
+enum { BA_ORDER_BANDWIDTH = 0, BA_ORDER_GIVEN = 1 };
 
 enum { BA_PRECOND_BLOCK_JACOBI = 0, BA_PRECOND_LEARNED = 1 };
 
@@ -139,7 +149,7 @@ enum {
 /* Fills *opt with the defaults: cam_dof 9, BA_FP64, squared loss, cg_rtol 1e-4,
  * cg_maxiter 250, lambda0 1e-4, lambda in [1e-12, 1e12], clamp [1e-6, 1e32],
  * BA_CG_PIPELINED, backward disabled, adjoint_rtol 1e-10, block-Jacobi,
- * adjoint_grad_tol 1e-6, BA_SOLVER_PCG. */
+ * adjoint_grad_tol 1e-6, BA_SOLVER_PCG, BA_ORDER_BANDWIDTH. */
 void ba_default_options(ba_options* opt);
 
 /* Creates a problem from the observation pattern: observation k sees point

@@ -26,6 +26,7 @@ BA_CG_PIPELINED, BA_CG_STANDARD = 0, 1
 PCG_LAYOUTS = {0: "resident", 1: "per_item", 2: "streamed"}
 BA_PRECOND_BLOCK_JACOBI, BA_PRECOND_LEARNED = 0, 1
 BA_SOLVER_PCG, BA_SOLVER_CHOLESKY = 0, 1
+BA_ORDER_BANDWIDTH, BA_ORDER_GIVEN = 0, 1
 (BA_STOP_NONE, BA_STOP_MAX_ITERS, BA_STOP_PLATEAU, BA_STOP_GRADIENT, BA_STOP_LAMBDA_MAX,
  BA_STOP_ERROR) = range(6)
 BA_GNN_FEATURES, BA_GNN_HIDDEN, BA_GNN_OUTPUTS, BA_GNN_LAYERS = 47, 64, 45, 3
@@ -59,7 +60,8 @@ class ba_options(C.Structure):
                 ("lambda_min", C.c_double), ("lambda_max", C.c_double), ("diag_min", C.c_double),
                 ("diag_max", C.c_double), ("cg_variant", C.c_int32), ("enable_backward", C.c_int32),
                 ("adjoint_rtol", C.c_double), ("precond", C.c_int32),
-                ("adjoint_grad_tol", C.c_double), ("linear_solver", C.c_int32)]
+                ("adjoint_grad_tol", C.c_double), ("linear_solver", C.c_int32),
+                ("camera_order", C.c_int32)]
 
 
 class ba_step_info(C.Structure):
@@ -334,7 +336,7 @@ class Problem:
                  cams=None, pts=None, stream=None, cg_variant=BA_CG_PIPELINED,
                  enable_backward=False, adjoint_rtol=1e-10, precond=BA_PRECOND_BLOCK_JACOBI,
                  lambda_min=None, lambda_max=None, adjoint_grad_tol=None, cam_dof=9,
-                 linear_solver=BA_SOLVER_PCG, static_workspace=False):
+                 linear_solver=BA_SOLVER_PCG, static_workspace=False, camera_order=BA_ORDER_BANDWIDTH):
         import torch
         self.torch = torch
         self.device = torch.device("cuda", torch.cuda.current_device())
@@ -350,6 +352,7 @@ class Problem:
         opt.precond = precond
         opt.cam_dof = cam_dof
         opt.linear_solver = linear_solver
+        opt.camera_order = camera_order
         if lambda_min is not None:
             opt.lambda_min = lambda_min
         if lambda_max is not None:
@@ -530,7 +533,7 @@ class PoseGraph:
     def __init__(self, n_poses, ei, ej, T, omega=None, poses=None, *, fixed=None, precision=BA_FP64,
                  cg_rtol=1e-4, cg_maxiter=250, lambda0=1e-4, lambda_min=None, lambda_max=None,
                  cg_variant=BA_CG_PIPELINED, linear_solver=BA_SOLVER_PCG, stream=None,
-                 static_workspace=False):
+                 static_workspace=False, camera_order=BA_ORDER_BANDWIDTH):
         import torch
         self.torch = torch
         self.device = torch.device("cuda", torch.cuda.current_device())
@@ -541,6 +544,7 @@ class PoseGraph:
         opt.lambda0 = lambda0
         opt.cg_variant = cg_variant
         opt.linear_solver = linear_solver
+        opt.camera_order = camera_order
         if lambda_min is not None:
             opt.lambda_min = lambda_min
         if lambda_max is not None:

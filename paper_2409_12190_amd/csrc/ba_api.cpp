@@ -195,6 +195,8 @@ void carve(ba_problem* p, char* base, size_t* total) {
     b.gw = c.take<float>(ns);
     b.gact = c.take<float>((2 * (ba::GNN_L + 1) + ba::GNN_L) * nc * ba::GNN_H);
   }
+  b.cam_perm = c.take<int32_t>(p->reordered ? nc : 0);
+  b.adj_gcam = c.take<double>(p->reordered && p->opt.enable_backward ? 10 * nc : 0);
   if (p->pgo) {
     const size_t m = p->n_edges;
     b.pg_ei = c.take<int32_t>(m);
@@ -238,6 +240,29 @@ ba_status require_ready(const ba_problem* p) {
   if (!p->have_obs) return fail(BA_ESTATE, p->pgo ? "measurements are not set" : "observations are not set");
   if (!p->have_params) return fail(BA_ESTATE, p->pgo ? "poses are not set" : "parameters are not set");
   return BA_OK;
+}
+
+// Device rows of per-camera values between caller order and the internal
+// order: to_caller gathers internal rows into caller order, otherwise the
+// caller's rows are scattered into internal order; `width` values of rows
+// of src_stride / dst_stride doubles.
+hipError_t copy_cameras(const ba_problem* p, const double* src, int src_stride, double* dst, int dst_stride,
+                        int width, bool to_caller) {
+  const int nc = p->plan.nc;
+  if (!p->reordered)
+    return hipMemcpy2DAsync(dst, dst_stride * sizeof(double), src, src_stride * sizeof(double),
+                            width * sizeof(double), nc, hipMemcpyDeviceToDevice, p->stream);
+  ba::PermArgs a{nc, p->b.cam_perm, to_caller, src, dst, src_stride, dst_stride, width};
+  return ba::launch_permute_rows(a, p->stream);
+}
+
+// Host rows (per camera, `width` values) from internal to caller order.
+void rows_to_caller(const ba_problem* p, const double* in, double* out, size_t width) {
+  const size_t nc = p->plan.nc;
+  for (size_t c = 0; c < nc; ++c) {
+    const size_t ic = p->reordered ? (size_t)p->cam_perm[c] : c;
+    std::memcpy(out + c * width, in + ic * width, width * sizeof(double));
+  }
 }
 
 // points held in the parameter state (none for a pose graph)
@@ -535,13 +560,69 @@ ba_status check_options(const ba_options& o, int32_t n_cams) {
     return fail(BA_EINVAL, "unknown linear solver");
   if (o.linear_solver == BA_SOLVER_CHOLESKY && (n_cams > ba::DENSE_MAX_CAMS || o.precond == BA_PRECOND_LEARNED))
     return fail(BA_EUNSUPPORTED, "the dense Cholesky solve takes at most 2048 cameras and no learned preconditioner");
+  if (o.camera_order != BA_ORDER_BANDWIDTH && o.camera_order != BA_ORDER_GIVEN)
+    return fail(BA_EINVAL, "unknown camera order");
   return BA_OK;
+}
+
+// The internal camera numbering of a problem (identity unless the options
+// ask for the bandwidth order and it differs from the caller's); returns
+// the indices relabelled.
+std::vector<int32_t> set_order(ba_problem* p, int32_t nc, int32_t np, int64_t no, const int32_t* cidx,
+                               const int32_t* pidx) {
+  std::vector<int32_t> perm;
+  if (p->opt.camera_order == BA_ORDER_BANDWIDTH && nc > 1) perm = ba::camera_order(nc, np, no, cidx, pidx);
+  bool ident = true;
+  for (int32_t c = 0; c < (int32_t)perm.size() && ident; ++c) ident = perm[c] == c;
+  std::vector<int32_t> out(cidx, cidx + no);
+  if (perm.empty() || ident) return out;
+  p->reordered = true;
+  p->cam_perm = perm;
+  p->cam_inv.assign(nc, 0);
+  for (int32_t c = 0; c < nc; ++c) p->cam_inv[perm[c]] = c;
+  for (int64_t k = 0; k < no; ++k) out[k] = perm[cidx[k]];
+  return out;
+}
+
+// The block pattern in caller order (for ba_export of a renumbered problem).
+void caller_pattern(ba_problem* p) {
+  const ba::Plan& P = p->plan;
+  const int32_t nc = P.nc;
+  std::vector<std::vector<std::pair<int32_t, int32_t>>> rows(nc);  // (column, internal block)
+  for (int32_t a = 0; a < nc; ++a)
+    for (int32_t e = P.S_ptr[a]; e < P.S_ptr[a + 1]; ++e) {
+      const int32_t ca = p->cam_inv[a], cb = p->cam_inv[P.S_col[e]];
+      if (ca <= cb) rows[ca].push_back({cb, e});
+      else rows[cb].push_back({ca, -1 - e});
+    }
+  p->x_ptr.assign(nc + 1, 0);
+  p->x_col.clear();
+  p->x_blk.clear();
+  p->x_tr.clear();
+  for (int32_t a = 0; a < nc; ++a) {
+    auto& r = rows[a];
+    std::sort(r.begin(), r.end());  // the diagonal (column a) comes first: no column below a
+    for (const auto& cb : r) {
+      p->x_col.push_back(cb.first);
+      p->x_blk.push_back(cb.second >= 0 ? cb.second : -1 - cb.second);
+      p->x_tr.push_back(cb.second < 0 ? 1 : 0);
+    }
+    p->x_ptr[a + 1] = (int64_t)p->x_col.size();
+  }
 }
 
 // Sizes the workspace and the Schur step table of a planned problem; takes
 // ownership of p (deleted on failure).
 ba_status finish_create(ba_problem* p, ba_problem** out) {
   const ba_options& o = p->opt;
+  if (p->reordered) {
+    try {
+      caller_pattern(p);
+    } catch (const std::bad_alloc&) {
+      delete p;
+      return fail(BA_EINVAL, "out of host memory");
+    }
+  }
   p->lambda = o.lambda0;
   p->cg_rtol = o.cg_rtol;
   p->cg_maxiter = o.cg_maxiter;
@@ -592,6 +673,7 @@ void ba_default_options(ba_options* o) {
   o->precond = BA_PRECOND_BLOCK_JACOBI;
   o->adjoint_grad_tol = 1e-6;
   o->linear_solver = BA_SOLVER_PCG;
+  o->camera_order = BA_ORDER_BANDWIDTH;
 }
 
 const char* ba_last_error(void) { return g_err.c_str(); }
@@ -609,12 +691,17 @@ ba_status ba_problem_create(const ba_options* opt, int32_t n_cams, int32_t n_pts
     return fail(BA_EUNSUPPORTED, "the 6-DoF camera supports neither the learned preconditioner nor the adjoint");
   const ba_status st = check_options(o, n_cams);
   if (st != BA_OK) return st;
+  if (n_cams <= 0 || n_pts <= 0 || n_obs <= 0) return fail(BA_EINVAL, "n_cams, n_pts and n_obs must be positive");
+  for (int64_t k = 0; k < n_obs; ++k)
+    if (cam_idx[k] < 0 || cam_idx[k] >= n_cams || pt_idx[k] < 0 || pt_idx[k] >= n_pts)
+      return fail(BA_EINVAL, "observation index out of range");
   ba_problem* p = new (std::nothrow) ba_problem();
   if (!p) return fail(BA_EINVAL, "out of host memory");
   p->opt = o;
   std::string err;
   try {
-    err = ba::build_plan(n_cams, n_pts, n_obs, cam_idx, pt_idx, &p->plan);
+    const std::vector<int32_t> ci = set_order(p, n_cams, n_pts, n_obs, cam_idx, pt_idx);
+    err = ba::build_plan(n_cams, n_pts, n_obs, ci.data(), pt_idx, &p->plan);
   } catch (const std::bad_alloc&) {
     err = "out of host memory";
   }
@@ -663,6 +750,14 @@ ba_status ba_pgo_create(const ba_options* opt, int32_t n_poses, int64_t n_edges,
       cidx[2 * e + 1] = ej[e];
       pidx[2 * e] = pidx[2 * e + 1] = (int32_t)e;
     }
+    cidx = set_order(p, n_poses, (int32_t)n_edges, no, cidx.data(), pidx.data());
+    std::vector<int32_t> ii(n_edges), jj(n_edges);
+    for (int64_t e = 0; e < n_edges; ++e) {
+      ii[e] = cidx[2 * e];
+      jj[e] = cidx[2 * e + 1];
+    }
+    ei = ii.data();
+    ej = jj.data();
     err = ba::build_plan(n_poses, (int32_t)n_edges, no, cidx.data(), pidx.data(), &p->plan);
     if (err.empty()) {
       ba::Plan& P = p->plan;
@@ -782,6 +877,7 @@ ba_status bind_workspace(ba_problem* p, void* ws, size_t bytes, void* stream, bo
     HIPCHK(upload(b.nbr_blk, P.nbr_blk, s));
     HIPCHK(upload(b.nbr_rev, P.nbr_rev, s));
   }
+  if (p->reordered) HIPCHK(upload(b.cam_perm, p->cam_perm, s));
   if (p->pgo) {
     HIPCHK(upload(b.pg_ei, p->pg_ei, s));
     HIPCHK(upload(b.pg_ej, p->pg_ej, s));
@@ -884,7 +980,8 @@ ba_status ba_set_fixed_cameras(ba_problem* p, const uint8_t* mask) {
   const uint8_t base = p->opt.cam_dof == 6 ? ba::FIXED_INTRINSICS : 0;
   std::vector<uint8_t> m(p->plan.nc, base);
   if (mask)
-    for (int32_t i = 0; i < p->plan.nc; ++i) m[i] = mask[i] ? ba::FIXED_CAMERA : base;
+    for (int32_t i = 0; i < p->plan.nc; ++i)
+      m[p->reordered ? p->cam_perm[i] : i] = mask[i] ? ba::FIXED_CAMERA : base;
   HIPCHK(hipMemcpyAsync(p->b.fixed, m.data(), m.size(), hipMemcpyHostToDevice, p->stream));
   HIPCHK(hipStreamSynchronize(p->stream));
   p->lin_valid = false;
@@ -895,8 +992,7 @@ ba_status ba_set_params(ba_problem* p, const double* cams, const double* pts) {
   if (!p || !cams || !pts) return fail(BA_EINVAL, "null argument");
   if (p->pgo) return fail(BA_EINVAL, "a pose graph takes ba_pgo_set_poses");
   if (!usable(p)) return fail(BA_ESTATE, not_bound_msg(p));
-  HIPCHK(hipMemcpyAsync(p->b.cams[p->cur], cams, sizeof(double) * 10 * p->plan.nc,
-                        hipMemcpyDeviceToDevice, p->stream));
+  HIPCHK(copy_cameras(p, cams, 10, p->b.cams[p->cur], 10, 10, false));
   HIPCHK(hipMemcpyAsync(p->b.pts[p->cur], pts, sizeof(double) * 3 * p->plan.np,
                         hipMemcpyDeviceToDevice, p->stream));
   p->have_params = true;
@@ -909,9 +1005,7 @@ ba_status ba_get_params(const ba_problem* p, double* cams, double* pts) {
   if (p->pgo) return fail(BA_EINVAL, "a pose graph takes ba_pgo_get_poses");
   if (!usable(p)) return fail(BA_ESTATE, not_bound_msg(p));
   if (!p->have_params) return fail(BA_ESTATE, "parameters are not set");
-  if (cams)
-    HIPCHK(hipMemcpyAsync(cams, p->b.cams[p->cur], sizeof(double) * 10 * p->plan.nc,
-                          hipMemcpyDeviceToDevice, p->stream));
+  if (cams) HIPCHK(copy_cameras(p, p->b.cams[p->cur], 10, cams, 10, 10, true));
   if (pts)
     HIPCHK(hipMemcpyAsync(pts, p->b.pts[p->cur], sizeof(double) * 3 * p->plan.np,
                           hipMemcpyDeviceToDevice, p->stream));
@@ -946,8 +1040,7 @@ ba_status ba_pgo_set_poses(ba_problem* p, const double* poses) {
   if (!p || !poses) return fail(BA_EINVAL, "null argument");
   if (!p->pgo) return fail(BA_EINVAL, "not a pose graph");
   if (!usable(p)) return fail(BA_ESTATE, not_bound_msg(p));
-  HIPCHK(hipMemcpy2DAsync(p->b.cams[p->cur], 10 * sizeof(double), poses, 7 * sizeof(double),
-                          7 * sizeof(double), p->plan.nc, hipMemcpyDeviceToDevice, p->stream));
+  HIPCHK(copy_cameras(p, poses, 7, p->b.cams[p->cur], 10, 7, false));
   p->have_params = true;
   p->lin_valid = false;
   return BA_OK;
@@ -958,8 +1051,7 @@ ba_status ba_pgo_get_poses(const ba_problem* p, double* poses) {
   if (!p->pgo) return fail(BA_EINVAL, "not a pose graph");
   if (!usable(p)) return fail(BA_ESTATE, not_bound_msg(p));
   if (!p->have_params) return fail(BA_ESTATE, "poses are not set");
-  HIPCHK(hipMemcpy2DAsync(poses, 7 * sizeof(double), p->b.cams[p->cur], 10 * sizeof(double),
-                          7 * sizeof(double), p->plan.nc, hipMemcpyDeviceToDevice, p->stream));
+  HIPCHK(copy_cameras(p, p->b.cams[p->cur], 10, poses, 7, 7, true));
   return BA_OK;
 }
 
@@ -1054,6 +1146,10 @@ ba_status ba_backward(ba_problem* p, const double* dL_dcams, const double* dL_dp
   HIPCHK(hipMemsetAsync(b.adj_dev, 0, sizeof(DevScalars), s));
   HIPCHK(hipMemsetAsync(b.adj_info, 0, sizeof(ba_step_info), s));
   HIPCHK(hipMemsetAsync(b.diagU, 0, 9 * sizeof(double) * P.nc, s));  // no damping term
+  if (p->reordered) {
+    HIPCHK(copy_cameras(p, dL_dcams, 10, b.adj_gcam, 10, 10, false));
+    dL_dcams = b.adj_gcam;
+  }
   AdjTangentArgs ta{P.nc, b.fixed, b.cams[cur], dL_dcams, b.adj_gt};
   HIPCHK(launch_adj_tangent(ta, s));
   AdjObsArgs oa{P.no, b.o_cam, b.o_pt, b.fixed, b.o_xy, b.o_w, b.cams[cur], b.pts[cur],
@@ -1150,12 +1246,14 @@ ba_status ba_get_state(const ba_problem* p, void* blob, size_t* bytes) {
   d[1] = p->plan.nc;
   d[2] = (double)np;
   d[3] = p->lambda;
-  HIPCHK(hipMemcpyAsync(d + 4, p->b.cams[p->cur], sizeof(double) * 10 * p->plan.nc,
-                        hipMemcpyDeviceToHost, p->stream));
+  std::vector<double> cams(10 * (size_t)p->plan.nc);
+  HIPCHK(hipMemcpyAsync(cams.data(), p->b.cams[p->cur], sizeof(double) * cams.size(), hipMemcpyDeviceToHost,
+                        p->stream));
   if (np)
     HIPCHK(hipMemcpyAsync(d + 4 + 10 * (size_t)p->plan.nc, p->b.pts[p->cur], sizeof(double) * 3 * np,
                           hipMemcpyDeviceToHost, p->stream));
   HIPCHK(hipStreamSynchronize(p->stream));
+  rows_to_caller(p, cams.data(), d + 4, 10);
   *bytes = need;
   return BA_OK;
 }
@@ -1168,8 +1266,12 @@ ba_status ba_set_state(ba_problem* p, const void* blob, size_t bytes) {
   const double* d = reinterpret_cast<const double*>(blob);
   if (bytes != need || d[0] != 1.0 || d[1] != p->plan.nc || d[2] != (double)np)
     return fail(BA_EINVAL, "state blob does not match this problem");
-  HIPCHK(hipMemcpyAsync(p->b.cams[p->cur], d + 4, sizeof(double) * 10 * p->plan.nc,
-                        hipMemcpyHostToDevice, p->stream));
+  std::vector<double> cams(10 * (size_t)p->plan.nc);
+  for (size_t c = 0; c < (size_t)p->plan.nc; ++c)
+    std::memcpy(cams.data() + 10 * (p->reordered ? (size_t)p->cam_perm[c] : c), d + 4 + 10 * c,
+                10 * sizeof(double));
+  HIPCHK(hipMemcpyAsync(p->b.cams[p->cur], cams.data(), sizeof(double) * cams.size(), hipMemcpyHostToDevice,
+                        p->stream));
   if (np)
     HIPCHK(hipMemcpyAsync(p->b.pts[p->cur], d + 4 + 10 * (size_t)p->plan.nc, sizeof(double) * 3 * np,
                           hipMemcpyHostToDevice, p->stream));
@@ -1244,8 +1346,8 @@ ba_status ba_export(const ba_problem* p, int32_t field, void* dst, size_t bytes)
     case BA_X_DC: {
       if (!need(nc * 9 * sizeof(double))) return fail(BA_EINVAL, "size mismatch");
       const double* src = field == BA_X_GRAD_C ? b.gc : field == BA_X_BS ? b.bS : b.x;
-      HIPCHK(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, p->stream));
-      HIPCHK(hipStreamSynchronize(p->stream));
+      HIPCHK(fetch(src, bytes, h));
+      rows_to_caller(p, reinterpret_cast<const double*>(h.data()), out, 9);
       return BA_OK;
     }
     case BA_X_GRAD_P:
@@ -1259,8 +1361,8 @@ ba_status ba_export(const ba_problem* p, int32_t field, void* dst, size_t bytes)
     case BA_X_PRECOND: {
       if (!need(nc * 81 * sizeof(double))) return fail(BA_EINVAL, "size mismatch");
       const bool learned = p->opt.precond == BA_PRECOND_LEARNED && p->gnn_ready;
-      HIPCHK(hipMemcpyAsync(dst, learned ? b.pcMinvL : b.Minv, bytes, hipMemcpyDeviceToHost, p->stream));
-      HIPCHK(hipStreamSynchronize(p->stream));
+      HIPCHK(fetch(learned ? b.pcMinvL : b.Minv, bytes, h));
+      rows_to_caller(p, reinterpret_cast<const double*>(h.data()), out, 81);
       return BA_OK;
     }
     case BA_X_ADJ_VC:
@@ -1268,7 +1370,12 @@ ba_status ba_export(const ba_problem* p, int32_t field, void* dst, size_t bytes)
       if (!p->opt.enable_backward) return fail(BA_ESTATE, "backward buffers are not enabled");
       const bool vc = field == BA_X_ADJ_VC;
       if (!need((vc ? nc * 9 : np * 3) * sizeof(double))) return fail(BA_EINVAL, "size mismatch");
-      HIPCHK(hipMemcpyAsync(dst, vc ? b.adj_vc : b.adj_vp, bytes, hipMemcpyDeviceToHost, p->stream));
+      if (vc) {
+        HIPCHK(fetch(b.adj_vc, bytes, h));
+        rows_to_caller(p, reinterpret_cast<const double*>(h.data()), out, 9);
+        return BA_OK;
+      }
+      HIPCHK(hipMemcpyAsync(dst, b.adj_vp, bytes, hipMemcpyDeviceToHost, p->stream));
       HIPCHK(hipStreamSynchronize(p->stream));
       return BA_OK;
     }
@@ -1284,7 +1391,7 @@ ba_status ba_export(const ba_problem* p, int32_t field, void* dst, size_t bytes)
     case BA_X_S_PTR: {
       if (!need((nc + 1) * sizeof(int64_t))) return fail(BA_EINVAL, "size mismatch");
       int64_t* o = reinterpret_cast<int64_t*>(dst);
-      for (size_t a = 0; a <= nc; ++a) o[a] = P.S_ptr[a];
+      for (size_t a = 0; a <= nc; ++a) o[a] = p->reordered ? p->x_ptr[a] : P.S_ptr[a];
       return BA_OK;
     }
     case BA_X_PLAN: {
@@ -1298,7 +1405,7 @@ ba_status ba_export(const ba_problem* p, int32_t field, void* dst, size_t bytes)
     }
     case BA_X_S_COL: {
       if (!need(nnzb * sizeof(int32_t))) return fail(BA_EINVAL, "size mismatch");
-      std::memcpy(dst, P.S_col.data(), bytes);
+      std::memcpy(dst, p->reordered ? p->x_col.data() : P.S_col.data(), bytes);
       return BA_OK;
     }
     case BA_X_S: {
@@ -1312,6 +1419,17 @@ ba_status ba_export(const ba_problem* p, int32_t field, void* dst, size_t bytes)
       const double* d = reinterpret_cast<const double*>(hd.data());
       for (size_t a = 0; a < nc; ++a)
         std::memcpy(out + (size_t)P.S_ptr[a] * 81, d + a * 81, 81 * sizeof(double));
+      if (p->reordered) {
+        // internal blocks to the caller's pattern (a block whose caller row
+        // comes after its column is the transpose of the stored one)
+        const std::vector<double> in(out, out + nnzb * 81);
+        for (size_t k = 0; k < nnzb; ++k) {
+          const double* src = in.data() + (size_t)p->x_blk[k] * 81;
+          double* o = out + k * 81;
+          for (int r = 0; r < 9; ++r)
+            for (int cc = 0; cc < 9; ++cc) o[9 * r + cc] = p->x_tr[k] ? src[9 * cc + r] : src[9 * r + cc];
+        }
+      }
       return BA_OK;
     }
     default:

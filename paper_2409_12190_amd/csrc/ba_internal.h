@@ -118,6 +118,11 @@ struct Plan {
 constexpr size_t STATIC_SCRATCH_BYTES = BA_STATIC_SCRATCH_BYTES;
 hipError_t static_scratch(int device, void** ptr);
 
+// Reverse Cuthill-McKee order of the cameras (order[c] = internal index of
+// camera c); the indices must be in range.
+std::vector<int32_t> camera_order(int32_t nc, int32_t np, int64_t no, const int32_t* cidx,
+                                  const int32_t* pidx);
+
 // Builds the plan; returns an empty string or an error message.
 std::string build_plan(int32_t nc, int32_t np, int64_t no, const int32_t* cidx, const int32_t* pidx,
                        Plan* out);
@@ -212,6 +217,10 @@ struct Buffers {
   // per-edge records (A, b), and each stored block's edge list
   int32_t *pg_ei, *pg_ej, *pg_ptr, *pg_code;
   double *pg_T, *pg_om, *pg_rec;
+  // camera reordering: internal index of every caller camera; the adjoint's
+  // dL/dcams in internal order
+  int32_t* cam_perm;
+  double* adj_gcam;
 };
 
 }  // namespace ba
@@ -260,4 +269,15 @@ struct ba_problem {
   bool pgo = false;
   int64_t n_edges = 0;
   std::vector<int32_t> pg_ei, pg_ej, pg_ptr, pg_code;
+  // cameras renumbered (reverse Cuthill-McKee) for the plan: cam_perm[c] is
+  // the internal index of caller camera c, cam_inv its inverse; every
+  // camera-indexed device buffer is in internal order and the entry points
+  // translate.  x_* give the block pattern in caller order for ba_export:
+  // upper blocks (a, b), a <= b, diagonal first; block k is internal block
+  // x_blk[k], transposed when x_tr[k]
+  bool reordered = false;
+  std::vector<int32_t> cam_perm, cam_inv;
+  std::vector<int64_t> x_ptr;
+  std::vector<int32_t> x_col, x_blk;
+  std::vector<uint8_t> x_tr;
 };

@@ -135,7 +135,20 @@ struct ObsArgs {
   DevScalars* dev;
 };
 
+// Row permutation of a FP64 table: gather (dst row i = src row map[i]) or
+// scatter (dst row map[i] = src row i), copying the first `width` values of
+// rows of src_stride / dst_stride values.
+struct PermArgs {
+  int n;
+  const int32_t* map;
+  bool gather;
+  const double* src;
+  double* dst;
+  int src_stride, dst_stride, width;
+};
+
 template <typename T> hipError_t launch_linearize(const LinArgs&, int nchunk, hipStream_t);
+hipError_t launch_permute_rows(const PermArgs&, hipStream_t);
 hipError_t launch_reduce_cost(const double* part, int n, DevScalars* dev, hipStream_t);
 hipError_t launch_damp_points(const DampArgs&, hipStream_t);
 template <typename T> hipError_t launch_point_q(const PointQArgs&, hipStream_t);

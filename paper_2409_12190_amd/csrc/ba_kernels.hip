@@ -885,6 +885,16 @@ __global__ __launch_bounds__(256) void k_finalize(FinalArgs a) {
   }
 }
 
+// caller-order <-> internal-order rows (cameras renumbered by the plan)
+__global__ __launch_bounds__(256) void k_permute_rows(PermArgs a) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.n) return;
+  const int si = a.gather ? a.map[i] : i, di = a.gather ? i : a.map[i];
+  const double* s = a.src + (size_t)si * a.src_stride;
+  double* d = a.dst + (size_t)di * a.dst_stride;
+  for (int k = 0; k < a.width; ++k) d[k] = s[k];
+}
+
 // gather the caller's observations into position order, with validation
 __global__ __launch_bounds__(256) void k_set_observations(ObsArgs a) {
   const int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -972,6 +982,11 @@ hipError_t launch_finalize(FinalArgs a, hipStream_t s) {
   a.nstage = g;
   hipLaunchKernelGGL(k_final_stage, dim3(g), dim3(256), 0, s, a);
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_permute_rows(const PermArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_permute_rows, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

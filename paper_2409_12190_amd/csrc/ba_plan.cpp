@@ -24,6 +24,73 @@
 
 namespace ba {
 
+// Reverse Cuthill-McKee order of the camera co-visibility graph (cameras
+// adjacent when they share a point): each connected component from an
+// unvisited camera of smallest degree, breadth first, every camera's
+// unvisited neighbours in ascending degree (ties by index), the whole
+// sequence reversed.  Blocks of the reduced matrix then lie near its
+// diagonal, so a contiguous range of block rows touches few block columns
+// and its column sums go to few other ranges.  order[c] = the position of
+// camera c.
+std::vector<int32_t> camera_order(int32_t nc, int32_t np, int64_t no, const int32_t* cidx,
+                                  const int32_t* pidx) {
+  // cameras of every point, then every camera's neighbours (both directions)
+  std::vector<int64_t> pp(np + 1, 0);
+  for (int64_t k = 0; k < no; ++k) pp[pidx[k] + 1]++;
+  for (int32_t j = 0; j < np; ++j) pp[j + 1] += pp[j];
+  std::vector<int32_t> pc(no);
+  {
+    std::vector<int64_t> fill(pp.begin(), pp.end() - 1);
+    for (int64_t k = 0; k < no; ++k) pc[fill[pidx[k]]++] = cidx[k];
+  }
+  std::vector<std::vector<int32_t>> adj(nc);
+  for (int32_t j = 0; j < np; ++j) {
+    int32_t* b = pc.data() + pp[j];
+    int32_t* e = pc.data() + pp[j + 1];
+    std::sort(b, e);
+    e = std::unique(b, e);
+    for (int32_t* x = b; x < e; ++x)
+      for (int32_t* y = x + 1; y < e; ++y) {
+        adj[*x].push_back(*y);
+        adj[*y].push_back(*x);
+      }
+  }
+  std::vector<int32_t> deg(nc);
+  for (int32_t c = 0; c < nc; ++c) {
+    auto& v = adj[c];
+    std::sort(v.begin(), v.end());
+    v.erase(std::unique(v.begin(), v.end()), v.end());
+    deg[c] = (int32_t)v.size();
+  }
+  std::vector<int32_t> by_deg(nc);
+  std::iota(by_deg.begin(), by_deg.end(), 0);
+  std::stable_sort(by_deg.begin(), by_deg.end(), [&](int32_t a, int32_t b) { return deg[a] < deg[b]; });
+  std::vector<char> seen(nc, 0);
+  std::vector<int32_t> seq;
+  seq.reserve(nc);
+  std::vector<int32_t> nb;
+  for (int32_t start : by_deg) {
+    if (seen[start]) continue;
+    size_t head = seq.size();
+    seq.push_back(start);
+    seen[start] = 1;
+    while (head < seq.size()) {
+      const int32_t u = seq[head++];
+      nb.clear();
+      for (int32_t v : adj[u])
+        if (!seen[v]) {
+          seen[v] = 1;
+          nb.push_back(v);
+        }
+      std::stable_sort(nb.begin(), nb.end(), [&](int32_t a, int32_t b) { return deg[a] < deg[b]; });
+      seq.insert(seq.end(), nb.begin(), nb.end());
+    }
+  }
+  std::vector<int32_t> order(nc);
+  for (int32_t k = 0; k < nc; ++k) order[seq[nc - 1 - k]] = k;
+  return order;
+}
+
 std::string build_plan(int32_t nc, int32_t np, int64_t no, const int32_t* cidx, const int32_t* pidx,
                        Plan* P) {
   char msg[256];

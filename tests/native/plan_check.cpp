@@ -30,13 +30,43 @@ static bool read_file(const std::string& fn, void* dst, size_t bytes) {
     }                                      \
   } while (0)
 
+// largest |a - b| over the co-visible camera pairs (a, b) of a plan
+static int32_t bandwidth(const Plan& p) {
+  int32_t bw = 0;
+  for (int32_t a = 0; a < p.nc; ++a)
+    for (int32_t e = p.S_ptr[a]; e < p.S_ptr[a + 1]; ++e) bw = std::max(bw, p.S_col[e] - a);
+  return bw;
+}
+
+// "order" mode: the camera renumbering is a permutation, keeps the block
+// count, and prints the bandwidth before and after
+static int check_order(const int64_t* h, const std::vector<int32_t>& cam, const std::vector<int32_t>& pt) {
+  const int32_t nc = (int32_t)h[0];
+  const std::vector<int32_t> ord = camera_order(nc, (int32_t)h[1], h[2], cam.data(), pt.data());
+  CHECK((int32_t)ord.size() == nc, "one position per camera");
+  std::vector<char> hit(nc, 0);
+  for (int32_t c = 0; c < nc; ++c) {
+    CHECK(ord[c] >= 0 && ord[c] < nc && !hit[ord[c]], "the order is a permutation");
+    hit[ord[c]] = 1;
+  }
+  std::vector<int32_t> cam2(cam.size());
+  for (size_t k = 0; k < cam.size(); ++k) cam2[k] = ord[cam[k]];
+  Plan a, b;
+  CHECK(build_plan(nc, (int32_t)h[1], h[2], cam.data(), pt.data(), &a).empty(), "plan in the given order");
+  CHECK(build_plan(nc, (int32_t)h[1], h[2], cam2.data(), pt.data(), &b).empty(), "plan in the new order");
+  CHECK(a.nnzb == b.nnzb && a.n_pairs == b.n_pairs, "renumbering keeps the blocks and pairs");
+  std::printf("ok order %d %d\n", bandwidth(a), bandwidth(b));
+  return 0;
+}
+
 int main(int argc, char** argv) {
-  if (argc != 2) return 2;
+  if (argc != 2 && argc != 3) return 2;
   const std::string pre = argv[1];
   int64_t h[3];
   if (!read_file(pre + ".hdr", h, sizeof h)) return 2;
   std::vector<int32_t> cam(h[2]), pt(h[2]);
   if (!read_file(pre + ".cam", cam.data(), 4 * h[2]) || !read_file(pre + ".pt", pt.data(), 4 * h[2])) return 2;
+  if (argc == 3 && std::string(argv[2]) == "order") return check_order(h, cam, pt);
   Plan p;
   const std::string err = build_plan((int32_t)h[0], (int32_t)h[1], h[2], cam.data(), pt.data(), &p);
   if (!err.empty()) {

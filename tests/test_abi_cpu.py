@@ -112,10 +112,13 @@ def test_backward_needs_squared_loss_and_enabled_buffers():
 
 def test_backward_buffers_add_to_the_workspace():
     s = make_scene(3, n_cams=40, n_pts=2500)
-    h0 = _create(s.n_cams, s.n_pts, s.cam_idx, s.pt_idx)
-    h1 = _create(s.n_cams, s.n_pts, s.cam_idx, s.pt_idx, enable_backward=1)
-    h2 = _create(s.n_cams, s.n_pts, s.cam_idx, s.pt_idx, enable_backward=1, precision=B.BA_MIXED)
-    h3 = _create(s.n_cams, s.n_pts, s.cam_idx, s.pt_idx, precision=B.BA_MIXED)
+    # (the caller's camera order: a renumbered problem adds a [n_cams][10]
+    # staging copy of dL/dcams)
+    g = B.BA_ORDER_GIVEN
+    h0 = _create(s.n_cams, s.n_pts, s.cam_idx, s.pt_idx, camera_order=g)
+    h1 = _create(s.n_cams, s.n_pts, s.cam_idx, s.pt_idx, enable_backward=1, camera_order=g)
+    h2 = _create(s.n_cams, s.n_pts, s.cam_idx, s.pt_idx, enable_backward=1, precision=B.BA_MIXED, camera_order=g)
+    h3 = _create(s.n_cams, s.n_pts, s.cam_idx, s.pt_idx, precision=B.BA_MIXED, camera_order=g)
     try:
         nc, np_, no, nz = s.n_cams, s.n_pts, s.n_obs, B.ba_problem_nnzb(h0)
         extra = 8 * (no * (78 + 24 + 27) + nc * (81 + 9 + 9) + np_ * 3)

@@ -545,13 +545,19 @@ def test_full_size_laps_scene_tracks_oracle(laps10000, precision):
     loop closures, at full size in the benchmark's launch configuration
     (pipelined PCG, rtol 1e-4; both precisions stream each upper block once
     per product from a copy in their storage precision).  Two LM steps
-    against the oracle: costs within the stated bound (mixed 1e-4, FP64
-    1e-5 relative), and the PCG step meets its tolerance on the exported
-    system (the residual property checked here in numpy)."""
+    against the oracle: costs within the stated bound, and the PCG step
+    meets its tolerance on the exported system (the residual property
+    checked here in numpy).  Bounds: FP64 1e-5 relative (the FP64 solve takes
+    the oracle's 139 CG iterations in either camera numbering, costs equal
+    to ~1e-11).  Mixed 1e-3: the FP32-rounded blocks change in their last
+    bit when only the summation order changes, and on this ill-conditioned
+    system the capped-tolerance step then moves the second step's cost by
+    up to 4.9e-4 (measured: 3.2e-5 in the caller's camera order, 4.9e-4 in
+    the library's renumbered order; the oracle itself moves 2.6e-11)."""
     s = laps10000
     g, o = gpu(s, precision=precision), orc(s)
     assert g.plan["pcg_layout"] == "streamed", g.plan
-    tol = 1e-4 if precision == B.BA_MIXED else 1e-5
+    tol = 1e-3 if precision == B.BA_MIXED else 1e-5
     for it in range(2):
         io, ig = o.lm_step(), g.lm_step()
         print(f"  step {it}: cost {ig['cost_after']:.9e} / {io['cost_after']:.9e} "
@@ -621,3 +627,42 @@ def test_cholesky_solve_mixed_precision_and_timing():
         p.close()
     print(f"  linear solve per LM step, 128 cameras: Cholesky {times[B.BA_SOLVER_CHOLESKY]:.3f} ms, "
           f"PCG {times[B.BA_SOLVER_PCG]:.3f} ms", flush=True)
+
+
+def test_camera_renumbering_is_invisible_to_the_caller():
+    """The library's internal camera order (reverse Cuthill-McKee) against
+    the caller's order on a shuffled trajectory: the same iterations (costs
+    1e-10, accept and lambda exact), the same exports in the caller's order
+    (pattern exactly, values element by element), parameters and state blobs
+    interchangeable, fixed cameras held."""
+    s = scene_of("cfg1_small")
+    sh = np.random.default_rng(1).permutation(s.n_cams)
+    cam_idx, cams0 = sh[s.cam_idx], np.empty_like(s.cams0)
+    cams0[sh] = s.cams0
+    fixed = sh[np.asarray(s.fixed_cams)] if s.fixed_cams is not None and len(s.fixed_cams) else [int(sh[0])]
+    kw = dict(precision=B.BA_FP64, huber_delta=s.huber_delta, fixed_cams=fixed, cams=cams0, pts=s.pts0,
+              cg_rtol=1e-12, cg_maxiter=1000, cg_variant=B.BA_CG_STANDARD)
+    a = B.Problem(s.n_cams, s.n_pts, cam_idx, s.pt_idx, s.obs, s.obs_w, camera_order=B.BA_ORDER_GIVEN, **kw)
+    b = B.Problem(s.n_cams, s.n_pts, cam_idx, s.pt_idx, s.obs, s.obs_w, camera_order=B.BA_ORDER_BANDWIDTH, **kw)
+    for it in range(3):
+        ia, ib = a.lm_step(), b.lm_step()
+        for k in ("cost_before", "cost_after"):
+            assert ib[k] == pytest.approx(ia[k], rel=1e-10), (it, k)
+        assert ib["accepted"] == ia["accepted"] and ib["lambda_next"] == ia["lambda_next"]
+        if it == 0:
+            np.testing.assert_array_equal(b.export(B.BA_X_S_PTR), a.export(B.BA_X_S_PTR))
+            np.testing.assert_array_equal(b.export(B.BA_X_S_COL), a.export(B.BA_X_S_COL))
+            for f, tol in ((B.BA_X_S, 1e-12), (B.BA_X_BS, 1e-12), (B.BA_X_GRAD_C, 1e-12),
+                           (B.BA_X_DC, 1e-9), (B.BA_X_PRECOND, 1e-11)):
+                close(b.export(f), a.export(f), tol, f"field {f}")
+    ca, pa = a.get_params()
+    cb, pb = b.get_params()
+    close(cb.cpu().numpy(), ca.cpu().numpy(), 1e-9, "cameras")
+    close(pb.cpu().numpy(), pa.cpu().numpy(), 1e-9, "points")
+    np.testing.assert_array_equal(cb.cpu().numpy()[fixed], cams0[fixed])
+    # a state blob of one numbering restores the other bit for bit
+    blob = b.get_state()
+    a.set_state(blob)
+    np.testing.assert_array_equal(a.get_params()[0].cpu().numpy(), cb.cpu().numpy())
+    a.close()
+    b.close()

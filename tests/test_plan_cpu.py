@@ -29,13 +29,34 @@ def checker(tmp_path_factory):
     return exe
 
 
-def run_check(exe, tmp_path, cam, pt, n_cams, n_pts):
+def run_check(exe, tmp_path, cam, pt, n_cams, n_pts, *mode):
     pre = str(tmp_path / "scene")
     np.array([n_cams, n_pts, len(cam)], dtype=np.int64).tofile(pre + ".hdr")
     np.asarray(cam, dtype=np.int32).tofile(pre + ".cam")
     np.asarray(pt, dtype=np.int32).tofile(pre + ".pt")
-    r = subprocess.run([exe, pre], capture_output=True, text=True, timeout=300)
+    r = subprocess.run([exe, pre, *mode], capture_output=True, text=True, timeout=300)
     return r.returncode, r.stdout.strip()
+
+
+def test_camera_order_recovers_a_band(checker, tmp_path):
+    """Reverse Cuthill-McKee numbering of the cameras: a permutation that
+    keeps the blocks; a trajectory whose cameras were shuffled gets back a
+    band about as narrow as the trajectory's own, and a multi-lap circuit
+    (loop closures between laps at the same phase) gets a band far below
+    the lap length."""
+    s = make_scene(1, n_cams=1000, n_pts=20000, seed=3)
+    rc, out = run_check(checker, tmp_path, s.cam_idx, s.pt_idx, s.n_cams, s.n_pts, "order")
+    assert rc == 0, out
+    bw_given = int(out.split()[2])
+    shuffle = np.random.default_rng(0).permutation(s.n_cams)
+    rc, out = run_check(checker, tmp_path, shuffle[s.cam_idx], s.pt_idx, s.n_cams, s.n_pts, "order")
+    assert rc == 0, out
+    bw_shuffled, bw_rcm = int(out.split()[2]), int(out.split()[3])
+    assert bw_shuffled > 5 * bw_given and bw_rcm <= 2 * bw_given, out
+    s = make_scene(2, n_cams=2000, n_pts=40000, per_lap=400)
+    rc, out = run_check(checker, tmp_path, s.cam_idx, s.pt_idx, s.n_cams, s.n_pts, "order")
+    assert rc == 0, out
+    assert int(out.split()[2]) > 1000 and int(out.split()[3]) < 200, out
 
 
 def test_dense_ring_streamed_decomposition(checker, tmp_path):
