@@ -87,7 +87,8 @@ def iteration_bytes(scene, nnzb, es, cg_iters):
 
 
 KERNEL_SOURCES = {
-    "pcg": ("ba_pcg.hip", "ba_reduce.h", "ba_kernels.h", "ba_internal.h"),
+    # (the plan decides which blocks and columns each PCG workgroup moves)
+    "pcg": ("ba_pcg.hip", "ba_reduce.h", "ba_kernels.h", "ba_internal.h", "ba_plan.cpp"),
 }
 DEFAULT_SOURCES = ("ba_kernels.hip", "ba_reduce.h", "ba_kernels.h", "ba_internal.h", "ba_device.h")
 
