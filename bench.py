@@ -207,10 +207,12 @@ def host_cores() -> int:
     return max(1, n)
 
 
-def cpu_baseline(scene, iters, single_iters, it_bytes_fn):
+def cpu_baseline(scene, iters, single_iters, it_bytes_fn, repeats=1):
     """The FP64 oracle on the host's cores: `iters` LM iterations of the
     whole scene at all cores (also the FP64 reference cost after them), then
-    `single_iters` at one thread (bounded sample)."""
+    `single_iters` at one thread (bounded sample); each timed `repeats`
+    times from the initial state, the median kept (the oracle's results do
+    not depend on the thread count or the repeat)."""
     from oracle import oracle as O
     nproc = host_cores()
     out = {}
@@ -218,18 +220,21 @@ def cpu_baseline(scene, iters, single_iters, it_bytes_fn):
         if n <= 0:
             continue
         O.set_threads(threads)
-        o = O.Oracle.from_scene(scene, options=O.OracleOptions(huber_delta=scene.huber_delta))
-        t0 = time.perf_counter()
-        infos = []
-        for _ in range(n):
-            infos.append(o.lm_step())
-        el = time.perf_counter() - t0
+        times = []
+        for _ in range(max(1, repeats)):
+            o = O.Oracle.from_scene(scene, options=O.OracleOptions(huber_delta=scene.huber_delta))
+            t0 = time.perf_counter()
+            infos = []
+            for _ in range(n):
+                infos.append(o.lm_step())
+            times.append(time.perf_counter() - t0)
+            del o
+        el = sorted(times)[len(times) // 2]
         cg = sum(i["cg_iters"] for i in infos) / n
-        out[threads] = dict(s=el, iters=n, cost=cost_after(infos[-1]), cg=cg,
-                            gbs=it_bytes_fn(cg) * n / el / 1e9)
-        log(f"[bench] oracle at {threads} threads: {n} LM iterations in {el:.1f} s "
+        out[threads] = dict(s=el, runs=[round(t, 2) for t in times], iters=n, cost=cost_after(infos[-1]),
+                            cg=cg, gbs=it_bytes_fn(cg) * n / el / 1e9)
+        log(f"[bench] oracle at {threads} threads: {n} LM iterations, median {el:.2f} s of {[round(t, 2) for t in times]} "
             f"(cost {out[threads]['cost']:.9e})")
-        del o
     O.set_threads(nproc)
     return out
 
@@ -264,6 +269,8 @@ def main():
                          "reference iterations; 0 disables the CPU legs)")
     ap.add_argument("--cpu-single-iters", type=int, default=1,
                     help="LM iterations of the oracle at one thread (bounded sample)")
+    ap.add_argument("--cpu-repeats", type=int, default=3,
+                    help="timed runs of each CPU leg (the median is reported)")
     ap.add_argument("--skip-fp64", action="store_true")
     ap.add_argument("--skip-learned", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
@@ -415,20 +422,22 @@ def main():
     if cpu_iters > 0:
         log("[bench] CPU baseline (oracle)")
         res = cpu_baseline(scene, cpu_iters, args.cpu_single_iters,
-                           lambda cg: iteration_bytes(scene, nnzb, 8, cg))
+                           lambda cg: iteration_bytes(scene, nnzb, 8, cg), args.cpu_repeats)
         nproc = host_cores()
         full = res[nproc]
         out["cpu_baseline"] = {
             "value": scene.n_obs * full["iters"] / full["s"], "unit": "obs*LM-iters/s", "cores": nproc,
             "kind": "oracle",
             "sample": f"{full['iters']} LM iterations of the whole scene from its initial state, FP64 "
-                      f"C oracle (OpenMP, results independent of the thread count), {full['s']:.1f} s",
+                      f"C oracle (OpenMP, results independent of the thread count), median {full['s']:.1f} s "
+                      f"of runs {full['runs']}",
             "cpu_model": cpu_model(), "effective_GB/s": round(full["gbs"], 2)}
         if 1 in res and nproc != 1:
             one = res[1]
             out["cpu_baseline"]["single_thread"] = {
                 "value": scene.n_obs * one["iters"] / one["s"], "cores": 1,
-                "sample": f"{one['iters']} LM iteration(s) from the initial state, {one['s']:.1f} s",
+                "sample": f"{one['iters']} LM iteration(s) from the initial state, median {one['s']:.1f} s "
+                          f"of runs {one['runs']}",
                 "effective_GB/s": round(one["gbs"], 2)}
         if full["iters"] >= ref_iters:
             F_o = full["cost"]
