@@ -55,6 +55,28 @@ __device__ __forceinline__ double uniform(double v) {
   return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
+// 64-bit DPP move; rows outside ROWS, and lanes the control gives no
+// source, read 0.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_mov(double v) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, ROWS, 0xF, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, ROWS, 0xF, true);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+// Sum over a full wavefront in a fixed order through DPP lane moves (no
+// LDS traffic): quads, rows of 16, then rows 1 and 3 take rows 0 and 2,
+// rows 2 and 3 take lane 31.  The total is valid in lane 63.
+__device__ __forceinline__ double dpp_wave_total(double v) {
+  v += dpp_mov<0xB1, 0xF>(v);   // quad_perm [1,0,3,2]
+  v += dpp_mov<0x4E, 0xF>(v);   // quad_perm [2,3,0,1]
+  v += dpp_mov<0x124, 0xF>(v);  // row_ror:4
+  v += dpp_mov<0x128, 0xF>(v);  // row_ror:8
+  v += dpp_mov<0x142, 0xA>(v);  // row_bcast:15
+  v += dpp_mov<0x143, 0xC>(v);  // row_bcast:31
+  return v;
+}
+
 constexpr long BARRIER_SPIN_LIMIT = 1L << 21;
 
 __device__ __forceinline__ void publish(double* p, double v) {
@@ -157,6 +179,72 @@ __device__ __forceinline__ bool poll_record(const double* rec, double& v0, doubl
   }
 }
 
+// The register-resident pipelined PCG also marks its own z columns of every
+// ring slot after the first pending, so that a reader polls the column words
+// it needs together with the dot records, in one round trip: no wait for the
+// columns' stores before the partials are published, no separate fetch after
+// the poll.  A thread polls PCG_POLL_WORDS column words at a time (one round
+// for up to PCG_POLL_WORDS * 1024 / 9 columns, more rounds beyond).
+constexpr int PCG_POLL_WORDS = 2;
+
+// Polls the block columns cols[0 .. n) of ring slot zk into LDS zl and, when
+// rec is not null, the three words of record rec into v0..v2 (with the first
+// round of columns); the loads of all still-pending words of a round are
+// issued together.  Returns false on timeout (error flag raised).
+__device__ __forceinline__ bool poll_slot(const int32_t* cols, int n, const double* zk, double* zl,
+                                          const double* rec, double& v0, double& v1, double& v2,
+                                          int* error) {
+  const unsigned long long* z = reinterpret_cast<const unsigned long long*>(zk);
+  const unsigned long long* r = reinterpret_cast<const unsigned long long*>(rec);
+  const int nw = n * 9, tid = threadIdx.x, nt = blockDim.x;
+  unsigned want = rec ? 7u << 8 : 0u;  // bit k < PCG_POLL_WORDS: word base + tid + k nt; bits 8..10: rec
+  long spins = 0;
+  for (int base = 0; base == 0 || base < nw; base += PCG_POLL_WORDS * nt) {
+#pragma unroll
+    for (int k = 0; k < PCG_POLL_WORDS; ++k)
+      if (base + tid + k * nt < nw) want |= 1u << k;
+    while (want) {
+      unsigned long long w[PCG_POLL_WORDS], rv[3];
+#pragma unroll
+      for (int k = 0; k < PCG_POLL_WORDS; ++k) {
+        w[k] = PCG_PENDING;
+        if ((want >> k) & 1u) {
+          const int u = base + tid + k * nt, j = u / 9;
+          // byte offset below 2^32 (fewer than 2^25 cameras): base + 32-bit offset addressing
+          const unsigned boff = ((unsigned)cols[j] * ZSTRIDE + (unsigned)(u - 9 * j)) * 8u;
+          w[k] = __hip_atomic_load(reinterpret_cast<const unsigned long long*>(
+                                       reinterpret_cast<const char*>(z) + boff),
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < 3; ++q)
+        rv[q] = (want >> 8) & 1u ? __hip_atomic_load(r + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                                 : PCG_PENDING;
+#pragma unroll
+      for (int k = 0; k < PCG_POLL_WORDS; ++k)
+        if (((want >> k) & 1u) && w[k] != PCG_PENDING) {
+          zl[base + tid + k * nt] = __longlong_as_double((long long)w[k]);
+          want &= ~(1u << k);
+        }
+      if (((want >> 8) & 1u) && rv[0] != PCG_PENDING && rv[1] != PCG_PENDING && rv[2] != PCG_PENDING) {
+        v0 = __longlong_as_double((long long)rv[0]);
+        v1 = __longlong_as_double((long long)rv[1]);
+        v2 = __longlong_as_double((long long)rv[2]);
+        want = 0u | (want & ((1u << PCG_POLL_WORDS) - 1u));
+      }
+      if (!want) break;
+      if (++spins > BARRIER_SPIN_LIMIT ||
+          (__hip_atomic_load(error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & ERR_BARRIER)) {
+        atomicOr(error, (int)ERR_BARRIER);
+        return false;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+  }
+  return true;
+}
+
 // Block values of a lane group's items (row `comp` of each block, or column
 // `comp` of a transposed upper block), with the item's LDS column slot and
 // local row.
@@ -234,8 +322,9 @@ __device__ __forceinline__ void pcg_spmv_segments(const PcgArgs& a, int ib, int 
 }
 
 // Output o of the product from the group partials (after
-// pcg_spmv_segments): valid in lane sub == 0 of each group of 8 lanes, for
-// o = (base + threadIdx.x) / 8 < nr * 9.
+// pcg_spmv_segments): valid in every lane of each group of 8 lanes (sums
+// over the group through DPP lane moves), for o = (base + threadIdx.x) / 8
+// < nr * 9.
 __device__ __forceinline__ double pcg_spmv_output(int o, int sub, int nr, int L, const int* rptr,
                                                   const double* seg) {
   double s = 0.0;
@@ -244,9 +333,9 @@ __device__ __forceinline__ double pcg_spmv_output(int o, int sub, int nr, int L,
     const int g0 = rptr[row] / L, g1 = (rptr[row + 1] - 1) / L;
     for (int gg = g0 + sub; gg <= g1; gg += 8) s += seg[(row + gg) * 9 + cp];
   }
-  s += __shfl_xor(s, 1, 64);
-  s += __shfl_xor(s, 2, 64);
-  s += __shfl_xor(s, 4, 64);
+  s += dpp_mov<0xB1, 0xF>(s);   // quad_perm [1,0,3,2]
+  s += dpp_mov<0x4E, 0xF>(s);   // quad_perm [2,3,0,1]
+  s += dpp_mov<0x141, 0xF>(s);  // row_half_mirror: the other quad of the 8
   return s;
 }
 
@@ -504,19 +593,170 @@ __global__ __launch_bounds__(PCG_THREADS) void k_pcg_pipelined(PcgArgs a) {
   }
   s_bb = block_sum(s_bb, red);
   if (tid == 0) publish(a.partB + (size_t)B * PART_STRIDE, s_bb);
-  // this workgroup's dot-product records of every iteration slot: pending
+  // this workgroup's dot-product records of every iteration slot, and (with
+  // register-resident blocks) its z columns of ring slots 1 .. maxiter + 1:
+  // pending
   for (int q = tid; q < 3 * (a.maxiter + 1); q += nt)
     clear_record(a.partA + (size_t)(q / 3) * pstride + (size_t)B * PART_STRIDE + (q - 3 * (q / 3)));
+  if (RES) {
+    for (int q = tid; q < (a.maxiter + 1) * n9; q += nt) {
+      const int sl = q / n9, k = q - sl * n9, row = k / 9;
+      clear_record(a.zring + (size_t)(sl + 1) * zstride + (size_t)(r0 + row) * ZSTRIDE + (k - 9 * row));
+    }
+  }
   bool ok = grid_barrier(a.gs, a.error);
   fetch_cols(ucl, a.zring, nuc, zl);
   double t0 = 0.0;
   for (int i = tid; i < G; i += nt) t0 += a.partB[(size_t)i * PART_STRIDE];
   const double bnorm = sqrt(block_sum(t0, red));
-  pcg_spmv<T, RES>(a, ib, i0, i1, nr, L, rptr, it, zl, seg, ws);
   __shared__ int poll_failed;
   __shared__ double red3s[3 * (PCG_THREADS / 64)];
+  if (tid == 0) poll_failed = 0;
+  pcg_spmv<T, RES>(a, ib, i0, i1, nr, L, rptr, it, zl, seg, ws);
   double rnorm = bnorm, gamma_old = 1.0, alpha_old = 1.0;
   int iters = 0, breakdown = 0;
+  if constexpr (RES) {
+    // Thread tid < n9 owns element tid of the workgroup's rows (at most
+    // PCG_RMAX * 9 < PCG_THREADS).  Wavefront 0 alone forms the step's
+    // scalars, while the others start the product, and hands them over
+    // through LDS with the product's barrier; the convergence test is read
+    // there too (the last iteration's product is formed and dropped).
+    const bool own = tid < n9;
+    const int orow = own ? tid / 9 : 0, ocp = tid - 9 * (tid / 9);
+    const unsigned zoff = (unsigned)(r0 + orow) * ZSTRIDE + (unsigned)ocp;
+    const int nwa = (n9 + 63) >> 6;  // wavefronts holding elements
+    const int nwr = (G + 63) >> 6;   // wavefronts polling dot records
+    __shared__ double scal[5];       // alpha, beta, residual norm; previous gamma, alpha
+    __shared__ int sstate;           // 0: continue, 1: converged or at maxiter, 2: breakdown
+    for (int i = 0; ok && bnorm > 0.0 && i <= a.maxiter; ++i) {
+      // local: partial dots of r, u, w; m = M w published in slot i + 1
+      double* zk = a.zring + (size_t)(i + 1) * zstride;
+      double s_g = 0.0, s_d = 0.0, s_r = 0.0;
+      if (own) {
+        double m = 0.0;
+#pragma unroll
+        for (int q = 0; q < 9; ++q) m += Ml[orow * 81 + ocp * 9 + q] * ws[orow * 9 + q];
+        ms_[tid] = m;
+        publish(zk + zoff, m);
+        const double r = rs[tid], u = us[tid], w = ws[tid];
+        s_g = r * u;
+        s_d = w * u;
+        s_r = r * r;
+      }
+      double* pa = a.partA + (size_t)i * pstride;
+      if (nwa == 1) {
+        // one wavefront holds every element: it publishes its sums itself
+        if (tid < 64) {
+          s_g = dpp_wave_total(s_g);
+          s_d = dpp_wave_total(s_d);
+          s_r = dpp_wave_total(s_r);
+          if (tid == 63) {
+            publish(pa + (size_t)B * PART_STRIDE, s_g);
+            publish(pa + (size_t)B * PART_STRIDE + 1, s_d);
+            publish(pa + (size_t)B * PART_STRIDE + 2, s_r);
+          }
+        }
+      } else {
+        __shared__ double red3[PCG_THREADS / 64][3];
+        if ((tid >> 6) < nwa) {
+          s_g = dpp_wave_total(s_g);
+          s_d = dpp_wave_total(s_d);
+          s_r = dpp_wave_total(s_r);
+          if ((tid & 63) == 63) {
+            red3[tid >> 6][0] = s_g;
+            red3[tid >> 6][1] = s_d;
+            red3[tid >> 6][2] = s_r;
+          }
+        }
+        __syncthreads();
+        if (tid < 3) {
+          double v = 0.0;
+          for (int w2 = 0; w2 < nwa; ++w2) v += red3[w2][tid];
+          publish(pa + (size_t)B * PART_STRIDE + tid, v);
+        }
+      }
+      // the z columns this workgroup reads and (thread t < G) workgroup t's
+      // partials, in one poll; each polling wavefront sums its partials
+      double tg = 0.0, td = 0.0, tr = 0.0;
+      if (!poll_slot(ucl, nuc, zk, zl, tid < G ? pa + (size_t)tid * PART_STRIDE : nullptr, tg, td, tr,
+                     a.error))
+        poll_failed = 1;
+      if ((tid >> 6) < nwr) {
+        tg = dpp_wave_total(tg);
+        td = dpp_wave_total(td);
+        tr = dpp_wave_total(tr);
+        if ((tid & 63) == 63) {
+          red3s[3 * (tid >> 6)] = tg;
+          red3s[3 * (tid >> 6) + 1] = td;
+          red3s[3 * (tid >> 6) + 2] = tr;
+        }
+      }
+      __syncthreads();
+      if (poll_failed) {
+        ok = false;
+        break;
+      }
+      if (tid < 64) {
+        // the wavefront sums in a fixed order: identical in every workgroup
+        double gamma = 0.0, delta = 0.0, rr = 0.0;
+        for (int w2 = 0; w2 < nwr; ++w2) {
+          gamma += red3s[3 * w2];
+          delta += red3s[3 * w2 + 1];
+          rr += red3s[3 * w2 + 2];
+        }
+        gamma = uniform(gamma);
+        delta = uniform(delta);
+        rr = uniform(rr);
+        const double rn = sqrt(rr);
+        int st = 0;
+        double alpha = 0.0, beta = 0.0;
+        if (rn <= a.rtol * bnorm || i == a.maxiter) {
+          st = 1;
+        } else {
+          beta = i > 0 ? gamma / scal[3] : 0.0;
+          const double den = i > 0 ? delta - beta * gamma / scal[4] : delta;
+          if (!(den > 0.0)) st = 2;
+          else alpha = gamma / den;
+        }
+        if (tid == 0) {
+          scal[0] = alpha;
+          scal[1] = beta;
+          scal[2] = rn;
+          scal[3] = gamma;
+          scal[4] = alpha;
+          sstate = st;
+        }
+      }
+      pcg_spmv_segments<T, RES>(a, ib, i0, i1, rptr, it, zl, seg);
+      iters = i;
+      if (sstate) {
+        rnorm = scal[2];
+        breakdown = sstate == 2;
+        break;
+      }
+      const double alpha = scal[0], beta = scal[1];
+      // n = S m, output by output, straight into the vector updates
+      for (int base = 0; base < n9 * 8; base += nt) {
+        const int t = base + tid, k = t >> 3, sub = t & 7;
+        const double nk = pcg_spmv_output(k, sub, nr, L, rptr, seg);
+        if (k < n9 && sub == 0) {
+          const double z = nk + beta * zs[k];
+          const double q = ms_[k] + beta * qs[k];
+          const double sv = ws[k] + beta * ss[k];
+          const double pv = us[k] + beta * ps[k];
+          zs[k] = z;
+          qs[k] = q;
+          ss[k] = sv;
+          ps[k] = pv;
+          xs[k] += alpha * pv;
+          rs[k] -= alpha * sv;
+          us[k] -= alpha * q;
+          ws[k] -= alpha * z;
+        }
+      }
+      __syncthreads();
+    }
+  } else {
   for (int i = 0; ok && bnorm > 0.0 && i <= a.maxiter; ++i) {
     // local: partial dots of r, u, w; m = M w published in slot i + 1
     double* zk = a.zring + (size_t)(i + 1) * zstride;
@@ -616,6 +856,7 @@ __global__ __launch_bounds__(PCG_THREADS) void k_pcg_pipelined(PcgArgs a) {
     __syncthreads();
     gamma_old = gamma;
     alpha_old = alpha;
+  }
   }
   for (int i = tid; i < n9; i += nt) a.x[9 * (size_t)r0 + i] = xs[i];
   if (B == 0 && tid == 0) {
