@@ -125,13 +125,14 @@ def bf16(a):
 
 
 def forward(theta, g, bf16_inference=False):
-    """Node outputs o and the activations.  bf16_inference: the input and
-    message layers take their operands (inputs, weights) rounded to bfloat16,
-    as the matrix-core inference does; sums and biases stay exact here."""
+    """Node outputs o and the activations.  bf16_inference: the message
+    layers take their operands (inputs, weights) rounded to bfloat16, as the
+    matrix-core inference does (its input layer stays unrounded); sums and
+    biases stay exact here."""
     p = unpack(theta)
     X, P = g["X"], g["P"]
     q = bf16 if bf16_inference else (lambda v: v)
-    z0 = q(X) @ q(p["W_in"]).T + p["b_in"]
+    z0 = X @ p["W_in"].T + p["b_in"]
     h = np.maximum(z0, 0.0)
     cache = {"z": [z0], "h": [h], "m": []}
     for l in range(LAYERS):

@@ -397,9 +397,9 @@ ba_status lm_step_impl(ba_problem* p, ba_step_info* out) {
   const bool learned = p->opt.precond == BA_PRECOND_LEARNED && p->gnn_ready;
   int32_t precond_used = 0;
   if (learned) {
-    PcFeatureArgs fa{P.nc, b.nbr_ptr, b.nbr, b.nbr_blk, b.blk_row, b.S_col, b.S, b.pcLinv,
-                     b.gX, b.gE, b.gw};
     const GraphDev gd = problem_graph(p);
+    PcFeatureArgs fa{P.nc, b.nbr_ptr, b.nbr, b.nbr_blk, b.S, b.pcLinv, b.gX, b.gE, b.gw, b.pc_params,
+                     gd.H[0]};
     auto infer = [&]() -> hipError_t {
       hipError_t e = launch_pc_features<T>(fa, s);
       if (e == hipSuccess) e = launch_gnn_forward_bf16(gd, b.pc_params, b.pc_wbf16, s);
@@ -1516,8 +1516,8 @@ ba_status ba_graph_build(ba_graph* g, ba_problem* p) {
     return fail(BA_EINVAL, "the graph was created for another camera pattern");
   if (!p->have_system) return fail(BA_ESTATE, "run ba_lm_step first (no reduced system yet)");
   const ba::Buffers& b = p->b;
-  ba::PcFeatureArgs fa{g->nc, b.nbr_ptr, b.nbr, b.nbr_blk, b.blk_row, b.S_col, b.S, b.pcLinv,
-                       g->dev.X, g->dev.E, g->dev.w};
+  ba::PcFeatureArgs fa{g->nc, b.nbr_ptr, b.nbr, b.nbr_blk, b.S, b.pcLinv, g->dev.X, g->dev.E, g->dev.w,
+                       nullptr, nullptr};
   HIPCHK(p->opt.precision == BA_MIXED ? ba::launch_pc_features<float>(fa, p->stream)
                                       : ba::launch_pc_features<double>(fa, p->stream));
   HIPCHK(hipStreamSynchronize(p->stream));

@@ -25,10 +25,9 @@ constexpr int64_t GNN_LAYER_SIZE = 2 * GNN_H * GNN_H + GNN_H;
 constexpr int64_t GNN_OFF_WOUT = GNN_OFF_L0 + GNN_L * GNN_LAYER_SIZE;
 constexpr int64_t GNN_OFF_BOUT = GNN_OFF_WOUT + GNN_O * GNN_H;
 constexpr int64_t GNN_NPARAM = GNN_OFF_BOUT + GNN_O;
-// BF16 copies of the input and message-layer weights, rows padded to K
-constexpr int GNN_KIN = 48;             // 47 inputs -> 3 k-steps of 16
-constexpr int GNN_KHID = 2 * GNN_H;     // [W_s | W_m]
-constexpr int64_t GNN_NBF16 = GNN_H * GNN_KIN + GNN_L * GNN_H * GNN_KHID;
+// BF16 copies of the message-layer weights, per layer [W_s | W_m] (64 x 128)
+constexpr int GNN_KHID = 2 * GNN_H;
+constexpr int64_t GNN_NBF16 = GNN_L * GNN_H * GNN_KHID;
 
 // Device view of one camera graph and its activations.
 struct GraphDev {
@@ -42,15 +41,20 @@ struct GraphDev {
 
 struct PcFeatureArgs {
   int nc;
-  const int32_t *nbr_ptr, *nbr, *nbr_blk, *blk_row, *S_col;
+  const int32_t *nbr_ptr, *nbr, *nbr_blk;
   const void* S;               // off-diagonal blocks, precision T
   const double* Linv;          // [nc][81] inverse Cholesky factors (lower)
   float *X, *E, *w;
+  // inference: the input layer h0 = relu(W_in x + b_in) of each camera is
+  // formed here too (FP32, as in training) into H0 [nc][GNN_H]; null: not
+  const float* params;
+  float* H0;
 };
 
 template <typename T> hipError_t launch_pc_features(const PcFeatureArgs&, hipStream_t);
 hipError_t launch_gnn_forward(const GraphDev&, const float* params, hipStream_t);
-// inference: BF16 matrix-core layers (weights converted once per parameter set)
+// inference: BF16 matrix-core message layers from H[0] (formed by the feature
+// kernel; weights converted once per parameter set)
 hipError_t launch_gnn_weights_bf16(const float* params, short* Wb, hipStream_t);
 hipError_t launch_gnn_forward_bf16(const GraphDev&, const float* params, const short* Wb, hipStream_t);
 // loss, d loss / d outputs (training) or the preconditioner blocks

@@ -37,9 +37,19 @@ __device__ __forceinline__ int lo9(int r, int c) { return (r * (r + 1)) / 2 + c;
 // ---------------------------------------------------------------------------
 // One workgroup of PC_FEAT_WAVES wavefronts per camera i; wavefront v takes
 // the camera's neighbour slots v, v + PC_FEAT_WAVES, ...: the lanes share one
-// block at a time through LDS (entry (r, c) of each 9x9 product per lane),
-// and the wavefronts' partial sums of E_i are added in wavefront order.
-constexpr int PC_FEAT_WAVES = 4;
+// block at a time through the wavefront's own LDS buffers (entry (r, c) of
+// each 9x9 product per lane; the wavefronts synchronise only within
+// themselves), and the wavefronts' partial sums of E_i are added in
+// wavefront order.
+constexpr int PC_FEAT_WAVES = 16;
+constexpr int PC_FEAT_WMAX = 1024;  // slots whose weights wait in LDS for the normalisation
+
+// Orders the LDS accesses of one wavefront's lanes (a wavefront-wide barrier).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 template <typename T>
 __global__ __launch_bounds__(64 * PC_FEAT_WAVES) void k_pc_features(PcFeatureArgs a) {
@@ -49,12 +59,15 @@ __global__ __launch_bounds__(64 * PC_FEAT_WAVES) void k_pc_features(PcFeatureArg
   __shared__ double Li[81];                    // this camera's Linv
   __shared__ double es[PC_FEAT_WAVES][45];
   __shared__ double as_[PC_FEAT_WAVES];
+  __shared__ double etot[45];
+  __shared__ float wl[PC_FEAT_WMAX];           // a_ij of the first PC_FEAT_WMAX slots
   const int i = blockIdx.x, wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   double* Bv = sm[wave][0];
   double* Ln = sm[wave][1];
   double* Pm = sm[wave][2];
   double* Tm = sm[wave][3];
   for (int q = threadIdx.x; q < 81; q += blockDim.x) Li[q] = a.Linv[81 * (size_t)i + q];
+  __syncthreads();
   const int s0 = a.nbr_ptr[i], s1 = a.nbr_ptr[i + 1];
   const T* __restrict__ Sv = reinterpret_cast<const T*>(a.S);
   // entry of E_i this lane accumulates (lanes < 45)
@@ -64,17 +77,18 @@ __global__ __launch_bounds__(64 * PC_FEAT_WAVES) void k_pc_features(PcFeatureArg
     ec = er + (lane - up9(er, er));
   }
   double e_acc = 0.0, asum = 0.0;
-  const int rounds = (s1 - s0 + PC_FEAT_WAVES - 1) / PC_FEAT_WAVES;
+  // this wavefront's slots: s0 + wave + PC_FEAT_WAVES * it, it < rounds
+  const int rounds = s1 - s0 > wave ? (s1 - s0 - wave + PC_FEAT_WAVES - 1) / PC_FEAT_WAVES : 0;
   // the next round's block and neighbour factor are loaded into registers
   // while the current one is processed (entries lane and lane + 64)
-  int nblk = 0, nra = 0, ncb = 0;
+  // (the neighbour of an upper block of row i has the larger index)
+  int nblk = 0, nother = 0;
   double pb0 = 0.0, pb1 = 0.0, pl0 = 0.0, pl1 = 0.0;
   auto prefetch = [&](int it) {
     const int sl = min(s0 + it * PC_FEAT_WAVES + wave, s1 - 1);
     nblk = a.nbr_blk[sl];
-    nra = a.blk_row[nblk];
-    ncb = a.S_col[nblk];
-    const int other = nra == i ? ncb : nra;
+    nother = a.nbr[sl];
+    const int other = nother;
     pb0 = (double)Sv[81 * (size_t)nblk + lane];
     pl0 = a.Linv[81 * (size_t)other + lane];
     const int q1 = min(lane + 64, 80);
@@ -85,14 +99,13 @@ __global__ __launch_bounds__(64 * PC_FEAT_WAVES) void k_pc_features(PcFeatureArg
   for (int it = 0; it < rounds; ++it) {
     const int sl = s0 + it * PC_FEAT_WAVES + wave;
     const bool valid = sl < s1;
-    const int ra = nra, cb = ncb;
-    const bool up = ra == i;  // camera i is the block's row (else its column)
+    const bool up = nother > i;  // camera i is the block's row (else its column)
     Bv[lane] = pb0;
     Ln[lane] = pl0;
     Bv[lane + 64] = pb1;
     Ln[lane + 64] = pl1;
     if (it + 1 < rounds) prefetch(it + 1);
-    __syncthreads();
+    wave_sync();
     const double* La = up ? Li : Ln;  // Linv of the block's row camera
     const double* Lb = up ? Ln : Li;  // and of its column camera
     // P = Linv_row S_e (lower-triangular factor)
@@ -102,7 +115,7 @@ __global__ __launch_bounds__(64 * PC_FEAT_WAVES) void k_pc_features(PcFeatureArg
       for (int k = 0; k <= r; ++k) v += La[9 * r + k] * Bv[9 * k + c];
       Pm[q] = v;
     }
-    __syncthreads();
+    wave_sync();
     // T = P Linv_col^T: the normalised block as stored
     double fro = 0.0;
     for (int q = lane; q < 81; q += 64) {
@@ -112,7 +125,7 @@ __global__ __launch_bounds__(64 * PC_FEAT_WAVES) void k_pc_features(PcFeatureArg
       Tm[q] = v;
       fro += v * v;
     }
-    __syncthreads();
+    wave_sync();
     fro = wave_sum(fro);
     if (valid) {
       // S^_ij = T (camera i is the block's row) or T^T: E_i += S^ S^^T
@@ -125,32 +138,50 @@ __global__ __launch_bounds__(64 * PC_FEAT_WAVES) void k_pc_features(PcFeatureArg
         e_acc += v;
       }
       const double aw = sqrt(fro);
-      if (lane == 0) a.w[sl] = (float)aw;  // normalised below
+      if (lane == 0) {  // normalised below
+        if (sl - s0 < PC_FEAT_WMAX) wl[sl - s0] = (float)aw;
+        else a.w[sl] = (float)aw;
+      }
       asum += aw;
     }
-    __syncthreads();
+    wave_sync();
   }
   if (lane < 45) es[wave][lane] = e_acc;
   if (lane == 0) as_[wave] = asum;
   __syncthreads();
-  double tot = 0.0, tr = 0.0;
-  for (int v = 0; v < PC_FEAT_WAVES; ++v) tot += as_[v];
-  for (int r = 0; r < 9; ++r)
-    for (int v = 0; v < PC_FEAT_WAVES; ++v) tr += es[v][up9(r, r)];
   const int t = threadIdx.x;
+  double tot = 0.0;
+  for (int v = 0; v < PC_FEAT_WAVES; ++v) tot += as_[v];
   if (t < 45) {
     double e = 0.0;
     for (int v = 0; v < PC_FEAT_WAVES; ++v) e += es[v][t];
+    etot[t] = e;
     a.E[45 * (size_t)i + t] = (float)e;
     a.X[GNN_F * (size_t)i + t] = (float)e;
-  } else if (t == 45) {
-    a.X[GNN_F * (size_t)i + 45] = (float)log1p(tr);
   } else if (t == 46) {
     a.X[GNN_F * (size_t)i + 46] = (float)log1p((double)(s1 - s0));
   }
-  // weights: a_ij / sum_j a_ij (each slot written above by its wavefront's lane 0)
+  // weights: a_ij / sum_j a_ij (each slot's a_ij stored above by its wavefront's lane 0)
+  for (int sl = s0 + t; sl < s1; sl += blockDim.x) {
+    const float aw = sl - s0 < PC_FEAT_WMAX ? wl[sl - s0] : a.w[sl];
+    a.w[sl] = tot > 0.0 ? (float)((double)aw / tot) : 0.0f;
+  }
   __syncthreads();
-  for (int sl = s0 + t; sl < s1; sl += blockDim.x) a.w[sl] = tot > 0.0 ? (float)((double)a.w[sl] / tot) : 0.0f;
+  double tr = 0.0;
+  for (int r = 0; r < 9; ++r) tr += etot[up9(r, r)];
+  const float xtr = (float)log1p(tr);
+  if (t == 45) a.X[GNN_F * (size_t)i + 45] = xtr;
+  if (a.H0 && t < GNN_H) {
+    // input layer of the network for this camera, the training formula:
+    // z = b_in + sum_k x_k W_in[t][k] in feature order, h0 = relu(z)
+    const float* W = a.params + GNN_OFF_WIN + (size_t)t * GNN_F;
+    float z = a.params[GNN_OFF_BIN + t];
+    for (int k = 0; k < GNN_F; ++k) {
+      const float xk = k < 45 ? (float)etot[k] : k == 45 ? xtr : (float)log1p((double)(s1 - s0));
+      z = fmaf(xk, W[k], z);
+    }
+    a.H0[GNN_H * (size_t)i + t] = fmaxf(z, 0.0f);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -366,8 +397,10 @@ __global__ __launch_bounds__(256) void k_gnn_adam(int64_t n, float* __restrict__
 }
 
 // ---------------------------------------------------------------------------
-// inference in BF16 on the matrix cores, FP32 accumulate: the same dense
-// layers as k_gnn_dense with inputs and weights rounded to bfloat16.
+// inference of the message layers in BF16 on the matrix cores, FP32
+// accumulate: the same layers as k_gnn_aggregate + k_gnn_dense with the
+// dense inputs and weights rounded to bfloat16 (the input layer is formed in
+// FP32 by the feature kernel).
 // ---------------------------------------------------------------------------
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
@@ -378,70 +411,23 @@ __device__ __forceinline__ short to_bf16(float f) {  // round to nearest even
   return (short)(u >> 16);
 }
 
-// weights of the input and message layers as BF16 rows padded to K:
-// [W_in | 0] (64 x 48), then per layer [W_s | W_m] (64 x 128)
+// weights of the message layers as BF16 rows: per layer [W_s | W_m] (64 x 128)
 __global__ __launch_bounds__(256) void k_gnn_weights_bf16(const float* __restrict__ P,
                                                           short* __restrict__ Wb) {
-  const int q = blockIdx.x * blockDim.x + threadIdx.x;
-  const int n_in = GNN_H * GNN_KIN;
-  if (q < n_in) {
-    const int o = q / GNN_KIN, k = q - GNN_KIN * (q / GNN_KIN);
-    Wb[q] = k < GNN_F ? to_bf16(P[GNN_OFF_WIN + o * GNN_F + k]) : (short)0;
-    return;
-  }
-  const int r = q - n_in;
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= GNN_L * GNN_H * GNN_KHID) return;
   const int l = r / (GNN_H * GNN_KHID), rr = r - l * (GNN_H * GNN_KHID);
   const int o = rr / GNN_KHID, k = rr - GNN_KHID * (rr / GNN_KHID);
   const float* L0 = P + GNN_OFF_L0 + l * GNN_LAYER_SIZE;
-  Wb[q] = to_bf16(k < GNN_H ? L0[o * GNN_H + k] : L0[GNN_H * GNN_H + o * GNN_H + (k - GNN_H)]);
-}
-
-// Z = [X | M] W^T + b, H = relu(Z); one workgroup per 16 rows, one 16x16
-// output tile per wavefront, v_mfma_f32_16x16x16_bf16 (lane l: A row l%16,
-// k 4(l/16)..+3; B column l%16, same k; D rows 4(l/16)..+3 of column l%16)
-__global__ __launch_bounds__(256) void k_gnn_dense_bf16(int n, const float* __restrict__ X, int K1,
-                                                         const float* __restrict__ M,
-                                                         const short* __restrict__ Wb, int Kp,
-                                                         const float* __restrict__ b,
-                                                         float* __restrict__ Z, float* __restrict__ H) {
-  // wavefront (workgroup, w) computes output rows r0..r0+15, columns
-  // 16 t .. 16 t + 15 with t = w (4 wavefronts cover the 64 columns)
-  const int lane = threadIdx.x & 63, t = threadIdx.x >> 6;
-  const int r0 = blockIdx.x * 16;
-  if (r0 >= n) return;
-  const int row = r0 + (lane & 15), kq = 4 * (lane >> 4);
-  f32x4 acc = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-  for (int kb = 0; kb < Kp; kb += 16) {
-    bf16x4 av;
-    for (int j = 0; j < 4; ++j) {
-      const int k = kb + kq + j;
-      float v = 0.0f;
-      if (row < n) {
-        if (k < K1) v = X[(size_t)row * K1 + k];
-        else if (M && k < K1 + GNN_H) v = M[(size_t)row * GNN_H + (k - K1)];
-      }
-      av[j] = to_bf16(v);
-    }
-    const short* w = Wb + (size_t)(16 * t + (lane & 15)) * Kp + kb + kq;
-    const bf16x4 bv = {w[0], w[1], w[2], w[3]};
-    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc, 0, 0, 0);
-  }
-  const int col = 16 * t + (lane & 15);
-  for (int j = 0; j < 4; ++j) {
-    const int r = r0 + kq + j;
-    if (r < n) {
-      const float z = acc[j] + b[col];
-      Z[(size_t)r * GNN_H + col] = z;
-      H[(size_t)r * GNN_H + col] = fmaxf(z, 0.0f);
-    }
-  }
+  Wb[r] = to_bf16(k < GNN_H ? L0[o * GNN_H + k] : L0[GNN_H * GNN_H + o * GNN_H + (k - GNN_H)]);
 }
 
 // One message-passing layer of the inference, aggregation fused:
 //   M = sum_s w_s H_nbr(s) for the workgroup's 16 rows (into LDS), then
-//   Z = [H | M] [W_s | W_m]^T + b, H' = relu(Z) on the matrix cores as in
-//   k_gnn_dense_bf16 (the aggregated messages never go to memory).
+//   Z = [H | M] [W_s | W_m]^T + b, H' = relu(Z) on the matrix cores (one
+//   16x16 output tile per wavefront, v_mfma_f32_16x16x16_bf16; lane l: A row
+//   l%16, k 4(l/16)..+3; B column l%16, same k; D rows 4(l/16)..+3 of column
+//   l%16); the aggregated messages never go to memory.
 __global__ __launch_bounds__(256) void k_gnn_layer_bf16(int n, const int32_t* __restrict__ nbr_ptr,
                                                          const int32_t* __restrict__ nbr,
                                                          const float* __restrict__ wgt,
@@ -451,19 +437,56 @@ __global__ __launch_bounds__(256) void k_gnn_layer_bf16(int n, const int32_t* __
                                                          float* __restrict__ Hout) {
   __shared__ float Ms[16][GNN_H + 4];
   const int r0 = blockIdx.x * 16;
+  const int lane = threadIdx.x & 63, t = threadIdx.x >> 6;
+  const int row = r0 + (lane & 15), kq = 4 * (lane >> 4);
+  // this lane's matrix-core operands that do not depend on the messages (its
+  // row's own features, the weights), requested before the aggregation
+  constexpr int KB = GNN_KHID / 16;
+  float hown[GNN_H / 16][4];
+#pragma unroll
+  for (int b4 = 0; b4 < GNN_H / 16; ++b4)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) hown[b4][j] = row < n ? Hin[(size_t)row * GNN_H + 16 * b4 + kq + j] : 0.0f;
+  bf16x4 wv4[KB];
   {
-    // thread t: row t / 16 of the workgroup, features 4 (t % 16) .. + 3
-    const int lr = threadIdx.x >> 4, f = 4 * (threadIdx.x & 15);
+    const short* w = Wb + (size_t)(16 * t + (lane & 15)) * GNN_KHID + kq;
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb) wv4[kb] = *reinterpret_cast<const bf16x4*>(w + 16 * kb);
+  }
+  {
+    // thread t: row t / 16 of the workgroup, features 4 (t % 16) .. + 3.
+    // The row's 16 threads load 32 neighbour slots at once (two each) and
+    // pass them round by shuffles, so the feature rows of 16 neighbours are
+    // requested together; the sum still takes the neighbours in order.
+    const int lr = threadIdx.x >> 4, j = threadIdx.x & 15, f = 4 * j;
     const int i = r0 + lr;
     float m0 = 0.0f, m1 = 0.0f, m2 = 0.0f, m3 = 0.0f;
-    if (i < n) {
-      for (int s = nbr_ptr[i]; s < nbr_ptr[i + 1]; ++s) {
-        const float ws = wgt[s];
-        const float4 h = *reinterpret_cast<const float4*>(Hin + (size_t)nbr[s] * GNN_H + f);
-        m0 = fmaf(ws, h.x, m0);
-        m1 = fmaf(ws, h.y, m1);
-        m2 = fmaf(ws, h.z, m2);
-        m3 = fmaf(ws, h.w, m3);
+    const int s0 = i < n ? nbr_ptr[i] : 0, s1 = i < n ? nbr_ptr[i + 1] : 0;
+    for (int sb = s0; sb < s1; sb += 32) {
+      const int cnt = min(32, s1 - sb);
+      const int my_n0 = j < cnt ? nbr[sb + j] : 0, my_n1 = j + 16 < cnt ? nbr[sb + j + 16] : 0;
+      const float my_w0 = j < cnt ? wgt[sb + j] : 0.0f, my_w1 = j + 16 < cnt ? wgt[sb + j + 16] : 0.0f;
+      for (int q0 = 0; q0 < cnt; q0 += 16) {
+        const int my_n = q0 == 0 ? my_n0 : my_n1;
+        const float my_w = q0 == 0 ? my_w0 : my_w1;
+        float4 h[16];
+        float wv[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+          const int src = __shfl(my_n, q, 16);
+          wv[q] = __shfl(my_w, q, 16);
+          h[q] = q0 + q < cnt ? *reinterpret_cast<const float4*>(Hin + (size_t)src * GNN_H + f)
+                              : float4{0.0f, 0.0f, 0.0f, 0.0f};
+        }
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+          if (q0 + q < cnt) {
+            m0 = fmaf(wv[q], h[q].x, m0);
+            m1 = fmaf(wv[q], h[q].y, m1);
+            m2 = fmaf(wv[q], h[q].z, m2);
+            m3 = fmaf(wv[q], h[q].w, m3);
+          }
+        }
       }
     }
     Ms[lr][f] = m0;
@@ -472,20 +495,18 @@ __global__ __launch_bounds__(256) void k_gnn_layer_bf16(int n, const int32_t* __
     Ms[lr][f + 3] = m3;
   }
   __syncthreads();
-  const int lane = threadIdx.x & 63, t = threadIdx.x >> 6;
-  const int row = r0 + (lane & 15), kq = 4 * (lane >> 4);
   f32x4 acc = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-  for (int kb = 0; kb < GNN_KHID; kb += 16) {
+#pragma unroll
+  for (int kb = 0; kb < KB; ++kb) {
     bf16x4 av;
+#pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const int k = kb + kq + j;
+      const int k = 16 * kb + kq + j;
       float v = 0.0f;
-      if (row < n) v = k < GNN_H ? Hin[(size_t)row * GNN_H + k] : Ms[lane & 15][k - GNN_H];
+      if (row < n) v = k < GNN_H ? hown[kb][j] : Ms[lane & 15][k - GNN_H];
       av[j] = to_bf16(v);
     }
-    const short* w = Wb + (size_t)(16 * t + (lane & 15)) * GNN_KHID + kb + kq;
-    const bf16x4 bv = {w[0], w[1], w[2], w[3]};
-    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, wv4[kb], acc, 0, 0, 0);
   }
   const int col = 16 * t + (lane & 15);
   for (int j = 0; j < 4; ++j) {
@@ -499,17 +520,15 @@ __global__ __launch_bounds__(256) void k_gnn_layer_bf16(int n, const int32_t* __
 // ---------------------------------------------------------------------------
 
 hipError_t launch_gnn_weights_bf16(const float* P, short* Wb, hipStream_t s) {
-  const int n = GNN_H * GNN_KIN + GNN_L * GNN_H * GNN_KHID;
+  const int n = GNN_L * GNN_H * GNN_KHID;
   hipLaunchKernelGGL(k_gnn_weights_bf16, dim3((n + 255) / 256), dim3(256), 0, s, P, Wb);
   return hipGetLastError();
 }
 
 hipError_t launch_gnn_forward_bf16(const GraphDev& g, const float* P, const short* Wb, hipStream_t s) {
   const dim3 grid((g.nc + 15) / 16), blk(256);
-  hipLaunchKernelGGL(k_gnn_dense_bf16, grid, blk, 0, s, g.nc, g.X, GNN_F, (const float*)nullptr, Wb,
-                     GNN_KIN, P + GNN_OFF_BIN, g.Z[0], g.H[0]);
   for (int l = 0; l < GNN_L; ++l) {
-    const short* Wl = Wb + GNN_H * GNN_KIN + (size_t)l * GNN_H * GNN_KHID;
+    const short* Wl = Wb + (size_t)l * GNN_H * GNN_KHID;
     const float* bl = P + GNN_OFF_L0 + l * GNN_LAYER_SIZE + 2 * GNN_H * GNN_H;
     hipLaunchKernelGGL(k_gnn_layer_bf16, grid, blk, 0, s, g.nc, g.nbr_ptr, g.nbr, g.w, g.H[l], Wl, bl,
                        g.H[l + 1]);

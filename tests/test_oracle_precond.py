@@ -131,21 +131,26 @@ def test_bf16_rounding_by_definition():
         assert G.bf16(x) == want, (x, G.bf16(x), want)
 
 
-def test_bf16_inference_equals_exact_when_operands_are_representable(system):
-    """With inputs and weights already on the bfloat16 grid the rounded
-    network's first layer is the exact one."""
+def test_bf16_inference_rounds_message_layer_operands_only(system):
+    """The rounded network keeps the input layer exact; a message layer whose
+    operands are already on the bfloat16 grid is the exact one (W_in = 0 and
+    b_in on the grid make h0 representable, W_m = 0 drops the messages), and
+    moving its weights off the grid changes it."""
     s, o, ptr, col, S, bS = system
     g = G.system_graph(ptr, col, S, s.n_cams)
     rng = np.random.default_rng(5)
     d = G.unpack(G.init_params(rng))
-    for k in d:
-        d[k][:] = G.bf16(d[k])
-        if k == "W_out":
-            d[k][:] = G.bf16(rng.normal(size=d[k].shape) * 0.05)
-    theta = G.pack(d)
-    # inputs on the grid too (the hidden activations are not: only the first layer is exact)
-    g2 = dict(g)
-    g2["X"] = G.bf16(g["X"])
-    o_exact, c_exact = G.forward(theta, g2)
-    o_b, c_b = G.forward(theta, g2, bf16_inference=True)
+    o_exact, c_exact = G.forward(G.pack(d), g)
+    o_b, c_b = G.forward(G.pack(d), g, bf16_inference=True)
     np.testing.assert_array_equal(c_b["z"][0], c_exact["z"][0])
+    d["W_in"][:] = 0.0
+    d["b_in"][:] = G.bf16(rng.normal(size=d["b_in"].shape))
+    d["W_s0"][:] = G.bf16(d["W_s0"])
+    d["W_m0"][:] = 0.0
+    _, c_exact = G.forward(G.pack(d), g)
+    _, c_b = G.forward(G.pack(d), g, bf16_inference=True)
+    np.testing.assert_array_equal(c_b["z"][1], c_exact["z"][1])
+    d["W_s0"][:] *= 1.0 + 2.0 ** -10      # off the grid: rounded back in the inference form
+    _, c_exact = G.forward(G.pack(d), g)
+    _, c_b = G.forward(G.pack(d), g, bf16_inference=True)
+    assert not np.array_equal(c_b["z"][1], c_exact["z"][1])
