@@ -1062,8 +1062,8 @@ __device__ __forceinline__ bool stream_spmv(const PcgArgs& a, const StreamCtx& c
   if (threadIdx.x == 0) publish(a.rflag + (size_t)slot * c.G + c.B, 1.0);
   // outputs: the groups rptr[row] / L .. (rptr[row + 1] - 1) / L touched row
   // `row` (none when the row has no upper block); 8 lanes per output,
-  // strided then a 3-step butterfly: fixed order; then the row's own column
-  // sum, when one of the workgroup's blocks lies in its column
+  // strided then three DPP lane moves: fixed order; then the row's own
+  // column sum, when one of the workgroup's blocks lies in its column
   for (int base = 0; base < nout * 8; base += blockDim.x) {
     const int t = base + threadIdx.x, o = t >> 3, sub = t & 7;
     double sum = 0.0;
@@ -1076,9 +1076,9 @@ __device__ __forceinline__ bool stream_spmv(const PcgArgs& a, const StreamCtx& c
         for (int gg = g0 + sub; gg <= g1; gg += 8) sum += seg[(row + gg) * 9 + cp];
       }
     }
-    sum += __shfl_xor(sum, 1, 64);
-    sum += __shfl_xor(sum, 2, 64);
-    sum += __shfl_xor(sum, 4, 64);
+    sum += dpp_mov<0xB1, 0xF>(sum);   // quad_perm [1,0,3,2]
+    sum += dpp_mov<0x4E, 0xF>(sum);   // quad_perm [2,3,0,1]
+    sum += dpp_mov<0x141, 0xF>(sum);  // row_half_mirror: the other quad of the 8
     if (o < nout && sub == 0) nl[o] = lcol[row] >= 0 ? sum + tl[lcol[row] * 9 + cp] : sum;
   }
   // wait for the workgroups that send to this one (thread t for sender t)
@@ -1118,6 +1118,8 @@ __global__ __launch_bounds__(PCG_THREADS) void k_pcg_stream(PcgArgs a) {
   __shared__ double red[PCG_THREADS / 64];
   __shared__ double red3[PCG_THREADS / 64][3];
   __shared__ double red3s[3 * (PCG_THREADS / 64)];
+  __shared__ double scal[5];  // alpha, beta, residual norm; previous gamma, alpha (wavefront 0)
+  __shared__ int sstate;      // 0: continue, 1: converged or at maxiter, 2: breakdown
   __shared__ int poll_failed;
   const int G = gridDim.x, B = xcd_block(blockIdx.x, gridDim.x), tid = threadIdx.x, nt = blockDim.x;
   StreamCtx c;
@@ -1198,6 +1200,17 @@ __global__ __launch_bounds__(PCG_THREADS) void k_pcg_stream(PcgArgs a) {
   for (int k = tid; k < 3 * (a.maxiter + 1); k += nt)
     clear_record(a.partA + (size_t)(k / 3) * pstride + (size_t)B * PART_STRIDE + (k - 3 * (k / 3)));
   for (int k = tid; k < a.maxiter + 2; k += nt) clear_record(a.rflag + (size_t)k * G + B);
+  // The z columns of this workgroup's rows are marked pending before their
+  // ring slot is read (readers poll them together with the dot records):
+  // slots 1 .. 3 here; slot i + 3 by each element's owner in iteration i,
+  // which the product's wait for its stores before it raises its flag
+  // completes before any workgroup can reach iteration i + 2, where slot
+  // i + 3 is read; the owner's own value store to it comes later in program
+  // order.
+  for (int k = tid; k < min(3, a.maxiter + 1) * n9; k += nt) {
+    const int sl = k / n9, e = k - sl * n9, rw = e / 9;
+    clear_record(a.zring + (size_t)(sl + 1) * zstride + (size_t)(r0 + rw) * ZSTRIDE + (e - 9 * rw));
+  }
   bool ok = grid_barrier(a.gs, a.error);
   fetch_cols(vcl, a.zring, c.nvc, zl);
   double t0 = 0.0;
@@ -1209,13 +1222,15 @@ __global__ __launch_bounds__(PCG_THREADS) void k_pcg_stream(PcgArgs a) {
     wl[tid] = w;
   }
   __syncthreads();
-  double rnorm = bnorm, gamma_old = 1.0, alpha_old = 1.0;
+  double rnorm = bnorm;
   int iters = 0, breakdown = 0;
+  const int nwr = (G + 63) >> 6;  // wavefronts polling dot records
   for (int i = 0; ok && bnorm > 0.0 && i <= a.maxiter; ++i) {
     // local: partial dots of r, u, w; m = M w published in slot i + 1
     double* zk = a.zring + (size_t)(i + 1) * zstride;
     double s_g = 0.0, s_d = 0.0, s_r = 0.0;
     if (own) {
+      if (i + 3 <= a.maxiter + 1) clear_record(zk + 2 * zstride + (size_t)(r0 + row) * ZSTRIDE + cp);
       double v = 0.0;
 #pragma unroll
       for (int k = 0; k < 9; ++k) v += Mr[k] * wl[row * 9 + k];
@@ -1226,21 +1241,22 @@ __global__ __launch_bounds__(PCG_THREADS) void k_pcg_stream(PcgArgs a) {
       s_d = w * u;
       s_r = r * r;
     }
-    s_g = wave_sum(s_g);
-    s_d = wave_sum(s_d);
-    s_r = wave_sum(s_r);
-    if ((tid & 63) == 0) {
-      red3[tid >> 6][0] = s_g;
-      red3[tid >> 6][1] = s_d;
-      red3[tid >> 6][2] = s_r;
+    const int nwa = (n9 + 63) >> 6;  // wavefronts holding elements
+    if ((tid >> 6) < nwa) {
+      s_g = dpp_wave_total(s_g);
+      s_d = dpp_wave_total(s_d);
+      s_r = dpp_wave_total(s_r);
+      if ((tid & 63) == 63) {
+        red3[tid >> 6][0] = s_g;
+        red3[tid >> 6][1] = s_d;
+        red3[tid >> 6][2] = s_r;
+      }
     }
-    // the m columns must have reached memory before the partials are seen
-    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     double* pa = a.partA + (size_t)i * pstride;
     if (tid < 3) {
       double v = 0.0;
-      for (int w2 = 0; w2 < PCG_THREADS / 64; ++w2) v += red3[w2][tid];
+      for (int w2 = 0; w2 < nwa; ++w2) v += red3[w2][tid];
       publish(pa + (size_t)B * PART_STRIDE + tid, v);
     }
     // the diagonal part of n = S m while the other workgroups catch up
@@ -1249,46 +1265,68 @@ __global__ __launch_bounds__(PCG_THREADS) void k_pcg_stream(PcgArgs a) {
 #pragma unroll
       for (int k = 0; k < 9; ++k) nd += drow[k] * ml[row * 9 + k];
     }
+    // the m columns this workgroup reads (into zl: w is no longer needed in
+    // its memory) and (thread t < G) workgroup t's partials, in one poll;
+    // each polling wavefront sums its partials
     double tg = 0.0, td = 0.0, tr = 0.0;
-    if (tid < G && !poll_record(pa + (size_t)tid * PART_STRIDE, tg, td, tr, a.error)) poll_failed = 1;
-    tg = wave_sum(tg);
-    td = wave_sum(td);
-    tr = wave_sum(tr);
-    if ((tid & 63) == 0) {
-      red3s[3 * (tid >> 6)] = tg;
-      red3s[3 * (tid >> 6) + 1] = td;
-      red3s[3 * (tid >> 6) + 2] = tr;
+    if (!poll_slot(vcl, c.nvc, zk, zl, tid < G ? pa + (size_t)tid * PART_STRIDE : nullptr, tg, td, tr,
+                   a.error))
+      poll_failed = 1;
+    if ((tid >> 6) < nwr) {
+      tg = dpp_wave_total(tg);
+      td = dpp_wave_total(td);
+      tr = dpp_wave_total(tr);
+      if ((tid & 63) == 63) {
+        red3s[3 * (tid >> 6)] = tg;
+        red3s[3 * (tid >> 6) + 1] = td;
+        red3s[3 * (tid >> 6) + 2] = tr;
+      }
     }
     __syncthreads();
     if (poll_failed) {
       ok = false;
       break;
     }
-    // every workgroup's m columns are in memory now (w is no longer needed
-    // in zl's memory)
-    fetch_cols(vcl, zk, c.nvc, zl);
-    double gamma = 0.0, delta = 0.0, rr = 0.0;
-#pragma unroll 2
-    for (int w2 = 0; w2 < PCG_THREADS / 64; ++w2) {
-      gamma += red3s[3 * w2];
-      delta += red3s[3 * w2 + 1];
-      rr += red3s[3 * w2 + 2];
+    if (tid < 64) {
+      // the step's scalars, in wavefront 0 only (the wavefront sums in a
+      // fixed order: identical in every workgroup)
+      double gamma = 0.0, delta = 0.0, rr = 0.0;
+      for (int w2 = 0; w2 < nwr; ++w2) {
+        gamma += red3s[3 * w2];
+        delta += red3s[3 * w2 + 1];
+        rr += red3s[3 * w2 + 2];
+      }
+      gamma = uniform(gamma);
+      delta = uniform(delta);
+      rr = uniform(rr);
+      const double rn = sqrt(rr);
+      int st_ = 0;
+      double al = 0.0, be = 0.0;
+      if (rn <= a.rtol * bnorm || i == a.maxiter) {
+        st_ = 1;
+      } else {
+        be = i > 0 ? gamma / scal[3] : 0.0;
+        const double den = i > 0 ? delta - be * gamma / scal[4] : delta;
+        if (!(den > 0.0)) st_ = 2;
+        else al = gamma / den;
+      }
+      if (tid == 0) {
+        scal[0] = al;
+        scal[1] = be;
+        scal[2] = rn;
+        scal[3] = gamma;
+        scal[4] = al;
+        sstate = st_;
+      }
     }
-    // (identical in every thread: scalar registers)
-    gamma = uniform(gamma);
-    delta = uniform(delta);
-    rr = uniform(rr);
+    __syncthreads();  // the scalars
     iters = i;
-    rnorm = sqrt(rr);
-    if (rnorm <= a.rtol * bnorm || i == a.maxiter) break;
-    const double beta = i > 0 ? gamma / gamma_old : 0.0;
-    const double den = i > 0 ? delta - beta * gamma / alpha_old : delta;
-    if (!(den > 0.0)) {
-      breakdown = 1;
+    if (sstate) {
+      rnorm = scal[2];
+      breakdown = sstate == 2;
       break;
     }
-    const double alpha = gamma / den;
-    __syncthreads();  // zl complete
+    const double alpha = scal[0], beta = scal[1];
     if (!stream_spmv<T>(a, c, i + 1, rptr, lcol, vcl, ipl, inl, zl, ml, tl, seg, st, nl, &poll_failed, Mr, A, Bf)) {
       ok = false;
       break;
@@ -1308,8 +1346,6 @@ __global__ __launch_bounds__(PCG_THREADS) void k_pcg_stream(PcgArgs a) {
       wl[tid] = w;
     }
     __syncthreads();
-    gamma_old = gamma;
-    alpha_old = alpha;
   }
   if (own) a.x[9 * (size_t)r0 + tid] = xl[tid];
   if (B == 0 && tid == 0) {
