@@ -35,14 +35,15 @@ __device__ __forceinline__ int lo9(int r, int c) { return (r * (r + 1)) / 2 + c;
 // T = Linv_row S_e Linv_col^T, by the same code from both endpoints, so the
 // two endpoints see bit-identical weights.
 // ---------------------------------------------------------------------------
-// One workgroup of PC_FEAT_WAVES wavefronts per camera i; wavefront v takes
-// the camera's neighbour slots v, v + PC_FEAT_WAVES, ...: the lanes share one
-// block at a time through the wavefront's own LDS buffers (entry (r, c) of
-// each 9x9 product per lane; the wavefronts synchronise only within
-// themselves), and the wavefronts' partial sums of E_i are added in
-// wavefront order.
-constexpr int PC_FEAT_WAVES = 16;
+// One workgroup of W wavefronts per camera i; wavefront v takes the
+// camera's neighbour slots v, v + W, ...: the lanes share one block at a
+// time through the wavefront's own LDS buffers (entry (r, c) of each 9x9
+// product per lane; the wavefronts synchronise only within themselves), and
+// the wavefronts' partial sums of E_i are added in wavefront order.  Small
+// graphs take W = 16 (each camera's few rounds are the kernel's latency),
+// large ones W = 4 (less LDS per workgroup: more cameras in flight).
 constexpr int PC_FEAT_WMAX = 1024;  // slots whose weights wait in LDS for the normalisation
+constexpr int PC_FEAT_SMALL = 1024;  // graphs up to this many cameras take 16 wavefronts
 
 // Orders the LDS accesses of one wavefront's lanes (a wavefront-wide barrier).
 __device__ __forceinline__ void wave_sync() {
@@ -51,7 +52,7 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <typename T>
+template <int PC_FEAT_WAVES, typename T>
 __global__ __launch_bounds__(64 * PC_FEAT_WAVES) void k_pc_features(PcFeatureArgs a) {
   // block, the neighbour's Linv, products (rows of 128: every lane stores
   // entries lane and lane + 64 without a branch)
@@ -538,7 +539,10 @@ hipError_t launch_gnn_forward_bf16(const GraphDev& g, const float* P, const shor
 
 template <typename T>
 hipError_t launch_pc_features(const PcFeatureArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_pc_features<T>, dim3(a.nc), dim3(64 * PC_FEAT_WAVES), 0, s, a);
+  if (a.nc <= PC_FEAT_SMALL)
+    hipLaunchKernelGGL((k_pc_features<16, T>), dim3(a.nc), dim3(64 * 16), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_pc_features<4, T>), dim3(a.nc), dim3(64 * 4), 0, s, a);
   return hipGetLastError();
 }
 template hipError_t launch_pc_features<float>(const PcFeatureArgs&, hipStream_t);
