@@ -42,9 +42,9 @@ def kernel_bytes(name, scene, nnzb, n_pairs, es, cg_iters):
     es = bytes per stored Jacobian / Q / S value (8 FP64, 4 mixed)."""
     no, nc, np_ = scene.n_obs, scene.n_cams, scene.n_pts
     nnz_off = nnzb - nc
-    if name == "linearize":   # obs xy, w, indices in; r, w, observation row (Jc, Jp, Q, w) and
+    if name == "linearize":   # obs xy, w, indices in; w, observation row (Jc, Jp, Q, w) and
         # record (r, w, e) out; cameras and points in; V, gp, Vinv, ep per point out
-        return (no * (16 + 8 + 4 + 4 + 16 + 8 + 31 * es + 40) + nc * 80
+        return (no * (16 + 8 + 4 + 4 + 8 + 31 * es + 40) + nc * 80
                 + np_ * (24 + 48 + 24 + 48 + 24))
     if name == "damp_points":  # V, gp in; Vinv, ep out (after a rejected step)
         return np_ * (48 + 24 + 48 + 24)

@@ -368,7 +368,7 @@ ba_status lm_step_impl(ba_problem* p, ba_step_info* out) {
   } else if (!p->lin_valid) {
     // linearisation with the point elimination of the current lambda
     LinArgs la{b.chunk_ptr, b.chunk_pt, b.pt_ptr, b.o_cam, b.o_pt, b.fixed, b.o_xy, b.o_w,
-               b.cams[cur], b.pts[cur], p->opt.huber_delta, b.r, b.w, b.J, b.V, b.gp,
+               b.cams[cur], b.pts[cur], p->opt.huber_delta, b.w, b.J, b.V, b.gp,
                b.part_cost, b.part_gmax, b.rec, p->opt.diag_min, p->opt.diag_max, b.Vinv, b.ep,
                b.dev, b.gsync};
     PHASE(0, launch_linearize<T>(la, nchunk, s));
@@ -1306,7 +1306,15 @@ ba_status ba_export(const ba_problem* p, int32_t field, void* dst, size_t bytes)
     case BA_X_WEIGHT: {
       const bool res = field == BA_X_RESIDUAL;
       if (!need(no * sizeof(double) * (res ? 2 : 1))) return fail(BA_EINVAL, "size mismatch");
-      HIPCHK(fetch(res ? (const void*)b.r : (const void*)b.w, no * sizeof(double) * (res ? 2 : 1), h));
+      if (res) {
+        // (r_x, r_y) are the first two words of each observation's 8-word record
+        h.resize(no * 2 * sizeof(double));
+        HIPCHK(hipMemcpy2DAsync(h.data(), 2 * sizeof(double), b.rec, 8 * sizeof(double), 2 * sizeof(double), no,
+                                hipMemcpyDeviceToHost, p->stream));
+        HIPCHK(hipStreamSynchronize(p->stream));
+      } else {
+        HIPCHK(fetch(b.w, no * sizeof(double), h));
+      }
       const double* v = reinterpret_cast<const double*>(h.data());
       for (size_t x = 0; x < no; ++x) {
         const size_t k = P.o_orig[x];

@@ -174,7 +174,8 @@ struct Buffers {
   double *o_xy, *o_w;
   // parameters: [0] current, [1] candidate
   double *cams[2], *pts[2];
-  // linearisation
+  // linearisation: w per observation; r [no][2] is the adjoint's residual
+  // at the solution (the step's residual is in rec)
   double *r, *w;
   void* J;  // float or double [no][NJ] (layout above)
   // [no][8] FP64 per observation: r0, r1, w, 0 (linearisation), then

@@ -15,10 +15,10 @@ struct LinArgs {
   const uint8_t* fixed;
   const double *o_xy, *o_w, *cams, *pts;
   double huber;
-  double *r, *w;
+  double* w;
   void* J;
   double *V, *gp, *part_cost, *part_gmax;
-  double* rec;
+  double* rec;  // per observation: r, w, e (the residual lives only here)
   // point elimination of the same pass (damping with the current lambda)
   double dmin, dmax;
   double *Vinv, *ep;

@@ -227,8 +227,6 @@ __global__ __launch_bounds__(CHUNK) void k_linearize(LinArgs a) {
 #pragma unroll
         for (int m = 6; m < 9; ++m) Jc[i][m] = 0.0;
     }
-    a.r[2 * (size_t)x] = rx;
-    a.r[2 * (size_t)x + 1] = ry;
     a.w[x] = w;
     store_row(reinterpret_cast<T*>(a.J) + (size_t)x * NJ, Jc, Jp);
     sh[0][t] = w * (Jp[0][0] * Jp[0][0] + Jp[1][0] * Jp[1][0]);
