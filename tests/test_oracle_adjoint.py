@@ -253,3 +253,42 @@ def test_gauss_newton_hessian_is_caught_by_finite_differences():
     v[free] = np.linalg.solve(Hgn[np.ix_(free, free)], gL[free])
     dx_gn = np.array([s.obs_w[k] * (J @ v[idx]) for k, (idx, J) in enumerate(Js)])
     assert np.abs(dx_gn - dx).max() > 1e-3 * np.abs(dx).max()
+
+
+def test_weight_derivative_is_orthogonal_to_the_weights():
+    """Scaling every weight by c scales F by c and leaves its minimiser in
+    place, so any loss of the solution has zero derivative along omega:
+    sum_k omega_k dL/d omega_k = 0 (up to the solve's round-off)."""
+    s = tiny_scene(seed=3)
+    o = solve_to_stationary(s)
+    gLc, gLp = loss_tangent_gradient(o, s)
+    _, dw, _, _ = o.backward(gLc, gLp)
+    terms = s.obs_w * dw
+    assert np.abs(terms).max() > 1e-6                       # a loss that does depend on the weights
+    assert abs(terms.sum()) <= 1e-8 * np.abs(terms).sum(), (terms.sum(), np.abs(terms).sum())
+
+
+def test_envelope_case_loss_equal_to_the_objective():
+    """L = F: at the optimum dF/dx = 0, so the adjoint's implicit part
+    vanishes for that loss, and the derivative of the optimal cost F* along
+    omega_k is the explicit term (1/2) |r_k|^2 alone (checked by central
+    differences of F*, re-solving at each perturbed weight)."""
+    s = tiny_scene(seed=3)
+    o = solve_to_stationary(s)
+    cams, pts = o.get_params()
+    o.compute_step()                                        # linearisation at the optimum
+    r, _, _, _, F = o.linearization()
+    _, _, gc, gp = o.normal()
+    explicit = 0.5 * np.sum(r * r, axis=1)
+    _, dw_impl, _, _ = o.backward(gc, gp)
+    assert np.abs(dw_impl).max() <= 1e-8 * explicit.max(), (np.abs(dw_impl).max(), explicit.max())
+
+    def optimal_cost(h, k):
+        w = s.obs_w.copy()
+        w[k] += h
+        return solve_to_stationary(s, w=w, cams=cams, pts=pts, iters=30).cost()
+
+    rng = np.random.default_rng(11)
+    for k in rng.choice(s.n_obs, 4, replace=False):
+        fd = central(lambda h: optimal_cost(h, k), 1e-3)
+        assert abs(fd - explicit[k]) <= 1e-6 * max(abs(fd), explicit.max()), (k, fd, explicit[k])
