@@ -190,8 +190,18 @@ def central(f, h):
     return (f(h) - f(-h)) / (2 * h)
 
 
-def test_adjoint_matches_finite_differences_through_the_solver():
-    s = tiny_scene(seed=2)
+def ring16_scene():
+    """The 16-camera workload (1,024 points, 4,096 observations) with the same
+    weights U(0.5, 1.5) and fixed cameras 0 and 1."""
+    s = make_scene(0)
+    s.obs_w = np.random.default_rng([7, 16]).uniform(0.5, 1.5, s.n_obs)
+    s.fixed_cams = np.array([0, 1], np.int32)
+    return s
+
+
+@pytest.mark.parametrize("scene", ["six_cameras", "ring16"])
+def test_adjoint_matches_finite_differences_through_the_solver(scene):
+    s = tiny_scene(seed=2) if scene == "six_cameras" else ring16_scene()
     o = solve_to_stationary(s)
     cams, pts = o.get_params()
     gLc, gLp = loss_tangent_gradient(o, s)
