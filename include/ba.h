@@ -160,7 +160,8 @@ void ba_default_options(ba_options* opt);
  * matrix and the table of observation pairs that feed each block.  No device
  * work is done.  Errors: BA_EINVAL for sizes <= 0 or indices out of range,
  * BA_EUNSUPPORTED for cam_dof other than 9 or 6 (6 with the learned
- * preconditioner or the adjoint) or a point seen more than 256 times. */
+ * preconditioner or the adjoint).  A point may be seen any number of times
+ * (points seen more than 256 times take their own kernels). */
 ba_status ba_problem_create(const ba_options* opt, int32_t n_cams, int32_t n_pts, int64_t n_obs,
                             const int32_t* cam_idx, const int32_t* pt_idx, ba_problem** out);
 

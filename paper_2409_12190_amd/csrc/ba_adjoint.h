@@ -63,9 +63,9 @@ struct AdjStatArgs {
 hipError_t launch_adj_stationarity(const AdjStatArgs&, hipStream_t);
 hipError_t launch_adj_tangent(const AdjTangentArgs&, hipStream_t);
 hipError_t launch_adj_obs(const AdjObsArgs&, hipStream_t);
-hipError_t launch_adj_points(const AdjPointArgs&, int nchunk, hipStream_t);
+hipError_t launch_adj_points(const AdjPointArgs&, int nchunk, LongChunks, hipStream_t);
 hipError_t launch_adj_camera(const AdjCameraArgs&, int nc, hipStream_t);
 hipError_t launch_adj_schur(const AdjSchurArgs&, int nwg, hipStream_t);
-hipError_t launch_adj_backsub(const AdjBackArgs&, int nchunk, hipStream_t);
+hipError_t launch_adj_backsub(const AdjBackArgs&, int nchunk, LongChunks, hipStream_t);
 
 }  // namespace ba

@@ -17,6 +17,7 @@
 //   J[x][24]  Jc (2x9) then Jp (2x3), fixed cameras' columns zero
 //   Y[x][27]  W_x V_j^-1 (9x3), V_j the exact point block.
 #include "ba_adjoint.h"
+#include "ba_reduce.h"
 #include "ba_device.h"
 
 namespace ba {
@@ -96,6 +97,37 @@ __global__ __launch_bounds__(128) void k_adj_obs(AdjObsArgs a) {
   a.r[2 * x + 1] = r1;
 }
 
+// Inverse of the 3x3 point block m (upper: 00 01 02 11 12 22) by the
+// adjugate into o (same layout); a block that is not positive definite
+// raises ERR_POINT_BLOCK.  An unobserved point (empty block) gets zeros.
+__device__ __forceinline__ void point_block_inverse(const double (&m)[6], bool observed, double (&o)[6],
+                                                    int* error) {
+  for (int q = 0; q < 6; ++q) o[q] = 0.0;
+  if (!observed) return;
+  const double c00 = m[3] * m[5] - m[4] * m[4];
+  const double c01 = m[2] * m[4] - m[1] * m[5];
+  const double c02 = m[1] * m[4] - m[2] * m[3];
+  const double c11 = m[0] * m[5] - m[2] * m[2];
+  const double c12 = m[1] * m[2] - m[0] * m[4];
+  const double c22 = m[0] * m[3] - m[1] * m[1];
+  const double det = m[0] * c00 + m[1] * c01 + m[2] * c02;
+  if (!(det > 0.0) || !isfinite(det) || !(m[0] > 0.0)) atomicOr(error, (int)ERR_POINT_BLOCK);
+  const double id = 1.0 / det;
+  o[0] = c00 * id; o[1] = c01 * id; o[2] = c02 * id;
+  o[3] = c11 * id; o[4] = c12 * id; o[5] = c22 * id;
+}
+
+// Y_x = W_x V_j^-1 of position x (W_x: the camera-point coupling rows of A_x).
+__device__ __forceinline__ void adj_y(const AdjPointArgs& a, int x, const double (&v)[6]) {
+  const double Vm[3][3] = {{v[0], v[1], v[2]}, {v[1], v[3], v[4]}, {v[2], v[4], v[5]}};
+  const double* A = a.A + 78 * (size_t)x;
+  double* Y = a.Y + 27 * (size_t)x;
+  for (int i = 0; i < 9; ++i) {
+    const double w0 = A[sym12(i, 9)], w1 = A[sym12(i, 10)], w2 = A[sym12(i, 11)];
+    for (int q = 0; q < 3; ++q) Y[3 * i + q] = w0 * Vm[0][q] + w1 * Vm[1][q] + w2 * Vm[2][q];
+  }
+}
+
 // per chunk of points: exact point blocks V_j (segmented sums in LDS, fixed
 // order), their inverses, and Y_x = W_x V_j^-1 for every position.  Also
 // clears the PCG grid-barrier counters (first workgroup).
@@ -113,6 +145,7 @@ __global__ __launch_bounds__(CHUNK) void k_adj_points(AdjPointArgs a) {
       a.gs->group[t - 1].count = 0u;
     }
   }
+  if (x1 - x0 > CHUNK) return;  // one long track: k_adj_points_long
   const int pidx[6][2] = {{0, 0}, {0, 1}, {0, 2}, {1, 1}, {1, 2}, {2, 2}};
   if (x < x1) {
     const double* A = a.A + 78 * (size_t)x;
@@ -125,20 +158,8 @@ __global__ __launch_bounds__(CHUNK) void k_adj_points(AdjPointArgs a) {
     double m[6] = {0, 0, 0, 0, 0, 0};
     for (int y = lo; y < hi; ++y)
       for (int q = 0; q < 6; ++q) m[q] += vs[q][y];
-    double o[6] = {0, 0, 0, 0, 0, 0};
-    if (hi > lo) {
-      const double c00 = m[3] * m[5] - m[4] * m[4];
-      const double c01 = m[2] * m[4] - m[1] * m[5];
-      const double c02 = m[1] * m[4] - m[2] * m[3];
-      const double c11 = m[0] * m[5] - m[2] * m[2];
-      const double c12 = m[1] * m[2] - m[0] * m[4];
-      const double c22 = m[0] * m[3] - m[1] * m[1];
-      const double det = m[0] * c00 + m[1] * c01 + m[2] * c02;
-      if (!(det > 0.0) || !isfinite(det) || !(m[0] > 0.0)) atomicOr(a.error, (int)ERR_POINT_BLOCK);
-      const double id = 1.0 / det;
-      o[0] = c00 * id; o[1] = c01 * id; o[2] = c02 * id;
-      o[3] = c11 * id; o[4] = c12 * id; o[5] = c22 * id;
-    }
+    double o[6];
+    point_block_inverse(m, hi > lo, o, a.error);
     double* Vg = a.Vinv + 6 * (size_t)jj;
     for (int q = 0; q < 6; ++q) {
       Vg[q] = o[q];
@@ -148,16 +169,38 @@ __global__ __launch_bounds__(CHUNK) void k_adj_points(AdjPointArgs a) {
   __syncthreads();
   if (x < x1) {
     const int jl = a.o_pt[x] - j0;
-    const double Vm[3][3] = {{vi[0][jl], vi[1][jl], vi[2][jl]},
-                             {vi[1][jl], vi[3][jl], vi[4][jl]},
-                             {vi[2][jl], vi[4][jl], vi[5][jl]}};
+    const double v[6] = {vi[0][jl], vi[1][jl], vi[2][jl], vi[3][jl], vi[4][jl], vi[5][jl]};
+    adj_y(a, x, v);
+  }
+}
+
+// The chunks of one point seen more than CHUNK times: each thread sums the
+// point block over the observations t, t + CHUNK, ...; the threads' partials
+// are added in a fixed order and thread 0 inverts.
+__global__ __launch_bounds__(CHUNK) void k_adj_points_long(AdjPointArgs a, const int32_t* chunks) {
+  __shared__ double lds[3 * (CHUNK / 64) + 6];
+  const int c = chunks[blockIdx.x];
+  const int x0 = a.chunk_ptr[c], x1 = a.chunk_ptr[c + 1], j = a.chunk_pt[c], t = threadIdx.x;
+  const int pidx[6][2] = {{0, 0}, {0, 1}, {0, 2}, {1, 1}, {1, 2}, {2, 2}};
+  double m[6] = {0, 0, 0, 0, 0, 0};
+  for (int x = x0 + t; x < x1; x += CHUNK) {
     const double* A = a.A + 78 * (size_t)x;
-    double* Y = a.Y + 27 * (size_t)x;
-    for (int i = 0; i < 9; ++i) {
-      const double w0 = A[sym12(i, 9)], w1 = A[sym12(i, 10)], w2 = A[sym12(i, 11)];
-      for (int q = 0; q < 3; ++q) Y[3 * i + q] = w0 * Vm[0][q] + w1 * Vm[1][q] + w2 * Vm[2][q];
+    for (int q = 0; q < 6; ++q) m[q] += A[sym12(9 + pidx[q][0], 9 + pidx[q][1])];
+  }
+  block_sum3(m[0], m[1], m[2], lds);
+  block_sum3(m[3], m[4], m[5], lds);
+  double* const vb = lds + 3 * (CHUNK / 64);
+  if (t == 0) {
+    double o[6];
+    point_block_inverse(m, true, o, a.error);
+    for (int q = 0; q < 6; ++q) {
+      a.Vinv[6 * (size_t)j + q] = o[q];
+      vb[q] = o[q];
     }
   }
+  __syncthreads();
+  const double v[6] = {vb[0], vb[1], vb[2], vb[3], vb[4], vb[5]};
+  for (int x = x0 + t; x < x1; x += CHUNK) adj_y(a, x, v);
 }
 
 // per camera: the exact camera block U_a = sum A_cc and the right-hand side
@@ -259,6 +302,26 @@ __global__ __launch_bounds__(SCHUR_THREADS) void k_adj_schur(AdjSchurArgs a) {
   }
 }
 
+// e_x = Jc v_c + Jp v_p of position x and its gradients dL/dx = w e_x,
+// dL/dw = -r . e_x (written in creation order).
+__device__ __forceinline__ void adj_gradients(const AdjBackArgs& a, int x, double v0, double v1, double v2) {
+  const double* J = a.J + 24 * (size_t)x;
+  const double* v = a.vc + 9 * (size_t)a.o_cam[x];
+  const double vpp[3] = {v0, v1, v2};
+  double e[2];
+  for (int m = 0; m < 2; ++m) {
+    double s = 0.0;
+    for (int i = 0; i < 9; ++i) s += J[9 * m + i] * v[i];
+    for (int i = 0; i < 3; ++i) s += J[18 + 3 * m + i] * vpp[i];
+    e[m] = s;
+  }
+  const int64_t k = a.o_orig[x];
+  const double w = a.o_w[x];
+  a.dLdx[2 * k] = w * e[0];
+  a.dLdx[2 * k + 1] = w * e[1];
+  if (a.dLdw) a.dLdw[k] = -(a.r[2 * x] * e[0] + a.r[2 * x + 1] * e[1]);
+}
+
 // back-substitution of the point part of v and the gradients:
 //   v_p = V_j^-1 (gL_p - sum_x W_x^T v_c(x)),  e_x = Jc v_c + Jp v_p,
 //   dL/dx = w e_x,  dL/dw = -r . e_x   (written in creation order)
@@ -267,6 +330,7 @@ __global__ __launch_bounds__(CHUNK) void k_adj_backsub(AdjBackArgs a) {
   __shared__ double vp[3][CHUNK];
   const int c = blockIdx.x;
   const int x0 = a.chunk_ptr[c], x1 = a.chunk_ptr[c + 1];
+  if (x1 - x0 > CHUNK) return;  // one long track: k_adj_backsub_long
   const int t = threadIdx.x, x = x0 + t;
   if (x < x1) {
     const double* A = a.A + 78 * (size_t)x;
@@ -302,22 +366,43 @@ __global__ __launch_bounds__(CHUNK) void k_adj_backsub(AdjBackArgs a) {
   }
   __syncthreads();
   if (x < x1) {
-    const double* J = a.J + 24 * (size_t)x;
-    const double* v = a.vc + 9 * (size_t)a.o_cam[x];
     const int jl = a.o_pt[x] - j0;
-    double e[2];
-    for (int m = 0; m < 2; ++m) {
-      double s = 0.0;
-      for (int i = 0; i < 9; ++i) s += J[9 * m + i] * v[i];
-      for (int i = 0; i < 3; ++i) s += J[18 + 3 * m + i] * vp[i][jl];
-      e[m] = s;
-    }
-    const int64_t k = a.o_orig[x];
-    const double w = a.o_w[x];
-    a.dLdx[2 * k] = w * e[0];
-    a.dLdx[2 * k + 1] = w * e[1];
-    if (a.dLdw) a.dLdw[k] = -(a.r[2 * x] * e[0] + a.r[2 * x + 1] * e[1]);
+    adj_gradients(a, x, vp[0][jl], vp[1][jl], vp[2][jl]);
   }
+}
+
+// The chunks of one point seen more than CHUNK times: each thread sums
+// W_x^T v_c over the observations t, t + CHUNK, ...; the threads' partials
+// are added in a fixed order and thread 0 forms v_p.
+__global__ __launch_bounds__(CHUNK) void k_adj_backsub_long(AdjBackArgs a, const int32_t* chunks) {
+  __shared__ double lds[3 * (CHUNK / 64) + 3];
+  const int c = chunks[blockIdx.x];
+  const int x0 = a.chunk_ptr[c], x1 = a.chunk_ptr[c + 1], j = a.chunk_pt[c], t = threadIdx.x;
+  double tk[3] = {0.0, 0.0, 0.0};
+  for (int x = x0 + t; x < x1; x += CHUNK) {
+    const double* A = a.A + 78 * (size_t)x;
+    const double* v = a.vc + 9 * (size_t)a.o_cam[x];
+    for (int q = 0; q < 3; ++q) {
+      double s = 0.0;
+      for (int i = 0; i < 9; ++i) s += A[sym12(i, 9 + q)] * v[i];
+      tk[q] += s;
+    }
+  }
+  block_sum3(tk[0], tk[1], tk[2], lds);
+  double* const vb = lds + 3 * (CHUNK / 64);
+  if (t == 0) {
+    const double* g = a.gL_pts + 3 * (size_t)j;
+    const double s0 = g[0] - tk[0], s1 = g[1] - tk[1], s2 = g[2] - tk[2];
+    const double* m = a.Vinv + 6 * (size_t)j;
+    const double d0 = m[0] * s0 + m[1] * s1 + m[2] * s2;
+    const double d1 = m[1] * s0 + m[3] * s1 + m[4] * s2;
+    const double d2 = m[2] * s0 + m[4] * s1 + m[5] * s2;
+    double* o = a.vp + 3 * (size_t)j;
+    o[0] = d0; o[1] = d1; o[2] = d2;
+    vb[0] = d0; vb[1] = d1; vb[2] = d2;
+  }
+  __syncthreads();
+  for (int x = x0 + t; x < x1; x += CHUNK) adj_gradients(a, x, vb[0], vb[1], vb[2]);
 }
 
 // Stationarity of theta, the premise of the adjoint: per camera and per point
@@ -382,8 +467,9 @@ hipError_t launch_adj_obs(const AdjObsArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_adj_points(const AdjPointArgs& a, int nchunk, hipStream_t s) {
+hipError_t launch_adj_points(const AdjPointArgs& a, int nchunk, LongChunks lc, hipStream_t s) {
   hipLaunchKernelGGL(k_adj_points, dim3(nchunk), dim3(CHUNK), 0, s, a);
+  if (lc.n > 0) hipLaunchKernelGGL(k_adj_points_long, dim3(lc.n), dim3(CHUNK), 0, s, a, lc.idx);
   return hipGetLastError();
 }
 
@@ -397,8 +483,9 @@ hipError_t launch_adj_schur(const AdjSchurArgs& a, int nwg, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_adj_backsub(const AdjBackArgs& a, int nchunk, hipStream_t s) {
+hipError_t launch_adj_backsub(const AdjBackArgs& a, int nchunk, LongChunks lc, hipStream_t s) {
   hipLaunchKernelGGL(k_adj_backsub, dim3(nchunk), dim3(CHUNK), 0, s, a);
+  if (lc.n > 0) hipLaunchKernelGGL(k_adj_backsub_long, dim3(lc.n), dim3(CHUNK), 0, s, a, lc.idx);
   return hipGetLastError();
 }
 

@@ -63,6 +63,11 @@ struct Carver {
 
 size_t elem_bytes(const ba_problem* p) { return p->opt.precision == BA_MIXED ? 4 : 8; }
 
+// the chunks of points seen more than CHUNK times (their own kernels)
+ba::LongChunks long_chunks(const ba_problem* p) {
+  return ba::LongChunks{p->b.long_chunk, (int)p->plan.long_chunk.size()};
+}
+
 void carve(ba_problem* p, char* base, size_t* total) {
   Carver c{base};
   const ba::Plan& P = p->plan;
@@ -78,6 +83,7 @@ void carve(ba_problem* p, char* base, size_t* total) {
   b.pt_ptr = c.take<int32_t>(P.pt_ptr.size());
   b.chunk_ptr = c.take<int32_t>(nch + 1);
   b.chunk_pt = c.take<int32_t>(nch + 1);
+  b.long_chunk = c.take<int32_t>(P.long_chunk.size());
   b.cam_ptr = c.take<int32_t>(nc + 1);
   b.cam_obs = c.take<int32_t>(P.cam_obs.size());
   b.S_ptr = c.take<int32_t>(nc + 1);
@@ -371,7 +377,7 @@ ba_status lm_step_impl(ba_problem* p, ba_step_info* out) {
                b.cams[cur], b.pts[cur], p->opt.huber_delta, b.w, b.J, b.V, b.gp,
                b.part_cost, b.part_gmax, b.rec, p->opt.diag_min, p->opt.diag_max, b.Vinv, b.ep,
                b.dev, b.gsync};
-    PHASE(0, launch_linearize<T>(la, nchunk, s));
+    PHASE(0, launch_linearize<T>(la, nchunk, long_chunks(p), s));
     PHASE(1, launch_reduce_cost(b.part_cost, nchunk, b.dev, s));
   } else {
     // same linearisation, new lambda (after a rejected step): damp again
@@ -464,7 +470,7 @@ ba_status lm_step_impl(ba_problem* p, ba_step_info* out) {
   } else {
     BackArgs ba_{b.chunk_ptr, b.chunk_pt, b.pt_ptr, b.o_cam, b.o_pt, b.J, b.w, b.x, b.gp, b.Vinv,
                  b.pts[cur], b.dp, b.pts[nxt], b.part_pred};
-    PHASE(8, launch_backsub<T>(ba_, nchunk, s));
+    PHASE(8, launch_backsub<T>(ba_, nchunk, long_chunks(p), s));
     RetractArgs ra{P.nc, b.fixed, b.cams[cur], b.x, b.gc, b.cams[nxt], b.part_linc};
     PHASE(9, launch_retract_cameras(ra, p->cam_blocks, s));
     CostArgs co{b.chunk_ptr, b.o_cam, b.o_pt, b.o_xy, b.o_w, b.cams[nxt], b.pts[nxt],
@@ -837,6 +843,7 @@ ba_status bind_workspace(ba_problem* p, void* ws, size_t bytes, void* stream, bo
   HIPCHK(upload(b.pt_ptr, P.pt_ptr, s));
   HIPCHK(upload(b.chunk_ptr, P.chunk_ptr, s));
   HIPCHK(upload(b.chunk_pt, P.chunk_pt, s));
+  HIPCHK(upload(b.long_chunk, P.long_chunk, s));
   HIPCHK(upload(b.cam_ptr, P.cam_ptr, s));
   HIPCHK(upload(b.cam_obs, P.cam_obs, s));
   HIPCHK(upload(b.S_ptr, P.S_ptr, s));
@@ -1176,7 +1183,7 @@ ba_status ba_backward(ba_problem* p, const double* dL_dcams, const double* dL_dp
   }
   AdjPointArgs pa{b.chunk_ptr, b.chunk_pt, b.pt_ptr, b.o_pt, b.adjA, b.Vinv, b.adjY, b.gsync,
                   &b.adj_dev->error};
-  HIPCHK(launch_adj_points(pa, nchunk, s));
+  HIPCHK(launch_adj_points(pa, nchunk, long_chunks(p), s));
   AdjCameraArgs ca{b.cam_ptr, b.cam_obs, b.o_pt, b.fixed, b.adjA, b.adjY, dL_dpts, b.adj_gt,
                    b.adjU, b.bS};
   HIPCHK(launch_adj_camera(ca, P.nc, s));
@@ -1193,7 +1200,7 @@ ba_status ba_backward(ba_problem* p, const double* dL_dcams, const double* dL_dp
   HIPCHK(launch_pcg<double>(ga, P.pcg_grid, P.pcg_resident, false, s));
   AdjBackArgs bb{b.chunk_ptr, b.chunk_pt, b.pt_ptr, b.o_cam, b.o_pt, b.o_orig, b.adjA, b.adjJ,
                  b.r, b.o_w, b.Vinv, b.adj_vc, dL_dpts, b.adj_vp, dL_dobs, dL_dw};
-  HIPCHK(launch_adj_backsub(bb, nchunk, s));
+  HIPCHK(launch_adj_backsub(bb, nchunk, long_chunks(p), s));
   HIPCHK(hipMemcpyAsync(p->hinfo, b.adj_info, sizeof(ba_step_info), hipMemcpyDeviceToHost, s));
   HIPCHK(hipMemcpyAsync(p->hscal, b.adj_dev, sizeof(DevScalars), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));

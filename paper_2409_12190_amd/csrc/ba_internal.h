@@ -44,7 +44,12 @@ constexpr int ITEM_TRANS = 1 << 16;   // PCG item flags: transposed upper block,
 constexpr int ITEM_DIAG = 1 << 17;    //   diagonal block (FP64, indexed by camera)
 constexpr int BARRIER_FANIN = 16;
 constexpr int MAX_BARRIER_GROUPS = 128;
-constexpr int MAX_TRACK = CHUNK;
+// Chunks holding one point seen more than CHUNK times (their own kernels
+// take them; the chunk kernels skip them).
+struct LongChunks {
+  const int32_t* idx;  // device: chunk indices
+  int n;
+};
 constexpr int FINAL_STAGE_MAX = 256;  // workgroups of the first acceptance-reduction stage
 constexpr int SI_STRIDE = 84;         // values per block of the streamed PCG copy of S (81 + zeros:
                                       // 16-byte aligned blocks in FP32)
@@ -63,6 +68,7 @@ struct Plan {
   std::vector<int32_t> pt_ptr;       // [np+1] position range of each point
   std::vector<int32_t> chunk_ptr;    // [nchunk+1] position range of each chunk
   std::vector<int32_t> chunk_pt;     // [nchunk+1] point range of each chunk
+  std::vector<int32_t> long_chunk;   // chunks with more than CHUNK positions (one point each)
   std::vector<int32_t> cam_ptr;      // [nc+1]
   std::vector<int32_t> cam_obs;      // positions grouped by camera
   std::vector<int32_t> S_ptr, S_col; // upper block pattern, diagonal first in each row
@@ -161,7 +167,7 @@ struct GridSync {
 // Device pointers carved out of the caller's workspace.
 struct Buffers {
   // plan
-  int32_t *o_cam, *o_pt, *pt_ptr, *chunk_ptr, *chunk_pt, *cam_ptr, *cam_obs;
+  int32_t *o_cam, *o_pt, *pt_ptr, *chunk_ptr, *chunk_pt, *cam_ptr, *cam_obs, *long_chunk;
   int32_t *S_ptr, *S_col, *T_ptr, *T_blk, *T_src;
   int32_t *pair_x, *pair_y, *slot_blk, *slot_pb, *slot_pe, *slot_lead, *blk_row, *stab, *swptr;
   int32_t *pcg_row, *item_ptr, *item_e, *item_code, *ucol_ptr, *ucol;

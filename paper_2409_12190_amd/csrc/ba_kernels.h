@@ -147,7 +147,7 @@ struct PermArgs {
   int src_stride, dst_stride, width;
 };
 
-template <typename T> hipError_t launch_linearize(const LinArgs&, int nchunk, hipStream_t);
+template <typename T> hipError_t launch_linearize(const LinArgs&, int nchunk, LongChunks, hipStream_t);
 hipError_t launch_permute_rows(const PermArgs&, hipStream_t);
 hipError_t launch_reduce_cost(const double* part, int n, DevScalars* dev, hipStream_t);
 hipError_t launch_damp_points(const DampArgs&, hipStream_t);
@@ -157,7 +157,7 @@ template <typename T> hipError_t launch_camera_finish(const CamFinishArgs&, int 
 template <typename T> int pcg_max_grid(bool resident, bool pipelined, bool stream = false);
 template <typename T>
 hipError_t launch_pcg(const PcgArgs&, int grid, bool resident, bool pipelined, hipStream_t);
-template <typename T> hipError_t launch_backsub(const BackArgs&, int nchunk, hipStream_t);
+template <typename T> hipError_t launch_backsub(const BackArgs&, int nchunk, LongChunks, hipStream_t);
 hipError_t launch_retract_cameras(const RetractArgs&, int nblk, hipStream_t);
 hipError_t launch_candidate_cost(const CostArgs&, int nchunk, hipStream_t);
 hipError_t launch_finalize(FinalArgs, hipStream_t);

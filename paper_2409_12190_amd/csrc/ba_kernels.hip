@@ -188,6 +188,134 @@ __device__ __forceinline__ void store_rec(double* rec, double r0, double r1, dou
 // factor Q_x and e_x.  One workgroup per point-aligned chunk; segmented sums
 // in LDS, fixed order.  Every observation row and record is written whole.
 // ---------------------------------------------------------------------------
+// Observation x of the linearisation: residual, robust weight and cost,
+// Jacobian row (written with w) and its 9 terms of the point sums (upper V_j,
+// then gp_j).
+template <typename T>
+__device__ __forceinline__ void lin_observation(const LinArgs& a, int x, double (&Jp)[2][3], double& rx,
+                                                double& ry, double& w, double& cost, double (&sv)[9]) {
+  const int ci = a.o_cam[x];
+  const int pj = a.o_pt[x];
+  const Camera cam = load_camera(a.cams + 10 * (size_t)ci);
+  const double* P = a.pts + 3 * (size_t)pj;
+  double Jc[2][9];
+  const Proj pr = project_jac(cam, v3(P[0], P[1], P[2]), Jc, Jp);
+  rx = pr.px - a.o_xy[2 * (size_t)x];
+  ry = pr.py - a.o_xy[2 * (size_t)x + 1];
+  double drho;
+  const double rho = robust_rho(rx * rx + ry * ry, a.huber, &drho);
+  const double om = a.o_w[x];
+  w = om * drho;
+  cost = 0.5 * om * rho;
+  const uint8_t fx = a.fixed[ci];
+  if (fx & FIXED_CAMERA) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int m = 0; m < 9; ++m) Jc[i][m] = 0.0;
+  } else if (fx & FIXED_INTRINSICS) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int m = 6; m < 9; ++m) Jc[i][m] = 0.0;
+  }
+  a.w[x] = w;
+  store_row(reinterpret_cast<T*>(a.J) + (size_t)x * NJ, Jc, Jp);
+  sv[0] = w * (Jp[0][0] * Jp[0][0] + Jp[1][0] * Jp[1][0]);
+  sv[1] = w * (Jp[0][0] * Jp[0][1] + Jp[1][0] * Jp[1][1]);
+  sv[2] = w * (Jp[0][0] * Jp[0][2] + Jp[1][0] * Jp[1][2]);
+  sv[3] = w * (Jp[0][1] * Jp[0][1] + Jp[1][1] * Jp[1][1]);
+  sv[4] = w * (Jp[0][1] * Jp[0][2] + Jp[1][1] * Jp[1][2]);
+  sv[5] = w * (Jp[0][2] * Jp[0][2] + Jp[1][2] * Jp[1][2]);
+  sv[6] = w * (Jp[0][0] * rx + Jp[1][0] * ry);
+  sv[7] = w * (Jp[0][1] * rx + Jp[1][1] * ry);
+  sv[8] = w * (Jp[0][2] * rx + Jp[1][2] * ry);
+}
+
+// The point-elimination factors of observation x from Jp as stored
+// (precision T), like every other reader of the row: both sides of the Schur
+// pair product and the right-hand side then use one rounding of Jp, which
+// keeps the reduced system symmetric.
+template <typename T>
+__device__ __forceinline__ void lin_factors(const LinArgs& a, int x, const double (&Jp)[2][3], double rx,
+                                            double ry, double w, const double (&pv)[6], const double (&pe)[3]) {
+  double Jq[2][3], Q[6], e[2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int m = 0; m < 3; ++m) Jq[i][m] = (double)(T)Jp[i][m];
+  point_factors(Jq, w, pv, pe, Q, e);
+  store_q(reinterpret_cast<T*>(a.J) + (size_t)x * NJ, Q, w);
+  store_rec(a.rec + 8 * (size_t)x, rx, ry, w, e[0], e[1]);
+}
+
+// A chunk holding one point seen more than CHUNK times: each thread takes
+// the point's observations t, t + CHUNK, ... and sums their terms in that
+// order; the threads' partials are then added in a fixed order.  The
+// observations' Jp, r and w for the factors are read back from the row and
+// the weight array.
+// red: CHUNK / 64 doubles; lds: 3 CHUNK / 64 + 9 doubles (reductions, then
+// the point's factors handed to every thread).
+template <typename T>
+__device__ void linearize_long_track(const LinArgs& a, int c, int x0, int x1, double* red, double* lds) {
+  double* const bc = lds + 3 * (CHUNK / 64);
+  const int t = threadIdx.x, j = a.chunk_pt[c];
+  double cost = 0.0, sv[9];
+#pragma unroll
+  for (int q = 0; q < 9; ++q) sv[q] = 0.0;
+  for (int x = x0 + t; x < x1; x += CHUNK) {
+    double Jp[2][3], rx, ry, w, cx, so[9];
+    lin_observation<T>(a, x, Jp, rx, ry, w, cx, so);
+    a.rec[8 * (size_t)x] = rx;
+    a.rec[8 * (size_t)x + 1] = ry;
+    cost += cx;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) sv[q] += so[q];
+  }
+  for (int q = 0; q < 9; q += 3) block_sum3(sv[q], sv[q + 1], sv[q + 2], lds);
+  double gmax = 0.0;
+  if (t == 0) {
+#pragma unroll
+    for (int q = 0; q < 6; ++q) a.V[6 * (size_t)j + q] = sv[q];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) a.gp[3 * (size_t)j + q] = sv[6 + q];
+    gmax = fmax(fabs(sv[6]), fmax(fabs(sv[7]), fabs(sv[8])));
+    double vi[6], ep[3];
+    damp_point(sv, sv + 6, a.dev->lambda, a.dmin, a.dmax, vi, ep, &a.dev->error);
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+      a.Vinv[6 * (size_t)j + q] = vi[q];
+      bc[q] = vi[q];
+    }
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      a.ep[3 * (size_t)j + q] = ep[q];
+      bc[6 + q] = ep[q];
+    }
+  }
+  __syncthreads();
+  double pv[6], pe[3];
+#pragma unroll
+  for (int q = 0; q < 6; ++q) pv[q] = bc[q];
+#pragma unroll
+  for (int q = 0; q < 3; ++q) pe[q] = bc[6 + q];
+  const T* Jall = reinterpret_cast<const T*>(a.J);
+  for (int x = x0 + t; x < x1; x += CHUNK) {
+    double Jp[2][3];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int m = 0; m < 3; ++m) Jp[i][m] = (double)Jall[(size_t)x * NJ + JP + 3 * i + m];
+    lin_factors<T>(a, x, Jp, a.rec[8 * (size_t)x], a.rec[8 * (size_t)x + 1], a.w[x], pv, pe);
+  }
+  const double tot = block_sum(cost, red);
+  const double gm = block_max(gmax, red);
+  if (t == 0) {
+    a.part_cost[c] = tot;
+    a.part_gmax[c] = gm;
+  }
+}
+
 template <typename T>
 __global__ __launch_bounds__(CHUNK) void k_linearize(LinArgs a) {
   __shared__ double sh[9][CHUNK];
@@ -197,47 +325,17 @@ __global__ __launch_bounds__(CHUNK) void k_linearize(LinArgs a) {
   const int t = threadIdx.x;
   const int x = x0 + t;
   if (c == 0) reset_grid_sync(a.gs, t);
+  if (x1 - x0 > CHUNK) return;  // one long track: k_linearize_long
   double cost = 0.0;
   double Jp[2][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
   double rx = 0.0, ry = 0.0, w = 0.0;
   int pj = 0;
   if (x < x1) {
-    const int ci = a.o_cam[x];
     pj = a.o_pt[x];
-    const Camera cam = load_camera(a.cams + 10 * (size_t)ci);
-    const double* P = a.pts + 3 * (size_t)pj;
-    double Jc[2][9];
-    const Proj pr = project_jac(cam, v3(P[0], P[1], P[2]), Jc, Jp);
-    rx = pr.px - a.o_xy[2 * (size_t)x];
-    ry = pr.py - a.o_xy[2 * (size_t)x + 1];
-    double drho;
-    const double rho = robust_rho(rx * rx + ry * ry, a.huber, &drho);
-    const double om = a.o_w[x];
-    w = om * drho;
-    cost = 0.5 * om * rho;
-    const uint8_t fx = a.fixed[ci];
-    if (fx & FIXED_CAMERA) {
+    double sv[9];
+    lin_observation<T>(a, x, Jp, rx, ry, w, cost, sv);
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int m = 0; m < 9; ++m) Jc[i][m] = 0.0;
-    } else if (fx & FIXED_INTRINSICS) {
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int m = 6; m < 9; ++m) Jc[i][m] = 0.0;
-    }
-    a.w[x] = w;
-    store_row(reinterpret_cast<T*>(a.J) + (size_t)x * NJ, Jc, Jp);
-    sh[0][t] = w * (Jp[0][0] * Jp[0][0] + Jp[1][0] * Jp[1][0]);
-    sh[1][t] = w * (Jp[0][0] * Jp[0][1] + Jp[1][0] * Jp[1][1]);
-    sh[2][t] = w * (Jp[0][0] * Jp[0][2] + Jp[1][0] * Jp[1][2]);
-    sh[3][t] = w * (Jp[0][1] * Jp[0][1] + Jp[1][1] * Jp[1][1]);
-    sh[4][t] = w * (Jp[0][1] * Jp[0][2] + Jp[1][1] * Jp[1][2]);
-    sh[5][t] = w * (Jp[0][2] * Jp[0][2] + Jp[1][2] * Jp[1][2]);
-    sh[6][t] = w * (Jp[0][0] * rx + Jp[1][0] * ry);
-    sh[7][t] = w * (Jp[0][1] * rx + Jp[1][1] * ry);
-    sh[8][t] = w * (Jp[0][2] * rx + Jp[1][2] * ry);
+    for (int q = 0; q < 9; ++q) sh[q][t] = sv[q];
   }
   __syncthreads();
   double gmax = 0.0;
@@ -275,22 +373,12 @@ __global__ __launch_bounds__(CHUNK) void k_linearize(LinArgs a) {
   __syncthreads();
   if (x < x1) {
     const int k = pj - j0;
-    double pv[6], pe[3], Q[6], e[2];
+    double pv[6], pe[3];
 #pragma unroll
     for (int q = 0; q < 6; ++q) pv[q] = sh[q][k];
 #pragma unroll
     for (int q = 0; q < 3; ++q) pe[q] = sh[6 + q][k];
-    // from Jp as stored (precision T), like every other reader of the row:
-    // both sides of the Schur pair product and the right-hand side then use
-    // one rounding of Jp, which keeps the reduced system symmetric
-    double Jq[2][3];
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-      for (int m = 0; m < 3; ++m) Jq[i][m] = (double)(T)Jp[i][m];
-    point_factors(Jq, w, pv, pe, Q, e);
-    store_q(reinterpret_cast<T*>(a.J) + (size_t)x * NJ, Q, w);
-    store_rec(a.rec + 8 * (size_t)x, rx, ry, w, e[0], e[1]);
+    lin_factors<T>(a, x, Jp, rx, ry, w, pv, pe);
   }
   const double tot = block_sum(cost, red);
   const double gm = block_max(gmax, red);
@@ -298,6 +386,15 @@ __global__ __launch_bounds__(CHUNK) void k_linearize(LinArgs a) {
     a.part_cost[c] = tot;
     a.part_gmax[c] = gm;
   }
+}
+
+// The chunks of one point seen more than CHUNK times (one workgroup each).
+template <typename T>
+__global__ __launch_bounds__(CHUNK) void k_linearize_long(LinArgs a, const int32_t* chunks) {
+  __shared__ double red[CHUNK / 64];
+  __shared__ double lds[3 * (CHUNK / 64) + 9];
+  const int c = chunks[blockIdx.x];
+  linearize_long_track<T>(a, c, a.chunk_ptr[c], a.chunk_ptr[c + 1], red, lds);
 }
 
 // F = sum of the chunk partials (fixed order), and the gradient max over points.
@@ -722,6 +819,7 @@ __global__ __launch_bounds__(CHUNK) void k_backsub(BackArgs a) {
   __shared__ double red[CHUNK / 64];
   const int c = blockIdx.x;
   const int x0 = a.chunk_ptr[c], x1 = a.chunk_ptr[c + 1];
+  if (x1 - x0 > CHUNK) return;  // one long track: k_backsub_long
   const int t = threadIdx.x, x = x0 + t;
   const T* __restrict__ Jall = reinterpret_cast<const T*>(a.J);
   double Jc[2][9], Jp[2][3], w = 0.0, ec0 = 0.0, ec1 = 0.0;
@@ -778,6 +876,73 @@ __global__ __launch_bounds__(CHUNK) void k_backsub(BackArgs a) {
   }
 }
 
+// The chunks of one point seen more than CHUNK times: each thread takes the
+// point's observations t, t + CHUNK, ... (sums in that order, then over the
+// threads in a fixed order); thread 0 forms dp.
+template <typename T>
+__global__ __launch_bounds__(CHUNK) void k_backsub_long(BackArgs a, const int32_t* chunks) {
+  __shared__ double red[CHUNK / 64];
+  __shared__ double lds[3 * (CHUNK / 64) + 3];
+  const int c = chunks[blockIdx.x];
+  const int x0 = a.chunk_ptr[c], x1 = a.chunk_ptr[c + 1], j = a.chunk_pt[c], t = threadIdx.x;
+  const T* __restrict__ Jall = reinterpret_cast<const T*>(a.J);
+  auto cam_term = [&](int x, double (&Jp)[2][3], double& w, double& ec0, double& ec1) {
+    double Jc[2][9];
+    load_J(Jall + (size_t)x * NJ, Jc, Jp);
+    w = a.w[x];
+    const double* dc = a.dc + 9 * (size_t)a.o_cam[x];
+    ec0 = 0.0;
+    ec1 = 0.0;
+#pragma unroll
+    for (int m = 0; m < 9; ++m) {
+      ec0 += Jc[0][m] * dc[m];
+      ec1 += Jc[1][m] * dc[m];
+    }
+  };
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+  for (int x = x0 + t; x < x1; x += CHUNK) {
+    double Jp[2][3], w, ec0, ec1;
+    cam_term(x, Jp, w, ec0, ec1);
+    s0 += w * (Jp[0][0] * ec0 + Jp[1][0] * ec1);
+    s1 += w * (Jp[0][1] * ec0 + Jp[1][1] * ec1);
+    s2 += w * (Jp[0][2] * ec0 + Jp[1][2] * ec1);
+  }
+  block_sum3(s0, s1, s2, lds);
+  double* const dpl = lds + 3 * (CHUNK / 64);
+  double lin = 0.0;
+  if (t == 0) {
+    const double* g = a.gp + 3 * (size_t)j;
+    const double r0 = -g[0] - s0, r1 = -g[1] - s1, r2 = -g[2] - s2;
+    const double* vi = a.Vinv + 6 * (size_t)j;
+    const double d0 = vi[0] * r0 + vi[1] * r1 + vi[2] * r2;
+    const double d1 = vi[1] * r0 + vi[3] * r1 + vi[4] * r2;
+    const double d2 = vi[2] * r0 + vi[4] * r1 + vi[5] * r2;
+    double* dp = a.dp + 3 * (size_t)j;
+    dp[0] = d0; dp[1] = d1; dp[2] = d2;
+    const double* P = a.pts + 3 * (size_t)j;
+    double* Pn = a.pts_new + 3 * (size_t)j;
+    Pn[0] = P[0] + d0; Pn[1] = P[1] + d1; Pn[2] = P[2] + d2;
+    lin = g[0] * d0 + g[1] * d1 + g[2] * d2;
+    dpl[0] = d0; dpl[1] = d1; dpl[2] = d2;
+  }
+  __syncthreads();
+  const double d0 = dpl[0], d1 = dpl[1], d2 = dpl[2];
+  double quad = 0.0;
+  for (int x = x0 + t; x < x1; x += CHUNK) {
+    double Jp[2][3], w, ec0, ec1;
+    cam_term(x, Jp, w, ec0, ec1);
+    const double e0 = ec0 + Jp[0][0] * d0 + Jp[0][1] * d1 + Jp[0][2] * d2;
+    const double e1 = ec1 + Jp[1][0] * d0 + Jp[1][1] * d1 + Jp[1][2] * d2;
+    quad += w * (e0 * e0 + e1 * e1);
+  }
+  const double ql = block_sum(quad, red);
+  const double ll = block_sum(lin, red);
+  if (t == 0) {
+    a.part_pred[2 * (size_t)c] = ql;
+    a.part_pred[2 * (size_t)c + 1] = ll;
+  }
+}
+
 // candidate cameras theta' = Exp(dc) theta (fixed cameras copied) and the
 // partials of gc . dc (one thread per camera).
 __global__ __launch_bounds__(256) void k_retract_cameras(RetractArgs a) {
@@ -804,16 +969,16 @@ __global__ __launch_bounds__(256) void k_retract_cameras(RetractArgs a) {
 __global__ __launch_bounds__(CHUNK) void k_candidate_cost(CostArgs a) {
   __shared__ double red[CHUNK / 64];
   const int c = blockIdx.x;
-  const int x = a.chunk_ptr[c] + threadIdx.x;
   double cost = 0.0;
-  if (x < a.chunk_ptr[c + 1]) {
+  // (more than one pass only in the chunk of a point seen more than CHUNK times)
+  for (int x = a.chunk_ptr[c] + threadIdx.x; x < a.chunk_ptr[c + 1]; x += CHUNK) {
     const Camera cam = load_camera(a.cams + 10 * (size_t)a.o_cam[x]);
     const double* P = a.pts + 3 * (size_t)a.o_pt[x];
     const Proj pr = project(cam, v3(P[0], P[1], P[2]));
     const double rx = pr.px - a.o_xy[2 * (size_t)x], ry = pr.py - a.o_xy[2 * (size_t)x + 1];
     double drho;
     const double rho = robust_rho(rx * rx + ry * ry, a.huber, &drho);
-    cost = 0.5 * a.o_w[x] * rho;
+    cost += 0.5 * a.o_w[x] * rho;
   }
   const double s = block_sum(cost, red);
   if (threadIdx.x == 0) a.part_cost_new[c] = s;
@@ -912,12 +1077,13 @@ __global__ __launch_bounds__(256) void k_set_observations(ObsArgs a) {
 // ---------------------------------------------------------------------------
 
 template <typename T>
-hipError_t launch_linearize(const LinArgs& a, int nchunk, hipStream_t s) {
+hipError_t launch_linearize(const LinArgs& a, int nchunk, LongChunks lc, hipStream_t s) {
   hipLaunchKernelGGL(k_linearize<T>, dim3(nchunk), dim3(CHUNK), 0, s, a);
+  if (lc.n > 0) hipLaunchKernelGGL(k_linearize_long<T>, dim3(lc.n), dim3(CHUNK), 0, s, a, lc.idx);
   return hipGetLastError();
 }
-template hipError_t launch_linearize<float>(const LinArgs&, int, hipStream_t);
-template hipError_t launch_linearize<double>(const LinArgs&, int, hipStream_t);
+template hipError_t launch_linearize<float>(const LinArgs&, int, LongChunks, hipStream_t);
+template hipError_t launch_linearize<double>(const LinArgs&, int, LongChunks, hipStream_t);
 
 hipError_t launch_reduce_cost(const double* part, int n, DevScalars* dev, hipStream_t s) {
   hipLaunchKernelGGL(k_reduce_cost, dim3(1), dim3(1024), 0, s, part, n, dev);
@@ -956,12 +1122,13 @@ template hipError_t launch_camera_finish<float>(const CamFinishArgs&, int, hipSt
 template hipError_t launch_camera_finish<double>(const CamFinishArgs&, int, hipStream_t);
 
 template <typename T>
-hipError_t launch_backsub(const BackArgs& a, int nchunk, hipStream_t s) {
+hipError_t launch_backsub(const BackArgs& a, int nchunk, LongChunks lc, hipStream_t s) {
   hipLaunchKernelGGL(k_backsub<T>, dim3(nchunk), dim3(CHUNK), 0, s, a);
+  if (lc.n > 0) hipLaunchKernelGGL(k_backsub_long<T>, dim3(lc.n), dim3(CHUNK), 0, s, a, lc.idx);
   return hipGetLastError();
 }
-template hipError_t launch_backsub<float>(const BackArgs&, int, hipStream_t);
-template hipError_t launch_backsub<double>(const BackArgs&, int, hipStream_t);
+template hipError_t launch_backsub<float>(const BackArgs&, int, LongChunks, hipStream_t);
+template hipError_t launch_backsub<double>(const BackArgs&, int, LongChunks, hipStream_t);
 
 hipError_t launch_retract_cameras(const RetractArgs& a, int nblk, hipStream_t s) {
   hipLaunchKernelGGL(k_retract_cameras, dim3(nblk), dim3(256), 0, s, a);

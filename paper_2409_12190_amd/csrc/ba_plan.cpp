@@ -8,7 +8,8 @@
 //     original index), so every point's track is a contiguous, camera-sorted
 //     run;
 //   - point-aligned chunks of at most CHUNK positions and at most CHUNK
-//     points (one workgroup each);
+//     points (one workgroup each), or of one point seen more than CHUNK
+//     times (listed in long_chunk);
 //   - positions grouped by camera;
 //   - the upper block pattern of the reduced camera matrix (camera a <= b
 //     share a point), diagonal first in each row, plus its transpose lists;
@@ -135,11 +136,6 @@ std::string build_plan(int32_t nc, int32_t np, int64_t no, const int32_t* cidx, 
   }
   p.max_track = 0;
   for (int32_t j = 0; j < np; ++j) p.max_track = std::max(p.max_track, p.pt_ptr[j + 1] - p.pt_ptr[j]);
-  if (p.max_track > MAX_TRACK) {
-    std::snprintf(msg, sizeof msg, "a point is observed %d times; at most %d are supported",
-                  p.max_track, MAX_TRACK);
-    return msg;
-  }
 
   // point-aligned chunks
   p.chunk_ptr.assign(1, 0);
@@ -148,8 +144,9 @@ std::string build_plan(int32_t nc, int32_t np, int64_t no, const int32_t* cidx, 
     int32_t start = 0;
     for (int32_t j = 0; j < np; ++j) {
       // at most CHUNK positions and at most CHUNK points (unobserved points
-      // have no positions) per chunk
-      if (p.pt_ptr[j + 1] - start > CHUNK || j - p.chunk_pt.back() >= CHUNK) {
+      // have no positions) per chunk, except that a point seen more than
+      // CHUNK times gets a chunk of its own
+      if (j > p.chunk_pt.back() && (p.pt_ptr[j + 1] - start > CHUNK || j - p.chunk_pt.back() >= CHUNK)) {
         p.chunk_ptr.push_back(p.pt_ptr[j]);
         p.chunk_pt.push_back(j);
         start = p.pt_ptr[j];
@@ -157,6 +154,9 @@ std::string build_plan(int32_t nc, int32_t np, int64_t no, const int32_t* cidx, 
     }
     p.chunk_ptr.push_back((int32_t)no);
     p.chunk_pt.push_back(np);
+    p.long_chunk.clear();
+    for (size_t c = 0; c + 1 < p.chunk_ptr.size(); ++c)
+      if (p.chunk_ptr[c + 1] - p.chunk_ptr[c] > CHUNK) p.long_chunk.push_back((int32_t)c);
   }
 
   // positions grouped by camera (ascending position inside a camera)

@@ -382,14 +382,16 @@ def _loop_closures(rng, cams, X, cam_idx, pt_idx, per_lap, n_laps, frac, rounds=
 
 def make_scene(cfg: int, seed: int = 0, noise_px: float = 1.0, perturb: bool = True,
                n_cams: Optional[int] = None, n_pts: Optional[int] = None,
-               per_lap: Optional[int] = None) -> Scene:
+               per_lap: Optional[int] = None, long_track: int = 0) -> Scene:
     """Build workload `cfg` with generator seed [cfg, seed].
 
     noise_px: standard deviation of the pixel noise per coordinate (0 gives
     noise-free observations).  perturb=False starts at the ground truth.
     n_cams / n_pts override the sizes (for small tests of a configuration's
     structure); per_lap sets the cameras per lap of the laps workload
-    (default: 1000, or all cameras when fewer)."""
+    (default: 1000, or all cameras when fewer).  long_track (ring workload
+    only): point 0 is seen by that many distinct cameras (every ring camera
+    sees the whole point cube)."""
     rng = np.random.default_rng([cfg, seed])
     obs_w = None
     huber = 0.0
@@ -397,6 +399,13 @@ def make_scene(cfg: int, seed: int = 0, noise_px: float = 1.0, perturb: bool = T
     if cfg == 0:
         nc, npt = n_cams or 16, n_pts or 1024
         cams, pts, cam_idx, pt_idx = _ring(rng, nc, npt, per_pt=min(4, nc))
+        if long_track:
+            if long_track > nc:
+                raise ValueError("long_track exceeds the number of cameras")
+            keep = pt_idx != 0
+            lt = np.sort(rng.choice(nc, size=long_track, replace=False)).astype(np.int32)
+            cam_idx = np.concatenate([lt, cam_idx[keep]]).astype(np.int32)
+            pt_idx = np.concatenate([np.zeros(long_track, np.int32), pt_idx[keep]]).astype(np.int32)
         iters = 10
     elif cfg == 1:
         nc, npt = n_cams or 1000, n_pts or 200_000

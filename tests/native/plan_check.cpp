@@ -73,6 +73,29 @@ int main(int argc, char** argv) {
     std::printf("plan error: %s\n", err.c_str());
     return 1;
   }
+  {
+    // chunks: cover every position and point in order, none empty when it
+    // has points with positions, at most CHUNK positions and CHUNK points
+    // each, or one point seen more than CHUNK times (and then listed)
+    const size_t nch = p.chunk_ptr.size() - 1;
+    CHECK(p.chunk_ptr.size() == p.chunk_pt.size() && p.chunk_ptr.front() == 0 && p.chunk_pt.front() == 0 &&
+              p.chunk_ptr.back() == h[2] && p.chunk_pt.back() == h[1],
+          "chunks cover the positions and points");
+    size_t nlong = 0;
+    for (size_t c = 0; c < nch; ++c) {
+      const int32_t x0 = p.chunk_ptr[c], x1 = p.chunk_ptr[c + 1], j0 = p.chunk_pt[c], j1 = p.chunk_pt[c + 1];
+      CHECK(x0 <= x1 && j0 < j1, "chunks ascend and hold at least one point");
+      CHECK(p.pt_ptr[j0] == x0 && p.pt_ptr[j1] == x1, "chunks are point-aligned");
+      if (x1 - x0 > CHUNK) {
+        CHECK(j1 - j0 == 1, "a chunk beyond CHUNK positions holds one point");
+        CHECK(nlong < p.long_chunk.size() && p.long_chunk[nlong] == (int32_t)c, "long chunks listed in order");
+        ++nlong;
+      } else {
+        CHECK(j1 - j0 <= CHUNK, "at most CHUNK points per chunk");
+      }
+    }
+    CHECK(nlong == p.long_chunk.size(), "only long chunks listed");
+  }
   if (p.pcg_resident) {
     CHECK(p.sgrid == 0 && p.srow.empty() && p.blk_pos.empty(), "resident plans carry no streamed decomposition");
     std::printf("ok resident\n");

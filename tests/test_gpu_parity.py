@@ -331,6 +331,60 @@ def test_ragged_tracks_and_chunks():
     g, o, out = run_parity(s, 4)
 
 
+def long_track_scene():
+    """The ring workload with 700 cameras and 3,000 points, point 0 seen by
+    600 cameras: more observations than a chunk of 256 holds."""
+    return make_scene(0, n_cams=700, n_pts=3000, long_track=600)
+
+
+def test_point_seen_more_than_a_chunk_matches_oracle():
+    """The long track runs through its own kernels (linearisation with the
+    point elimination, back-substitution; the candidate cost strides over
+    it): its point block, gradient and step match the oracle element by
+    element, and the FP64 LM iterations match."""
+    s = long_track_scene()
+    g, o = gpu(s, cg_variant=B.BA_CG_STANDARD), orc(s)
+    g.set_cg(0.0, 15)
+    info_g = g.lm_step()
+    r, w, Jc, Jp, F = o.linearization()                   # the oracle at the step's start
+    close(g.export(B.BA_X_RESIDUAL), r, 1e-12, "r")
+    close(g.export(B.BA_X_WEIGHT), w, 1e-12, "w")
+    assert abs(info_g["cost_before"] - F) <= 1e-12 * F
+    U, V, gc, gp = o.normal()
+    Vg, gpg = g.export(B.BA_X_V), g.export(B.BA_X_GRAD_P)
+    close(Vg, V, 1e-12, "V")
+    close(Vg[0], V[0], 1e-12, "V of the long track")
+    close(gpg, gp, 1e-11, "gp")
+    close(gpg[0], gp[0], 1e-11, "gp of the long track")
+    close(g.export(B.BA_X_GRAD_C), gc, 1e-11, "gc")
+    info_o = o.lm_step(rtol=0.0, maxiter=15)
+    ptr, col, S, bS = o.schur()
+    close(g.export(B.BA_X_S), S, 1e-10, "S")
+    close(g.export(B.BA_X_BS), bS, 1e-10, "bS")
+    dc, dp, _ = o.step()
+    dpg = g.export(B.BA_X_DP)
+    close(g.export(B.BA_X_DC), dc, 1e-8, "dc")
+    close(dpg, dp, 1e-8, "dp")
+    close(dpg[0], dp[0], 1e-8, "dp of the long track")
+    assert abs(info_g["pred"] - info_o["pred"]) <= 1e-9 * abs(info_o["pred"])
+    assert abs(info_g["cost_after"] - info_o["cost_after"]) <= 1e-9 * info_o["cost_after"]
+    run_parity(s, 6)
+
+
+def test_point_seen_more_than_a_chunk_mixed_tracks_oracle():
+    """The mixed form on the long-track scene: the first three iterations
+    within 1e-4 relative cost of the FP64 oracle (the bound of the mixed
+    form's parity test), every accepted step lowering the cost."""
+    s = long_track_scene()
+    g, o = gpu(s, precision=B.BA_MIXED), orc(s)
+    for it in range(3):
+        io, ig = o.lm_step(), g.lm_step()
+        assert ig["status"] == 0
+        assert abs(ig["cost_before"] - io["cost_before"]) <= 1e-4 * io["cost_before"], it
+        if ig["accepted"]:
+            assert ig["cost_after"] < ig["cost_before"]
+
+
 def test_rejects_bad_observations():
     s = make_scene(0)
     obs = s.obs.copy()

@@ -101,3 +101,27 @@ def test_clique_beyond_column_capacity_is_not_streamed(checker, tmp_path):
     rc, out = run_check(checker, tmp_path, cams, pts, 600, 30000)
     assert rc == 0, out
     assert out.startswith("ok unstreamed"), out
+
+
+def test_long_tracks_get_chunks_of_their_own(checker, tmp_path):
+    """Points seen more than a chunk's 256 observations: the first point, two
+    consecutive points and a point after an unobserved one each get one
+    chunk, listed as long; no chunk is empty of points (checked by the
+    program with the other chunk invariants)."""
+    n_cams = 700
+    rng = np.random.default_rng(3)
+    cams, pts = [], []
+    lengths = {0: 600, 1: 300, 2: 257, 4: 400}
+    for j in range(40):
+        k = lengths.get(j, 0 if j == 3 else int(rng.integers(2, 20)))
+        cams.append(np.sort(rng.choice(n_cams, size=k, replace=False)))
+        pts.append(np.full(k, j))
+    cam, pt = np.concatenate(cams), np.concatenate(pts)
+    rc, out = run_check(checker, tmp_path, cam, pt, n_cams, 40)
+    assert rc == 0, out
+
+
+def test_long_track_of_the_ring_workload(checker, tmp_path):
+    s = make_scene(0, n_cams=700, n_pts=3000, long_track=600)
+    rc, out = run_check(checker, tmp_path, s.cam_idx, s.pt_idx, s.n_cams, s.n_pts)
+    assert rc == 0, out
