@@ -914,7 +914,21 @@ constexpr int STREAM_GROUPS_MAX = StreamShape<float>::groups;
 // a wavefront's staging area holds every piece its lanes move, so that the
 // LDS stores need no lane-dependent branch (such a branch inside the
 // lockstep loop lets the compiler restructure it into a divergent nest)
-constexpr int STREAM_WAVE_BYTES = STREAM_LOADS * 64 * 16;
+// With FP32 blocks the staged blocks of groups 4 and 5 start one 16-byte
+// piece later than packed: the lanes of a wavefront half then read the rows
+// and columns of their groups' blocks with fewer LDS bank conflicts (3 passes
+// per read instead of 4, for 32 banks of 4 bytes).  One spare piece per
+// wavefront holds the shift of the lane pieces past the blocks.
+constexpr int STREAM_SKEW_GROUP = 4;
+constexpr int STREAM_WAVE_BYTES = (STREAM_LOADS * 64 + 1) * 16;
+template <typename T>
+__device__ __forceinline__ int stream_piece(int p) {
+  return sizeof(T) == 4 && p >= STREAM_SKEW_GROUP * (SI_STRIDE * 4 / 16) ? p + 1 : p;
+}
+template <typename T>
+__device__ __forceinline__ int stream_group_offset(int gl) {
+  return gl * SI_STRIDE + (sizeof(T) == 4 && gl >= STREAM_SKEW_GROUP ? 4 : 0);
+}
 
 // wait until the exchange flag at f (one sender, one product) is raised
 __device__ __forceinline__ bool poll_flag(const double* f, int* error) {
@@ -990,7 +1004,8 @@ __device__ __forceinline__ bool stream_spmv(const PcgArgs& a, const StreamCtx& c
     auto fetch = [&](f32x4_t (&buf)[STREAM_LOADS], int k) { stream_fetch<T>(a, c, buf, k); };
     auto stage = [&](const f32x4_t (&buf)[STREAM_LOADS]) {
 #pragma unroll
-      for (int j = 0; j < STREAM_LOADS; ++j) *reinterpret_cast<f32x4_t*>(wst + (64 * j + lane) * 16) = buf[j];
+      for (int j = 0; j < STREAM_LOADS; ++j)
+        *reinterpret_cast<f32x4_t*>(wst + stream_piece<T>(64 * j + lane) * 16) = buf[j];
     };
     double acc = 0.0;
     int cur = -1, row = 0;
@@ -1004,7 +1019,7 @@ __device__ __forceinline__ bool stream_spmv(const PcgArgs& a, const StreamCtx& c
           acc = 0.0;
           cur = row;
         }
-        const T* blk = reinterpret_cast<const T*>(wst + gl * SI_STRIDE * sizeof(T));
+        const T* blk = reinterpret_cast<const T*>(wst + stream_group_offset<T>(gl) * sizeof(T));
         const double* zc = zl + col * 9;
         const double* va = ml + row * 9;
 #pragma unroll
