@@ -945,6 +945,17 @@ __device__ __forceinline__ bool poll_flag(const double* f, int* error) {
   return true;
 }
 
+// threadIdx.x passed through an empty asm statement: address arithmetic
+// derived from it is redone where it is used instead of being hoisted out of
+// the CG loop.  Hoisted, those per-lane addresses outlive the registers and
+// are spilled to scratch, and the wait for each reload also waits for every
+// load issued before it (the next product's block prefetch among them).
+__device__ __forceinline__ int fresh_tid() {
+  int t = threadIdx.x;
+  asm volatile("" : "+v"(t));
+  return t;
+}
+
 // Per-workgroup constants of the streamed product.
 struct StreamCtx {
   int B, G, r0, nr, sib, nitems, L, vb, nvc, ib, src;  // src: this thread's sender (t < senders)
@@ -959,7 +970,7 @@ template <typename T>
 __device__ __forceinline__ void stream_fetch(const PcgArgs& a, const StreamCtx& c,
                                              f32x4_t (&buf)[STREAM_LOADS], int k) {
   using Sh = StreamShape<T>;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int tx = fresh_tid(), wave = tx >> 6, lane = tx & 63;
   const unsigned char* __restrict__ SIb =
       reinterpret_cast<const unsigned char*>(a.SI) + (size_t)c.sib * SI_STRIDE * sizeof(T);
 #pragma unroll
@@ -991,7 +1002,7 @@ __device__ __forceinline__ bool stream_spmv(const PcgArgs& a, const StreamCtx& c
                                             double (&Mr)[9], f32x4_t (&A)[STREAM_LOADS],
                                             f32x4_t (&Bf)[STREAM_LOADS]) {
   using Sh = StreamShape<T>;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int tx = fresh_tid(), wave = tx >> 6, lane = tx & 63;
   const int gl = lane / 9, comp = lane - 9 * gl;
   const bool computes = gl < Sh::wave_groups;
   const int g = wave * Sh::wave_groups + gl;
@@ -1061,26 +1072,26 @@ __device__ __forceinline__ bool stream_spmv(const PcgArgs& a, const StreamCtx& c
   const int nout = c.nr * 9;
   {
     // (assigned in every thread: the previous values are dead here)
-    const int o = min((int)threadIdx.x, nout - 1);
+    const int o = min(tx, nout - 1);
     const size_t q = 81 * (size_t)(c.r0 + o / 9) + 9 * (o % 9);
 #pragma unroll
     for (int k = 0; k < 9; ++k) Mr[k] = a.Minv[q + k];
   }
   // column sums of other workgroups' rows to their exchange slots
   double* rk = a.rring + (size_t)slot * a.rstride + c.vbase;
-  for (int u = threadIdx.x; u < c.nvc * 9; u += blockDim.x) {
+  for (int u = tx; u < c.nvc * 9; u += blockDim.x) {
     const int j = u / 9, b = vcl[j];
     if (b < c.r0 || b >= c.r0 + c.nr) publish(rk + u, tl[u]);
   }
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
-  if (threadIdx.x == 0) publish(a.rflag + (size_t)slot * c.G + c.B, 1.0);
+  if (tx == 0) publish(a.rflag + (size_t)slot * c.G + c.B, 1.0);
   // outputs: the groups rptr[row] / L .. (rptr[row + 1] - 1) / L touched row
   // `row` (none when the row has no upper block); 8 lanes per output,
   // strided then three DPP lane moves: fixed order; then the row's own
   // column sum, when one of the workgroup's blocks lies in its column
   for (int base = 0; base < nout * 8; base += blockDim.x) {
-    const int t = base + threadIdx.x, o = t >> 3, sub = t & 7;
+    const int t = base + tx, o = t >> 3, sub = t & 7;
     double sum = 0.0;
     int row = 0, cp = 0;
     if (o < nout) {
@@ -1100,16 +1111,16 @@ __device__ __forceinline__ bool stream_spmv(const PcgArgs& a, const StreamCtx& c
   if (c.src >= 0 && !poll_flag(a.rflag + (size_t)slot * c.G + c.src, a.error)) *poll_failed = 1;
   __syncthreads();
   // their slots, in the fixed order of each row's list; tl cleared
-  if (!*poll_failed && threadIdx.x < nout) {
-    const int row = threadIdx.x / 9, cp = threadIdx.x - 9 * row;
+  if (!*poll_failed && tx < nout) {
+    const int row = tx / 9, cp = tx - 9 * row;
     const double* rs = a.rring + (size_t)slot * a.rstride + cp;
     const int k0 = ipl[row], k1 = ipl[row + 1];
     double sum = 0.0;
 #pragma unroll 4
     for (int k = k0; k < k1; ++k) sum += rs[k < STREAM_IN_MAX ? inl[k] : a.in_off[c.ib + k]];
-    nl[threadIdx.x] += sum;
+    nl[tx] += sum;
   }
-  for (int u = threadIdx.x; u < c.nvc * 9; u += blockDim.x) tl[u] = 0.0;
+  for (int u = tx; u < c.nvc * 9; u += blockDim.x) tl[u] = 0.0;
   __syncthreads();
   return *poll_failed == 0;
 }
@@ -1347,18 +1358,19 @@ __global__ __launch_bounds__(PCG_THREADS) void k_pcg_stream(PcgArgs a) {
       break;
     }
     if (own) {
-      const double n = nl[tid] + nd;
+      const int t2 = fresh_tid();
+      const double n = nl[t2] + nd;
       z = n + beta * z;
       q = m + beta * q;
-      const double s = w + beta * sl[tid];
-      sl[tid] = s;
-      const double p = u + beta * pl[tid];
-      pl[tid] = p;
-      xl[tid] += alpha * p;
+      const double s = w + beta * sl[t2];
+      sl[t2] = s;
+      const double p = u + beta * pl[t2];
+      pl[t2] = p;
+      xl[t2] += alpha * p;
       r -= alpha * s;
       u -= alpha * q;
       w -= alpha * z;
-      wl[tid] = w;
+      wl[t2] = w;
     }
     __syncthreads();
   }
