@@ -1000,7 +1000,8 @@ __device__ __forceinline__ bool stream_spmv(const PcgArgs& a, const StreamCtx& c
                                             const double* ml, double* tl, double* seg,
                                             unsigned char* st, double* nl, int* poll_failed,
                                             double (&Mr)[9], f32x4_t (&A)[STREAM_LOADS],
-                                            f32x4_t (&Bf)[STREAM_LOADS]) {
+                                            f32x4_t (&Bf)[STREAM_LOADS], const double* rec,
+                                            unsigned long long (&rv)[3]) {
   using Sh = StreamShape<T>;
   const int tx = fresh_tid(), wave = tx >> 6, lane = tx & 63;
   const int gl = lane / 9, comp = lane - 9 * gl;
@@ -1106,6 +1107,15 @@ __device__ __forceinline__ bool stream_spmv(const PcgArgs& a, const StreamCtx& c
     sum += dpp_mov<0x4E, 0xF>(sum);   // quad_perm [2,3,0,1]
     sum += dpp_mov<0x141, 0xF>(sum);  // row_half_mirror: the other quad of the 8
     if (o < nout && sub == 0) nl[o] = lcol[row] >= 0 ? sum + tl[lcol[row] * 9 + cp] : sum;
+  }
+  // the three words at rec (a dot record, when given), read once while the
+  // senders' flags are awaited: write-once words, so a value that is not
+  // pending is final (the caller polls again for a pending one)
+  if (rec) {
+#pragma unroll
+    for (int q = 0; q < 3; ++q)
+      rv[q] = __hip_atomic_load(reinterpret_cast<const unsigned long long*>(rec) + q, __ATOMIC_RELAXED,
+                                __HIP_MEMORY_SCOPE_AGENT);
   }
   // wait for the workgroups that send to this one (thread t for sender t)
   if (c.src >= 0 && !poll_flag(a.rflag + (size_t)slot * c.G + c.src, a.error)) *poll_failed = 1;
@@ -1242,7 +1252,9 @@ __global__ __launch_bounds__(PCG_THREADS) void k_pcg_stream(PcgArgs a) {
   double t0 = 0.0;
   for (int i = tid; i < G; i += nt) t0 += a.partB[(size_t)i * PART_STRIDE];
   const double bnorm = uniform(sqrt(block_sum(t0, red)));  // (its barriers complete zl)
-  if (ok) ok = stream_spmv<T>(a, c, 0, rptr, lcol, vcl, ipl, inl, zl, ml, tl, seg, st, nl, &poll_failed, Mr, A, Bf);
+  unsigned long long rv[3];
+  if (ok) ok = stream_spmv<T>(a, c, 0, rptr, lcol, vcl, ipl, inl, zl, ml, tl, seg, st, nl, &poll_failed, Mr, A, Bf,
+                              nullptr, rv);
   if (own) {
     w = nl[tid] + nd;
     wl[tid] = w;
@@ -1292,12 +1304,41 @@ __global__ __launch_bounds__(PCG_THREADS) void k_pcg_stream(PcgArgs a) {
       for (int k = 0; k < 9; ++k) nd += drow[k] * ml[row * 9 + k];
     }
     // the m columns this workgroup reads (into zl: w is no longer needed in
-    // its memory) and (thread t < G) workgroup t's partials, in one poll;
-    // each polling wavefront sums its partials
+    // its memory) and (thread t < G) workgroup t's dot partials.  The product
+    // n = S m needs no scalar of this iteration: with FP32 blocks it is formed
+    // before the partials of all workgroups are read (the grid-wide
+    // reduction waits behind the streaming, the partials are read during the
+    // product's exchange, and the last iteration's product is formed and
+    // dropped); with FP64 blocks the columns and partials are polled
+    // together and the product follows the scalars (each order measured the
+    // faster one for its precision)
+    constexpr bool defer = sizeof(T) == 4;
     double tg = 0.0, td = 0.0, tr = 0.0;
-    if (!poll_slot(vcl, c.nvc, zk, zl, tid < G ? pa + (size_t)tid * PART_STRIDE : nullptr, tg, td, tr,
-                   a.error))
-      poll_failed = 1;
+    const double* rec = tid < G ? pa + (size_t)tid * PART_STRIDE : nullptr;
+    if (!poll_slot(vcl, c.nvc, zk, zl, defer ? nullptr : rec, tg, td, tr, a.error)) poll_failed = 1;
+    if constexpr (defer) {
+      __syncthreads();
+      if (poll_failed) {
+        ok = false;
+        break;
+      }
+      if (!stream_spmv<T>(a, c, i + 1, rptr, lcol, vcl, ipl, inl, zl, ml, tl, seg, st, nl, &poll_failed, Mr, A, Bf,
+                          rec, rv)) {
+        ok = false;
+        break;
+      }
+      // partials still pending when read are polled
+      if (rec) {
+        if (rv[0] != PCG_PENDING && rv[1] != PCG_PENDING && rv[2] != PCG_PENDING) {
+          tg = __longlong_as_double((long long)rv[0]);
+          td = __longlong_as_double((long long)rv[1]);
+          tr = __longlong_as_double((long long)rv[2]);
+        } else if (!poll_slot(vcl, 0, zk, zl, rec, tg, td, tr, a.error)) {
+          poll_failed = 1;
+        }
+      }
+    }
+    // each polling wavefront sums its partials
     if ((tid >> 6) < nwr) {
       tg = dpp_wave_total(tg);
       td = dpp_wave_total(td);
@@ -1353,9 +1394,12 @@ __global__ __launch_bounds__(PCG_THREADS) void k_pcg_stream(PcgArgs a) {
       break;
     }
     const double alpha = scal[0], beta = scal[1];
-    if (!stream_spmv<T>(a, c, i + 1, rptr, lcol, vcl, ipl, inl, zl, ml, tl, seg, st, nl, &poll_failed, Mr, A, Bf)) {
-      ok = false;
-      break;
+    if constexpr (!defer) {
+      if (!stream_spmv<T>(a, c, i + 1, rptr, lcol, vcl, ipl, inl, zl, ml, tl, seg, st, nl, &poll_failed, Mr, A,
+                          Bf, nullptr, rv)) {
+        ok = false;
+        break;
+      }
     }
     if (own) {
       const int t2 = fresh_tid();
