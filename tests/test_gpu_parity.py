@@ -221,6 +221,34 @@ def test_streamed_pcg_path_matches_oracle():
             assert abs(ig["cost_after"] - io["cost_after"]) <= forms[f] * io["cost_after"], (f, it)
 
 
+@pytest.mark.parametrize("precision", [B.BA_FP64, B.BA_MIXED])
+@pytest.mark.parametrize("maxiter", [1, 7])
+def test_streamed_pcg_stopped_by_its_iteration_cap_matches_oracle(precision, maxiter):
+    """The streamed kernel (pipelined recurrence) stopped by its iteration cap
+    (tolerance 0) on a problem created with that cap: the exchange rings then
+    hold exactly cap + 2 slots and the last one is used (with FP32 blocks the
+    last iteration forms its product and drops it).  The pipelined and the
+    standard recurrence produce the same iterates in exact arithmetic, so the
+    step after the cap equals the oracle's after as many iterations, element
+    by element: FP64 within 1e-8 of the largest entry (rounding of a few
+    products in another order); mixed within 1e-5 (the FP32-rounded blocks
+    perturb S by about 6e-8 relative, amplified over at most 7 iterations)."""
+    s = make_scene(0, n_cams=400, n_pts=40000)
+    g = gpu(s, precision=precision, cg_maxiter=maxiter)
+    o = orc(s)
+    assert g.plan["pcg_layout"] == "streamed", g.plan
+    g.set_cg(0.0, maxiter)
+    info_g = g.lm_step()
+    info_o = o.lm_step(rtol=0.0, maxiter=maxiter)
+    assert info_g["status"] == 0 and info_g["cg_breakdown"] == 0
+    assert info_g["cg_iters"] == info_o["cg_iters"] == maxiter, (info_g["cg_iters"], info_o["cg_iters"])
+    tol = 1e-8 if precision == B.BA_FP64 else 1e-5
+    dc, dp, _ = o.step()
+    close(g.export(B.BA_X_DC), dc, tol, "dc")
+    close(g.export(B.BA_X_DP), dp, tol, "dp")
+    g.close()
+
+
 def test_mixed_pcg_beyond_streamed_column_capacity_matches_oracle():
     """500 ring cameras: a streamed workgroup would need more distinct block
     columns than the streamed kernel holds in LDS, so the mixed solve reads
