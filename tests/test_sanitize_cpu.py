@@ -4,7 +4,7 @@ pose graph) driven by tests/native/oracle_drive.c, and the plan builder
 driven by tests/native/plan_check.cpp, each compiled with
 -fsanitize=address,undefined and run on generated inputs.  Any report aborts
 the program (-fno-sanitize-recover), so the test only has to see exit 0;
-the driver's results are also checked against the ordinarily built oracle."""
+oracle_drive's results are also checked against the ordinarily built oracle."""
 import os
 import shutil
 import subprocess
